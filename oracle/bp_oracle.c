@@ -1,0 +1,613 @@
+/*
+ * bp_oracle.c -- plain, slow, single-threaded CPU oracle for bound
+ * propagation and probing.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the parity reference for the GPU
+ * library.  Only the test suite, the smoke check and the CPU-baseline leg of
+ * the benchmark load it.  It shares no code, header, table or helper with
+ * the GPU path, and the GPU path never calls it.
+ *
+ * What it computes (the paper's Section 2.1 "Bound Propagation" and
+ * Section 2.2 "Probing Cache"):
+ *
+ *   rows      lo_k <= sum_i a_ki x_i <= hi_k      (the paper's  a.z <= g  is
+ *             the case lo = -inf; a finite lo is the mirrored row)
+ *   activity  L_min^k = sum_{a>0} a l_i + sum_{a<0} a u_i   (Section 2.1,
+ *             first display) and its mirror L_max^k
+ *   bounds    u_i <- min_k (g_k - L_min^k + a_ki l_i) / a_ki  over a_ki > 0,
+ *             l_i <- max_k (g_k - L_min^k + a_ki u_i) / a_ki  over a_ki < 0
+ *             (Section 2.1, second display), and the mirrored forms for lo
+ *   rounds    the two steps repeat while some update passes a threshold
+ *             (Section 2.1, closing sentence of the bound formulas)
+ *   probing   a binary fixed to 0 and to 1, each propagated from the same
+ *             base (Section 2.2), the implications being the bounds that
+ *             differ from the base
+ *
+ * Readings where the paper is silent (each one is also listed with the
+ * design notes):
+ *   - rounds are round-synchronous (Jacobi): every row of a round sees the
+ *     bounds as they were when the round started;
+ *   - activities are the correctly rounded exact sum of the rounded terms
+ *     fl(a*b) over the finite contributions; infinite contributions are
+ *     counted, and a candidate uses the residual activity only when at most
+ *     the variable's own contribution is infinite;
+ *   - candidate op order: v = fl(fl(side - act) + fl(a*b_own)), c = fl(v/a);
+ *     integer variables round c up/down with tolerance inttol;
+ *   - threshold: integer variables accept any strict improvement;
+ *     continuous ones accept an old infinite bound, else an improvement
+ *     larger than tau * max(1, |old bound|);
+ *   - feasibility tolerance feastol (absolute) for the row test and for a
+ *     crossing of continuous bounds (Section 3 uses 1e-6 absolute);
+ *   - propagation after a call's first round only revisits rows holding a
+ *     variable whose bounds changed in the previous round (Section 1,
+ *     "propagation on changed constraints");
+ *   - -0.0 is stored as +0.0.
+ *
+ * Two modes give the same results: DEFINITION recomputes every row and every
+ * variable in every round; WORKLIST only the rows of the changed variables.
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -shared -fPIC.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_INFEASIBLE 1
+#define ORC_ROUND_LIMIT 2
+#define ORC_EINVAL (-1)
+#define ORC_ENOMEM (-2)
+#define ORC_ECAPACITY (-4)
+
+#define ORC_MODE_WORKLIST 0
+#define ORC_MODE_DEFINITION 1
+
+typedef struct {
+    int64_t m, n, nnz;
+    const int64_t *row_ptr;
+    const int32_t *col;
+    const double *val;
+    const double *lo, *hi;
+    const uint8_t *vtype; /* 0 continuous, 1 integer */
+} orc_instance;
+
+typedef struct {
+    double feastol, inttol, tau;
+    int32_t max_rounds;
+} orc_options;
+
+typedef struct {
+    int32_t status, rounds;
+    int64_t nnz_propagated;
+    int32_t n_infeasible_rows;
+    int64_t infeasible_row;
+    int32_t infeasible_var;
+} orc_result;
+
+/* ------------------------------------------------------------------------ */
+/* Correctly rounded sum of doubles.                                         */
+/*                                                                           */
+/* Shewchuk's adaptive-precision summation (Shewchuk 1997, "Adaptive        */
+/* Precision Floating-Point Arithmetic and Fast Robust Geometric            */
+/* Predicates"): the running sum is kept as a list of non-overlapping       */
+/* partials of increasing magnitude whose exact sum equals the exact sum of */
+/* the inputs so far.  Each input is merged with two-sum steps.  The final  */
+/* value adds the partials from the largest down and fixes the one case     */
+/* where that rounding could be off: a remainder of exactly half an ulp,    */
+/* resolved by the sign of the next partial.  Inputs must be finite.        */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double *p;
+    int64_t len, cap;
+    double stack[64];
+} orc_partials;
+
+static void partials_init(orc_partials *s) {
+    s->p = s->stack;
+    s->len = 0;
+    s->cap = 64;
+}
+
+static void partials_free(orc_partials *s) {
+    if (s->p != s->stack) free(s->p);
+}
+
+static int partials_push(orc_partials *s, double v) {
+    if (s->len == s->cap) {
+        int64_t nc = s->cap * 2;
+        double *np_ = (double *)malloc((size_t)nc * sizeof(double));
+        if (!np_) return -1;
+        memcpy(np_, s->p, (size_t)s->len * sizeof(double));
+        if (s->p != s->stack) free(s->p);
+        s->p = np_;
+        s->cap = nc;
+    }
+    s->p[s->len++] = v;
+    return 0;
+}
+
+static int partials_add(orc_partials *s, double x) {
+    int64_t keep = 0;
+    for (int64_t j = 0; j < s->len; ++j) {
+        double y = s->p[j];
+        if (fabs(x) < fabs(y)) { double t = x; x = y; y = t; }
+        double hi = x + y;
+        double lo = y - (hi - x); /* exact error of hi, since |x| >= |y| */
+        if (lo != 0.0) s->p[keep++] = lo;
+        x = hi;
+    }
+    s->len = keep;
+    return partials_push(s, x);
+}
+
+static double partials_round(const orc_partials *s) {
+    int64_t k = s->len;
+    if (k == 0) return 0.0;
+    double hi = s->p[--k];
+    double lo = 0.0;
+    while (k > 0) {
+        double x = hi;
+        double y = s->p[--k];
+        hi = x + y;
+        double yr = hi - x;
+        lo = y - yr;
+        if (lo != 0.0) break;
+    }
+    /* hi + lo is exact here and lo is at most half an ulp of hi.  If lo is
+     * exactly half an ulp and the next lower partial has the same sign, the
+     * true sum lies beyond the halfway point: round away from hi. */
+    if (k > 0 && ((lo < 0.0 && s->p[k - 1] < 0.0) || (lo > 0.0 && s->p[k - 1] > 0.0))) {
+        double y = lo * 2.0;
+        double x = hi + y;
+        double yr = x - hi;
+        if (y == yr) hi = x;
+    }
+    return hi;
+}
+
+double orc_exact_sum(const double *x, int64_t n) {
+    orc_partials s;
+    partials_init(&s);
+    for (int64_t i = 0; i < n; ++i) {
+        if (partials_add(&s, x[i]) != 0) { partials_free(&s); return NAN; }
+    }
+    double r = partials_round(&s);
+    partials_free(&s);
+    return r;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Propagation.                                                             */
+/* ------------------------------------------------------------------------ */
+static double canon(double x) { return x == 0.0 ? 0.0 : x; }
+
+typedef struct {
+    double minfin, maxfin;
+    int64_t ninf_min, ninf_max;
+} orc_activity;
+
+/* Row activity (Section 2.1, first display, and its mirror).  Terms are the
+ * rounded products a*l (a > 0) or a*u (a < 0) for the minimum; the maximum
+ * swaps l and u.  Infinite contributions are counted, not summed. */
+static int row_activity(const orc_instance *I, int64_t k, const double *lb, const double *ub,
+                        double *buf_min, double *buf_max, orc_activity *act) {
+    int64_t a0 = I->row_ptr[k], a1 = I->row_ptr[k + 1];
+    int64_t nmin = 0, nmax = 0;
+    act->ninf_min = 0;
+    act->ninf_max = 0;
+    for (int64_t p = a0; p < a1; ++p) {
+        int32_t i = I->col[p];
+        double a = I->val[p];
+        double bmin = a > 0.0 ? lb[i] : ub[i];
+        double bmax = a > 0.0 ? ub[i] : lb[i];
+        if (isinf(bmin)) act->ninf_min += 1; else buf_min[nmin++] = a * bmin;
+        if (isinf(bmax)) act->ninf_max += 1; else buf_max[nmax++] = a * bmax;
+    }
+    act->minfin = canon(orc_exact_sum(buf_min, nmin));
+    act->maxfin = canon(orc_exact_sum(buf_max, nmax));
+    if (isnan(act->minfin) || isnan(act->maxfin)) return ORC_ENOMEM;
+    return 0;
+}
+
+static int row_infeasible(const orc_instance *I, int64_t k, const orc_activity *act,
+                          const orc_options *o) {
+    if (act->ninf_min == 0 && act->minfin > I->hi[k] + o->feastol) return 1;
+    if (act->ninf_max == 0 && act->maxfin < I->lo[k] - o->feastol) return 1;
+    return 0;
+}
+
+/* Candidates of one nonzero (Section 2.1, second display, with its mirror
+ * for lo).  Writes an upper candidate into *cu / a lower one into *cl when
+ * present (they start at +inf / -inf). */
+static void nonzero_candidates(const orc_instance *I, int64_t k, double a, int32_t i,
+                               const orc_activity *act, const double *lb, const double *ub,
+                               const orc_options *o, double *cl, double *cu) {
+    int is_int = I->vtype[i] != 0;
+    double hi = I->hi[k], lo = I->lo[k];
+    if (!isinf(hi)) {
+        double bown = a > 0.0 ? lb[i] : ub[i];
+        int own_inf = isinf(bown);
+        int have = 0;
+        double v = 0.0;
+        if (!own_inf && act->ninf_min == 0) {
+            double r = hi - act->minfin;
+            double t = a * bown;
+            v = r + t;
+            have = 1;
+        } else if (own_inf && act->ninf_min == 1) {
+            v = hi - act->minfin;
+            have = 1;
+        }
+        if (have) {
+            double c = v / a;
+            if (a > 0.0) { /* upper bound candidate */
+                if (is_int) c = floor(c + o->inttol);
+                if (c < *cu) *cu = c;
+            } else {       /* lower bound candidate */
+                if (is_int) c = ceil(c - o->inttol);
+                if (c > *cl) *cl = c;
+            }
+        }
+    }
+    if (!isinf(lo)) {
+        double bown = a > 0.0 ? ub[i] : lb[i];
+        int own_inf = isinf(bown);
+        int have = 0;
+        double v = 0.0;
+        if (!own_inf && act->ninf_max == 0) {
+            double r = lo - act->maxfin;
+            double t = a * bown;
+            v = r + t;
+            have = 1;
+        } else if (own_inf && act->ninf_max == 1) {
+            v = lo - act->maxfin;
+            have = 1;
+        }
+        if (have) {
+            double c = v / a;
+            if (a > 0.0) { /* lower bound candidate */
+                if (is_int) c = ceil(c - o->inttol);
+                if (c > *cl) *cl = c;
+            } else {       /* upper bound candidate */
+                if (is_int) c = floor(c + o->inttol);
+                if (c < *cu) *cu = c;
+            }
+        }
+    }
+}
+
+/* Threshold test (the paper only says "a threshold"; reading above). */
+static int accept_upper(int is_int, double cand, double old, const orc_options *o) {
+    if (is_int) return cand < old;
+    if (isinf(old)) return !isinf(cand) && cand < old;
+    return cand < old - o->tau * fmax(1.0, fabs(old));
+}
+
+static int accept_lower(int is_int, double cand, double old, const orc_options *o) {
+    if (is_int) return cand > old;
+    if (isinf(old)) return !isinf(cand) && cand > old;
+    return cand > old + o->tau * fmax(1.0, fabs(old));
+}
+
+typedef struct {
+    int64_t *col_ptr; /* CSC built here, independently of the GPU path */
+    int32_t *col_row;
+    double *buf_min, *buf_max;
+    double *cl, *cu;
+    int32_t *touched;   /* vars with a candidate this round */
+    uint8_t *tmark;
+    int32_t *rows, *next_rows; /* worklists */
+    uint8_t *rmark;
+    int32_t *changed;   /* S_r */
+    double *nlb, *nub;  /* staged new bounds (definition mode) */
+} orc_work;
+
+static void work_free(orc_work *w) {
+    free(w->col_ptr); free(w->col_row); free(w->buf_min); free(w->buf_max);
+    free(w->cl); free(w->cu); free(w->touched); free(w->tmark);
+    free(w->rows); free(w->next_rows); free(w->rmark); free(w->changed);
+    free(w->nlb); free(w->nub);
+    memset(w, 0, sizeof(*w));
+}
+
+static int work_init(const orc_instance *I, orc_work *w) {
+    memset(w, 0, sizeof(*w));
+    int64_t m = I->m, n = I->n, nnz = I->nnz;
+    int64_t maxlen = 0;
+    for (int64_t k = 0; k < m; ++k) {
+        int64_t L = I->row_ptr[k + 1] - I->row_ptr[k];
+        if (L > maxlen) maxlen = L;
+    }
+    w->col_ptr = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    w->col_row = (int32_t *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t));
+    w->buf_min = (double *)malloc((size_t)(maxlen > 0 ? maxlen : 1) * sizeof(double));
+    w->buf_max = (double *)malloc((size_t)(maxlen > 0 ? maxlen : 1) * sizeof(double));
+    w->cl = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    w->cu = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    w->touched = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    w->tmark = (uint8_t *)calloc((size_t)(n > 0 ? n : 1), 1);
+    w->rows = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
+    w->next_rows = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
+    w->rmark = (uint8_t *)calloc((size_t)(m > 0 ? m : 1), 1);
+    w->changed = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    w->nlb = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    w->nub = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    if (!w->col_ptr || !w->col_row || !w->buf_min || !w->buf_max || !w->cl || !w->cu ||
+        !w->touched || !w->tmark || !w->rows || !w->next_rows || !w->rmark || !w->changed ||
+        !w->nlb || !w->nub) {
+        work_free(w);
+        return ORC_ENOMEM;
+    }
+    for (int64_t p = 0; p < nnz; ++p) w->col_ptr[I->col[p] + 1] += 1;
+    for (int64_t i = 0; i < n; ++i) w->col_ptr[i + 1] += w->col_ptr[i];
+    int64_t *fill = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    if (!fill) { work_free(w); return ORC_ENOMEM; }
+    memcpy(fill, w->col_ptr, (size_t)n * sizeof(int64_t));
+    for (int64_t k = 0; k < m; ++k)
+        for (int64_t p = I->row_ptr[k]; p < I->row_ptr[k + 1]; ++p)
+            w->col_row[fill[I->col[p]]++] = (int32_t)k;
+    free(fill);
+    for (int64_t i = 0; i < n; ++i) { w->cl[i] = -INFINITY; w->cu[i] = INFINITY; }
+    return 0;
+}
+
+/* Validation of the instance and of a bound vector (malformed input is an
+ * error, not a propagation outcome). */
+int orc_validate(const orc_instance *I) {
+    if (I->m < 0 || I->n < 0 || I->nnz < 0) return ORC_EINVAL;
+    if (I->m >= INT32_MAX || I->n >= INT32_MAX) return ORC_EINVAL;
+    if (I->row_ptr[0] != 0 || I->row_ptr[I->m] != I->nnz) return ORC_EINVAL;
+    for (int64_t k = 0; k < I->m; ++k) {
+        if (I->row_ptr[k + 1] < I->row_ptr[k]) return ORC_EINVAL;
+        if (isnan(I->lo[k]) || isnan(I->hi[k]) || I->lo[k] > I->hi[k]) return ORC_EINVAL;
+        if (I->lo[k] == INFINITY || I->hi[k] == -INFINITY) return ORC_EINVAL;
+        for (int64_t p = I->row_ptr[k]; p < I->row_ptr[k + 1]; ++p) {
+            if (I->col[p] < 0 || I->col[p] >= I->n) return ORC_EINVAL;
+            if (p > I->row_ptr[k] && I->col[p] <= I->col[p - 1]) return ORC_EINVAL;
+            if (!(I->val[p] != 0.0) || isinf(I->val[p])) return ORC_EINVAL; /* also NaN */
+        }
+    }
+    for (int64_t i = 0; i < I->n; ++i)
+        if (I->vtype[i] > 1) return ORC_EINVAL;
+    return 0;
+}
+
+static void add_row(const orc_instance *I, orc_work *w, int64_t k, int64_t *cnt) {
+    (void)I;
+    if (!w->rmark[k]) { w->rmark[k] = 1; w->next_rows[(*cnt)++] = (int32_t)k; }
+}
+
+/* PROPAGATE.  lb/ub (length n) are read and written in place.  changed ==
+ * NULL with n_changed < 0 is a cold start (every row in the first round);
+ * otherwise the first round holds the rows of the listed variables. */
+int orc_propagate(const orc_instance *I, double *lb, double *ub, const int32_t *changed,
+                  int64_t n_changed, const orc_options *o, int mode, orc_result *res) {
+    res->status = ORC_OK;
+    res->rounds = 0;
+    res->nnz_propagated = 0;
+    res->n_infeasible_rows = 0;
+    res->infeasible_row = -1;
+    res->infeasible_var = -1;
+    const int64_t m = I->m, n = I->n;
+    /* Step 0: an empty box before any round. */
+    for (int64_t i = 0; i < n; ++i) {
+        if (isnan(lb[i]) || isnan(ub[i])) return ORC_EINVAL;
+        double slack = I->vtype[i] ? 0.0 : o->feastol;
+        if (lb[i] > ub[i] + slack) {
+            res->status = ORC_INFEASIBLE;
+            res->infeasible_var = (int32_t)i;
+            return ORC_INFEASIBLE;
+        }
+    }
+    if (changed != NULL && n_changed == 0) return ORC_OK;
+    orc_work w;
+    int rc = work_init(I, &w);
+    if (rc) return rc;
+    for (int64_t i = 0; i < n; ++i) { lb[i] = canon(lb[i]); ub[i] = canon(ub[i]); }
+
+    /* First worklist. */
+    int64_t nrows = 0;
+    if (changed == NULL) {
+        for (int64_t k = 0; k < m; ++k) w.next_rows[nrows++] = (int32_t)k;
+    } else {
+        for (int64_t t = 0; t < n_changed; ++t) {
+            int32_t i = changed[t];
+            if (i < 0 || i >= n) { work_free(&w); return ORC_EINVAL; }
+            for (int64_t p = w.col_ptr[i]; p < w.col_ptr[i + 1]; ++p) add_row(I, &w, w.col_row[p], &nrows);
+        }
+    }
+
+    orc_activity *acts = NULL;
+    if (mode == ORC_MODE_DEFINITION) {
+        acts = (orc_activity *)malloc((size_t)(m > 0 ? m : 1) * sizeof(orc_activity));
+        if (!acts) { work_free(&w); return ORC_ENOMEM; }
+    }
+
+    int status = ORC_OK;
+    for (;;) {
+        /* Step 1: the round's worklist R_r. */
+        if (nrows == 0) break;
+        if (res->rounds >= o->max_rounds) { status = ORC_ROUND_LIMIT; break; }
+        { int32_t *t = w.rows; w.rows = w.next_rows; w.next_rows = t; }
+        int64_t cur = nrows;
+        for (int64_t t = 0; t < cur; ++t) w.rmark[w.rows[t]] = 0;
+        res->rounds += 1;
+        for (int64_t t = 0; t < cur; ++t) {
+            int64_t k = w.rows[t];
+            res->nnz_propagated += I->row_ptr[k + 1] - I->row_ptr[k];
+        }
+
+        int64_t ntouched = 0;
+        int64_t bad_row = -1, n_bad = 0;
+        if (mode == ORC_MODE_WORKLIST) {
+            /* Steps 2-4 over R_r only. */
+            for (int64_t t = 0; t < cur; ++t) {
+                int64_t k = w.rows[t];
+                orc_activity act;
+                if ((rc = row_activity(I, k, lb, ub, w.buf_min, w.buf_max, &act))) goto fail;
+                if (row_infeasible(I, k, &act, o)) {
+                    n_bad += 1;
+                    if (bad_row < 0 || k < bad_row) bad_row = k;
+                    continue;
+                }
+                if (n_bad) continue; /* the round ends infeasible; skip candidates */
+                for (int64_t p = I->row_ptr[k]; p < I->row_ptr[k + 1]; ++p) {
+                    int32_t i = I->col[p];
+                    nonzero_candidates(I, k, I->val[p], i, &act, lb, ub, o, &w.cl[i], &w.cu[i]);
+                    if (!w.tmark[i]) { w.tmark[i] = 1; w.touched[ntouched++] = i; }
+                }
+            }
+        } else {
+            /* Definition: every row's activity, every row's candidates. */
+            for (int64_t k = 0; k < m; ++k) {
+                if ((rc = row_activity(I, k, lb, ub, w.buf_min, w.buf_max, &acts[k]))) goto fail;
+                if (row_infeasible(I, k, &acts[k], o)) {
+                    n_bad += 1;
+                    if (bad_row < 0 || k < bad_row) bad_row = k;
+                }
+            }
+            if (!n_bad) {
+                for (int64_t k = 0; k < m; ++k)
+                    for (int64_t p = I->row_ptr[k]; p < I->row_ptr[k + 1]; ++p)
+                        nonzero_candidates(I, k, I->val[p], I->col[p], &acts[k], lb, ub, o,
+                                           &w.cl[I->col[p]], &w.cu[I->col[p]]);
+                for (int64_t i = 0; i < n; ++i) w.touched[ntouched++] = (int32_t)i;
+            }
+        }
+        if (n_bad) {
+            /* Step 3: the round ends with the row evidence. */
+            res->status = ORC_INFEASIBLE;
+            res->infeasible_row = bad_row;
+            res->n_infeasible_rows = (int32_t)n_bad;
+            status = ORC_INFEASIBLE;
+            for (int64_t t = 0; t < ntouched; ++t) {
+                int32_t i = w.touched[t];
+                w.cl[i] = -INFINITY; w.cu[i] = INFINITY; w.tmark[i] = 0;
+            }
+            break;
+        }
+
+        /* Step 5: acceptance against the round-start bounds (staged). */
+        int64_t nchg = 0;
+        int32_t bad_var = -1;
+        for (int64_t t = 0; t < ntouched; ++t) {
+            int32_t i = w.touched[t];
+            int is_int = I->vtype[i] != 0;
+            double L = w.cl[i], U = w.cu[i];
+            double nl = lb[i], nu = ub[i];
+            int ch = 0;
+            if (accept_upper(is_int, U, ub[i], o)) { nu = canon(U); ch = 1; }
+            if (accept_lower(is_int, L, lb[i], o)) { nl = canon(L); ch = 1; }
+            /* Step 6: crossing. */
+            if (ch && nl > nu) {
+                if (is_int || nl - nu > o->feastol) {
+                    if (bad_var < 0 || i < bad_var) bad_var = i;
+                } else {
+                    nl = nu;
+                }
+            }
+            w.nlb[i] = nl;
+            w.nub[i] = nu;
+            if (ch) w.changed[nchg++] = i;
+            w.cl[i] = -INFINITY; w.cu[i] = INFINITY; w.tmark[i] = 0;
+        }
+        /* Step 7: commit all at once. */
+        for (int64_t t = 0; t < nchg; ++t) {
+            int32_t i = w.changed[t];
+            lb[i] = w.nlb[i];
+            ub[i] = w.nub[i];
+        }
+        if (bad_var >= 0) {
+            res->status = ORC_INFEASIBLE;
+            res->infeasible_var = bad_var;
+            status = ORC_INFEASIBLE;
+            break;
+        }
+        /* Next worklist: rows holding a changed variable. */
+        nrows = 0;
+        for (int64_t t = 0; t < nchg; ++t) {
+            int32_t i = w.changed[t];
+            for (int64_t p = w.col_ptr[i]; p < w.col_ptr[i + 1]; ++p) add_row(I, &w, w.col_row[p], &nrows);
+        }
+    }
+    res->status = status;
+    free(acts);
+    work_free(&w);
+    return status;
+fail:
+    free(acts);
+    work_free(&w);
+    return rc;
+}
+
+/* PROBE (Section 2.2): for each listed binary j and v in {0, 1}, propagate
+ * from the base (lb, ub) with j fixed to v.  Probe p = 2t + v.  Implied
+ * list of a feasible (or round-limited) probe: every variable whose bounds
+ * differ from the base, ascending.  Infeasible probes list nothing.
+ * Returns ORC_ECAPACITY (with *required set) if cap is too small. */
+int orc_probe(const orc_instance *I, const double *base_lb, const double *base_ub,
+              const int32_t *vars, int32_t k, const orc_options *o, int mode,
+              int8_t *status, int32_t *rounds, int64_t *nnz, int32_t *n_infeasible_rows,
+              int64_t *off, int32_t *ivar, double *ilb, double *iub, int64_t cap,
+              int64_t *required) {
+    const int64_t n = I->n;
+    double *lb = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    double *ub = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    if (!lb || !ub) { free(lb); free(ub); return ORC_ENOMEM; }
+    int64_t total = 0;
+    off[0] = 0;
+    int rc_all = 0;
+    for (int32_t t = 0; t < k; ++t) {
+        int32_t j = vars[t];
+        if (j < 0 || j >= n || I->vtype[j] == 0 || base_lb[j] < 0.0 || base_ub[j] > 1.0) {
+            free(lb); free(ub);
+            return ORC_EINVAL;
+        }
+        for (int v = 0; v < 2; ++v) {
+            int64_t p = 2 * (int64_t)t + v;
+            double fv = (double)v;
+            orc_result r;
+            memset(&r, 0, sizeof(r));
+            r.infeasible_row = -1;
+            r.infeasible_var = -1;
+            if (fv < base_lb[j] || fv > base_ub[j]) {
+                r.status = ORC_INFEASIBLE;
+                r.infeasible_var = j;
+            } else if (base_lb[j] == fv && base_ub[j] == fv) {
+                r.status = ORC_OK;
+            } else {
+                memcpy(lb, base_lb, (size_t)n * sizeof(double));
+                memcpy(ub, base_ub, (size_t)n * sizeof(double));
+                lb[j] = fv;
+                ub[j] = fv;
+                int rc = orc_propagate(I, lb, ub, &j, 1, o, mode, &r);
+                if (rc < 0) { free(lb); free(ub); return rc; }
+            }
+            status[p] = (int8_t)r.status;
+            rounds[p] = r.rounds;
+            nnz[p] = r.nnz_propagated;
+            if (n_infeasible_rows) n_infeasible_rows[p] = r.n_infeasible_rows;
+            int64_t cnt = 0;
+            if (r.status != ORC_INFEASIBLE && !(base_lb[j] == fv && base_ub[j] == fv)) {
+                for (int64_t i = 0; i < n; ++i) {
+                    if (lb[i] != base_lb[i] || ub[i] != base_ub[i]) {
+                        if (total + cnt < cap) {
+                            ivar[total + cnt] = (int32_t)i;
+                            ilb[total + cnt] = lb[i];
+                            iub[total + cnt] = ub[i];
+                        }
+                        cnt += 1;
+                    }
+                }
+            }
+            total += cnt;
+            off[p + 1] = total;
+        }
+    }
+    free(lb);
+    free(ub);
+    if (required) *required = total;
+    if (total > cap) rc_all = ORC_ECAPACITY;
+    return rc_all;
+}

@@ -1,0 +1,186 @@
+"""ctypes front end of the C oracle ``bp_oracle.c`` (test infrastructure only).
+
+The C file is compiled with gcc, without FMA contraction and without fast
+math, into ``liborc.so`` next to it.  Nothing here is shared with the GPU
+library: the two sides only receive the same seeded input arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "bp_oracle.c")
+LIB = os.path.join(HERE, "liborc.so")
+
+BP_OK, BP_INFEASIBLE, BP_ROUND_LIMIT = 0, 1, 2
+MODE_WORKLIST, MODE_DEFINITION = 0, 1
+
+
+@dataclass
+class Options:
+    feastol: float = 1e-6
+    inttol: float = 1e-6
+    tau: float = 1e-3
+    max_rounds: int = 1000
+
+
+class _Inst(C.Structure):
+    _fields_ = [("m", C.c_int64), ("n", C.c_int64), ("nnz", C.c_int64),
+                ("row_ptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p),
+                ("lo", C.c_void_p), ("hi", C.c_void_p), ("vtype", C.c_void_p)]
+
+
+class _Opt(C.Structure):
+    _fields_ = [("feastol", C.c_double), ("inttol", C.c_double), ("tau", C.c_double),
+                ("max_rounds", C.c_int32)]
+
+
+class _Res(C.Structure):
+    _fields_ = [("status", C.c_int32), ("rounds", C.c_int32), ("nnz_propagated", C.c_int64),
+                ("n_infeasible_rows", C.c_int32), ("infeasible_row", C.c_int64),
+                ("infeasible_var", C.c_int32)]
+
+
+_lib = None
+
+
+def compile_to(src: str, out: str) -> str:
+    """gcc -O2, no FMA contraction, no fast math."""
+    tmp = out + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                           "-fPIC", "-shared", "-o", tmp, src, "-lm"])
+    os.replace(tmp, out)
+    return out
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle when the library is missing or older than its source."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        compile_to(SRC, LIB)
+    return LIB
+
+
+def bind(path: str):
+    """Load an oracle library built from ``bp_oracle.c`` (or a variant of it)."""
+    lib = C.CDLL(path)
+    lib.orc_exact_sum.restype = C.c_double
+    lib.orc_exact_sum.argtypes = [C.c_void_p, C.c_int64]
+    lib.orc_validate.restype = C.c_int
+    lib.orc_validate.argtypes = [C.POINTER(_Inst)]
+    lib.orc_propagate.restype = C.c_int
+    lib.orc_propagate.argtypes = [C.POINTER(_Inst), C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_int64, C.POINTER(_Opt), C.c_int, C.POINTER(_Res)]
+    lib.orc_probe.restype = C.c_int
+    lib.orc_probe.argtypes = [C.POINTER(_Inst), C.c_void_p, C.c_void_p, C.c_void_p,
+                              C.c_int32, C.POINTER(_Opt), C.c_int] + [C.c_void_p] * 8 + \
+                             [C.c_int64, C.POINTER(C.c_int64)]
+    return lib
+
+
+def load():
+    global _lib
+    if _lib is None:
+        build()
+        _lib = bind(LIB)
+    return _lib
+
+
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class _Held:
+    """Keeps contiguous copies alive while the C side reads them."""
+
+    def __init__(self, inst):
+        self.row_ptr = np.ascontiguousarray(inst["row_ptr"], dtype=np.int64)
+        self.col = np.ascontiguousarray(inst["col"], dtype=np.int32)
+        self.val = np.ascontiguousarray(inst["val"], dtype=np.float64)
+        self.lo = np.ascontiguousarray(inst["lo"], dtype=np.float64)
+        self.hi = np.ascontiguousarray(inst["hi"], dtype=np.float64)
+        self.vtype = np.ascontiguousarray(inst["vtype"], dtype=np.uint8)
+        self.s = _Inst(int(inst["m"]), int(inst["n"]), int(self.row_ptr[-1]),
+                       _ptr(self.row_ptr), _ptr(self.col), _ptr(self.val), _ptr(self.lo),
+                       _ptr(self.hi), _ptr(self.vtype))
+
+
+def _opt(o):
+    o = o or Options()
+    return _Opt(o.feastol, o.inttol, o.tau, o.max_rounds)
+
+
+def exact_sum(x, lib=None) -> float:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    return float((lib or load()).orc_exact_sum(_ptr(x), x.size))
+
+
+def validate(inst, lib=None) -> int:
+    h = _Held(inst)
+    return int((lib or load()).orc_validate(C.byref(h.s)))
+
+
+def propagate(inst, lb=None, ub=None, changed=None, opts: Options = None,
+              mode: int = MODE_WORKLIST, lib=None):
+    """Round-synchronous propagation.  Returns (result dict, lb, ub)."""
+    lib = lib or load()
+    h = _Held(inst)
+    lb = np.array(inst["lb"] if lb is None else lb, dtype=np.float64, copy=True)
+    ub = np.array(inst["ub"] if ub is None else ub, dtype=np.float64, copy=True)
+    res = _Res()
+    if changed is None:
+        rc = lib.orc_propagate(C.byref(h.s), _ptr(lb), _ptr(ub), None, -1,
+                                  C.byref(_opt(opts)), mode, C.byref(res))
+    else:
+        ch = np.ascontiguousarray(changed, dtype=np.int32)
+        rc = lib.orc_propagate(C.byref(h.s), _ptr(lb), _ptr(ub),
+                                  _ptr(ch) if ch.size else C.c_void_p(1), ch.size,
+                                  C.byref(_opt(opts)), mode, C.byref(res))
+    if rc < 0:
+        raise ValueError("oracle propagate failed with code %d" % rc)
+    out = dict(status=res.status, rounds=res.rounds, nnz_propagated=res.nnz_propagated,
+               n_infeasible_rows=res.n_infeasible_rows, infeasible_row=res.infeasible_row,
+               infeasible_var=res.infeasible_var)
+    return out, lb, ub
+
+
+def probe(inst, base_lb, base_ub, vars_, opts: Options = None, mode: int = MODE_WORKLIST,
+          lib=None):
+    """Double probing of binaries around the base.  Returns a dict of arrays:
+    status/rounds/nnz/n_infeasible_rows per probe (probe 2t+v is vars[t]=v),
+    off[2k+1] and the concatenated implied (var, lb, ub) lists."""
+    lib = lib or load()
+    h = _Held(inst)
+    base_lb = np.ascontiguousarray(base_lb, dtype=np.float64)
+    base_ub = np.ascontiguousarray(base_ub, dtype=np.float64)
+    vs = np.ascontiguousarray(vars_, dtype=np.int32)
+    k = vs.size
+    st = np.zeros(2 * k, np.int8)
+    rd = np.zeros(2 * k, np.int32)
+    nz = np.zeros(2 * k, np.int64)
+    nir = np.zeros(2 * k, np.int32)
+    off = np.zeros(2 * k + 1, np.int64)
+    cap = 1 << 16
+    while True:
+        iv = np.zeros(cap, np.int32)
+        il = np.zeros(cap)
+        iu = np.zeros(cap)
+        req = C.c_int64(0)
+        rc = lib.orc_probe(C.byref(h.s), _ptr(base_lb), _ptr(base_ub), _ptr(vs), k,
+                              C.byref(_opt(opts)), mode, _ptr(st), _ptr(rd), _ptr(nz),
+                              _ptr(nir), _ptr(off), _ptr(iv), _ptr(il), _ptr(iu), cap,
+                              C.byref(req))
+        if rc == -4:
+            cap = int(req.value)
+            continue
+        if rc < 0:
+            raise ValueError("oracle probe failed with code %d" % rc)
+        tot = int(off[-1])
+        return dict(status=st, rounds=rd, nnz=nz, n_infeasible_rows=nir, off=off,
+                    var=iv[:tot].copy(), lb=il[:tot].copy(), ub=iu[:tot].copy())

@@ -1,0 +1,122 @@
+"""Planted mistakes in the CPU oracle must be caught by its pins.
+
+Each mutant is a one-line textual change of ``oracle/bp_oracle.c`` (a
+dropped term, a wrong sign or index, a swapped operand), compiled on the CPU
+into a temporary library.  The pins (worked examples, brute force, exact
+Gauss-Seidel, closed forms, planted-point invariants) are run against it
+and at least one must fail.
+"""
+import math
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import exact_gs_fixed_point, feasible_points, implied_dict, load_golden
+from paper_2510_20499_amd import gen
+
+SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle",
+                   "bp_oracle.c")
+
+MUTANTS = {
+    "own_term_sign": ("v = r + t;", "v = r - t;"),
+    "own_term_dropped": ("v = r + t;", "v = r;"),
+    "activity_bounds_swapped": ("double bmin = a > 0.0 ? lb[i] : ub[i];",
+                                "double bmin = a > 0.0 ? ub[i] : lb[i];"),
+    "no_integer_floor": ("if (is_int) c = floor(c + o->inttol);", "if (is_int) c = floor(c);"),
+    "inttol_sign": ("if (is_int) c = ceil(c - o->inttol);", "if (is_int) c = ceil(c + o->inttol);"),
+    "threshold_sign": ("return cand < old - o->tau * fmax(1.0, fabs(old));",
+                       "return cand < old + o->tau * fmax(1.0, fabs(old));"),
+    "inf_count_rule": ("} else if (own_inf && act->ninf_min == 1) {",
+                       "} else if (own_inf && act->ninf_min == 0) {"),
+    "row_test_tolerance": ("if (act->ninf_min == 0 && act->minfin > I->hi[k] + o->feastol) return 1;",
+                           "if (act->ninf_min == 0 && act->minfin > I->hi[k] + 1.0) return 1;"),
+    "worklist_skips_first_row": (
+        "for (int64_t p = w.col_ptr[i]; p < w.col_ptr[i + 1]; ++p) add_row(I, &w, w.col_row[p], &nrows);\n        }\n    }",
+        "for (int64_t p = w.col_ptr[i] + 1; p < w.col_ptr[i + 1]; ++p) add_row(I, &w, w.col_row[p], &nrows);\n        }\n    }"),
+    "division_operand": ("double c = v / a;", "double c = v / fabs(a);"),
+}
+
+
+def _pins_hold(lib) -> bool:
+    try:
+        for name in ("w1", "w2", "w3"):
+            inst, d = load_golden(name)
+            r, lb, ub = oracle.propagate(inst, lib=lib)
+            c = d["cold"]
+            if (r["status"], r["rounds"], r["nnz_propagated"]) != (c["status"], c["rounds"], c["nnz_propagated"]):
+                return False
+            if list(lb) != [float(x) for x in c["lb"]] or list(ub) != [float(x) for x in c["ub"]]:
+                return False
+            P = oracle.probe(inst, lb, ub, d["probe_vars"], lib=lib)
+            for p, exp in enumerate(d["probes"]):
+                if (P["status"][p], P["rounds"][p], P["nnz"][p]) != (exp["status"], exp["rounds"], exp["nnz"]):
+                    return False
+                if "n_infeasible_rows" in exp and P["n_infeasible_rows"][p] != exp["n_infeasible_rows"]:
+                    return False
+                want = {int(v): (float(a), float(b)) for v, a, b in exp["implied"]}
+                if implied_dict(P, p) != want:
+                    return False
+        for seed in range(120):
+            inst = gen.make_micro(seed)
+            F = feasible_points(inst)
+            r, lb, ub = oracle.propagate(inst, lib=lib)
+            if r["status"] == oracle.BP_INFEASIBLE:
+                if F:
+                    return False
+                continue
+            for x in F:
+                if not all(lb[i] <= x[i] <= ub[i] for i in range(inst["n"])):
+                    return False
+            ok, glb, gub = exact_gs_fixed_point(inst)
+            if not ok or [float(x) for x in glb] != list(lb) or [float(x) for x in gub] != list(ub):
+                return False
+        for seed in range(5):
+            inst = gen.make("tiny", seed)
+            r, lb, ub = oracle.propagate(inst, lib=lib)
+            x = inst["xstar"]
+            if r["status"] != oracle.BP_OK or not ((lb <= x + 1e-6).all() and (x <= ub + 1e-6).all()):
+                return False
+        inst = gen.make("tiny_inf", 0)
+        r, lb, ub = oracle.propagate(inst, lib=lib)
+        x = inst["xstar"]
+        if r["status"] != oracle.BP_OK or not ((lb <= x + 1e-6).all() and (x <= ub + 1e-6).all()):
+            return False
+        n = 6
+        a = [1.5, 2.0, 3.0, 0.7, 5.0, 9.0]
+        g = 10.0
+        inst = gen.from_rows(n, [(list(range(n)), a)], [-math.inf], [g], [1] * n, [0.0] * n, [30.0] * n)
+        r, lb, ub = oracle.propagate(inst, lib=lib)
+        if list(ub) != [min(30.0, math.floor(g / a[j] + 1e-6)) for j in range(n)]:
+            return False
+        # 0.3 / 0.1 evaluates to 2.9999999999999996: the integer tolerance
+        # gives x <= 3, and symmetrically x >= 3 from 0.1 x >= 0.3.
+        inst = gen.from_rows(1, [([0], [0.1])], [-math.inf], [0.3], [1], [0.0], [10.0])
+        if list(oracle.propagate(inst, lib=lib)[2]) != [3.0]:
+            return False
+        inst = gen.from_rows(1, [([0], [0.1])], [0.3], [math.inf], [1], [0.0], [10.0])
+        if list(oracle.propagate(inst, lib=lib)[1]) != [3.0]:
+            return False
+    except (ValueError, ZeroDivisionError, OverflowError):
+        return False
+    return True
+
+
+def test_unmutated_oracle_passes_pins():
+    assert _pins_hold(oracle.load())
+
+
+@pytest.mark.parametrize("mutant", sorted(MUTANTS))
+def test_mutant_is_caught(mutant):
+    src = open(SRC).read()
+    old, new = MUTANTS[mutant]
+    assert src.count(old) >= 1, mutant
+    mutated = src.replace(old, new, 1)
+    with tempfile.TemporaryDirectory() as d:
+        cpath = os.path.join(d, "mut.c")
+        with open(cpath, "w") as fh:
+            fh.write(mutated)
+        lib = oracle.bind(oracle.compile_to(cpath, os.path.join(d, "libmut.so")))
+        assert not _pins_hold(lib), "pins did not catch mutant %s" % mutant

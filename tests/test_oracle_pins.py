@@ -1,0 +1,335 @@
+"""Pins of the CPU oracle to things other than itself.
+
+* Hand-computed worked examples (tests/golden, Sections 2.1-2.2).
+* The exact-sum routine against Python's math.fsum and exact rationals.
+* Brute force on micro instances: no feasible integer point is ever cut
+  off, infeasibility only when there is no feasible point, and each probe's
+  implied box holds every feasible point with the probed value.
+* An exact-rational Gauss-Seidel propagator (another schedule, other
+  arithmetic) reaching the same greatest fixed point on pure-integer
+  instances.
+* Closed forms (a single knapsack row) and invariants (bounds only shrink,
+  a fixed point is a fixed point, the planted point survives).
+* Definition mode (every row each round) equals worklist mode.
+"""
+import math
+import random
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import exact_gs_fixed_point, feasible_points, implied_dict, load_golden
+from paper_2510_20499_amd import gen
+
+INF = float("inf")
+
+
+# ------------------------------------------------------------------ golden
+@pytest.mark.parametrize("name", ["w1", "w2", "w3"])
+@pytest.mark.parametrize("mode", [oracle.MODE_WORKLIST, oracle.MODE_DEFINITION])
+def test_golden_cold(name, mode):
+    inst, d = load_golden(name)
+    r, lb, ub = oracle.propagate(inst, mode=mode)
+    c = d["cold"]
+    assert r["status"] == c["status"]
+    assert r["rounds"] == c["rounds"]
+    assert r["nnz_propagated"] == c["nnz_propagated"]
+    assert list(lb) == [float(x) for x in c["lb"]]
+    assert list(ub) == [float(x) for x in c["ub"]]
+    r2, lb2, ub2 = oracle.propagate(inst, lb, ub, mode=mode)
+    assert r2["rounds"] == d["second_cold"]["rounds"]
+    assert r2["nnz_propagated"] == d["second_cold"]["nnz_propagated"]
+    assert (lb2 == lb).all() and (ub2 == ub).all()
+
+
+@pytest.mark.parametrize("name", ["w1", "w2", "w3"])
+def test_golden_probes(name):
+    inst, d = load_golden(name)
+    _, lb, ub = oracle.propagate(inst)
+    P = oracle.probe(inst, lb, ub, d["probe_vars"])
+    for p, exp in enumerate(d["probes"]):
+        assert P["status"][p] == exp["status"], p
+        assert P["rounds"][p] == exp["rounds"], p
+        assert P["nnz"][p] == exp["nnz"], p
+        if "n_infeasible_rows" in exp:
+            assert P["n_infeasible_rows"][p] == exp["n_infeasible_rows"]
+        got = implied_dict(P, p)
+        want = {int(v): (float(a), float(b)) for v, a, b in exp["implied"]}
+        assert got == want, (p, got, want)
+
+
+def test_golden_w1_infeasible_evidence():
+    inst, _ = load_golden("w1")
+    _, lb, ub = oracle.propagate(inst)
+    lb = lb.copy(); ub = ub.copy()
+    lb[0] = ub[0] = 0.0
+    r, _, _ = oracle.propagate(inst, lb, ub, changed=[0])
+    assert r["status"] == oracle.BP_INFEASIBLE
+    assert r["infeasible_row"] == 1 and r["n_infeasible_rows"] == 1
+    assert r["rounds"] == 2 and r["nnz_propagated"] == 16
+
+
+def test_golden_w1_hull_matches_brute_force():
+    inst, _ = load_golden("w1")
+    _, lb, ub = oracle.propagate(inst)
+    # Enumerate the integer part; z is continuous with box [lo_z, hi_z].
+    pts = []
+    for x1 in (0, 1):
+        for x2 in (0, 1):
+            for x3 in (0, 1):
+                for y in range(0, 11):
+                    if x1 + x2 + x3 < 2 or x2 + x3 > 1 or -10 * x1 + 4 * y > 2:
+                        continue
+                    zlo, zhi = max(0.0, 7 - 20 * x2), min(100.0, 5.0 * y)
+                    if zlo <= zhi:
+                        pts.append((x1, x2, x3, y, zlo, zhi))
+    assert pts
+    for x1, x2, x3, y, zlo, zhi in pts:
+        for i, xv in enumerate((x1, x2, x3, y)):
+            assert lb[i] <= xv <= ub[i]
+        assert lb[4] <= zlo and zhi <= ub[4] + 1e-9
+    P = oracle.probe(inst, lb, ub, [0, 1, 2])
+    for t in range(3):
+        for v in (0, 1):
+            sub = [p for p in pts if p[t] == v]
+            p = 2 * t + v
+            if not sub:
+                assert P["status"][p] == oracle.BP_INFEASIBLE
+                continue
+            imp = implied_dict(P, p)
+            box_lb = [imp.get(i, (lb[i], ub[i]))[0] for i in range(5)]
+            box_ub = [imp.get(i, (lb[i], ub[i]))[1] for i in range(5)]
+            for q in sub:
+                for i in range(4):
+                    assert box_lb[i] <= q[i] <= box_ub[i]
+                assert box_lb[4] <= q[4] + 1e-9 and q[5] <= box_ub[4] + 1e-9
+
+
+# --------------------------------------------------------------- exact sum
+def _exact_round(xs):
+    """Correct rounding of an exact rational sum (ties to even), computed
+    through Fraction and Python's own float conversion."""
+    return float(sum((Fraction(x) for x in xs), Fraction(0)))
+
+
+def test_exact_sum_vs_fsum_and_fractions():
+    rng = np.random.default_rng(5)
+    for trial in range(300):
+        n = int(rng.integers(0, 60))
+        x = rng.standard_normal(n) * np.exp2(rng.integers(-60, 60, size=n))
+        if trial % 3 == 0 and n > 2:  # heavy cancellation
+            x = np.concatenate([x, -x[: n // 2] * (1 + 2.0 ** -52)])
+        got = oracle.exact_sum(x)
+        assert got == math.fsum(x)
+        assert got == _exact_round(x.tolist())
+
+
+def test_exact_sum_special_cases():
+    assert oracle.exact_sum([]) == 0.0
+    assert oracle.exact_sum([1e16, 1.0, -1e16]) == 1.0
+    # Halfway cases: 1 + 2^-53 is a tie that rounds to even (1.0); an extra
+    # tiny term of either sign decides it.
+    assert oracle.exact_sum([1.0, 2.0 ** -53]) == 1.0
+    assert oracle.exact_sum([1.0, 2.0 ** -53, 2.0 ** -100]) == 1.0 + 2.0 ** -52
+    assert oracle.exact_sum([1.0, 2.0 ** -53, -(2.0 ** -100)]) == 1.0
+    assert oracle.exact_sum([2.0 ** 1000, 1.0, -(2.0 ** 1000)]) == 1.0
+    assert oracle.exact_sum([5e-324, 5e-324]) == 1e-323
+
+
+# ------------------------------------------------------------- brute force
+@pytest.mark.parametrize("seed", range(300))
+def test_micro_brute_force(seed):
+    inst = gen.make_micro(seed)
+    F = feasible_points(inst)
+    r, lb, ub = oracle.propagate(inst)
+    if r["status"] == oracle.BP_INFEASIBLE:
+        assert F == []
+        return
+    assert r["status"] == oracle.BP_OK
+    for x in F:
+        assert all(lb[i] <= x[i] <= ub[i] for i in range(inst["n"]))
+    # Probes of every unfixed binary.
+    bins = [i for i in range(inst["n"]) if lb[i] == 0.0 and ub[i] == 1.0]
+    if not bins:
+        return
+    P = oracle.probe(inst, lb, ub, bins)
+    for t, j in enumerate(bins):
+        for v in (0, 1):
+            p = 2 * t + v
+            sub = [x for x in F if x[j] == v]
+            if P["status"][p] == oracle.BP_INFEASIBLE:
+                assert sub == []
+                continue
+            imp = implied_dict(P, p)
+            assert imp[j] == (float(v), float(v))
+            for x in sub:
+                for i in range(inst["n"]):
+                    a, b = imp.get(i, (lb[i], ub[i]))
+                    assert a <= x[i] <= b
+
+
+@pytest.mark.parametrize("seed", range(150))
+def test_micro_gauss_seidel_exact(seed):
+    """Round-synchronous FP propagation equals a Gauss-Seidel sweep in exact
+    rationals: pure-integer propagation has one greatest fixed point."""
+    inst = gen.make_micro(seed + 1000)
+    ok, glb, gub = exact_gs_fixed_point(inst)
+    r, lb, ub = oracle.propagate(inst)
+    if not ok:
+        assert r["status"] == oracle.BP_INFEASIBLE
+        return
+    assert r["status"] == oracle.BP_OK
+    assert [Fraction(x) for x in lb] == glb
+    assert [Fraction(x) for x in ub] == gub
+
+
+# ------------------------------------------------------------ closed forms
+@pytest.mark.parametrize("seed", range(20))
+def test_knapsack_closed_form(seed):
+    rng = random.Random(seed)
+    n = rng.randint(1, 12)
+    a = [rng.uniform(0.5, 20.0) for _ in range(n)]
+    g = rng.uniform(0.0, 50.0)
+    U = [float(rng.randint(0, 30)) for _ in range(n)]
+    inst = gen.from_rows(n, [(list(range(n)), a)], [-INF], [g], [1] * n, [0.0] * n, U)
+    r, lb, ub = oracle.propagate(inst)
+    assert r["status"] == oracle.BP_OK
+    for j in range(n):
+        want = min(U[j], math.floor(g / a[j] + 1e-6))
+        assert ub[j] == want
+        assert lb[j] == 0.0
+    changed = any(ub[j] < U[j] for j in range(n))
+    assert r["rounds"] == (2 if changed else 1)
+
+
+def test_integer_tolerance_near_integer_ratio():
+    # fl(0.3) / fl(0.1) = 2.9999999999999996 and the exact ratio of the two
+    # doubles is below 3 as well; the absolute tolerance 1e-6 (Section 3)
+    # makes the rounded bound 3 on both sides.
+    assert 0.3 / 0.1 < 3.0
+    inst = gen.from_rows(1, [([0], [0.1])], [-INF], [0.3], [1], [0.0], [10.0])
+    _, lb, ub = oracle.propagate(inst)
+    assert ub[0] == 3.0
+    inst = gen.from_rows(1, [([0], [0.1])], [0.3], [INF], [1], [0.0], [10.0])
+    _, lb, ub = oracle.propagate(inst)
+    assert lb[0] == 3.0
+
+
+def test_single_row_continuous_threshold():
+    # x + y <= 10, x,y continuous in [0, 100] -> both ub 10 (old 100 >> 10).
+    inst = gen.from_rows(2, [([0, 1], [1.0, 1.0])], [-INF], [10.0], [0, 0], [0, 0], [100, 100])
+    _, lb, ub = oracle.propagate(inst)
+    assert list(ub) == [10.0, 10.0]
+    # A move smaller than 1e-3 * max(1, |ub|) is not taken: 10.005 vs 10.
+    inst = gen.from_rows(1, [([0], [1.0])], [-INF], [9.995], [0], [0], [10.0])
+    r, lb, ub = oracle.propagate(inst)
+    assert ub[0] == 10.0 and r["rounds"] == 1
+    inst = gen.from_rows(1, [([0], [1.0])], [-INF], [9.985], [0], [0], [10.0])
+    _, lb, ub = oracle.propagate(inst)
+    assert ub[0] == 9.985
+
+
+def test_empty_row_and_empty_changed():
+    inst = gen.from_rows(1, [([], []), ([0], [2.0])], [-INF, -INF], [-1.0, 3.0], [1], [0], [5])
+    r, _, _ = oracle.propagate(inst)
+    assert r["status"] == oracle.BP_INFEASIBLE and r["infeasible_row"] == 0
+    inst = gen.from_rows(1, [([], []), ([0], [2.0])], [-INF, -INF], [0.0, 3.0], [1], [0], [5])
+    r, lb, ub = oracle.propagate(inst)
+    assert r["status"] == oracle.BP_OK and ub[0] == 1.0
+    r, _, _ = oracle.propagate(inst, lb, ub, changed=[])
+    assert r["rounds"] == 0 and r["nnz_propagated"] == 0
+
+
+def test_initial_box_check_and_round_limit():
+    inst = gen.from_rows(2, [([0, 1], [1.0, 1.0])], [-INF], [1.0], [1, 0], [0, 2.0], [1, 1.9999995])
+    r, _, _ = oracle.propagate(inst)  # continuous crossing within feastol is fine
+    assert r["status"] != oracle.BP_INFEASIBLE or r["infeasible_var"] != 1
+    inst2 = gen.from_rows(2, [([0, 1], [1.0, 1.0])], [-INF], [1.0], [1, 1], [0, 2.0], [1, 1.0])
+    r, _, _ = oracle.propagate(inst2)
+    assert r["status"] == oracle.BP_INFEASIBLE and r["infeasible_var"] == 1 and r["rounds"] == 0
+    # A chain x0 <= x1 - 1 <= ... needs many rounds: cut at max_rounds.
+    n = 30
+    rows = [([i, i + 1], [1.0, -1.0]) for i in range(n - 1)]
+    inst3 = gen.from_rows(n, rows, [-INF] * (n - 1), [-1.0] * (n - 1), [1] * n, [0.0] * n, [100.0] * n)
+    r, lb, ub = oracle.propagate(inst3, opts=oracle.Options(max_rounds=5))
+    assert r["status"] == oracle.BP_ROUND_LIMIT and r["rounds"] == 5
+    r, lb, ub = oracle.propagate(inst3)
+    assert r["status"] == oracle.BP_OK
+    assert list(lb) == [float(i) for i in range(n)]
+    assert list(ub) == [100.0 - (n - 1 - i) for i in range(n)]
+
+
+# -------------------------------------------------------------- invariants
+def _instances():
+    out = [("tiny", s, gen.make("tiny", s)) for s in range(10)]
+    out += [("tiny_inf", s, gen.make("tiny_inf", s)) for s in range(5)]
+    out += [("single", s, gen.make("single", s, scale=0.02)) for s in range(3)]
+    out += [("probe", 0, gen.make("probe", 0, scale=0.004))]
+    return out
+
+
+@pytest.mark.parametrize("name,seed,inst", _instances(), ids=lambda v: str(v)[:12] if not isinstance(v, dict) else "inst")
+def test_invariants(name, seed, inst):
+    r, lb, ub = oracle.propagate(inst)
+    assert r["status"] == oracle.BP_OK
+    assert (lb >= inst["lb"]).all() and (ub <= inst["ub"]).all()
+    x = inst["xstar"]
+    integ = inst["vtype"] == 1
+    assert (lb[integ] <= x[integ]).all() and (x[integ] <= ub[integ]).all()
+    assert (lb[~integ] <= x[~integ] + 1e-6).all() and (x[~integ] <= ub[~integ] + 1e-6).all()
+    r2, lb2, ub2 = oracle.propagate(inst, lb, ub)
+    assert r2["rounds"] == 1 and (lb2 == lb).all() and (ub2 == ub).all()
+    r3, _, _ = oracle.propagate(inst, lb, ub, changed=[])
+    assert r3["rounds"] == 0
+    # Definition mode is bit-identical.
+    rd, lbd, ubd = oracle.propagate(inst, mode=oracle.MODE_DEFINITION)
+    assert rd == r and (lbd == lb).all() and (ubd == ub).all()
+    # Probing at the planted value keeps x* inside the implied box.
+    bins = np.nonzero(integ & (lb == 0) & (ub == 1))[0][:20]
+    if bins.size:
+        P = oracle.probe(inst, lb, ub, bins)
+        for t, j in enumerate(bins):
+            p = 2 * t + int(x[j])
+            assert P["status"][p] != oracle.BP_INFEASIBLE
+            imp = implied_dict(P, p)
+            for i, (a, b) in imp.items():
+                tol = 0 if integ[i] else 1e-6
+                assert a - tol <= x[i] <= b + tol
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_permutation_metamorphic(seed):
+    inst = gen.make("single", seed, scale=0.01)
+    r, lb, ub = oracle.propagate(inst)
+    rng = np.random.default_rng(seed)
+    m, n = inst["m"], inst["n"]
+    pr = rng.permutation(m)          # new row k' = old row pr[k']
+    pc = rng.permutation(n)          # new col of old var i is qc[i]
+    qc = np.argsort(pc)
+    rows = []
+    rp, c, v = inst["row_ptr"], inst["col"], inst["val"]
+    for k in pr:
+        cc = qc[c[rp[k]:rp[k + 1]]]
+        o = np.argsort(cc)
+        rows.append((cc[o], v[rp[k]:rp[k + 1]][o]))
+    P = gen.from_rows(n, rows, inst["lo"][pr], inst["hi"][pr], inst["vtype"][pc],
+                      inst["lb"][pc], inst["ub"][pc])
+    r2, lb2, ub2 = oracle.propagate(P)
+    assert r2["status"] == r["status"] and r2["rounds"] == r["rounds"]
+    assert r2["nnz_propagated"] == r["nnz_propagated"]
+    # The column permutation also reorders the terms inside every row, so
+    # this pins the order-independence of the activity sums.
+    assert (lb2 == lb[pc]).all() and (ub2 == ub[pc]).all()
+
+
+def test_validate_rejects_malformed():
+    good = gen.make("tiny", 0)
+    assert oracle.validate(good) == 0
+    bad = dict(good); bad["val"] = good["val"].copy(); bad["val"][3] = 0.0
+    assert oracle.validate(bad) == -1
+    bad = dict(good); bad["col"] = good["col"].copy(); bad["col"][1] = bad["col"][0]
+    assert oracle.validate(bad) == -1
+    bad = dict(good); bad["lo"] = good["lo"].copy(); bad["lo"][0] = good["hi"][0] + 1
+    assert oracle.validate(bad) == -1
