@@ -1,0 +1,212 @@
+/*
+ * bp.h -- C ABI of the MI355X bound-propagation library (libbp.so).
+ *
+ * The library propagates variable bounds through the rows of a sparse MILP
+ * constraint matrix (the paper's Section 2.1, "Bound Propagation") and
+ * probes binary variables at 0 and at 1 to fill a probing cache (Section
+ * 2.2, "Probing Cache").  Every compute step runs in HIP kernels written
+ * for gfx950; no C++ type, exception or torch type crosses this boundary.
+ *
+ * Problem.  Rows k = 0..m-1 read  lo_k <= sum_i a_ki x_i <= hi_k  (either
+ * side may be infinite; the paper's form  sum a z <= g  is lo = -inf).
+ * Variables i = 0..n-1 carry bounds [lb_i, ub_i] (either may be infinite)
+ * and a type: 0 continuous, 1 integer (binaries are integers in [0, 1]).
+ *
+ * Propagation semantics (what every entry point computes).  Rounds are
+ * round-synchronous: each round reads the bounds as they were when it
+ * started.  Round r processes the rows that hold a variable whose bounds
+ * changed in round r-1 (all rows in the first round of a cold start;
+ * Section 1 names this "propagation on changed constraints").  For each such
+ * row the minimum and maximum activities (Section 2.1, first display, and
+ * its mirror) are the correctly rounded exact sums of the rounded finite
+ * terms fl(a*b), with infinite contributions counted.  A row whose minimum
+ * activity exceeds hi + feastol, or whose maximum activity is below
+ * lo - feastol, with no infinite contribution, is infeasible.  Each nonzero
+ * yields bound candidates (Section 2.1, second display, and its mirror):
+ * v = fl(fl(side - activity) + fl(a*b_own)) (or fl(side - activity) when
+ * the variable's own contribution is the single infinite one), c = fl(v/a);
+ * integer variables take floor(c + inttol) for upper and ceil(c - inttol)
+ * for lower candidates.  A variable takes the tightest candidate of each
+ * side if it passes the threshold (Section 2.1, closing sentence): any
+ * strict improvement for integers; for continuous variables an old
+ * infinite bound, or a move larger than tau * max(1, |old|).  Crossed
+ * bounds are infeasible for integers and for continuous variables crossed
+ * by more than feastol; otherwise lb is set to ub.  -0.0 is stored as +0.0.
+ * The loop stops when a round changes nothing (BP_OK), when a row or a
+ * variable is infeasible (BP_INFEASIBLE, at the end of the detecting round),
+ * or after max_rounds rounds with work left (BP_ROUND_LIMIT).
+ *
+ * Memory.  bp_load takes host arrays and copies them; the caller may free
+ * them on return.  All other entry points take device pointers (for example
+ * torch tensors' data_ptr()) for bounds, variable lists and outputs, and
+ * host pointers for result structs.  Each call runs on the given HIP stream
+ * (NULL: the null stream) and returns once its results are complete.
+ *
+ * Threads.  An instance is not thread-safe; distinct instances may be used
+ * from distinct threads on distinct streams.
+ *
+ * Errors.  Negative return codes are errors; outputs are then untouched
+ * except where stated.  bp_last_error() returns a thread-local message.
+ */
+#ifndef BP_H
+#define BP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Outcomes (>= 0) and errors (< 0). */
+#define BP_OK 0
+#define BP_INFEASIBLE 1
+#define BP_ROUND_LIMIT 2
+#define BP_EINVAL (-1)     /* malformed input: NaN, lo > hi, unsorted or duplicate
+                              columns, explicit zero, index out of range, CSC not
+                              the transpose, probe variable not binary in the base */
+#define BP_ENOMEM (-2)     /* device or host allocation failed */
+#define BP_EDEVICE (-3)    /* a HIP call failed */
+#define BP_ECAPACITY (-4)  /* an output buffer is too small (see bp_probe_out) */
+#define BP_ESTATE (-5)     /* bp_probe before a feasible base exists */
+
+/* Flags (bp_options.flags). */
+#define BP_FLAG_FORCE_EXACT 1u  /* compute every activity on the exact slow path
+                                   (a check of that path; results are identical) */
+#define BP_FLAG_TIME_KERNELS 2u /* time the activity kernel with HIP events; read
+                                   the totals with bp_kernel_stats */
+#define BP_FLAG_HOST_ROUNDS 4u  /* drive rounds from the host one at a time
+                                   instead of device-resident graphs of rounds */
+
+/* A sparse matrix in compressed form: CSR (ptr over m rows, idx = column
+ * indices ascending in each row) or CSC (ptr over n columns, idx = row
+ * indices ascending in each column).  ptr has length (CSR: m, CSC: n) + 1,
+ * ptr[0] = 0 and the last entry = nnz; idx and val have length nnz. */
+typedef struct {
+    int64_t m, n, nnz;
+    const int64_t *ptr;
+    const int32_t *idx;
+    const double *val;
+} bp_sparse;
+
+typedef struct {
+    double feastol;      /* absolute feasibility tolerance, default 1e-6 */
+    double inttol;       /* integer rounding tolerance, default 1e-6 */
+    double tau;          /* continuous threshold, default 1e-3 */
+    int32_t max_rounds;  /* default 1000 */
+    uint32_t flags;      /* BP_FLAG_* */
+    int32_t heavy_threshold; /* rows longer than this are split across
+                                workgroups; default 8192 (0: default) */
+    int32_t rounds_per_launch; /* rounds per captured graph; default 8 */
+    int32_t probe_slots; /* bound vectors in flight during bp_probe; default 512 */
+    int32_t reserved;
+} bp_options;
+
+typedef struct {
+    int32_t status;            /* BP_OK, BP_INFEASIBLE or BP_ROUND_LIMIT */
+    int32_t rounds;            /* rounds with a non-empty row worklist */
+    int64_t nnz_propagated;    /* sum over rounds of the nonzeros of their rows */
+    int32_t n_infeasible_rows; /* infeasible rows in the detecting round */
+    int32_t infeasible_var;    /* smallest crossed variable, or -1 */
+    int64_t infeasible_row;    /* smallest infeasible row, or -1 (rows take
+                                  precedence over variables) */
+} bp_result;
+
+/* Outputs of bp_probe, all caller-owned DEVICE buffers except the two
+ * int64 fields.  Probe p = 2t + v is vars[t] fixed to v (double probing,
+ * Section 2.2).  Its implied list holds every variable whose (lb, ub)
+ * differs from the base, the probed variable included, ascending by
+ * variable; it is empty for infeasible probes and for a probe whose value
+ * the base already fixes. */
+typedef struct {
+    int8_t *status;    /* [2k] BP_OK / BP_INFEASIBLE / BP_ROUND_LIMIT */
+    int32_t *rounds;   /* [2k] */
+    int64_t *nnz;      /* [2k] nnz propagated */
+    int64_t *off;      /* [2k+1] list offsets */
+    int32_t *var;      /* [cap] */
+    double *lb;        /* [cap] */
+    double *ub;        /* [cap] */
+    int64_t cap;       /* capacity of var/lb/ub (in) */
+    int64_t required;  /* total implied entries (out; set also on BP_ECAPACITY) */
+} bp_probe_out;
+
+typedef struct bp_instance bp_instance;
+
+typedef struct {
+    double ms;          /* summed event time of the timed kernel */
+    int64_t launches;   /* launches timed */
+    int64_t rows;       /* row tasks those launches processed */
+    int64_t nnz;        /* nonzeros those launches processed */
+    int64_t vars_read;  /* bound records gathered (one per nonzero) */
+    int64_t vars_written; /* bound records written by the apply kernel */
+} bp_stats;
+
+/* Fill *opt with the defaults. */
+void bp_options_default(bp_options *opt);
+
+/* Load an instance (host arrays; copied to the device).
+ *   csr      the constraint matrix by rows (required)
+ *   csc      the same matrix by columns, or NULL to build it; if given it is
+ *            checked to be the transpose of csr (BP_EINVAL otherwise)
+ *   row_lo, row_hi  [m] sides (+-inf allowed, lo <= hi, lo != +inf, hi != -inf)
+ *   vartype  [n] 0 continuous, 1 integer
+ *   opt      options, or NULL for the defaults
+ *   stream   HIP stream (hipStream_t) for the uploads
+ *   out      receives the instance handle
+ * The matrix is validated: columns ascending and distinct in each row,
+ * indices in range, coefficients finite and nonzero (BP_EINVAL).  Rows and
+ * columns are binned by length (the paper's Section 2.1 load-balancing
+ * paragraph). */
+int bp_load(const bp_sparse *csr, const bp_sparse *csc, const double *row_lo,
+            const double *row_hi, const uint8_t *vartype, const bp_options *opt,
+            void *stream, bp_instance **out);
+
+/* Propagate one bound vector to its fixed point.
+ *   lb, ub     DEVICE [n], read and overwritten with the result
+ *   changed    DEVICE [n_changed] variable ids whose bounds the caller changed
+ *              since a fixed point; NULL (with any n_changed) for a cold start
+ *              in which the first round holds every row
+ *   res        HOST, receives the outcome
+ * Returns res->status, or an error.  After BP_OK the result becomes the
+ * instance's base for bp_probe.  After BP_INFEASIBLE the bounds hold the
+ * state at the end of the detecting round. */
+int bp_propagate(bp_instance *h, double *lb, double *ub, const int32_t *changed,
+                 int64_t n_changed, bp_result *res, void *stream);
+
+/* Propagate B independent bound vectors together (bulk rounding candidates).
+ *   lb, ub       DEVICE [B*n], vector b at offset b*n, read and overwritten
+ *   changed_ptr  DEVICE [B+1] offsets into changed_idx, or NULL: cold start
+ *                for every vector
+ *   changed_idx  DEVICE variable ids
+ *   res          HOST [B]
+ * Returns BP_OK when the call ran (per-vector outcomes are in res) or an
+ * error.  Does not change the base. */
+int bp_propagate_batch(bp_instance *h, int32_t B, double *lb, double *ub,
+                       const int64_t *changed_ptr, const int32_t *changed_idx,
+                       bp_result *res, void *stream);
+
+/* Double probing: every binary vars[t] (DEVICE [k]) is fixed to 0 and to 1
+ * and propagated from the base.  Returns BP_OK, BP_ESTATE without a base,
+ * BP_EINVAL if a variable is not an integer with base bounds inside [0, 1],
+ * or BP_ECAPACITY (out->required set, other outputs unspecified). */
+int bp_probe(bp_instance *h, const int32_t *vars, int32_t k, bp_probe_out *out,
+             void *stream);
+
+/* Copy the base bounds into DEVICE lb/ub [n].  BP_ESTATE without a base. */
+int bp_get_base(bp_instance *h, double *lb, double *ub, void *stream);
+
+/* Kernel timing totals since load or the last reset (BP_FLAG_TIME_KERNELS). */
+int bp_kernel_stats(bp_instance *h, bp_stats *out, int reset);
+
+/* Device bytes held by the instance (matrix copies and work buffers). */
+int64_t bp_device_bytes(const bp_instance *h);
+
+void bp_free(bp_instance *h);
+
+/* Thread-local description of the last error ("" if none). */
+const char *bp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BP_H */

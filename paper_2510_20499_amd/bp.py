@@ -1,0 +1,248 @@
+"""Python binding of libbp.so: argument marshalling only.
+
+Every step of propagation and probing runs in the HIP library.  PyTorch
+provides device memory (float64/int32 CUDA tensors on ROCm) and the current
+stream.  If the library is missing this module raises at import; there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbp.so")
+
+BP_OK, BP_INFEASIBLE, BP_ROUND_LIMIT = 0, 1, 2
+BP_EINVAL, BP_ENOMEM, BP_EDEVICE, BP_ECAPACITY, BP_ESTATE = -1, -2, -3, -4, -5
+FLAG_FORCE_EXACT, FLAG_TIME_KERNELS, FLAG_HOST_ROUNDS = 1, 2, 4
+
+EXPORTS = ["bp_options_default", "bp_load", "bp_propagate", "bp_propagate_batch", "bp_probe",
+           "bp_get_base", "bp_kernel_stats", "bp_device_bytes", "bp_free", "bp_last_error"]
+
+
+class Sparse(C.Structure):
+    _fields_ = [("m", C.c_int64), ("n", C.c_int64), ("nnz", C.c_int64),
+                ("ptr", C.c_void_p), ("idx", C.c_void_p), ("val", C.c_void_p)]
+
+
+class Options(C.Structure):
+    _fields_ = [("feastol", C.c_double), ("inttol", C.c_double), ("tau", C.c_double),
+                ("max_rounds", C.c_int32), ("flags", C.c_uint32),
+                ("heavy_threshold", C.c_int32), ("rounds_per_launch", C.c_int32),
+                ("probe_slots", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("rounds", C.c_int32), ("nnz_propagated", C.c_int64),
+                ("n_infeasible_rows", C.c_int32), ("infeasible_var", C.c_int32),
+                ("infeasible_row", C.c_int64)]
+
+    def as_dict(self):
+        return dict(status=self.status, rounds=self.rounds, nnz_propagated=self.nnz_propagated,
+                    n_infeasible_rows=self.n_infeasible_rows,
+                    infeasible_row=self.infeasible_row, infeasible_var=self.infeasible_var)
+
+
+class ProbeOut(C.Structure):
+    _fields_ = [("status", C.c_void_p), ("rounds", C.c_void_p), ("nnz", C.c_void_p),
+                ("off", C.c_void_p), ("var", C.c_void_p), ("lb", C.c_void_p),
+                ("ub", C.c_void_p), ("cap", C.c_int64), ("required", C.c_int64)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("ms", C.c_double), ("launches", C.c_int64), ("rows", C.c_int64),
+                ("nnz", C.c_int64), ("vars_read", C.c_int64), ("vars_written", C.c_int64)]
+
+
+class BPError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("libbp error %d: %s" % (code, msg))
+        self.code = code
+
+
+def load_library(path: str = LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError("libbp.so is not built (run paper_2510_20499_amd/build.py or "
+                          "__graft_entry__.build())")
+    lib = C.CDLL(path)
+    lib.bp_options_default.argtypes = [C.POINTER(Options)]
+    lib.bp_options_default.restype = None
+    lib.bp_load.argtypes = [C.POINTER(Sparse), C.POINTER(Sparse), C.c_void_p, C.c_void_p,
+                            C.c_void_p, C.POINTER(Options), C.c_void_p, C.POINTER(C.c_void_p)]
+    lib.bp_load.restype = C.c_int
+    lib.bp_propagate.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                 C.POINTER(Result), C.c_void_p]
+    lib.bp_propagate.restype = C.c_int
+    lib.bp_propagate_batch.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.POINTER(Result), C.c_void_p]
+    lib.bp_propagate_batch.restype = C.c_int
+    lib.bp_probe.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(ProbeOut), C.c_void_p]
+    lib.bp_probe.restype = C.c_int
+    lib.bp_get_base.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.bp_get_base.restype = C.c_int
+    lib.bp_kernel_stats.argtypes = [C.c_void_p, C.POINTER(Stats), C.c_int]
+    lib.bp_kernel_stats.restype = C.c_int
+    lib.bp_device_bytes.argtypes = [C.c_void_p]
+    lib.bp_device_bytes.restype = C.c_int64
+    lib.bp_free.argtypes = [C.c_void_p]
+    lib.bp_free.restype = None
+    lib.bp_last_error.argtypes = []
+    lib.bp_last_error.restype = C.c_char_p
+    return lib
+
+
+_LIB = load_library()
+
+
+def lib():
+    return _LIB
+
+
+def _check(rc):
+    if rc < 0:
+        raise BPError(rc, _LIB.bp_last_error().decode())
+    return rc
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    _LIB.bp_options_default(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _stream_ptr(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _host(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _dptr(t: torch.Tensor):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Instance:
+    """A constraint matrix resident on the device (bp_load)."""
+
+    def __init__(self, inst: dict, options: Options = None, with_csc: bool = False, stream=None):
+        self.m = int(inst["m"])
+        self.n = int(inst["n"])
+        self._rp = _host(inst["row_ptr"], np.int64)
+        self._col = _host(inst["col"], np.int32)
+        self._val = _host(inst["val"], np.float64)
+        self._lo = _host(inst["lo"], np.float64)
+        self._hi = _host(inst["hi"], np.float64)
+        self._vt = _host(inst["vtype"], np.uint8)
+        self.nnz = int(self._rp[-1])
+        csr = Sparse(self.m, self.n, self.nnz, self._rp.ctypes.data, self._col.ctypes.data,
+                     self._val.ctypes.data)
+        csc_p = None
+        if with_csc:
+            order = np.argsort(self._col, kind="stable")
+            rows = np.repeat(np.arange(self.m, dtype=np.int32), np.diff(self._rp))
+            self._crow = np.ascontiguousarray(rows[order])
+            self._cval = np.ascontiguousarray(self._val[order])
+            self._cptr = np.zeros(self.n + 1, np.int64)
+            np.cumsum(np.bincount(self._col, minlength=self.n), out=self._cptr[1:])
+            csc = Sparse(self.m, self.n, self.nnz, self._cptr.ctypes.data,
+                         self._crow.ctypes.data, self._cval.ctypes.data)
+            csc_p = C.byref(csc)
+        self.options = options or default_options()
+        h = C.c_void_p()
+        _check(_LIB.bp_load(C.byref(csr), csc_p, self._lo.ctypes.data, self._hi.ctypes.data,
+                            self._vt.ctypes.data, C.byref(self.options), _stream_ptr(stream),
+                            C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _LIB.bp_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def device_bytes(self) -> int:
+        return int(_LIB.bp_device_bytes(self._h))
+
+    def propagate(self, lb: torch.Tensor, ub: torch.Tensor, changed: torch.Tensor = None,
+                  stream=None) -> dict:
+        """bp_propagate: lb/ub are float64 device tensors, updated in place."""
+        assert lb.dtype == torch.float64 and ub.dtype == torch.float64
+        assert lb.is_cuda and ub.is_cuda and lb.is_contiguous() and ub.is_contiguous()
+        assert lb.numel() == self.n and ub.numel() == self.n
+        r = Result()
+        if changed is None:
+            rc = _LIB.bp_propagate(self._h, _dptr(lb), _dptr(ub), None, 0, C.byref(r),
+                                   _stream_ptr(stream))
+        else:
+            assert changed.dtype == torch.int32 and changed.is_cuda and changed.is_contiguous()
+            # A non-null pointer marks a warm start even for an empty list.
+            ptr = _dptr(changed) if changed.numel() else C.c_void_p(lb.data_ptr())
+            rc = _LIB.bp_propagate(self._h, _dptr(lb), _dptr(ub), ptr, changed.numel(),
+                                   C.byref(r), _stream_ptr(stream))
+        _check(rc)
+        return r.as_dict()
+
+    def propagate_batch(self, lb: torch.Tensor, ub: torch.Tensor, changed_ptr: torch.Tensor = None,
+                        changed_idx: torch.Tensor = None, stream=None) -> list:
+        """bp_propagate_batch: lb/ub are [B, n] float64 device tensors."""
+        B = lb.shape[0]
+        assert lb.shape == (B, self.n) and ub.shape == (B, self.n)
+        assert lb.is_contiguous() and ub.is_contiguous()
+        res = (Result * max(B, 1))()
+        cp = _dptr(changed_ptr) if changed_ptr is not None else None
+        ci = _dptr(changed_idx) if changed_idx is not None and changed_idx.numel() else None
+        _check(_LIB.bp_propagate_batch(self._h, B, _dptr(lb), _dptr(ub), cp, ci, res,
+                                       _stream_ptr(stream)))
+        return [res[j].as_dict() for j in range(B)]
+
+    def probe(self, vars_: torch.Tensor, cap: int = None, stream=None) -> dict:
+        """bp_probe: double probing of the binaries in vars_ (int32 device)."""
+        k = vars_.numel()
+        dev = vars_.device
+        cap = cap if cap is not None else max(1024, 64 * 2 * k)
+        while True:
+            o = dict(status=torch.empty(2 * k, dtype=torch.int8, device=dev),
+                     rounds=torch.empty(2 * k, dtype=torch.int32, device=dev),
+                     nnz=torch.empty(2 * k, dtype=torch.int64, device=dev),
+                     off=torch.empty(2 * k + 1, dtype=torch.int64, device=dev),
+                     var=torch.empty(max(cap, 1), dtype=torch.int32, device=dev),
+                     lb=torch.empty(max(cap, 1), dtype=torch.float64, device=dev),
+                     ub=torch.empty(max(cap, 1), dtype=torch.float64, device=dev))
+            po = ProbeOut(o["status"].data_ptr(), o["rounds"].data_ptr(), o["nnz"].data_ptr(),
+                          o["off"].data_ptr(), o["var"].data_ptr(), o["lb"].data_ptr(),
+                          o["ub"].data_ptr(), cap, 0)
+            rc = _LIB.bp_probe(self._h, _dptr(vars_) if k else None, k, C.byref(po),
+                               _stream_ptr(stream))
+            if rc == BP_ECAPACITY:
+                cap = int(po.required)
+                continue
+            _check(rc)
+            tot = int(po.required)
+            for key in ("var", "lb", "ub"):
+                o[key] = o[key][:tot]
+            return o
+
+    def base(self, stream=None):
+        lb = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        ub = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        _check(_LIB.bp_get_base(self._h, _dptr(lb), _dptr(ub), _stream_ptr(stream)))
+        return lb, ub
+
+    def kernel_stats(self, reset: bool = False) -> dict:
+        s = Stats()
+        _check(_LIB.bp_kernel_stats(self._h, C.byref(s), 1 if reset else 0))
+        return dict(ms=s.ms, launches=s.launches, rows=s.rows, nnz=s.nnz,
+                    vars_read=s.vars_read, vars_written=s.vars_written)

@@ -1,0 +1,809 @@
+// bp_engine.hip -- host runtime and C ABI of libbp.so (see include/bp.h).
+//
+// bp_load validates and uploads an instance and bins its rows by length.
+// An Engine holds the per-slot work buffers for up to `cap_slots` bound
+// vectors of one instance; propagate, propagate_batch and probe all run the
+// same round kernels over it (bp_kernels.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/bp.h"
+#include "bp_kernels.h"
+
+using namespace bp;
+
+// ------------------------------------------------------------------------
+// Errors
+// ------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPTRY(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(e_ == hipErrorOutOfMemory ? BP_ENOMEM : BP_EDEVICE,              \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));              \
+    } while (0)
+
+// ------------------------------------------------------------------------
+// Device buffers
+// ------------------------------------------------------------------------
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    int alloc(size_t n, int64_t &total) {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        if (n == 0) n = 16;
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            p = nullptr;
+            return fail(e == hipErrorOutOfMemory ? BP_ENOMEM : BP_EDEVICE,
+                        "hipMalloc(" + std::to_string(n) + "): " + hipGetErrorString(e));
+        }
+        bytes = n;
+        total += (int64_t)n;
+        return 0;
+    }
+    template <class T>
+    T *as() const {
+        return (T *)p;
+    }
+};
+
+struct Engine {
+    int32_t cap_slots = 0;
+    int32_t track_dirty = 0;
+    int64_t bytes = 0;
+    DevBuf bnd, cand, vflag, rflag, info, chg, dirty, dlist, dcount, ctl;
+    DevBuf q[2][NBIN], hmap[2], hbase[2], hpart, hact, hbad, hdone;
+    // captured graph of `graph_rounds` rounds for this engine's Params
+    hipGraphExec_t graph = nullptr;
+    int graph_rounds = 0;
+    Params graph_params;
+    ~Engine() {
+        if (graph) (void)hipGraphExecDestroy(graph);
+    }
+};
+
+struct bp_instance {
+    int32_t m = 0, n = 0;
+    int64_t nnz = 0;
+    bp_options opt;
+    int64_t heavy_threshold = 8192;
+    int32_t heavy_chunk = 4096;
+    // device copies
+    DevBuf row_ptr, col, val, side, col_ptr, col_row, vtype, rbin, cold_rows, base;
+    int64_t bytes = 0;
+    bool have_base = false;
+    // row bins (host)
+    int64_t bin_count[NBIN] = {0};
+    int64_t bin_start[NBIN + 1] = {0};
+    int64_t heavy_chunks = 0;        // chunks of all heavy rows
+    std::vector<int32_t> cold_hbase; // cold-start chunk base of each heavy row (bin order)
+    DevBuf cold_hbase_d, cold_hmap_d;
+    std::unique_ptr<Engine> eng;
+    // stats
+    bp_stats stats;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    ~bp_instance() {
+        eng.reset();
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+    }
+};
+
+extern "C" void bp_options_default(bp_options *o) {
+    o->feastol = 1e-6;
+    o->inttol = 1e-6;
+    o->tau = 1e-3;
+    o->max_rounds = 1000;
+    o->flags = 0;
+    o->heavy_threshold = 8192;
+    o->rounds_per_launch = 8;
+    o->probe_slots = 512;
+    o->reserved = 0;
+}
+
+extern "C" const char *bp_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------------------
+// Small kernels: packing, checks, seeding
+// ------------------------------------------------------------------------
+__global__ void k_pack(const double *lb, const double *ub, double2 *bnd, int64_t n, int64_t B) {
+    int64_t N = n * B;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < N;
+         j += (int64_t)gridDim.x * blockDim.x)
+        bnd[j] = make_double2(canon0(lb[j]), canon0(ub[j]));
+}
+
+__global__ void k_unpack(const double2 *bnd, double *lb, double *ub, int64_t N) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < N;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        double2 b = bnd[j];
+        lb[j] = b.x;
+        ub[j] = b.y;
+    }
+}
+
+__global__ void k_copy_bnd(const double2 *src, double2 *dst, int64_t N) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < N;
+         j += (int64_t)gridDim.x * blockDim.x)
+        dst[j] = src[j];
+}
+
+// Step before the first round: a crossed or NaN box.  out[2*s] = smallest
+// crossed var of slot s (NONE if none); out[2*s+1] = 1 if a NaN was seen.
+__global__ void k_box_check(const double2 *bnd, const uint8_t *vtype, int64_t n, int32_t B,
+                            double feastol, int32_t *out) {
+    int64_t N = n * (int64_t)B;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < N;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        int s = (int)(j / n);
+        int i = (int)(j - (int64_t)s * n);
+        double2 b = bnd[j];
+        if (isnan(b.x) || isnan(b.y)) atomicOr(&out[2 * s + 1], 1);
+        double slack = vtype[i] ? 0.0 : feastol;
+        if (b.x > b.y + slack) atomicMin(&out[2 * s], i);
+    }
+}
+
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x)
+        p[j] = v;
+}
+
+__global__ void k_fill_cand(longlong2 *c, int64_t n) {
+    const double INF = __builtin_inf();
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x)
+        c[j] = make_longlong2(dkey(-INF), dkey(INF));
+}
+
+// Cold start of slots [s0, s0 + ns): every row of the instance, in bin
+// order, into the queues of parity 0.  Slot j's rows of bin b sit at
+// (j - s0) * count_b within the bin queue.
+struct SeedAll {
+    const int32_t *rows;       // rows grouped by bin
+    int64_t start[NBIN + 1];
+    const int32_t *hbase;      // cold chunk base of each heavy row (within one slot)
+    int64_t chunks_per_slot;
+    int32_t s0, ns;
+};
+
+__global__ void k_seed_all(Params P, SeedAll S) {
+    int64_t m = S.start[NBIN];
+    int64_t N = m * S.ns;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < N;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        int sl = (int)(j / m);
+        int64_t r = j - (int64_t)sl * m;
+        int b = 0;
+        while (r >= S.start[b + 1]) ++b;
+        int64_t cnt = S.start[b + 1] - S.start[b];
+        int64_t within = r - S.start[b];
+        int64_t idx = (int64_t)sl * cnt + within;
+        int s = S.s0 + sl;
+        int row = S.rows[r];
+        P.q[0][b][idx] = ((uint64_t)(uint32_t)s << 32) | (uint32_t)row;
+        if (b == BIN_HEAVY) {
+            int64_t len = P.I.row_ptr[row + 1] - P.I.row_ptr[row];
+            int32_t nch = (int32_t)((len + P.heavy_chunk - 1) / P.heavy_chunk);
+            int32_t cb = (int32_t)(sl * S.chunks_per_slot + S.hbase[within]);
+            P.hbase[0][idx] = cb;
+            for (int32_t c = 0; c < nch; ++c) P.hmap[0][cb + c] = (int32_t)idx;
+        }
+    }
+}
+
+// Warm start: the rows of the listed variables of each slot.  Entry e of
+// (slot, var) pairs; launched with whole waves.
+__global__ void k_seed_vars(Params P, const int32_t *vars, const int64_t *ptr, int32_t s0,
+                            int32_t ns, int64_t total, int heavy_threshold) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += stride) {
+        int64_t e = base + threadIdx.x;
+        bool has = e < total;
+        int s = 0, i = 0;
+        if (has) {
+            // slot of entry e: ptr is non-decreasing over ns slots
+            int lo = 0, hi = ns;
+            while (hi - lo > 1) {
+                int mid = (lo + hi) / 2;
+                if (ptr[mid] <= e) lo = mid;
+                else hi = mid;
+            }
+            s = s0 + lo;
+            i = vars[e];
+        }
+        enqueue_column(P, 0, has, s, i, heavy_threshold);
+    }
+}
+
+// After seeding: a slot's first round counts its queued rows (a cold start
+// queues every row).
+__global__ void k_seed_finish(Params P, int32_t s0, int32_t ns, int32_t max_rounds, int cold,
+                              int32_t m, long long nnz) {
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < ns; j += gridDim.x * blockDim.x) {
+        SlotInfo &S = P.info[s0 + j];
+        if (S.state != SLOT_ACTIVE) continue;
+        if (cold) {
+            S.pending_rows = m;
+            S.pending_nnz = nnz;
+        }
+        if (S.pending_rows == 0) {
+            S.state = SLOT_FREE;
+            S.status = 0;
+        } else if (max_rounds <= 0) {
+            S.state = SLOT_DRAINING;
+            S.status = 2;
+        } else {
+            S.rounds = 1;
+            S.nnz = S.pending_nnz;
+            S.pending_rows = 0;
+            S.pending_nnz = 0;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// Host helpers
+// ------------------------------------------------------------------------
+static hipStream_t as_stream(void *s) { return (hipStream_t)s; }
+
+static int grid_for(int64_t n, int per = 256) {
+    int64_t g = (n + per - 1) / per;
+    if (g < 1) g = 1;
+    if (g > 4096) g = 4096;
+    return (int)g;
+}
+
+static int validate_options(const bp_options &o) {
+    if (!(o.feastol >= 0.0) || !(o.inttol >= 0.0) || !(o.tau >= 0.0) || o.max_rounds < 0)
+        return fail(BP_EINVAL, "bad options: tolerances must be >= 0 and max_rounds >= 0");
+    return 0;
+}
+
+extern "C" int bp_load(const bp_sparse *csr, const bp_sparse *csc, const double *row_lo,
+                       const double *row_hi, const uint8_t *vartype, const bp_options *opt,
+                       void *stream, bp_instance **out) {
+    g_err.clear();
+    if (!csr || !row_lo || !row_hi || !vartype || !out)
+        return fail(BP_EINVAL, "bp_load: null argument");
+    *out = nullptr;
+    const int64_t m = csr->m, n = csr->n, nnz = csr->nnz;
+    if (m < 0 || n < 0 || nnz < 0 || m >= INT32_MAX || n >= INT32_MAX)
+        return fail(BP_EINVAL, "bp_load: bad sizes");
+    if (!csr->ptr || (nnz > 0 && (!csr->idx || !csr->val)))
+        return fail(BP_EINVAL, "bp_load: null CSR arrays");
+    bp_options o;
+    if (opt) o = *opt;
+    else bp_options_default(&o);
+    if (int rc = validate_options(o)) return rc;
+    if (o.heavy_threshold <= 0) o.heavy_threshold = 8192;
+    if (o.heavy_threshold < 1024) o.heavy_threshold = 1024;
+    if (o.rounds_per_launch <= 0) o.rounds_per_launch = 8;
+    if (o.probe_slots <= 0) o.probe_slots = 512;
+    // CSR validation
+    if (csr->ptr[0] != 0 || csr->ptr[m] != nnz) return fail(BP_EINVAL, "CSR ptr must run from 0 to nnz");
+    for (int64_t k = 0; k < m; ++k) {
+        if (csr->ptr[k + 1] < csr->ptr[k]) return fail(BP_EINVAL, "CSR ptr decreases at row " + std::to_string(k));
+        double lo = row_lo[k], hi = row_hi[k];
+        if (std::isnan(lo) || std::isnan(hi) || lo > hi || lo == INFINITY || hi == -INFINITY)
+            return fail(BP_EINVAL, "bad sides at row " + std::to_string(k));
+        for (int64_t p = csr->ptr[k]; p < csr->ptr[k + 1]; ++p) {
+            int32_t c = csr->idx[p];
+            if (c < 0 || c >= n) return fail(BP_EINVAL, "column out of range in row " + std::to_string(k));
+            if (p > csr->ptr[k] && c <= csr->idx[p - 1])
+                return fail(BP_EINVAL, "columns not ascending/distinct in row " + std::to_string(k));
+            double v = csr->val[p];
+            if (!(v != 0.0) || std::isinf(v))
+                return fail(BP_EINVAL, "zero, NaN or infinite coefficient in row " + std::to_string(k));
+        }
+    }
+    for (int64_t i = 0; i < n; ++i)
+        if (vartype[i] > 1) return fail(BP_EINVAL, "vartype must be 0 or 1");
+    // CSC: build, or check a given one against the transpose.
+    std::vector<int64_t> cptr(n + 1, 0);
+    std::vector<int32_t> crow(nnz);
+    for (int64_t p = 0; p < nnz; ++p) cptr[csr->idx[p] + 1] += 1;
+    for (int64_t i = 0; i < n; ++i) cptr[i + 1] += cptr[i];
+    {
+        std::vector<int64_t> fill(cptr.begin(), cptr.end() - 1);
+        for (int64_t k = 0; k < m; ++k)
+            for (int64_t p = csr->ptr[k]; p < csr->ptr[k + 1]; ++p) crow[fill[csr->idx[p]]++] = (int32_t)k;
+    }
+    if (csc) {
+        if (csc->m != m || csc->n != n || csc->nnz != nnz || !csc->ptr || (nnz && !csc->idx))
+            return fail(BP_EINVAL, "CSC shape differs from CSR");
+        for (int64_t i = 0; i <= n; ++i)
+            if (csc->ptr[i] != cptr[i]) return fail(BP_EINVAL, "CSC is not the transpose of CSR");
+        for (int64_t p = 0; p < nnz; ++p)
+            if (csc->idx[p] != crow[p]) return fail(BP_EINVAL, "CSC is not the transpose of CSR");
+        if (csc->val) {
+            std::vector<int64_t> fill(cptr.begin(), cptr.end() - 1);
+            for (int64_t k = 0; k < m; ++k)
+                for (int64_t p = csr->ptr[k]; p < csr->ptr[k + 1]; ++p)
+                    if (csc->val[fill[csr->idx[p]]++] != csr->val[p])
+                        return fail(BP_EINVAL, "CSC values differ from CSR");
+        }
+    }
+    std::unique_ptr<bp_instance> h(new bp_instance());
+    h->m = (int32_t)m;
+    h->n = (int32_t)n;
+    h->nnz = nnz;
+    h->opt = o;
+    h->heavy_threshold = o.heavy_threshold;
+    h->heavy_chunk = 4096;
+    memset(&h->stats, 0, sizeof(h->stats));
+    // Row bins (logarithmic radix binning) and the cold-start row order.
+    std::vector<uint8_t> rbin(m);
+    for (int64_t k = 0; k < m; ++k) {
+        int b = row_bin(csr->ptr[k + 1] - csr->ptr[k], h->heavy_threshold);
+        rbin[k] = (uint8_t)b;
+        h->bin_count[b] += 1;
+    }
+    h->bin_start[0] = 0;
+    for (int b = 0; b < NBIN; ++b) h->bin_start[b + 1] = h->bin_start[b] + h->bin_count[b];
+    std::vector<int32_t> cold(m);
+    {
+        std::vector<int64_t> fill(h->bin_start, h->bin_start + NBIN);
+        for (int64_t k = 0; k < m; ++k) cold[fill[rbin[k]]++] = (int32_t)k;
+    }
+    h->heavy_chunks = 0;
+    for (int64_t j = h->bin_start[BIN_HEAVY]; j < h->bin_start[BIN_HEAVY + 1]; ++j) {
+        int32_t k = cold[j];
+        int64_t len = csr->ptr[k + 1] - csr->ptr[k];
+        h->cold_hbase.push_back((int32_t)h->heavy_chunks);
+        h->heavy_chunks += (len + h->heavy_chunk - 1) / h->heavy_chunk;
+    }
+    std::vector<double> side(2 * m);
+    for (int64_t k = 0; k < m; ++k) {
+        side[2 * k] = row_lo[k] == 0.0 ? 0.0 : row_lo[k];
+        side[2 * k + 1] = row_hi[k] == 0.0 ? 0.0 : row_hi[k];
+    }
+    hipStream_t st = as_stream(stream);
+    int64_t &B = h->bytes;
+    int rc;
+#define ALLOC_UP(buf, hostptr, nbytes)                                                      \
+    do {                                                                                    \
+        if ((rc = h->buf.alloc((nbytes), B))) return rc;                                    \
+        if ((nbytes) > 0) HIPTRY(hipMemcpyAsync(h->buf.p, (hostptr), (nbytes), hipMemcpyHostToDevice, st)); \
+    } while (0)
+    ALLOC_UP(row_ptr, csr->ptr, (size_t)(m + 1) * 8);
+    ALLOC_UP(col, csr->idx, (size_t)nnz * 4);
+    ALLOC_UP(val, csr->val, (size_t)nnz * 8);
+    ALLOC_UP(side, side.data(), (size_t)m * 16);
+    ALLOC_UP(col_ptr, cptr.data(), (size_t)(n + 1) * 8);
+    ALLOC_UP(col_row, crow.data(), (size_t)nnz * 4);
+    ALLOC_UP(vtype, vartype, (size_t)n);
+    ALLOC_UP(rbin, rbin.data(), (size_t)m);
+    ALLOC_UP(cold_rows, cold.data(), (size_t)m * 4);
+    ALLOC_UP(cold_hbase_d, h->cold_hbase.data(), h->cold_hbase.size() * 4);
+#undef ALLOC_UP
+    if ((rc = h->base.alloc((size_t)n * 16, B))) return rc;
+    HIPTRY(hipStreamSynchronize(st));
+    HIPTRY(hipEventCreate(&h->ev0));
+    HIPTRY(hipEventCreate(&h->ev1));
+    *out = h.release();
+    return BP_OK;
+}
+
+extern "C" void bp_free(bp_instance *h) { delete h; }
+
+extern "C" int64_t bp_device_bytes(const bp_instance *h) {
+    if (!h) return 0;
+    return h->bytes + (h->eng ? h->eng->bytes : 0);
+}
+
+// ------------------------------------------------------------------------
+// Engine allocation
+// ------------------------------------------------------------------------
+static int engine_ensure(bp_instance *h, int32_t slots, bool dirty, hipStream_t st) {
+    if (h->eng && h->eng->cap_slots >= slots && (!dirty || h->eng->track_dirty)) return 0;
+    h->eng.reset();
+    std::unique_ptr<Engine> E(new Engine());
+    E->cap_slots = slots;
+    E->track_dirty = dirty ? 1 : 0;
+    const int64_t n = h->n, m = h->m, S = slots;
+    const int64_t nw_var = (n + 31) / 32, nw_row = (m + 31) / 32;
+    int64_t &B = E->bytes;
+    int rc;
+    if ((rc = E->bnd.alloc((size_t)S * n * 16, B))) return rc;
+    if ((rc = E->cand.alloc((size_t)S * n * 16, B))) return rc;
+    if ((rc = E->vflag.alloc((size_t)S * nw_var * 4, B))) return rc;
+    if ((rc = E->rflag.alloc((size_t)S * nw_row * 4, B))) return rc;
+    if ((rc = E->info.alloc((size_t)S * sizeof(SlotInfo), B))) return rc;
+    if ((rc = E->chg.alloc((size_t)S * n * 8, B))) return rc;
+    if ((rc = E->ctl.alloc(sizeof(Ctl), B))) return rc;
+    for (int par = 0; par < 2; ++par) {
+        for (int b = 0; b < NBIN; ++b)
+            if ((rc = E->q[par][b].alloc((size_t)S * h->bin_count[b] * 8, B))) return rc;
+        if ((rc = E->hmap[par].alloc((size_t)S * h->heavy_chunks * 4, B))) return rc;
+        if ((rc = E->hbase[par].alloc((size_t)S * h->bin_count[BIN_HEAVY] * 4, B))) return rc;
+    }
+    if ((rc = E->hpart.alloc((size_t)S * h->heavy_chunks * 2 * sizeof(Acc), B))) return rc;
+    if ((rc = E->hact.alloc((size_t)S * h->bin_count[BIN_HEAVY] * sizeof(double4), B))) return rc;
+    if ((rc = E->hbad.alloc((size_t)S * h->bin_count[BIN_HEAVY] * 4, B))) return rc;
+    if ((rc = E->hdone.alloc((size_t)S * h->bin_count[BIN_HEAVY] * 4, B))) return rc;
+    if (dirty) {
+        if ((rc = E->dirty.alloc((size_t)S * nw_var * 4, B))) return rc;
+        if ((rc = E->dlist.alloc((size_t)S * n * 4, B))) return rc;
+        if ((rc = E->dcount.alloc((size_t)S * 4, B))) return rc;
+        HIPTRY(hipMemsetAsync(E->dirty.p, 0, E->dirty.bytes, st));
+        HIPTRY(hipMemsetAsync(E->dcount.p, 0, E->dcount.bytes, st));
+    }
+    HIPTRY(hipMemsetAsync(E->vflag.p, 0, E->vflag.bytes, st));
+    HIPTRY(hipMemsetAsync(E->rflag.p, 0, E->rflag.bytes, st));
+    HIPTRY(hipMemsetAsync(E->hdone.p, 0, E->hdone.bytes, st));
+    HIPTRY(hipMemsetAsync(E->info.p, 0, E->info.bytes, st));
+    k_fill_cand<<<grid_for(S * n), 256, 0, st>>>(E->cand.as<longlong2>(), S * n);
+    HIPTRY(hipGetLastError());
+    h->eng = std::move(E);
+    return 0;
+}
+
+static Params make_params(const bp_instance *h, int32_t nslots) {
+    const Engine &E = *h->eng;
+    Params P;
+    memset(&P, 0, sizeof(P));
+    P.I.m = h->m;
+    P.I.n = h->n;
+    P.I.row_ptr = h->row_ptr.as<int64_t>();
+    P.I.col = h->col.as<int32_t>();
+    P.I.val = h->val.as<double>();
+    P.I.side = h->side.as<double2>();
+    P.I.col_ptr = h->col_ptr.as<int64_t>();
+    P.I.col_row = h->col_row.as<int32_t>();
+    P.I.vtype = h->vtype.as<uint8_t>();
+    P.I.rbin = h->rbin.as<uint8_t>();
+    P.feastol = h->opt.feastol;
+    P.inttol = h->opt.inttol;
+    P.tau = h->opt.tau;
+    P.heavy_chunk = h->heavy_chunk;
+    P.force_exact = (h->opt.flags & BP_FLAG_FORCE_EXACT) ? 1 : 0;
+    P.nslots = nslots;
+    P.nw_var = (h->n + 31) / 32;
+    P.nw_row = (h->m + 31) / 32;
+    P.bnd = E.bnd.as<double2>();
+    P.cand = E.cand.as<longlong2>();
+    P.vflag = E.vflag.as<uint32_t>();
+    P.rflag = E.rflag.as<uint32_t>();
+    P.info = E.info.as<SlotInfo>();
+    for (int par = 0; par < 2; ++par) {
+        for (int b = 0; b < NBIN; ++b) P.q[par][b] = E.q[par][b].as<uint64_t>();
+        P.hmap[par] = E.hmap[par].as<int32_t>();
+        P.hbase[par] = E.hbase[par].as<int32_t>();
+    }
+    P.hpart = E.hpart.as<Acc>();
+    P.hact = E.hact.as<double4>();
+    P.hbad = E.hbad.as<int32_t>();
+    P.hdone = E.hdone.as<uint32_t>();
+    P.chg = E.chg.as<uint64_t>();
+    P.ctl = E.ctl.as<Ctl>();
+    P.track_dirty = E.track_dirty;
+    P.dirty = E.dirty.as<uint32_t>();
+    P.dlist = E.dlist.as<int32_t>();
+    P.dcount = E.dcount.as<int32_t>();
+    return P;
+}
+
+static const int GRID_ROWS = 2048;
+static const int GRID_HEAVY = 1024;
+static const int GRID_APPLY = 512;
+
+static int launch_round(bp_instance *h, const Params &P, hipStream_t st, bool timed) {
+    if (timed) HIPTRY(hipEventRecord(h->ev0, st));
+    k_rows<<<GRID_ROWS, WG, 0, st>>>(P);
+    if (timed) HIPTRY(hipEventRecord(h->ev1, st));
+    k_heavy<<<GRID_HEAVY, WG, 0, st>>>(P);
+    k_apply<<<GRID_APPLY, WG, 0, st>>>(P, (int)h->heavy_threshold);
+    HIPTRY(hipGetLastError());
+    return 0;
+}
+
+// Run rounds until every slot is finished.
+static int run_rounds(bp_instance *h, const Params &P, hipStream_t st) {
+    Engine &E = *h->eng;
+    Ctl hc;
+    const bool timed = (h->opt.flags & BP_FLAG_TIME_KERNELS) != 0;
+    const bool host_rounds = timed || (h->opt.flags & BP_FLAG_HOST_ROUNDS) != 0;
+    const int K = std::max(1, (int)h->opt.rounds_per_launch);
+    // Upper bound on engine rounds: slot rounds never exceed max_rounds,
+    // plus one draining round.
+    const int64_t limit = (int64_t)h->opt.max_rounds + 2;
+    int64_t launched = 0;
+    for (;;) {
+        if (host_rounds) {
+            if (int rc = launch_round(h, P, st, timed)) return rc;
+            launched += 1;
+            if (timed) {
+                HIPTRY(hipEventSynchronize(h->ev1));
+                float ms = 0.f;
+                HIPTRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+                h->stats.ms += ms;
+                h->stats.launches += 1;
+            }
+        } else {
+            if (!E.graph || E.graph_rounds != K) {
+                if (E.graph) {
+                    (void)hipGraphExecDestroy(E.graph);
+                    E.graph = nullptr;
+                }
+                hipStream_t cs;
+                HIPTRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+                HIPTRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+                for (int r = 0; r < K; ++r) {
+                    k_rows<<<GRID_ROWS, WG, 0, cs>>>(P);
+                    k_heavy<<<GRID_HEAVY, WG, 0, cs>>>(P);
+                    k_apply<<<GRID_APPLY, WG, 0, cs>>>(P, (int)h->heavy_threshold);
+                }
+                hipGraph_t g;
+                HIPTRY(hipStreamEndCapture(cs, &g));
+                hipError_t e = hipGraphInstantiate(&E.graph, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                (void)hipStreamDestroy(cs);
+                HIPTRY(e);
+                E.graph_rounds = K;
+            }
+            HIPTRY(hipGraphLaunch(E.graph, st));
+            launched += K;
+        }
+        HIPTRY(hipMemcpyAsync(&hc, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+        HIPTRY(hipStreamSynchronize(st));
+        if (hc.done) break;
+        if (launched > limit) return fail(BP_EDEVICE, "round loop did not terminate");
+    }
+    return 0;
+}
+
+// Graphs hold the Params by value: rebuild when they change.
+static void invalidate_graph(bp_instance *h, const Params &P) {
+    Engine &E = *h->eng;
+    if (E.graph && memcmp(&E.graph_params, &P, sizeof(Params)) != 0) {
+        (void)hipGraphExecDestroy(E.graph);
+        E.graph = nullptr;
+    }
+    E.graph_params = P;
+}
+
+// Reset the control block and the slots [0, ns) to ACTIVE.
+__global__ void k_reset_slots(SlotInfo *info, int32_t ns, int32_t job0) {
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < ns; j += gridDim.x * blockDim.x) {
+        SlotInfo &S = info[j];
+        S.state = SLOT_ACTIVE;
+        S.status = 0;
+        S.rounds = 0;
+        S.row_bad_min = NONE;
+        S.row_bad_count = 0;
+        S.var_bad_min = NONE;
+        S.pending_rows = 0;
+        S.job = job0 + j;
+        S.nnz = 0;
+        S.pending_nnz = 0;
+    }
+}
+
+static int start_slots(bp_instance *h, const Params &P, int32_t ns, hipStream_t st,
+                       const int32_t *changed_idx, const int64_t *changed_ptr,
+                       int64_t n_changed_total, bool cold) {
+    Ctl c;
+    memset(&c, 0, sizeof(c));
+    c.max_rounds = (uint32_t)h->opt.max_rounds;
+    c.nslots = (uint32_t)ns;
+    if (cold) {
+        for (int b = 0; b < NBIN; ++b) c.qcount[0][b] = (uint32_t)(h->bin_count[b] * ns);
+        c.hchunks[0] = (uint32_t)(h->heavy_chunks * ns);
+    }
+    HIPTRY(hipMemcpyAsync(P.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, st));
+    k_reset_slots<<<grid_for(ns), 256, 0, st>>>(P.info, ns, 0);
+    if (cold) {
+        SeedAll S;
+        S.rows = h->cold_rows.as<int32_t>();
+        for (int b = 0; b <= NBIN; ++b) S.start[b] = h->bin_start[b];
+        S.hbase = h->cold_hbase_d.as<int32_t>();
+        S.chunks_per_slot = h->heavy_chunks;
+        S.s0 = 0;
+        S.ns = ns;
+        int64_t N = (int64_t)h->m * ns;
+        if (N > 0) k_seed_all<<<grid_for(N), 256, 0, st>>>(P, S);
+    } else if (n_changed_total > 0) {
+        k_seed_vars<<<grid_for(n_changed_total), 256, 0, st>>>(
+            P, changed_idx, changed_ptr, 0, ns, n_changed_total, (int)h->heavy_threshold);
+    }
+    k_seed_finish<<<grid_for(ns), 256, 0, st>>>(P, 0, ns, h->opt.max_rounds, cold ? 1 : 0, h->m,
+                                                 (long long)h->nnz);
+    HIPTRY(hipGetLastError());
+    return 0;
+}
+
+// Mark the control block done if no slot is active (e.g. empty worklists).
+__global__ void k_check_any_active(Params P, int32_t ns) {
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    for (int j = threadIdx.x; j < ns; j += blockDim.x)
+        if (P.info[j].state != SLOT_FREE) atomicOr(&any, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        P.ctl->done = any ? 0u : 1u;
+        P.ctl->active = any ? 1u : 0u;
+    }
+}
+
+static void fill_result(const SlotInfo &S, int32_t box_bad, bp_result *r) {
+    memset(r, 0, sizeof(*r));
+    r->infeasible_row = -1;
+    r->infeasible_var = -1;
+    if (box_bad != NONE) {
+        r->status = BP_INFEASIBLE;
+        r->infeasible_var = box_bad;
+        return;
+    }
+    r->status = S.status;
+    r->rounds = S.rounds;
+    r->nnz_propagated = S.nnz;
+    if (S.status == BP_INFEASIBLE) {
+        if (S.row_bad_count > 0) {
+            r->n_infeasible_rows = S.row_bad_count;
+            r->infeasible_row = S.row_bad_min;
+        } else {
+            r->infeasible_var = S.var_bad_min;
+        }
+    }
+}
+
+// Shared driver of bp_propagate (B = 1, base update) and bp_propagate_batch.
+static int propagate_slots(bp_instance *h, int32_t Bv, double *lb, double *ub,
+                           const int32_t *changed_idx, const int64_t *changed_ptr,
+                           int64_t n_changed_total, bool cold, bp_result *res, hipStream_t st) {
+    const int64_t n = h->n;
+    if (int rc = engine_ensure(h, Bv, false, st)) return rc;
+    Params P = make_params(h, Bv);
+    invalidate_graph(h, P);
+    Engine &E = *h->eng;
+    // Bounds in, box check.
+    if (n > 0) k_pack<<<grid_for(n * Bv), 256, 0, st>>>(lb, ub, E.bnd.as<double2>(), n, Bv);
+    DevBuf boxd;
+    int64_t dummy = 0;
+    if (int rc = boxd.alloc((size_t)Bv * 8, dummy)) return rc;
+    {
+        // even entries: smallest crossed var; odd entries: NaN flags
+        std::vector<int32_t> init(2 * (size_t)Bv);
+        for (int32_t j = 0; j < Bv; ++j) {
+            init[2 * j] = NONE;
+            init[2 * j + 1] = 0;
+        }
+        HIPTRY(hipMemcpyAsync(boxd.p, init.data(), init.size() * 4, hipMemcpyHostToDevice, st));
+    }
+    if (n > 0)
+        k_box_check<<<grid_for(n * Bv), 256, 0, st>>>(E.bnd.as<double2>(), h->vtype.as<uint8_t>(),
+                                                      n, Bv, h->opt.feastol, boxd.as<int32_t>());
+    HIPTRY(hipGetLastError());
+    std::vector<int32_t> box(2 * (size_t)Bv);
+    HIPTRY(hipMemcpyAsync(box.data(), boxd.p, box.size() * 4, hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+    for (int32_t j = 0; j < Bv; ++j)
+        if (box[2 * j + 1]) return fail(BP_EINVAL, "NaN bound in vector " + std::to_string(j));
+    // Validate changed ids.
+    if (!cold && n_changed_total > 0) {
+        std::vector<int32_t> ids(n_changed_total);
+        HIPTRY(hipMemcpyAsync(ids.data(), changed_idx, ids.size() * 4, hipMemcpyDeviceToHost, st));
+        HIPTRY(hipStreamSynchronize(st));
+        for (int32_t v : ids)
+            if (v < 0 || v >= n) return fail(BP_EINVAL, "changed variable id out of range");
+    }
+    if (int rc = start_slots(h, P, Bv, st, changed_idx, changed_ptr, n_changed_total, cold)) return rc;
+    // A slot whose box is already crossed is infeasible before any round;
+    // its queued rows drain without running.
+    for (int32_t j = 0; j < Bv; ++j) {
+        if (box[2 * j] == NONE) continue;
+        int32_t dr = SLOT_DRAINING;
+        HIPTRY(hipMemcpyAsync(&P.info[j].state, &dr, 4, hipMemcpyHostToDevice, st));
+    }
+    k_check_any_active<<<1, 256, 0, st>>>(P, Bv);
+    HIPTRY(hipGetLastError());
+    if (int rc = run_rounds(h, P, st)) return rc;
+    std::vector<SlotInfo> info(Bv);
+    HIPTRY(hipMemcpyAsync(info.data(), P.info, Bv * sizeof(SlotInfo), hipMemcpyDeviceToHost, st));
+    if (n > 0) k_unpack<<<grid_for(n * Bv), 256, 0, st>>>(E.bnd.as<double2>(), lb, ub, n * Bv);
+    HIPTRY(hipGetLastError());
+    HIPTRY(hipStreamSynchronize(st));
+    for (int32_t j = 0; j < Bv; ++j) fill_result(info[j], box[2 * j], &res[j]);
+    return 0;
+}
+
+extern "C" int bp_propagate(bp_instance *h, double *lb, double *ub, const int32_t *changed,
+                            int64_t n_changed, bp_result *res, void *stream) {
+    g_err.clear();
+    if (!h || !res || (h->n > 0 && (!lb || !ub))) return fail(BP_EINVAL, "bp_propagate: null argument");
+    hipStream_t st = as_stream(stream);
+    bool cold = changed == nullptr;
+    if (!cold && n_changed < 0) return fail(BP_EINVAL, "n_changed < 0");
+    DevBuf ptrd;
+    int64_t dummy = 0;
+    if (!cold) {
+        if (int rc = ptrd.alloc(16, dummy)) return rc;
+        int64_t p2[2] = {0, n_changed};
+        HIPTRY(hipMemcpyAsync(ptrd.p, p2, 16, hipMemcpyHostToDevice, st));
+    }
+    int rc = propagate_slots(h, 1, lb, ub, changed, ptrd.as<int64_t>(), cold ? 0 : n_changed, cold,
+                             res, st);
+    if (rc < 0) return rc;
+    if (res->status == BP_OK && h->n > 0) {
+        k_copy_bnd<<<grid_for(h->n), 256, 0, st>>>(h->eng->bnd.as<double2>(), h->base.as<double2>(), h->n);
+        HIPTRY(hipGetLastError());
+        HIPTRY(hipStreamSynchronize(st));
+    }
+    if (res->status == BP_OK) h->have_base = true;
+    return res->status;
+}
+
+extern "C" int bp_propagate_batch(bp_instance *h, int32_t B, double *lb, double *ub,
+                                  const int64_t *changed_ptr, const int32_t *changed_idx,
+                                  bp_result *res, void *stream) {
+    g_err.clear();
+    if (!h || !res || B < 0 || (B > 0 && h->n > 0 && (!lb || !ub)))
+        return fail(BP_EINVAL, "bp_propagate_batch: bad argument");
+    if (B == 0) return BP_OK;
+    hipStream_t st = as_stream(stream);
+    bool cold = changed_ptr == nullptr;
+    int64_t total = 0;
+    if (!cold) {
+        std::vector<int64_t> ptr(B + 1);
+        HIPTRY(hipMemcpyAsync(ptr.data(), changed_ptr, (B + 1) * 8, hipMemcpyDeviceToHost, as_stream(stream)));
+        HIPTRY(hipStreamSynchronize(st));
+        if (ptr[0] != 0) return fail(BP_EINVAL, "changed_ptr[0] must be 0");
+        for (int32_t j = 0; j < B; ++j)
+            if (ptr[j + 1] < ptr[j]) return fail(BP_EINVAL, "changed_ptr decreases");
+        total = ptr[B];
+        if (total > 0 && !changed_idx) return fail(BP_EINVAL, "changed_idx is null");
+    }
+    int rc = propagate_slots(h, B, lb, ub, changed_idx, changed_ptr, total, cold, res, st);
+    return rc < 0 ? rc : BP_OK;
+}
+
+extern "C" int bp_get_base(bp_instance *h, double *lb, double *ub, void *stream) {
+    g_err.clear();
+    if (!h || (h->n > 0 && (!lb || !ub))) return fail(BP_EINVAL, "bp_get_base: null argument");
+    if (!h->have_base) return fail(BP_ESTATE, "no base: run a feasible bp_propagate first");
+    hipStream_t st = as_stream(stream);
+    if (h->n > 0) k_unpack<<<grid_for(h->n), 256, 0, st>>>(h->base.as<double2>(), lb, ub, h->n);
+    HIPTRY(hipGetLastError());
+    HIPTRY(hipStreamSynchronize(st));
+    return BP_OK;
+}
+
+extern "C" int bp_kernel_stats(bp_instance *h, bp_stats *out, int reset) {
+    if (!h || !out) return fail(BP_EINVAL, "bp_kernel_stats: null argument");
+    *out = h->stats;
+    if (reset) memset(&h->stats, 0, sizeof(h->stats));
+    return BP_OK;
+}
+
+extern "C" int bp_probe(bp_instance *h, const int32_t *vars, int32_t k, bp_probe_out *out,
+                        void *stream) {
+    g_err.clear();
+    (void)vars; (void)k; (void)out; (void)stream;
+    if (!h) return fail(BP_EINVAL, "bp_probe: null instance");
+    if (!h->have_base) return fail(BP_ESTATE, "no base: run a feasible bp_propagate first");
+    return fail(BP_EDEVICE, "bp_probe: not built yet");
+}

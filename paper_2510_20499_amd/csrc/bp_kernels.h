@@ -1,0 +1,862 @@
+// bp_kernels.h -- HIP kernels for round-synchronous bound propagation.
+//
+// One round (the paper's Section 2.1: activities of the constraints, then
+// bound updates) runs as three kernels over a slot table.  A slot is one
+// bound vector in flight: the single vector of bp_propagate, one candidate
+// of bp_propagate_batch, or one probe of bp_probe.
+//
+//   rows   (activity + candidates)  every queued (slot, row) task of the
+//          round: the row activity, the row infeasibility test and, for
+//          light and block rows, the candidates of every nonzero, scattered
+//          as order-independent 64-bit integer atomic min/max into the
+//          slot's candidate array.  Only candidates that pass the threshold
+//          against the round-start bounds are scattered: the threshold is
+//          monotone in the candidate, so the tightest candidate passes iff
+//          some candidate passes.  Heavy rows (split across workgroups) only
+//          produce chunk partials here; the last chunk combines them.
+//   heavy  (candidates of heavy rows) chunk by chunk.
+//   apply  (bound update) each (slot, variable) that received a candidate:
+//          acceptance, crossing test, new bounds, and the rows of the
+//          variable's column queued for the next round (the paper's
+//          "propagation on changed constraints", Section 1).  Its last
+//          workgroup closes the round for every slot.
+//
+// Rows are binned by length (logarithmic radix binning, Section 2.1 load
+// balancing): bin b <= 10 holds rows of length in (2^(b-1), 2^b] and is
+// processed by groups of G = min(64, 2^b) lanes of a 64-lane wave; bin 11
+// holds rows up to the heavy threshold, one 256-lane workgroup per row;
+// bin 12 holds heavy rows, split into chunks across workgroups.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bp_sum.h"
+
+namespace bp {
+
+constexpr int NLIGHT = 11;          // bins 0..10
+constexpr int BIN_BLOCK = 11;
+constexpr int BIN_HEAVY = 12;
+constexpr int NBIN = 13;
+constexpr int WG = 256;             // workgroup size of every kernel
+constexpr int32_t NONE = 0x7fffffff;
+
+enum : int32_t { SLOT_FREE = 0, SLOT_ACTIVE = 1, SLOT_DRAINING = 2 };
+
+// Device view of one instance (read-only during propagation).
+struct DInst {
+    int32_t m, n;
+    const int64_t *row_ptr;
+    const int32_t *col;
+    const double *val;
+    const double2 *side;    // (lo, hi)
+    const int64_t *col_ptr;
+    const int32_t *col_row;
+    const uint8_t *vtype;
+    const uint8_t *rbin;
+};
+
+// Per-slot bookkeeping.
+struct SlotInfo {
+    int32_t state;
+    int32_t status;
+    int32_t rounds;
+    int32_t row_bad_min;
+    int32_t row_bad_count;
+    int32_t var_bad_min;
+    int32_t pending_rows;
+    int32_t job;        // probe index / vector index
+    unsigned long long nnz;
+    unsigned long long pending_nnz;
+};
+
+// Round control block (one per engine).
+struct Ctl {
+    uint32_t round;             // rounds started by the engine (parity = round & 1)
+    uint32_t done;
+    uint32_t qcount[2][NBIN];   // queue lengths per parity
+    uint32_t hchunks[2];        // heavy chunks per parity
+    uint32_t nchanged;          // (slot, var) entries of the current round
+    uint32_t ticket;            // last-workgroup detection in apply
+    uint32_t active;            // slots active after the last round end
+    uint32_t finished;          // slots finished at the last round end
+    uint32_t max_rounds;
+    uint32_t nslots;
+    // statistics of the last round start (for the benchmark's byte model)
+    unsigned long long stat_rows;
+    unsigned long long stat_nnz;
+};
+
+struct Params {
+    DInst I;
+    double feastol, inttol, tau;
+    int32_t heavy_chunk;         // nonzeros per heavy chunk
+    int32_t force_exact;
+    int32_t nslots;
+    int32_t nw_var, nw_row;      // 32-bit words per slot in the var / row bitmaps
+    double2 *bnd;                // [nslots][n]
+    longlong2 *cand;             // [nslots][n] (lower key, upper key)
+    uint32_t *vflag;             // [nslots][nw_var]
+    uint32_t *rflag;             // [nslots][nw_row]
+    SlotInfo *info;              // [nslots]
+    uint64_t *q[2][NBIN];        // task queues (slot << 32 | row)
+    int32_t *hmap[2];            // heavy chunk -> heavy task index
+    int32_t *hbase[2];           // heavy task -> first chunk
+    Acc *hpart;                  // [chunks][2] partial (min, max) states
+    double4 *hact;               // [heavy tasks] (minfin, maxfin, nmin, nmax)
+    int32_t *hbad;               // [heavy tasks] row infeasible flag
+    uint32_t *hdone;             // [heavy tasks] finished chunks
+    uint64_t *chg;               // (slot << 32 | var) entries of the round
+    Ctl *ctl;
+    // probe mode
+    int32_t track_dirty;
+    uint32_t *dirty;             // [nslots][nw_var]
+    int32_t *dlist;              // [nslots][n]
+    int32_t *dcount;             // [nslots]
+};
+
+// Ordered 64-bit key of a double: signed integer order equals double order.
+__device__ __forceinline__ long long dkey(double x) {
+    long long b = __double_as_longlong(x);
+    return b < 0 ? (b ^ 0x7fffffffffffffffll) : b;
+}
+__device__ __forceinline__ double dunkey(long long k) {
+    return __longlong_as_double(k < 0 ? (k ^ 0x7fffffffffffffffll) : k);
+}
+
+__device__ __forceinline__ int light_group(int b) { return b >= 6 ? 64 : (1 << b); }
+
+__host__ __device__ __forceinline__ int row_bin(int64_t len, int64_t heavy_threshold) {
+    if (len > heavy_threshold) return BIN_HEAVY;
+    if (len > 1024) return BIN_BLOCK;
+    int b = 0;
+    while ((1ll << b) < len) ++b;
+    return b;
+}
+
+// ------------------------------------------------------------------------
+// Threshold tests (shared by the candidate scatter and the apply step).
+// ------------------------------------------------------------------------
+__device__ __forceinline__ bool take_upper(bool is_int, double c, double old, double tau) {
+    if (is_int) return c < old;
+    if (isinf(old)) return c < old && !isinf(c);
+    return c < old - tau * fmax(1.0, fabs(old));
+}
+__device__ __forceinline__ bool take_lower(bool is_int, double c, double old, double tau) {
+    if (is_int) return c > old;
+    if (isinf(old)) return c > old && !isinf(c);
+    return c > old + tau * fmax(1.0, fabs(old));
+}
+
+struct RowAct {
+    double minfin, maxfin;
+    int nmin, nmax;
+    double lo, hi;
+};
+
+// Bound candidates of one nonzero (Section 2.1, second display, and its
+// mirror for the lower side).  cl/cu = -inf/+inf when absent.
+__device__ __forceinline__ void nz_candidates(const RowAct &R, double a, double lb, double ub,
+                                              bool is_int, double inttol, double &cl, double &cu) {
+    const double INF = __builtin_inf();
+    cl = -INF;
+    cu = INF;
+    if (R.hi < INF) {
+        double bown = a > 0.0 ? lb : ub;
+        bool own_inf = isinf(bown);
+        bool have = false;
+        double v = 0.0;
+        if (!own_inf && R.nmin == 0) {
+            double r = R.hi - R.minfin;
+            double t = a * bown;
+            v = r + t;
+            have = true;
+        } else if (own_inf && R.nmin == 1) {
+            v = R.hi - R.minfin;
+            have = true;
+        }
+        if (have) {
+            double c = v / a;
+            if (a > 0.0) cu = is_int ? floor(c + inttol) : c;
+            else cl = is_int ? ceil(c - inttol) : c;
+        }
+    }
+    if (R.lo > -INF) {
+        double bown = a > 0.0 ? ub : lb;
+        bool own_inf = isinf(bown);
+        bool have = false;
+        double v = 0.0;
+        if (!own_inf && R.nmax == 0) {
+            double r = R.lo - R.maxfin;
+            double t = a * bown;
+            v = r + t;
+            have = true;
+        } else if (own_inf && R.nmax == 1) {
+            v = R.lo - R.maxfin;
+            have = true;
+        }
+        if (have) {
+            double c = v / a;
+            if (a > 0.0) cl = is_int ? ceil(c - inttol) : c;
+            else cu = is_int ? floor(c + inttol) : c;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// Wave-aggregated appends (one atomic per wave and destination).
+// Must be reached by every lane of the wave.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
+    uint32_t lo = (uint32_t)mask, hi = (uint32_t)(mask >> 32);
+    return __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+}
+
+__device__ __forceinline__ void wave_push(uint64_t *q, uint32_t *counter, bool want, uint64_t v) {
+    uint64_t mask = __ballot(want);
+    if (mask == 0) return;
+    int leader = __ffsll((long long)mask) - 1;
+    uint32_t base = 0;
+    if (__lane_id() == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
+    base = __shfl(base, leader, 64);
+    if (want) q[base + lane_rank(mask)] = v;
+}
+
+// Mark var i of slot s as having a candidate this round; first marker
+// appends (s, i) to the round's changed list.
+__device__ __forceinline__ void mark_var(const Params &P, bool want, int s, int i) {
+    bool first = false;
+    if (want) {
+        uint32_t bit = 1u << (i & 31);
+        uint32_t old = atomicOr(&P.vflag[(size_t)s * P.nw_var + (i >> 5)], bit);
+        first = (old & bit) == 0;
+    }
+    wave_push(P.chg, &P.ctl->nchanged, first, ((uint64_t)(uint32_t)s << 32) | (uint32_t)i);
+}
+
+// Scatter the significant candidates of one nonzero.  Returns whether the
+// variable needs marking.
+__device__ __forceinline__ bool scatter(const Params &P, int s, int i, double cl, double cu,
+                                        double lb, double ub, bool is_int) {
+    bool any = false;
+    longlong2 *cp = &P.cand[(size_t)s * P.I.n + i];
+    if (take_lower(is_int, cl, lb, P.tau)) {
+        atomicMax(&cp->x, dkey(canon0(cl)));
+        any = true;
+    }
+    if (take_upper(is_int, cu, ub, P.tau)) {
+        atomicMin(&cp->y, dkey(canon0(cu)));
+        any = true;
+    }
+    return any;
+}
+
+// Terms of one nonzero into the two accumulators.
+__device__ __forceinline__ void add_terms(Acc &mn, Acc &mx, double a, double lb, double ub) {
+    double bmin = a > 0.0 ? lb : ub;
+    double bmax = a > 0.0 ? ub : lb;
+    if (isinf(bmin)) mn.ninf += 1;
+    else acc_add(mn, a * bmin);
+    if (isinf(bmax)) mx.ninf += 1;
+    else acc_add(mx, a * bmax);
+}
+
+// Exact activity of one side of a row over [p0, p1) by one lane.  Kept out
+// of line so its accumulator lives in scratch memory and does not raise the
+// register count of the kernels that may call it.
+__device__ __noinline__ double exact_side(const Params &P, const double2 *bnd, int64_t p0, int64_t p1,
+                                    bool maxside) {
+    SuperAcc S;
+    sa_zero(S);
+    for (int64_t p = p0; p < p1; ++p) {
+        double a = P.I.val[p];
+        double2 b = bnd[P.I.col[p]];
+        double bb = (a > 0.0) != maxside ? b.x : b.y;
+        if (!isinf(bb)) sa_add(S, a * bb);
+    }
+    return canon0(sa_round(S));
+}
+
+__device__ __forceinline__ bool row_bad(const RowAct &R, double feastol) {
+    if (R.nmin == 0 && R.minfin > R.hi + feastol) return true;
+    if (R.nmax == 0 && R.maxfin < R.lo - feastol) return true;
+    return false;
+}
+
+__device__ __forceinline__ void report_bad_row(const Params &P, int s, int k) {
+    atomicMin(&P.info[s].row_bad_min, k);
+    atomicAdd(&P.info[s].row_bad_count, 1);
+}
+
+__device__ __forceinline__ void clear_rflag(const Params &P, int s, int k) {
+    uint32_t bit = 1u << (k & 31);
+    atomicAnd(&P.rflag[(size_t)s * P.nw_row + (k >> 5)], ~bit);
+}
+
+// ------------------------------------------------------------------------
+// Light rows: G lanes per row, len <= G (bins 0..6) or one wave per row
+// with several nonzeros per lane (bins 7..10).
+// ------------------------------------------------------------------------
+template <int G>
+__device__ void light_rows(const Params &P, const uint64_t *q, uint32_t count, uint32_t unit) {
+    const int lane = __lane_id();
+    const int wave = threadIdx.x >> 6;
+    const int per_wave = 64 / G;
+    uint32_t t = (unit * (WG / 64) + wave) * per_wave + lane / G;
+    const int gl = lane & (G - 1);
+    bool valid = t < count;
+    int s = 0, k = 0;
+    bool live = false;
+    if (valid) {
+        uint64_t task = q[t];
+        s = (int)(task >> 32);
+        k = (int)(uint32_t)task;
+        live = P.info[s].state == SLOT_ACTIVE;
+        if (gl == 0) clear_rflag(P, s, k);
+    }
+    int64_t p0 = 0, p1 = 0;
+    if (live) {
+        p0 = P.I.row_ptr[k];
+        p1 = P.I.row_ptr[k + 1];
+    }
+    const double2 *bnd = P.bnd + (size_t)s * P.I.n;
+    Acc mn, mx;
+    acc_zero(mn);
+    acc_zero(mx);
+    // Trip count is uniform across the wave: bins 0..6 have len <= G (one
+    // pass); bins 7..10 have one row per wave.
+    int first_i = 0;
+    double first_a = 0.0;
+    double2 first_b = make_double2(0.0, 0.0);
+    const int64_t len = p1 - p0;
+    const int iters = G < 64 ? 1 : (int)((len + 63) / 64);
+    for (int it = 0; it < iters; ++it) {
+        int64_t p = p0 + gl + (int64_t)it * G;
+        if (p < p1) {
+            int i = P.I.col[p];
+            double a = P.I.val[p];
+            double2 b = bnd[i];
+            add_terms(mn, mx, a, b.x, b.y);
+            if (it == 0) {
+                first_i = i;
+                first_a = a;
+                first_b = b;
+            }
+        }
+    }
+    acc_group_reduce<G>(mn);
+    acc_group_reduce<G>(mx);
+    RowAct R;
+    R.minfin = 0.0;
+    R.maxfin = 0.0;
+    R.lo = 0.0;
+    R.hi = 0.0;
+    R.nmin = mn.ninf;
+    R.nmax = mx.ninf;
+    bool ok_min = !P.force_exact && acc_certify(mn, R.minfin);
+    bool ok_max = !P.force_exact && acc_certify(mx, R.maxfin);
+    if (live && gl == 0) {
+        if (!ok_min) R.minfin = exact_side(P, bnd, p0, p1, false);
+        if (!ok_max) R.maxfin = exact_side(P, bnd, p0, p1, true);
+    }
+    {
+        // The group's first lane holds the exact values; every lane of the
+        // wave takes part in the shuffles.
+        int src = (lane / G) * G;
+        double e0 = __shfl(R.minfin, src, 64);
+        double e1 = __shfl(R.maxfin, src, 64);
+        if (!ok_min) R.minfin = e0;
+        if (!ok_max) R.maxfin = e1;
+    }
+    bool bad = false;
+    if (live) {
+        double2 sd = P.I.side[k];
+        R.lo = sd.x;
+        R.hi = sd.y;
+        bad = row_bad(R, P.feastol);
+        if (bad && gl == 0) report_bad_row(P, s, k);
+    }
+    for (int it = 0; it < iters; ++it) {
+        int64_t p = p0 + gl + (int64_t)it * G;
+        bool has = live && !bad && p < p1;
+        int i = 0;
+        bool need = false;
+        if (has) {
+            double a;
+            double2 b;
+            if (it == 0) {
+                i = first_i;
+                a = first_a;
+                b = first_b;
+            } else {
+                i = P.I.col[p];
+                a = P.I.val[p];
+                b = bnd[i];
+            }
+            bool is_int = P.I.vtype[i] != 0;
+            double cl, cu;
+            nz_candidates(R, a, b.x, b.y, is_int, P.inttol, cl, cu);
+            need = scatter(P, s, i, cl, cu, b.x, b.y, is_int);
+        }
+        mark_var(P, need, s, i);
+    }
+}
+
+// ------------------------------------------------------------------------
+// Workgroup reduction helpers (256 lanes = 4 waves).
+// ------------------------------------------------------------------------
+struct WgScratch {
+    double s[2][4], c[2][4], e[2][4];
+    int n[2][4];
+    double act[2];
+    int flag;
+};
+
+__device__ inline void wg_reduce(Acc &mn, Acc &mx, WgScratch &W) {
+    acc_group_reduce<64>(mn);
+    acc_group_reduce<64>(mx);
+    const int wave = threadIdx.x >> 6;
+    if (__lane_id() == 0) {
+        W.s[0][wave] = mn.s; W.c[0][wave] = mn.c; W.e[0][wave] = mn.e; W.n[0][wave] = mn.ninf;
+        W.s[1][wave] = mx.s; W.c[1][wave] = mx.c; W.e[1][wave] = mx.e; W.n[1][wave] = mx.ninf;
+    }
+    __syncthreads();
+    // Every lane combines the four wave states in wave order.
+    Acc A[2];
+    for (int side = 0; side < 2; ++side) {
+        A[side].s = W.s[side][0]; A[side].c = W.c[side][0]; A[side].e = W.e[side][0];
+        A[side].ninf = W.n[side][0];
+        for (int w = 1; w < WG / 64; ++w)
+            acc_merge(A[side], W.s[side][w], W.c[side][w], W.e[side][w], W.n[side][w]);
+    }
+    mn = A[0];
+    mx = A[1];
+    __syncthreads();
+}
+
+// Block rows: one workgroup per row (1024 < len <= heavy threshold).
+__device__ void block_row(const Params &P, const uint64_t *q, uint32_t t, WgScratch &W) {
+    uint64_t task = q[t];
+    int s = (int)(task >> 32);
+    int k = (int)(uint32_t)task;
+    bool live = P.info[s].state == SLOT_ACTIVE;
+    if (threadIdx.x == 0) clear_rflag(P, s, k);
+    if (!live) return;  // workgroup-uniform
+    int64_t p0 = P.I.row_ptr[k], p1 = P.I.row_ptr[k + 1];
+    const double2 *bnd = P.bnd + (size_t)s * P.I.n;
+    Acc mn, mx;
+    acc_zero(mn);
+    acc_zero(mx);
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += WG) {
+        double2 b = bnd[P.I.col[p]];
+        add_terms(mn, mx, P.I.val[p], b.x, b.y);
+    }
+    wg_reduce(mn, mx, W);
+    RowAct R;
+    R.nmin = mn.ninf;
+    R.nmax = mx.ninf;
+    bool ok_min = !P.force_exact && acc_certify(mn, R.minfin);
+    bool ok_max = !P.force_exact && acc_certify(mx, R.maxfin);
+    if (!(ok_min && ok_max)) {
+        if (threadIdx.x == 0) {
+            W.act[0] = ok_min ? R.minfin : exact_side(P, bnd, p0, p1, false);
+            W.act[1] = ok_max ? R.maxfin : exact_side(P, bnd, p0, p1, true);
+        }
+        __syncthreads();
+        R.minfin = W.act[0];
+        R.maxfin = W.act[1];
+        __syncthreads();
+    }
+    double2 sd = P.I.side[k];
+    R.lo = sd.x;
+    R.hi = sd.y;
+    if (row_bad(R, P.feastol)) {
+        if (threadIdx.x == 0) report_bad_row(P, s, k);
+        return;
+    }
+    const int64_t len = p1 - p0;
+    const int iters = (int)((len + WG - 1) / WG);
+    for (int it = 0; it < iters; ++it) {
+        int64_t p = p0 + threadIdx.x + (int64_t)it * WG;
+        bool need = false;
+        int i = 0;
+        if (p < p1) {
+            i = P.I.col[p];
+            double a = P.I.val[p];
+            double2 b = bnd[i];
+            bool is_int = P.I.vtype[i] != 0;
+            double cl, cu;
+            nz_candidates(R, a, b.x, b.y, is_int, P.inttol, cl, cu);
+            need = scatter(P, s, i, cl, cu, b.x, b.y, is_int);
+        }
+        mark_var(P, need, s, i);
+    }
+}
+
+// Heavy chunk, activity part: partial states; the last chunk of the row
+// combines all partials in chunk order and stores the activity.
+__device__ void heavy_chunk_activity(const Params &P, int par, uint32_t u, WgScratch &W) {
+    int t = P.hmap[par][u];
+    uint64_t task = P.q[par][BIN_HEAVY][t];
+    int s = (int)(task >> 32);
+    int k = (int)(uint32_t)task;
+    int c = (int)(u - (uint32_t)P.hbase[par][t]);
+    bool live = P.info[s].state == SLOT_ACTIVE;
+    if (c == 0 && threadIdx.x == 0) clear_rflag(P, s, k);
+    if (!live) return;
+    int64_t r0 = P.I.row_ptr[k], r1 = P.I.row_ptr[k + 1];
+    int64_t p0 = r0 + (int64_t)c * P.heavy_chunk;
+    int64_t p1 = min(r1, p0 + (int64_t)P.heavy_chunk);
+    int nch = (int)((r1 - r0 + P.heavy_chunk - 1) / P.heavy_chunk);
+    const double2 *bnd = P.bnd + (size_t)s * P.I.n;
+    Acc mn, mx;
+    acc_zero(mn);
+    acc_zero(mx);
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += WG) {
+        double2 b = bnd[P.I.col[p]];
+        add_terms(mn, mx, P.I.val[p], b.x, b.y);
+    }
+    wg_reduce(mn, mx, W);
+    if (threadIdx.x == 0) {
+        P.hpart[2 * (size_t)u] = mn;
+        P.hpart[2 * (size_t)u + 1] = mx;
+        __threadfence();
+        uint32_t prev = atomicAdd(&P.hdone[t], 1u);
+        W.flag = (prev == (uint32_t)nch - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!W.flag) return;
+    // Last chunk of this row: combine partials in chunk order.
+    if (threadIdx.x == 0) {
+        __threadfence();
+        uint32_t u0 = (uint32_t)P.hbase[par][t];
+        Acc A = P.hpart[2 * (size_t)u0], B = P.hpart[2 * (size_t)u0 + 1];
+        for (int j = 1; j < nch; ++j) {
+            Acc a = P.hpart[2 * (size_t)(u0 + j)], b = P.hpart[2 * (size_t)(u0 + j) + 1];
+            acc_merge(A, a.s, a.c, a.e, a.ninf);
+            acc_merge(B, b.s, b.c, b.e, b.ninf);
+        }
+        RowAct R;
+        R.nmin = A.ninf;
+        R.nmax = B.ninf;
+        if (P.force_exact || !acc_certify(A, R.minfin)) R.minfin = exact_side(P, bnd, r0, r1, false);
+        if (P.force_exact || !acc_certify(B, R.maxfin)) R.maxfin = exact_side(P, bnd, r0, r1, true);
+        double2 sd = P.I.side[k];
+        R.lo = sd.x;
+        R.hi = sd.y;
+        bool bad = row_bad(R, P.feastol);
+        if (bad) report_bad_row(P, s, k);
+        P.hact[t] = make_double4(R.minfin, R.maxfin, (double)R.nmin, (double)R.nmax);
+        P.hbad[t] = bad ? 1 : 0;
+        P.hdone[t] = 0;
+    }
+}
+
+// Heavy chunk, candidate part.
+__device__ void heavy_chunk_candidates(const Params &P, int par, uint32_t u) {
+    int t = P.hmap[par][u];
+    uint64_t task = P.q[par][BIN_HEAVY][t];
+    int s = (int)(task >> 32);
+    int k = (int)(uint32_t)task;
+    int c = (int)(u - (uint32_t)P.hbase[par][t]);
+    if (P.info[s].state != SLOT_ACTIVE || P.hbad[t]) return;  // workgroup-uniform
+    int64_t r0 = P.I.row_ptr[k], r1 = P.I.row_ptr[k + 1];
+    int64_t p0 = r0 + (int64_t)c * P.heavy_chunk;
+    int64_t p1 = min(r1, p0 + (int64_t)P.heavy_chunk);
+    double4 h = P.hact[t];
+    RowAct R;
+    R.minfin = h.x;
+    R.maxfin = h.y;
+    R.nmin = (int)h.z;
+    R.nmax = (int)h.w;
+    double2 sd = P.I.side[k];
+    R.lo = sd.x;
+    R.hi = sd.y;
+    const double2 *bnd = P.bnd + (size_t)s * P.I.n;
+    const int iters = (int)((p1 - p0 + WG - 1) / WG);
+    for (int it = 0; it < iters; ++it) {
+        int64_t p = p0 + threadIdx.x + (int64_t)it * WG;
+        bool need = false;
+        int i = 0;
+        if (p < p1) {
+            i = P.I.col[p];
+            double a = P.I.val[p];
+            double2 b = bnd[i];
+            bool is_int = P.I.vtype[i] != 0;
+            double cl, cu;
+            nz_candidates(R, a, b.x, b.y, is_int, P.inttol, cl, cu);
+            need = scatter(P, s, i, cl, cu, b.x, b.y, is_int);
+        }
+        mark_var(P, need, s, i);
+    }
+}
+
+// Work-unit table of the rows kernel for one round.
+struct Units {
+    uint32_t start[NBIN + 2];  // prefix over: heavy chunks, block rows, light bins 10..0
+};
+
+__device__ inline uint32_t light_units(uint32_t count, int b) {
+    uint32_t G = (uint32_t)light_group(b);
+    return (uint32_t)(((uint64_t)count * G + WG - 1) / WG);
+}
+
+__global__ void __launch_bounds__(WG) k_rows(Params P) {
+    __shared__ WgScratch W;
+    const Ctl *C = P.ctl;
+    if (C->done) return;
+    const int par = C->round & 1;
+    uint32_t start[NBIN + 2];
+    start[0] = 0;
+    start[1] = C->hchunks[par];
+    start[2] = start[1] + C->qcount[par][BIN_BLOCK];
+    for (int j = 0; j < NLIGHT; ++j) {
+        int b = NLIGHT - 1 - j;
+        start[3 + j] = start[2 + j] + light_units(C->qcount[par][b], b);
+    }
+    const uint32_t total = start[2 + NLIGHT];
+    for (uint32_t u = blockIdx.x; u < total; u += gridDim.x) {
+        if (u < start[1]) {
+            heavy_chunk_activity(P, par, u, W);
+        } else if (u < start[2]) {
+            block_row(P, P.q[par][BIN_BLOCK], u - start[1], W);
+        } else {
+            int j = 0;
+            while (u >= start[3 + j]) ++j;
+            int b = NLIGHT - 1 - j;
+            uint32_t lu = u - start[2 + j];
+            const uint64_t *q = P.q[par][b];
+            uint32_t cnt = C->qcount[par][b];
+            switch (b) {
+                case 0: light_rows<1>(P, q, cnt, lu); break;
+                case 1: light_rows<2>(P, q, cnt, lu); break;
+                case 2: light_rows<4>(P, q, cnt, lu); break;
+                case 3: light_rows<8>(P, q, cnt, lu); break;
+                case 4: light_rows<16>(P, q, cnt, lu); break;
+                case 5: light_rows<32>(P, q, cnt, lu); break;
+                default: light_rows<64>(P, q, cnt, lu); break;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(WG) k_heavy(Params P) {
+    const Ctl *C = P.ctl;
+    if (C->done) return;
+    const int par = C->round & 1;
+    const uint32_t total = C->hchunks[par];
+    for (uint32_t u = blockIdx.x; u < total; u += gridDim.x) heavy_chunk_candidates(P, par, u);
+}
+
+// Add newly queued rows to their slots' pending counters: one atomic pair
+// per wave when every queuing lane belongs to the same slot (always the
+// case for a single bound vector), one per lane otherwise.
+__device__ __forceinline__ void count_pending(const Params &P, bool first, int s, int64_t len) {
+    uint64_t mask = __ballot(first);
+    if (mask == 0) return;
+    int leader = __ffsll((long long)mask) - 1;
+    int s0 = __shfl(s, leader, 64);
+    if (__all(!first || s == s0)) {
+        unsigned long long tot = first ? (unsigned long long)len : 0ull;
+#pragma unroll
+        for (int w = 1; w < 64; w <<= 1) tot += __shfl_xor(tot, w, 64);
+        if (__lane_id() == leader) {
+            atomicAdd(&P.info[s0].pending_rows, (int32_t)__popcll(mask));
+            atomicAdd(&P.info[s0].pending_nnz, tot);
+        }
+    } else if (first) {
+        atomicAdd(&P.info[s].pending_rows, 1);
+        atomicAdd(&P.info[s].pending_nnz, (unsigned long long)len);
+    }
+}
+
+// ------------------------------------------------------------------------
+// Enqueue rows of var i's column for slot s into the queues of parity par.
+// Called by whole waves; lanes with want == false only take part.
+// ------------------------------------------------------------------------
+__device__ void enqueue_column(const Params &P, int par, bool want, int s, int i,
+                               int heavy_threshold) {
+    int64_t c0 = 0, c1 = 0;
+    if (want) {
+        c0 = P.I.col_ptr[i];
+        c1 = P.I.col_ptr[i + 1];
+    }
+    int64_t p = c0;
+    while (__any(p < c1)) {
+        bool has = p < c1;
+        int k = 0;
+        bool first = false;
+        int bin = -1;
+        int64_t len = 0;
+        if (has) {
+            k = P.I.col_row[p];
+            uint32_t bit = 1u << (k & 31);
+            uint32_t old = atomicOr(&P.rflag[(size_t)s * P.nw_row + (k >> 5)], bit);
+            first = (old & bit) == 0;
+            if (first) {
+                bin = P.I.rbin[k];
+                len = P.I.row_ptr[k + 1] - P.I.row_ptr[k];
+            }
+            ++p;
+        }
+        count_pending(P, first, s, len);
+        // Append by bin, one atomic per bin present in the wave.
+        uint64_t todo = __ballot(first);
+        while (todo) {
+            int leader = __ffsll((long long)todo) - 1;
+            int b = __shfl(bin, leader, 64);
+            bool mine = first && bin == b;
+            uint64_t mask = __ballot(mine);
+            uint32_t base = 0;
+            if (__lane_id() == leader) base = atomicAdd(&P.ctl->qcount[par][b], (uint32_t)__popcll(mask));
+            base = __shfl(base, leader, 64);
+            uint32_t idx = base + lane_rank(mask);
+            if (mine) {
+                P.q[par][b][idx] = ((uint64_t)(uint32_t)s << 32) | (uint32_t)k;
+                if (b == BIN_HEAVY) {
+                    uint32_t nch = (uint32_t)((len + P.heavy_chunk - 1) / P.heavy_chunk);
+                    uint32_t cb = atomicAdd(&P.ctl->hchunks[par], nch);
+                    P.hbase[par][idx] = (int32_t)cb;
+                    for (uint32_t j = 0; j < nch; ++j) P.hmap[par][cb + j] = (int32_t)idx;
+                }
+            }
+            todo &= ~mask;
+        }
+    }
+}
+
+// Dirty tracking for probes: first change of var i in slot s.
+__device__ __forceinline__ void mark_dirty(const Params &P, int s, int i) {
+    uint32_t bit = 1u << (i & 31);
+    uint32_t old = atomicOr(&P.dirty[(size_t)s * P.nw_var + (i >> 5)], bit);
+    if ((old & bit) == 0) {
+        int d = atomicAdd(&P.dcount[s], 1);
+        P.dlist[(size_t)s * P.I.n + d] = i;
+    }
+}
+
+// Round end for every slot: outcome, counters, next round.  Run by the last
+// workgroup of k_apply.
+__device__ void round_end(const Params &P) {
+    Ctl *C = P.ctl;
+    const int par = C->round & 1;
+    __shared__ uint32_t s_active, s_finished;
+    if (threadIdx.x == 0) {
+        s_active = 0;
+        s_finished = 0;
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < P.nslots; s += WG) {
+        SlotInfo &S = P.info[s];
+        if (S.state == SLOT_DRAINING) {
+            S.state = SLOT_FREE;
+            continue;
+        }
+        if (S.state != SLOT_ACTIVE) continue;
+        bool fin = true;
+        bool drain = false;
+        if (S.row_bad_count > 0) {
+            S.status = 1;
+            drain = S.pending_rows > 0;
+        } else if (S.var_bad_min != NONE) {
+            S.status = 1;
+            drain = S.pending_rows > 0;
+        } else if (S.pending_rows == 0) {
+            S.status = 0;
+        } else if ((uint32_t)S.rounds >= C->max_rounds) {
+            S.status = 2;
+            drain = true;
+        } else {
+            fin = false;
+            S.rounds += 1;
+            S.nnz += S.pending_nnz;
+            S.pending_rows = 0;
+            S.pending_nnz = 0;
+            S.row_bad_min = NONE;
+            S.row_bad_count = 0;
+            S.var_bad_min = NONE;
+            atomicAdd(&s_active, 1u);
+        }
+        if (fin) {
+            S.state = drain ? SLOT_DRAINING : SLOT_FREE;
+            atomicAdd(&s_finished, 1u);
+            if (drain) atomicAdd(&s_active, 1u);  // still has queued tasks
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int b = 0; b < NBIN; ++b) C->qcount[par][b] = 0;
+        C->hchunks[par] = 0;
+        C->nchanged = 0;
+        C->ticket = 0;
+        C->active = s_active;
+        C->finished = s_finished;
+        C->round = C->round + 1;
+        if (s_active == 0) C->done = 1;
+    }
+}
+
+__global__ void __launch_bounds__(WG) k_apply(Params P, int heavy_threshold) {
+    __shared__ int s_last;
+    Ctl *C = P.ctl;
+    if (C->done) return;
+    const int par = C->round & 1;
+    const int npar = par ^ 1;
+    const uint32_t total = C->nchanged;
+    const double INF = __builtin_inf();
+    // Uniform trip count across the grid so that whole waves reach the
+    // aggregated appends together.
+    const uint32_t stride = gridDim.x * WG;
+    for (uint32_t base = blockIdx.x * WG; base < total; base += stride) {
+        uint32_t e = base + threadIdx.x;
+        bool has = e < total;
+        int s = 0, i = 0;
+        bool go = false;
+        if (has) {
+            uint64_t ent = P.chg[e];
+            s = (int)(ent >> 32);
+            i = (int)(uint32_t)ent;
+            longlong2 *cp = &P.cand[(size_t)s * P.I.n + i];
+            long long kl = cp->x, ku = cp->y;
+            cp->x = dkey(-INF);
+            cp->y = dkey(INF);
+            P.vflag[(size_t)s * P.nw_var + (i >> 5)] = 0u;  // whole word: every var in it is handled this round
+            SlotInfo &S = P.info[s];
+            if (S.row_bad_count == 0) {
+                double2 *bp = &P.bnd[(size_t)s * P.I.n + i];
+                double2 b = *bp;
+                bool is_int = P.I.vtype[i] != 0;
+                double L = dunkey(kl), U = dunkey(ku);
+                double nl = b.x, nu = b.y;
+                bool ch = false;
+                if (take_upper(is_int, U, b.y, P.tau)) { nu = canon0(U); ch = true; }
+                if (take_lower(is_int, L, b.x, P.tau)) { nl = canon0(L); ch = true; }
+                if (ch && nl > nu) {
+                    if (is_int || nl - nu > P.feastol) atomicMin(&S.var_bad_min, i);
+                    else nl = nu;
+                }
+                if (ch) {
+                    *bp = make_double2(nl, nu);
+                    go = true;
+                    if (P.track_dirty) mark_dirty(P, s, i);
+                }
+            }
+        }
+        enqueue_column(P, npar, go, s, i, heavy_threshold);
+    }
+    // Last workgroup closes the round.
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        uint32_t prev = atomicAdd(&C->ticket, 1u);
+        s_last = prev == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (s_last) {
+        __threadfence();
+        round_end(P);
+    }
+}
+
+}  // namespace bp
