@@ -1,0 +1,153 @@
+"""Benchmark: bound propagation on the single-instance workload (one GPU).
+
+A step is one cold propagation to the fixed point of the single-instance
+workload (m=100k rows, n=150k variables, ~1M nonzeros, power-law rows plus
+~20 dense rows of 10k-50k nonzeros), from the initial bounds, with the
+changed-row worklist: every row in the first round, then only the rows of
+variables whose bounds changed.  The instance and the initial bounds are
+resident in device memory before the timed region; each step restores the
+initial bounds with a device-to-device copy and calls bp_propagate.
+
+Output: one JSON line with propagated nonzeros per second, the roofline of
+the activity kernel (algorithmic bytes per launch over its HIP-event time)
+and the CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E datasheet peak
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="run only this many plain steps (for profilers) and exit")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see the sharding notes in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2510_20499_amd import bp, gen
+
+    dev = torch.device("cuda:0")
+    inst = gen.make("single", args.seed)
+    m, n, nnz = inst["m"], inst["n"], int(inst["row_ptr"][-1])
+    I = bp.Instance(inst)
+    lb0 = torch.tensor(inst["lb"], dtype=torch.float64, device=dev)
+    ub0 = torch.tensor(inst["ub"], dtype=torch.float64, device=dev)
+    lb = torch.empty_like(lb0)
+    ub = torch.empty_like(ub0)
+
+    def step():
+        lb.copy_(lb0)
+        ub.copy_(ub0)
+        return I.propagate(lb, ub)
+
+    if args.profile_steps:
+        for _ in range(args.profile_steps):
+            r = step()
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_steps": args.profile_steps, "result": r}), flush=True)
+        return
+
+    for _ in range(args.warmup):
+        r0 = step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    total_nnz = 0
+    for _ in range(args.steps):
+        r = step()
+        total_nnz += r["nnz_propagated"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert r["status"] == bp.BP_OK and r == r0
+    value = total_nnz / dt
+
+    # Roofline of the activity kernel: HIP events around each launch (rounds
+    # driven from the host), and the bytes the method must move per launch:
+    # 12 B per nonzero (int32 column + f64 coefficient), 24 B per row
+    # (row pointer + two sides), 16 B per distinct bound record read.
+    Ic = bp.Instance(inst, bp.default_options(flags=bp.FLAG_COUNT_VARS))
+    lc, uc = lb0.clone(), ub0.clone()
+    Ic.propagate(lc, uc)
+    cs = Ic.kernel_stats(reset=True)
+    del Ic
+    It = bp.Instance(inst, bp.default_options(flags=bp.FLAG_TIME_KERNELS))
+    lt, ut = lb0.clone(), ub0.clone()
+    It.propagate(lt, ut)  # warm
+    It.kernel_stats(reset=True)
+    reps = 5
+    for _ in range(reps):
+        lt.copy_(lb0)
+        ut.copy_(ub0)
+        It.propagate(lt, ut)
+    ts = It.kernel_stats(reset=True)
+    launches = ts["launches"] / reps
+    alg_bytes_per_call = 12 * cs["nnz"] + 24 * cs["rows"] + 16 * cs["vars_read"]
+    bytes_per_launch = alg_bytes_per_call / max(launches, 1)
+    avg_launch_ms = ts["ms"] / max(ts["launches"], 1)
+    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 5), "traffic": None,
+                "kernel": "k_rows", "avg_launch_us": round(avg_launch_ms * 1e3, 3),
+                "launches_per_step": launches,
+                "alg_bytes_per_launch": int(bytes_per_launch)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        reps_cpu = 0
+        t_cpu = 0.0
+        nnz_cpu = 0
+        while reps_cpu < 1 or (t_cpu < 10.0 and reps_cpu < 5):
+            tc = time.perf_counter()
+            ro, _, _ = oracle.propagate(inst)
+            t_cpu += time.perf_counter() - tc
+            nnz_cpu += ro["nnz_propagated"]
+            reps_cpu += 1
+        assert ro["nnz_propagated"] == r["nnz_propagated"] and ro["rounds"] == r["rounds"]
+        cpu = {"value": nnz_cpu / t_cpu, "unit": "nnz/s", "cores": 1, "kind": "oracle",
+               "sample": "%d cold propagation(s) of the full single-instance workload, "
+                         "worklist mode, one thread" % reps_cpu}
+
+    out = {
+        "metric": "propagated nnz/s (plain cold propagation, single instance)",
+        "value": value,
+        "unit": "nnz/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded generator standing in for MIPLIB2017)",
+        "config": {"workload": "single-instance plain propagation: m=%d, n=%d, nnz=%d, cold start "
+                               "to fixed point with changed-row worklist" % (m, n, nnz),
+                   "m": m, "n": n, "nnz": nnz, "seed": args.seed,
+                   "rounds": r["rounds"], "nnz_propagated_per_step": r["nnz_propagated"],
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

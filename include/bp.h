@@ -76,6 +76,9 @@ extern "C" {
                                    the totals with bp_kernel_stats */
 #define BP_FLAG_HOST_ROUNDS 4u  /* drive rounds from the host one at a time
                                    instead of device-resident graphs of rounds */
+#define BP_FLAG_COUNT_VARS 8u   /* count the distinct bound records each round
+                                   gathers (bp_stats.vars_read); slower, for
+                                   byte accounting only */
 
 /* A sparse matrix in compressed form: CSR (ptr over m rows, idx = column
  * indices ascending in each row) or CSC (ptr over n columns, idx = row
@@ -96,9 +99,10 @@ typedef struct {
     uint32_t flags;      /* BP_FLAG_* */
     int32_t heavy_threshold; /* rows longer than this are split across
                                 workgroups; default 8192 (0: default) */
-    int32_t rounds_per_launch; /* rounds per captured graph; default 8 */
+    int32_t rounds_per_launch; /* rounds per captured graph; default 16 */
     int32_t probe_slots; /* bound vectors in flight during bp_probe; default 512 */
-    int32_t reserved;
+    int32_t heavy_chunk; /* nonzeros per workgroup of a heavy row; default 1024,
+                            rounded up to a multiple of 256 */
 } bp_options;
 
 typedef struct {
@@ -131,13 +135,17 @@ typedef struct {
 
 typedef struct bp_instance bp_instance;
 
+/* Counters since load or the last reset.  ms and launches cover the
+ * activity kernel (k_rows) when BP_FLAG_TIME_KERNELS is set; the other
+ * fields are kept always except vars_read (BP_FLAG_COUNT_VARS). */
 typedef struct {
-    double ms;          /* summed event time of the timed kernel */
-    int64_t launches;   /* launches timed */
-    int64_t rows;       /* row tasks those launches processed */
-    int64_t nnz;        /* nonzeros those launches processed */
-    int64_t vars_read;  /* bound records gathered (one per nonzero) */
-    int64_t vars_written; /* bound records written by the apply kernel */
+    double ms;            /* summed HIP-event time of the activity kernel */
+    int64_t launches;     /* activity-kernel launches timed */
+    int64_t rows;         /* row tasks processed (sum over rounds of |R_r|) */
+    int64_t nnz;          /* nonzeros of those rows */
+    int64_t vars_read;    /* distinct (vector, variable) bound records read per
+                             round, summed over rounds */
+    int64_t vars_written; /* bound records written (accepted changes) */
 } bp_stats;
 
 /* Fill *opt with the defaults. */
@@ -194,7 +202,7 @@ int bp_probe(bp_instance *h, const int32_t *vars, int32_t k, bp_probe_out *out,
 /* Copy the base bounds into DEVICE lb/ub [n].  BP_ESTATE without a base. */
 int bp_get_base(bp_instance *h, double *lb, double *ub, void *stream);
 
-/* Kernel timing totals since load or the last reset (BP_FLAG_TIME_KERNELS). */
+/* Counters and kernel timing since load or the last reset (see bp_stats). */
 int bp_kernel_stats(bp_instance *h, bp_stats *out, int reset);
 
 /* Device bytes held by the instance (matrix copies and work buffers). */

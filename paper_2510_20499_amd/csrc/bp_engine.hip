@@ -4,6 +4,7 @@
 // An Engine holds the per-slot work buffers for up to `cap_slots` bound
 // vectors of one instance; propagate, propagate_batch and probe all run the
 // same round kernels over it (bp_kernels.h).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -72,8 +73,8 @@ struct Engine {
     int32_t cap_slots = 0;
     int32_t track_dirty = 0;
     int64_t bytes = 0;
-    DevBuf bnd, cand, vflag, rflag, info, chg, dirty, dlist, dcount, ctl;
-    DevBuf q[2][NBIN], hmap[2], hbase[2], hpart, hact, hbad, hdone;
+    DevBuf bnd, cand, vflag, rflag, info, chg, dirty, dlist, dcount, ctl, touched;
+    DevBuf q[2][NBIN], hrec[2], hpart;
     // captured graph of `graph_rounds` rounds for this engine's Params
     hipGraphExec_t graph = nullptr;
     int graph_rounds = 0;
@@ -98,7 +99,7 @@ struct bp_instance {
     int64_t bin_start[NBIN + 1] = {0};
     int64_t heavy_chunks = 0;        // chunks of all heavy rows
     std::vector<int32_t> cold_hbase; // cold-start chunk base of each heavy row (bin order)
-    DevBuf cold_hbase_d, cold_hmap_d;
+    DevBuf cold_hbase_d;
     std::unique_ptr<Engine> eng;
     // stats
     bp_stats stats;
@@ -117,9 +118,9 @@ extern "C" void bp_options_default(bp_options *o) {
     o->max_rounds = 1000;
     o->flags = 0;
     o->heavy_threshold = 8192;
-    o->rounds_per_launch = 8;
+    o->rounds_per_launch = 16;
     o->probe_slots = 512;
-    o->reserved = 0;
+    o->heavy_chunk = 1024;
 }
 
 extern "C" const char *bp_last_error(void) { return g_err.c_str(); }
@@ -203,13 +204,13 @@ __global__ void k_seed_all(Params P, SeedAll S) {
         int64_t idx = (int64_t)sl * cnt + within;
         int s = S.s0 + sl;
         int row = S.rows[r];
-        P.q[0][b][idx] = ((uint64_t)(uint32_t)s << 32) | (uint32_t)row;
         if (b == BIN_HEAVY) {
             int64_t len = P.I.row_ptr[row + 1] - P.I.row_ptr[row];
             int32_t nch = (int32_t)((len + P.heavy_chunk - 1) / P.heavy_chunk);
-            int32_t cb = (int32_t)(sl * S.chunks_per_slot + S.hbase[within]);
-            P.hbase[0][idx] = cb;
-            for (int32_t c = 0; c < nch; ++c) P.hmap[0][cb + c] = (int32_t)idx;
+            int64_t cb = (int64_t)sl * S.chunks_per_slot + S.hbase[within];
+            for (int32_t c = 0; c < nch; ++c) P.hrec[0][cb + c] = make_int4(s, row, c, nch);
+        } else {
+            P.q[0][b][idx] = ((uint64_t)(uint32_t)s << 32) | (uint32_t)row;
         }
     }
 }
@@ -223,6 +224,8 @@ __global__ void k_seed_vars(Params P, const int32_t *vars, const int64_t *ptr, i
         int64_t e = base + threadIdx.x;
         bool has = e < total;
         int s = 0, i = 0;
+        long long c0 = 0;
+        uint32_t clen = 0;
         if (has) {
             // slot of entry e: ptr is non-decreasing over ns slots
             int lo = 0, hi = ns;
@@ -233,8 +236,10 @@ __global__ void k_seed_vars(Params P, const int32_t *vars, const int64_t *ptr, i
             }
             s = s0 + lo;
             i = vars[e];
+            c0 = P.I.col_ptr[i];
+            clen = (uint32_t)(P.I.col_ptr[i + 1] - c0);
         }
-        enqueue_column(P, 0, has, s, i, heavy_threshold);
+        enqueue_columns(P, 0, has, s, c0, clen);
     }
 }
 
@@ -258,6 +263,8 @@ __global__ void k_seed_finish(Params P, int32_t s0, int32_t ns, int32_t max_roun
         } else {
             S.rounds = 1;
             S.nnz = S.pending_nnz;
+            atomicAdd(&P.ctl->stat_rows, (unsigned long long)S.pending_rows);
+            atomicAdd(&P.ctl->stat_nnz, S.pending_nnz);
             S.pending_rows = 0;
             S.pending_nnz = 0;
         }
@@ -300,8 +307,10 @@ extern "C" int bp_load(const bp_sparse *csr, const bp_sparse *csc, const double 
     if (int rc = validate_options(o)) return rc;
     if (o.heavy_threshold <= 0) o.heavy_threshold = 8192;
     if (o.heavy_threshold < 1024) o.heavy_threshold = 1024;
-    if (o.rounds_per_launch <= 0) o.rounds_per_launch = 8;
+    if (o.rounds_per_launch <= 0) o.rounds_per_launch = 16;
     if (o.probe_slots <= 0) o.probe_slots = 512;
+    if (o.heavy_chunk <= 0) o.heavy_chunk = 1024;
+    o.heavy_chunk = (o.heavy_chunk + WG - 1) / WG * WG;
     // CSR validation
     if (csr->ptr[0] != 0 || csr->ptr[m] != nnz) return fail(BP_EINVAL, "CSR ptr must run from 0 to nnz");
     for (int64_t k = 0; k < m; ++k) {
@@ -352,7 +361,7 @@ extern "C" int bp_load(const bp_sparse *csr, const bp_sparse *csc, const double 
     h->nnz = nnz;
     h->opt = o;
     h->heavy_threshold = o.heavy_threshold;
-    h->heavy_chunk = 4096;
+    h->heavy_chunk = o.heavy_chunk;
     memset(&h->stats, 0, sizeof(h->stats));
     // Row bins (logarithmic radix binning) and the cold-start row order.
     std::vector<uint8_t> rbin(m);
@@ -418,7 +427,10 @@ extern "C" int64_t bp_device_bytes(const bp_instance *h) {
 // Engine allocation
 // ------------------------------------------------------------------------
 static int engine_ensure(bp_instance *h, int32_t slots, bool dirty, hipStream_t st) {
-    if (h->eng && h->eng->cap_slots >= slots && (!dirty || h->eng->track_dirty)) return 0;
+    const bool count = (h->opt.flags & BP_FLAG_COUNT_VARS) != 0;
+    if (h->eng && h->eng->cap_slots >= slots && (!dirty || h->eng->track_dirty) &&
+        (!count || h->eng->touched.p))
+        return 0;
     h->eng.reset();
     std::unique_ptr<Engine> E(new Engine());
     E->cap_slots = slots;
@@ -435,15 +447,15 @@ static int engine_ensure(bp_instance *h, int32_t slots, bool dirty, hipStream_t 
     if ((rc = E->chg.alloc((size_t)S * n * 8, B))) return rc;
     if ((rc = E->ctl.alloc(sizeof(Ctl), B))) return rc;
     for (int par = 0; par < 2; ++par) {
-        for (int b = 0; b < NBIN; ++b)
+        for (int b = 0; b < BIN_HEAVY; ++b)
             if ((rc = E->q[par][b].alloc((size_t)S * h->bin_count[b] * 8, B))) return rc;
-        if ((rc = E->hmap[par].alloc((size_t)S * h->heavy_chunks * 4, B))) return rc;
-        if ((rc = E->hbase[par].alloc((size_t)S * h->bin_count[BIN_HEAVY] * 4, B))) return rc;
+        if ((rc = E->hrec[par].alloc((size_t)S * h->heavy_chunks * sizeof(int4), B))) return rc;
     }
     if ((rc = E->hpart.alloc((size_t)S * h->heavy_chunks * 2 * sizeof(Acc), B))) return rc;
-    if ((rc = E->hact.alloc((size_t)S * h->bin_count[BIN_HEAVY] * sizeof(double4), B))) return rc;
-    if ((rc = E->hbad.alloc((size_t)S * h->bin_count[BIN_HEAVY] * 4, B))) return rc;
-    if ((rc = E->hdone.alloc((size_t)S * h->bin_count[BIN_HEAVY] * 4, B))) return rc;
+    if (count) {
+        if ((rc = E->touched.alloc((size_t)S * nw_var * 4, B))) return rc;
+        HIPTRY(hipMemsetAsync(E->touched.p, 0, E->touched.bytes, st));
+    }
     if (dirty) {
         if ((rc = E->dirty.alloc((size_t)S * nw_var * 4, B))) return rc;
         if ((rc = E->dlist.alloc((size_t)S * n * 4, B))) return rc;
@@ -453,7 +465,6 @@ static int engine_ensure(bp_instance *h, int32_t slots, bool dirty, hipStream_t 
     }
     HIPTRY(hipMemsetAsync(E->vflag.p, 0, E->vflag.bytes, st));
     HIPTRY(hipMemsetAsync(E->rflag.p, 0, E->rflag.bytes, st));
-    HIPTRY(hipMemsetAsync(E->hdone.p, 0, E->hdone.bytes, st));
     HIPTRY(hipMemsetAsync(E->info.p, 0, E->info.bytes, st));
     k_fill_cand<<<grid_for(S * n), 256, 0, st>>>(E->cand.as<longlong2>(), S * n);
     HIPTRY(hipGetLastError());
@@ -490,15 +501,12 @@ static Params make_params(const bp_instance *h, int32_t nslots) {
     P.info = E.info.as<SlotInfo>();
     for (int par = 0; par < 2; ++par) {
         for (int b = 0; b < NBIN; ++b) P.q[par][b] = E.q[par][b].as<uint64_t>();
-        P.hmap[par] = E.hmap[par].as<int32_t>();
-        P.hbase[par] = E.hbase[par].as<int32_t>();
+        P.hrec[par] = E.hrec[par].as<int4>();
     }
     P.hpart = E.hpart.as<Acc>();
-    P.hact = E.hact.as<double4>();
-    P.hbad = E.hbad.as<int32_t>();
-    P.hdone = E.hdone.as<uint32_t>();
     P.chg = E.chg.as<uint64_t>();
     P.ctl = E.ctl.as<Ctl>();
+    P.touched = (h->opt.flags & BP_FLAG_COUNT_VARS) ? E.touched.as<uint32_t>() : nullptr;
     P.track_dirty = E.track_dirty;
     P.dirty = E.dirty.as<uint32_t>();
     P.dlist = E.dlist.as<int32_t>();
@@ -511,11 +519,16 @@ static const int GRID_HEAVY = 1024;
 static const int GRID_APPLY = 512;
 
 static int launch_round(bp_instance *h, const Params &P, hipStream_t st, bool timed) {
-    if (timed) HIPTRY(hipEventRecord(h->ev0, st));
-    k_rows<<<GRID_ROWS, WG, 0, st>>>(P);
-    if (timed) HIPTRY(hipEventRecord(h->ev1, st));
+    if (timed) {
+        // Start/stop events recorded by the dispatch of k_rows itself, so the
+        // interval is the kernel's execution (no dispatch latency).
+        hipExtLaunchKernelGGL(k_rows, dim3(GRID_ROWS), dim3(WG), 0, st, h->ev0, h->ev1, 0, P);
+    } else {
+        k_rows<<<GRID_ROWS, WG, 0, st>>>(P);
+    }
     k_heavy<<<GRID_HEAVY, WG, 0, st>>>(P);
-    k_apply<<<GRID_APPLY, WG, 0, st>>>(P, (int)h->heavy_threshold);
+    k_apply<<<GRID_APPLY, WG, 0, st>>>(P);
+    k_end<<<1, WG, 0, st>>>(P);
     HIPTRY(hipGetLastError());
     return 0;
 }
@@ -554,7 +567,8 @@ static int run_rounds(bp_instance *h, const Params &P, hipStream_t st) {
                 for (int r = 0; r < K; ++r) {
                     k_rows<<<GRID_ROWS, WG, 0, cs>>>(P);
                     k_heavy<<<GRID_HEAVY, WG, 0, cs>>>(P);
-                    k_apply<<<GRID_APPLY, WG, 0, cs>>>(P, (int)h->heavy_threshold);
+                    k_apply<<<GRID_APPLY, WG, 0, cs>>>(P);
+                    k_end<<<1, WG, 0, cs>>>(P);
                 }
                 hipGraph_t g;
                 HIPTRY(hipStreamEndCapture(cs, &g));
@@ -572,6 +586,10 @@ static int run_rounds(bp_instance *h, const Params &P, hipStream_t st) {
         if (hc.done) break;
         if (launched > limit) return fail(BP_EDEVICE, "round loop did not terminate");
     }
+    h->stats.rows += (int64_t)hc.stat_rows;
+    h->stats.nnz += (int64_t)hc.stat_nnz;
+    h->stats.vars_read += (int64_t)hc.stat_vars;
+    h->stats.vars_written += (int64_t)hc.stat_written;
     return 0;
 }
 

@@ -77,14 +77,15 @@ struct Ctl {
     uint32_t qcount[2][NBIN];   // queue lengths per parity
     uint32_t hchunks[2];        // heavy chunks per parity
     uint32_t nchanged;          // (slot, var) entries of the current round
-    uint32_t ticket;            // last-workgroup detection in apply
     uint32_t active;            // slots active after the last round end
     uint32_t finished;          // slots finished at the last round end
     uint32_t max_rounds;
     uint32_t nslots;
-    // statistics of the last round start (for the benchmark's byte model)
-    unsigned long long stat_rows;
-    unsigned long long stat_nnz;
+    // cumulative counters (byte accounting)
+    unsigned long long stat_rows;    // row tasks at round starts
+    unsigned long long stat_nnz;     // their nonzeros
+    unsigned long long stat_vars;    // distinct bound records read per round
+    unsigned long long stat_written; // accepted bound changes
 };
 
 struct Params {
@@ -100,14 +101,12 @@ struct Params {
     uint32_t *rflag;             // [nslots][nw_row]
     SlotInfo *info;              // [nslots]
     uint64_t *q[2][NBIN];        // task queues (slot << 32 | row)
-    int32_t *hmap[2];            // heavy chunk -> heavy task index
-    int32_t *hbase[2];           // heavy task -> first chunk
+    int4 *hrec[2];               // heavy chunks: (slot, row, chunk index, chunks of the row)
     Acc *hpart;                  // [chunks][2] partial (min, max) states
-    double4 *hact;               // [heavy tasks] (minfin, maxfin, nmin, nmax)
-    int32_t *hbad;               // [heavy tasks] row infeasible flag
-    uint32_t *hdone;             // [heavy tasks] finished chunks
     uint64_t *chg;               // (slot << 32 | var) entries of the round
     Ctl *ctl;
+    uint32_t *touched;           // [nslots][nw_var] bound records read this round
+                                 // (only when counting them)
     // probe mode
     int32_t track_dirty;
     uint32_t *dirty;             // [nslots][nw_var]
@@ -251,6 +250,14 @@ __device__ __forceinline__ bool scatter(const Params &P, int s, int i, double cl
     return any;
 }
 
+// Distinct bound records read in this round (accounting mode only).
+__device__ __forceinline__ void count_read(const Params &P, int s, int i) {
+    if (!P.touched) return;
+    uint32_t bit = 1u << (i & 31);
+    uint32_t old = atomicOr(&P.touched[(size_t)s * P.nw_var + (i >> 5)], bit);
+    if ((old & bit) == 0) atomicAdd(&P.ctl->stat_vars, 1ull);
+}
+
 // Terms of one nonzero into the two accumulators.
 __device__ __forceinline__ void add_terms(Acc &mn, Acc &mx, double a, double lb, double ub) {
     double bmin = a > 0.0 ? lb : ub;
@@ -307,18 +314,21 @@ __device__ void light_rows(const Params &P, const uint64_t *q, uint32_t count, u
     bool valid = t < count;
     int s = 0, k = 0;
     bool live = false;
+    int64_t p0 = 0, p1 = 0;
+    double2 sd = make_double2(0.0, 0.0);
     if (valid) {
         uint64_t task = q[t];
         s = (int)(task >> 32);
         k = (int)(uint32_t)task;
-        live = P.info[s].state == SLOT_ACTIVE;
-        if (gl == 0) clear_rflag(P, s, k);
-    }
-    int64_t p0 = 0, p1 = 0;
-    if (live) {
+        // independent loads, issued together
+        int32_t state = P.info[s].state;
         p0 = P.I.row_ptr[k];
         p1 = P.I.row_ptr[k + 1];
+        sd = P.I.side[k];
+        live = state == SLOT_ACTIVE;
+        if (gl == 0) clear_rflag(P, s, k);
     }
+    if (!live) p1 = p0;
     const double2 *bnd = P.bnd + (size_t)s * P.I.n;
     Acc mn, mx;
     acc_zero(mn);
@@ -328,6 +338,7 @@ __device__ void light_rows(const Params &P, const uint64_t *q, uint32_t count, u
     int first_i = 0;
     double first_a = 0.0;
     double2 first_b = make_double2(0.0, 0.0);
+    uint8_t first_t = 0;
     const int64_t len = p1 - p0;
     const int iters = G < 64 ? 1 : (int)((len + 63) / 64);
     for (int it = 0; it < iters; ++it) {
@@ -336,11 +347,14 @@ __device__ void light_rows(const Params &P, const uint64_t *q, uint32_t count, u
             int i = P.I.col[p];
             double a = P.I.val[p];
             double2 b = bnd[i];
+            uint8_t vt = P.I.vtype[i];
             add_terms(mn, mx, a, b.x, b.y);
+            count_read(P, s, i);
             if (it == 0) {
                 first_i = i;
                 first_a = a;
                 first_b = b;
+                first_t = vt;
             }
         }
     }
@@ -370,7 +384,6 @@ __device__ void light_rows(const Params &P, const uint64_t *q, uint32_t count, u
     }
     bool bad = false;
     if (live) {
-        double2 sd = P.I.side[k];
         R.lo = sd.x;
         R.hi = sd.y;
         bad = row_bad(R, P.feastol);
@@ -384,16 +397,18 @@ __device__ void light_rows(const Params &P, const uint64_t *q, uint32_t count, u
         if (has) {
             double a;
             double2 b;
+            bool is_int;
             if (it == 0) {
                 i = first_i;
                 a = first_a;
                 b = first_b;
+                is_int = first_t != 0;
             } else {
                 i = P.I.col[p];
                 a = P.I.val[p];
                 b = bnd[i];
+                is_int = P.I.vtype[i] != 0;
             }
-            bool is_int = P.I.vtype[i] != 0;
             double cl, cu;
             nz_candidates(R, a, b.x, b.y, is_int, P.inttol, cl, cu);
             need = scatter(P, s, i, cl, cu, b.x, b.y, is_int);
@@ -450,6 +465,7 @@ __device__ void block_row(const Params &P, const uint64_t *q, uint32_t t, WgScra
     for (int64_t p = p0 + threadIdx.x; p < p1; p += WG) {
         double2 b = bnd[P.I.col[p]];
         add_terms(mn, mx, P.I.val[p], b.x, b.y);
+        count_read(P, s, P.I.col[p]);
     }
     wg_reduce(mn, mx, W);
     RowAct R;
@@ -493,21 +509,18 @@ __device__ void block_row(const Params &P, const uint64_t *q, uint32_t t, WgScra
     }
 }
 
-// Heavy chunk, activity part: partial states; the last chunk of the row
-// combines all partials in chunk order and stores the activity.
+// Heavy chunk, activity part: the partial states of one chunk of a heavy
+// row.  The chunks of a row are contiguous; the candidate kernel of the
+// same round combines them (the kernel boundary makes them visible).
 __device__ void heavy_chunk_activity(const Params &P, int par, uint32_t u, WgScratch &W) {
-    int t = P.hmap[par][u];
-    uint64_t task = P.q[par][BIN_HEAVY][t];
-    int s = (int)(task >> 32);
-    int k = (int)(uint32_t)task;
-    int c = (int)(u - (uint32_t)P.hbase[par][t]);
-    bool live = P.info[s].state == SLOT_ACTIVE;
+    const int4 rec = P.hrec[par][u];
+    const int s = rec.x, k = rec.y, c = rec.z;
+    const bool live = P.info[s].state == SLOT_ACTIVE;
+    const int64_t r0 = P.I.row_ptr[k], r1 = P.I.row_ptr[k + 1];
     if (c == 0 && threadIdx.x == 0) clear_rflag(P, s, k);
-    if (!live) return;
-    int64_t r0 = P.I.row_ptr[k], r1 = P.I.row_ptr[k + 1];
+    if (!live) return;  // workgroup-uniform
     int64_t p0 = r0 + (int64_t)c * P.heavy_chunk;
     int64_t p1 = min(r1, p0 + (int64_t)P.heavy_chunk);
-    int nch = (int)((r1 - r0 + P.heavy_chunk - 1) / P.heavy_chunk);
     const double2 *bnd = P.bnd + (size_t)s * P.I.n;
     Acc mn, mx;
     acc_zero(mn);
@@ -515,64 +528,58 @@ __device__ void heavy_chunk_activity(const Params &P, int par, uint32_t u, WgScr
     for (int64_t p = p0 + threadIdx.x; p < p1; p += WG) {
         double2 b = bnd[P.I.col[p]];
         add_terms(mn, mx, P.I.val[p], b.x, b.y);
+        count_read(P, s, P.I.col[p]);
     }
     wg_reduce(mn, mx, W);
     if (threadIdx.x == 0) {
         P.hpart[2 * (size_t)u] = mn;
         P.hpart[2 * (size_t)u + 1] = mx;
-        __threadfence();
-        uint32_t prev = atomicAdd(&P.hdone[t], 1u);
-        W.flag = (prev == (uint32_t)nch - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    if (!W.flag) return;
-    // Last chunk of this row: combine partials in chunk order.
-    if (threadIdx.x == 0) {
-        __threadfence();
-        uint32_t u0 = (uint32_t)P.hbase[par][t];
-        Acc A = P.hpart[2 * (size_t)u0], B = P.hpart[2 * (size_t)u0 + 1];
-        for (int j = 1; j < nch; ++j) {
-            Acc a = P.hpart[2 * (size_t)(u0 + j)], b = P.hpart[2 * (size_t)(u0 + j) + 1];
-            acc_merge(A, a.s, a.c, a.e, a.ninf);
-            acc_merge(B, b.s, b.c, b.e, b.ninf);
-        }
-        RowAct R;
-        R.nmin = A.ninf;
-        R.nmax = B.ninf;
-        if (P.force_exact || !acc_certify(A, R.minfin)) R.minfin = exact_side(P, bnd, r0, r1, false);
-        if (P.force_exact || !acc_certify(B, R.maxfin)) R.maxfin = exact_side(P, bnd, r0, r1, true);
-        double2 sd = P.I.side[k];
-        R.lo = sd.x;
-        R.hi = sd.y;
-        bool bad = row_bad(R, P.feastol);
-        if (bad) report_bad_row(P, s, k);
-        P.hact[t] = make_double4(R.minfin, R.maxfin, (double)R.nmin, (double)R.nmax);
-        P.hbad[t] = bad ? 1 : 0;
-        P.hdone[t] = 0;
     }
 }
 
-// Heavy chunk, candidate part.
+// Heavy chunk, candidate part.  Every wave combines the row's partials
+// (lane l takes chunks l, l+64, ... in order, then a butterfly), certifies
+// the sums and tests the row; the chunk's nonzeros then give candidates.
 __device__ void heavy_chunk_candidates(const Params &P, int par, uint32_t u) {
-    int t = P.hmap[par][u];
-    uint64_t task = P.q[par][BIN_HEAVY][t];
-    int s = (int)(task >> 32);
-    int k = (int)(uint32_t)task;
-    int c = (int)(u - (uint32_t)P.hbase[par][t]);
-    if (P.info[s].state != SLOT_ACTIVE || P.hbad[t]) return;  // workgroup-uniform
-    int64_t r0 = P.I.row_ptr[k], r1 = P.I.row_ptr[k + 1];
-    int64_t p0 = r0 + (int64_t)c * P.heavy_chunk;
-    int64_t p1 = min(r1, p0 + (int64_t)P.heavy_chunk);
-    double4 h = P.hact[t];
+    const int4 rec = P.hrec[par][u];
+    const int s = rec.x, k = rec.y, c = rec.z, nch = rec.w;
+    if (P.info[s].state != SLOT_ACTIVE) return;  // workgroup-uniform
+    const int lane = __lane_id();
+    const int64_t r0 = P.I.row_ptr[k], r1 = P.I.row_ptr[k + 1];
+    const double2 sd = P.I.side[k];
+    const double2 *bnd = P.bnd + (size_t)s * P.I.n;
+    const uint32_t u0 = u - (uint32_t)c;
+    Acc A, B;
+    acc_zero(A);
+    acc_zero(B);
+    for (int j = lane; j < nch; j += 64) {
+        Acc a = P.hpart[2 * (size_t)(u0 + j)], b = P.hpart[2 * (size_t)(u0 + j) + 1];
+        acc_merge(A, a.s, a.c, a.e, a.ninf);
+        acc_merge(B, b.s, b.c, b.e, b.ninf);
+    }
+    acc_group_reduce<64>(A);
+    acc_group_reduce<64>(B);
     RowAct R;
-    R.minfin = h.x;
-    R.maxfin = h.y;
-    R.nmin = (int)h.z;
-    R.nmax = (int)h.w;
-    double2 sd = P.I.side[k];
+    R.minfin = 0.0;
+    R.maxfin = 0.0;
+    R.nmin = A.ninf;
+    R.nmax = B.ninf;
     R.lo = sd.x;
     R.hi = sd.y;
-    const double2 *bnd = P.bnd + (size_t)s * P.I.n;
+    bool ok_min = !P.force_exact && acc_certify(A, R.minfin);
+    bool ok_max = !P.force_exact && acc_certify(B, R.maxfin);
+    if (lane == 0) {
+        if (!ok_min) R.minfin = exact_side(P, bnd, r0, r1, false);
+        if (!ok_max) R.maxfin = exact_side(P, bnd, r0, r1, true);
+    }
+    R.minfin = __shfl(R.minfin, 0, 64);
+    R.maxfin = __shfl(R.maxfin, 0, 64);
+    if (row_bad(R, P.feastol)) {  // uniform across the workgroup
+        if (c == 0 && threadIdx.x == 0) report_bad_row(P, s, k);
+        return;
+    }
+    int64_t p0 = r0 + (int64_t)c * P.heavy_chunk;
+    int64_t p1 = min(r1, p0 + (int64_t)P.heavy_chunk);
     const int iters = (int)((p1 - p0 + WG - 1) / WG);
     for (int it = 0; it < iters; ++it) {
         int64_t p = p0 + threadIdx.x + (int64_t)it * WG;
@@ -672,57 +679,91 @@ __device__ __forceinline__ void count_pending(const Params &P, bool first, int s
 }
 
 // ------------------------------------------------------------------------
-// Enqueue rows of var i's column for slot s into the queues of parity par.
-// Called by whole waves; lanes with want == false only take part.
+// Queueing rows for the next round.
 // ------------------------------------------------------------------------
-__device__ void enqueue_column(const Params &P, int par, bool want, int s, int i,
-                               int heavy_threshold) {
-    int64_t c0 = 0, c1 = 0;
-    if (want) {
-        c0 = P.I.col_ptr[i];
-        c1 = P.I.col_ptr[i + 1];
+// Append the (slot, row) tasks of the lanes with first == true to their bin
+// queues of parity par: one ballot per bin, then one atomic per non-empty bin
+// issued by lanes 0..NBIN-1 in parallel.  Reached by every lane of the wave.
+__device__ __forceinline__ void append_rows(const Params &P, int par, bool first, int s, int k,
+                                            int bin, int64_t len) {
+    if (!__any(first)) return;
+    const int lane = __lane_id();
+    // Heavy rows: a range of chunk records (rare; one atomic per row).
+    if (first && bin == BIN_HEAVY) {
+        int nch = (int)((len + P.heavy_chunk - 1) / P.heavy_chunk);
+        uint32_t cb = atomicAdd(&P.ctl->hchunks[par], (uint32_t)nch);
+        for (int c = 0; c < nch; ++c) P.hrec[par][cb + c] = make_int4(s, k, c, nch);
     }
-    int64_t p = c0;
-    while (__any(p < c1)) {
-        bool has = p < c1;
+    const bool lt = first && bin != BIN_HEAVY;
+    uint32_t cnt = 0;
+    uint64_t mine = 0;
+#pragma unroll
+    for (int b = 0; b < BIN_HEAVY; ++b) {
+        uint64_t mb = __ballot(lt && bin == b);
+        if (lane == b) cnt = (uint32_t)__popcll(mb);
+        if (lt && bin == b) mine = mb;
+    }
+    uint32_t base = 0;
+    if (lane < BIN_HEAVY && cnt) base = atomicAdd(&P.ctl->qcount[par][lane], cnt);
+    uint32_t mybase = __shfl(base, lt ? bin : 0, 64);
+    if (lt) P.q[par][bin][mybase + lane_rank(mine)] = ((uint64_t)(uint32_t)s << 32) | (uint32_t)k;
+}
+
+// Queue, for the round of parity par, the rows of the column of the
+// variable held by each lane with want == true (at most one per lane).  The
+// column entries of the whole wave are walked 64 at a time, so a wave
+// needs ceil(sum of column lengths / 64) steps.  A row is queued once per
+// slot: the first lane to set its bit in the slot's row bitmap appends it.
+// Reached by every lane of the wave.
+__device__ void enqueue_columns(const Params &P, int par, bool want, int s, long long c0,
+                                uint32_t len) {
+    const int lane = __lane_id();
+    if (!want) {
+        c0 = 0;
+        len = 0;
+    }
+    uint32_t incl = len;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t y = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += y;
+    }
+    const uint32_t tot = __shfl(incl, 63, 64);
+    for (uint32_t off = 0; off < tot; off += 64) {
+        const uint32_t j = off + lane;
+        const bool has = j < tot;
+        // owner lane: the smallest o with incl[o] > j (six halvings of 64)
+        int lo = 0, hi = 63;
+#pragma unroll
+        for (int step = 0; step < 6; ++step) {
+            int mid = (lo + hi) >> 1;
+            uint32_t v = __shfl(incl, mid, 64);
+            if (v > j) hi = mid;
+            else lo = mid + 1;
+        }
+        const uint32_t oincl = __shfl(incl, lo, 64);
+        const uint32_t olen = __shfl(len, lo, 64);
+        const long long oc0 = __shfl(c0, lo, 64);
+        const int os = __shfl(s, lo, 64);
         int k = 0;
+        int bin = 0;
+        int64_t rlen = 0;
         bool first = false;
-        int bin = -1;
-        int64_t len = 0;
         if (has) {
-            k = P.I.col_row[p];
+            k = P.I.col_row[oc0 + (long long)(j - (oincl - olen))];
             uint32_t bit = 1u << (k & 31);
-            uint32_t old = atomicOr(&P.rflag[(size_t)s * P.nw_row + (k >> 5)], bit);
-            first = (old & bit) == 0;
-            if (first) {
-                bin = P.I.rbin[k];
-                len = P.I.row_ptr[k + 1] - P.I.row_ptr[k];
-            }
-            ++p;
+            uint32_t *wp = &P.rflag[(size_t)os * P.nw_row + (k >> 5)];
+            // Independent loads issued together.  Rows shared by many changed
+            // variables (dense rows) are mostly seen set already: the relaxed
+            // load spares their atomics.
+            uint32_t cur = __hip_atomic_load(wp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            bin = P.I.rbin[k];
+            int64_t rp0 = P.I.row_ptr[k], rp1 = P.I.row_ptr[k + 1];
+            if ((cur & bit) == 0) first = (atomicOr(wp, bit) & bit) == 0;
+            rlen = rp1 - rp0;
         }
-        count_pending(P, first, s, len);
-        // Append by bin, one atomic per bin present in the wave.
-        uint64_t todo = __ballot(first);
-        while (todo) {
-            int leader = __ffsll((long long)todo) - 1;
-            int b = __shfl(bin, leader, 64);
-            bool mine = first && bin == b;
-            uint64_t mask = __ballot(mine);
-            uint32_t base = 0;
-            if (__lane_id() == leader) base = atomicAdd(&P.ctl->qcount[par][b], (uint32_t)__popcll(mask));
-            base = __shfl(base, leader, 64);
-            uint32_t idx = base + lane_rank(mask);
-            if (mine) {
-                P.q[par][b][idx] = ((uint64_t)(uint32_t)s << 32) | (uint32_t)k;
-                if (b == BIN_HEAVY) {
-                    uint32_t nch = (uint32_t)((len + P.heavy_chunk - 1) / P.heavy_chunk);
-                    uint32_t cb = atomicAdd(&P.ctl->hchunks[par], nch);
-                    P.hbase[par][idx] = (int32_t)cb;
-                    for (uint32_t j = 0; j < nch; ++j) P.hmap[par][cb + j] = (int32_t)idx;
-                }
-            }
-            todo &= ~mask;
-        }
+        count_pending(P, first, os, first ? rlen : 0);
+        append_rows(P, par, first, os, k, bin, rlen);
     }
 }
 
@@ -736,10 +777,10 @@ __device__ __forceinline__ void mark_dirty(const Params &P, int s, int i) {
     }
 }
 
-// Round end for every slot: outcome, counters, next round.  Run by the last
-// workgroup of k_apply.
-__device__ void round_end(const Params &P) {
+// Round end for every slot: outcome, counters, next round (one workgroup).
+__global__ void __launch_bounds__(WG) k_end(Params P) {
     Ctl *C = P.ctl;
+    if (C->done) return;
     const int par = C->round & 1;
     __shared__ uint32_t s_active, s_finished;
     if (threadIdx.x == 0) {
@@ -771,6 +812,8 @@ __device__ void round_end(const Params &P) {
             fin = false;
             S.rounds += 1;
             S.nnz += S.pending_nnz;
+            atomicAdd(&C->stat_rows, (unsigned long long)S.pending_rows);
+            atomicAdd(&C->stat_nnz, S.pending_nnz);
             S.pending_rows = 0;
             S.pending_nnz = 0;
             S.row_bad_min = NONE;
@@ -784,12 +827,15 @@ __device__ void round_end(const Params &P) {
             if (drain) atomicAdd(&s_active, 1u);  // still has queued tasks
         }
     }
+    if (P.touched) {
+        size_t words = (size_t)P.nslots * P.nw_var;
+        for (size_t w = threadIdx.x; w < words; w += WG) P.touched[w] = 0u;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int b = 0; b < NBIN; ++b) C->qcount[par][b] = 0;
         C->hchunks[par] = 0;
         C->nchanged = 0;
-        C->ticket = 0;
         C->active = s_active;
         C->finished = s_finished;
         C->round = C->round + 1;
@@ -797,26 +843,32 @@ __device__ void round_end(const Params &P) {
     }
 }
 
-__global__ void __launch_bounds__(WG) k_apply(Params P, int heavy_threshold) {
-    __shared__ int s_last;
+constexpr int APPLY_V = 16;  // changed variables per wave and step in k_apply
+
+__global__ void __launch_bounds__(WG) k_apply(Params P) {
     Ctl *C = P.ctl;
     if (C->done) return;
     const int par = C->round & 1;
     const int npar = par ^ 1;
     const uint32_t total = C->nchanged;
     const double INF = __builtin_inf();
-    // Uniform trip count across the grid so that whole waves reach the
-    // aggregated appends together.
-    const uint32_t stride = gridDim.x * WG;
-    for (uint32_t base = blockIdx.x * WG; base < total; base += stride) {
-        uint32_t e = base + threadIdx.x;
-        bool has = e < total;
+    const int lane = __lane_id();
+    const uint32_t nwaves = gridDim.x * (WG / 64);
+    const uint32_t gw = blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
+    // Wave-uniform trip count: whole waves reach the aggregated appends.
+    for (uint32_t e0 = gw * APPLY_V; e0 < total; e0 += nwaves * APPLY_V) {
+        uint32_t e = e0 + lane;
+        bool has = lane < APPLY_V && e < total;
         int s = 0, i = 0;
         bool go = false;
+        long long c0 = 0;
+        uint32_t clen = 0;
         if (has) {
             uint64_t ent = P.chg[e];
             s = (int)(ent >> 32);
             i = (int)(uint32_t)ent;
+            c0 = P.I.col_ptr[i];
+            clen = (uint32_t)(P.I.col_ptr[i + 1] - c0);
             longlong2 *cp = &P.cand[(size_t)s * P.I.n + i];
             long long kl = cp->x, ku = cp->y;
             cp->x = dkey(-INF);
@@ -843,19 +895,10 @@ __global__ void __launch_bounds__(WG) k_apply(Params P, int heavy_threshold) {
                 }
             }
         }
-        enqueue_column(P, npar, go, s, i, heavy_threshold);
-    }
-    // Last workgroup closes the round.
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        uint32_t prev = atomicAdd(&C->ticket, 1u);
-        s_last = prev == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (s_last) {
-        __threadfence();
-        round_end(P);
+        uint64_t wm = __ballot(go);
+        if (wm && lane == __ffsll((long long)wm) - 1)
+            atomicAdd(&C->stat_written, (unsigned long long)__popcll(wm));
+        enqueue_columns(P, npar, go, s, c0, clen);
     }
 }
 

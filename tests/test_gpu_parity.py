@@ -78,6 +78,14 @@ def test_single_heavy_paths_small_threshold():
     both(I, inst, what="heavy1024")
 
 
+def test_heavy_rows_many_chunks():
+    # 256-nonzero chunks: the dense rows of the full single-instance workload
+    # split into up to ~200 chunks, more than one partial per merging lane.
+    inst = gen.make("single", 0, scale=0.5)
+    I = bp().Instance(inst, _opts(heavy_chunk=256, heavy_threshold=2048))
+    both(I, inst, what="chunks256")
+
+
 def test_probe_workload_scaled():
     inst = gen.make("probe", 0, scale=0.004)
     I = bp().Instance(inst)
