@@ -33,6 +33,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="run only this many plain steps (for profilers) and exit")
+    ap.add_argument("--skip-probe", action="store_true",
+                    help="skip the batched double-probing measurement")
+    ap.add_argument("--probe-vars", type=int, default=4096)
+    ap.add_argument("--probe-plain", type=int, default=256,
+                    help="binaries probed one call at a time for the plain baseline")
+    ap.add_argument("--probe-cpu", type=int, default=0,
+                    help="binaries the oracle probes for a CPU probing rate (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -125,6 +132,8 @@ def main():
                "sample": "%d cold propagation(s) of the full single-instance workload, "
                          "worklist mode, one thread" % reps_cpu}
 
+    probe = None if args.skip_probe else bench_probe(args, bp, gen, torch, np)
+
     out = {
         "metric": "propagated nnz/s (plain cold propagation, single instance)",
         "value": value,
@@ -145,8 +154,76 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "probe_batched": probe,
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_probe(args, bp, gen, torch, np):
+    """Double probing on the probe workload (m=500k, n=1M, ~8M nnz, 70%
+    binaries, set-cover and big-M rows): a seeded sample of unfixed binaries
+    of the root fixed point, each probed at 0 and 1.  Plain: one bp_probe
+    call per binary (k = 1).  Batched: one call for all of them, slots
+    refilled at round boundaries."""
+    dev = torch.device("cuda:0")
+    inst = gen.make("probe", args.seed)
+    I = bp.Instance(inst)
+    lb = torch.tensor(inst["lb"], dtype=torch.float64, device=dev)
+    ub = torch.tensor(inst["ub"], dtype=torch.float64, device=dev)
+    root = I.propagate(lb, ub)
+    assert root["status"] == bp.BP_OK
+    vs = gen.pick_probe_vars(inst, lb.cpu().numpy(), ub.cpu().numpy(), args.probe_vars, seed=args.seed)
+    k = int(vs.size)
+    vars_d = torch.tensor(vs, dtype=torch.int32, device=dev)
+    # batched
+    G = I.probe(vars_d)  # warm (sizes the output buffers)
+    cap = int(G["off"][-1].item()) + 16
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        G = I.probe(vars_d, cap=cap)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / reps
+    nnz_b = int(G["nnz"].sum().item())
+    rounds = G["rounds"].cpu().numpy()
+    # plain: one binary per call
+    kp = min(args.probe_plain, k)
+    I.probe(vars_d[:1], cap=cap)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nnz_p = 0
+    for t in range(kp):
+        Gp = I.probe(vars_d[t:t + 1], cap=cap)
+        nnz_p += int(Gp["nnz"].sum().item())
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    res = {
+        "workload": "double probing: m=%d, n=%d, nnz=%d; %d binaries x {0,1} = %d bound vectors"
+                    % (inst["m"], inst["n"], int(inst["row_ptr"][-1]), k, 2 * k),
+        "batched_probes_per_s": 2 * k / tb,
+        "batched_nnz_per_s": nnz_b / tb,
+        "batched_ms": tb * 1e3,
+        "plain_probes_per_s": 2 * kp / tp,
+        "plain_nnz_per_s": nnz_p / tp,
+        "batched_over_plain": (2 * k / tb) / (2 * kp / tp),
+        "probe_slots": int(I.options.probe_slots),
+        "rounds_mean": float(rounds.mean()), "rounds_max": int(rounds.max()),
+        "nnz_per_probe_mean": nnz_b / (2 * k),
+        "implied_entries": int(G["off"][-1].item()),
+        "infeasible_probes": int((G["status"] == bp.BP_INFEASIBLE).sum().item()),
+    }
+    if args.probe_cpu:
+        import oracle
+        _, olb, oub = oracle.propagate(inst)
+        kc = min(args.probe_cpu, k)
+        tc = time.perf_counter()
+        O = oracle.probe(inst, olb, oub, vs[:kc])
+        tc = time.perf_counter() - tc
+        res["cpu_baseline"] = {"value": 2 * kc / tc, "unit": "probes/s", "cores": 1,
+                               "kind": "oracle", "nnz_per_s": float(O["nnz"].sum()) / tc,
+                               "sample": "%d binaries x {0,1}" % kc}
+    return res
 
 
 if __name__ == "__main__":

@@ -122,6 +122,7 @@ typedef struct {
  * variable; it is empty for infeasible probes and for a probe whose value
  * the base already fixes. */
 typedef struct {
+    /* status/rounds/nnz may be NULL when k == 0; off always has 2k+1 entries */
     int8_t *status;    /* [2k] BP_OK / BP_INFEASIBLE / BP_ROUND_LIMIT */
     int32_t *rounds;   /* [2k] */
     int64_t *nnz;      /* [2k] nnz propagated */

@@ -79,6 +79,11 @@ struct Engine {
     hipGraphExec_t graph = nullptr;
     int graph_rounds = 0;
     Params graph_params;
+    ProbeIO graph_io;
+    bool graph_probe = false;
+    // slots [0, clean_slots) hold the base of version clean_version
+    int32_t clean_slots = 0;
+    int64_t clean_version = -1;
     ~Engine() {
         if (graph) (void)hipGraphExecDestroy(graph);
     }
@@ -94,6 +99,11 @@ struct bp_instance {
     DevBuf row_ptr, col, val, side, col_ptr, col_row, vtype, rbin, cold_rows, base;
     int64_t bytes = 0;
     bool have_base = false;
+    int64_t base_version = 0;
+    // probe staging (reused across calls)
+    DevBuf st_var, st_lb, st_ub, st_off, st_cnt, scratch_i32;
+    DevBuf st_status, st_rounds, st_nnz, st_vars;  // per-job results and the probe list
+    int64_t st_cap = 0, st_jobs = 0;
     // row bins (host)
     int64_t bin_count[NBIN] = {0};
     int64_t bin_start[NBIN + 1] = {0};
@@ -518,7 +528,8 @@ static const int GRID_ROWS = 2048;
 static const int GRID_HEAVY = 1024;
 static const int GRID_APPLY = 512;
 
-static int launch_round(bp_instance *h, const Params &P, hipStream_t st, bool timed) {
+static int launch_round(bp_instance *h, const Params &P, const ProbeIO *io, hipStream_t st,
+                        bool timed) {
     if (timed) {
         // Start/stop events recorded by the dispatch of k_rows itself, so the
         // interval is the kernel's execution (no dispatch latency).
@@ -529,24 +540,23 @@ static int launch_round(bp_instance *h, const Params &P, hipStream_t st, bool ti
     k_heavy<<<GRID_HEAVY, WG, 0, st>>>(P);
     k_apply<<<GRID_APPLY, WG, 0, st>>>(P);
     k_end<<<1, WG, 0, st>>>(P);
+    if (io) k_retire<<<std::min(P.nslots, 4096), WG, 0, st>>>(P, *io);
     HIPTRY(hipGetLastError());
     return 0;
 }
 
-// Run rounds until every slot is finished.
-static int run_rounds(bp_instance *h, const Params &P, hipStream_t st) {
+// Run rounds until every slot is finished (and, when probing, every job).
+static int run_rounds(bp_instance *h, const Params &P, const ProbeIO *io, int64_t limit,
+                      hipStream_t st) {
     Engine &E = *h->eng;
     Ctl hc;
     const bool timed = (h->opt.flags & BP_FLAG_TIME_KERNELS) != 0;
     const bool host_rounds = timed || (h->opt.flags & BP_FLAG_HOST_ROUNDS) != 0;
     const int K = std::max(1, (int)h->opt.rounds_per_launch);
-    // Upper bound on engine rounds: slot rounds never exceed max_rounds,
-    // plus one draining round.
-    const int64_t limit = (int64_t)h->opt.max_rounds + 2;
     int64_t launched = 0;
     for (;;) {
         if (host_rounds) {
-            if (int rc = launch_round(h, P, st, timed)) return rc;
+            if (int rc = launch_round(h, P, io, st, timed)) return rc;
             launched += 1;
             if (timed) {
                 HIPTRY(hipEventSynchronize(h->ev1));
@@ -569,6 +579,7 @@ static int run_rounds(bp_instance *h, const Params &P, hipStream_t st) {
                     k_heavy<<<GRID_HEAVY, WG, 0, cs>>>(P);
                     k_apply<<<GRID_APPLY, WG, 0, cs>>>(P);
                     k_end<<<1, WG, 0, cs>>>(P);
+                    if (io) k_retire<<<std::min(P.nslots, 4096), WG, 0, cs>>>(P, *io);
                 }
                 hipGraph_t g;
                 HIPTRY(hipStreamEndCapture(cs, &g));
@@ -593,21 +604,27 @@ static int run_rounds(bp_instance *h, const Params &P, hipStream_t st) {
     return 0;
 }
 
-// Graphs hold the Params by value: rebuild when they change.
-static void invalidate_graph(bp_instance *h, const Params &P) {
+// Graphs hold their kernel arguments by value: rebuild when they change.
+static void invalidate_graph(bp_instance *h, const Params &P, const ProbeIO *io) {
     Engine &E = *h->eng;
-    if (E.graph && memcmp(&E.graph_params, &P, sizeof(Params)) != 0) {
+    bool same = E.graph && memcmp(&E.graph_params, &P, sizeof(Params)) == 0 &&
+                E.graph_probe == (io != nullptr) &&
+                (!io || memcmp(&E.graph_io, io, sizeof(ProbeIO)) == 0);
+    if (E.graph && !same) {
         (void)hipGraphExecDestroy(E.graph);
         E.graph = nullptr;
     }
     E.graph_params = P;
+    E.graph_probe = io != nullptr;
+    if (io) E.graph_io = *io;
 }
 
-// Reset the control block and the slots [0, ns) to ACTIVE.
-__global__ void k_reset_slots(SlotInfo *info, int32_t ns, int32_t job0) {
+// Reset the slots [0, ns) to `state`.
+__global__ void k_reset_slots(SlotInfo *info, int32_t ns, int32_t job0, int32_t state) {
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < ns; j += gridDim.x * blockDim.x) {
         SlotInfo &S = info[j];
-        S.state = SLOT_ACTIVE;
+        S.state = state;
+        S.retire = 0;
         S.status = 0;
         S.rounds = 0;
         S.row_bad_min = NONE;
@@ -632,7 +649,7 @@ static int start_slots(bp_instance *h, const Params &P, int32_t ns, hipStream_t 
         c.hchunks[0] = (uint32_t)(h->heavy_chunks * ns);
     }
     HIPTRY(hipMemcpyAsync(P.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, st));
-    k_reset_slots<<<grid_for(ns), 256, 0, st>>>(P.info, ns, 0);
+    k_reset_slots<<<grid_for(ns), 256, 0, st>>>(P.info, ns, 0, SLOT_ACTIVE);
     if (cold) {
         SeedAll S;
         S.rows = h->cold_rows.as<int32_t>();
@@ -696,8 +713,9 @@ static int propagate_slots(bp_instance *h, int32_t Bv, double *lb, double *ub,
     const int64_t n = h->n;
     if (int rc = engine_ensure(h, Bv, false, st)) return rc;
     Params P = make_params(h, Bv);
-    invalidate_graph(h, P);
+    invalidate_graph(h, P, nullptr);
     Engine &E = *h->eng;
+    E.clean_slots = 0;  // the vectors overwrite slots [0, Bv)
     // Bounds in, box check.
     if (n > 0) k_pack<<<grid_for(n * Bv), 256, 0, st>>>(lb, ub, E.bnd.as<double2>(), n, Bv);
     DevBuf boxd;
@@ -739,7 +757,7 @@ static int propagate_slots(bp_instance *h, int32_t Bv, double *lb, double *ub,
     }
     k_check_any_active<<<1, 256, 0, st>>>(P, Bv);
     HIPTRY(hipGetLastError());
-    if (int rc = run_rounds(h, P, st)) return rc;
+    if (int rc = run_rounds(h, P, nullptr, (int64_t)h->opt.max_rounds + 2, st)) return rc;
     std::vector<SlotInfo> info(Bv);
     HIPTRY(hipMemcpyAsync(info.data(), P.info, Bv * sizeof(SlotInfo), hipMemcpyDeviceToHost, st));
     if (n > 0) k_unpack<<<grid_for(n * Bv), 256, 0, st>>>(E.bnd.as<double2>(), lb, ub, n * Bv);
@@ -771,7 +789,10 @@ extern "C" int bp_propagate(bp_instance *h, double *lb, double *ub, const int32_
         HIPTRY(hipGetLastError());
         HIPTRY(hipStreamSynchronize(st));
     }
-    if (res->status == BP_OK) h->have_base = true;
+    if (res->status == BP_OK) {
+        h->have_base = true;
+        h->base_version += 1;
+    }
     return res->status;
 }
 
@@ -817,11 +838,139 @@ extern "C" int bp_kernel_stats(bp_instance *h, bp_stats *out, int reset) {
     return BP_OK;
 }
 
+// Probe variables must be integers whose base bounds lie in [0, 1].
+__global__ void k_check_probe_vars(const int32_t *vars, int32_t k, int32_t n, const uint8_t *vtype,
+                                   const double2 *base, int32_t *bad) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < k; t += gridDim.x * blockDim.x) {
+        int j = vars[t];
+        bool ok = j >= 0 && j < n;
+        if (ok) {
+            double2 b = base[j];
+            ok = vtype[j] != 0 && b.x >= 0.0 && b.y <= 1.0;
+        }
+        if (!ok) atomicMin(bad, t);
+    }
+}
+
+// Done before the first round when no slot was admitted with work.
+__global__ void k_probe_start_check(Params P) {
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    for (int j = threadIdx.x; j < P.nslots; j += blockDim.x)
+        if (P.info[j].state != SLOT_FREE) atomicOr(&any, 1);
+    __syncthreads();
+    if (threadIdx.x == 0)
+        P.ctl->done = (!any && P.ctl->next_job >= P.ctl->total_jobs) ? 1u : 0u;
+}
+
+static int ensure_buf(DevBuf &b, size_t bytes) {
+    if (b.p && b.bytes >= bytes) return 0;
+    int64_t dummy = 0;
+    return b.alloc(bytes, dummy);
+}
+
 extern "C" int bp_probe(bp_instance *h, const int32_t *vars, int32_t k, bp_probe_out *out,
                         void *stream) {
     g_err.clear();
-    (void)vars; (void)k; (void)out; (void)stream;
-    if (!h) return fail(BP_EINVAL, "bp_probe: null instance");
+    if (!h || !out || k < 0 || (k > 0 && !vars)) return fail(BP_EINVAL, "bp_probe: bad argument");
+    if (!out->off || out->cap < 0 || (k > 0 && (!out->status || !out->rounds || !out->nnz)))
+        return fail(BP_EINVAL, "bp_probe: null output buffer");
+    if (out->cap > 0 && (!out->var || !out->lb || !out->ub))
+        return fail(BP_EINVAL, "bp_probe: null list buffer");
     if (!h->have_base) return fail(BP_ESTATE, "no base: run a feasible bp_propagate first");
-    return fail(BP_EDEVICE, "bp_probe: not built yet");
+    hipStream_t st = as_stream(stream);
+    const int64_t n = h->n;
+    const int64_t jobs = 2 * (int64_t)k;
+    if (k == 0) {
+        int64_t zero = 0;
+        HIPTRY(hipMemcpyAsync(out->off, &zero, 8, hipMemcpyHostToDevice, st));
+        HIPTRY(hipStreamSynchronize(st));
+        out->required = 0;
+        return BP_OK;
+    }
+    // Validate the variables on the device against the base.
+    if (int rc = ensure_buf(h->scratch_i32, 16)) return rc;
+    {
+        int32_t none = NONE;
+        HIPTRY(hipMemcpyAsync(h->scratch_i32.p, &none, 4, hipMemcpyHostToDevice, st));
+        k_check_probe_vars<<<grid_for(k), 256, 0, st>>>(vars, k, h->n, h->vtype.as<uint8_t>(),
+                                                        h->base.as<double2>(), h->scratch_i32.as<int32_t>());
+        HIPTRY(hipGetLastError());
+        int32_t bad = NONE;
+        HIPTRY(hipMemcpyAsync(&bad, h->scratch_i32.p, 4, hipMemcpyDeviceToHost, st));
+        HIPTRY(hipStreamSynchronize(st));
+        if (bad != NONE)
+            return fail(BP_EINVAL, "probe variable at position " + std::to_string(bad) +
+                                       " is not an integer with base bounds inside [0, 1]");
+    }
+    const int32_t S = (int32_t)std::min<int64_t>(std::max(1, h->opt.probe_slots), jobs);
+    if (int rc = engine_ensure(h, S, true, st)) return rc;
+    Engine &E = *h->eng;
+    // Slots hold the base; probes restore what they change, so slots stay
+    // clean across calls while the base is unchanged.
+    if (E.clean_version != h->base_version) E.clean_slots = 0;
+    if (E.clean_slots < S && n > 0) {
+        for (int32_t j = E.clean_slots; j < S; ++j)
+            k_copy_bnd<<<grid_for(n), 256, 0, st>>>(h->base.as<double2>(),
+                                                    E.bnd.as<double2>() + (size_t)j * n, n);
+        HIPTRY(hipGetLastError());
+    }
+    // Staging for the implied lists.
+    const int64_t cap = std::max<int64_t>(out->cap, 1);
+    if (int rc = ensure_buf(h->st_var, (size_t)cap * 4)) return rc;
+    if (int rc = ensure_buf(h->st_lb, (size_t)cap * 8)) return rc;
+    if (int rc = ensure_buf(h->st_ub, (size_t)cap * 8)) return rc;
+    if (int rc = ensure_buf(h->st_off, (size_t)jobs * 8)) return rc;
+    if (int rc = ensure_buf(h->st_cnt, (size_t)jobs * 8)) return rc;
+    // Library-owned copies keep the captured graph's arguments stable across calls.
+    if (int rc = ensure_buf(h->st_status, (size_t)jobs)) return rc;
+    if (int rc = ensure_buf(h->st_rounds, (size_t)jobs * 4)) return rc;
+    if (int rc = ensure_buf(h->st_nnz, (size_t)jobs * 8)) return rc;
+    if (int rc = ensure_buf(h->st_vars, (size_t)k * 4)) return rc;
+    HIPTRY(hipMemcpyAsync(h->st_vars.p, vars, (size_t)k * 4, hipMemcpyDeviceToDevice, st));
+    ProbeIO IO;
+    IO.vars = h->st_vars.as<int32_t>();
+    IO.base = h->base.as<double2>();
+    IO.status = h->st_status.as<int8_t>();
+    IO.rounds = h->st_rounds.as<int32_t>();
+    IO.nnz = h->st_nnz.as<int64_t>();
+    IO.stage_off = h->st_off.as<int64_t>();
+    IO.stage_cnt = h->st_cnt.as<int64_t>();
+    IO.stage_var = h->st_var.as<int32_t>();
+    IO.stage_lb = h->st_lb.as<double>();
+    IO.stage_ub = h->st_ub.as<double>();
+    IO.stage_cap = cap;
+    Params P = make_params(h, S);
+    invalidate_graph(h, P, &IO);
+    Ctl c;
+    memset(&c, 0, sizeof(c));
+    c.max_rounds = (uint32_t)h->opt.max_rounds;
+    c.nslots = (uint32_t)S;
+    c.total_jobs = (uint32_t)jobs;
+    HIPTRY(hipMemcpyAsync(P.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, st));
+    k_reset_slots<<<grid_for(S), 256, 0, st>>>(P.info, S, 0, SLOT_FREE);
+    k_retire<<<std::min(S, 4096), WG, 0, st>>>(P, IO);  // first admissions
+    k_probe_start_check<<<1, 256, 0, st>>>(P);
+    HIPTRY(hipGetLastError());
+    const int64_t limit = ((int64_t)h->opt.max_rounds + 2) * (jobs + 1);
+    if (int rc = run_rounds(h, P, &IO, limit, st)) return rc;
+    E.clean_slots = S;
+    E.clean_version = h->base_version;
+    Ctl hc;
+    HIPTRY(hipMemcpyAsync(&hc, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+    out->required = (int64_t)hc.stage_count;
+    HIPTRY(hipMemcpyAsync(out->status, IO.status, (size_t)jobs, hipMemcpyDeviceToDevice, st));
+    HIPTRY(hipMemcpyAsync(out->rounds, IO.rounds, (size_t)jobs * 4, hipMemcpyDeviceToDevice, st));
+    HIPTRY(hipMemcpyAsync(out->nnz, IO.nnz, (size_t)jobs * 8, hipMemcpyDeviceToDevice, st));
+    if (out->required > out->cap)
+        return fail(BP_ECAPACITY, "implied lists need " + std::to_string(out->required) +
+                                      " entries, capacity is " + std::to_string(out->cap));
+    k_probe_offsets<<<1, WG, 0, st>>>(IO.stage_cnt, out->off, jobs);
+    k_probe_gather<<<grid_for(jobs * 64, 256), 256, 0, st>>>(IO, out->off, jobs, out->var, out->lb,
+                                                              out->ub);
+    HIPTRY(hipGetLastError());
+    HIPTRY(hipStreamSynchronize(st));
+    return BP_OK;
 }

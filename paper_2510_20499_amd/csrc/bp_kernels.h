@@ -68,6 +68,8 @@ struct SlotInfo {
     int32_t job;        // probe index / vector index
     unsigned long long nnz;
     unsigned long long pending_nnz;
+    int32_t retire;     // finished at the last round end, results not yet written
+    int32_t pad_;
 };
 
 // Round control block (one per engine).
@@ -81,6 +83,10 @@ struct Ctl {
     uint32_t finished;          // slots finished at the last round end
     uint32_t max_rounds;
     uint32_t nslots;
+    // probing: jobs are admitted in order into free slots
+    uint32_t next_job;
+    uint32_t total_jobs;
+    unsigned long long stage_count;  // implied entries staged so far
     // cumulative counters (byte accounting)
     unsigned long long stat_rows;    // row tasks at round starts
     unsigned long long stat_nnz;     // their nonzeros
@@ -716,7 +722,10 @@ __device__ __forceinline__ void append_rows(const Params &P, int par, bool first
 // slot: the first lane to set its bit in the slot's row bitmap appends it.
 // Reached by every lane of the wave.
 __device__ void enqueue_columns(const Params &P, int par, bool want, int s, long long c0,
-                                uint32_t len) {
+                                uint32_t len, bool count = true, uint32_t *rows_out = nullptr,
+                                unsigned long long *nnz_out = nullptr) {
+    uint32_t tot_rows = 0;
+    unsigned long long tot_nnz = 0;
     const int lane = __lane_id();
     if (!want) {
         c0 = 0;
@@ -762,9 +771,19 @@ __device__ void enqueue_columns(const Params &P, int par, bool want, int s, long
             if ((cur & bit) == 0) first = (atomicOr(wp, bit) & bit) == 0;
             rlen = rp1 - rp0;
         }
-        count_pending(P, first, os, first ? rlen : 0);
+        if (count) {
+            count_pending(P, first, os, first ? rlen : 0);
+        } else {
+            unsigned long long x = first ? (unsigned long long)rlen : 0ull;
+#pragma unroll
+            for (int w = 1; w < 64; w <<= 1) x += __shfl_xor(x, w, 64);
+            tot_nnz += x;
+            tot_rows += (uint32_t)__popcll(__ballot(first));
+        }
         append_rows(P, par, first, os, k, bin, rlen);
     }
+    if (rows_out) *rows_out = tot_rows;
+    if (nnz_out) *nnz_out = tot_nnz;
 }
 
 // Dirty tracking for probes: first change of var i in slot s.
@@ -823,6 +842,7 @@ __global__ void __launch_bounds__(WG) k_end(Params P) {
         }
         if (fin) {
             S.state = drain ? SLOT_DRAINING : SLOT_FREE;
+            S.retire = 1;
             atomicAdd(&s_finished, 1u);
             if (drain) atomicAdd(&s_active, 1u);  // still has queued tasks
         }
@@ -839,7 +859,7 @@ __global__ void __launch_bounds__(WG) k_end(Params P) {
         C->active = s_active;
         C->finished = s_finished;
         C->round = C->round + 1;
-        if (s_active == 0) C->done = 1;
+        if (s_active == 0 && C->next_job >= C->total_jobs) C->done = 1;
     }
 }
 
@@ -899,6 +919,261 @@ __global__ void __launch_bounds__(WG) k_apply(Params P) {
         if (wm && lane == __ffsll((long long)wm) - 1)
             atomicAdd(&C->stat_written, (unsigned long long)__popcll(wm));
         enqueue_columns(P, npar, go, s, c0, clen);
+    }
+}
+
+// ------------------------------------------------------------------------
+// Probing (the paper's Section 2.2): jobs p = 2t + v fix vars[t] to v.
+// Slots are retired and refilled at round boundaries.
+// ------------------------------------------------------------------------
+struct ProbeIO {
+    const int32_t *vars;     // [k]
+    const double2 *base;     // [n] base bounds
+    int8_t *status;          // [2k]
+    int32_t *rounds;         // [2k]
+    int64_t *nnz;            // [2k]
+    int64_t *stage_off;      // [2k] start of the probe's staged list
+    int64_t *stage_cnt;      // [2k] its length
+    int32_t *stage_var;      // [stage_cap] lists, ascending within a probe
+    double *stage_lb, *stage_ub;
+    int64_t stage_cap;
+};
+
+constexpr int SORT_MAX = 4096;  // lists up to this length are sorted in LDS
+
+struct RetireScratch {
+    int32_t key[SORT_MAX];
+    uint32_t wsum[WG];
+    uint32_t total;
+    long long off;
+    int32_t job, cnt, flag;
+};
+
+// Write the job's outcome and reserve its staged list.
+__device__ void write_job(const Params &P, const ProbeIO &IO, int p, int status, int rounds,
+                          unsigned long long nnz, int cnt, RetireScratch &R) {
+    if (threadIdx.x == 0) {
+        IO.status[p] = (int8_t)status;
+        IO.rounds[p] = rounds;
+        IO.nnz[p] = (int64_t)nnz;
+        unsigned long long off = atomicAdd(&P.ctl->stage_count, (unsigned long long)cnt);
+        IO.stage_off[p] = (int64_t)off;
+        IO.stage_cnt[p] = cnt;
+        R.off = (long long)off;
+    }
+    __syncthreads();
+}
+
+// Stage the dirty variables of slot s (with their bounds) in ascending order
+// at R.off: bitonic sort in LDS for short lists, an ordered scan of the
+// dirty bitmap for long ones.
+__device__ void stage_sorted(const Params &P, const ProbeIO &IO, int s, int cnt, RetireScratch &R) {
+    const long long off = R.off;
+    if (off + cnt > IO.stage_cap) return;  // counted only; the call reports the size
+    const double2 *bnd = P.bnd + (size_t)s * P.I.n;
+    if (cnt <= SORT_MAX) {
+        int npow = 1;
+        while (npow < cnt) npow <<= 1;
+        for (int t = threadIdx.x; t < npow; t += WG)
+            R.key[t] = t < cnt ? P.dlist[(size_t)s * P.I.n + t] : 0x7fffffff;
+        __syncthreads();
+        for (int size = 2; size <= npow; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int t = threadIdx.x; t < npow; t += WG) {
+                    int u = t ^ stride;
+                    if (u > t) {
+                        bool up = (t & size) == 0;
+                        int a = R.key[t], b = R.key[u];
+                        if ((a > b) == up) {
+                            R.key[t] = b;
+                            R.key[u] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int t = threadIdx.x; t < cnt; t += WG) {
+            int i = R.key[t];
+            double2 b = bnd[i];
+            IO.stage_var[off + t] = i;
+            IO.stage_lb[off + t] = b.x;
+            IO.stage_ub[off + t] = b.y;
+        }
+        __syncthreads();
+    } else {
+        const uint32_t *dw = P.dirty + (size_t)s * P.nw_var;
+        long long run = 0;
+        for (int w0 = 0; w0 < P.nw_var; w0 += WG) {
+            int w = w0 + threadIdx.x;
+            uint32_t bits = w < P.nw_var ? dw[w] : 0u;
+            R.wsum[threadIdx.x] = (uint32_t)__popc(bits);
+            __syncthreads();
+            if (threadIdx.x == 0) {  // exclusive prefix of the popcounts
+                uint32_t acc = 0;
+                for (int t = 0; t < WG; ++t) {
+                    uint32_t x = R.wsum[t];
+                    R.wsum[t] = acc;
+                    acc += x;
+                }
+                R.total = acc;
+            }
+            __syncthreads();
+            long long pos = run + R.wsum[threadIdx.x];
+            while (bits) {
+                int b = __ffs(bits) - 1;
+                bits &= bits - 1;
+                int i = w * 32 + b;
+                double2 bb = bnd[i];
+                IO.stage_var[off + pos] = i;
+                IO.stage_lb[off + pos] = bb.x;
+                IO.stage_ub[off + pos] = bb.y;
+                ++pos;
+            }
+            run += R.total;
+            __syncthreads();
+        }
+    }
+}
+
+// Restore the dirty variables of slot s to the base and clear its bitmap.
+__device__ void restore_slot(const Params &P, const ProbeIO &IO, int s, int cnt) {
+    double2 *bnd = P.bnd + (size_t)s * P.I.n;
+    uint32_t *dw = P.dirty + (size_t)s * P.nw_var;
+    for (int t = threadIdx.x; t < cnt; t += WG) {
+        int i = P.dlist[(size_t)s * P.I.n + t];
+        bnd[i] = IO.base[i];
+        dw[i >> 5] = 0u;  // every set bit of the word belongs to this list
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) P.dcount[s] = 0;
+}
+
+// One workgroup per slot: write the results of a slot that finished at the
+// last round end, restore it, then admit the next probes into free slots.
+__global__ void __launch_bounds__(WG) k_retire(Params P, ProbeIO IO) {
+    __shared__ RetireScratch R;
+    Ctl *C = P.ctl;
+    const int par = C->round & 1;
+    for (int s = blockIdx.x; s < P.nslots; s += gridDim.x) {
+        SlotInfo &S = P.info[s];
+        if (S.retire) {
+            const int p = S.job;
+            const int status = S.status;
+            const int cnt = status == 1 ? 0 : P.dcount[s];
+            const int dcnt = P.dcount[s];
+            write_job(P, IO, p, status, S.rounds, S.nnz, cnt, R);
+            if (cnt > 0) stage_sorted(P, IO, s, cnt, R);
+            restore_slot(P, IO, s, dcnt);
+            if (threadIdx.x == 0) S.retire = 0;
+            __syncthreads();
+        }
+        if (S.state != SLOT_FREE) continue;
+        // Admit jobs until one needs rounds or none is left.
+        for (;;) {
+            if (threadIdx.x == 0) R.job = (int)atomicAdd(&C->next_job, 1u);
+            __syncthreads();
+            const int p = R.job;
+            __syncthreads();
+            if ((uint32_t)p >= C->total_jobs) break;
+            const int j = IO.vars[p >> 1];
+            const double v = (double)(p & 1);
+            const double2 b = IO.base[j];
+            if (v < b.x || v > b.y) {  // the value is outside the base box
+                write_job(P, IO, p, 1, 0, 0ull, 0, R);
+                continue;
+            }
+            if (b.x == v && b.y == v) {  // the base already fixes j at v
+                write_job(P, IO, p, 0, 0, 0ull, 0, R);
+                continue;
+            }
+            if (threadIdx.x == 0) {
+                P.bnd[(size_t)s * P.I.n + j] = make_double2(v, v);
+                P.dirty[(size_t)s * P.nw_var + (j >> 5)] = 1u << (j & 31);
+                P.dlist[(size_t)s * P.I.n] = j;
+                P.dcount[s] = 1;
+                S.status = 0;
+                S.rounds = 0;
+                S.row_bad_min = NONE;
+                S.row_bad_count = 0;
+                S.var_bad_min = NONE;
+                S.pending_rows = 0;
+                S.pending_nnz = 0;
+                S.nnz = 0;
+                S.job = p;
+                S.retire = 0;
+            }
+            // The first round holds the rows of column j (one wave queues them).
+            if (threadIdx.x < 64) {
+                long long c0 = P.I.col_ptr[j];
+                uint32_t len = (uint32_t)(P.I.col_ptr[j + 1] - c0);
+                uint32_t rows = 0;
+                unsigned long long nnz = 0;
+                enqueue_columns(P, par, threadIdx.x == 0, s, c0, len, false, &rows, &nnz);
+                if (threadIdx.x == 0) {
+                    R.flag = rows > 0 ? 1 : 0;
+                    if (rows > 0) {
+                        S.rounds = 1;
+                        S.nnz = nnz;
+                        S.state = SLOT_ACTIVE;
+                        atomicAdd(&C->stat_rows, (unsigned long long)rows);
+                        atomicAdd(&C->stat_nnz, nnz);
+                    }
+                }
+            }
+            __syncthreads();
+            if (R.flag) break;
+            // Variable in no row: nothing to propagate; its list is itself.
+            write_job(P, IO, p, 0, 0, 0ull, 1, R);
+            if (threadIdx.x == 0 && R.off + 1 <= IO.stage_cap) {
+                IO.stage_var[R.off] = j;
+                IO.stage_lb[R.off] = v;
+                IO.stage_ub[R.off] = v;
+            }
+            restore_slot(P, IO, s, 1);
+            __syncthreads();
+        }
+        __syncthreads();
+    }
+}
+
+// off[p+1] = off[p] + count[p] over 2k probes (one workgroup).
+__global__ void __launch_bounds__(WG) k_probe_offsets(const int64_t *cnt, int64_t *off, int64_t np) {
+    __shared__ long long part[WG];
+    __shared__ long long carry;
+    if (threadIdx.x == 0) {
+        carry = 0;
+        off[0] = 0;
+    }
+    __syncthreads();
+    for (int64_t b0 = 0; b0 < np; b0 += WG) {
+        int64_t p = b0 + threadIdx.x;
+        long long x = p < np ? cnt[p] : 0;
+        part[threadIdx.x] = x;
+        __syncthreads();
+        for (int d = 1; d < WG; d <<= 1) {
+            long long y = threadIdx.x >= d ? part[threadIdx.x - d] : 0;
+            __syncthreads();
+            part[threadIdx.x] += y;
+            __syncthreads();
+        }
+        if (p < np) off[p + 1] = carry + part[threadIdx.x];
+        __syncthreads();
+        if (threadIdx.x == WG - 1) carry += part[WG - 1];
+        __syncthreads();
+    }
+}
+
+// Copy every probe's staged list to its place in the caller's arrays.
+__global__ void k_probe_gather(const ProbeIO IO, const int64_t *off, int64_t np, int32_t *ovar,
+                               double *olb, double *oub) {
+    for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
+        int64_t src = IO.stage_off[p], dst = off[p], c = IO.stage_cnt[p];
+        for (int64_t t = threadIdx.x; t < c; t += blockDim.x) {
+            ovar[dst + t] = IO.stage_var[src + t];
+            olb[dst + t] = IO.stage_lb[src + t];
+            oub[dst + t] = IO.stage_ub[src + t];
+        }
     }
 }
 

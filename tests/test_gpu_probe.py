@@ -1,0 +1,140 @@
+"""GPU parity of double probing (bp_probe) against the CPU oracle: per-probe
+outcome, rounds, propagated nonzeros and implication lists (integer bounds
+bit-exact, continuous bounds within 1e-9 relative)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import bp, dev, gpu_propagate
+from helpers import load_golden, rel_close
+from paper_2510_20499_amd import gen
+
+pytestmark = pytest.mark.gpu
+INF = math.inf
+
+
+def _probe_both(inst, vars_, slots=None, cap=None, opts_kw=None):
+    kw = dict(opts_kw or {})
+    if slots is not None:
+        kw["probe_slots"] = slots
+    I = bp().Instance(inst, bp().default_options(**kw))
+    r, lb, ub = gpu_propagate(I, inst)
+    assert r["status"] == bp().BP_OK
+    vs = np.asarray(vars_, np.int32)
+    G = I.probe(dev(vs, torch.int32), cap=cap)
+    torch.cuda.synchronize()
+    O = oracle.probe(inst, lb, ub, vs)
+    integ = inst["vtype"] == 1
+    st = G["status"].cpu().numpy()
+    rd = G["rounds"].cpu().numpy()
+    nz = G["nnz"].cpu().numpy()
+    off = G["off"].cpu().numpy()
+    gv = G["var"].cpu().numpy()
+    gl = G["lb"].cpu().numpy()
+    gu = G["ub"].cpu().numpy()
+    assert np.array_equal(st, O["status"]), (np.nonzero(st != O["status"])[0][:10])
+    assert np.array_equal(rd, O["rounds"]), (np.nonzero(rd != O["rounds"])[0][:10])
+    assert np.array_equal(nz, O["nnz"])
+    assert np.array_equal(off, O["off"])
+    assert np.array_equal(gv, O["var"])
+    ii = integ[gv] if gv.size else np.zeros(0, bool)
+    assert np.array_equal(gl[ii], O["lb"][ii]) and np.array_equal(gu[ii], O["ub"][ii])
+    assert rel_close(gl[~ii], O["lb"][~ii]) and rel_close(gu[~ii], O["ub"][~ii])
+    return G, O
+
+
+@pytest.mark.parametrize("name", ["w1", "w2"])
+def test_golden_probes(name):
+    inst, d = load_golden(name)
+    G, O = _probe_both(inst, d["probe_vars"])
+    for p, exp in enumerate(d["probes"]):
+        assert int(G["status"][p]) == exp["status"]
+        assert int(G["rounds"][p]) == exp["rounds"]
+        assert int(G["nnz"][p]) == exp["nnz"]
+
+
+def _binaries(inst, lb, ub):
+    return np.nonzero((inst["vtype"] == 1) & (lb >= 0) & (ub <= 1))[0]
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("slots", [512, 7])
+def test_tiny_all_binaries(seed, slots):
+    inst = gen.make("tiny", seed)
+    _, lb, ub = oracle.propagate(inst)
+    _probe_both(inst, _binaries(inst, lb, ub), slots=slots)
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_micro_probes(seed):
+    inst = gen.make_micro(seed)
+    r, lb, ub = oracle.propagate(inst)
+    if r["status"] != oracle.BP_OK:
+        return
+    vs = _binaries(inst, lb, ub)
+    if vs.size:
+        _probe_both(inst, vs, slots=3)
+
+
+def test_probe_workload_scaled():
+    inst = gen.make("probe", 0, scale=0.004)
+    _, lb, ub = oracle.propagate(inst)
+    vs = gen.pick_probe_vars(inst, lb, ub, 300, seed=0)
+    _probe_both(inst, vs, slots=64)
+
+
+def test_single_scaled_with_heavy_rows():
+    inst = gen.make("single", 1, scale=0.05)
+    _, lb, ub = oracle.propagate(inst)
+    vs = gen.pick_probe_vars(inst, lb, ub, 120, seed=1)
+    _probe_both(inst, vs, slots=32, opts_kw=dict(heavy_threshold=1024))
+
+
+def test_long_implication_list_uses_bitmap_path():
+    # y + x_j <= 1 for 5000 binaries x_j: probing y = 1 fixes all of them.
+    m = 5000
+    n = m + 1
+    rows = [([j, m], [1.0, 1.0]) for j in range(m)]
+    inst = gen.from_rows(n, rows, [-INF] * m, [1.0] * m, [1] * n, [0.0] * n, [1.0] * n)
+    G, O = _probe_both(inst, [m, 0, 1])
+    assert int(G["off"][2]) - int(G["off"][1]) == m + 1
+
+
+def test_capacity_two_phase_and_states():
+    inst = gen.make("tiny", 2)
+    I = bp().Instance(inst)
+    vs = dev(np.arange(0, 10, dtype=np.int32), torch.int32)
+    with pytest.raises(bp().BPError) as e:  # no base yet
+        I.probe(vs)
+    assert e.value.code == bp().BP_ESTATE
+    _, lb, ub = gpu_propagate(I, inst)
+    bins = _binaries(inst, lb, ub)
+    G = I.probe(dev(bins[:20].astype(np.int32), torch.int32), cap=1)  # grows via required
+    O = oracle.probe(inst, lb, ub, bins[:20])
+    assert np.array_equal(G["var"].cpu().numpy(), O["var"])
+    cont = np.nonzero(inst["vtype"] == 0)[0][:1].astype(np.int32)
+    with pytest.raises(bp().BPError) as e:
+        I.probe(dev(cont, torch.int32))
+    assert e.value.code == bp().BP_EINVAL
+    # empty probe list
+    G = I.probe(dev(np.zeros(0, np.int32), torch.int32))
+    assert int(G["off"][0]) == 0
+
+
+def test_repeated_calls_keep_slots_clean():
+    inst = gen.make("tiny", 4)
+    I = bp().Instance(inst, bp().default_options(probe_slots=16))
+    _, lb, ub = gpu_propagate(I, inst)
+    vs = _binaries(inst, lb, ub).astype(np.int32)
+    O = oracle.probe(inst, lb, ub, vs)
+    for _ in range(3):
+        G = I.probe(dev(vs, torch.int32))
+        assert np.array_equal(G["var"].cpu().numpy(), O["var"])
+        assert np.array_equal(G["status"].cpu().numpy(), O["status"])
+    # a propagate in between (slots reused by the plain path) then probe again
+    gpu_propagate(I, inst, lb, ub)
+    G = I.probe(dev(vs, torch.int32))
+    assert np.array_equal(G["var"].cpu().numpy(), O["var"])
