@@ -38,6 +38,8 @@ def main():
     ap.add_argument("--probe-vars", type=int, default=4096)
     ap.add_argument("--probe-plain", type=int, default=256,
                     help="binaries probed one call at a time for the plain baseline")
+    ap.add_argument("--only-probe", action="store_true",
+                    help="run only the double-probing measurement (for profilers)")
     ap.add_argument("--probe-cpu", type=int, default=0,
                     help="binaries the oracle probes for a CPU probing rate (0: skip)")
     args = ap.parse_args()
@@ -50,6 +52,10 @@ def main():
     import torch
 
     from paper_2510_20499_amd import bp, gen
+
+    if args.only_probe:
+        print(json.dumps({"probe_batched": bench_probe(args, bp, gen, torch, np)}), flush=True)
+        return
 
     dev = torch.device("cuda:0")
     inst = gen.make("single", args.seed)

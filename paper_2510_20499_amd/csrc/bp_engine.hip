@@ -73,7 +73,7 @@ struct Engine {
     int32_t cap_slots = 0;
     int32_t track_dirty = 0;
     int64_t bytes = 0;
-    DevBuf bnd, cand, vflag, rflag, info, chg, dirty, dlist, dcount, ctl, touched;
+    DevBuf bnd, cand, vflag, rflag, info, chg, dirty, dlist, dcount, ctl, touched, filt;
     DevBuf q[2][NBIN], hrec[2], hpart;
     // captured graph of `graph_rounds` rounds for this engine's Params
     hipGraphExec_t graph = nullptr;
@@ -81,9 +81,6 @@ struct Engine {
     Params graph_params;
     ProbeIO graph_io;
     bool graph_probe = false;
-    // slots [0, clean_slots) hold the base of version clean_version
-    int32_t clean_slots = 0;
-    int64_t clean_version = -1;
     ~Engine() {
         if (graph) (void)hipGraphExecDestroy(graph);
     }
@@ -467,6 +464,8 @@ static int engine_ensure(bp_instance *h, int32_t slots, bool dirty, hipStream_t 
         HIPTRY(hipMemsetAsync(E->touched.p, 0, E->touched.bytes, st));
     }
     if (dirty) {
+        if ((rc = E->filt.alloc((size_t)S * FILT_WORDS * 4, B))) return rc;
+        HIPTRY(hipMemsetAsync(E->filt.p, 0, E->filt.bytes, st));
         if ((rc = E->dirty.alloc((size_t)S * nw_var * 4, B))) return rc;
         if ((rc = E->dlist.alloc((size_t)S * n * 4, B))) return rc;
         if ((rc = E->dcount.alloc((size_t)S * 4, B))) return rc;
@@ -517,7 +516,9 @@ static Params make_params(const bp_instance *h, int32_t nslots) {
     P.chg = E.chg.as<uint64_t>();
     P.ctl = E.ctl.as<Ctl>();
     P.touched = (h->opt.flags & BP_FLAG_COUNT_VARS) ? E.touched.as<uint32_t>() : nullptr;
-    P.track_dirty = E.track_dirty;
+    P.track_dirty = 0;  // set by bp_probe, which reads bounds as an overlay on the base
+    P.base = h->base.as<double2>();
+    P.filt = E.filt.as<uint32_t>();
     P.dirty = E.dirty.as<uint32_t>();
     P.dlist = E.dlist.as<int32_t>();
     P.dcount = E.dcount.as<int32_t>();
@@ -715,7 +716,6 @@ static int propagate_slots(bp_instance *h, int32_t Bv, double *lb, double *ub,
     Params P = make_params(h, Bv);
     invalidate_graph(h, P, nullptr);
     Engine &E = *h->eng;
-    E.clean_slots = 0;  // the vectors overwrite slots [0, Bv)
     // Bounds in, box check.
     if (n > 0) k_pack<<<grid_for(n * Bv), 256, 0, st>>>(lb, ub, E.bnd.as<double2>(), n, Bv);
     DevBuf boxd;
@@ -907,15 +907,8 @@ extern "C" int bp_probe(bp_instance *h, const int32_t *vars, int32_t k, bp_probe
     const int32_t S = (int32_t)std::min<int64_t>(std::max(1, h->opt.probe_slots), jobs);
     if (int rc = engine_ensure(h, S, true, st)) return rc;
     Engine &E = *h->eng;
-    // Slots hold the base; probes restore what they change, so slots stay
-    // clean across calls while the base is unchanged.
-    if (E.clean_version != h->base_version) E.clean_slots = 0;
-    if (E.clean_slots < S && n > 0) {
-        for (int32_t j = E.clean_slots; j < S; ++j)
-            k_copy_bnd<<<grid_for(n), 256, 0, st>>>(h->base.as<double2>(),
-                                                    E.bnd.as<double2>() + (size_t)j * n, n);
-        HIPTRY(hipGetLastError());
-    }
+    // Probe slots read the base except where their dirty bits are set; a
+    // retired probe clears its bits, so no slot needs initialising.
     // Staging for the implied lists.
     const int64_t cap = std::max<int64_t>(out->cap, 1);
     if (int rc = ensure_buf(h->st_var, (size_t)cap * 4)) return rc;
@@ -942,6 +935,7 @@ extern "C" int bp_probe(bp_instance *h, const int32_t *vars, int32_t k, bp_probe
     IO.stage_ub = h->st_ub.as<double>();
     IO.stage_cap = cap;
     Params P = make_params(h, S);
+    P.track_dirty = 1;
     invalidate_graph(h, P, &IO);
     Ctl c;
     memset(&c, 0, sizeof(c));
@@ -955,8 +949,6 @@ extern "C" int bp_probe(bp_instance *h, const int32_t *vars, int32_t k, bp_probe
     HIPTRY(hipGetLastError());
     const int64_t limit = ((int64_t)h->opt.max_rounds + 2) * (jobs + 1);
     if (int rc = run_rounds(h, P, &IO, limit, st)) return rc;
-    E.clean_slots = S;
-    E.clean_version = h->base_version;
     Ctl hc;
     HIPTRY(hipMemcpyAsync(&hc, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     HIPTRY(hipStreamSynchronize(st));

@@ -113,11 +113,37 @@ struct Params {
     Ctl *ctl;
     uint32_t *touched;           // [nslots][nw_var] bound records read this round
                                  // (only when counting them)
-    // probe mode
+    // probe mode: bounds are an overlay on the base; a slot's own record
+    // of var i is valid only where its dirty bit is set
     int32_t track_dirty;
+    const double2 *base;         // [n]
+    uint32_t *filt;              // [nslots][FILT_WORDS] hashed summary of the dirty bits
     uint32_t *dirty;             // [nslots][nw_var]
     int32_t *dlist;              // [nslots][n]
     int32_t *dcount;             // [nslots]
+};
+
+constexpr int FILT_WORDS = 1024;  // 32768-bit dirty filter per slot (4 KB)
+
+__device__ __forceinline__ uint32_t fhash(int i) { return ((uint32_t)i * 2654435761u) >> 17; }
+
+// Bound records of one slot.  Outside probing a slot owns a dense vector;
+// while probing it reads the base except where its dirty bit is set (the
+// small hashed filter answers "certainly clean" for almost every variable
+// from cache).
+struct BView {
+    const double2 *own, *base;
+    const uint32_t *filt, *dirty;
+    int overlay;
+    __device__ __forceinline__ double2 operator[](int i) const {
+        if (!overlay) return own[i];
+        double2 b = base[i];
+        uint32_t h = fhash(i);
+        if ((filt[h >> 5] >> (h & 31)) & 1u) {
+            if ((dirty[i >> 5] >> (i & 31)) & 1u) b = own[i];
+        }
+        return b;
+    }
 };
 
 // Ordered 64-bit key of a double: signed integer order equals double order.
@@ -127,6 +153,16 @@ __device__ __forceinline__ long long dkey(double x) {
 }
 __device__ __forceinline__ double dunkey(long long k) {
     return __longlong_as_double(k < 0 ? (k ^ 0x7fffffffffffffffll) : k);
+}
+
+__device__ __forceinline__ BView bview(const Params &P, int s) {
+    BView v;
+    v.own = P.bnd + (size_t)s * P.I.n;
+    v.base = P.base;
+    v.filt = P.filt + (size_t)s * FILT_WORDS;
+    v.dirty = P.dirty + (size_t)s * P.nw_var;
+    v.overlay = P.track_dirty;
+    return v;
 }
 
 __device__ __forceinline__ int light_group(int b) { return b >= 6 ? 64 : (1 << b); }
@@ -277,7 +313,7 @@ __device__ __forceinline__ void add_terms(Acc &mn, Acc &mx, double a, double lb,
 // Exact activity of one side of a row over [p0, p1) by one lane.  Kept out
 // of line so its accumulator lives in scratch memory and does not raise the
 // register count of the kernels that may call it.
-__device__ __noinline__ double exact_side(const Params &P, const double2 *bnd, int64_t p0, int64_t p1,
+__device__ __noinline__ double exact_side(const Params &P, const BView &bnd, int64_t p0, int64_t p1,
                                     bool maxside) {
     SuperAcc S;
     sa_zero(S);
@@ -335,7 +371,7 @@ __device__ void light_rows(const Params &P, const uint64_t *q, uint32_t count, u
         if (gl == 0) clear_rflag(P, s, k);
     }
     if (!live) p1 = p0;
-    const double2 *bnd = P.bnd + (size_t)s * P.I.n;
+    const BView bnd = bview(P, s);
     Acc mn, mx;
     acc_zero(mn);
     acc_zero(mx);
@@ -464,7 +500,7 @@ __device__ void block_row(const Params &P, const uint64_t *q, uint32_t t, WgScra
     if (threadIdx.x == 0) clear_rflag(P, s, k);
     if (!live) return;  // workgroup-uniform
     int64_t p0 = P.I.row_ptr[k], p1 = P.I.row_ptr[k + 1];
-    const double2 *bnd = P.bnd + (size_t)s * P.I.n;
+    const BView bnd = bview(P, s);
     Acc mn, mx;
     acc_zero(mn);
     acc_zero(mx);
@@ -527,7 +563,7 @@ __device__ void heavy_chunk_activity(const Params &P, int par, uint32_t u, WgScr
     if (!live) return;  // workgroup-uniform
     int64_t p0 = r0 + (int64_t)c * P.heavy_chunk;
     int64_t p1 = min(r1, p0 + (int64_t)P.heavy_chunk);
-    const double2 *bnd = P.bnd + (size_t)s * P.I.n;
+    const BView bnd = bview(P, s);
     Acc mn, mx;
     acc_zero(mn);
     acc_zero(mx);
@@ -553,7 +589,7 @@ __device__ void heavy_chunk_candidates(const Params &P, int par, uint32_t u) {
     const int lane = __lane_id();
     const int64_t r0 = P.I.row_ptr[k], r1 = P.I.row_ptr[k + 1];
     const double2 sd = P.I.side[k];
-    const double2 *bnd = P.bnd + (size_t)s * P.I.n;
+    const BView bnd = bview(P, s);
     const uint32_t u0 = u - (uint32_t)c;
     Acc A, B;
     acc_zero(A);
@@ -790,6 +826,8 @@ __device__ void enqueue_columns(const Params &P, int par, bool want, int s, long
 __device__ __forceinline__ void mark_dirty(const Params &P, int s, int i) {
     uint32_t bit = 1u << (i & 31);
     uint32_t old = atomicOr(&P.dirty[(size_t)s * P.nw_var + (i >> 5)], bit);
+    uint32_t h = fhash(i);
+    atomicOr(&P.filt[(size_t)s * FILT_WORDS + (h >> 5)], 1u << (h & 31));
     if ((old & bit) == 0) {
         int d = atomicAdd(&P.dcount[s], 1);
         P.dlist[(size_t)s * P.I.n + d] = i;
@@ -897,7 +935,7 @@ __global__ void __launch_bounds__(WG) k_apply(Params P) {
             SlotInfo &S = P.info[s];
             if (S.row_bad_count == 0) {
                 double2 *bp = &P.bnd[(size_t)s * P.I.n + i];
-                double2 b = *bp;
+                double2 b = bview(P, s)[i];
                 bool is_int = P.I.vtype[i] != 0;
                 double L = dunkey(kl), U = dunkey(ku);
                 double nl = b.x, nu = b.y;
@@ -970,7 +1008,7 @@ __device__ void write_job(const Params &P, const ProbeIO &IO, int p, int status,
 __device__ void stage_sorted(const Params &P, const ProbeIO &IO, int s, int cnt, RetireScratch &R) {
     const long long off = R.off;
     if (off + cnt > IO.stage_cap) return;  // counted only; the call reports the size
-    const double2 *bnd = P.bnd + (size_t)s * P.I.n;
+    const BView bnd = bview(P, s);
     if (cnt <= SORT_MAX) {
         int npow = 1;
         while (npow < cnt) npow <<= 1;
@@ -1038,12 +1076,14 @@ __device__ void stage_sorted(const Params &P, const ProbeIO &IO, int s, int cnt,
 
 // Restore the dirty variables of slot s to the base and clear its bitmap.
 __device__ void restore_slot(const Params &P, const ProbeIO &IO, int s, int cnt) {
-    double2 *bnd = P.bnd + (size_t)s * P.I.n;
     uint32_t *dw = P.dirty + (size_t)s * P.nw_var;
+    uint32_t *fw = P.filt + (size_t)s * FILT_WORDS;
     for (int t = threadIdx.x; t < cnt; t += WG) {
         int i = P.dlist[(size_t)s * P.I.n + t];
-        bnd[i] = IO.base[i];
-        dw[i >> 5] = 0u;  // every set bit of the word belongs to this list
+        // every set bit of these words belongs to this list: the slot
+        // reads the base again
+        dw[i >> 5] = 0u;
+        fw[fhash(i) >> 5] = 0u;
     }
     __syncthreads();
     if (threadIdx.x == 0) P.dcount[s] = 0;
@@ -1090,6 +1130,7 @@ __global__ void __launch_bounds__(WG) k_retire(Params P, ProbeIO IO) {
             if (threadIdx.x == 0) {
                 P.bnd[(size_t)s * P.I.n + j] = make_double2(v, v);
                 P.dirty[(size_t)s * P.nw_var + (j >> 5)] = 1u << (j & 31);
+                P.filt[(size_t)s * FILT_WORDS + (fhash(j) >> 5)] = 1u << (fhash(j) & 31);
                 P.dlist[(size_t)s * P.I.n] = j;
                 P.dcount[s] = 1;
                 S.status = 0;
