@@ -211,6 +211,80 @@ int64_t bp_device_bytes(const bp_instance *h);
 
 void bp_free(bp_instance *h);
 
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of propagate and probe requests over several
+ * resident instances (the batching and serving pattern around the paper's
+ * Section 2.1 propagation and Section 2.2 probing).  Every request becomes
+ * jobs (one per propagate request, two per probed binary); jobs of all
+ * requests and instances advance round-synchronously in the same launches,
+ * each in a slot of a fixed pool whose size is set by a device-memory
+ * budget.  A slot that finishes is refilled with the next queued job at the
+ * next round boundary, so requests that arrive while others run join the
+ * work already on the device.  Each job's result equals what bp_propagate
+ * (from the instance's base with the request's bounds applied) or bp_probe
+ * would return for it alone.
+ * ------------------------------------------------------------------------- */
+#define BP_REQ_PROBE 0      /* probe `count` binaries at 0 and at 1 */
+#define BP_REQ_PROPAGATE 1  /* intersect `count` variables' bounds with
+                               [lb, ub] and propagate from the base */
+
+typedef struct bp_server bp_server;
+
+typedef struct {
+    int32_t instance;      /* index into the instances given to bp_server_create */
+    int32_t kind;          /* BP_REQ_PROBE or BP_REQ_PROPAGATE */
+    int32_t count;         /* binaries (probe) or bound changes (propagate) */
+    int32_t reserved;
+    const int32_t *vars;   /* HOST [count]; distinct variables */
+    const double *lb;      /* HOST [count] new bounds (propagate only) */
+    const double *ub;
+} bp_request;
+
+typedef struct {
+    int64_t id;            /* as returned by bp_server_submit */
+    int32_t instance, kind;
+    int32_t jobs;          /* 1 (propagate) or 2*count (probe) */
+    int32_t reserved;
+    double submit_us;      /* host clock, microseconds since bp_server_create */
+    double done_us;        /* when the server observed the last job finish */
+} bp_completion;
+
+/* Create a server over `count` loaded instances, each with a base (a
+ * feasible bp_propagate was run on it; BP_ESTATE otherwise).  The slot pool
+ * holds as many bound vectors as fit in `budget_bytes` of device memory,
+ * at most opt->probe_slots (opt NULL: the first instance's options).  The
+ * instances must outlive the server. */
+int bp_server_create(bp_instance *const *instances, int32_t count, const bp_options *opt,
+                     int64_t budget_bytes, void *stream, bp_server **out);
+
+/* Queue a request (arrays are copied).  BP_EINVAL for a bad instance index,
+ * kind, variable, a repeated variable, or a probe variable that is not a
+ * binary of the base. */
+int bp_server_submit(bp_server *sv, const bp_request *req, int64_t *id);
+
+/* Move queued requests to the device, run up to `rounds` rounds, and
+ * collect the requests that finished.  *busy receives the number of
+ * requests submitted and not yet finished. */
+int bp_server_run(bp_server *sv, int32_t rounds, int32_t *busy);
+
+/* Finished requests since the last poll, in completion order (at most max;
+ * *n receives the number written). */
+int bp_server_poll(bp_server *sv, bp_completion *out, int32_t max, int32_t *n);
+
+/* Results of a finished request, into HOST arrays of `jobs` entries (status,
+ * rounds, nnz, n_bad_rows, bad_row, bad_var; any may be NULL) and its
+ * implication lists: off [jobs+1], var/lb/ub [cap] (job j's list is
+ * [off[j], off[j+1]), ascending by variable).  BP_ECAPACITY with *required
+ * set if cap is too small; BP_ESTATE if the request has not finished. */
+int bp_server_results(bp_server *sv, int64_t id, int8_t *status, int32_t *rounds, int64_t *nnz,
+                      int32_t *n_bad_rows, int32_t *bad_row, int32_t *bad_var, int64_t *off,
+                      int32_t *var, double *lb, double *ub, int64_t cap, int64_t *required);
+
+/* Slots in the pool and device bytes per slot. */
+int bp_server_info(const bp_server *sv, int32_t *slots, int64_t *bytes_per_slot);
+
+void bp_server_destroy(bp_server *sv);
+
 /* Thread-local description of the last error ("" if none). */
 const char *bp_last_error(void);
 

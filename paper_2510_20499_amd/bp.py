@@ -21,7 +21,10 @@ BP_EINVAL, BP_ENOMEM, BP_EDEVICE, BP_ECAPACITY, BP_ESTATE = -1, -2, -3, -4, -5
 FLAG_FORCE_EXACT, FLAG_TIME_KERNELS, FLAG_HOST_ROUNDS, FLAG_COUNT_VARS = 1, 2, 4, 8
 
 EXPORTS = ["bp_options_default", "bp_load", "bp_propagate", "bp_propagate_batch", "bp_probe",
-           "bp_get_base", "bp_kernel_stats", "bp_device_bytes", "bp_free", "bp_last_error"]
+           "bp_get_base", "bp_kernel_stats", "bp_device_bytes", "bp_free", "bp_last_error",
+           "bp_server_create", "bp_server_submit", "bp_server_run", "bp_server_poll",
+           "bp_server_results", "bp_server_info", "bp_server_destroy"]
+REQ_PROBE, REQ_PROPAGATE = 0, 1
 
 
 class Sparse(C.Structure):
@@ -58,6 +61,18 @@ class Stats(C.Structure):
                 ("nnz", C.c_int64), ("vars_read", C.c_int64), ("vars_written", C.c_int64)]
 
 
+class Request(C.Structure):
+    _fields_ = [("instance", C.c_int32), ("kind", C.c_int32), ("count", C.c_int32),
+                ("reserved", C.c_int32), ("vars", C.c_void_p), ("lb", C.c_void_p),
+                ("ub", C.c_void_p)]
+
+
+class Completion(C.Structure):
+    _fields_ = [("id", C.c_int64), ("instance", C.c_int32), ("kind", C.c_int32),
+                ("jobs", C.c_int32), ("reserved", C.c_int32), ("submit_us", C.c_double),
+                ("done_us", C.c_double)]
+
+
 class BPError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("libbp error %d: %s" % (code, msg))
@@ -92,6 +107,23 @@ def load_library(path: str = LIB_PATH):
     lib.bp_free.restype = None
     lib.bp_last_error.argtypes = []
     lib.bp_last_error.restype = C.c_char_p
+    lib.bp_server_create.argtypes = [C.c_void_p, C.c_int32, C.POINTER(Options), C.c_int64,
+                                     C.c_void_p, C.POINTER(C.c_void_p)]
+    lib.bp_server_create.restype = C.c_int
+    lib.bp_server_submit.argtypes = [C.c_void_p, C.POINTER(Request), C.POINTER(C.c_int64)]
+    lib.bp_server_submit.restype = C.c_int
+    lib.bp_server_run.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]
+    lib.bp_server_run.restype = C.c_int
+    lib.bp_server_poll.argtypes = [C.c_void_p, C.POINTER(Completion), C.c_int32,
+                                   C.POINTER(C.c_int32)]
+    lib.bp_server_poll.restype = C.c_int
+    lib.bp_server_results.argtypes = [C.c_void_p, C.c_int64] + [C.c_void_p] * 10 + \
+                                     [C.c_int64, C.POINTER(C.c_int64)]
+    lib.bp_server_results.restype = C.c_int
+    lib.bp_server_info.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
+    lib.bp_server_info.restype = C.c_int
+    lib.bp_server_destroy.argtypes = [C.c_void_p]
+    lib.bp_server_destroy.restype = None
     return lib
 
 
@@ -246,3 +278,85 @@ class Instance:
         _check(_LIB.bp_kernel_stats(self._h, C.byref(s), 1 if reset else 0))
         return dict(ms=s.ms, launches=s.launches, rows=s.rows, nnz=s.nnz,
                     vars_read=s.vars_read, vars_written=s.vars_written)
+
+
+class Server:
+    """Continuous-batching server over loaded instances (bp_server_*)."""
+
+    def __init__(self, instances, budget_bytes: int, options: Options = None, stream=None):
+        self._insts = list(instances)  # keep them alive
+        arr = (C.c_void_p * len(self._insts))(*[i._h.value for i in self._insts])
+        h = C.c_void_p()
+        _check(_LIB.bp_server_create(arr, len(self._insts),
+                                     C.byref(options) if options is not None else None,
+                                     int(budget_bytes), _stream_ptr(stream), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _LIB.bp_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        s, b = C.c_int32(), C.c_int64()
+        _check(_LIB.bp_server_info(self._h, C.byref(s), C.byref(b)))
+        return dict(slots=s.value, bytes_per_slot=b.value)
+
+    def submit(self, instance: int, kind: int, vars_, lb=None, ub=None) -> int:
+        v = np.ascontiguousarray(vars_, dtype=np.int32)
+        lbp = ubp = None
+        keep = [v]
+        if kind == REQ_PROPAGATE:
+            lbp = np.ascontiguousarray(lb, dtype=np.float64)
+            ubp = np.ascontiguousarray(ub, dtype=np.float64)
+            keep += [lbp, ubp]
+        r = Request(instance, kind, v.size, 0, v.ctypes.data if v.size else None,
+                    lbp.ctypes.data if lbp is not None and lbp.size else None,
+                    ubp.ctypes.data if ubp is not None and ubp.size else None)
+        rid = C.c_int64()
+        _check(_LIB.bp_server_submit(self._h, C.byref(r), C.byref(rid)))
+        return rid.value
+
+    def run(self, rounds: int) -> int:
+        busy = C.c_int32()
+        _check(_LIB.bp_server_run(self._h, rounds, C.byref(busy)))
+        return busy.value
+
+    def poll(self, max_items: int = 4096):
+        buf = (Completion * max_items)()
+        n = C.c_int32()
+        _check(_LIB.bp_server_poll(self._h, buf, max_items, C.byref(n)))
+        return [dict(id=buf[i].id, instance=buf[i].instance, kind=buf[i].kind, jobs=buf[i].jobs,
+                     submit_us=buf[i].submit_us, done_us=buf[i].done_us) for i in range(n.value)]
+
+    def results(self, rid: int, jobs: int) -> dict:
+        req = C.c_int64()
+        cap = 0
+        while True:
+            st = np.zeros(jobs, np.int8)
+            rd = np.zeros(jobs, np.int32)
+            nz = np.zeros(jobs, np.int64)
+            nb = np.zeros(jobs, np.int32)
+            br = np.zeros(jobs, np.int32)
+            bv = np.zeros(jobs, np.int32)
+            off = np.zeros(jobs + 1, np.int64)
+            var = np.zeros(max(cap, 1), np.int32)
+            lb = np.zeros(max(cap, 1))
+            ub = np.zeros(max(cap, 1))
+            rc = _LIB.bp_server_results(self._h, rid, st.ctypes.data, rd.ctypes.data,
+                                        nz.ctypes.data, nb.ctypes.data, br.ctypes.data,
+                                        bv.ctypes.data, off.ctypes.data, var.ctypes.data,
+                                        lb.ctypes.data, ub.ctypes.data, cap, C.byref(req))
+            if rc == BP_ECAPACITY:
+                cap = int(req.value)
+                continue
+            _check(rc)
+            tot = int(off[-1])
+            return dict(status=st, rounds=rd, nnz=nz, n_infeasible_rows=nb, infeasible_row=br,
+                        infeasible_var=bv, off=off, var=var[:tot], lb=lb[:tot], ub=ub[:tot])

@@ -69,9 +69,24 @@ struct DevBuf {
     }
 };
 
+// Per-slot capacities of an engine: variables and rows per slot (the largest
+// instance whose vectors it holds), tasks per bin and heavy chunks per slot.
+struct Shape {
+    int64_t sn = 0, sm = 0;
+    int64_t bin_cap[NBIN] = {0};
+    int64_t heavy_chunks = 0;
+    bool covers(const Shape &o) const {
+        if (sn < o.sn || sm < o.sm || heavy_chunks < o.heavy_chunks) return false;
+        for (int b = 0; b < NBIN; ++b)
+            if (bin_cap[b] < o.bin_cap[b]) return false;
+        return true;
+    }
+};
+
 struct Engine {
     int32_t cap_slots = 0;
     int32_t track_dirty = 0;
+    Shape shape;
     int64_t bytes = 0;
     DevBuf bnd, cand, vflag, rflag, info, chg, dirty, dlist, dcount, ctl, touched, filt;
     DevBuf q[2][NBIN], hrec[2], hpart;
@@ -79,8 +94,8 @@ struct Engine {
     hipGraphExec_t graph = nullptr;
     int graph_rounds = 0;
     Params graph_params;
-    ProbeIO graph_io;
-    bool graph_probe = false;
+    JobIO graph_io;
+    bool graph_jobs = false;
     ~Engine() {
         if (graph) (void)hipGraphExecDestroy(graph);
     }
@@ -99,8 +114,8 @@ struct bp_instance {
     int64_t base_version = 0;
     // probe staging (reused across calls)
     DevBuf st_var, st_lb, st_ub, st_off, st_cnt, scratch_i32;
-    DevBuf st_status, st_rounds, st_nnz, st_vars;  // per-job results and the probe list
-    int64_t st_cap = 0, st_jobs = 0;
+    DevBuf st_status, st_rounds, st_nnz, st_jobs;  // per-job results and descriptors
+    int64_t st_cap = 0;
     // row bins (host)
     int64_t bin_count[NBIN] = {0};
     int64_t bin_start[NBIN + 1] = {0};
@@ -246,7 +261,7 @@ __global__ void k_seed_vars(Params P, const int32_t *vars, const int64_t *ptr, i
             c0 = P.I.col_ptr[i];
             clen = (uint32_t)(P.I.col_ptr[i + 1] - c0);
         }
-        enqueue_columns(P, 0, has, s, c0, clen);
+        enqueue_columns<false>(P, 0, has, s, c0, clen);
     }
 }
 
@@ -433,16 +448,28 @@ extern "C" int64_t bp_device_bytes(const bp_instance *h) {
 // ------------------------------------------------------------------------
 // Engine allocation
 // ------------------------------------------------------------------------
-static int engine_ensure(bp_instance *h, int32_t slots, bool dirty, hipStream_t st) {
-    const bool count = (h->opt.flags & BP_FLAG_COUNT_VARS) != 0;
-    if (h->eng && h->eng->cap_slots >= slots && (!dirty || h->eng->track_dirty) &&
-        (!count || h->eng->touched.p))
+static Shape shape_of(const bp_instance *h) {
+    Shape sh;
+    sh.sn = h->n;
+    sh.sm = h->m;
+    for (int b = 0; b < NBIN; ++b) sh.bin_cap[b] = h->bin_count[b];
+    sh.heavy_chunks = h->heavy_chunks;
+    return sh;
+}
+
+// (Re)allocate `E` for `slots` bound vectors of shape `sh`; dirty: with the
+// overlay bookkeeping of jobs; count: with the distinct-record bitmap.
+static int engine_alloc(std::unique_ptr<Engine> &eng, const Shape &sh, int32_t slots, bool dirty,
+                        bool count, hipStream_t st) {
+    if (eng && eng->cap_slots >= slots && eng->shape.covers(sh) && (!dirty || eng->track_dirty) &&
+        (!count || eng->touched.p))
         return 0;
-    h->eng.reset();
+    eng.reset();
     std::unique_ptr<Engine> E(new Engine());
     E->cap_slots = slots;
     E->track_dirty = dirty ? 1 : 0;
-    const int64_t n = h->n, m = h->m, S = slots;
+    E->shape = sh;
+    const int64_t n = std::max<int64_t>(sh.sn, 1), m = std::max<int64_t>(sh.sm, 1), S = slots;
     const int64_t nw_var = (n + 31) / 32, nw_row = (m + 31) / 32;
     int64_t &B = E->bytes;
     int rc;
@@ -455,10 +482,10 @@ static int engine_ensure(bp_instance *h, int32_t slots, bool dirty, hipStream_t 
     if ((rc = E->ctl.alloc(sizeof(Ctl), B))) return rc;
     for (int par = 0; par < 2; ++par) {
         for (int b = 0; b < BIN_HEAVY; ++b)
-            if ((rc = E->q[par][b].alloc((size_t)S * h->bin_count[b] * 8, B))) return rc;
-        if ((rc = E->hrec[par].alloc((size_t)S * h->heavy_chunks * sizeof(int4), B))) return rc;
+            if ((rc = E->q[par][b].alloc((size_t)S * sh.bin_cap[b] * 8, B))) return rc;
+        if ((rc = E->hrec[par].alloc((size_t)S * sh.heavy_chunks * sizeof(int4), B))) return rc;
     }
-    if ((rc = E->hpart.alloc((size_t)S * h->heavy_chunks * 2 * sizeof(Acc), B))) return rc;
+    if ((rc = E->hpart.alloc((size_t)S * sh.heavy_chunks * 2 * sizeof(Acc), B))) return rc;
     if (count) {
         if ((rc = E->touched.alloc((size_t)S * nw_var * 4, B))) return rc;
         HIPTRY(hipMemsetAsync(E->touched.p, 0, E->touched.bytes, st));
@@ -477,32 +504,45 @@ static int engine_ensure(bp_instance *h, int32_t slots, bool dirty, hipStream_t 
     HIPTRY(hipMemsetAsync(E->info.p, 0, E->info.bytes, st));
     k_fill_cand<<<grid_for(S * n), 256, 0, st>>>(E->cand.as<longlong2>(), S * n);
     HIPTRY(hipGetLastError());
-    h->eng = std::move(E);
+    eng = std::move(E);
     return 0;
 }
 
-static Params make_params(const bp_instance *h, int32_t nslots) {
-    const Engine &E = *h->eng;
+static int engine_ensure(bp_instance *h, int32_t slots, bool dirty, hipStream_t st) {
+    return engine_alloc(h->eng, shape_of(h), slots, dirty, (h->opt.flags & BP_FLAG_COUNT_VARS) != 0,
+                        st);
+}
+
+static DInst dinst_of(const bp_instance *h) {
+    DInst I;
+    I.m = h->m;
+    I.n = h->n;
+    I.row_ptr = h->row_ptr.as<int64_t>();
+    I.col = h->col.as<int32_t>();
+    I.val = h->val.as<double>();
+    I.side = h->side.as<double2>();
+    I.col_ptr = h->col_ptr.as<int64_t>();
+    I.col_row = h->col_row.as<int32_t>();
+    I.vtype = h->vtype.as<uint8_t>();
+    I.rbin = h->rbin.as<uint8_t>();
+    I.base = h->base.as<double2>();
+    return I;
+}
+
+// Kernel arguments for an engine; the instance fields are set by the caller.
+static Params engine_params(const Engine &E, const bp_options &opt, int32_t heavy_chunk,
+                            int32_t nslots) {
     Params P;
     memset(&P, 0, sizeof(P));
-    P.I.m = h->m;
-    P.I.n = h->n;
-    P.I.row_ptr = h->row_ptr.as<int64_t>();
-    P.I.col = h->col.as<int32_t>();
-    P.I.val = h->val.as<double>();
-    P.I.side = h->side.as<double2>();
-    P.I.col_ptr = h->col_ptr.as<int64_t>();
-    P.I.col_row = h->col_row.as<int32_t>();
-    P.I.vtype = h->vtype.as<uint8_t>();
-    P.I.rbin = h->rbin.as<uint8_t>();
-    P.feastol = h->opt.feastol;
-    P.inttol = h->opt.inttol;
-    P.tau = h->opt.tau;
-    P.heavy_chunk = h->heavy_chunk;
-    P.force_exact = (h->opt.flags & BP_FLAG_FORCE_EXACT) ? 1 : 0;
+    P.feastol = opt.feastol;
+    P.inttol = opt.inttol;
+    P.tau = opt.tau;
+    P.heavy_chunk = heavy_chunk;
+    P.force_exact = (opt.flags & BP_FLAG_FORCE_EXACT) ? 1 : 0;
     P.nslots = nslots;
-    P.nw_var = (h->n + 31) / 32;
-    P.nw_row = (h->m + 31) / 32;
+    P.sn = (int32_t)std::max<int64_t>(E.shape.sn, 1);
+    P.snw = (int32_t)((P.sn + 31) / 32);
+    P.srw = (int32_t)((std::max<int64_t>(E.shape.sm, 1) + 31) / 32);
     P.bnd = E.bnd.as<double2>();
     P.cand = E.cand.as<longlong2>();
     P.vflag = E.vflag.as<uint32_t>();
@@ -515,9 +555,8 @@ static Params make_params(const bp_instance *h, int32_t nslots) {
     P.hpart = E.hpart.as<Acc>();
     P.chg = E.chg.as<uint64_t>();
     P.ctl = E.ctl.as<Ctl>();
-    P.touched = (h->opt.flags & BP_FLAG_COUNT_VARS) ? E.touched.as<uint32_t>() : nullptr;
-    P.track_dirty = 0;  // set by bp_probe, which reads bounds as an overlay on the base
-    P.base = h->base.as<double2>();
+    P.touched = (opt.flags & BP_FLAG_COUNT_VARS) ? E.touched.as<uint32_t>() : nullptr;
+    P.overlay = 0;  // jobs read bounds as an overlay on the base
     P.filt = E.filt.as<uint32_t>();
     P.dirty = E.dirty.as<uint32_t>();
     P.dlist = E.dlist.as<int32_t>();
@@ -525,29 +564,37 @@ static Params make_params(const bp_instance *h, int32_t nslots) {
     return P;
 }
 
+static Params make_params(const bp_instance *h, int32_t nslots) {
+    Params P = engine_params(*h->eng, h->opt, h->heavy_chunk, nslots);
+    P.I = dinst_of(h);
+    P.multi = 0;
+    P.insts = nullptr;
+    return P;
+}
+
 static const int GRID_ROWS = 2048;
 static const int GRID_HEAVY = 1024;
 static const int GRID_APPLY = 512;
 
-static int launch_round(bp_instance *h, const Params &P, const ProbeIO *io, hipStream_t st,
+static int launch_round(bp_instance *h, const Params &P, const JobIO *io, hipStream_t st,
                         bool timed) {
     if (timed) {
         // Start/stop events recorded by the dispatch of k_rows itself, so the
         // interval is the kernel's execution (no dispatch latency).
-        hipExtLaunchKernelGGL(k_rows, dim3(GRID_ROWS), dim3(WG), 0, st, h->ev0, h->ev1, 0, P);
+        hipExtLaunchKernelGGL(k_rows<false>, dim3(GRID_ROWS), dim3(WG), 0, st, h->ev0, h->ev1, 0, P);
     } else {
-        k_rows<<<GRID_ROWS, WG, 0, st>>>(P);
+        k_rows<false><<<GRID_ROWS, WG, 0, st>>>(P);
     }
-    k_heavy<<<GRID_HEAVY, WG, 0, st>>>(P);
-    k_apply<<<GRID_APPLY, WG, 0, st>>>(P);
+    k_heavy<false><<<GRID_HEAVY, WG, 0, st>>>(P);
+    k_apply<false><<<GRID_APPLY, WG, 0, st>>>(P);
     k_end<<<1, WG, 0, st>>>(P);
-    if (io) k_retire<<<std::min(P.nslots, 4096), WG, 0, st>>>(P, *io);
+    if (io) k_retire<false><<<std::min(P.nslots, 4096), WG, 0, st>>>(P, *io);
     HIPTRY(hipGetLastError());
     return 0;
 }
 
 // Run rounds until every slot is finished (and, when probing, every job).
-static int run_rounds(bp_instance *h, const Params &P, const ProbeIO *io, int64_t limit,
+static int run_rounds(bp_instance *h, const Params &P, const JobIO *io, int64_t limit,
                       hipStream_t st) {
     Engine &E = *h->eng;
     Ctl hc;
@@ -576,11 +623,11 @@ static int run_rounds(bp_instance *h, const Params &P, const ProbeIO *io, int64_
                 HIPTRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
                 HIPTRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
                 for (int r = 0; r < K; ++r) {
-                    k_rows<<<GRID_ROWS, WG, 0, cs>>>(P);
-                    k_heavy<<<GRID_HEAVY, WG, 0, cs>>>(P);
-                    k_apply<<<GRID_APPLY, WG, 0, cs>>>(P);
+                    k_rows<false><<<GRID_ROWS, WG, 0, cs>>>(P);
+                    k_heavy<false><<<GRID_HEAVY, WG, 0, cs>>>(P);
+                    k_apply<false><<<GRID_APPLY, WG, 0, cs>>>(P);
                     k_end<<<1, WG, 0, cs>>>(P);
-                    if (io) k_retire<<<std::min(P.nslots, 4096), WG, 0, cs>>>(P, *io);
+                    if (io) k_retire<false><<<std::min(P.nslots, 4096), WG, 0, cs>>>(P, *io);
                 }
                 hipGraph_t g;
                 HIPTRY(hipStreamEndCapture(cs, &g));
@@ -606,17 +653,17 @@ static int run_rounds(bp_instance *h, const Params &P, const ProbeIO *io, int64_
 }
 
 // Graphs hold their kernel arguments by value: rebuild when they change.
-static void invalidate_graph(bp_instance *h, const Params &P, const ProbeIO *io) {
+static void invalidate_graph(bp_instance *h, const Params &P, const JobIO *io) {
     Engine &E = *h->eng;
     bool same = E.graph && memcmp(&E.graph_params, &P, sizeof(Params)) == 0 &&
-                E.graph_probe == (io != nullptr) &&
-                (!io || memcmp(&E.graph_io, io, sizeof(ProbeIO)) == 0);
+                E.graph_jobs == (io != nullptr) &&
+                (!io || memcmp(&E.graph_io, io, sizeof(JobIO)) == 0);
     if (E.graph && !same) {
         (void)hipGraphExecDestroy(E.graph);
         E.graph = nullptr;
     }
     E.graph_params = P;
-    E.graph_probe = io != nullptr;
+    E.graph_jobs = io != nullptr;
     if (io) E.graph_io = *io;
 }
 
@@ -920,11 +967,11 @@ extern "C" int bp_probe(bp_instance *h, const int32_t *vars, int32_t k, bp_probe
     if (int rc = ensure_buf(h->st_status, (size_t)jobs)) return rc;
     if (int rc = ensure_buf(h->st_rounds, (size_t)jobs * 4)) return rc;
     if (int rc = ensure_buf(h->st_nnz, (size_t)jobs * 8)) return rc;
-    if (int rc = ensure_buf(h->st_vars, (size_t)k * 4)) return rc;
-    HIPTRY(hipMemcpyAsync(h->st_vars.p, vars, (size_t)k * 4, hipMemcpyDeviceToDevice, st));
-    ProbeIO IO;
-    IO.vars = h->st_vars.as<int32_t>();
-    IO.base = h->base.as<double2>();
+    if (int rc = ensure_buf(h->st_jobs, (size_t)jobs * sizeof(Job))) return rc;
+    k_make_probe_jobs<<<grid_for(jobs), 256, 0, st>>>(vars, k, h->st_jobs.as<Job>());
+    JobIO IO;
+    memset(&IO, 0, sizeof(IO));
+    IO.jobs = h->st_jobs.as<Job>();
     IO.status = h->st_status.as<int8_t>();
     IO.rounds = h->st_rounds.as<int32_t>();
     IO.nnz = h->st_nnz.as<int64_t>();
@@ -935,7 +982,7 @@ extern "C" int bp_probe(bp_instance *h, const int32_t *vars, int32_t k, bp_probe
     IO.stage_ub = h->st_ub.as<double>();
     IO.stage_cap = cap;
     Params P = make_params(h, S);
-    P.track_dirty = 1;
+    P.overlay = 1;
     invalidate_graph(h, P, &IO);
     Ctl c;
     memset(&c, 0, sizeof(c));
@@ -944,7 +991,7 @@ extern "C" int bp_probe(bp_instance *h, const int32_t *vars, int32_t k, bp_probe
     c.total_jobs = (uint32_t)jobs;
     HIPTRY(hipMemcpyAsync(P.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, st));
     k_reset_slots<<<grid_for(S), 256, 0, st>>>(P.info, S, 0, SLOT_FREE);
-    k_retire<<<std::min(S, 4096), WG, 0, st>>>(P, IO);  // first admissions
+    k_retire<false><<<std::min(S, 4096), WG, 0, st>>>(P, IO);  // first admissions
     k_probe_start_check<<<1, 256, 0, st>>>(P);
     HIPTRY(hipGetLastError());
     const int64_t limit = ((int64_t)h->opt.max_rounds + 2) * (jobs + 1);
@@ -959,10 +1006,12 @@ extern "C" int bp_probe(bp_instance *h, const int32_t *vars, int32_t k, bp_probe
     if (out->required > out->cap)
         return fail(BP_ECAPACITY, "implied lists need " + std::to_string(out->required) +
                                       " entries, capacity is " + std::to_string(out->cap));
-    k_probe_offsets<<<1, WG, 0, st>>>(IO.stage_cnt, out->off, jobs);
-    k_probe_gather<<<grid_for(jobs * 64, 256), 256, 0, st>>>(IO, out->off, jobs, out->var, out->lb,
-                                                              out->ub);
+    k_job_offsets<<<1, WG, 0, st>>>(IO.stage_cnt, out->off, jobs);
+    k_job_gather<<<grid_for(jobs * 64, 256), 256, 0, st>>>(IO, out->off, jobs, out->var, out->lb,
+                                                            out->ub);
     HIPTRY(hipGetLastError());
     HIPTRY(hipStreamSynchronize(st));
     return BP_OK;
 }
+
+#include "bp_server.h"

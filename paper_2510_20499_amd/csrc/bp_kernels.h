@@ -1,25 +1,30 @@
 // bp_kernels.h -- HIP kernels for round-synchronous bound propagation.
 //
 // One round (the paper's Section 2.1: activities of the constraints, then
-// bound updates) runs as three kernels over a slot table.  A slot is one
-// bound vector in flight: the single vector of bp_propagate, one candidate
-// of bp_propagate_batch, or one probe of bp_probe.
+// bound updates) runs as kernels over a slot table.  A slot is one bound
+// vector in flight: the vector of bp_propagate, one candidate of
+// bp_propagate_batch, one probe of bp_probe, or one job of a serving
+// request.  Slots may belong to different instances (serving); each slot's
+// per-variable arrays have a fixed stride sized for the largest instance.
 //
-//   rows   (activity + candidates)  every queued (slot, row) task of the
-//          round: the row activity, the row infeasibility test and, for
-//          light and block rows, the candidates of every nonzero, scattered
-//          as order-independent 64-bit integer atomic min/max into the
-//          slot's candidate array.  Only candidates that pass the threshold
-//          against the round-start bounds are scattered: the threshold is
-//          monotone in the candidate, so the tightest candidate passes iff
-//          some candidate passes.  Heavy rows (split across workgroups) only
-//          produce chunk partials here; the last chunk combines them.
-//   heavy  (candidates of heavy rows) chunk by chunk.
-//   apply  (bound update) each (slot, variable) that received a candidate:
-//          acceptance, crossing test, new bounds, and the rows of the
-//          variable's column queued for the next round (the paper's
-//          "propagation on changed constraints", Section 1).  Its last
-//          workgroup closes the round for every slot.
+//   k_rows   (activity + candidates) every queued (slot, row) task of the
+//            round: the row activity, the row infeasibility test and, for
+//            light and block rows, the candidates of every nonzero,
+//            scattered as order-independent 64-bit integer atomic min/max
+//            into the slot's candidate array.  Only candidates that pass
+//            the threshold against the round-start bounds are scattered:
+//            the threshold is monotone in the candidate, so the tightest
+//            candidate passes iff some candidate passes.  Heavy rows only
+//            produce chunk partials here.
+//   k_heavy  (candidates of heavy rows) combines the partials of each row,
+//            tests it, and scatters the candidates of each chunk.
+//   k_apply  (bound update) each (slot, variable) that received a
+//            candidate: acceptance, crossing test, new bounds, and the rows
+//            of the variable's column queued for the next round (the
+//            paper's "propagation on changed constraints", Section 1).
+//   k_end    per-slot round end (one workgroup).
+//   k_retire (jobs only) results of finished jobs, slot restore, admission
+//            of the next jobs into free slots.
 //
 // Rows are binned by length (logarithmic radix binning, Section 2.1 load
 // balancing): bin b <= 10 holds rows of length in (2^(b-1), 2^b] and is
@@ -40,6 +45,7 @@ constexpr int BIN_HEAVY = 12;
 constexpr int NBIN = 13;
 constexpr int WG = 256;             // workgroup size of every kernel
 constexpr int32_t NONE = 0x7fffffff;
+constexpr int FILT_WORDS = 1024;    // 32768-bit dirty filter per slot (4 KB)
 
 enum : int32_t { SLOT_FREE = 0, SLOT_ACTIVE = 1, SLOT_DRAINING = 2 };
 
@@ -54,6 +60,7 @@ struct DInst {
     const int32_t *col_row;
     const uint8_t *vtype;
     const uint8_t *rbin;
+    const double2 *base;    // base bounds (jobs read them as an overlay)
 };
 
 // Per-slot bookkeeping.
@@ -65,11 +72,11 @@ struct SlotInfo {
     int32_t row_bad_count;
     int32_t var_bad_min;
     int32_t pending_rows;
-    int32_t job;        // probe index / vector index
+    int32_t job;        // job or vector index
     unsigned long long nnz;
     unsigned long long pending_nnz;
     int32_t retire;     // finished at the last round end, results not yet written
-    int32_t pad_;
+    int32_t inst;       // instance of the slot
 };
 
 // Round control block (one per engine).
@@ -79,13 +86,15 @@ struct Ctl {
     uint32_t qcount[2][NBIN];   // queue lengths per parity
     uint32_t hchunks[2];        // heavy chunks per parity
     uint32_t nchanged;          // (slot, var) entries of the current round
-    uint32_t active;            // slots active after the last round end
+    uint32_t active;            // slots active or draining after the last round end
     uint32_t finished;          // slots finished at the last round end
     uint32_t max_rounds;
     uint32_t nslots;
-    // probing: jobs are admitted in order into free slots
+    // jobs are admitted in order into free slots
     uint32_t next_job;
     uint32_t total_jobs;
+    uint32_t done_jobs;              // entries of the completion ring
+    uint32_t pad_;
     unsigned long long stage_count;  // implied entries staged so far
     // cumulative counters (byte accounting)
     unsigned long long stat_rows;    // row tasks at round starts
@@ -95,42 +104,49 @@ struct Ctl {
 };
 
 struct Params {
-    DInst I;
+    DInst I;                     // the instance when there is one
+    const DInst *insts;          // per-instance table when slots mix instances
+    int32_t multi;
     double feastol, inttol, tau;
     int32_t heavy_chunk;         // nonzeros per heavy chunk
     int32_t force_exact;
     int32_t nslots;
-    int32_t nw_var, nw_row;      // 32-bit words per slot in the var / row bitmaps
-    double2 *bnd;                // [nslots][n]
-    longlong2 *cand;             // [nslots][n] (lower key, upper key)
-    uint32_t *vflag;             // [nslots][nw_var]
-    uint32_t *rflag;             // [nslots][nw_row]
+    int32_t sn;                  // variables per slot (stride of the per-variable arrays)
+    int32_t snw, srw;            // 32-bit words per slot of the variable / row bitmaps
+    double2 *bnd;                // [nslots][sn]
+    longlong2 *cand;             // [nslots][sn] (lower key, upper key)
+    uint32_t *vflag;             // [nslots][snw]
+    uint32_t *rflag;             // [nslots][srw]
     SlotInfo *info;              // [nslots]
     uint64_t *q[2][NBIN];        // task queues (slot << 32 | row)
     int4 *hrec[2];               // heavy chunks: (slot, row, chunk index, chunks of the row)
     Acc *hpart;                  // [chunks][2] partial (min, max) states
     uint64_t *chg;               // (slot << 32 | var) entries of the round
     Ctl *ctl;
-    uint32_t *touched;           // [nslots][nw_var] bound records read this round
+    uint32_t *touched;           // [nslots][snw] bound records read this round
                                  // (only when counting them)
-    // probe mode: bounds are an overlay on the base; a slot's own record
-    // of var i is valid only where its dirty bit is set
-    int32_t track_dirty;
-    const double2 *base;         // [n]
+    // jobs: bounds are an overlay on the instance's base; a slot's own
+    // record of var i is valid only where its dirty bit is set
+    int32_t overlay;
     uint32_t *filt;              // [nslots][FILT_WORDS] hashed summary of the dirty bits
-    uint32_t *dirty;             // [nslots][nw_var]
-    int32_t *dlist;              // [nslots][n]
+    uint32_t *dirty;             // [nslots][snw]
+    int32_t *dlist;              // [nslots][sn]
     int32_t *dcount;             // [nslots]
 };
 
-constexpr int FILT_WORDS = 1024;  // 32768-bit dirty filter per slot (4 KB)
+// Instance of slot s (MULTI: slots mix instances; otherwise the kernel
+// argument, uniform across the grid).
+template <bool MULTI>
+__device__ __forceinline__ DInst inst_of(const Params &P, int s) {
+    if constexpr (MULTI) return P.insts[P.info[s].inst];
+    else return P.I;
+}
 
 __device__ __forceinline__ uint32_t fhash(int i) { return ((uint32_t)i * 2654435761u) >> 17; }
 
-// Bound records of one slot.  Outside probing a slot owns a dense vector;
-// while probing it reads the base except where its dirty bit is set (the
-// small hashed filter answers "certainly clean" for almost every variable
-// from cache).
+// Bound records of one slot.  Outside jobs a slot owns a dense vector; a
+// job reads the base except where its dirty bit is set (the small hashed
+// filter answers "certainly clean" for almost every variable from cache).
 struct BView {
     const double2 *own, *base;
     const uint32_t *filt, *dirty;
@@ -146,6 +162,16 @@ struct BView {
     }
 };
 
+__device__ __forceinline__ BView bview(const Params &P, int s, const double2 *base) {
+    BView v;
+    v.own = P.bnd + (size_t)s * P.sn;
+    v.base = base;
+    v.filt = P.filt + (size_t)s * FILT_WORDS;
+    v.dirty = P.dirty + (size_t)s * P.snw;
+    v.overlay = P.overlay;
+    return v;
+}
+
 // Ordered 64-bit key of a double: signed integer order equals double order.
 __device__ __forceinline__ long long dkey(double x) {
     long long b = __double_as_longlong(x);
@@ -153,16 +179,6 @@ __device__ __forceinline__ long long dkey(double x) {
 }
 __device__ __forceinline__ double dunkey(long long k) {
     return __longlong_as_double(k < 0 ? (k ^ 0x7fffffffffffffffll) : k);
-}
-
-__device__ __forceinline__ BView bview(const Params &P, int s) {
-    BView v;
-    v.own = P.bnd + (size_t)s * P.I.n;
-    v.base = P.base;
-    v.filt = P.filt + (size_t)s * FILT_WORDS;
-    v.dirty = P.dirty + (size_t)s * P.nw_var;
-    v.overlay = P.track_dirty;
-    return v;
 }
 
 __device__ __forceinline__ int light_group(int b) { return b >= 6 ? 64 : (1 << b); }
@@ -269,7 +285,7 @@ __device__ __forceinline__ void mark_var(const Params &P, bool want, int s, int 
     bool first = false;
     if (want) {
         uint32_t bit = 1u << (i & 31);
-        uint32_t old = atomicOr(&P.vflag[(size_t)s * P.nw_var + (i >> 5)], bit);
+        uint32_t old = atomicOr(&P.vflag[(size_t)s * P.snw + (i >> 5)], bit);
         first = (old & bit) == 0;
     }
     wave_push(P.chg, &P.ctl->nchanged, first, ((uint64_t)(uint32_t)s << 32) | (uint32_t)i);
@@ -280,7 +296,7 @@ __device__ __forceinline__ void mark_var(const Params &P, bool want, int s, int 
 __device__ __forceinline__ bool scatter(const Params &P, int s, int i, double cl, double cu,
                                         double lb, double ub, bool is_int) {
     bool any = false;
-    longlong2 *cp = &P.cand[(size_t)s * P.I.n + i];
+    longlong2 *cp = &P.cand[(size_t)s * P.sn + i];
     if (take_lower(is_int, cl, lb, P.tau)) {
         atomicMax(&cp->x, dkey(canon0(cl)));
         any = true;
@@ -296,7 +312,7 @@ __device__ __forceinline__ bool scatter(const Params &P, int s, int i, double cl
 __device__ __forceinline__ void count_read(const Params &P, int s, int i) {
     if (!P.touched) return;
     uint32_t bit = 1u << (i & 31);
-    uint32_t old = atomicOr(&P.touched[(size_t)s * P.nw_var + (i >> 5)], bit);
+    uint32_t old = atomicOr(&P.touched[(size_t)s * P.snw + (i >> 5)], bit);
     if ((old & bit) == 0) atomicAdd(&P.ctl->stat_vars, 1ull);
 }
 
@@ -313,13 +329,13 @@ __device__ __forceinline__ void add_terms(Acc &mn, Acc &mx, double a, double lb,
 // Exact activity of one side of a row over [p0, p1) by one lane.  Kept out
 // of line so its accumulator lives in scratch memory and does not raise the
 // register count of the kernels that may call it.
-__device__ __noinline__ double exact_side(const Params &P, const BView &bnd, int64_t p0, int64_t p1,
-                                    bool maxside) {
+__device__ __noinline__ double exact_side(const DInst &I, const BView &bnd, int64_t p0, int64_t p1,
+                                          bool maxside) {
     SuperAcc S;
     sa_zero(S);
     for (int64_t p = p0; p < p1; ++p) {
-        double a = P.I.val[p];
-        double2 b = bnd[P.I.col[p]];
+        double a = I.val[p];
+        double2 b = bnd[I.col[p]];
         double bb = (a > 0.0) != maxside ? b.x : b.y;
         if (!isinf(bb)) sa_add(S, a * bb);
     }
@@ -339,14 +355,14 @@ __device__ __forceinline__ void report_bad_row(const Params &P, int s, int k) {
 
 __device__ __forceinline__ void clear_rflag(const Params &P, int s, int k) {
     uint32_t bit = 1u << (k & 31);
-    atomicAnd(&P.rflag[(size_t)s * P.nw_row + (k >> 5)], ~bit);
+    atomicAnd(&P.rflag[(size_t)s * P.srw + (k >> 5)], ~bit);
 }
 
 // ------------------------------------------------------------------------
 // Light rows: G lanes per row, len <= G (bins 0..6) or one wave per row
 // with several nonzeros per lane (bins 7..10).
 // ------------------------------------------------------------------------
-template <int G>
+template <bool MULTI, int G>
 __device__ void light_rows(const Params &P, const uint64_t *q, uint32_t count, uint32_t unit) {
     const int lane = __lane_id();
     const int wave = threadIdx.x >> 6;
@@ -358,20 +374,22 @@ __device__ void light_rows(const Params &P, const uint64_t *q, uint32_t count, u
     bool live = false;
     int64_t p0 = 0, p1 = 0;
     double2 sd = make_double2(0.0, 0.0);
+    DInst I = P.I;
     if (valid) {
         uint64_t task = q[t];
         s = (int)(task >> 32);
         k = (int)(uint32_t)task;
+        I = inst_of<MULTI>(P, s);
         // independent loads, issued together
         int32_t state = P.info[s].state;
-        p0 = P.I.row_ptr[k];
-        p1 = P.I.row_ptr[k + 1];
-        sd = P.I.side[k];
+        p0 = I.row_ptr[k];
+        p1 = I.row_ptr[k + 1];
+        sd = I.side[k];
         live = state == SLOT_ACTIVE;
         if (gl == 0) clear_rflag(P, s, k);
     }
     if (!live) p1 = p0;
-    const BView bnd = bview(P, s);
+    const BView bnd = bview(P, s, I.base);
     Acc mn, mx;
     acc_zero(mn);
     acc_zero(mx);
@@ -386,10 +404,10 @@ __device__ void light_rows(const Params &P, const uint64_t *q, uint32_t count, u
     for (int it = 0; it < iters; ++it) {
         int64_t p = p0 + gl + (int64_t)it * G;
         if (p < p1) {
-            int i = P.I.col[p];
-            double a = P.I.val[p];
+            int i = I.col[p];
+            double a = I.val[p];
             double2 b = bnd[i];
-            uint8_t vt = P.I.vtype[i];
+            uint8_t vt = I.vtype[i];
             add_terms(mn, mx, a, b.x, b.y);
             count_read(P, s, i);
             if (it == 0) {
@@ -412,8 +430,8 @@ __device__ void light_rows(const Params &P, const uint64_t *q, uint32_t count, u
     bool ok_min = !P.force_exact && acc_certify(mn, R.minfin);
     bool ok_max = !P.force_exact && acc_certify(mx, R.maxfin);
     if (live && gl == 0) {
-        if (!ok_min) R.minfin = exact_side(P, bnd, p0, p1, false);
-        if (!ok_max) R.maxfin = exact_side(P, bnd, p0, p1, true);
+        if (!ok_min) R.minfin = exact_side(I, bnd, p0, p1, false);
+        if (!ok_max) R.maxfin = exact_side(I, bnd, p0, p1, true);
     }
     {
         // The group's first lane holds the exact values; every lane of the
@@ -446,10 +464,10 @@ __device__ void light_rows(const Params &P, const uint64_t *q, uint32_t count, u
                 b = first_b;
                 is_int = first_t != 0;
             } else {
-                i = P.I.col[p];
-                a = P.I.val[p];
+                i = I.col[p];
+                a = I.val[p];
                 b = bnd[i];
-                is_int = P.I.vtype[i] != 0;
+                is_int = I.vtype[i] != 0;
             }
             double cl, cu;
             nz_candidates(R, a, b.x, b.y, is_int, P.inttol, cl, cu);
@@ -492,6 +510,7 @@ __device__ inline void wg_reduce(Acc &mn, Acc &mx, WgScratch &W) {
 }
 
 // Block rows: one workgroup per row (1024 < len <= heavy threshold).
+template <bool MULTI>
 __device__ void block_row(const Params &P, const uint64_t *q, uint32_t t, WgScratch &W) {
     uint64_t task = q[t];
     int s = (int)(task >> 32);
@@ -499,15 +518,16 @@ __device__ void block_row(const Params &P, const uint64_t *q, uint32_t t, WgScra
     bool live = P.info[s].state == SLOT_ACTIVE;
     if (threadIdx.x == 0) clear_rflag(P, s, k);
     if (!live) return;  // workgroup-uniform
-    int64_t p0 = P.I.row_ptr[k], p1 = P.I.row_ptr[k + 1];
-    const BView bnd = bview(P, s);
+    const DInst I = inst_of<MULTI>(P, s);
+    int64_t p0 = I.row_ptr[k], p1 = I.row_ptr[k + 1];
+    const BView bnd = bview(P, s, I.base);
     Acc mn, mx;
     acc_zero(mn);
     acc_zero(mx);
     for (int64_t p = p0 + threadIdx.x; p < p1; p += WG) {
-        double2 b = bnd[P.I.col[p]];
-        add_terms(mn, mx, P.I.val[p], b.x, b.y);
-        count_read(P, s, P.I.col[p]);
+        double2 b = bnd[I.col[p]];
+        add_terms(mn, mx, I.val[p], b.x, b.y);
+        count_read(P, s, I.col[p]);
     }
     wg_reduce(mn, mx, W);
     RowAct R;
@@ -517,15 +537,15 @@ __device__ void block_row(const Params &P, const uint64_t *q, uint32_t t, WgScra
     bool ok_max = !P.force_exact && acc_certify(mx, R.maxfin);
     if (!(ok_min && ok_max)) {
         if (threadIdx.x == 0) {
-            W.act[0] = ok_min ? R.minfin : exact_side(P, bnd, p0, p1, false);
-            W.act[1] = ok_max ? R.maxfin : exact_side(P, bnd, p0, p1, true);
+            W.act[0] = ok_min ? R.minfin : exact_side(I, bnd, p0, p1, false);
+            W.act[1] = ok_max ? R.maxfin : exact_side(I, bnd, p0, p1, true);
         }
         __syncthreads();
         R.minfin = W.act[0];
         R.maxfin = W.act[1];
         __syncthreads();
     }
-    double2 sd = P.I.side[k];
+    double2 sd = I.side[k];
     R.lo = sd.x;
     R.hi = sd.y;
     if (row_bad(R, P.feastol)) {
@@ -539,10 +559,10 @@ __device__ void block_row(const Params &P, const uint64_t *q, uint32_t t, WgScra
         bool need = false;
         int i = 0;
         if (p < p1) {
-            i = P.I.col[p];
-            double a = P.I.val[p];
+            i = I.col[p];
+            double a = I.val[p];
             double2 b = bnd[i];
-            bool is_int = P.I.vtype[i] != 0;
+            bool is_int = I.vtype[i] != 0;
             double cl, cu;
             nz_candidates(R, a, b.x, b.y, is_int, P.inttol, cl, cu);
             need = scatter(P, s, i, cl, cu, b.x, b.y, is_int);
@@ -554,23 +574,25 @@ __device__ void block_row(const Params &P, const uint64_t *q, uint32_t t, WgScra
 // Heavy chunk, activity part: the partial states of one chunk of a heavy
 // row.  The chunks of a row are contiguous; the candidate kernel of the
 // same round combines them (the kernel boundary makes them visible).
+template <bool MULTI>
 __device__ void heavy_chunk_activity(const Params &P, int par, uint32_t u, WgScratch &W) {
     const int4 rec = P.hrec[par][u];
     const int s = rec.x, k = rec.y, c = rec.z;
     const bool live = P.info[s].state == SLOT_ACTIVE;
-    const int64_t r0 = P.I.row_ptr[k], r1 = P.I.row_ptr[k + 1];
     if (c == 0 && threadIdx.x == 0) clear_rflag(P, s, k);
     if (!live) return;  // workgroup-uniform
+    const DInst I = inst_of<MULTI>(P, s);
+    const int64_t r0 = I.row_ptr[k], r1 = I.row_ptr[k + 1];
     int64_t p0 = r0 + (int64_t)c * P.heavy_chunk;
     int64_t p1 = min(r1, p0 + (int64_t)P.heavy_chunk);
-    const BView bnd = bview(P, s);
+    const BView bnd = bview(P, s, I.base);
     Acc mn, mx;
     acc_zero(mn);
     acc_zero(mx);
     for (int64_t p = p0 + threadIdx.x; p < p1; p += WG) {
-        double2 b = bnd[P.I.col[p]];
-        add_terms(mn, mx, P.I.val[p], b.x, b.y);
-        count_read(P, s, P.I.col[p]);
+        double2 b = bnd[I.col[p]];
+        add_terms(mn, mx, I.val[p], b.x, b.y);
+        count_read(P, s, I.col[p]);
     }
     wg_reduce(mn, mx, W);
     if (threadIdx.x == 0) {
@@ -582,14 +604,16 @@ __device__ void heavy_chunk_activity(const Params &P, int par, uint32_t u, WgScr
 // Heavy chunk, candidate part.  Every wave combines the row's partials
 // (lane l takes chunks l, l+64, ... in order, then a butterfly), certifies
 // the sums and tests the row; the chunk's nonzeros then give candidates.
+template <bool MULTI>
 __device__ void heavy_chunk_candidates(const Params &P, int par, uint32_t u) {
     const int4 rec = P.hrec[par][u];
     const int s = rec.x, k = rec.y, c = rec.z, nch = rec.w;
     if (P.info[s].state != SLOT_ACTIVE) return;  // workgroup-uniform
+    const DInst I = inst_of<MULTI>(P, s);
     const int lane = __lane_id();
-    const int64_t r0 = P.I.row_ptr[k], r1 = P.I.row_ptr[k + 1];
-    const double2 sd = P.I.side[k];
-    const BView bnd = bview(P, s);
+    const int64_t r0 = I.row_ptr[k], r1 = I.row_ptr[k + 1];
+    const double2 sd = I.side[k];
+    const BView bnd = bview(P, s, I.base);
     const uint32_t u0 = u - (uint32_t)c;
     Acc A, B;
     acc_zero(A);
@@ -611,8 +635,8 @@ __device__ void heavy_chunk_candidates(const Params &P, int par, uint32_t u) {
     bool ok_min = !P.force_exact && acc_certify(A, R.minfin);
     bool ok_max = !P.force_exact && acc_certify(B, R.maxfin);
     if (lane == 0) {
-        if (!ok_min) R.minfin = exact_side(P, bnd, r0, r1, false);
-        if (!ok_max) R.maxfin = exact_side(P, bnd, r0, r1, true);
+        if (!ok_min) R.minfin = exact_side(I, bnd, r0, r1, false);
+        if (!ok_max) R.maxfin = exact_side(I, bnd, r0, r1, true);
     }
     R.minfin = __shfl(R.minfin, 0, 64);
     R.maxfin = __shfl(R.maxfin, 0, 64);
@@ -628,10 +652,10 @@ __device__ void heavy_chunk_candidates(const Params &P, int par, uint32_t u) {
         bool need = false;
         int i = 0;
         if (p < p1) {
-            i = P.I.col[p];
-            double a = P.I.val[p];
+            i = I.col[p];
+            double a = I.val[p];
             double2 b = bnd[i];
-            bool is_int = P.I.vtype[i] != 0;
+            bool is_int = I.vtype[i] != 0;
             double cl, cu;
             nz_candidates(R, a, b.x, b.y, is_int, P.inttol, cl, cu);
             need = scatter(P, s, i, cl, cu, b.x, b.y, is_int);
@@ -640,21 +664,18 @@ __device__ void heavy_chunk_candidates(const Params &P, int par, uint32_t u) {
     }
 }
 
-// Work-unit table of the rows kernel for one round.
-struct Units {
-    uint32_t start[NBIN + 2];  // prefix over: heavy chunks, block rows, light bins 10..0
-};
-
 __device__ inline uint32_t light_units(uint32_t count, int b) {
     uint32_t G = (uint32_t)light_group(b);
     return (uint32_t)(((uint64_t)count * G + WG - 1) / WG);
 }
 
+template <bool MULTI>
 __global__ void __launch_bounds__(WG) k_rows(Params P) {
     __shared__ WgScratch W;
     const Ctl *C = P.ctl;
     if (C->done) return;
     const int par = C->round & 1;
+    // Work units: heavy chunks, block rows, then light bins 10..0.
     uint32_t start[NBIN + 2];
     start[0] = 0;
     start[1] = C->hchunks[par];
@@ -666,9 +687,9 @@ __global__ void __launch_bounds__(WG) k_rows(Params P) {
     const uint32_t total = start[2 + NLIGHT];
     for (uint32_t u = blockIdx.x; u < total; u += gridDim.x) {
         if (u < start[1]) {
-            heavy_chunk_activity(P, par, u, W);
+            heavy_chunk_activity<MULTI>(P, par, u, W);
         } else if (u < start[2]) {
-            block_row(P, P.q[par][BIN_BLOCK], u - start[1], W);
+            block_row<MULTI>(P, P.q[par][BIN_BLOCK], u - start[1], W);
         } else {
             int j = 0;
             while (u >= start[3 + j]) ++j;
@@ -677,27 +698,31 @@ __global__ void __launch_bounds__(WG) k_rows(Params P) {
             const uint64_t *q = P.q[par][b];
             uint32_t cnt = C->qcount[par][b];
             switch (b) {
-                case 0: light_rows<1>(P, q, cnt, lu); break;
-                case 1: light_rows<2>(P, q, cnt, lu); break;
-                case 2: light_rows<4>(P, q, cnt, lu); break;
-                case 3: light_rows<8>(P, q, cnt, lu); break;
-                case 4: light_rows<16>(P, q, cnt, lu); break;
-                case 5: light_rows<32>(P, q, cnt, lu); break;
-                default: light_rows<64>(P, q, cnt, lu); break;
+                case 0: light_rows<MULTI, 1>(P, q, cnt, lu); break;
+                case 1: light_rows<MULTI, 2>(P, q, cnt, lu); break;
+                case 2: light_rows<MULTI, 4>(P, q, cnt, lu); break;
+                case 3: light_rows<MULTI, 8>(P, q, cnt, lu); break;
+                case 4: light_rows<MULTI, 16>(P, q, cnt, lu); break;
+                case 5: light_rows<MULTI, 32>(P, q, cnt, lu); break;
+                default: light_rows<MULTI, 64>(P, q, cnt, lu); break;
             }
         }
         __syncthreads();
     }
 }
 
+template <bool MULTI>
 __global__ void __launch_bounds__(WG) k_heavy(Params P) {
     const Ctl *C = P.ctl;
     if (C->done) return;
     const int par = C->round & 1;
     const uint32_t total = C->hchunks[par];
-    for (uint32_t u = blockIdx.x; u < total; u += gridDim.x) heavy_chunk_candidates(P, par, u);
+    for (uint32_t u = blockIdx.x; u < total; u += gridDim.x) heavy_chunk_candidates<MULTI>(P, par, u);
 }
 
+// ------------------------------------------------------------------------
+// Queueing rows for the next round.
+// ------------------------------------------------------------------------
 // Add newly queued rows to their slots' pending counters: one atomic pair
 // per wave when every queuing lane belongs to the same slot (always the
 // case for a single bound vector), one per lane otherwise.
@@ -720,17 +745,14 @@ __device__ __forceinline__ void count_pending(const Params &P, bool first, int s
     }
 }
 
-// ------------------------------------------------------------------------
-// Queueing rows for the next round.
-// ------------------------------------------------------------------------
 // Append the (slot, row) tasks of the lanes with first == true to their bin
-// queues of parity par: one ballot per bin, then one atomic per non-empty bin
-// issued by lanes 0..NBIN-1 in parallel.  Reached by every lane of the wave.
+// queues of parity par: one ballot per bin, then one atomic per non-empty
+// bin issued by lanes 0..BIN_HEAVY-1 in parallel; heavy rows become chunk
+// records.  Reached by every lane of the wave.
 __device__ __forceinline__ void append_rows(const Params &P, int par, bool first, int s, int k,
                                             int bin, int64_t len) {
     if (!__any(first)) return;
     const int lane = __lane_id();
-    // Heavy rows: a range of chunk records (rare; one atomic per row).
     if (first && bin == BIN_HEAVY) {
         int nch = (int)((len + P.heavy_chunk - 1) / P.heavy_chunk);
         uint32_t cb = atomicAdd(&P.ctl->hchunks[par], (uint32_t)nch);
@@ -751,12 +773,14 @@ __device__ __forceinline__ void append_rows(const Params &P, int par, bool first
     if (lt) P.q[par][bin][mybase + lane_rank(mine)] = ((uint64_t)(uint32_t)s << 32) | (uint32_t)k;
 }
 
-// Queue, for the round of parity par, the rows of the column of the
-// variable held by each lane with want == true (at most one per lane).  The
-// column entries of the whole wave are walked 64 at a time, so a wave
-// needs ceil(sum of column lengths / 64) steps.  A row is queued once per
+// Queue, for the round of parity par, the rows of the column [c0, c0+len)
+// of the variable held by each lane with want == true (at most one per
+// lane; lanes may hold different slots and instances).  The column entries
+// of the whole wave are walked 64 at a time.  A row is queued once per
 // slot: the first lane to set its bit in the slot's row bitmap appends it.
-// Reached by every lane of the wave.
+// With count == false the slot counters are left alone and the wave totals
+// (rows, nonzeros) are returned instead.  Reached by every lane of the wave.
+template <bool MULTI>
 __device__ void enqueue_columns(const Params &P, int par, bool want, int s, long long c0,
                                 uint32_t len, bool count = true, uint32_t *rows_out = nullptr,
                                 unsigned long long *nnz_out = nullptr) {
@@ -795,15 +819,16 @@ __device__ void enqueue_columns(const Params &P, int par, bool want, int s, long
         int64_t rlen = 0;
         bool first = false;
         if (has) {
-            k = P.I.col_row[oc0 + (long long)(j - (oincl - olen))];
+            const DInst I = inst_of<MULTI>(P, os);
+            k = I.col_row[oc0 + (long long)(j - (oincl - olen))];
             uint32_t bit = 1u << (k & 31);
-            uint32_t *wp = &P.rflag[(size_t)os * P.nw_row + (k >> 5)];
+            uint32_t *wp = &P.rflag[(size_t)os * P.srw + (k >> 5)];
             // Independent loads issued together.  Rows shared by many changed
             // variables (dense rows) are mostly seen set already: the relaxed
             // load spares their atomics.
             uint32_t cur = __hip_atomic_load(wp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            bin = P.I.rbin[k];
-            int64_t rp0 = P.I.row_ptr[k], rp1 = P.I.row_ptr[k + 1];
+            bin = I.rbin[k];
+            int64_t rp0 = I.row_ptr[k], rp1 = I.row_ptr[k + 1];
             if ((cur & bit) == 0) first = (atomicOr(wp, bit) & bit) == 0;
             rlen = rp1 - rp0;
         }
@@ -822,15 +847,15 @@ __device__ void enqueue_columns(const Params &P, int par, bool want, int s, long
     if (nnz_out) *nnz_out = tot_nnz;
 }
 
-// Dirty tracking for probes: first change of var i in slot s.
+// Dirty tracking for jobs: first change of var i in slot s.
 __device__ __forceinline__ void mark_dirty(const Params &P, int s, int i) {
     uint32_t bit = 1u << (i & 31);
-    uint32_t old = atomicOr(&P.dirty[(size_t)s * P.nw_var + (i >> 5)], bit);
+    uint32_t old = atomicOr(&P.dirty[(size_t)s * P.snw + (i >> 5)], bit);
     uint32_t h = fhash(i);
     atomicOr(&P.filt[(size_t)s * FILT_WORDS + (h >> 5)], 1u << (h & 31));
     if ((old & bit) == 0) {
         int d = atomicAdd(&P.dcount[s], 1);
-        P.dlist[(size_t)s * P.I.n + d] = i;
+        P.dlist[(size_t)s * P.sn + d] = i;
     }
 }
 
@@ -886,7 +911,7 @@ __global__ void __launch_bounds__(WG) k_end(Params P) {
         }
     }
     if (P.touched) {
-        size_t words = (size_t)P.nslots * P.nw_var;
+        size_t words = (size_t)P.nslots * P.snw;
         for (size_t w = threadIdx.x; w < words; w += WG) P.touched[w] = 0u;
     }
     __syncthreads();
@@ -903,6 +928,7 @@ __global__ void __launch_bounds__(WG) k_end(Params P) {
 
 constexpr int APPLY_V = 16;  // changed variables per wave and step in k_apply
 
+template <bool MULTI>
 __global__ void __launch_bounds__(WG) k_apply(Params P) {
     Ctl *C = P.ctl;
     if (C->done) return;
@@ -925,18 +951,19 @@ __global__ void __launch_bounds__(WG) k_apply(Params P) {
             uint64_t ent = P.chg[e];
             s = (int)(ent >> 32);
             i = (int)(uint32_t)ent;
-            c0 = P.I.col_ptr[i];
-            clen = (uint32_t)(P.I.col_ptr[i + 1] - c0);
-            longlong2 *cp = &P.cand[(size_t)s * P.I.n + i];
+            const DInst I = inst_of<MULTI>(P, s);
+            c0 = I.col_ptr[i];
+            clen = (uint32_t)(I.col_ptr[i + 1] - c0);
+            longlong2 *cp = &P.cand[(size_t)s * P.sn + i];
             long long kl = cp->x, ku = cp->y;
             cp->x = dkey(-INF);
             cp->y = dkey(INF);
-            P.vflag[(size_t)s * P.nw_var + (i >> 5)] = 0u;  // whole word: every var in it is handled this round
+            P.vflag[(size_t)s * P.snw + (i >> 5)] = 0u;  // whole word: every var in it is handled this round
             SlotInfo &S = P.info[s];
             if (S.row_bad_count == 0) {
-                double2 *bp = &P.bnd[(size_t)s * P.I.n + i];
-                double2 b = bview(P, s)[i];
-                bool is_int = P.I.vtype[i] != 0;
+                double2 *bp = &P.bnd[(size_t)s * P.sn + i];
+                double2 b = bview(P, s, I.base)[i];
+                bool is_int = I.vtype[i] != 0;
                 double L = dunkey(kl), U = dunkey(ku);
                 double nl = b.x, nu = b.y;
                 bool ch = false;
@@ -949,32 +976,46 @@ __global__ void __launch_bounds__(WG) k_apply(Params P) {
                 if (ch) {
                     *bp = make_double2(nl, nu);
                     go = true;
-                    if (P.track_dirty) mark_dirty(P, s, i);
+                    if (P.overlay) mark_dirty(P, s, i);
                 }
             }
         }
         uint64_t wm = __ballot(go);
         if (wm && lane == __ffsll((long long)wm) - 1)
             atomicAdd(&C->stat_written, (unsigned long long)__popcll(wm));
-        enqueue_columns(P, npar, go, s, c0, clen);
+        enqueue_columns<MULTI>(P, npar, go, s, c0, clen);
     }
 }
 
 // ------------------------------------------------------------------------
-// Probing (the paper's Section 2.2): jobs p = 2t + v fix vars[t] to v.
-// Slots are retired and refilled at round boundaries.
+// Jobs (the paper's Section 2.2 probing, and serving requests).  A job is
+// either a probe (fix binary a at value b) or a fixing job (apply the bound
+// fixings [a, a+b) of the fix list and propagate).  Jobs are admitted in
+// order into free slots at round boundaries; their bounds are an overlay
+// on the instance's base.
 // ------------------------------------------------------------------------
-struct ProbeIO {
-    const int32_t *vars;     // [k]
-    const double2 *base;     // [n] base bounds
-    int8_t *status;          // [2k]
-    int32_t *rounds;         // [2k]
-    int64_t *nnz;            // [2k]
-    int64_t *stage_off;      // [2k] start of the probe's staged list
-    int64_t *stage_cnt;      // [2k] its length
-    int32_t *stage_var;      // [stage_cap] lists, ascending within a probe
+enum : int32_t { JOB_PROBE = 0, JOB_FIX = 1 };
+
+struct Job {
+    int32_t inst, kind, a, b;
+};
+
+struct JobIO {
+    const Job *jobs;         // [total]
+    const int32_t *fix_var;  // fixings of JOB_FIX jobs
+    const double2 *fix_box;
+    int8_t *status;          // [total]
+    int32_t *rounds;
+    int64_t *nnz;
+    int32_t *n_bad_rows;     // infeasibility evidence (may be null)
+    int32_t *bad_row;
+    int32_t *bad_var;
+    int64_t *stage_off;      // [total] start of the job's staged list
+    int64_t *stage_cnt;      // [total] its length
+    int32_t *stage_var;      // [stage_cap] lists, ascending within a job
     double *stage_lb, *stage_ub;
     int64_t stage_cap;
+    uint32_t *done_ring;     // finished job ids in completion order (may be null)
 };
 
 constexpr int SORT_MAX = 4096;  // lists up to this length are sorted in LDS
@@ -984,20 +1025,32 @@ struct RetireScratch {
     uint32_t wsum[WG];
     uint32_t total;
     long long off;
-    int32_t job, cnt, flag;
+    int32_t job, flag, badv;
+    uint32_t rows;
+    unsigned long long nnz;
 };
 
-// Write the job's outcome and reserve its staged list.
-__device__ void write_job(const Params &P, const ProbeIO &IO, int p, int status, int rounds,
-                          unsigned long long nnz, int cnt, RetireScratch &R) {
+// Write a job's outcome and reserve its staged list.
+__device__ void write_job(const Params &P, const JobIO &IO, int p, int status, int rounds,
+                          unsigned long long nnz, int nbad, int badrow, int badvar, int cnt,
+                          RetireScratch &R) {
     if (threadIdx.x == 0) {
         IO.status[p] = (int8_t)status;
         IO.rounds[p] = rounds;
         IO.nnz[p] = (int64_t)nnz;
+        if (IO.n_bad_rows) {
+            IO.n_bad_rows[p] = nbad;
+            IO.bad_row[p] = badrow;
+            IO.bad_var[p] = badvar;
+        }
         unsigned long long off = atomicAdd(&P.ctl->stage_count, (unsigned long long)cnt);
         IO.stage_off[p] = (int64_t)off;
         IO.stage_cnt[p] = cnt;
         R.off = (long long)off;
+        if (IO.done_ring) {
+            uint32_t d = atomicAdd(&P.ctl->done_jobs, 1u);
+            IO.done_ring[d] = (uint32_t)p;
+        }
     }
     __syncthreads();
 }
@@ -1005,15 +1058,16 @@ __device__ void write_job(const Params &P, const ProbeIO &IO, int p, int status,
 // Stage the dirty variables of slot s (with their bounds) in ascending order
 // at R.off: bitonic sort in LDS for short lists, an ordered scan of the
 // dirty bitmap for long ones.
-__device__ void stage_sorted(const Params &P, const ProbeIO &IO, int s, int cnt, RetireScratch &R) {
+__device__ void stage_sorted(const Params &P, const JobIO &IO, int s, const DInst &I, int cnt,
+                             RetireScratch &R) {
     const long long off = R.off;
     if (off + cnt > IO.stage_cap) return;  // counted only; the call reports the size
-    const BView bnd = bview(P, s);
+    const BView bnd = bview(P, s, I.base);
     if (cnt <= SORT_MAX) {
         int npow = 1;
         while (npow < cnt) npow <<= 1;
         for (int t = threadIdx.x; t < npow; t += WG)
-            R.key[t] = t < cnt ? P.dlist[(size_t)s * P.I.n + t] : 0x7fffffff;
+            R.key[t] = t < cnt ? P.dlist[(size_t)s * P.sn + t] : 0x7fffffff;
         __syncthreads();
         for (int size = 2; size <= npow; size <<= 1) {
             for (int stride = size >> 1; stride > 0; stride >>= 1) {
@@ -1040,11 +1094,12 @@ __device__ void stage_sorted(const Params &P, const ProbeIO &IO, int s, int cnt,
         }
         __syncthreads();
     } else {
-        const uint32_t *dw = P.dirty + (size_t)s * P.nw_var;
+        const uint32_t *dw = P.dirty + (size_t)s * P.snw;
+        const int nw = (I.n + 31) / 32;
         long long run = 0;
-        for (int w0 = 0; w0 < P.nw_var; w0 += WG) {
+        for (int w0 = 0; w0 < nw; w0 += WG) {
             int w = w0 + threadIdx.x;
-            uint32_t bits = w < P.nw_var ? dw[w] : 0u;
+            uint32_t bits = w < nw ? dw[w] : 0u;
             R.wsum[threadIdx.x] = (uint32_t)__popc(bits);
             __syncthreads();
             if (threadIdx.x == 0) {  // exclusive prefix of the popcounts
@@ -1074,24 +1129,136 @@ __device__ void stage_sorted(const Params &P, const ProbeIO &IO, int s, int cnt,
     }
 }
 
-// Restore the dirty variables of slot s to the base and clear its bitmap.
-__device__ void restore_slot(const Params &P, const ProbeIO &IO, int s, int cnt) {
-    uint32_t *dw = P.dirty + (size_t)s * P.nw_var;
+// Forget the dirty variables of slot s: it reads the base again.
+__device__ void restore_slot(const Params &P, int s, int cnt) {
+    uint32_t *dw = P.dirty + (size_t)s * P.snw;
     uint32_t *fw = P.filt + (size_t)s * FILT_WORDS;
     for (int t = threadIdx.x; t < cnt; t += WG) {
-        int i = P.dlist[(size_t)s * P.I.n + t];
-        // every set bit of these words belongs to this list: the slot
-        // reads the base again
+        int i = P.dlist[(size_t)s * P.sn + t];
+        // every set bit of these words belongs to this list
         dw[i >> 5] = 0u;
         fw[fhash(i) >> 5] = 0u;
     }
     __syncthreads();
     if (threadIdx.x == 0) P.dcount[s] = 0;
+    __syncthreads();
+}
+
+__device__ __forceinline__ int dcount_now(const Params &P, int s) {
+    return (int)__hip_atomic_load(&P.dcount[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Set up job p in the free slot s.  Returns true if the slot now runs it;
+// false if the job finished at admission (its results are written).
+template <bool MULTI>
+__device__ bool admit_job(const Params &P, const JobIO &IO, int s, int p, int par,
+                          RetireScratch &R) {
+    SlotInfo &S = P.info[s];
+    const Job J = IO.jobs[p];
+    DInst I;
+    if constexpr (MULTI) I = P.insts[J.inst];
+    else I = P.I;
+    if (J.kind == JOB_PROBE) {
+        const int j = J.a;
+        const double v = (double)J.b;
+        const double2 b = I.base[j];
+        if (v < b.x || v > b.y) {  // the value is outside the base box
+            write_job(P, IO, p, 1, 0, 0ull, 0, -1, j, 0, R);
+            return false;
+        }
+        if (b.x == v && b.y == v) {  // the base already fixes j at v
+            write_job(P, IO, p, 0, 0, 0ull, 0, -1, -1, 0, R);
+            return false;
+        }
+    }
+    if (threadIdx.x == 0) {
+        S.status = 0;
+        S.rounds = 0;
+        S.row_bad_min = NONE;
+        S.row_bad_count = 0;
+        S.var_bad_min = NONE;
+        S.pending_rows = 0;
+        S.pending_nnz = 0;
+        S.nnz = 0;
+        S.job = p;
+        S.retire = 0;
+        S.inst = J.inst;
+        R.badv = NONE;
+        R.rows = 0;
+        R.nnz = 0;
+    }
+    __syncthreads();
+    // Apply the job's bounds (each changed variable becomes dirty).
+    if (J.kind == JOB_PROBE) {
+        if (threadIdx.x == 0) {
+            P.bnd[(size_t)s * P.sn + J.a] = make_double2((double)J.b, (double)J.b);
+            mark_dirty(P, s, J.a);
+        }
+    } else {
+        for (int f = J.a + threadIdx.x; f < J.a + J.b; f += WG) {
+            const int i = IO.fix_var[f];
+            const double2 fb = IO.fix_box[f];
+            const double2 b = I.base[i];
+            double nl = canon0(fmax(b.x, fb.x)), nu = canon0(fmin(b.y, fb.y));
+            double slack = I.vtype[i] ? 0.0 : P.feastol;
+            if (nl > nu + slack) atomicMin(&R.badv, i);
+            if (nl != b.x || nu != b.y) {
+                P.bnd[(size_t)s * P.sn + i] = make_double2(nl, nu);
+                mark_dirty(P, s, i);
+            }
+        }
+    }
+    __syncthreads();
+    const int nd = dcount_now(P, s);
+    if (R.badv != NONE) {  // a crossed box before the first round
+        write_job(P, IO, p, 1, 0, 0ull, 0, -1, R.badv, 0, R);
+        restore_slot(P, s, nd);
+        return false;
+    }
+    // The first round holds the rows of the changed variables.
+    const int wave = threadIdx.x >> 6;
+    for (int d0 = wave * 64; d0 < nd; d0 += WG) {
+        int d = d0 + __lane_id();
+        bool want = d < nd;
+        long long c0 = 0;
+        uint32_t len = 0;
+        if (want) {
+            int i = P.dlist[(size_t)s * P.sn + d];
+            c0 = I.col_ptr[i];
+            len = (uint32_t)(I.col_ptr[i + 1] - c0);
+        }
+        uint32_t rows = 0;
+        unsigned long long nnz = 0;
+        enqueue_columns<MULTI>(P, par, want, s, c0, len, false, &rows, &nnz);
+        if (__lane_id() == 0) {
+            atomicAdd(&R.rows, rows);
+            atomicAdd(&R.nnz, nnz);
+        }
+    }
+    __syncthreads();
+    if (R.rows > 0) {
+        if (threadIdx.x == 0) {
+            S.rounds = 1;
+            S.nnz = R.nnz;
+            S.state = SLOT_ACTIVE;
+            atomicAdd(&P.ctl->stat_rows, (unsigned long long)R.rows);
+            atomicAdd(&P.ctl->stat_nnz, R.nnz);
+        }
+        __syncthreads();
+        return true;
+    }
+    // Changed variables in no row: nothing to propagate; the list is the
+    // changed variables themselves.
+    write_job(P, IO, p, 0, 0, 0ull, 0, -1, -1, nd, R);
+    stage_sorted(P, IO, s, I, nd, R);
+    restore_slot(P, s, nd);
+    return false;
 }
 
 // One workgroup per slot: write the results of a slot that finished at the
-// last round end, restore it, then admit the next probes into free slots.
-__global__ void __launch_bounds__(WG) k_retire(Params P, ProbeIO IO) {
+// last round end, restore it, then admit the next jobs into free slots.
+template <bool MULTI>
+__global__ void __launch_bounds__(WG) k_retire(Params P, JobIO IO) {
     __shared__ RetireScratch R;
     Ctl *C = P.ctl;
     const int par = C->round & 1;
@@ -1100,11 +1267,23 @@ __global__ void __launch_bounds__(WG) k_retire(Params P, ProbeIO IO) {
         if (S.retire) {
             const int p = S.job;
             const int status = S.status;
-            const int cnt = status == 1 ? 0 : P.dcount[s];
-            const int dcnt = P.dcount[s];
-            write_job(P, IO, p, status, S.rounds, S.nnz, cnt, R);
-            if (cnt > 0) stage_sorted(P, IO, s, cnt, R);
-            restore_slot(P, IO, s, dcnt);
+            const int dcnt = dcount_now(P, s);
+            const int cnt = status == 1 ? 0 : dcnt;
+            DInst I;
+            if constexpr (MULTI) I = P.insts[S.inst];
+            else I = P.I;
+            int nbad = 0, brow = -1, bvar = -1;
+            if (status == 1) {
+                if (S.row_bad_count > 0) {
+                    nbad = S.row_bad_count;
+                    brow = S.row_bad_min;
+                } else {
+                    bvar = S.var_bad_min;
+                }
+            }
+            write_job(P, IO, p, status, S.rounds, S.nnz, nbad, brow, bvar, cnt, R);
+            if (cnt > 0) stage_sorted(P, IO, s, I, cnt, R);
+            restore_slot(P, s, dcnt);
             if (threadIdx.x == 0) S.retire = 0;
             __syncthreads();
         }
@@ -1116,70 +1295,14 @@ __global__ void __launch_bounds__(WG) k_retire(Params P, ProbeIO IO) {
             const int p = R.job;
             __syncthreads();
             if ((uint32_t)p >= C->total_jobs) break;
-            const int j = IO.vars[p >> 1];
-            const double v = (double)(p & 1);
-            const double2 b = IO.base[j];
-            if (v < b.x || v > b.y) {  // the value is outside the base box
-                write_job(P, IO, p, 1, 0, 0ull, 0, R);
-                continue;
-            }
-            if (b.x == v && b.y == v) {  // the base already fixes j at v
-                write_job(P, IO, p, 0, 0, 0ull, 0, R);
-                continue;
-            }
-            if (threadIdx.x == 0) {
-                P.bnd[(size_t)s * P.I.n + j] = make_double2(v, v);
-                P.dirty[(size_t)s * P.nw_var + (j >> 5)] = 1u << (j & 31);
-                P.filt[(size_t)s * FILT_WORDS + (fhash(j) >> 5)] = 1u << (fhash(j) & 31);
-                P.dlist[(size_t)s * P.I.n] = j;
-                P.dcount[s] = 1;
-                S.status = 0;
-                S.rounds = 0;
-                S.row_bad_min = NONE;
-                S.row_bad_count = 0;
-                S.var_bad_min = NONE;
-                S.pending_rows = 0;
-                S.pending_nnz = 0;
-                S.nnz = 0;
-                S.job = p;
-                S.retire = 0;
-            }
-            // The first round holds the rows of column j (one wave queues them).
-            if (threadIdx.x < 64) {
-                long long c0 = P.I.col_ptr[j];
-                uint32_t len = (uint32_t)(P.I.col_ptr[j + 1] - c0);
-                uint32_t rows = 0;
-                unsigned long long nnz = 0;
-                enqueue_columns(P, par, threadIdx.x == 0, s, c0, len, false, &rows, &nnz);
-                if (threadIdx.x == 0) {
-                    R.flag = rows > 0 ? 1 : 0;
-                    if (rows > 0) {
-                        S.rounds = 1;
-                        S.nnz = nnz;
-                        S.state = SLOT_ACTIVE;
-                        atomicAdd(&C->stat_rows, (unsigned long long)rows);
-                        atomicAdd(&C->stat_nnz, nnz);
-                    }
-                }
-            }
-            __syncthreads();
-            if (R.flag) break;
-            // Variable in no row: nothing to propagate; its list is itself.
-            write_job(P, IO, p, 0, 0, 0ull, 1, R);
-            if (threadIdx.x == 0 && R.off + 1 <= IO.stage_cap) {
-                IO.stage_var[R.off] = j;
-                IO.stage_lb[R.off] = v;
-                IO.stage_ub[R.off] = v;
-            }
-            restore_slot(P, IO, s, 1);
-            __syncthreads();
+            if (admit_job<MULTI>(P, IO, s, p, par, R)) break;
         }
         __syncthreads();
     }
 }
 
-// off[p+1] = off[p] + count[p] over 2k probes (one workgroup).
-__global__ void __launch_bounds__(WG) k_probe_offsets(const int64_t *cnt, int64_t *off, int64_t np) {
+// off[p+1] = off[p] + count[p] over np jobs (one workgroup).
+__global__ void __launch_bounds__(WG) k_job_offsets(const int64_t *cnt, int64_t *off, int64_t np) {
     __shared__ long long part[WG];
     __shared__ long long carry;
     if (threadIdx.x == 0) {
@@ -1205,9 +1328,9 @@ __global__ void __launch_bounds__(WG) k_probe_offsets(const int64_t *cnt, int64_
     }
 }
 
-// Copy every probe's staged list to its place in the caller's arrays.
-__global__ void k_probe_gather(const ProbeIO IO, const int64_t *off, int64_t np, int32_t *ovar,
-                               double *olb, double *oub) {
+// Copy every job's staged list to its place in the caller's arrays.
+__global__ void k_job_gather(const JobIO IO, const int64_t *off, int64_t np, int32_t *ovar,
+                             double *olb, double *oub) {
     for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
         int64_t src = IO.stage_off[p], dst = off[p], c = IO.stage_cnt[p];
         for (int64_t t = threadIdx.x; t < c; t += blockDim.x) {
@@ -1215,6 +1338,18 @@ __global__ void k_probe_gather(const ProbeIO IO, const int64_t *off, int64_t np,
             olb[dst + t] = IO.stage_lb[src + t];
             oub[dst + t] = IO.stage_ub[src + t];
         }
+    }
+}
+
+// Probe jobs 2t + v: binary vars[t] at value v.
+__global__ void k_make_probe_jobs(const int32_t *vars, int32_t k, Job *jobs) {
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < 2 * k; p += gridDim.x * blockDim.x) {
+        Job J;
+        J.inst = 0;
+        J.kind = JOB_PROBE;
+        J.a = vars[p >> 1];
+        J.b = p & 1;
+        jobs[p] = J;
     }
 }
 

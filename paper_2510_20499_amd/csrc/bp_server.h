@@ -1,0 +1,509 @@
+// bp_server.h -- continuous-batching server (part of bp_engine.hip's
+// translation unit; see include/bp.h for the C ABI).
+//
+// All requests become jobs in one device job list: a probe request of k
+// binaries is 2k probe jobs, a propagate request is one fixing job.  One
+// engine whose slots may hold any of the server's instances runs them: each
+// round's kernels process the tasks of every busy slot, and k_retire
+// writes finished jobs' results, restores their slots and admits the next
+// jobs.  The host appends newly submitted requests between graph launches
+// and collects finished jobs from a completion ring.
+#pragma once
+#include <chrono>
+#include <deque>
+#include <unordered_map>
+
+struct JobOut {
+    int32_t job;
+    int32_t status, rounds, n_bad_rows, bad_row, bad_var;
+    int64_t nnz, stage_off, stage_cnt;
+};
+
+// Results of the finished jobs ring[r0 .. r1) into a compact array.
+__global__ void k_collect(const JobIO IO, const uint32_t *ring, uint32_t r0, uint32_t r1, JobOut *out) {
+    for (uint32_t t = r0 + blockIdx.x * blockDim.x + threadIdx.x; t < r1; t += gridDim.x * blockDim.x) {
+        uint32_t p = ring[t];
+        JobOut o;
+        o.job = (int32_t)p;
+        o.status = IO.status[p];
+        o.rounds = IO.rounds[p];
+        o.n_bad_rows = IO.n_bad_rows[p];
+        o.bad_row = IO.bad_row[p];
+        o.bad_var = IO.bad_var[p];
+        o.nnz = IO.nnz[p];
+        o.stage_off = IO.stage_off[p];
+        o.stage_cnt = IO.stage_cnt[p];
+        out[t - r0] = o;
+    }
+}
+
+// Done before the next round when no slot is busy and no job waits.
+__global__ void k_jobs_done_check(Params P) {
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    for (int j = threadIdx.x; j < P.nslots; j += blockDim.x)
+        if (P.info[j].state != SLOT_FREE) atomicOr(&any, 1);
+    __syncthreads();
+    if (threadIdx.x == 0)
+        P.ctl->done = (!any && P.ctl->next_job >= P.ctl->total_jobs) ? 1u : 0u;
+}
+
+struct ServerReq {
+    int64_t id = 0;
+    int32_t inst = 0, kind = 0, count = 0, njobs = 0;
+    std::vector<int32_t> vars;
+    std::vector<double> lb, ub;
+    int32_t remaining = 0;
+    bool on_device = false, done = false;
+    double submit_us = 0, done_us = 0;
+    std::vector<JobOut> out;              // per job
+    std::vector<std::vector<int32_t>> lvar; // per job implied lists
+    std::vector<std::vector<double>> llb, lub;
+};
+
+struct bp_server {
+    std::vector<bp_instance *> insts;
+    bp_options opt;
+    int32_t heavy_chunk = 1024;
+    hipStream_t st = nullptr;
+    std::unique_ptr<Engine> eng;
+    DevBuf dinst;
+    int32_t slots = 0;
+    int64_t bytes_per_slot = 0;
+    // device job storage
+    DevBuf jobs, fix_var, fix_box, r_status, r_rounds, r_nnz, r_nbad, r_brow, r_bvar, r_soff, r_scnt;
+    DevBuf stage_var, stage_lb, stage_ub, ring, collect;
+    int64_t cap_jobs = 0, cap_fix = 0, cap_stage = 0;
+    int64_t njobs_dev = 0, nfix_dev = 0;
+    uint32_t ring_seen = 0;
+    std::vector<int64_t> job_req;   // device job -> request id
+    std::vector<int32_t> job_local; // device job -> index within its request
+    // host side
+    std::deque<int64_t> pending;
+    std::unordered_map<int64_t, ServerReq> reqs;
+    std::deque<int64_t> completed;
+    int64_t next_id = 1;
+    int64_t unfinished = 0;
+    std::vector<std::vector<uint8_t>> vtype;   // host copies for validation
+    std::vector<std::vector<double2>> base;
+    std::chrono::steady_clock::time_point t0;
+    Params P;
+    JobIO IO;
+    hipGraphExec_t graph = nullptr;
+    int graph_rounds = 0;
+    ~bp_server() {
+        if (graph) (void)hipGraphExecDestroy(graph);
+    }
+    double now_us() const {
+        return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+// Device bytes one slot of shape `sh` needs (the engine's per-slot arrays).
+static int64_t slot_bytes(const Shape &sh) {
+    int64_t n = std::max<int64_t>(sh.sn, 1), m = std::max<int64_t>(sh.sm, 1);
+    int64_t nw = (n + 31) / 32, mw = (m + 31) / 32;
+    int64_t b = 16 * n + 16 * n + 8 * n + 4 * n;   // bounds, candidates, changed list, dirty list
+    b += 4 * nw * 2 + 4 * mw;                      // var, dirty and row bitmaps
+    b += 4 * FILT_WORDS + (int64_t)sizeof(SlotInfo) + 4;
+    for (int q = 0; q < BIN_HEAVY; ++q) b += 2 * 8 * sh.bin_cap[q];
+    b += 2 * 16 * sh.heavy_chunks + 64 * sh.heavy_chunks;
+    return b;
+}
+
+extern "C" int bp_server_create(bp_instance *const *instances, int32_t count, const bp_options *opt,
+                                int64_t budget_bytes, void *stream, bp_server **out) {
+    g_err.clear();
+    if (!instances || count <= 0 || !out || budget_bytes <= 0)
+        return fail(BP_EINVAL, "bp_server_create: bad argument");
+    *out = nullptr;
+    std::unique_ptr<bp_server> sv(new bp_server());
+    sv->st = as_stream(stream);
+    sv->opt = opt ? *opt : instances[0]->opt;
+    if (int rc = validate_options(sv->opt)) return rc;
+    if (sv->opt.rounds_per_launch <= 0) sv->opt.rounds_per_launch = 16;
+    Shape sh;
+    for (int32_t t = 0; t < count; ++t) {
+        bp_instance *h = instances[t];
+        if (!h) return fail(BP_EINVAL, "bp_server_create: null instance");
+        if (!h->have_base) return fail(BP_ESTATE, "instance " + std::to_string(t) + " has no base");
+        if (t == 0) sv->heavy_chunk = h->heavy_chunk;
+        else if (h->heavy_chunk != sv->heavy_chunk)
+            return fail(BP_EINVAL, "instances must share the heavy chunk size");
+        Shape s1 = shape_of(h);
+        sh.sn = std::max(sh.sn, s1.sn);
+        sh.sm = std::max(sh.sm, s1.sm);
+        for (int b = 0; b < NBIN; ++b) sh.bin_cap[b] = std::max(sh.bin_cap[b], s1.bin_cap[b]);
+        sh.heavy_chunks = std::max(sh.heavy_chunks, s1.heavy_chunks);
+        sv->insts.push_back(h);
+    }
+    sv->bytes_per_slot = slot_bytes(sh);
+    int64_t fit = budget_bytes / sv->bytes_per_slot;
+    sv->slots = (int32_t)std::min<int64_t>(fit, std::max(1, sv->opt.probe_slots));
+    if (sv->slots < 1) return fail(BP_ENOMEM, "budget smaller than one slot (" +
+                                                  std::to_string(sv->bytes_per_slot) + " bytes)");
+    hipStream_t st = sv->st;
+    if (int rc = engine_alloc(sv->eng, sh, sv->slots, true, false, st)) return rc;
+    // instance table and host copies for request validation
+    std::vector<DInst> tab;
+    for (bp_instance *h : sv->insts) {
+        tab.push_back(dinst_of(h));
+        std::vector<uint8_t> vt(h->n);
+        std::vector<double2> bs(h->n);
+        if (h->n) {
+            HIPTRY(hipMemcpyAsync(vt.data(), h->vtype.p, h->n, hipMemcpyDeviceToHost, st));
+            HIPTRY(hipMemcpyAsync(bs.data(), h->base.p, (size_t)h->n * 16, hipMemcpyDeviceToHost, st));
+        }
+        sv->vtype.push_back(std::move(vt));
+        sv->base.push_back(std::move(bs));
+    }
+    int64_t dummy = 0;
+    if (int rc = sv->dinst.alloc(tab.size() * sizeof(DInst), dummy)) return rc;
+    HIPTRY(hipMemcpyAsync(sv->dinst.p, tab.data(), tab.size() * sizeof(DInst), hipMemcpyHostToDevice, st));
+    // job storage
+    sv->cap_jobs = 1 << 21;
+    sv->cap_fix = 1 << 24;
+    sv->cap_stage = 1 << 25;
+    const int64_t J = sv->cap_jobs;
+    int rc;
+    if ((rc = sv->jobs.alloc(J * sizeof(Job), dummy))) return rc;
+    if ((rc = sv->fix_var.alloc(sv->cap_fix * 4, dummy))) return rc;
+    if ((rc = sv->fix_box.alloc(sv->cap_fix * 16, dummy))) return rc;
+    if ((rc = sv->r_status.alloc(J, dummy))) return rc;
+    if ((rc = sv->r_rounds.alloc(J * 4, dummy))) return rc;
+    if ((rc = sv->r_nnz.alloc(J * 8, dummy))) return rc;
+    if ((rc = sv->r_nbad.alloc(J * 4, dummy))) return rc;
+    if ((rc = sv->r_brow.alloc(J * 4, dummy))) return rc;
+    if ((rc = sv->r_bvar.alloc(J * 4, dummy))) return rc;
+    if ((rc = sv->r_soff.alloc(J * 8, dummy))) return rc;
+    if ((rc = sv->r_scnt.alloc(J * 8, dummy))) return rc;
+    if ((rc = sv->stage_var.alloc(sv->cap_stage * 4, dummy))) return rc;
+    if ((rc = sv->stage_lb.alloc(sv->cap_stage * 8, dummy))) return rc;
+    if ((rc = sv->stage_ub.alloc(sv->cap_stage * 8, dummy))) return rc;
+    if ((rc = sv->ring.alloc(J * 4, dummy))) return rc;
+    if ((rc = sv->collect.alloc(J * sizeof(JobOut), dummy))) return rc;
+    JobIO &IO = sv->IO;
+    memset(&IO, 0, sizeof(IO));
+    IO.jobs = sv->jobs.as<Job>();
+    IO.fix_var = sv->fix_var.as<int32_t>();
+    IO.fix_box = sv->fix_box.as<double2>();
+    IO.status = sv->r_status.as<int8_t>();
+    IO.rounds = sv->r_rounds.as<int32_t>();
+    IO.nnz = sv->r_nnz.as<int64_t>();
+    IO.n_bad_rows = sv->r_nbad.as<int32_t>();
+    IO.bad_row = sv->r_brow.as<int32_t>();
+    IO.bad_var = sv->r_bvar.as<int32_t>();
+    IO.stage_off = sv->r_soff.as<int64_t>();
+    IO.stage_cnt = sv->r_scnt.as<int64_t>();
+    IO.stage_var = sv->stage_var.as<int32_t>();
+    IO.stage_lb = sv->stage_lb.as<double>();
+    IO.stage_ub = sv->stage_ub.as<double>();
+    IO.stage_cap = sv->cap_stage;
+    IO.done_ring = sv->ring.as<uint32_t>();
+    Params P = engine_params(*sv->eng, sv->opt, sv->heavy_chunk, sv->slots);
+    P.I = tab[0];
+    P.multi = 1;
+    P.insts = sv->dinst.as<DInst>();
+    P.overlay = 1;
+    sv->P = P;
+    Ctl c;
+    memset(&c, 0, sizeof(c));
+    c.max_rounds = (uint32_t)sv->opt.max_rounds;
+    c.nslots = (uint32_t)sv->slots;
+    c.done = 1;
+    HIPTRY(hipMemcpyAsync(P.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, st));
+    k_reset_slots<<<grid_for(sv->slots), 256, 0, st>>>(P.info, sv->slots, 0, SLOT_FREE);
+    HIPTRY(hipGetLastError());
+    HIPTRY(hipStreamSynchronize(st));
+    sv->t0 = std::chrono::steady_clock::now();
+    *out = sv.release();
+    return BP_OK;
+}
+
+extern "C" void bp_server_destroy(bp_server *sv) { delete sv; }
+
+extern "C" int bp_server_info(const bp_server *sv, int32_t *slots, int64_t *bytes_per_slot) {
+    if (!sv) return fail(BP_EINVAL, "bp_server_info: null server");
+    if (slots) *slots = sv->slots;
+    if (bytes_per_slot) *bytes_per_slot = sv->bytes_per_slot;
+    return BP_OK;
+}
+
+extern "C" int bp_server_submit(bp_server *sv, const bp_request *req, int64_t *id) {
+    g_err.clear();
+    if (!sv || !req || !id) return fail(BP_EINVAL, "bp_server_submit: null argument");
+    if (req->instance < 0 || req->instance >= (int32_t)sv->insts.size())
+        return fail(BP_EINVAL, "bad instance index");
+    if (req->kind != BP_REQ_PROBE && req->kind != BP_REQ_PROPAGATE) return fail(BP_EINVAL, "bad kind");
+    if (req->count < 0 || (req->count > 0 && !req->vars)) return fail(BP_EINVAL, "bad variable list");
+    if (req->kind == BP_REQ_PROPAGATE && req->count > 0 && (!req->lb || !req->ub))
+        return fail(BP_EINVAL, "propagate request without bounds");
+    const bp_instance *h = sv->insts[req->instance];
+    const int64_t njobs = req->kind == BP_REQ_PROBE ? 2 * (int64_t)req->count : 1;
+    if (njobs > sv->cap_jobs || (req->kind == BP_REQ_PROPAGATE && req->count > sv->cap_fix))
+        return fail(BP_EINVAL, "request larger than the server's job storage");
+    std::vector<int32_t> seen;
+    seen.assign(req->vars, req->vars + req->count);
+    std::sort(seen.begin(), seen.end());
+    for (size_t t = 0; t < seen.size(); ++t) {
+        if (seen[t] < 0 || seen[t] >= h->n) return fail(BP_EINVAL, "variable out of range");
+        if (t && seen[t] == seen[t - 1]) return fail(BP_EINVAL, "repeated variable in a request");
+    }
+    if (req->kind == BP_REQ_PROBE) {
+        for (int32_t t = 0; t < req->count; ++t) {
+            int32_t j = req->vars[t];
+            const double2 b = sv->base[req->instance][j];
+            if (!sv->vtype[req->instance][j] || b.x < 0.0 || b.y > 1.0)
+                return fail(BP_EINVAL, "probe variable is not a binary of the base");
+        }
+    } else {
+        for (int32_t t = 0; t < req->count; ++t)
+            if (std::isnan(req->lb[t]) || std::isnan(req->ub[t])) return fail(BP_EINVAL, "NaN bound");
+    }
+    ServerReq R;
+    R.id = sv->next_id++;
+    R.inst = req->instance;
+    R.kind = req->kind;
+    R.count = req->count;
+    R.njobs = (int32_t)njobs;
+    R.vars.assign(req->vars, req->vars + req->count);
+    if (req->kind == BP_REQ_PROPAGATE) {
+        R.lb.assign(req->lb, req->lb + req->count);
+        R.ub.assign(req->ub, req->ub + req->count);
+    }
+    R.remaining = R.njobs;
+    R.submit_us = sv->now_us();
+    R.out.resize(R.njobs);
+    R.lvar.resize(R.njobs);
+    R.llb.resize(R.njobs);
+    R.lub.resize(R.njobs);
+    *id = R.id;
+    if (R.njobs == 0) {  // nothing to run: finished at once
+        R.done = true;
+        R.done_us = R.submit_us;
+        sv->completed.push_back(R.id);
+        sv->reqs.emplace(R.id, std::move(R));
+        return BP_OK;
+    }
+    sv->pending.push_back(R.id);
+    sv->reqs.emplace(R.id, std::move(R));
+    sv->unfinished += 1;
+    return BP_OK;
+}
+
+// Copy queued requests into the device job list while it has room.
+static int server_append(bp_server *sv) {
+    hipStream_t st = sv->st;
+    // The job list is rewound whenever every job on it has finished.
+    if (sv->njobs_dev > 0 && sv->ring_seen == (uint32_t)sv->njobs_dev && !sv->pending.empty()) {
+        sv->njobs_dev = 0;
+        sv->nfix_dev = 0;
+        sv->ring_seen = 0;
+        sv->job_req.clear();
+        sv->job_local.clear();
+        uint32_t zeros[4] = {0, 0, 0, 0};
+        Ctl *C = sv->P.ctl;
+        HIPTRY(hipMemcpyAsync(&C->next_job, zeros, 12, hipMemcpyHostToDevice, st));  // next, total, done_jobs
+        unsigned long long z = 0;
+        HIPTRY(hipMemcpyAsync(&C->stage_count, &z, 8, hipMemcpyHostToDevice, st));
+    }
+    std::vector<Job> nj;
+    std::vector<int32_t> fv;
+    std::vector<double2> fb;
+    while (!sv->pending.empty()) {
+        ServerReq &R = sv->reqs[sv->pending.front()];
+        int64_t nfix = R.kind == BP_REQ_PROPAGATE ? R.count : 0;
+        if (sv->njobs_dev + (int64_t)nj.size() + R.njobs > sv->cap_jobs) break;
+        if (sv->nfix_dev + (int64_t)fv.size() + nfix > sv->cap_fix) break;
+        for (int32_t j = 0; j < R.njobs; ++j) {
+            Job J;
+            J.inst = R.inst;
+            if (R.kind == BP_REQ_PROBE) {
+                J.kind = JOB_PROBE;
+                J.a = R.vars[j >> 1];
+                J.b = j & 1;
+            } else {
+                J.kind = JOB_FIX;
+                J.a = (int32_t)(sv->nfix_dev + (int64_t)fv.size());
+                J.b = R.count;
+                for (int32_t t = 0; t < R.count; ++t) {
+                    fv.push_back(R.vars[t]);
+                    fb.push_back(make_double2(R.lb[t], R.ub[t]));
+                }
+            }
+            nj.push_back(J);
+            sv->job_req.push_back(R.id);
+            sv->job_local.push_back(j);
+        }
+        R.on_device = true;
+        sv->pending.pop_front();
+    }
+    if (nj.empty()) return 0;
+    HIPTRY(hipMemcpyAsync(sv->jobs.as<Job>() + sv->njobs_dev, nj.data(), nj.size() * sizeof(Job),
+                          hipMemcpyHostToDevice, st));
+    if (!fv.empty()) {
+        HIPTRY(hipMemcpyAsync(sv->fix_var.as<int32_t>() + sv->nfix_dev, fv.data(), fv.size() * 4,
+                              hipMemcpyHostToDevice, st));
+        HIPTRY(hipMemcpyAsync(sv->fix_box.as<double2>() + sv->nfix_dev, fb.data(), fb.size() * 16,
+                              hipMemcpyHostToDevice, st));
+    }
+    sv->njobs_dev += (int64_t)nj.size();
+    sv->nfix_dev += (int64_t)fv.size();
+    uint32_t tot = (uint32_t)sv->njobs_dev;
+    HIPTRY(hipMemcpyAsync(&sv->P.ctl->total_jobs, &tot, 4, hipMemcpyHostToDevice, st));
+    // Admit right away, then recompute the done flag.
+    k_retire<true><<<std::min(sv->slots, 4096), WG, 0, st>>>(sv->P, sv->IO);
+    k_jobs_done_check<<<1, 256, 0, st>>>(sv->P);
+    HIPTRY(hipGetLastError());
+    return 0;
+}
+
+// Gather finished jobs from the completion ring and finish requests.
+static int server_collect(bp_server *sv) {
+    hipStream_t st = sv->st;
+    Ctl hc;
+    HIPTRY(hipMemcpyAsync(&hc, sv->P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+    const uint32_t r0 = sv->ring_seen, r1 = hc.done_jobs;
+    if (r1 == r0) return 0;
+    if (hc.stage_count > (unsigned long long)sv->cap_stage)
+        return fail(BP_ECAPACITY, "server implication storage exceeded");
+    const int64_t nr = r1 - r0;
+    k_collect<<<grid_for(nr), 256, 0, st>>>(sv->IO, sv->ring.as<uint32_t>(), r0, r1, sv->collect.as<JobOut>());
+    HIPTRY(hipGetLastError());
+    std::vector<JobOut> got(nr);
+    HIPTRY(hipMemcpyAsync(got.data(), sv->collect.p, nr * sizeof(JobOut), hipMemcpyDeviceToHost, st));
+    // their lists form one contiguous range of the stage
+    int64_t s0 = INT64_MAX, s1 = 0;
+    HIPTRY(hipStreamSynchronize(st));
+    for (const JobOut &o : got) {
+        if (o.stage_cnt > 0) {
+            s0 = std::min<int64_t>(s0, o.stage_off);
+            s1 = std::max<int64_t>(s1, o.stage_off + o.stage_cnt);
+        }
+    }
+    std::vector<int32_t> sv_var;
+    std::vector<double> sv_lb, sv_ub;
+    if (s1 > s0) {
+        int64_t c = s1 - s0;
+        sv_var.resize(c);
+        sv_lb.resize(c);
+        sv_ub.resize(c);
+        HIPTRY(hipMemcpyAsync(sv_var.data(), sv->stage_var.as<int32_t>() + s0, c * 4, hipMemcpyDeviceToHost, st));
+        HIPTRY(hipMemcpyAsync(sv_lb.data(), sv->stage_lb.as<double>() + s0, c * 8, hipMemcpyDeviceToHost, st));
+        HIPTRY(hipMemcpyAsync(sv_ub.data(), sv->stage_ub.as<double>() + s0, c * 8, hipMemcpyDeviceToHost, st));
+        HIPTRY(hipStreamSynchronize(st));
+    }
+    const double t = sv->now_us();
+    for (const JobOut &o : got) {
+        ServerReq &R = sv->reqs[sv->job_req[o.job]];
+        int32_t j = sv->job_local[o.job];
+        R.out[j] = o;
+        if (o.stage_cnt > 0) {
+            int64_t a = o.stage_off - s0;
+            R.lvar[j].assign(sv_var.begin() + a, sv_var.begin() + a + o.stage_cnt);
+            R.llb[j].assign(sv_lb.begin() + a, sv_lb.begin() + a + o.stage_cnt);
+            R.lub[j].assign(sv_ub.begin() + a, sv_ub.begin() + a + o.stage_cnt);
+        }
+        if (--R.remaining == 0) {
+            R.done = true;
+            R.done_us = t;
+            sv->completed.push_back(R.id);
+            sv->unfinished -= 1;
+        }
+    }
+    sv->ring_seen = r1;
+    return 0;
+}
+
+extern "C" int bp_server_run(bp_server *sv, int32_t rounds, int32_t *busy) {
+    g_err.clear();
+    if (!sv || rounds < 0) return fail(BP_EINVAL, "bp_server_run: bad argument");
+    hipStream_t st = sv->st;
+    if (int rc = server_append(sv)) return rc;
+    const int K = std::max(1, (int)sv->opt.rounds_per_launch);
+    if (!sv->graph || sv->graph_rounds != K) {
+        if (sv->graph) (void)hipGraphExecDestroy(sv->graph);
+        sv->graph = nullptr;
+        hipStream_t cs;
+        HIPTRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        HIPTRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        for (int r = 0; r < K; ++r) {
+            k_rows<true><<<GRID_ROWS, WG, 0, cs>>>(sv->P);
+            k_heavy<true><<<GRID_HEAVY, WG, 0, cs>>>(sv->P);
+            k_apply<true><<<GRID_APPLY, WG, 0, cs>>>(sv->P);
+            k_end<<<1, WG, 0, cs>>>(sv->P);
+            k_retire<true><<<std::min(sv->slots, 4096), WG, 0, cs>>>(sv->P, sv->IO);
+        }
+        hipGraph_t g;
+        HIPTRY(hipStreamEndCapture(cs, &g));
+        hipError_t e = hipGraphInstantiate(&sv->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        (void)hipStreamDestroy(cs);
+        HIPTRY(e);
+        sv->graph_rounds = K;
+    }
+    for (int32_t r = 0; r < rounds; r += K) {
+        HIPTRY(hipGraphLaunch(sv->graph, st));
+        if (int rc = server_collect(sv)) return rc;
+        if (int rc = server_append(sv)) return rc;
+    }
+    if (rounds == 0)
+        if (int rc = server_collect(sv)) return rc;
+    if (busy) *busy = (int32_t)sv->unfinished;
+    return BP_OK;
+}
+
+extern "C" int bp_server_poll(bp_server *sv, bp_completion *out, int32_t max, int32_t *n) {
+    if (!sv || !n || max < 0 || (max > 0 && !out)) return fail(BP_EINVAL, "bp_server_poll: bad argument");
+    int32_t k = 0;
+    while (k < max && !sv->completed.empty()) {
+        const ServerReq &R = sv->reqs[sv->completed.front()];
+        bp_completion &c = out[k++];
+        c.id = R.id;
+        c.instance = R.inst;
+        c.kind = R.kind;
+        c.jobs = R.njobs;
+        c.reserved = 0;
+        c.submit_us = R.submit_us;
+        c.done_us = R.done_us;
+        sv->completed.pop_front();
+    }
+    *n = k;
+    return BP_OK;
+}
+
+extern "C" int bp_server_results(bp_server *sv, int64_t id, int8_t *status, int32_t *rounds,
+                                 int64_t *nnz, int32_t *n_bad_rows, int32_t *bad_row,
+                                 int32_t *bad_var, int64_t *off, int32_t *var, double *lb,
+                                 double *ub, int64_t cap, int64_t *required) {
+    g_err.clear();
+    if (!sv) return fail(BP_EINVAL, "bp_server_results: null server");
+    auto it = sv->reqs.find(id);
+    if (it == sv->reqs.end()) return fail(BP_EINVAL, "unknown request id");
+    const ServerReq &R = it->second;
+    if (!R.done) return fail(BP_ESTATE, "request has not finished");
+    int64_t tot = 0;
+    for (int32_t j = 0; j < R.njobs; ++j) tot += (int64_t)R.lvar[j].size();
+    if (required) *required = tot;
+    if (tot > cap) return fail(BP_ECAPACITY, "lists need " + std::to_string(tot) + " entries");
+    int64_t pos = 0;
+    for (int32_t j = 0; j < R.njobs; ++j) {
+        const JobOut &o = R.out[j];
+        if (status) status[j] = (int8_t)o.status;
+        if (rounds) rounds[j] = o.rounds;
+        if (nnz) nnz[j] = o.nnz;
+        if (n_bad_rows) n_bad_rows[j] = o.n_bad_rows;
+        if (bad_row) bad_row[j] = o.bad_row;
+        if (bad_var) bad_var[j] = o.bad_var;
+        if (off) off[j] = pos;
+        for (size_t t = 0; t < R.lvar[j].size(); ++t, ++pos) {
+            if (var) var[pos] = R.lvar[j][t];
+            if (lb) lb[pos] = R.llb[j][t];
+            if (ub) ub[pos] = R.lub[j][t];
+        }
+    }
+    if (off) off[R.njobs] = pos;
+    return BP_OK;
+}
