@@ -24,6 +24,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E datasheet peak
 
 
+def log(msg):
+    """Progress line on stderr (the JSON result goes to stdout)."""
+    print(msg, file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -38,14 +43,22 @@ def main():
     ap.add_argument("--probe-vars", type=int, default=4096)
     ap.add_argument("--probe-plain", type=int, default=256,
                     help="binaries probed one call at a time for the plain baseline")
+    ap.add_argument("--serving", action="store_true",
+                    help="also run the serving measurement (64-instance mix, Poisson requests)")
+    ap.add_argument("--only-serving", action="store_true")
+    ap.add_argument("--serve-instances", type=int, default=64)
+    ap.add_argument("--serve-mmax", type=float, default=1e6)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-rounds", type=int, default=4,
+                    help="rounds per server step between admissions")
     ap.add_argument("--only-probe", action="store_true",
                     help="run only the double-probing measurement (for profilers)")
     ap.add_argument("--probe-cpu", type=int, default=0,
                     help="binaries the oracle probes for a CPU probing rate (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see the sharding notes in DESIGN.md).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path.",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -55,6 +68,9 @@ def main():
 
     if args.only_probe:
         print(json.dumps({"probe_batched": bench_probe(args, bp, gen, torch, np)}), flush=True)
+        return
+    if args.only_serving:
+        print(json.dumps({"serving": bench_serving(args, bp, gen, torch, np)}), flush=True)
         return
 
     dev = torch.device("cuda:0")
@@ -139,6 +155,7 @@ def main():
                          "worklist mode, one thread" % reps_cpu}
 
     probe = None if args.skip_probe else bench_probe(args, bp, gen, torch, np)
+    serving = bench_serving(args, bp, gen, torch, np) if args.serving else None
 
     out = {
         "metric": "propagated nnz/s (plain cold propagation, single instance)",
@@ -161,6 +178,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "probe_batched": probe,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 
@@ -230,6 +248,157 @@ def bench_probe(args, bp, gen, torch, np):
                                "kind": "oracle", "nnz_per_s": float(O["nnz"].sum()) / tc,
                                "sample": "%d binaries x {0,1}" % kc}
     return res
+
+
+def bench_serving(args, bp, gen, torch, np):
+    """Serving: seeded instances with m log-uniform in [1e3, mmax] (n = 1.5 m,
+    nnz ~ 8 m), resident on the device; a seeded request trace, instance
+    uniform, half propagate requests (1% of the unfixed binaries fixed to a
+    random 0/1) and half probe requests (k = round(exp(U[0, ln 512])) unfixed
+    binaries).  C is the saturated rate (all requests queued at once); then
+    Poisson arrivals at 0.5 C and 0.9 C report p50/p99 latency.  Baseline:
+    the same requests served one at a time in arrival order (FIFO) with
+    bp_propagate / bp_probe, its latency derived from measured service times
+    and the same arrival times."""
+    import math
+    dev = torch.device("cuda:0")
+    t_gen = time.perf_counter()
+    insts = gen.make_serving(args.seed, count=args.serve_instances, m_hi=args.serve_mmax)
+    t_gen = time.perf_counter() - t_gen
+    log("serving: %d instances generated in %.1f s" % (len(insts), t_gen))
+    loaded, bases = [], []
+    for inst in insts:
+        I = bp.Instance(inst)
+        lb = torch.tensor(inst["lb"], dtype=torch.float64, device=dev)
+        ub = torch.tensor(inst["ub"], dtype=torch.float64, device=dev)
+        r = I.propagate(lb, ub)
+        assert r["status"] == bp.BP_OK
+        loaded.append(I)
+        bases.append((lb.cpu().numpy(), ub.cpu().numpy()))
+    rng = np.random.default_rng(args.seed + 17)
+    reqs = []
+    for _ in range(args.serve_requests):
+        t = int(rng.integers(0, len(insts)))
+        lb, ub = bases[t]
+        bins = np.nonzero((insts[t]["vtype"] == 1) & (lb == 0) & (ub == 1))[0]
+        if rng.uniform() < 0.5:
+            k = max(1, int(round(0.01 * bins.size)))
+            vs = np.sort(rng.choice(bins, size=min(k, bins.size), replace=False)).astype(np.int32)
+            val = rng.integers(0, 2, size=vs.size).astype(np.float64)
+            reqs.append((t, bp.REQ_PROPAGATE, vs, val))
+        else:
+            k = int(round(math.exp(rng.uniform(0, math.log(512)))))
+            vs = np.sort(rng.choice(bins, size=min(k, bins.size), replace=False)).astype(np.int32)
+            reqs.append((t, bp.REQ_PROBE, vs, None))
+    nnz_total = sum(int(i["row_ptr"][-1]) for i in insts)
+    opts = bp.default_options(rounds_per_launch=args.serve_rounds)
+    budget = 64 << 30
+    S = bp.Server(loaded, budget, opts)
+    info = S.info()
+    S.close()
+    log("serving: instances resident, %d requests, %d slots of %d bytes"
+        % (len(reqs), info["slots"], info["bytes_per_slot"]))
+
+    def run_trace(arrivals):
+        """arrivals: seconds from start (None: all at once).  Returns
+        (elapsed s, latencies us, jobs, nnz)."""
+        t_create = time.perf_counter()
+        S0 = bp.Server(loaded, budget, opts)
+        ids = {}
+        i = 0
+        n = len(reqs)
+        done = {}
+        t0 = time.perf_counter()
+        t_note = t_last = t0
+        while len(done) < n:
+            now = time.perf_counter() - t0
+            while i < n and (arrivals is None or arrivals[i] <= now):
+                t, kind, vs, val = reqs[i]
+                rid = S0.submit(t, kind, vs, val, val)
+                ids[rid] = i
+                i += 1
+            busy = S0.run(args.serve_rounds)
+            got = S0.poll(100000)
+            for c in got:
+                done[ids[c["id"]]] = c
+            tn = time.perf_counter()
+            if got:
+                t_last = tn
+            if tn - t_note > 5.0:
+                log("  serving: %d/%d done, %d submitted, %d unfinished, %.1f s"
+                    % (len(done), n, i, busy, tn - t0))
+                t_note = tn
+            if busy and tn - t_last > 60.0:
+                raise RuntimeError("serving made no progress for 60 s (%d/%d done, %d unfinished)"
+                                   % (len(done), n, busy))
+            if busy == 0 and i < n and arrivals is not None:
+                wait = arrivals[i] - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(wait)
+        elapsed = time.perf_counter() - t0
+        lat = []
+        for j in range(n):
+            arr_us = (0.0 if arrivals is None else arrivals[j] * 1e6) + (t0 - t_create) * 1e6
+            lat.append(done[j]["done_us"] - arr_us)
+        S0.close()
+        return elapsed, np.array(lat)
+
+    # saturated rate
+    el_sat, lat_sat = run_trace(None)
+    C = len(reqs) / el_sat
+    log("serving: saturated %.1f requests/s" % C)
+    out = {"workload": "%d instances, m log-uniform [1e3, %g], %d nnz resident; %d requests "
+                       "(50%% propagate fixing 1%% of binaries, 50%% probe k~exp U[0, ln 512])"
+                       % (len(insts), args.serve_mmax, nnz_total, len(reqs)),
+           "slots": info["slots"], "bytes_per_slot": info["bytes_per_slot"],
+           "generate_s": t_gen, "saturated_requests_per_s": C,
+           "saturated_p50_ms": float(np.percentile(lat_sat, 50)) / 1e3,
+           "saturated_p99_ms": float(np.percentile(lat_sat, 99)) / 1e3}
+    for frac in (0.5, 0.9):
+        gaps = rng.exponential(1.0 / (frac * C), size=len(reqs))
+        arrivals = np.cumsum(gaps)
+        el, lat = run_trace(arrivals)
+        log("serving: load %g done in %.1f s" % (frac, el))
+        out["load_%g" % frac] = {"offered_per_s": frac * C, "served_per_s": len(reqs) / el,
+                                 "p50_ms": float(np.percentile(lat, 50)) / 1e3,
+                                 "p99_ms": float(np.percentile(lat, 99)) / 1e3}
+    # FIFO one-at-a-time baseline: service time of every request alone
+    svc = np.zeros(len(reqs))
+    t_fifo = time.perf_counter()
+    for j, (t, kind, vs, val) in enumerate(reqs):
+        if time.perf_counter() - t_fifo > 5.0:
+            log("  fifo baseline: %d/%d requests" % (j, len(reqs)))
+            t_fifo = time.perf_counter()
+        I = loaded[t]
+        lb0, ub0 = bases[t]
+        ts = time.perf_counter()
+        if kind == bp.REQ_PROBE:
+            I.probe(torch.tensor(vs, dtype=torch.int32, device=dev))
+        else:
+            lb = torch.tensor(lb0, device=dev)
+            ub = torch.tensor(ub0, device=dev)
+            vv = torch.tensor(vs, dtype=torch.long, device=dev)
+            vals = torch.tensor(val, device=dev)
+            lb[vv] = torch.maximum(lb[vv], vals)
+            ub[vv] = torch.minimum(ub[vv], vals)
+            I.propagate(lb, ub, torch.tensor(vs, dtype=torch.int32, device=dev))
+        torch.cuda.synchronize()
+        svc[j] = time.perf_counter() - ts
+    base = {"saturated_requests_per_s": len(reqs) / svc.sum()}
+    for frac in (0.5, 0.9):
+        rng2 = np.random.default_rng(args.seed + int(frac * 100))
+        arrivals = np.cumsum(rng2.exponential(1.0 / (frac * C), size=len(reqs)))
+        finish = np.zeros(len(reqs))
+        tcur = 0.0
+        for j in range(len(reqs)):
+            tcur = max(tcur, arrivals[j]) + svc[j]
+            finish[j] = tcur
+        lat = (finish - arrivals) * 1e3
+        base["load_%g" % frac] = {"p50_ms": float(np.percentile(lat, 50)),
+                                  "p99_ms": float(np.percentile(lat, 99))}
+    out["fifo_one_at_a_time"] = base
+    out["throughput_over_fifo"] = C / base["saturated_requests_per_s"]
+    return out
 
 
 if __name__ == "__main__":

@@ -200,6 +200,29 @@ int bp_propagate_batch(bp_instance *h, int32_t B, double *lb, double *ub,
 int bp_probe(bp_instance *h, const int32_t *vars, int32_t k, bp_probe_out *out,
              void *stream);
 
+/* Schedule chosen by bp_autotune. */
+typedef struct {
+    int32_t heavy_threshold;   /* rows longer than this split across workgroups */
+    int32_t heavy_chunk;       /* nonzeros per workgroup of a heavy row */
+    int32_t rounds_per_launch; /* rounds per captured graph */
+    int32_t probe_slots;       /* bound vectors in flight while probing */
+    double ms;                 /* time of the chosen schedule on the workload */
+    int32_t trials;            /* schedules timed (0: taken from the cache) */
+    int32_t from_cache;
+} bp_tuning;
+
+/* Autotuner: time candidate schedules (heavy-row threshold and chunk size,
+ * rounds per graph; and probe slots when vars != NULL) on the caller's own
+ * workload -- a cold bp_propagate from DEVICE lb/ub [n] (left unchanged),
+ * then, if k > 0, bp_probe of DEVICE vars [k] from the resulting base -- and
+ * keep the fastest in the instance's options.  Every schedule computes the
+ * same results; only time differs.  With cache_path != NULL the choice is
+ * read from / appended to that text file, keyed by the device architecture
+ * and a signature of the instance (sizes and row-length bins).  The base is
+ * left at the cold propagation's result. */
+int bp_autotune(bp_instance *h, const double *lb, const double *ub, const int32_t *vars,
+                int32_t k, const char *cache_path, bp_tuning *out, void *stream);
+
 /* Copy the base bounds into DEVICE lb/ub [n].  BP_ESTATE without a base. */
 int bp_get_base(bp_instance *h, double *lb, double *ub, void *stream);
 

@@ -23,7 +23,7 @@ FLAG_FORCE_EXACT, FLAG_TIME_KERNELS, FLAG_HOST_ROUNDS, FLAG_COUNT_VARS = 1, 2, 4
 EXPORTS = ["bp_options_default", "bp_load", "bp_propagate", "bp_propagate_batch", "bp_probe",
            "bp_get_base", "bp_kernel_stats", "bp_device_bytes", "bp_free", "bp_last_error",
            "bp_server_create", "bp_server_submit", "bp_server_run", "bp_server_poll",
-           "bp_server_results", "bp_server_info", "bp_server_destroy"]
+           "bp_server_results", "bp_server_info", "bp_server_destroy", "bp_autotune"]
 REQ_PROBE, REQ_PROPAGATE = 0, 1
 
 
@@ -71,6 +71,12 @@ class Completion(C.Structure):
     _fields_ = [("id", C.c_int64), ("instance", C.c_int32), ("kind", C.c_int32),
                 ("jobs", C.c_int32), ("reserved", C.c_int32), ("submit_us", C.c_double),
                 ("done_us", C.c_double)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("heavy_threshold", C.c_int32), ("heavy_chunk", C.c_int32),
+                ("rounds_per_launch", C.c_int32), ("probe_slots", C.c_int32),
+                ("ms", C.c_double), ("trials", C.c_int32), ("from_cache", C.c_int32)]
 
 
 class BPError(RuntimeError):
@@ -122,6 +128,9 @@ def load_library(path: str = LIB_PATH):
     lib.bp_server_results.restype = C.c_int
     lib.bp_server_info.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
     lib.bp_server_info.restype = C.c_int
+    lib.bp_autotune.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                C.c_char_p, C.POINTER(Tuning), C.c_void_p]
+    lib.bp_autotune.restype = C.c_int
     lib.bp_server_destroy.argtypes = [C.c_void_p]
     lib.bp_server_destroy.restype = None
     return lib
@@ -266,6 +275,20 @@ class Instance:
             for key in ("var", "lb", "ub"):
                 o[key] = o[key][:tot]
             return o
+
+    def autotune(self, lb: torch.Tensor, ub: torch.Tensor, vars_: torch.Tensor = None,
+                 cache_path: str = None, stream=None) -> dict:
+        """bp_autotune on a cold propagation from (lb, ub) and, if given, a
+        probe of vars_; the chosen schedule stays in the instance."""
+        t = Tuning()
+        k = 0 if vars_ is None else vars_.numel()
+        _check(_LIB.bp_autotune(self._h, _dptr(lb), _dptr(ub),
+                                _dptr(vars_) if k else None, k,
+                                cache_path.encode() if cache_path else None, C.byref(t),
+                                _stream_ptr(stream)))
+        return dict(heavy_threshold=t.heavy_threshold, heavy_chunk=t.heavy_chunk,
+                    rounds_per_launch=t.rounds_per_launch, probe_slots=t.probe_slots,
+                    ms=t.ms, trials=t.trials, from_cache=bool(t.from_cache))
 
     def base(self, stream=None):
         lb = torch.empty(self.n, dtype=torch.float64, device="cuda")

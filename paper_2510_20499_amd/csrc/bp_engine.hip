@@ -49,7 +49,10 @@ struct DevBuf {
         if (p) (void)hipFree(p);
     }
     int alloc(size_t n, int64_t &total) {
-        if (p) (void)hipFree(p);
+        if (p) {
+            (void)hipFree(p);
+            total -= (int64_t)bytes;
+        }
         p = nullptr;
         bytes = 0;
         if (n == 0) n = 16;
@@ -121,6 +124,7 @@ struct bp_instance {
     int64_t bin_start[NBIN + 1] = {0};
     int64_t heavy_chunks = 0;        // chunks of all heavy rows
     std::vector<int32_t> cold_hbase; // cold-start chunk base of each heavy row (bin order)
+    std::vector<int32_t> row_len;    // host copy of the row lengths (re-binning)
     DevBuf cold_hbase_d;
     std::unique_ptr<Engine> eng;
     // stats
@@ -311,6 +315,50 @@ static int validate_options(const bp_options &o) {
     return 0;
 }
 
+// Row bins (logarithmic radix binning, the paper's Section 2.1 load
+// balancing) for the instance's heavy threshold and chunk size: the bin of
+// every row, the cold-start row order grouped by bin, and the chunk table
+// of the heavy rows.  Run at load and again when the autotuner changes the
+// schedule.
+static int bin_rows(bp_instance *h, hipStream_t st) {
+    const int64_t m = h->m;
+    for (int b = 0; b < NBIN; ++b) h->bin_count[b] = 0;
+    std::vector<uint8_t> rbin(m);
+    for (int64_t k = 0; k < m; ++k) {
+        int b = row_bin(h->row_len[k], h->heavy_threshold);
+        rbin[k] = (uint8_t)b;
+        h->bin_count[b] += 1;
+    }
+    h->bin_start[0] = 0;
+    for (int b = 0; b < NBIN; ++b) h->bin_start[b + 1] = h->bin_start[b] + h->bin_count[b];
+    std::vector<int32_t> cold(m);
+    {
+        std::vector<int64_t> fill(h->bin_start, h->bin_start + NBIN);
+        for (int64_t k = 0; k < m; ++k) cold[fill[rbin[k]]++] = (int32_t)k;
+    }
+    h->heavy_chunks = 0;
+    h->cold_hbase.clear();
+    for (int64_t j = h->bin_start[BIN_HEAVY]; j < h->bin_start[BIN_HEAVY + 1]; ++j) {
+        int64_t len = h->row_len[cold[j]];
+        h->cold_hbase.push_back((int32_t)h->heavy_chunks);
+        h->heavy_chunks += (len + h->heavy_chunk - 1) / h->heavy_chunk;
+    }
+    int rc;
+    HIPTRY(hipStreamSynchronize(st));  // the previous tables may still be in use
+    if ((rc = h->rbin.alloc((size_t)m, h->bytes))) return rc;
+    if ((rc = h->cold_rows.alloc((size_t)m * 4, h->bytes))) return rc;
+    if ((rc = h->cold_hbase_d.alloc(h->cold_hbase.size() * 4, h->bytes))) return rc;
+    if (m) {
+        HIPTRY(hipMemcpyAsync(h->rbin.p, rbin.data(), (size_t)m, hipMemcpyHostToDevice, st));
+        HIPTRY(hipMemcpyAsync(h->cold_rows.p, cold.data(), (size_t)m * 4, hipMemcpyHostToDevice, st));
+    }
+    if (!h->cold_hbase.empty())
+        HIPTRY(hipMemcpyAsync(h->cold_hbase_d.p, h->cold_hbase.data(), h->cold_hbase.size() * 4,
+                              hipMemcpyHostToDevice, st));
+    HIPTRY(hipStreamSynchronize(st));
+    return 0;
+}
+
 extern "C" int bp_load(const bp_sparse *csr, const bp_sparse *csc, const double *row_lo,
                        const double *row_hi, const uint8_t *vartype, const bp_options *opt,
                        void *stream, bp_instance **out) {
@@ -385,27 +433,8 @@ extern "C" int bp_load(const bp_sparse *csr, const bp_sparse *csc, const double 
     h->heavy_threshold = o.heavy_threshold;
     h->heavy_chunk = o.heavy_chunk;
     memset(&h->stats, 0, sizeof(h->stats));
-    // Row bins (logarithmic radix binning) and the cold-start row order.
-    std::vector<uint8_t> rbin(m);
-    for (int64_t k = 0; k < m; ++k) {
-        int b = row_bin(csr->ptr[k + 1] - csr->ptr[k], h->heavy_threshold);
-        rbin[k] = (uint8_t)b;
-        h->bin_count[b] += 1;
-    }
-    h->bin_start[0] = 0;
-    for (int b = 0; b < NBIN; ++b) h->bin_start[b + 1] = h->bin_start[b] + h->bin_count[b];
-    std::vector<int32_t> cold(m);
-    {
-        std::vector<int64_t> fill(h->bin_start, h->bin_start + NBIN);
-        for (int64_t k = 0; k < m; ++k) cold[fill[rbin[k]]++] = (int32_t)k;
-    }
-    h->heavy_chunks = 0;
-    for (int64_t j = h->bin_start[BIN_HEAVY]; j < h->bin_start[BIN_HEAVY + 1]; ++j) {
-        int32_t k = cold[j];
-        int64_t len = csr->ptr[k + 1] - csr->ptr[k];
-        h->cold_hbase.push_back((int32_t)h->heavy_chunks);
-        h->heavy_chunks += (len + h->heavy_chunk - 1) / h->heavy_chunk;
-    }
+    h->row_len.resize(m);
+    for (int64_t k = 0; k < m; ++k) h->row_len[k] = (int32_t)(csr->ptr[k + 1] - csr->ptr[k]);
     std::vector<double> side(2 * m);
     for (int64_t k = 0; k < m; ++k) {
         side[2 * k] = row_lo[k] == 0.0 ? 0.0 : row_lo[k];
@@ -426,10 +455,8 @@ extern "C" int bp_load(const bp_sparse *csr, const bp_sparse *csc, const double 
     ALLOC_UP(col_ptr, cptr.data(), (size_t)(n + 1) * 8);
     ALLOC_UP(col_row, crow.data(), (size_t)nnz * 4);
     ALLOC_UP(vtype, vartype, (size_t)n);
-    ALLOC_UP(rbin, rbin.data(), (size_t)m);
-    ALLOC_UP(cold_rows, cold.data(), (size_t)m * 4);
-    ALLOC_UP(cold_hbase_d, h->cold_hbase.data(), h->cold_hbase.size() * 4);
 #undef ALLOC_UP
+    if ((rc = bin_rows(h.get(), st))) return rc;
     if ((rc = h->base.alloc((size_t)n * 16, B))) return rc;
     HIPTRY(hipStreamSynchronize(st));
     HIPTRY(hipEventCreate(&h->ev0));
@@ -1015,3 +1042,4 @@ extern "C" int bp_probe(bp_instance *h, const int32_t *vars, int32_t k, bp_probe
 }
 
 #include "bp_server.h"
+#include "bp_tune.h"

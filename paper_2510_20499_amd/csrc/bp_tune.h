@@ -1,0 +1,216 @@
+// bp_tune.h -- schedule autotuner (part of bp_engine.hip's translation unit;
+// see include/bp.h for the C ABI).
+//
+// The schedule knobs change how rows are mapped to workgroups and how many
+// rounds a graph holds, never the arithmetic: every candidate must return
+// the same outcome, rounds and propagated nonzeros, and the tuner checks
+// that on every trial.  Candidates are timed on the caller's own workload.
+#pragma once
+#include <chrono>
+#include <cstdio>
+#include <fstream>
+#include <sstream>
+
+static std::string tune_key(const bp_instance *h) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        arch = prop.gcnArchName;
+    for (char &c : arch)
+        if (c == ' ') c = '_';
+    // row-length histogram by powers of two: independent of the schedule
+    std::vector<int64_t> hist(34, 0);
+    for (int32_t L : h->row_len) {
+        int b = 0;
+        while ((1ll << b) < L) ++b;
+        hist[b] += 1;
+    }
+    std::ostringstream os;
+    os << arch << "/m" << h->m << "/n" << h->n << "/z" << h->nnz << "/h";
+    for (size_t b = 0; b < hist.size(); ++b)
+        if (hist[b]) os << b << ":" << hist[b] << ",";
+    return os.str();
+}
+
+static bool tune_lookup(const char *path, const std::string &key, bp_tuning *t) {
+    if (!path) return false;
+    std::ifstream f(path);
+    if (!f) return false;
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        std::istringstream is(line);
+        std::string k;
+        bp_tuning x;
+        memset(&x, 0, sizeof(x));
+        if (!(is >> k >> x.heavy_threshold >> x.heavy_chunk >> x.rounds_per_launch >> x.probe_slots >> x.ms))
+            continue;
+        if (k == key) {
+            *t = x;
+            found = true;  // the last entry for a key wins
+        }
+    }
+    return found;
+}
+
+static void tune_store(const char *path, const std::string &key, const bp_tuning &t) {
+    if (!path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s %d %d %d %d %.6f\n", key.c_str(), t.heavy_threshold, t.heavy_chunk,
+            t.rounds_per_launch, t.probe_slots, t.ms);
+    fclose(f);
+}
+
+static int tune_apply(bp_instance *h, const bp_tuning &t, hipStream_t st) {
+    h->opt.heavy_threshold = t.heavy_threshold;
+    h->opt.heavy_chunk = t.heavy_chunk;
+    h->opt.rounds_per_launch = t.rounds_per_launch;
+    if (t.probe_slots > 0) h->opt.probe_slots = t.probe_slots;
+    if (h->heavy_threshold != t.heavy_threshold || h->heavy_chunk != t.heavy_chunk) {
+        h->heavy_threshold = t.heavy_threshold;
+        h->heavy_chunk = t.heavy_chunk;
+        return bin_rows(h, st);
+    }
+    return 0;
+}
+
+extern "C" int bp_autotune(bp_instance *h, const double *lb, const double *ub, const int32_t *vars,
+                           int32_t k, const char *cache_path, bp_tuning *out, void *stream) {
+    g_err.clear();
+    if (!h || !out || (h->n > 0 && (!lb || !ub)) || k < 0 || (k > 0 && !vars))
+        return fail(BP_EINVAL, "bp_autotune: bad argument");
+    hipStream_t st = as_stream(stream);
+    const std::string key = tune_key(h);
+    bp_tuning best;
+    memset(&best, 0, sizeof(best));
+    if (tune_lookup(cache_path, key, &best)) {
+        if (int rc = tune_apply(h, best, st)) return rc;
+        best.trials = 0;
+        best.from_cache = 1;
+        *out = best;
+        return BP_OK;
+    }
+    const int64_t n = h->n;
+    DevBuf wl, wu;
+    int64_t dummy = 0;
+    if (int rc = wl.alloc((size_t)std::max<int64_t>(n, 1) * 8, dummy)) return rc;
+    if (int rc = wu.alloc((size_t)std::max<int64_t>(n, 1) * 8, dummy)) return rc;
+    bp_result ref;
+    bool have_ref = false;
+    int trials = 0;
+    // One timed cold propagation (best of two); checks the result is the
+    // same for every schedule.
+    auto time_prop = [&](double &ms) -> int {
+        ms = 1e300;
+        for (int rep = 0; rep < 2; ++rep) {
+            if (n) {
+                HIPTRY(hipMemcpyAsync(wl.p, lb, (size_t)n * 8, hipMemcpyDeviceToDevice, st));
+                HIPTRY(hipMemcpyAsync(wu.p, ub, (size_t)n * 8, hipMemcpyDeviceToDevice, st));
+            }
+            HIPTRY(hipStreamSynchronize(st));
+            bp_result r;
+            auto t0 = std::chrono::steady_clock::now();
+            int rc = bp_propagate(h, wl.as<double>(), wu.as<double>(), nullptr, 0, &r, st);
+            auto t1 = std::chrono::steady_clock::now();
+            if (rc < 0) return rc;
+            ms = std::min(ms, std::chrono::duration<double, std::milli>(t1 - t0).count());
+            if (!have_ref) {
+                ref = r;
+                have_ref = true;
+            } else if (r.status != ref.status || r.rounds != ref.rounds ||
+                       r.nnz_propagated != ref.nnz_propagated) {
+                return fail(BP_EDEVICE, "autotuner: a schedule changed the propagation result");
+            }
+        }
+        ++trials;
+        return 0;
+    };
+    const int32_t thresholds[] = {2048, 4096, 8192, 16384, 32768};
+    const int32_t chunks[] = {512, 1024, 2048, 4096};
+    const int32_t rounds[] = {4, 8, 16, 32};
+    best.ms = 1e300;
+    bp_tuning cur = best;
+    cur.rounds_per_launch = 16;
+    cur.probe_slots = h->opt.probe_slots;
+    for (int32_t ht : thresholds) {
+        for (int32_t hc : chunks) {
+            if (hc > ht) continue;
+            cur.heavy_threshold = ht;
+            cur.heavy_chunk = hc;
+            if (int rc = tune_apply(h, cur, st)) return rc;
+            double ms;
+            if (int rc = time_prop(ms)) return rc;
+            if (ms < best.ms) {
+                best = cur;
+                best.ms = ms;
+            }
+        }
+    }
+    for (int32_t rpl : rounds) {
+        cur = best;
+        cur.rounds_per_launch = rpl;
+        if (int rc = tune_apply(h, cur, st)) return rc;
+        double ms;
+        if (int rc = time_prop(ms)) return rc;
+        if (ms < best.ms) {
+            best = cur;
+            best.ms = ms;
+        }
+    }
+    if (int rc = tune_apply(h, best, st)) return rc;
+    double ms_final;
+    if (int rc = time_prop(ms_final)) return rc;  // leaves the base at the cold result
+    if (k > 0 && ref.status == BP_OK) {
+        // Probe slots, timed on bp_probe of the caller's variables.
+        const int64_t jobs = 2 * (int64_t)k;
+        DevBuf ps, pr, pn, po;
+        if (int rc = ps.alloc(jobs, dummy)) return rc;
+        if (int rc = pr.alloc(jobs * 4, dummy)) return rc;
+        if (int rc = pn.alloc(jobs * 8, dummy)) return rc;
+        if (int rc = po.alloc((jobs + 1) * 8, dummy)) return rc;
+        bp_probe_out o;
+        memset(&o, 0, sizeof(o));
+        o.status = ps.as<int8_t>();
+        o.rounds = pr.as<int32_t>();
+        o.nnz = pn.as<int64_t>();
+        o.off = po.as<int64_t>();
+        o.cap = 0;
+        int rc = bp_probe(h, vars, k, &o, st);
+        if (rc < 0 && rc != BP_ECAPACITY) return rc;
+        const int64_t cap = std::max<int64_t>(o.required, 1);
+        DevBuf pv, pl, pu;
+        if ((rc = pv.alloc(cap * 4, dummy))) return rc;
+        if ((rc = pl.alloc(cap * 8, dummy))) return rc;
+        if ((rc = pu.alloc(cap * 8, dummy))) return rc;
+        o.var = pv.as<int32_t>();
+        o.lb = pl.as<double>();
+        o.ub = pu.as<double>();
+        o.cap = cap;
+        const int32_t slot_opts[] = {64, 128, 256, 512, 1024, 2048};
+        double best_probe = 1e300;
+        int32_t best_slots = h->opt.probe_slots;
+        for (int32_t sl : slot_opts) {
+            if (sl > jobs && sl != slot_opts[0]) break;
+            h->opt.probe_slots = sl;
+            if ((rc = bp_probe(h, vars, k, &o, st)) < 0) return rc;  // warm (sizes the slots)
+            auto t0 = std::chrono::steady_clock::now();
+            if ((rc = bp_probe(h, vars, k, &o, st)) < 0) return rc;
+            double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            ++trials;
+            if (o.required != cap) return fail(BP_EDEVICE, "autotuner: a schedule changed the probe result");
+            if (ms < best_probe) {
+                best_probe = ms;
+                best_slots = sl;
+            }
+        }
+        h->opt.probe_slots = best_slots;
+        best.probe_slots = best_slots;
+    }
+    best.trials = trials;
+    best.from_cache = 0;
+    tune_store(cache_path, key, best);
+    *out = best;
+    return BP_OK;
+}

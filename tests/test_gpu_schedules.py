@@ -1,0 +1,58 @@
+"""Schedule invariance: every row-split schedule the autotuner may choose
+(heavy-row threshold, heavy chunk size, rounds per graph, probe slots)
+returns bit-identical results; the autotuner keeps a schedule and its cache
+round-trips."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import assert_same, bp, dev, gpu_propagate
+from paper_2510_20499_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("ht,hc,rpl", [(1024, 256, 1), (2048, 512, 4), (4096, 1024, 8),
+                                        (8192, 4096, 16), (32768, 2048, 32)])
+def test_schedules_give_identical_results(ht, hc, rpl):
+    inst = gen.make("single", 6, scale=0.2)
+    ro, lo, uo = oracle.propagate(inst)
+    I = bp().Instance(inst, bp().default_options(heavy_threshold=ht, heavy_chunk=hc,
+                                                 rounds_per_launch=rpl))
+    rg, lg, ug = gpu_propagate(I, inst)
+    assert_same(inst, rg, lg, ug, ro, lo, uo, "schedule %d/%d/%d" % (ht, hc, rpl))
+    assert np.array_equal(lg, lo) and np.array_equal(ug, uo)
+
+
+def test_autotune_and_cache():
+    inst = gen.make("single", 7, scale=0.1)
+    I = bp().Instance(inst)
+    lb = dev(inst["lb"], torch.float64)
+    ub = dev(inst["ub"], torch.float64)
+    _, blb, bub = oracle.propagate(inst)
+    vs = gen.pick_probe_vars(inst, blb, bub, 40, seed=2)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tune.txt")
+        t = I.autotune(lb, ub, dev(vs, torch.int32), cache_path=path)
+        assert t["trials"] > 10 and not t["from_cache"]
+        assert (lb.cpu().numpy() == inst["lb"]).all()  # inputs untouched
+        # results with the chosen schedule still match the oracle
+        r, lg, ug = gpu_propagate(I, inst)
+        ro, lo, uo = oracle.propagate(inst)
+        assert_same(inst, r, lg, ug, ro, lo, uo, "tuned")
+        G = I.probe(dev(vs, torch.int32))
+        O = oracle.probe(inst, lo, uo, vs)
+        assert np.array_equal(G["var"].cpu().numpy(), O["var"])
+        assert np.array_equal(G["status"].cpu().numpy(), O["status"])
+        # a new instance of the same matrix reads the cache
+        I2 = bp().Instance(inst)
+        t2 = I2.autotune(lb, ub, dev(vs, torch.int32), cache_path=path)
+        assert t2["from_cache"] and t2["trials"] == 0
+        for key in ("heavy_threshold", "heavy_chunk", "rounds_per_launch", "probe_slots"):
+            assert t2[key] == t[key]
+        r2, lg2, ug2 = gpu_propagate(I2, inst)
+        assert_same(inst, r2, lg2, ug2, ro, lo, uo, "cached")
