@@ -29,6 +29,42 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def fresh(*ts):
+    """Clones of device tensors (a call's in/out bounds)."""
+    return tuple(t.clone() for t in ts)
+
+
+def kernel_roofline(bp, inst, call, reps=5, **opt):
+    """Roofline of the activity kernel k_rows for one call `call(I)`.
+
+    Time: HIP events recorded around each k_rows launch (rounds driven from
+    the host so every launch is bracketed), averaged over `reps` calls.
+    Bytes: what the method must move per launch -- 12 B per nonzero (int32
+    column + f64 coefficient), 24 B per row (row pointer + two sides), 16 B
+    per distinct bound record read -- counted by an instrumented run of the
+    same call and divided by the launches per call."""
+    Ic = bp.Instance(inst, bp.default_options(flags=bp.FLAG_COUNT_VARS, **opt))
+    call(Ic)
+    cs = Ic.kernel_stats(reset=True)
+    del Ic
+    It = bp.Instance(inst, bp.default_options(flags=bp.FLAG_TIME_KERNELS, **opt))
+    call(It)  # warm
+    It.kernel_stats(reset=True)
+    for _ in range(reps):
+        call(It)
+    ts = It.kernel_stats(reset=True)
+    del It
+    launches = ts["launches"] / reps
+    alg_bytes_per_call = 12 * cs["nnz"] + 24 * cs["rows"] + 16 * cs["vars_read"]
+    bytes_per_launch = alg_bytes_per_call / max(launches, 1)
+    avg_launch_ms = ts["ms"] / max(ts["launches"], 1)
+    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 5), "traffic": None,
+            "kernel": "k_rows", "avg_launch_us": round(avg_launch_ms * 1e3, 3),
+            "launches_per_call": launches, "alg_bytes_per_launch": int(bytes_per_launch)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -51,6 +87,13 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-rounds", type=int, default=4,
                     help="rounds per server step between admissions")
+    ap.add_argument("--skip-bulk", action="store_true",
+                    help="skip the bulk-rounding (fix-and-propagate batch) measurement")
+    ap.add_argument("--only-bulk", action="store_true")
+    ap.add_argument("--bulk-vectors", type=int, default=256)
+    ap.add_argument("--bulk-steps", type=int, default=3)
+    ap.add_argument("--bulk-plain", type=int, default=16,
+                    help="vectors propagated one call at a time for the plain baseline")
     ap.add_argument("--only-probe", action="store_true",
                     help="run only the double-probing measurement (for profilers)")
     ap.add_argument("--probe-cpu", type=int, default=0,
@@ -68,6 +111,9 @@ def main():
 
     if args.only_probe:
         print(json.dumps({"probe_batched": bench_probe(args, bp, gen, torch, np)}), flush=True)
+        return
+    if args.only_bulk:
+        print(json.dumps({"bulk_batched": bench_bulk(args, bp, gen, torch, np)}), flush=True)
         return
     if args.only_serving:
         print(json.dumps({"serving": bench_serving(args, bp, gen, torch, np)}), flush=True)
@@ -107,35 +153,7 @@ def main():
     assert r["status"] == bp.BP_OK and r == r0
     value = total_nnz / dt
 
-    # Roofline of the activity kernel: HIP events around each launch (rounds
-    # driven from the host), and the bytes the method must move per launch:
-    # 12 B per nonzero (int32 column + f64 coefficient), 24 B per row
-    # (row pointer + two sides), 16 B per distinct bound record read.
-    Ic = bp.Instance(inst, bp.default_options(flags=bp.FLAG_COUNT_VARS))
-    lc, uc = lb0.clone(), ub0.clone()
-    Ic.propagate(lc, uc)
-    cs = Ic.kernel_stats(reset=True)
-    del Ic
-    It = bp.Instance(inst, bp.default_options(flags=bp.FLAG_TIME_KERNELS))
-    lt, ut = lb0.clone(), ub0.clone()
-    It.propagate(lt, ut)  # warm
-    It.kernel_stats(reset=True)
-    reps = 5
-    for _ in range(reps):
-        lt.copy_(lb0)
-        ut.copy_(ub0)
-        It.propagate(lt, ut)
-    ts = It.kernel_stats(reset=True)
-    launches = ts["launches"] / reps
-    alg_bytes_per_call = 12 * cs["nnz"] + 24 * cs["rows"] + 16 * cs["vars_read"]
-    bytes_per_launch = alg_bytes_per_call / max(launches, 1)
-    avg_launch_ms = ts["ms"] / max(ts["launches"], 1)
-    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 5), "traffic": None,
-                "kernel": "k_rows", "avg_launch_us": round(avg_launch_ms * 1e3, 3),
-                "launches_per_step": launches,
-                "alg_bytes_per_launch": int(bytes_per_launch)}
+    roofline = kernel_roofline(bp, inst, lambda J: J.propagate(*fresh(lb0, ub0)))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -155,6 +173,7 @@ def main():
                          "worklist mode, one thread" % reps_cpu}
 
     probe = None if args.skip_probe else bench_probe(args, bp, gen, torch, np)
+    bulk = None if args.skip_bulk else bench_bulk(args, bp, gen, torch, np)
     serving = bench_serving(args, bp, gen, torch, np) if args.serving else None
 
     out = {
@@ -178,6 +197,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "probe_batched": probe,
+        "bulk_batched": bulk,
         "serving": serving,
     }
     print(json.dumps(out), flush=True)
@@ -248,6 +268,122 @@ def bench_probe(args, bp, gen, torch, np):
                                "kind": "oracle", "nnz_per_s": float(O["nnz"].sum()) / tc,
                                "sample": "%d binaries x {0,1}" % kc}
     return res
+
+
+def bench_bulk(args, bp, gen, torch, np):
+    """Bulk-rounding fix-and-propagate on the bulk workload (m=2M, n=3M,
+    50% binary, 30% integer in [0,1000], ~20M nnz): B bound vectors per
+    call, each the root fixed point with a seeded 5% of the unfixed integer
+    variables fixed to rint(U[lb, ub]), propagated from their changed lists
+    with bp_propagate_batch.  The schedule comes from the autotuner.  Plain:
+    the same vectors one per call."""
+    dev = torch.device("cuda:0")
+    B = args.bulk_vectors
+    t = time.perf_counter()
+    inst = gen.make("bulk", args.seed)
+    log("bulk: instance generated in %.1f s" % (time.perf_counter() - t))
+    t = time.perf_counter()
+    I = bp.Instance(inst)
+    torch.cuda.synchronize()
+    t_load = time.perf_counter() - t
+    lb0 = torch.tensor(inst["lb"], dtype=torch.float64, device=dev)
+    ub0 = torch.tensor(inst["ub"], dtype=torch.float64, device=dev)
+    tune = I.autotune(lb0, ub0)
+    opt_kw = dict(heavy_threshold=tune["heavy_threshold"], heavy_chunk=tune["heavy_chunk"],
+                  rounds_per_launch=tune["rounds_per_launch"])
+    log("bulk: loaded in %.1f s, tuned %s" % (t_load, opt_kw))
+    # Root bounds: the cold propagation's result.  At this size the root
+    # may stop at the round limit; its bounds are still valid (every
+    # tightening is implied), so they serve as the root of the candidates.
+    rl, ru = fresh(lb0, ub0)
+    root = I.propagate(rl, ru)
+    assert root["status"] in (bp.BP_OK, bp.BP_ROUND_LIMIT), root
+    # cold root propagation at this size (plain path)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    reps_cold = 3
+    for _ in range(reps_cold):
+        r = I.propagate(*fresh(lb0, ub0))
+    torch.cuda.synchronize()
+    t_cold = (time.perf_counter() - t) / reps_cold
+    lists = gen.bulk_fix_lists(inst, rl.cpu().numpy(), ru.cpu().numpy(), B, frac=0.05, seed=args.seed)
+    ptr = np.zeros(B + 1, np.int64)
+    ptr[1:] = np.cumsum([p.size for p, _ in lists])
+    idx = torch.tensor(np.concatenate([p for p, _ in lists]), dtype=torch.int32, device=dev)
+    vals = torch.tensor(np.concatenate([v for _, v in lists]), dtype=torch.float64, device=dev)
+    vec = torch.repeat_interleave(torch.arange(B, device=dev), torch.tensor(np.diff(ptr), device=dev))
+    flat = vec * inst["n"] + idx.long()
+    ptr_d = torch.tensor(ptr, dtype=torch.int64, device=dev)
+    LB = torch.empty(B, inst["n"], dtype=torch.float64, device=dev)
+    UB = torch.empty_like(LB)
+
+    def restore():
+        LB.copy_(rl.expand(B, -1))
+        UB.copy_(ru.expand(B, -1))
+        LB.view(-1)[flat] = vals
+        UB.view(-1)[flat] = vals
+
+    def batch_call(J):
+        restore()
+        return J.propagate_batch(LB, UB, ptr_d, idx)
+
+    log("bulk: %d vectors of %d fixings ready" % (B, int(ptr[1])))
+    res = batch_call(I)  # warm
+    torch.cuda.synchronize()
+    tb = 0.0
+    for _ in range(args.bulk_steps):
+        restore()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = I.propagate_batch(LB, UB, ptr_d, idx)
+        torch.cuda.synchronize()
+        tb += time.perf_counter() - t
+    tb /= args.bulk_steps
+    nnz_b = sum(x["nnz_propagated"] for x in res)
+    status = np.array([x["status"] for x in res])
+    rounds = np.array([x["rounds"] for x in res])
+    log("bulk: batched %.1f ms per call" % (tb * 1e3))
+    # plain: the first vectors, one per call
+    kp = min(args.bulk_plain, B)
+    L1 = torch.empty(1, inst["n"], dtype=torch.float64, device=dev)
+    U1 = torch.empty_like(L1)
+    tp = 0.0
+    nnz_p = 0
+    for v in range(-1, kp):
+        w = max(v, 0)
+        a, b = int(ptr[w]), int(ptr[w + 1])
+        sel = idx[a:b].long()
+        L1[0].copy_(rl)
+        U1[0].copy_(ru)
+        L1[0, sel] = vals[a:b]
+        U1[0, sel] = vals[a:b]
+        p1 = torch.tensor([0, b - a], dtype=torch.int64, device=dev)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r1 = I.propagate_batch(L1, U1, p1, idx[a:b])
+        torch.cuda.synchronize()
+        if v >= 0:  # v = -1 is a warm-up call
+            tp += time.perf_counter() - t
+            nnz_p += r1[0]["nnz_propagated"]
+            assert r1[0] == res[v], (v, r1[0], res[v])
+    log("bulk: plain %.2f ms per vector" % (tp / kp * 1e3))
+    roof = kernel_roofline(bp, inst, batch_call, reps=2, **opt_kw)
+    return {
+        "workload": "bulk rounding: m=%d, n=%d, nnz=%d; %d vectors per call, each fixing %d "
+                    "integer variables (5%%) and propagating"
+                    % (inst["m"], inst["n"], int(inst["row_ptr"][-1]), B, int(ptr[1])),
+        "batched_nnz_per_s": nnz_b / tb, "batched_ms": tb * 1e3,
+        "batched_vectors_per_s": B / tb,
+        "plain_nnz_per_s": nnz_p / tp, "plain_vectors_per_s": kp / tp,
+        "batched_over_plain": (B / tb) / (kp / tp),
+        "infeasible": int((status == bp.BP_INFEASIBLE).sum()),
+        "rounds_mean": float(rounds.mean()), "rounds_max": int(rounds.max()),
+        "nnz_per_vector_mean": nnz_b / B,
+        "root_cold": {"ms": t_cold * 1e3, "rounds": r["rounds"], "status": r["status"],
+                      "nnz_per_s": r["nnz_propagated"] / t_cold},
+        "load_s": t_load, "schedule": opt_kw, "tune_trials": tune["trials"],
+        "roofline": roof,
+    }
 
 
 def bench_serving(args, bp, gen, torch, np):

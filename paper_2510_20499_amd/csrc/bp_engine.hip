@@ -66,6 +66,11 @@ struct DevBuf {
         total += (int64_t)n;
         return 0;
     }
+    // Keeps the allocation when it is already large enough.
+    int grow(size_t n, int64_t &total) {
+        if (p && bytes >= std::max<size_t>(n, 16)) return 0;
+        return alloc(n, total);
+    }
     template <class T>
     T *as() const {
         return (T *)p;
@@ -119,6 +124,7 @@ struct bp_instance {
     DevBuf st_var, st_lb, st_ub, st_off, st_cnt, scratch_i32;
     DevBuf st_status, st_rounds, st_nnz, st_jobs;  // per-job results and descriptors
     int64_t st_cap = 0;
+    DevBuf box_d, ptr_d;  // per-call box-check results and changed-list offsets
     // row bins (host)
     int64_t bin_count[NBIN] = {0};
     int64_t bin_start[NBIN + 1] = {0};
@@ -792,9 +798,8 @@ static int propagate_slots(bp_instance *h, int32_t Bv, double *lb, double *ub,
     Engine &E = *h->eng;
     // Bounds in, box check.
     if (n > 0) k_pack<<<grid_for(n * Bv), 256, 0, st>>>(lb, ub, E.bnd.as<double2>(), n, Bv);
-    DevBuf boxd;
-    int64_t dummy = 0;
-    if (int rc = boxd.alloc((size_t)Bv * 8, dummy)) return rc;
+    DevBuf &boxd = h->box_d;
+    if (int rc = boxd.grow((size_t)Bv * 8, h->bytes)) return rc;
     {
         // even entries: smallest crossed var; odd entries: NaN flags
         std::vector<int32_t> init(2 * (size_t)Bv);
@@ -848,14 +853,13 @@ extern "C" int bp_propagate(bp_instance *h, double *lb, double *ub, const int32_
     hipStream_t st = as_stream(stream);
     bool cold = changed == nullptr;
     if (!cold && n_changed < 0) return fail(BP_EINVAL, "n_changed < 0");
-    DevBuf ptrd;
-    int64_t dummy = 0;
+    DevBuf &ptrd = h->ptr_d;
     if (!cold) {
-        if (int rc = ptrd.alloc(16, dummy)) return rc;
+        if (int rc = ptrd.grow(16, h->bytes)) return rc;
         int64_t p2[2] = {0, n_changed};
         HIPTRY(hipMemcpyAsync(ptrd.p, p2, 16, hipMemcpyHostToDevice, st));
     }
-    int rc = propagate_slots(h, 1, lb, ub, changed, ptrd.as<int64_t>(), cold ? 0 : n_changed, cold,
+    int rc = propagate_slots(h, 1, lb, ub, changed, cold ? nullptr : ptrd.as<int64_t>(), cold ? 0 : n_changed, cold,
                              res, st);
     if (rc < 0) return rc;
     if (res->status == BP_OK && h->n > 0) {

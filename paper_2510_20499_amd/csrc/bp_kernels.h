@@ -1288,13 +1288,28 @@ __global__ void __launch_bounds__(WG) k_retire(Params P, JobIO IO) {
             __syncthreads();
         }
         if (S.state != SLOT_FREE) continue;
-        // Admit jobs until one needs rounds or none is left.
+        // Admit jobs until one needs rounds or none is left.  A job is
+        // claimed by compare-and-swap, so the counter never passes the end
+        // of the list: jobs the host appends later are still claimed.
         for (;;) {
-            if (threadIdx.x == 0) R.job = (int)atomicAdd(&C->next_job, 1u);
+            if (threadIdx.x == 0) {
+                const uint32_t tot = C->total_jobs;
+                uint32_t cur = __hip_atomic_load(&C->next_job, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                int got = -1;
+                while (cur < tot) {
+                    const uint32_t prev = atomicCAS(&C->next_job, cur, cur + 1u);
+                    if (prev == cur) {
+                        got = (int)cur;
+                        break;
+                    }
+                    cur = prev;
+                }
+                R.job = got;
+            }
             __syncthreads();
             const int p = R.job;
             __syncthreads();
-            if ((uint32_t)p >= C->total_jobs) break;
+            if (p < 0) break;
             if (admit_job<MULTI>(P, IO, s, p, par, R)) break;
         }
         __syncthreads();

@@ -407,22 +407,31 @@ def pick_probe_vars(inst, lb, ub, k: int, seed: int = 0):
     return np.sort(rng.choice(cand, size=k, replace=False)).astype(np.int32)
 
 
-def bulk_fix_vectors(inst, lb, ub, count: int, frac: float = 0.05, seed: int = 0):
-    """Bulk-rounding candidates: ``count`` bound vectors, each fixing a seeded
-    ``frac`` of the integer variables to rint(U[lb, ub]).  Returns
-    (LB[count, n], UB[count, n], changed lists)."""
+def bulk_fix_lists(inst, lb, ub, count: int, frac: float = 0.05, seed: int = 0):
+    """Bulk-rounding candidates as fixing lists: for each of ``count``
+    vectors, a seeded ``frac`` of the unfixed integer variables (sorted) and
+    their values rint(U[lb, ub]).  Returns a list of (vars int32, values)."""
     rng = _stream(seed + 104729)[0]
-    n = inst["n"]
     ints = np.nonzero(inst["vtype"] == 1)[0]
     ints = ints[np.isfinite(lb[ints]) & np.isfinite(ub[ints]) & (lb[ints] < ub[ints])]
+    k = int(round(frac * ints.size))
+    out = []
+    for _ in range(count):
+        pick = np.sort(rng.choice(ints, size=k, replace=False))
+        val = np.rint(rng.uniform(lb[pick], ub[pick]))
+        out.append((pick.astype(np.int32), val))
+    return out
+
+
+def bulk_fix_vectors(inst, lb, ub, count: int, frac: float = 0.05, seed: int = 0):
+    """Bulk-rounding candidates as dense bound vectors: (LB[count, n],
+    UB[count, n], changed lists), the fixings of bulk_fix_lists applied to
+    (lb, ub)."""
     LB = np.repeat(lb[None, :], count, axis=0)
     UB = np.repeat(ub[None, :], count, axis=0)
     changed = []
-    k = int(round(frac * ints.size))
-    for v in range(count):
-        pick = np.sort(rng.choice(ints, size=k, replace=False))
-        val = np.rint(rng.uniform(lb[pick], ub[pick]))
+    for v, (pick, val) in enumerate(bulk_fix_lists(inst, lb, ub, count, frac, seed)):
         LB[v, pick] = val
         UB[v, pick] = val
-        changed.append(pick.astype(np.int32))
+        changed.append(pick)
     return LB, UB, changed

@@ -162,3 +162,38 @@ def test_serving_infeasible_fixings():
     _, mix, _ = _serve(loaded, reqs, budget=64 << 20)
     for j, req in enumerate(reqs):
         _same(mix[j], _oracle_result(insts[t], bases[t], req), insts[t], "inf%d" % j, evidence=True)
+
+
+def test_serving_trickle_arrivals():
+    """Requests arrive one at a time between short steps, with idle steps
+    on an empty server before and between them: every job is still
+    admitted (the job counter never runs past the end of the list) and
+    every result matches the oracle."""
+    insts, loaded, bases = _instances()
+    reqs = _requests(insts, bases, 30, seed=21)
+    opts = bp().default_options(rounds_per_launch=2)
+    per_slot = bp().Server(loaded, 1 << 40, opts).info()["bytes_per_slot"]
+    S = bp().Server(loaded, 4 * per_slot, opts)
+    assert S.info()["slots"] == 4
+    assert S.run(8) == 0  # idle steps before anything arrives
+    ids = []
+    for j, (t, kind, vs, lo, hi) in enumerate(reqs):
+        ids.append(S.submit(t, kind, vs, lo, hi))
+        S.run(2)  # the next request arrives while this one may still run
+        if j == len(reqs) // 2:
+            guard = 0
+            while S.run(2):
+                guard += 1
+                assert guard < 10000
+            assert S.run(8) == 0  # idle again, then more arrivals
+    guard = 0
+    while S.run(2):
+        guard += 1
+        assert guard < 10000
+    done = {c["id"] for c in S.poll(100000)}
+    assert done == set(ids)
+    for j, rid in enumerate(ids):
+        t, kind, vs, lo, hi = reqs[j]
+        jobs = 2 * vs.size if kind == bp().REQ_PROBE else 1
+        _same(S.results(rid, jobs), _oracle_result(insts[t], bases[t], reqs[j]), insts[t],
+              "trickle%d" % j, evidence=kind == bp().REQ_PROPAGATE)
