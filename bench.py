@@ -87,6 +87,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-rounds", type=int, default=4,
                     help="rounds per server step between admissions")
+    ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
+                    help="only copy a device buffer of this many MiB 5 times (a kernel of "
+                         "known traffic, for scaling hardware byte counters) and exit")
     ap.add_argument("--skip-bulk", action="store_true",
                     help="skip the bulk-rounding (fix-and-propagate batch) measurement")
     ap.add_argument("--only-bulk", action="store_true")
@@ -111,6 +114,15 @@ def main():
 
     if args.only_probe:
         print(json.dumps({"probe_batched": bench_probe(args, bp, gen, torch, np)}), flush=True)
+        return
+    if args.copy_calibrate:
+        nb = args.copy_calibrate << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nb, "copy_bytes_written": nb, "copies": 5}), flush=True)
         return
     if args.only_bulk:
         print(json.dumps({"bulk_batched": bench_bulk(args, bp, gen, torch, np)}), flush=True)
@@ -438,9 +450,9 @@ def bench_serving(args, bp, gen, torch, np):
     def run_trace(arrivals):
         """arrivals: seconds from start (None: all at once).  Returns
         (elapsed s, latencies us, jobs, nnz)."""
-        t_create = time.perf_counter()
         S0 = bp.Server(loaded, budget, opts)
         ids = {}
+        sub_py = {}
         i = 0
         n = len(reqs)
         done = {}
@@ -450,6 +462,7 @@ def bench_serving(args, bp, gen, torch, np):
             now = time.perf_counter() - t0
             while i < n and (arrivals is None or arrivals[i] <= now):
                 t, kind, vs, val = reqs[i]
+                sub_py[i] = time.perf_counter()
                 rid = S0.submit(t, kind, vs, val, val)
                 ids[rid] = i
                 i += 1
@@ -472,10 +485,14 @@ def bench_serving(args, bp, gen, torch, np):
                 if wait > 0:
                     time.sleep(wait)
         elapsed = time.perf_counter() - t0
+        # Latency from arrival to the server observing the last job done.
+        # The server stamps in its own clock; the submit stamp of each
+        # request maps the arrival time onto it.
         lat = []
         for j in range(n):
-            arr_us = (0.0 if arrivals is None else arrivals[j] * 1e6) + (t0 - t_create) * 1e6
-            lat.append(done[j]["done_us"] - arr_us)
+            arr_py = t0 + (0.0 if arrivals is None else arrivals[j])
+            off_us = done[j]["submit_us"] - sub_py[j] * 1e6
+            lat.append(done[j]["done_us"] - (arr_py * 1e6 + off_us))
         S0.close()
         return elapsed, np.array(lat)
 

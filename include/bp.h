@@ -79,6 +79,9 @@ extern "C" {
 #define BP_FLAG_COUNT_VARS 8u   /* count the distinct bound records each round
                                    gathers (bp_stats.vars_read); slower, for
                                    byte accounting only */
+#define BP_FLAG_BATCH_SLOTS 16u /* run bp_propagate_batch on the slot engine
+                                   (one slot per vector) whatever the batch
+                                   size; results are identical */
 
 /* A sparse matrix in compressed form: CSR (ptr over m rows, idx = column
  * indices ascending in each row) or CSC (ptr over n columns, idx = row

@@ -97,7 +97,7 @@ struct Engine {
     Shape shape;
     int64_t bytes = 0;
     DevBuf bnd, cand, vflag, rflag, info, chg, dirty, dlist, dcount, ctl, touched, filt;
-    DevBuf q[2][NBIN], hrec[2], hpart;
+    DevBuf q[2][NBIN], hrec[2], hpart, hrng;
     // captured graph of `graph_rounds` rounds for this engine's Params
     hipGraphExec_t graph = nullptr;
     int graph_rounds = 0;
@@ -108,6 +108,8 @@ struct Engine {
         if (graph) (void)hipGraphExecDestroy(graph);
     }
 };
+
+#include "bp_lv.h"
 
 struct bp_instance {
     int32_t m = 0, n = 0;
@@ -133,11 +135,13 @@ struct bp_instance {
     std::vector<int32_t> row_len;    // host copy of the row lengths (re-binning)
     DevBuf cold_hbase_d;
     std::unique_ptr<Engine> eng;
+    std::unique_ptr<LvEngine> lv;  // one-vector-per-lane batch engine
     // stats
     bp_stats stats;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     ~bp_instance() {
         eng.reset();
+        lv.reset();
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
     }
@@ -519,6 +523,7 @@ static int engine_alloc(std::unique_ptr<Engine> &eng, const Shape &sh, int32_t s
         if ((rc = E->hrec[par].alloc((size_t)S * sh.heavy_chunks * sizeof(int4), B))) return rc;
     }
     if ((rc = E->hpart.alloc((size_t)S * sh.heavy_chunks * 2 * sizeof(Acc), B))) return rc;
+    if ((rc = E->hrng.alloc((size_t)S * sh.heavy_chunks * sizeof(double), B))) return rc;
     if (count) {
         if ((rc = E->touched.alloc((size_t)S * nw_var * 4, B))) return rc;
         HIPTRY(hipMemsetAsync(E->touched.p, 0, E->touched.bytes, st));
@@ -586,6 +591,7 @@ static Params engine_params(const Engine &E, const bp_options &opt, int32_t heav
         P.hrec[par] = E.hrec[par].as<int4>();
     }
     P.hpart = E.hpart.as<Acc>();
+    P.hrng = E.hrng.as<double>();
     P.chg = E.chg.as<uint64_t>();
     P.ctl = E.ctl.as<Ctl>();
     P.touched = (opt.flags & BP_FLAG_COUNT_VARS) ? E.touched.as<uint32_t>() : nullptr;
@@ -874,6 +880,8 @@ extern "C" int bp_propagate(bp_instance *h, double *lb, double *ub, const int32_
     return res->status;
 }
 
+#include "bp_lv_run.h"
+
 extern "C" int bp_propagate_batch(bp_instance *h, int32_t B, double *lb, double *ub,
                                   const int64_t *changed_ptr, const int32_t *changed_idx,
                                   bp_result *res, void *stream) {
@@ -884,8 +892,9 @@ extern "C" int bp_propagate_batch(bp_instance *h, int32_t B, double *lb, double 
     hipStream_t st = as_stream(stream);
     bool cold = changed_ptr == nullptr;
     int64_t total = 0;
+    std::vector<int64_t> ptr;
     if (!cold) {
-        std::vector<int64_t> ptr(B + 1);
+        ptr.resize(B + 1);
         HIPTRY(hipMemcpyAsync(ptr.data(), changed_ptr, (B + 1) * 8, hipMemcpyDeviceToHost, as_stream(stream)));
         HIPTRY(hipStreamSynchronize(st));
         if (ptr[0] != 0) return fail(BP_EINVAL, "changed_ptr[0] must be 0");
@@ -893,6 +902,11 @@ extern "C" int bp_propagate_batch(bp_instance *h, int32_t B, double *lb, double 
             if (ptr[j + 1] < ptr[j]) return fail(BP_EINVAL, "changed_ptr decreases");
         total = ptr[B];
         if (total > 0 && !changed_idx) return fail(BP_EINVAL, "changed_idx is null");
+    }
+    // Batches of LV_MIN_BATCH vectors or more run one vector per lane.
+    if (B >= LV_MIN_BATCH && !(h->opt.flags & BP_FLAG_BATCH_SLOTS)) {
+        int rc = lv_propagate(h, B, lb, ub, changed_idx, changed_ptr, ptr, cold, res, st);
+        return rc < 0 ? rc : BP_OK;
     }
     int rc = propagate_slots(h, B, lb, ub, changed_idx, changed_ptr, total, cold, res, st);
     return rc < 0 ? rc : BP_OK;

@@ -121,6 +121,7 @@ struct Params {
     uint64_t *q[2][NBIN];        // task queues (slot << 32 | row)
     int4 *hrec[2];               // heavy chunks: (slot, row, chunk index, chunks of the row)
     Acc *hpart;                  // [chunks][2] partial (min, max) states
+    double *hrng;                // [chunks] partial widths (slack filter)
     uint64_t *chg;               // (slot << 32 | var) entries of the round
     Ctl *ctl;
     uint32_t *touched;           // [nslots][snw] bound records read this round
@@ -209,7 +210,43 @@ struct RowAct {
     double minfin, maxfin;
     int nmin, nmax;
     double lo, hi;
+    double rng;  // largest nonzero width of the row (slack filter)
 };
+
+// Slack filter.  The width of a nonzero bounds from above how much slack
+// its row must have before no candidate of the row can move the
+// variable's bounds: |a| times (domain + 1 + 2^-50 max|bound|), enlarged
+// by 2^-40.  With every contribution finite and slack S = side - activity
+// at least the width, the candidate of the Section 2.1 formula is, after
+// its three roundings (each below 2^-53 relative), still at least one unit
+// beyond the opposite bound: neither the threshold test nor integer
+// rounding can accept it.  An infinite bound gives an infinite width.
+__device__ __forceinline__ double nz_width(double a, double lb, double ub) {
+    double d = ub - lb;
+    d = d + 1.0;
+    d = d + fmax(fabs(lb), fabs(ub)) * 0x1p-50;
+    return (fabs(a) * d) * (1.0 + 0x1p-40);
+}
+
+// True when no candidate of the row can be taken: on each side the side is
+// infinite, at least two contributions are infinite (no candidate exists),
+// or all are finite and the slack reaches the row's width.  The slacks are
+// the same floating-point differences the candidate formula starts from.
+__device__ __forceinline__ bool row_quiet(const RowAct &R) {
+    const double INF = __builtin_inf();
+    const bool fin = R.rng < INF;
+    const bool qhi = R.hi == INF || R.nmin >= 2 || (R.nmin == 0 && fin && R.hi - R.minfin >= R.rng);
+    const bool qlo = R.lo == -INF || R.nmax >= 2 || (R.nmax == 0 && fin && R.maxfin - R.lo >= R.rng);
+    return qhi && qlo;
+}
+
+// Maximum over aligned groups of G lanes (order-free).
+template <int G>
+__device__ __forceinline__ double group_max(double x) {
+#pragma unroll
+    for (int w = 1; w < G; w <<= 1) x = fmax(x, __shfl_xor(x, w, 64));
+    return x;
+}
 
 // Bound candidates of one nonzero (Section 2.1, second display, and its
 // mirror for the lower side).  cl/cu = -inf/+inf when absent.
@@ -399,6 +436,7 @@ __device__ void light_rows(const Params &P, const uint64_t *q, uint32_t count, u
     double first_a = 0.0;
     double2 first_b = make_double2(0.0, 0.0);
     uint8_t first_t = 0;
+    double wmax = 0.0;
     const int64_t len = p1 - p0;
     const int iters = G < 64 ? 1 : (int)((len + 63) / 64);
     for (int it = 0; it < iters; ++it) {
@@ -409,6 +447,7 @@ __device__ void light_rows(const Params &P, const uint64_t *q, uint32_t count, u
             double2 b = bnd[i];
             uint8_t vt = I.vtype[i];
             add_terms(mn, mx, a, b.x, b.y);
+            wmax = fmax(wmax, nz_width(a, b.x, b.y));
             count_read(P, s, i);
             if (it == 0) {
                 first_i = i;
@@ -427,6 +466,7 @@ __device__ void light_rows(const Params &P, const uint64_t *q, uint32_t count, u
     R.hi = 0.0;
     R.nmin = mn.ninf;
     R.nmax = mx.ninf;
+    R.rng = group_max<G>(wmax);
     bool ok_min = !P.force_exact && acc_certify(mn, R.minfin);
     bool ok_max = !P.force_exact && acc_certify(mx, R.maxfin);
     if (live && gl == 0) {
@@ -442,16 +482,17 @@ __device__ void light_rows(const Params &P, const uint64_t *q, uint32_t count, u
         if (!ok_min) R.minfin = e0;
         if (!ok_max) R.maxfin = e1;
     }
-    bool bad = false;
+    bool bad = false, quiet = false;
     if (live) {
         R.lo = sd.x;
         R.hi = sd.y;
         bad = row_bad(R, P.feastol);
         if (bad && gl == 0) report_bad_row(P, s, k);
+        quiet = !bad && row_quiet(R);
     }
     for (int it = 0; it < iters; ++it) {
         int64_t p = p0 + gl + (int64_t)it * G;
-        bool has = live && !bad && p < p1;
+        bool has = live && !bad && !quiet && p < p1;
         int i = 0;
         bool need = false;
         if (has) {
@@ -483,19 +524,26 @@ __device__ void light_rows(const Params &P, const uint64_t *q, uint32_t count, u
 struct WgScratch {
     double s[2][4], c[2][4], e[2][4];
     int n[2][4];
+    double w[4];
     double act[2];
     int flag;
 };
 
-__device__ inline void wg_reduce(Acc &mn, Acc &mx, WgScratch &W) {
+// Workgroup reduction of the two accumulators and of the width maximum;
+// every lane ends with the same values.
+__device__ inline void wg_reduce(Acc &mn, Acc &mx, double &wmax, WgScratch &W) {
     acc_group_reduce<64>(mn);
     acc_group_reduce<64>(mx);
+    wmax = group_max<64>(wmax);
     const int wave = threadIdx.x >> 6;
     if (__lane_id() == 0) {
         W.s[0][wave] = mn.s; W.c[0][wave] = mn.c; W.e[0][wave] = mn.e; W.n[0][wave] = mn.ninf;
         W.s[1][wave] = mx.s; W.c[1][wave] = mx.c; W.e[1][wave] = mx.e; W.n[1][wave] = mx.ninf;
+        W.w[wave] = wmax;
     }
     __syncthreads();
+    wmax = W.w[0];
+    for (int w = 1; w < WG / 64; ++w) wmax = fmax(wmax, W.w[w]);
     // Every lane combines the four wave states in wave order.
     Acc A[2];
     for (int side = 0; side < 2; ++side) {
@@ -524,15 +572,19 @@ __device__ void block_row(const Params &P, const uint64_t *q, uint32_t t, WgScra
     Acc mn, mx;
     acc_zero(mn);
     acc_zero(mx);
+    double wmax = 0.0;
     for (int64_t p = p0 + threadIdx.x; p < p1; p += WG) {
         double2 b = bnd[I.col[p]];
-        add_terms(mn, mx, I.val[p], b.x, b.y);
+        double a = I.val[p];
+        add_terms(mn, mx, a, b.x, b.y);
+        wmax = fmax(wmax, nz_width(a, b.x, b.y));
         count_read(P, s, I.col[p]);
     }
-    wg_reduce(mn, mx, W);
+    wg_reduce(mn, mx, wmax, W);
     RowAct R;
     R.nmin = mn.ninf;
     R.nmax = mx.ninf;
+    R.rng = wmax;
     bool ok_min = !P.force_exact && acc_certify(mn, R.minfin);
     bool ok_max = !P.force_exact && acc_certify(mx, R.maxfin);
     if (!(ok_min && ok_max)) {
@@ -552,6 +604,7 @@ __device__ void block_row(const Params &P, const uint64_t *q, uint32_t t, WgScra
         if (threadIdx.x == 0) report_bad_row(P, s, k);
         return;
     }
+    if (row_quiet(R)) return;  // workgroup-uniform
     const int64_t len = p1 - p0;
     const int iters = (int)((len + WG - 1) / WG);
     for (int it = 0; it < iters; ++it) {
@@ -589,15 +642,19 @@ __device__ void heavy_chunk_activity(const Params &P, int par, uint32_t u, WgScr
     Acc mn, mx;
     acc_zero(mn);
     acc_zero(mx);
+    double wmax = 0.0;
     for (int64_t p = p0 + threadIdx.x; p < p1; p += WG) {
         double2 b = bnd[I.col[p]];
-        add_terms(mn, mx, I.val[p], b.x, b.y);
+        double a = I.val[p];
+        add_terms(mn, mx, a, b.x, b.y);
+        wmax = fmax(wmax, nz_width(a, b.x, b.y));
         count_read(P, s, I.col[p]);
     }
-    wg_reduce(mn, mx, W);
+    wg_reduce(mn, mx, wmax, W);
     if (threadIdx.x == 0) {
         P.hpart[2 * (size_t)u] = mn;
         P.hpart[2 * (size_t)u + 1] = mx;
+        P.hrng[u] = wmax;
     }
 }
 
@@ -618,10 +675,12 @@ __device__ void heavy_chunk_candidates(const Params &P, int par, uint32_t u) {
     Acc A, B;
     acc_zero(A);
     acc_zero(B);
+    double wmax = 0.0;
     for (int j = lane; j < nch; j += 64) {
         Acc a = P.hpart[2 * (size_t)(u0 + j)], b = P.hpart[2 * (size_t)(u0 + j) + 1];
         acc_merge(A, a.s, a.c, a.e, a.ninf);
         acc_merge(B, b.s, b.c, b.e, b.ninf);
+        wmax = fmax(wmax, P.hrng[u0 + j]);
     }
     acc_group_reduce<64>(A);
     acc_group_reduce<64>(B);
@@ -630,6 +689,7 @@ __device__ void heavy_chunk_candidates(const Params &P, int par, uint32_t u) {
     R.maxfin = 0.0;
     R.nmin = A.ninf;
     R.nmax = B.ninf;
+    R.rng = group_max<64>(wmax);
     R.lo = sd.x;
     R.hi = sd.y;
     bool ok_min = !P.force_exact && acc_certify(A, R.minfin);
@@ -644,6 +704,7 @@ __device__ void heavy_chunk_candidates(const Params &P, int par, uint32_t u) {
         if (c == 0 && threadIdx.x == 0) report_bad_row(P, s, k);
         return;
     }
+    if (row_quiet(R)) return;  // uniform across the workgroup
     int64_t p0 = r0 + (int64_t)c * P.heavy_chunk;
     int64_t p1 = min(r1, p0 + (int64_t)P.heavy_chunk);
     const int iters = (int)((p1 - p0 + WG - 1) / WG);
@@ -670,7 +731,10 @@ __device__ inline uint32_t light_units(uint32_t count, int b) {
 }
 
 template <bool MULTI>
-__global__ void __launch_bounds__(WG) k_rows(Params P) {
+#ifndef BP_ROWS_WAVES
+#define BP_ROWS_WAVES 4  // waves per SIMD the row kernel's register budget targets
+#endif
+__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(BP_ROWS_WAVES))) k_rows(Params P) {
     __shared__ WgScratch W;
     const Ctl *C = P.ctl;
     if (C->done) return;

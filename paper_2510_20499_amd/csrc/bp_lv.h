@@ -1,0 +1,804 @@
+// bp_lv.h -- batched propagation of many bound vectors of one instance,
+// one vector per lane (part of bp_engine.hip's translation unit; the C ABI
+// entry is bp_propagate_batch in include/bp.h).
+//
+// The rounds are those of the slot engine (Section 2.1 activities and
+// bound updates, restricted to changed constraints), with the bound vectors
+// of a batch laid side by side: the bound record of variable i in vector v
+// sits at bnd[i * V + v].  A wave serves 64 consecutive vectors (a group):
+// for a queued (row, group) task it reads each nonzero's column and
+// coefficient once, as wave-uniform values, and the 64 vectors' bound
+// records of that column as one contiguous 1 KB load.  The matrix is read
+// once per group instead of once per vector, and no bound gather touches a
+// line that holds no other vector's record.
+//
+// Worklists are 64-bit masks: rmask[par][g][k] has bit l set when vector
+// g*64+l has row k queued.  The first vector to queue (k, g) appends k to
+// the group's task list; the mask deduplicates the rest.  Rows of up to
+// LV_SHORT nonzeros are one task; longer rows are split into chunks of
+// LV_CHUNK nonzeros whose per-lane partial sums a second kernel combines.
+// Per-vector counters and evidence are accumulated in lane registers and
+// flushed once per wave, so no counter is hit by more than one atomic per
+// wave.  Arithmetic, the order-free integer atomics, the certified sums
+// and the exact fallback are those of the slot engine: a vector's result
+// is the same whichever engine runs it.
+#pragma once
+
+namespace bp {
+
+constexpr int LV_SHORT = 64;          // rows up to this length: one task
+constexpr int LV_CHUNK = 512;         // nonzeros per chunk of longer rows
+constexpr int LV_MAX_GROUPS = 128;    // batches of up to 8192 vectors
+constexpr int LV_UNROLL = 8;          // bound loads issued together
+
+struct LvVec {
+    int32_t state, status, rounds;
+    int32_t row_bad_min, row_bad_count, var_bad_min;
+    unsigned long long nnz, pending_rows, pending_nnz;
+};
+
+struct LvCtl {
+    uint32_t round, done, active, pad_;
+    uint32_t nshort[2][LV_MAX_GROUPS];  // short-row tasks per parity and group
+    uint32_t nlong[2][LV_MAX_GROUPS];   // chunk tasks per parity and group
+    uint32_t nchg[LV_MAX_GROUPS];       // variables with candidates this round
+    unsigned long long stat_rows, stat_nnz, stat_vars, stat_written;
+};
+
+struct LvParams {
+    DInst I;
+    double feastol, inttol, tau;
+    int32_t force_exact, count_vars, max_rounds;
+    int32_t B, V, NG;
+    int32_t m, n;
+    double2 *bnd;        // [n][V]
+    longlong2 *cand;     // [n][V] (lower key, upper key)
+    uint64_t *vmask;     // [NG][n] vectors with a candidate for the variable
+    uint64_t *rmask[2];  // [NG][m] vectors that have the row queued
+    int32_t *qs[2];      // [NG][m] short-row tasks
+    int2 *ql[2];         // [NG][lcap] chunk tasks (row, chunk)
+    int64_t lcap;        // chunk tasks per group and parity (every chunk of every long row)
+    Acc *lpart;          // [NG][lcap][2][64] per-lane partial (min, max) states
+    double *lrng;        // [NG][lcap][64] per-lane partial widths
+    uint64_t *lmask;     // [NG][lcap] queued vectors of the chunk's row
+    int32_t *chg;        // [NG][n] variables with candidates this round
+    uint64_t *touched;   // [NG][n] bound records read this round (counting only)
+    uint32_t *rtouch;    // [m / 32] rows read this round by any group (counting only)
+    LvVec *vec;          // [V]
+    LvCtl *ctl;
+};
+
+__device__ __forceinline__ int rl_i32(int x, int t) { return __builtin_amdgcn_readlane(x, t); }
+__device__ __forceinline__ double rl_f64(double x, int t) {
+    long long b = __double_as_longlong(x);
+    int lo = __builtin_amdgcn_readlane((int)(uint32_t)b, t);
+    int hi = __builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), t);
+    return __longlong_as_double(((long long)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Wave-local buffer of appends to one list: lane j holds the j-th pending
+// entry; 64 entries (or the end of the wave's work) cost one atomic.
+struct WaveBuf {
+    int32_t val;
+    int n;  // wave-uniform
+};
+
+__device__ __forceinline__ void wbuf_flush(WaveBuf &w, uint32_t *counter, int32_t *list) {
+    if (w.n == 0) return;
+    uint32_t base = 0;
+    if (__lane_id() == 0) base = atomicAdd(counter, (uint32_t)w.n);
+    base = __shfl(base, 0, 64);
+    if (__lane_id() < w.n) list[base + __lane_id()] = w.val;
+    w.n = 0;
+}
+
+// Append x (a wave-uniform value) to the buffer.
+__device__ __forceinline__ void wbuf_push(WaveBuf &w, int32_t x, uint32_t *counter, int32_t *list) {
+    if (__lane_id() == w.n) w.val = x;
+    w.n += 1;
+    if (w.n == 64) wbuf_flush(w, counter, list);
+}
+
+// Exact activity of one side of row [p0, p1) for the vector of this lane.
+__device__ __noinline__ double lv_exact_side(const LvParams &P, int v, int64_t p0, int64_t p1,
+                                             bool maxside) {
+    SuperAcc S;
+    sa_zero(S);
+    for (int64_t p = p0; p < p1; ++p) {
+        double a = P.I.val[p];
+        double2 b = P.bnd[(size_t)P.I.col[p] * P.V + v];
+        double bb = (a > 0.0) != maxside ? b.x : b.y;
+        if (!isinf(bb)) sa_add(S, a * bb);
+    }
+    return canon0(sa_round(S));
+}
+
+// Per-wave counts of a counting run: row tasks, their nonzeros, distinct
+// bound records read.  Flushed once per wave.
+struct LvCount {
+    unsigned long long rows, nnz, vars;
+};
+
+__device__ __forceinline__ void lv_count_read(const LvParams &P, int g, int i, uint64_t live,
+                                              LvCount &K) {
+    if (!P.count_vars || live == 0) return;
+    uint64_t old = 0;
+    if (__lane_id() == 0) old = atomicOr((unsigned long long *)&P.touched[(size_t)g * P.n + i], live);
+    old = __shfl(old, 0, 64);
+    K.vars += (unsigned long long)__popcll(live & ~old);
+}
+
+// The matrix term counts a row once per round over all groups (the row is
+// shared by the whole batch).
+__device__ __forceinline__ void lv_count_row(const LvParams &P, int k, int64_t len, LvCount &K) {
+    if (!P.count_vars) return;
+    uint32_t old = 0;
+    if (__lane_id() == 0) old = atomicOr(&P.rtouch[k >> 5], 1u << (k & 31));
+    old = __shfl(old, 0, 64);
+    if (!((old >> (k & 31)) & 1u)) {
+        K.rows += 1;
+        K.nnz += (unsigned long long)len;
+    }
+}
+
+__device__ __forceinline__ void lv_count_flush(const LvParams &P, const LvCount &K) {
+    if (!P.count_vars || __lane_id() != 0) return;
+    if (K.rows) atomicAdd(&P.ctl->stat_rows, K.rows);
+    if (K.nnz) atomicAdd(&P.ctl->stat_nnz, K.nnz);
+    if (K.vars) atomicAdd(&P.ctl->stat_vars, K.vars);
+}
+
+// Activity over nonzeros [q0, q1) of a row (at most 64 per block), for the
+// lanes in `live`.  Columns and coefficients are loaded once per block,
+// one per lane, and broadcast; bound records are loaded LV_UNROLL at a time.
+__device__ __forceinline__ void lv_accumulate(const LvParams &P, int g, int v, bool live,
+                                              uint64_t livemask, int64_t q0, int64_t q1, Acc &mn,
+                                              Acc &mx, double &wmax, LvCount &K) {
+    for (int64_t b0 = q0; b0 < q1; b0 += 64) {
+        const int len = (int)min((int64_t)64, q1 - b0);
+        int cj = 0;
+        double aj = 0.0;
+        if (__lane_id() < len) {
+            cj = P.I.col[b0 + __lane_id()];
+            aj = P.I.val[b0 + __lane_id()];
+        }
+        for (int t0 = 0; t0 < len; t0 += LV_UNROLL) {
+            double2 b[LV_UNROLL];
+#pragma unroll
+            for (int u = 0; u < LV_UNROLL; ++u) {
+                b[u] = make_double2(0.0, 0.0);
+                if (t0 + u < len && live) b[u] = P.bnd[(size_t)rl_i32(cj, t0 + u) * P.V + v];
+            }
+#pragma unroll
+            for (int u = 0; u < LV_UNROLL; ++u) {
+                if (t0 + u < len) {
+                    double a = rl_f64(aj, t0 + u);
+                    if (live) {
+                        add_terms(mn, mx, a, b[u].x, b[u].y);
+                        wmax = fmax(wmax, nz_width(a, b[u].x, b[u].y));
+                    }
+                    lv_count_read(P, g, rl_i32(cj, t0 + u), livemask, K);
+                }
+            }
+        }
+    }
+}
+
+// Candidates of nonzeros [q0, q1) for the lanes in `want`; variables that
+// receive a significant candidate are marked in vmask and listed.
+__device__ __forceinline__ void lv_candidates(const LvParams &P, int g, int v, bool want,
+                                              const RowAct &R, int64_t q0, int64_t q1, WaveBuf &wb) {
+    if (__ballot(want) == 0) return;
+    for (int64_t b0 = q0; b0 < q1; b0 += 64) {
+        const int len = (int)min((int64_t)64, q1 - b0);
+        int cj = 0;
+        double aj = 0.0;
+        if (__lane_id() < len) {
+            cj = P.I.col[b0 + __lane_id()];
+            aj = P.I.val[b0 + __lane_id()];
+        }
+        for (int t0 = 0; t0 < len; t0 += LV_UNROLL) {
+            double2 b[LV_UNROLL];
+#pragma unroll
+            for (int u = 0; u < LV_UNROLL; ++u) {
+                b[u] = make_double2(0.0, 0.0);
+                if (t0 + u < len && want) b[u] = P.bnd[(size_t)rl_i32(cj, t0 + u) * P.V + v];
+            }
+#pragma unroll
+            for (int u = 0; u < LV_UNROLL; ++u) {
+                if (t0 + u < len) {
+                    const int i = rl_i32(cj, t0 + u);
+                    const double a = rl_f64(aj, t0 + u);
+                    bool pass = false;
+                    if (want) {
+                        const bool is_int = P.I.vtype[i] != 0;
+                        double cl, cu;
+                        nz_candidates(R, a, b[u].x, b[u].y, is_int, P.inttol, cl, cu);
+                        longlong2 *cp = &P.cand[(size_t)i * P.V + v];
+                        if (take_lower(is_int, cl, b[u].x, P.tau)) {
+                            atomicMax(&cp->x, dkey(canon0(cl)));
+                            pass = true;
+                        }
+                        if (take_upper(is_int, cu, b[u].y, P.tau)) {
+                            atomicMin(&cp->y, dkey(canon0(cu)));
+                            pass = true;
+                        }
+                    }
+                    const uint64_t pm = __ballot(pass);
+                    if (pm) {
+                        uint64_t old = 0;
+                        if (__lane_id() == 0)
+                            old = atomicOr((unsigned long long *)&P.vmask[(size_t)g * P.n + i], pm);
+                        old = __shfl(old, 0, 64);
+                        if (old == 0) wbuf_push(wb, i, &P.ctl->nchg[g], P.chg + (size_t)g * P.n);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Certified activities of the lane's vector, with the exact fallback.
+__device__ __forceinline__ void lv_finish_act(const LvParams &P, int v, bool live, Acc &mn, Acc &mx,
+                                              int64_t p0, int64_t p1, RowAct &R) {
+    R.nmin = mn.ninf;
+    R.nmax = mx.ninf;
+    R.minfin = 0.0;
+    R.maxfin = 0.0;
+    bool ok_min = live && !P.force_exact && acc_certify(mn, R.minfin);
+    bool ok_max = live && !P.force_exact && acc_certify(mx, R.maxfin);
+    if (live && !ok_min) R.minfin = lv_exact_side(P, v, p0, p1, false);
+    if (live && !ok_max) R.maxfin = lv_exact_side(P, v, p0, p1, true);
+}
+
+// One short row for the 64 vectors of group g: activity, row test and
+// candidates in one task.
+__device__ void lv_short_row(const LvParams &P, int par, int g, int v, bool active, int k,
+                             int &bad_min, int &bad_cnt, WaveBuf &wb, LvCount &K) {
+    uint64_t *mp = &P.rmask[par][(size_t)g * P.m + k];
+    const uint64_t word = *mp;
+    const uint64_t livemask = word & __ballot(active);
+    const bool live = (livemask >> __lane_id()) & 1ull;
+    const int64_t p0 = P.I.row_ptr[k], p1 = P.I.row_ptr[k + 1];
+    const double2 sd = P.I.side[k];
+    if (__lane_id() == 0) *mp = 0ull;  // the word is queued again only by a later round
+    lv_count_row(P, k, p1 - p0, K);
+    Acc mn, mx;
+    acc_zero(mn);
+    acc_zero(mx);
+    double wmax = 0.0;
+    lv_accumulate(P, g, v, live, livemask, p0, p1, mn, mx, wmax, K);
+    RowAct R;
+    lv_finish_act(P, v, live, mn, mx, p0, p1, R);
+    R.lo = sd.x;
+    R.hi = sd.y;
+    R.rng = wmax;
+    bool bad = false;
+    if (live) {
+        bad = row_bad(R, P.feastol);
+        if (bad) {
+            bad_min = min(bad_min, k);
+            bad_cnt += 1;
+        }
+    }
+    const bool want = live && !bad && !row_quiet(R);
+    lv_candidates(P, g, v, want, R, p0, p1, wb);
+}
+
+// Chunk c of a long row: per-lane partial states.
+__device__ void lv_chunk_activity(const LvParams &P, int par, int g, int v, bool active, uint32_t u,
+                                  LvCount &K) {
+    const int2 rec = P.ql[par][(size_t)g * P.lcap + u];
+    const int k = rec.x, c = rec.y;
+    const uint64_t livemask = P.rmask[par][(size_t)g * P.m + k] & __ballot(active);
+    const bool live = (livemask >> __lane_id()) & 1ull;
+    const int64_t r0 = P.I.row_ptr[k], r1 = P.I.row_ptr[k + 1];
+    const int64_t q0 = r0 + (int64_t)c * LV_CHUNK, q1 = min(r1, q0 + (int64_t)LV_CHUNK);
+    if (__lane_id() == 0) P.lmask[(size_t)g * P.lcap + u] = livemask;
+    if (c == 0) lv_count_row(P, k, r1 - r0, K);
+    Acc mn, mx;
+    acc_zero(mn);
+    acc_zero(mx);
+    double wmax = 0.0;
+    lv_accumulate(P, g, v, live, livemask, q0, q1, mn, mx, wmax, K);
+    const size_t base = ((size_t)g * P.lcap + u) * 128;
+    P.lpart[base + __lane_id()] = mn;
+    P.lpart[base + 64 + __lane_id()] = mx;
+    P.lrng[((size_t)g * P.lcap + u) * 64 + __lane_id()] = wmax;
+}
+
+// Row kernel: chunk partials of long rows, then short rows.  Grid (x, NG).
+__global__ void __launch_bounds__(WG) k_lv_rows(LvParams P) {
+    LvCtl *C = P.ctl;
+    if (C->done) return;
+    const int par = C->round & 1;
+    const int g = blockIdx.y;
+    const int v = g * 64 + __lane_id();
+    const bool active = P.vec[v].state == SLOT_ACTIVE;
+    const uint32_t nw = gridDim.x * (WG / 64);
+    const uint32_t w = blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
+    const uint32_t nl = C->nlong[par][g], ns = C->nshort[par][g];
+    int bad_min = NONE, bad_cnt = 0;
+    WaveBuf wb;
+    wb.val = 0;
+    wb.n = 0;
+    LvCount K = {0ull, 0ull, 0ull};
+    for (uint32_t t = w; t < nl + ns; t += nw) {
+        if (t < nl) lv_chunk_activity(P, par, g, v, active, t, K);
+        else lv_short_row(P, par, g, v, active, P.qs[par][(size_t)g * P.m + (t - nl)], bad_min, bad_cnt, wb, K);
+    }
+    wbuf_flush(wb, &C->nchg[g], P.chg + (size_t)g * P.n);
+    lv_count_flush(P, K);
+    if (bad_cnt) {
+        atomicMin(&P.vec[v].row_bad_min, bad_min);
+        atomicAdd(&P.vec[v].row_bad_count, bad_cnt);
+    }
+}
+
+// Long rows: each chunk task combines the row's partials (lane-wise, in
+// chunk order), tests the row and computes the chunk's candidates.
+__global__ void __launch_bounds__(WG) k_lv_heavy(LvParams P) {
+    LvCtl *C = P.ctl;
+    if (C->done) return;
+    const int par = C->round & 1;
+    const int g = blockIdx.y;
+    const int v = g * 64 + __lane_id();
+    const bool active = P.vec[v].state == SLOT_ACTIVE;
+    const uint32_t nw = gridDim.x * (WG / 64);
+    const uint32_t w = blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
+    const uint32_t nl = C->nlong[par][g];
+    int bad_min = NONE, bad_cnt = 0;
+    WaveBuf wb;
+    wb.val = 0;
+    wb.n = 0;
+    for (uint32_t u = w; u < nl; u += nw) {
+        const int2 rec = P.ql[par][(size_t)g * P.lcap + u];
+        const int k = rec.x, c = rec.y;
+        const uint64_t livemask = P.lmask[(size_t)g * P.lcap + u];
+        const bool live = ((livemask >> __lane_id()) & 1ull) && active;
+        const int64_t r0 = P.I.row_ptr[k], r1 = P.I.row_ptr[k + 1];
+        const int nch = (int)((r1 - r0 + LV_CHUNK - 1) / LV_CHUNK);
+        const uint32_t u0 = u - (uint32_t)c;
+        if (c == 0 && __lane_id() == 0) P.rmask[par][(size_t)g * P.m + k] = 0ull;
+        Acc A, Bm;
+        acc_zero(A);
+        acc_zero(Bm);
+        double wmax = 0.0;
+        for (int j = 0; j < nch; ++j) {
+            const size_t base = ((size_t)g * P.lcap + u0 + j) * 128;
+            Acc a = P.lpart[base + __lane_id()], b = P.lpart[base + 64 + __lane_id()];
+            acc_merge(A, a.s, a.c, a.e, a.ninf);
+            acc_merge(Bm, b.s, b.c, b.e, b.ninf);
+            wmax = fmax(wmax, P.lrng[((size_t)g * P.lcap + u0 + j) * 64 + __lane_id()]);
+        }
+        RowAct R;
+        lv_finish_act(P, v, live, A, Bm, r0, r1, R);
+        const double2 sd = P.I.side[k];
+        R.lo = sd.x;
+        R.hi = sd.y;
+        R.rng = wmax;
+        bool bad = false;
+        if (live) {
+            bad = row_bad(R, P.feastol);
+            if (bad && c == 0) {
+                bad_min = min(bad_min, k);
+                bad_cnt += 1;
+            }
+        }
+        const bool want = live && !bad && !row_quiet(R);
+        const int64_t q0 = r0 + (int64_t)c * LV_CHUNK, q1 = min(r1, q0 + (int64_t)LV_CHUNK);
+        lv_candidates(P, g, v, want, R, q0, q1, wb);
+    }
+    wbuf_flush(wb, &C->nchg[g], P.chg + (size_t)g * P.n);
+    if (bad_cnt) {
+        atomicMin(&P.vec[v].row_bad_min, bad_min);
+        atomicAdd(&P.vec[v].row_bad_count, bad_cnt);
+    }
+}
+
+// Bound updates of the round's candidates, and the rows of every changed
+// variable queued for the next round.  With seed = 1 (before the first
+// round) the listed variables count as changed for the vectors in their
+// masks and their rows go to the first round's queues.  Grid (x, NG).
+__global__ void __launch_bounds__(WG) k_lv_apply(LvParams P, int seed) {
+    LvCtl *C = P.ctl;
+    if (!seed && C->done) return;
+    const int tgt = seed ? 0 : ((C->round & 1) ^ 1);
+    const int g = blockIdx.y;
+    const int lane = __lane_id();
+    const int v = g * 64 + lane;
+    const double INF = __builtin_inf();
+    const LvVec &Vv = P.vec[v];
+    const bool active = Vv.state == SLOT_ACTIVE && (seed || Vv.row_bad_count == 0);
+    const uint32_t nw = gridDim.x * (WG / 64);
+    const uint32_t w = blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
+    const uint32_t total = C->nchg[g];
+    unsigned long long my_rows = 0, my_nnz = 0;
+    int var_bad = NONE;
+    uint32_t written = 0;
+    for (uint32_t e = w; e < total; e += nw) {
+        const int i = P.chg[(size_t)g * P.n + e];
+        uint64_t *vm = &P.vmask[(size_t)g * P.n + i];
+        const uint64_t mask = *vm;
+        const bool mine = (mask >> lane) & 1ull;
+        bool go = false;
+        if (seed) {
+            go = mine && active;
+        } else {
+            longlong2 *cp = &P.cand[(size_t)i * P.V + v];
+            long long kl = 0, ku = 0;
+            if (mine) {
+                kl = cp->x;
+                ku = cp->y;
+                *cp = make_longlong2(dkey(-INF), dkey(INF));
+            }
+            if (mine && active) {
+                double2 *bp = &P.bnd[(size_t)i * P.V + v];
+                const double2 b = *bp;
+                const bool is_int = P.I.vtype[i] != 0;
+                const double L = dunkey(kl), U = dunkey(ku);
+                double nl = b.x, nu = b.y;
+                bool ch = false;
+                if (take_upper(is_int, U, b.y, P.tau)) { nu = canon0(U); ch = true; }
+                if (take_lower(is_int, L, b.x, P.tau)) { nl = canon0(L); ch = true; }
+                if (ch && nl > nu) {
+                    if (is_int || nl - nu > P.feastol) var_bad = min(var_bad, i);
+                    else nl = nu;
+                }
+                if (ch) {
+                    *bp = make_double2(nl, nu);
+                    go = true;
+                }
+            }
+        }
+        if (lane == 0) *vm = 0ull;
+        const uint64_t gm = __ballot(go);
+        written += __popcll(gm);
+        if (gm == 0) continue;
+        const int64_t c0 = P.I.col_ptr[i], c1 = P.I.col_ptr[i + 1];
+        for (int64_t j0 = c0; j0 < c1; j0 += 64) {
+            const int64_t j = j0 + lane;
+            const bool has = j < c1;
+            int k = 0;
+            int64_t len = 0;
+            uint64_t newb = 0;
+            bool first = false;
+            if (has) {
+                k = P.I.col_row[j];
+                len = P.I.row_ptr[k + 1] - P.I.row_ptr[k];
+                const uint64_t old =
+                    atomicOr((unsigned long long *)&P.rmask[tgt][(size_t)g * P.m + k], gm);
+                newb = gm & ~old;
+                first = old == 0;
+            }
+            // queue (k, g) once: short rows as one task, long rows as chunks
+            const bool qshort = first && len <= LV_SHORT;
+            const uint64_t sm = __ballot(qshort);
+            if (sm) {
+                const int leader = __ffsll((long long)sm) - 1;
+                uint32_t base = 0;
+                if (lane == leader) base = atomicAdd(&C->nshort[tgt][g], (uint32_t)__popcll(sm));
+                base = __shfl(base, leader, 64);
+                if (qshort) P.qs[tgt][(size_t)g * P.m + base + lane_rank(sm)] = k;
+            }
+            if (first && len > LV_SHORT) {
+                const int nch = (int)((len + LV_CHUNK - 1) / LV_CHUNK);
+                uint32_t base = atomicAdd(&C->nlong[tgt][g], (uint32_t)nch);
+                for (int c = 0; c < nch; ++c) P.ql[tgt][(size_t)g * P.lcap + base + c] = make_int2(k, c);
+            }
+            // per-vector counts of the newly queued rows
+            uint64_t any = __ballot(newb != 0);
+            while (any) {
+                const int t = __ffsll((long long)any) - 1;
+                any &= any - 1;
+                const uint64_t nb = (uint64_t)rl_i32((int)(uint32_t)newb, t) |
+                                    ((uint64_t)(uint32_t)rl_i32((int)(uint32_t)(newb >> 32), t) << 32);
+                const int lt = rl_i32((int)len, t);
+                if ((nb >> lane) & 1ull) {
+                    my_rows += 1;
+                    my_nnz += (unsigned long long)lt;
+                }
+            }
+        }
+    }
+    if (my_rows) {
+        atomicAdd(&P.vec[v].pending_rows, my_rows);
+        atomicAdd(&P.vec[v].pending_nnz, my_nnz);
+    }
+    if (var_bad != NONE) atomicMin(&P.vec[v].var_bad_min, var_bad);
+    if (lane == 0 && written && !seed) atomicAdd(&C->stat_written, (unsigned long long)written);
+}
+
+// Round end for every vector (one workgroup).
+__global__ void __launch_bounds__(WG) k_lv_end(LvParams P) {
+    LvCtl *C = P.ctl;
+    if (C->done) return;
+    const int par = C->round & 1;
+    __shared__ uint32_t s_active;
+    if (threadIdx.x == 0) s_active = 0;
+    __syncthreads();
+    for (int v = threadIdx.x; v < P.V; v += WG) {
+        LvVec &S = P.vec[v];
+        if (S.state != SLOT_ACTIVE) continue;
+        bool fin = true;
+        if (S.row_bad_count > 0 || S.var_bad_min != NONE) {
+            S.status = 1;
+        } else if (S.pending_rows == 0) {
+            S.status = 0;
+        } else if ((uint32_t)S.rounds >= (uint32_t)P.max_rounds) {
+            S.status = 2;
+        } else {
+            fin = false;
+            S.rounds += 1;
+            S.nnz += S.pending_nnz;
+            if (!P.count_vars) {  // counting runs count the tasks themselves
+                atomicAdd(&C->stat_rows, S.pending_rows);
+                atomicAdd(&C->stat_nnz, S.pending_nnz);
+            }
+            S.pending_rows = 0;
+            S.pending_nnz = 0;
+            atomicAdd(&s_active, 1u);
+        }
+        if (fin) S.state = SLOT_FREE;
+    }
+    if (P.count_vars) {
+        size_t words = (size_t)P.NG * P.n;
+        for (size_t t = threadIdx.x; t < words; t += WG) P.touched[t] = 0ull;
+        for (size_t t = threadIdx.x; t < (size_t)(P.m + 31) / 32; t += WG) P.rtouch[t] = 0u;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int g = 0; g < P.NG; ++g) {
+            C->nshort[par][g] = 0;
+            C->nlong[par][g] = 0;
+            C->nchg[g] = 0;
+        }
+        C->active = s_active;
+        C->round = C->round + 1;
+        if (s_active == 0) C->done = 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Set-up kernels
+// ---------------------------------------------------------------------------
+
+// Bounds in: [B][n] row-major vectors to the [n][V] layout through a
+// 64 x 64 LDS tile; crossed and NaN boxes per vector.
+__global__ void __launch_bounds__(WG) k_lv_pack(const double *lb, const double *ub, double2 *bnd,
+                                                int32_t n, int32_t B, int32_t V, const uint8_t *vtype,
+                                                double feastol, int32_t *box) {
+    __shared__ double2 tile[64][65];
+    const int64_t tiles_i = (n + 63) / 64;
+    const int ngv = V / 64;
+    for (int64_t t = blockIdx.x; t < tiles_i * ngv; t += gridDim.x) {
+        const int64_t i0 = (t / ngv) * 64;
+        const int v0 = (int)(t % ngv) * 64;
+        // read: 4 waves, each lane one variable, rows of vectors
+        for (int r = threadIdx.x >> 6; r < 64; r += WG / 64) {
+            const int v = v0 + r;
+            const int64_t i = i0 + __lane_id();
+            double2 b = make_double2(0.0, 0.0);
+            if (v < B && i < n) {
+                b = make_double2(canon0(lb[(size_t)v * n + i]), canon0(ub[(size_t)v * n + i]));
+                if (isnan(b.x) || isnan(b.y)) atomicOr(&box[2 * v + 1], 1);
+                const double slack = vtype[i] ? 0.0 : feastol;
+                if (b.x > b.y + slack) atomicMin(&box[2 * v], (int32_t)i);
+            }
+            tile[r][__lane_id()] = b;
+        }
+        __syncthreads();
+        for (int c = threadIdx.x >> 6; c < 64; c += WG / 64) {
+            const int64_t i = i0 + c;
+            if (i < n) bnd[(size_t)i * V + v0 + __lane_id()] = tile[__lane_id()][c];
+        }
+        __syncthreads();
+    }
+}
+
+// Bounds out: [n][V] back to [B][n].
+__global__ void __launch_bounds__(WG) k_lv_unpack(const double2 *bnd, double *lb, double *ub,
+                                                  int32_t n, int32_t B, int32_t V) {
+    __shared__ double2 tile[64][65];
+    const int64_t tiles_i = (n + 63) / 64;
+    const int ngv = V / 64;
+    for (int64_t t = blockIdx.x; t < tiles_i * ngv; t += gridDim.x) {
+        const int64_t i0 = (t / ngv) * 64;
+        const int v0 = (int)(t % ngv) * 64;
+        for (int c = threadIdx.x >> 6; c < 64; c += WG / 64) {
+            const int64_t i = i0 + c;
+            tile[__lane_id()][c] = i < n ? bnd[(size_t)i * V + v0 + __lane_id()] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        for (int r = threadIdx.x >> 6; r < 64; r += WG / 64) {
+            const int v = v0 + r;
+            const int64_t i = i0 + __lane_id();
+            if (v < B && i < n) {
+                const double2 b = tile[r][__lane_id()];
+                lb[(size_t)v * n + i] = b.x;
+                ub[(size_t)v * n + i] = b.y;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_lv_fill_cand(longlong2 *c, size_t N) {
+    const double INF = __builtin_inf();
+    for (size_t j = blockIdx.x * (size_t)blockDim.x + threadIdx.x; j < N; j += (size_t)gridDim.x * blockDim.x)
+        c[j] = make_longlong2(dkey(-INF), dkey(INF));
+}
+
+__global__ void k_lv_fill_u64(uint64_t *p, size_t N) {
+    for (size_t j = blockIdx.x * (size_t)blockDim.x + threadIdx.x; j < N; j += (size_t)gridDim.x * blockDim.x)
+        p[j] = 0ull;
+}
+
+// Vectors: active unless their box is crossed (box[2v] != NONE).
+__global__ void k_lv_reset(LvParams P, const int32_t *box) {
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < P.V; v += gridDim.x * blockDim.x) {
+        LvVec &S = P.vec[v];
+        S.state = (v < P.B && box[2 * v] == NONE) ? SLOT_ACTIVE : SLOT_FREE;
+        S.status = 0;
+        S.rounds = 0;
+        S.row_bad_min = NONE;
+        S.row_bad_count = 0;
+        S.var_bad_min = NONE;
+        S.nnz = 0;
+        S.pending_rows = 0;
+        S.pending_nnz = 0;
+    }
+}
+
+// Cold start: every row queued for every active vector.  short_rows and
+// long_chunks list the instance's rows by class (long rows as (row, chunk)).
+__global__ void k_lv_seed_cold(LvParams P, const int32_t *short_rows, int64_t nshort,
+                               const int2 *long_chunks, int64_t nlong) {
+    const int g = blockIdx.y;
+    uint64_t lanes = 0;
+    for (int l = 0; l < 64; ++l)
+        if (P.vec[g * 64 + l].state == SLOT_ACTIVE) lanes |= 1ull << l;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nshort; j += (int64_t)gridDim.x * blockDim.x) {
+        const int k = short_rows[j];
+        P.qs[0][(size_t)g * P.m + j] = k;
+        P.rmask[0][(size_t)g * P.m + k] = lanes;
+    }
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nlong; j += (int64_t)gridDim.x * blockDim.x) {
+        const int2 r = long_chunks[j];
+        P.ql[0][(size_t)g * P.lcap + j] = r;
+        if (r.y == 0) P.rmask[0][(size_t)g * P.m + r.x] = lanes;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        P.ctl->nshort[0][g] = (uint32_t)(lanes ? nshort : 0);
+        P.ctl->nlong[0][g] = (uint32_t)(lanes ? nlong : 0);
+    }
+}
+
+// Warm start: the listed variables of every vector (entries of
+// changed_idx, vector v owning [ptr[v], ptr[v+1])) are marked in vmask and
+// listed once per group; k_lv_apply with seed = 1 then queues their rows.
+__global__ void k_lv_seed_vars(LvParams P, const int32_t *vars, const int64_t *ptr, int64_t e0,
+                               int64_t total) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += stride) {
+        const int64_t e = e0 + base + threadIdx.x;  // entry of vars; ptr is absolute
+        const bool has = base + threadIdx.x < total;
+        int v = 0, i = 0;
+        bool first = false;
+        if (has) {
+            int lo = 0, hi = P.B;
+            while (hi - lo > 1) {
+                int mid = (lo + hi) / 2;
+                if (ptr[mid] <= e) lo = mid;
+                else hi = mid;
+            }
+            v = lo;
+            i = vars[e];
+            if (P.vec[v].state == SLOT_ACTIVE) {
+                const uint64_t bit = 1ull << (v & 63);
+                const uint64_t old = atomicOr((unsigned long long *)&P.vmask[(size_t)(v >> 6) * P.n + i], bit);
+                first = old == 0;
+            }
+        }
+        // one atomic per wave when the wave's new entries share a group
+        const int g = v >> 6;
+        const uint64_t fm = __ballot(first);
+        if (fm) {
+            const int leader = __ffsll((long long)fm) - 1;
+            const int g0 = __shfl(g, leader, 64);
+            if (__ballot(first && g != g0) == 0) {
+                uint32_t b = 0;
+                if (__lane_id() == leader) b = atomicAdd(&P.ctl->nchg[g0], (uint32_t)__popcll(fm));
+                b = __shfl(b, leader, 64);
+                if (first) P.chg[(size_t)g0 * P.n + b + lane_rank(fm)] = i;
+            } else if (first) {
+                uint32_t slot = atomicAdd(&P.ctl->nchg[g], 1u);
+                P.chg[(size_t)g * P.n + slot] = i;
+            }
+        }
+    }
+}
+
+// After seeding: first-round counters of every vector.
+__global__ void k_lv_seed_finish(LvParams P, int cold, long long nnz) {
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < P.V; v += gridDim.x * blockDim.x) {
+        LvVec &S = P.vec[v];
+        if (S.state != SLOT_ACTIVE) continue;
+        if (cold) {
+            S.pending_rows = (unsigned long long)P.m;
+            S.pending_nnz = (unsigned long long)nnz;
+        }
+        if (S.pending_rows == 0) {
+            S.state = SLOT_FREE;
+            S.status = 0;
+        } else if (P.max_rounds <= 0) {
+            S.state = SLOT_FREE;
+            S.status = 2;
+        } else {
+            S.rounds = 1;
+            S.nnz = S.pending_nnz;
+            if (!P.count_vars) {
+                atomicAdd(&P.ctl->stat_rows, S.pending_rows);
+                atomicAdd(&P.ctl->stat_nnz, S.pending_nnz);
+            }
+            S.pending_rows = 0;
+            S.pending_nnz = 0;
+        }
+    }
+}
+
+// After seeding: clear the variable lists, set the done flag.
+__global__ void k_lv_start(LvParams P) {
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    for (int v = threadIdx.x; v < P.V; v += blockDim.x)
+        if (P.vec[v].state == SLOT_ACTIVE) atomicOr(&any, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int g = 0; g < P.NG; ++g) P.ctl->nchg[g] = 0;
+        P.ctl->done = any ? 0u : 1u;
+        P.ctl->active = any ? 1u : 0u;
+    }
+}
+
+// After the last round: rows queued for a round that never ran leave their
+// mask words set; clear them so the masks start empty next time.
+__global__ void k_lv_cleanup(LvParams P) {
+    const int par = P.ctl->round & 1;
+    const int g = blockIdx.y;
+    const uint32_t ns = P.ctl->nshort[par][g], nl = P.ctl->nlong[par][g];
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ns + nl; t += gridDim.x * blockDim.x) {
+        const int k = t < ns ? P.qs[par][(size_t)g * P.m + t] : P.ql[par][(size_t)g * P.lcap + (t - ns)].x;
+        P.rmask[par][(size_t)g * P.m + k] = 0ull;
+    }
+}
+
+__global__ void k_lv_cleanup_counts(LvParams P) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        for (int p = 0; p < 2; ++p)
+            for (int g = 0; g < P.NG; ++g) {
+                P.ctl->nshort[p][g] = 0;
+                P.ctl->nlong[p][g] = 0;
+            }
+        for (int g = 0; g < P.NG; ++g) P.ctl->nchg[g] = 0;
+    }
+}
+
+}  // namespace bp
+
+// Device buffers of the one-vector-per-lane engine (sized for V lanes; a
+// call with fewer vectors uses the same buffers with a smaller stride).
+struct LvEngine {
+    int32_t Vcap = 0;
+    int64_t lcap = 0, nshort = 0, nlong = 0;
+    bool have_touched = false;
+    DevBuf bnd, cand, vmask, rmask[2], qs[2], ql[2], lpart, lrng, lmask, chg, touched, rtouch, vec, ctl, box;
+    DevBuf short_rows, long_chunks;  // cold-start tasks of the instance
+    hipGraphExec_t graph = nullptr;
+    int graph_rounds = 0;
+    bp::LvParams graph_params;
+    ~LvEngine() {
+        if (graph) (void)hipGraphExecDestroy(graph);
+    }
+};

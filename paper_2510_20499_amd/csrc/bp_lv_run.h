@@ -1,0 +1,298 @@
+// bp_lv_run.h -- host driver of the one-vector-per-lane batch engine (part
+// of bp_engine.hip's translation unit; see bp_lv.h for the kernels).
+#pragma once
+
+static const int LV_GRID_ROWS = 2048;   // workgroups per round kernel, over all groups
+static const int LV_MIN_BATCH = 16;     // smaller batches run on the slot engine
+
+// Cold-start task tables of the instance: short rows, and (row, chunk) of
+// the long rows.  They set the chunk-task capacity of a group.
+static int lv_tables(bp_instance *h, LvEngine &L, hipStream_t st) {
+    std::vector<int32_t> sr;
+    std::vector<int2> lc;
+    for (int64_t k = 0; k < h->m; ++k) {
+        const int64_t len = h->row_len[k];
+        if (len <= LV_SHORT) {
+            sr.push_back((int32_t)k);
+        } else {
+            const int64_t nch = (len + LV_CHUNK - 1) / LV_CHUNK;
+            for (int64_t c = 0; c < nch; ++c) lc.push_back(make_int2((int)k, (int)c));
+        }
+    }
+    L.nshort = (int64_t)sr.size();
+    L.nlong = (int64_t)lc.size();
+    L.lcap = std::max<int64_t>(L.nlong, 1);
+    int rc;
+    if ((rc = L.short_rows.alloc(sr.size() * 4, h->bytes))) return rc;
+    if ((rc = L.long_chunks.alloc(lc.size() * sizeof(int2), h->bytes))) return rc;
+    if (!sr.empty()) HIPTRY(hipMemcpyAsync(L.short_rows.p, sr.data(), sr.size() * 4, hipMemcpyHostToDevice, st));
+    if (!lc.empty())
+        HIPTRY(hipMemcpyAsync(L.long_chunks.p, lc.data(), lc.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+    HIPTRY(hipStreamSynchronize(st));
+    return 0;
+}
+
+// Buffers for V lanes (grow only).  The candidate keys are filled with
+// (-inf, +inf) and every mask with zero once; each call leaves them so.
+static int lv_ensure(bp_instance *h, int32_t V, bool count, hipStream_t st) {
+    if (!h->lv) {
+        h->lv.reset(new LvEngine());
+        if (int rc = lv_tables(h, *h->lv, st)) return rc;
+    }
+    LvEngine &L = *h->lv;
+    const int64_t n = std::max<int32_t>(h->n, 1), m = std::max<int32_t>(h->m, 1);
+    int64_t &B = h->bytes;
+    int rc;
+    if (L.Vcap < V) {
+        if (L.graph) {
+            (void)hipGraphExecDestroy(L.graph);
+            L.graph = nullptr;
+        }
+        const int64_t NG = V / 64;
+        if ((rc = L.bnd.alloc((size_t)n * V * 16, B))) return rc;
+        if ((rc = L.cand.alloc((size_t)n * V * 16, B))) return rc;
+        if ((rc = L.vmask.alloc((size_t)NG * n * 8, B))) return rc;
+        for (int p = 0; p < 2; ++p) {
+            if ((rc = L.rmask[p].alloc((size_t)NG * m * 8, B))) return rc;
+            if ((rc = L.qs[p].alloc((size_t)NG * m * 4, B))) return rc;
+            if ((rc = L.ql[p].alloc((size_t)NG * L.lcap * sizeof(int2), B))) return rc;
+        }
+        if ((rc = L.lpart.alloc((size_t)NG * L.lcap * 128 * sizeof(Acc), B))) return rc;
+        if ((rc = L.lrng.alloc((size_t)NG * L.lcap * 64 * 8, B))) return rc;
+        if ((rc = L.lmask.alloc((size_t)NG * L.lcap * 8, B))) return rc;
+        if ((rc = L.chg.alloc((size_t)NG * n * 4, B))) return rc;
+        if ((rc = L.vec.alloc((size_t)V * sizeof(LvVec), B))) return rc;
+        if ((rc = L.box.alloc((size_t)V * 8, B))) return rc;
+        if (!L.ctl.p && (rc = L.ctl.alloc(sizeof(LvCtl), B))) return rc;
+        k_lv_fill_cand<<<4096, 256, 0, st>>>(L.cand.as<longlong2>(), (size_t)n * V);
+        k_lv_fill_u64<<<4096, 256, 0, st>>>(L.vmask.as<uint64_t>(), (size_t)NG * n);
+        for (int p = 0; p < 2; ++p) k_lv_fill_u64<<<4096, 256, 0, st>>>(L.rmask[p].as<uint64_t>(), (size_t)NG * m);
+        HIPTRY(hipGetLastError());
+        L.Vcap = V;
+        L.have_touched = false;
+    }
+    if (count && !L.have_touched) {
+        const int64_t NG = L.Vcap / 64;
+        if ((rc = L.touched.alloc((size_t)NG * n * 8, B))) return rc;
+        if ((rc = L.rtouch.alloc((size_t)(m + 63) / 64 * 8, B))) return rc;
+        k_lv_fill_u64<<<4096, 256, 0, st>>>(L.touched.as<uint64_t>(), (size_t)NG * n);
+        k_lv_fill_u64<<<64, 256, 0, st>>>(L.rtouch.as<uint64_t>(), (size_t)(m + 63) / 64);
+        HIPTRY(hipGetLastError());
+        L.have_touched = true;
+    }
+    HIPTRY(hipStreamSynchronize(st));
+    return 0;
+}
+
+static LvParams lv_params(const bp_instance *h, int32_t Bp, int32_t V, bool count) {
+    LvEngine &L = *h->lv;
+    LvParams P;
+    memset(&P, 0, sizeof(P));
+    P.I = dinst_of(h);
+    P.feastol = h->opt.feastol;
+    P.inttol = h->opt.inttol;
+    P.tau = h->opt.tau;
+    P.force_exact = (h->opt.flags & BP_FLAG_FORCE_EXACT) ? 1 : 0;
+    P.count_vars = count ? 1 : 0;
+    P.max_rounds = h->opt.max_rounds;
+    P.B = Bp;
+    P.V = V;
+    P.NG = V / 64;
+    P.m = h->m;
+    P.n = h->n;
+    P.bnd = L.bnd.as<double2>();
+    P.cand = L.cand.as<longlong2>();
+    P.vmask = L.vmask.as<uint64_t>();
+    for (int p = 0; p < 2; ++p) {
+        P.rmask[p] = L.rmask[p].as<uint64_t>();
+        P.qs[p] = L.qs[p].as<int32_t>();
+        P.ql[p] = L.ql[p].as<int2>();
+    }
+    P.lcap = L.lcap;
+    P.lpart = L.lpart.as<Acc>();
+    P.lrng = L.lrng.as<double>();
+    P.lmask = L.lmask.as<uint64_t>();
+    P.chg = L.chg.as<int32_t>();
+    P.touched = count ? L.touched.as<uint64_t>() : nullptr;
+    P.rtouch = count ? L.rtouch.as<uint32_t>() : nullptr;
+    P.vec = L.vec.as<LvVec>();
+    P.ctl = L.ctl.as<LvCtl>();
+    return P;
+}
+
+static void lv_launch_round(bp_instance *h, const LvParams &P, hipStream_t st, bool timed) {
+    const int gx = std::max(1, LV_GRID_ROWS / P.NG);
+    const dim3 grid(gx, P.NG);
+    if (timed) hipExtLaunchKernelGGL(k_lv_rows, grid, dim3(WG), 0, st, h->ev0, h->ev1, 0, P);
+    else k_lv_rows<<<grid, WG, 0, st>>>(P);
+    k_lv_heavy<<<grid, WG, 0, st>>>(P);
+    k_lv_apply<<<dim3(std::max(1, GRID_APPLY * 2 / P.NG), P.NG), WG, 0, st>>>(P, 0);
+    k_lv_end<<<1, WG, 0, st>>>(P);
+}
+
+// Rounds until every vector is finished: graphs of K rounds, or host rounds
+// with the row kernel timed by events.
+static int lv_run_rounds(bp_instance *h, const LvParams &P, hipStream_t st) {
+    LvEngine &L = *h->lv;
+    const bool timed = (h->opt.flags & BP_FLAG_TIME_KERNELS) != 0;
+    const bool host_rounds = timed || (h->opt.flags & BP_FLAG_HOST_ROUNDS) != 0;
+    const int K = std::max(1, (int)h->opt.rounds_per_launch);
+    const int64_t limit = (int64_t)h->opt.max_rounds + 2;
+    if (L.graph && (L.graph_rounds != K || memcmp(&L.graph_params, &P, sizeof(LvParams)) != 0)) {
+        (void)hipGraphExecDestroy(L.graph);
+        L.graph = nullptr;
+    }
+    LvCtl hc;
+    int64_t launched = 0;
+    for (;;) {
+        if (host_rounds) {
+            lv_launch_round(h, P, st, timed);
+            HIPTRY(hipGetLastError());
+            launched += 1;
+            if (timed) {
+                HIPTRY(hipEventSynchronize(h->ev1));
+                float ms = 0.f;
+                HIPTRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+                h->stats.ms += ms;
+                h->stats.launches += 1;
+            }
+        } else {
+            if (!L.graph) {
+                hipStream_t cs;
+                HIPTRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+                HIPTRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+                for (int r = 0; r < K; ++r) lv_launch_round(h, P, cs, false);
+                hipGraph_t g;
+                HIPTRY(hipStreamEndCapture(cs, &g));
+                hipError_t e = hipGraphInstantiate(&L.graph, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                (void)hipStreamDestroy(cs);
+                HIPTRY(e);
+                L.graph_rounds = K;
+                L.graph_params = P;
+            }
+            HIPTRY(hipGraphLaunch(L.graph, st));
+            launched += K;
+        }
+        HIPTRY(hipMemcpyAsync(&hc, P.ctl, sizeof(LvCtl), hipMemcpyDeviceToHost, st));
+        HIPTRY(hipStreamSynchronize(st));
+        if (hc.done) break;
+        if (launched > limit) return fail(BP_EDEVICE, "round loop did not terminate");
+    }
+    h->stats.rows += (int64_t)hc.stat_rows;
+    h->stats.nnz += (int64_t)hc.stat_nnz;
+    h->stats.vars_read += (int64_t)hc.stat_vars;
+    h->stats.vars_written += (int64_t)hc.stat_written;
+    return 0;
+}
+
+static void lv_fill_result(const LvVec &S, int32_t box_bad, bp_result *r) {
+    memset(r, 0, sizeof(*r));
+    r->infeasible_row = -1;
+    r->infeasible_var = -1;
+    if (box_bad != NONE) {
+        r->status = BP_INFEASIBLE;
+        r->infeasible_var = box_bad;
+        return;
+    }
+    r->status = S.status;
+    r->rounds = S.rounds;
+    r->nnz_propagated = (int64_t)S.nnz;
+    if (S.status == BP_INFEASIBLE) {
+        if (S.row_bad_count > 0) {
+            r->n_infeasible_rows = S.row_bad_count;
+            r->infeasible_row = S.row_bad_min;
+        } else {
+            r->infeasible_var = S.var_bad_min;
+        }
+    }
+}
+
+// One piece of a batch: vectors [0, Bp) of lb/ub (row-major [Bp][n]), their
+// changed lists given by ptr (absolute offsets into idx, Bp + 1 entries).
+static int lv_piece(bp_instance *h, int32_t Bp, double *lb, double *ub, const int32_t *idx,
+                    const int64_t *ptr_dev, int64_t e0, int64_t ecount, bool cold, bp_result *res,
+                    hipStream_t st) {
+    const int32_t V = (Bp + 63) / 64 * 64;
+    const bool count = (h->opt.flags & BP_FLAG_COUNT_VARS) != 0;
+    if (int rc = lv_ensure(h, V, count, st)) return rc;
+    LvEngine &L = *h->lv;
+    const LvParams P = lv_params(h, Bp, V, count);
+    const int64_t n = h->n;
+    const int NG = P.NG;
+    // bounds in, box check
+    {
+        std::vector<int32_t> init(2 * (size_t)V);
+        for (int32_t j = 0; j < V; ++j) {
+            init[2 * j] = NONE;
+            init[2 * j + 1] = 0;
+        }
+        HIPTRY(hipMemcpyAsync(L.box.p, init.data(), init.size() * 4, hipMemcpyHostToDevice, st));
+    }
+    if (n > 0) {
+        const int64_t tiles = (n + 63) / 64 * NG;
+        k_lv_pack<<<(int)std::min<int64_t>(tiles, 8192), WG, 0, st>>>(lb, ub, P.bnd, (int32_t)n, Bp, V,
+                                                                     h->vtype.as<uint8_t>(), h->opt.feastol,
+                                                                     L.box.as<int32_t>());
+    }
+    HIPTRY(hipGetLastError());
+    std::vector<int32_t> box(2 * (size_t)V);
+    HIPTRY(hipMemcpyAsync(box.data(), L.box.p, box.size() * 4, hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+    for (int32_t j = 0; j < Bp; ++j)
+        if (box[2 * j + 1]) return fail(BP_EINVAL, "NaN bound in vector " + std::to_string(j));
+    if (!cold && ecount > 0) {
+        std::vector<int32_t> ids(ecount);
+        HIPTRY(hipMemcpyAsync(ids.data(), idx + e0, ids.size() * 4, hipMemcpyDeviceToHost, st));
+        HIPTRY(hipStreamSynchronize(st));
+        for (int32_t v : ids)
+            if (v < 0 || v >= n) return fail(BP_EINVAL, "changed variable id out of range");
+    }
+    // control block, vectors, seeds
+    LvCtl c;
+    memset(&c, 0, sizeof(c));
+    HIPTRY(hipMemcpyAsync(P.ctl, &c, sizeof(LvCtl), hipMemcpyHostToDevice, st));
+    k_lv_reset<<<grid_for(V), 256, 0, st>>>(P, L.box.as<int32_t>());
+    const int gx = std::max(1, LV_GRID_ROWS / NG);
+    if (cold) {
+        if (h->m > 0)
+            k_lv_seed_cold<<<dim3(std::max(1, gx / 4), NG), 256, 0, st>>>(
+                P, L.short_rows.as<int32_t>(), L.nshort, L.long_chunks.as<int2>(), L.nlong);
+    } else if (ecount > 0) {
+        k_lv_seed_vars<<<grid_for(ecount), 256, 0, st>>>(P, idx, ptr_dev, e0, ecount);
+        k_lv_apply<<<dim3(gx, NG), WG, 0, st>>>(P, 1);
+    }
+    k_lv_seed_finish<<<grid_for(V), 256, 0, st>>>(P, cold ? 1 : 0, (long long)h->nnz);
+    k_lv_start<<<1, 256, 0, st>>>(P);
+    HIPTRY(hipGetLastError());
+    if (int rc = lv_run_rounds(h, P, st)) return rc;
+    k_lv_cleanup<<<dim3(std::max(1, gx / 4), NG), 256, 0, st>>>(P);
+    k_lv_cleanup_counts<<<1, 64, 0, st>>>(P);
+    if (n > 0) {
+        const int64_t tiles = (n + 63) / 64 * NG;
+        k_lv_unpack<<<(int)std::min<int64_t>(tiles, 8192), WG, 0, st>>>(P.bnd, lb, ub, (int32_t)n, Bp, V);
+    }
+    HIPTRY(hipGetLastError());
+    std::vector<LvVec> vec(Bp);
+    HIPTRY(hipMemcpyAsync(vec.data(), P.vec, Bp * sizeof(LvVec), hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+    for (int32_t j = 0; j < Bp; ++j) lv_fill_result(vec[j], box[2 * j], &res[j]);
+    return 0;
+}
+
+// A batch in pieces of at most 64 * LV_MAX_GROUPS vectors.
+static int lv_propagate(bp_instance *h, int32_t B, double *lb, double *ub, const int32_t *idx,
+                        const int64_t *ptr_dev, const std::vector<int64_t> &ptr, bool cold,
+                        bp_result *res, hipStream_t st) {
+    const int32_t maxv = 64 * LV_MAX_GROUPS;
+    const int64_t n = h->n;
+    for (int32_t v0 = 0; v0 < B; v0 += maxv) {
+        const int32_t Bp = std::min(maxv, B - v0);
+        const int64_t e0 = cold ? 0 : ptr[v0];
+        const int64_t ec = cold ? 0 : ptr[v0 + Bp] - ptr[v0];
+        if (int rc = lv_piece(h, Bp, lb + (size_t)v0 * n, ub + (size_t)v0 * n, idx,
+                              cold ? nullptr : ptr_dev + v0, e0, ec, cold, res + v0, st))
+            return rc;
+    }
+    return 0;
+}

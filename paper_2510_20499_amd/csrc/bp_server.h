@@ -108,7 +108,7 @@ static int64_t slot_bytes(const Shape &sh) {
     b += 4 * nw * 2 + 4 * mw;                      // var, dirty and row bitmaps
     b += 4 * FILT_WORDS + (int64_t)sizeof(SlotInfo) + 4;
     for (int q = 0; q < BIN_HEAVY; ++q) b += 2 * 8 * sh.bin_cap[q];
-    b += 2 * 16 * sh.heavy_chunks + 64 * sh.heavy_chunks;
+    b += 2 * 16 * sh.heavy_chunks + 64 * sh.heavy_chunks + 8 * sh.heavy_chunks;
     return b;
 }
 

@@ -123,3 +123,121 @@ def rel_close(a, b, tol=1e-9):
     with np.errstate(invalid="ignore"):
         near = np.abs(a - b) <= tol * scale
     return bool(np.all(same | near))
+
+
+# ---------------------------------------------------------------------------
+# Slack filter of the row kernels, restated for tests.  A row none of whose
+# candidates can be taken skips its candidate pass on the GPU; the rule must
+# never skip a row the definition would let tighten a bound.
+# ---------------------------------------------------------------------------
+INF = math.inf
+
+
+def filter_width(a, lb, ub):
+    """Width of one nonzero: |a| (ub - lb + 1 + 2^-50 max|bound|) (1 + 2^-40),
+    in the kernels' operation order (each step rounded to double)."""
+    d = ub - lb
+    d = d + 1.0
+    d = d + max(abs(lb), abs(ub)) * 2.0 ** -50
+    return (abs(a) * d) * (1.0 + 2.0 ** -40)
+
+
+def filter_quiet(minfin, maxfin, nmin, nmax, lo, hi, rng):
+    """The kernels' decision that no candidate of a row can be taken."""
+    fin = rng < INF
+    qhi = hi == INF or nmin >= 2 or (nmin == 0 and fin and hi - minfin >= rng)
+    qlo = lo == -INF or nmax >= 2 or (nmax == 0 and fin and maxfin - lo >= rng)
+    return qhi and qlo
+
+
+def slack_edge_instance(seed, count=300, naive=False, lengths=(1, 7)):
+    """Rows with disjoint variables whose slack is placed at the slack
+    filter's threshold, give or take a few ulps to 1e-3 relative: binaries,
+    integers with non-integral bounds, continuous variables of magnitude up
+    to 1e13 with small domains, coefficients of magnitude 1e-3..1e3.
+    naive=True places the slack at max |a| (ub - lb) instead (the threshold
+    without the integer unit and the rounding margins).  Returns the
+    instance and, per row, (minfin, maxfin, width).  Row lengths are
+    uniform in [lengths[0], lengths[1])."""
+    rs = np.random.default_rng(seed)
+    rows, lo, hi, vt, lb, ub, info = [], [], [], [], [], [], []
+    eps = [0.0, 2.0 ** -52, -2.0 ** -52, 2.0 ** -45, -2.0 ** -45, 2.0 ** -40, -2.0 ** -40,
+           1e-9, -1e-9, 1e-3, -1e-3]
+    n = 0
+    for _ in range(count):
+        L = int(rs.integers(lengths[0], lengths[1]))
+        cols = list(range(n, n + L))
+        n += L
+        vals, ls, us = [], [], []
+        for _ in range(L):
+            kind = int(rs.integers(0, 4))
+            if kind == 0:
+                l, u, t = 0.0, 1.0, 1
+            elif kind == 1:
+                l = float(rs.integers(-5, 5)) + float(rs.choice([0.0, 0.25, 0.5]))
+                u = l + float(rs.integers(1, 8)) + float(rs.choice([0.0, 0.3]))
+                t = 1
+            elif kind == 2:
+                c = float(rs.choice([-1.0, 1.0])) * 10.0 ** rs.uniform(6, 13)
+                l, u, t = c, c + 10.0 ** rs.uniform(-4, 2), 0
+            else:
+                l = rs.uniform(-100, 0)
+                u, t = l + rs.uniform(0, 200), 0
+            vals.append(float(rs.choice([-1.0, 1.0])) * 10.0 ** rs.uniform(-3, 3))
+            ls.append(float(l))
+            us.append(float(u))
+            vt.append(t)
+        tmin = [a * l if a > 0 else a * u for a, l, u in zip(vals, ls, us)]
+        tmax = [a * u if a > 0 else a * l for a, l, u in zip(vals, ls, us)]
+        mn, mx = math.fsum(tmin), math.fsum(tmax)
+        if naive:
+            w = max(abs(a) * (u - l) for a, l, u in zip(vals, ls, us))
+        else:
+            w = max(filter_width(a, l, u) for a, l, u in zip(vals, ls, us))
+        kind = int(rs.integers(0, 3))  # 0: a.x <= hi, 1: lo <= a.x, 2: both
+        h = mn + w * (1.0 + eps[int(rs.integers(len(eps)))]) if kind != 1 else INF
+        g = mx - w * (1.0 + eps[int(rs.integers(len(eps)))]) if kind != 0 else -INF
+        if g > h:  # both sides at the threshold would cross: keep the upper one
+            g = -INF
+        rows.append((cols, vals))
+        lo.append(g)
+        hi.append(h)
+        lb.extend(ls)
+        ub.extend(us)
+        info.append((mn, mx, max(filter_width(a, l, u) for a, l, u in zip(vals, ls, us))))
+    inst = gen.from_rows(n, rows, lo, hi, vt, lb, ub)
+    return inst, info
+
+
+def stack_instances(parts):
+    """Block-diagonal instance of the given instances (disjoint variables)."""
+    rows, lo, hi, vt, lb, ub = [], [], [], [], [], []
+    n = 0
+    for inst in parts:
+        rp = inst["row_ptr"]
+        for k in range(inst["m"]):
+            rows.append((inst["col"][rp[k]:rp[k + 1]] + n, inst["val"][rp[k]:rp[k + 1]]))
+        lo.extend(inst["lo"])
+        hi.extend(inst["hi"])
+        vt.extend(inst["vtype"])
+        lb.extend(inst["lb"])
+        ub.extend(inst["ub"])
+        n += inst["n"]
+    return gen.from_rows(n, rows, lo, hi, vt, lb, ub)
+
+
+def row_instance(inst, k):
+    """Row k alone, over its own variables."""
+    rp = inst["row_ptr"]
+    c = inst["col"][rp[k]:rp[k + 1]]
+    v = inst["val"][rp[k]:rp[k + 1]]
+    return gen.from_rows(len(c), [(np.arange(len(c)), v)], [inst["lo"][k]], [inst["hi"][k]],
+                         inst["vtype"][c], inst["lb"][c], inst["ub"][c])
+
+
+def keep_rows(inst, ks):
+    """The rows ks of inst (variables unchanged; others become empty columns)."""
+    rp = inst["row_ptr"]
+    rows = [(inst["col"][rp[k]:rp[k + 1]], inst["val"][rp[k]:rp[k + 1]]) for k in ks]
+    return gen.from_rows(inst["n"], rows, inst["lo"][ks], inst["hi"][ks], inst["vtype"],
+                         inst["lb"], inst["ub"])

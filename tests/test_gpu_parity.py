@@ -10,7 +10,7 @@ import torch
 
 import oracle
 from gpu_util import assert_same, both, bp, dev, gpu_propagate
-from helpers import load_golden
+from helpers import keep_rows, load_golden, row_instance, slack_edge_instance, stack_instances
 from paper_2510_20499_amd import gen
 
 pytestmark = pytest.mark.gpu
@@ -202,3 +202,26 @@ def test_batch_matches_single_vectors():
     ro, lo, uo = oracle.propagate(inst)
     for v in range(3):
         assert_same(inst, res[v], tl[v].cpu().numpy(), tu[v].cpu().numpy(), ro, lo, uo, "coldbatch")
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_slack_filter_edges(seed):
+    """Rows whose slack sits at the slack filter's threshold, and at the
+    naive threshold max |a| (ub - lb) where some rows do tighten, in light,
+    block and heavy rows: the rows the kernels skip and the rows they
+    process must both give the oracle's result."""
+    parts = [slack_edge_instance(seed, 300)[0],
+             slack_edge_instance(seed + 10, 300, naive=True)[0],
+             slack_edge_instance(seed + 20, 12, lengths=(1500, 6000))[0],
+             slack_edge_instance(seed + 30, 12, naive=True, lengths=(1500, 6000))[0]]
+    inst = stack_instances(parts)
+    # rows that are infeasible on their own would end the run in its first
+    # rounds; keep the others so that every bound is compared
+    ok = [k for k in range(inst["m"]) if oracle.propagate(row_instance(inst, k))[0]["status"] == 0]
+    inst = keep_rows(inst, ok)
+    r0, lb0, ub0 = oracle.propagate(inst)
+    assert r0["status"] == 0 and r0["rounds"] >= 2
+    assert ((lb0 != inst["lb"]) | (ub0 != inst["ub"])).sum() >= 20  # some rows do tighten
+    for thr in (2048, 8192):
+        I = bp().Instance(inst, bp().default_options(heavy_threshold=thr, heavy_chunk=512))
+        both(I, inst, what="slack-edge thr=%d" % thr)
