@@ -97,6 +97,9 @@ def main():
     ap.add_argument("--bulk-steps", type=int, default=3)
     ap.add_argument("--bulk-plain", type=int, default=16,
                     help="vectors propagated one call at a time for the plain baseline")
+    ap.add_argument("--profile-bulk", type=int, default=0,
+                    help="run only this many batched bulk calls (no tuning, no baselines; "
+                         "for profilers) and exit")
     ap.add_argument("--only-probe", action="store_true",
                     help="run only the double-probing measurement (for profilers)")
     ap.add_argument("--probe-cpu", type=int, default=0,
@@ -300,9 +303,13 @@ def bench_bulk(args, bp, gen, torch, np):
     t_load = time.perf_counter() - t
     lb0 = torch.tensor(inst["lb"], dtype=torch.float64, device=dev)
     ub0 = torch.tensor(inst["ub"], dtype=torch.float64, device=dev)
-    tune = I.autotune(lb0, ub0)
-    opt_kw = dict(heavy_threshold=tune["heavy_threshold"], heavy_chunk=tune["heavy_chunk"],
-                  rounds_per_launch=tune["rounds_per_launch"])
+    if args.profile_bulk:
+        tune = dict(trials=0)
+        opt_kw = {}
+    else:
+        tune = I.autotune(lb0, ub0)
+        opt_kw = dict(heavy_threshold=tune["heavy_threshold"], heavy_chunk=tune["heavy_chunk"],
+                      rounds_per_launch=tune["rounds_per_launch"])
     log("bulk: loaded in %.1f s, tuned %s" % (t_load, opt_kw))
     # Root bounds: the cold propagation's result.  At this size the root
     # may stop at the round limit; its bounds are still valid (every
@@ -313,11 +320,12 @@ def bench_bulk(args, bp, gen, torch, np):
     # cold root propagation at this size (plain path)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    reps_cold = 3
+    reps_cold = 0 if args.profile_bulk else 3
+    r = root
     for _ in range(reps_cold):
         r = I.propagate(*fresh(lb0, ub0))
     torch.cuda.synchronize()
-    t_cold = (time.perf_counter() - t) / reps_cold
+    t_cold = (time.perf_counter() - t) / max(reps_cold, 1)
     lists = gen.bulk_fix_lists(inst, rl.cpu().numpy(), ru.cpu().numpy(), B, frac=0.05, seed=args.seed)
     ptr = np.zeros(B + 1, np.int64)
     ptr[1:] = np.cumsum([p.size for p, _ in lists])
@@ -342,6 +350,12 @@ def bench_bulk(args, bp, gen, torch, np):
     log("bulk: %d vectors of %d fixings ready" % (B, int(ptr[1])))
     res = batch_call(I)  # warm
     torch.cuda.synchronize()
+    if args.profile_bulk:
+        for _ in range(args.profile_bulk):
+            res = batch_call(I)
+        torch.cuda.synchronize()
+        return {"profile_bulk": args.profile_bulk,
+                "nnz_per_call": sum(x["nnz_propagated"] for x in res)}
     tb = 0.0
     for _ in range(args.bulk_steps):
         restore()

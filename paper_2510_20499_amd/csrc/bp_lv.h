@@ -491,7 +491,7 @@ __global__ void __launch_bounds__(WG) k_lv_apply(LvParams P, int seed) {
             while (any) {
                 const int t = __ffsll((long long)any) - 1;
                 any &= any - 1;
-                const uint64_t nb = (uint64_t)rl_i32((int)(uint32_t)newb, t) |
+                const uint64_t nb = (uint64_t)(uint32_t)rl_i32((int)(uint32_t)newb, t) |
                                     ((uint64_t)(uint32_t)rl_i32((int)(uint32_t)(newb >> 32), t) << 32);
                 const int lt = rl_i32((int)len, t);
                 if ((nb >> lane) & 1ull) {
