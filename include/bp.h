@@ -191,7 +191,12 @@ int bp_propagate(bp_instance *h, double *lb, double *ub, const int32_t *changed,
  *   changed_idx  DEVICE variable ids
  *   res          HOST [B]
  * Returns BP_OK when the call ran (per-vector outcomes are in res) or an
- * error.  Does not change the base. */
+ * error.  Does not change the base.  The bounds of a vector whose outcome
+ * is BP_INFEASIBLE are unspecified (with 16 or more vectors they keep the
+ * input).  Batches of 16 or more vectors run one vector per lane (bounds
+ * stored [variable][vector] in device memory the instance keeps; about
+ * 32 B per variable and vector); BP_FLAG_BATCH_SLOTS keeps the slot
+ * engine.  Results are the same either way. */
 int bp_propagate_batch(bp_instance *h, int32_t B, double *lb, double *ub,
                        const int64_t *changed_ptr, const int32_t *changed_idx,
                        bp_result *res, void *stream);

@@ -1352,29 +1352,17 @@ __global__ void __launch_bounds__(WG) k_retire(Params P, JobIO IO) {
             __syncthreads();
         }
         if (S.state != SLOT_FREE) continue;
-        // Admit jobs until one needs rounds or none is left.  A job is
-        // claimed by compare-and-swap, so the counter never passes the end
-        // of the list: jobs the host appends later are still claimed.
+        // Admit jobs until one needs rounds or none is left.  A claim past
+        // the end of the list takes no job; the counter may then exceed the
+        // list length, and a host that appends jobs first lowers it back to
+        // the old length (no kernel runs meanwhile).
         for (;;) {
-            if (threadIdx.x == 0) {
-                const uint32_t tot = C->total_jobs;
-                uint32_t cur = __hip_atomic_load(&C->next_job, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                int got = -1;
-                while (cur < tot) {
-                    const uint32_t prev = atomicCAS(&C->next_job, cur, cur + 1u);
-                    if (prev == cur) {
-                        got = (int)cur;
-                        break;
-                    }
-                    cur = prev;
-                }
-                R.job = got;
-            }
+            if (threadIdx.x == 0) R.job = (int)atomicAdd(&C->next_job, 1u);
             __syncthreads();
-            const int p = R.job;
+            const uint32_t p = (uint32_t)R.job;
             __syncthreads();
-            if (p < 0) break;
-            if (admit_job<MULTI>(P, IO, s, p, par, R)) break;
+            if (p >= C->total_jobs) break;
+            if (admit_job<MULTI>(P, IO, s, (int)p, par, R)) break;
         }
         __syncthreads();
     }

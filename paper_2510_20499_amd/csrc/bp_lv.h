@@ -65,8 +65,24 @@ struct LvParams {
     uint64_t *touched;   // [NG][n] bound records read this round (counting only)
     uint32_t *rtouch;    // [m / 32] rows read this round by any group (counting only)
     LvVec *vec;          // [V]
+    uint32_t *vbad;      // [V] vector has an infeasible row this round (set early, read relaxed)
     LvCtl *ctl;
 };
+
+// A vector with an infeasible row in the current round finishes at its end
+// with row evidence and unspecified bounds: its candidates can change
+// nothing, so they are skipped once the flag is seen.  The flag only goes
+// from 0 to 1 within a round; a stale read merely computes them anyway.
+__device__ __forceinline__ bool lv_known_bad(const LvParams &P, int v) {
+    return __hip_atomic_load(&P.vbad[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+}
+
+__device__ __forceinline__ void lv_mark_bad(const LvParams &P, int v, bool bad, bool &flagged) {
+    if (bad && !flagged) {
+        __hip_atomic_store(&P.vbad[v], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        flagged = true;
+    }
+}
 
 __device__ __forceinline__ int rl_i32(int x, int t) { return __builtin_amdgcn_readlane(x, t); }
 __device__ __forceinline__ double rl_f64(double x, int t) {
@@ -254,11 +270,12 @@ __device__ __forceinline__ void lv_finish_act(const LvParams &P, int v, bool liv
 // One short row for the 64 vectors of group g: activity, row test and
 // candidates in one task.
 __device__ void lv_short_row(const LvParams &P, int par, int g, int v, bool active, int k,
-                             int &bad_min, int &bad_cnt, WaveBuf &wb, LvCount &K) {
+                             int &bad_min, int &bad_cnt, bool &flagged, WaveBuf &wb, LvCount &K) {
     uint64_t *mp = &P.rmask[par][(size_t)g * P.m + k];
     const uint64_t word = *mp;
     const uint64_t livemask = word & __ballot(active);
     const bool live = (livemask >> __lane_id()) & 1ull;
+    const bool kb = live && lv_known_bad(P, v);
     const int64_t p0 = P.I.row_ptr[k], p1 = P.I.row_ptr[k + 1];
     const double2 sd = P.I.side[k];
     if (__lane_id() == 0) *mp = 0ull;  // the word is queued again only by a later round
@@ -280,8 +297,9 @@ __device__ void lv_short_row(const LvParams &P, int par, int g, int v, bool acti
             bad_min = min(bad_min, k);
             bad_cnt += 1;
         }
+        lv_mark_bad(P, v, bad, flagged);
     }
-    const bool want = live && !bad && !row_quiet(R);
+    const bool want = live && !bad && !kb && !flagged && !row_quiet(R);
     lv_candidates(P, g, v, want, R, p0, p1, wb);
 }
 
@@ -319,13 +337,15 @@ __global__ void __launch_bounds__(WG) k_lv_rows(LvParams P) {
     const uint32_t w = blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
     const uint32_t nl = C->nlong[par][g], ns = C->nshort[par][g];
     int bad_min = NONE, bad_cnt = 0;
+    bool flagged = false;
     WaveBuf wb;
     wb.val = 0;
     wb.n = 0;
     LvCount K = {0ull, 0ull, 0ull};
     for (uint32_t t = w; t < nl + ns; t += nw) {
         if (t < nl) lv_chunk_activity(P, par, g, v, active, t, K);
-        else lv_short_row(P, par, g, v, active, P.qs[par][(size_t)g * P.m + (t - nl)], bad_min, bad_cnt, wb, K);
+        else lv_short_row(P, par, g, v, active, P.qs[par][(size_t)g * P.m + (t - nl)], bad_min, bad_cnt,
+                          flagged, wb, K);
     }
     wbuf_flush(wb, &C->nchg[g], P.chg + (size_t)g * P.n);
     lv_count_flush(P, K);
@@ -348,6 +368,7 @@ __global__ void __launch_bounds__(WG) k_lv_heavy(LvParams P) {
     const uint32_t w = blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
     const uint32_t nl = C->nlong[par][g];
     int bad_min = NONE, bad_cnt = 0;
+    bool flagged = false;
     WaveBuf wb;
     wb.val = 0;
     wb.n = 0;
@@ -356,6 +377,7 @@ __global__ void __launch_bounds__(WG) k_lv_heavy(LvParams P) {
         const int k = rec.x, c = rec.y;
         const uint64_t livemask = P.lmask[(size_t)g * P.lcap + u];
         const bool live = ((livemask >> __lane_id()) & 1ull) && active;
+        const bool kb = live && lv_known_bad(P, v);
         const int64_t r0 = P.I.row_ptr[k], r1 = P.I.row_ptr[k + 1];
         const int nch = (int)((r1 - r0 + LV_CHUNK - 1) / LV_CHUNK);
         const uint32_t u0 = u - (uint32_t)c;
@@ -384,8 +406,9 @@ __global__ void __launch_bounds__(WG) k_lv_heavy(LvParams P) {
                 bad_min = min(bad_min, k);
                 bad_cnt += 1;
             }
+            lv_mark_bad(P, v, bad, flagged);
         }
-        const bool want = live && !bad && !row_quiet(R);
+        const bool want = live && !bad && !kb && !flagged && !row_quiet(R);
         const int64_t q0 = r0 + (int64_t)c * LV_CHUNK, q1 = min(r1, q0 + (int64_t)LV_CHUNK);
         lv_candidates(P, g, v, want, R, q0, q1, wb);
     }
@@ -519,6 +542,7 @@ __global__ void __launch_bounds__(WG) k_lv_end(LvParams P) {
     __syncthreads();
     for (int v = threadIdx.x; v < P.V; v += WG) {
         LvVec &S = P.vec[v];
+        P.vbad[v] = 0u;
         if (S.state != SLOT_ACTIVE) continue;
         bool fin = true;
         if (S.row_bad_count > 0 || S.var_bad_min != NONE) {
@@ -598,13 +622,15 @@ __global__ void __launch_bounds__(WG) k_lv_pack(const double *lb, const double *
 
 // Bounds out: [n][V] back to [B][n].
 __global__ void __launch_bounds__(WG) k_lv_unpack(const double2 *bnd, double *lb, double *ub,
-                                                  int32_t n, int32_t B, int32_t V) {
+                                                  int32_t n, int32_t B, int32_t V, const uint8_t *wmask) {
     __shared__ double2 tile[64][65];
     const int64_t tiles_i = (n + 63) / 64;
     const int ngv = V / 64;
     for (int64_t t = blockIdx.x; t < tiles_i * ngv; t += gridDim.x) {
         const int64_t i0 = (t / ngv) * 64;
         const int v0 = (int)(t % ngv) * 64;
+        // vectors whose bounds are written back (uniform over the tile)
+        if (__ballot(wmask[v0 + __lane_id()] != 0) == 0) continue;
         for (int c = threadIdx.x >> 6; c < 64; c += WG / 64) {
             const int64_t i = i0 + c;
             tile[__lane_id()][c] = i < n ? bnd[(size_t)i * V + v0 + __lane_id()] : make_double2(0.0, 0.0);
@@ -613,7 +639,7 @@ __global__ void __launch_bounds__(WG) k_lv_unpack(const double2 *bnd, double *lb
         for (int r = threadIdx.x >> 6; r < 64; r += WG / 64) {
             const int v = v0 + r;
             const int64_t i = i0 + __lane_id();
-            if (v < B && i < n) {
+            if (v < B && i < n && wmask[v]) {
                 const double2 b = tile[r][__lane_id()];
                 lb[(size_t)v * n + i] = b.x;
                 ub[(size_t)v * n + i] = b.y;
@@ -647,6 +673,7 @@ __global__ void k_lv_reset(LvParams P, const int32_t *box) {
         S.nnz = 0;
         S.pending_rows = 0;
         S.pending_nnz = 0;
+        P.vbad[v] = 0u;
     }
 }
 
@@ -717,6 +744,63 @@ __global__ void k_lv_seed_vars(LvParams P, const int32_t *vars, const int64_t *p
             }
         }
     }
+}
+
+// Warm start by rows (large changed lists): row k is queued for the
+// vectors in the OR of its variables' masks.  One wave per row; no atomics
+// on the masks.  Grid (x, NG).
+__global__ void __launch_bounds__(WG) k_lv_seed_rows(LvParams P) {
+    const int g = blockIdx.y;
+    const int lane = __lane_id();
+    const int v = g * 64 + lane;
+    const uint64_t activemask = __ballot(P.vec[v].state == SLOT_ACTIVE);
+    const uint32_t nw = gridDim.x * (WG / 64);
+    const uint32_t w = blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
+    unsigned long long my_rows = 0, my_nnz = 0;
+    WaveBuf wb;
+    wb.val = 0;
+    wb.n = 0;
+    for (uint32_t k = w; k < (uint32_t)P.m; k += nw) {
+        const int64_t p0 = P.I.row_ptr[k], p1 = P.I.row_ptr[k + 1];
+        uint64_t acc = 0;
+        for (int64_t j = p0 + lane; j < p1; j += 64) acc |= P.vmask[(size_t)g * P.n + P.I.col[j]];
+        uint32_t lo = (uint32_t)acc, hi = (uint32_t)(acc >> 32);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            lo |= (uint32_t)__shfl_xor((int)lo, o, 64);
+            hi |= (uint32_t)__shfl_xor((int)hi, o, 64);
+        }
+        const uint64_t mask = (((uint64_t)hi << 32) | lo) & activemask;
+        if (mask == 0) continue;
+        const int64_t len = p1 - p0;
+        if (lane == 0) P.rmask[0][(size_t)g * P.m + k] = mask;
+        if (len <= LV_SHORT) {
+            wbuf_push(wb, (int32_t)k, &P.ctl->nshort[0][g], P.qs[0] + (size_t)g * P.m);
+        } else {
+            const int nch = (int)((len + LV_CHUNK - 1) / LV_CHUNK);
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(&P.ctl->nlong[0][g], (uint32_t)nch);
+            base = __shfl(base, 0, 64);
+            for (int c = lane; c < nch; c += 64) P.ql[0][(size_t)g * P.lcap + base + c] = make_int2((int)k, c);
+        }
+        if ((mask >> lane) & 1ull) {
+            my_rows += 1;
+            my_nnz += (unsigned long long)len;
+        }
+    }
+    wbuf_flush(wb, &P.ctl->nshort[0][g], P.qs[0] + (size_t)g * P.m);
+    if (my_rows) {
+        atomicAdd(&P.vec[v].pending_rows, my_rows);
+        atomicAdd(&P.vec[v].pending_nnz, my_nnz);
+    }
+}
+
+// After row seeding: clear the variable masks that k_lv_seed_vars set.
+__global__ void k_lv_seed_clear(LvParams P) {
+    const int g = blockIdx.y;
+    const uint32_t cnt = P.ctl->nchg[g];
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += gridDim.x * blockDim.x)
+        P.vmask[(size_t)g * P.n + P.chg[(size_t)g * P.n + e]] = 0ull;
 }
 
 // After seeding: first-round counters of every vector.
@@ -793,7 +877,8 @@ struct LvEngine {
     int32_t Vcap = 0;
     int64_t lcap = 0, nshort = 0, nlong = 0;
     bool have_touched = false;
-    DevBuf bnd, cand, vmask, rmask[2], qs[2], ql[2], lpart, lrng, lmask, chg, touched, rtouch, vec, ctl, box;
+    DevBuf bnd, cand, vmask, rmask[2], qs[2], ql[2], lpart, lrng, lmask, chg, touched, rtouch, vec, vbad, ctl,
+        box, wmask;
     DevBuf short_rows, long_chunks;  // cold-start tasks of the instance
     hipGraphExec_t graph = nullptr;
     int graph_rounds = 0;

@@ -62,6 +62,8 @@ static int lv_ensure(bp_instance *h, int32_t V, bool count, hipStream_t st) {
         if ((rc = L.lmask.alloc((size_t)NG * L.lcap * 8, B))) return rc;
         if ((rc = L.chg.alloc((size_t)NG * n * 4, B))) return rc;
         if ((rc = L.vec.alloc((size_t)V * sizeof(LvVec), B))) return rc;
+        if ((rc = L.vbad.alloc((size_t)V * 4, B))) return rc;
+        if ((rc = L.wmask.alloc((size_t)V, B))) return rc;
         if ((rc = L.box.alloc((size_t)V * 8, B))) return rc;
         if (!L.ctl.p && (rc = L.ctl.alloc(sizeof(LvCtl), B))) return rc;
         k_lv_fill_cand<<<4096, 256, 0, st>>>(L.cand.as<longlong2>(), (size_t)n * V);
@@ -116,6 +118,7 @@ static LvParams lv_params(const bp_instance *h, int32_t Bp, int32_t V, bool coun
     P.touched = count ? L.touched.as<uint64_t>() : nullptr;
     P.rtouch = count ? L.rtouch.as<uint32_t>() : nullptr;
     P.vec = L.vec.as<LvVec>();
+    P.vbad = L.vbad.as<uint32_t>();
     P.ctl = L.ctl.as<LvCtl>();
     return P;
 }
@@ -260,7 +263,19 @@ static int lv_piece(bp_instance *h, int32_t Bp, double *lb, double *ub, const in
                 P, L.short_rows.as<int32_t>(), L.nshort, L.long_chunks.as<int2>(), L.nlong);
     } else if (ecount > 0) {
         k_lv_seed_vars<<<grid_for(ecount), 256, 0, st>>>(P, idx, ptr_dev, e0, ecount);
-        k_lv_apply<<<dim3(gx, NG), WG, 0, st>>>(P, 1);
+        // Queue the rows of the listed variables: by columns (one atomic per
+        // column entry and group) for short lists, by rows (a read of the
+        // matrix per group, no atomics) when the columns would cover a good
+        // part of it.
+        const double col_cost = 4.0 * (double)std::min<int64_t>(ecount, (int64_t)n * NG) *
+                                ((double)h->nnz / (double)std::max<int64_t>(n, 1));
+        const double row_cost = (double)NG * ((double)h->nnz + (double)h->m);
+        if (col_cost > row_cost) {
+            k_lv_seed_rows<<<dim3(gx, NG), WG, 0, st>>>(P);
+            k_lv_seed_clear<<<dim3(std::max(1, gx / 4), NG), 256, 0, st>>>(P);
+        } else {
+            k_lv_apply<<<dim3(gx, NG), WG, 0, st>>>(P, 1);
+        }
     }
     k_lv_seed_finish<<<grid_for(V), 256, 0, st>>>(P, cold ? 1 : 0, (long long)h->nnz);
     k_lv_start<<<1, 256, 0, st>>>(P);
@@ -268,15 +283,27 @@ static int lv_piece(bp_instance *h, int32_t Bp, double *lb, double *ub, const in
     if (int rc = lv_run_rounds(h, P, st)) return rc;
     k_lv_cleanup<<<dim3(std::max(1, gx / 4), NG), 256, 0, st>>>(P);
     k_lv_cleanup_counts<<<1, 64, 0, st>>>(P);
-    if (n > 0) {
-        const int64_t tiles = (n + 63) / 64 * NG;
-        k_lv_unpack<<<(int)std::min<int64_t>(tiles, 8192), WG, 0, st>>>(P.bnd, lb, ub, (int32_t)n, Bp, V);
-    }
     HIPTRY(hipGetLastError());
     std::vector<LvVec> vec(Bp);
     HIPTRY(hipMemcpyAsync(vec.data(), P.vec, Bp * sizeof(LvVec), hipMemcpyDeviceToHost, st));
     HIPTRY(hipStreamSynchronize(st));
     for (int32_t j = 0; j < Bp; ++j) lv_fill_result(vec[j], box[2 * j], &res[j]);
+    // Bounds out, except for infeasible vectors (their bounds are
+    // unspecified; they keep the input).
+    std::vector<uint8_t> wm(V, 0);
+    bool any = false;
+    for (int32_t j = 0; j < Bp; ++j) {
+        wm[j] = res[j].status != BP_INFEASIBLE;
+        any = any || wm[j];
+    }
+    if (n > 0 && any) {
+        HIPTRY(hipMemcpyAsync(L.wmask.p, wm.data(), V, hipMemcpyHostToDevice, st));
+        const int64_t tiles = (n + 63) / 64 * NG;
+        k_lv_unpack<<<(int)std::min<int64_t>(tiles, 8192), WG, 0, st>>>(P.bnd, lb, ub, (int32_t)n, Bp, V,
+                                                                       L.wmask.as<uint8_t>());
+        HIPTRY(hipGetLastError());
+        HIPTRY(hipStreamSynchronize(st));
+    }
     return 0;
 }
 

@@ -340,6 +340,17 @@ static int server_append(bp_server *sv) {
         sv->pending.pop_front();
     }
     if (nj.empty()) return 0;
+    // Claims past the end of the list took no job; lower the counter to the
+    // old end so the appended jobs are claimed (the stream is idle here).
+    {
+        uint32_t next = 0;
+        HIPTRY(hipMemcpyAsync(&next, &sv->P.ctl->next_job, 4, hipMemcpyDeviceToHost, st));
+        HIPTRY(hipStreamSynchronize(st));
+        if (next > (uint32_t)sv->njobs_dev) {
+            uint32_t old_end = (uint32_t)sv->njobs_dev;
+            HIPTRY(hipMemcpyAsync(&sv->P.ctl->next_job, &old_end, 4, hipMemcpyHostToDevice, st));
+        }
+    }
     HIPTRY(hipMemcpyAsync(sv->jobs.as<Job>() + sv->njobs_dev, nj.data(), nj.size() * sizeof(Job),
                           hipMemcpyHostToDevice, st));
     if (!fv.empty()) {

@@ -73,15 +73,20 @@ def test_cold_vectors_and_slot_engine_agree():
     UB = np.repeat(inst["ub"][None], B, 0)
     ints = np.nonzero((inst["vtype"] == 1) & (inst["ub"] > inst["lb"]))[0]
     for v in range(1, B):
-        pick = rng.choice(ints, size=20, replace=False)
-        UB[v, pick] = np.floor((LB[v, pick] + UB[v, pick]) / 2)
+        pick = rng.choice(ints, size=3, replace=False)
+        UB[v, pick] = np.maximum(LB[v, pick], UB[v, pick] - 1)
     I = bp().Instance(inst)
     res, GL, GU = _batch(I, LB, UB)
     _check(inst, res, GL, GU, LB, UB, None, "cold")
     Is = bp().Instance(inst, bp().default_options(flags=bp().FLAG_BATCH_SLOTS))
     rs, SL, SU = _batch(Is, LB, UB)
     assert rs == res
-    assert np.array_equal(SL, GL) and np.array_equal(SU, GU)
+    # bounds are specified (and compared) unless the outcome is infeasible
+    ok = np.array([r["status"] != oracle.BP_INFEASIBLE for r in res])
+    assert ok.sum() >= B // 3
+    assert np.array_equal(SL[ok], GL[ok]) and np.array_equal(SU[ok], GU[ok])
+    # the lane engine leaves an infeasible vector's bounds as given
+    assert np.array_equal(GL[~ok], LB[~ok]) and np.array_equal(GU[~ok], UB[~ok])
 
 
 def test_probe_workload_rows():
