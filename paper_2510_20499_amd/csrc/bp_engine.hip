@@ -83,8 +83,10 @@ struct Shape {
     int64_t sn = 0, sm = 0;
     int64_t bin_cap[NBIN] = {0};
     int64_t heavy_chunks = 0;
+    int64_t heavy_rows = 0;
     bool covers(const Shape &o) const {
-        if (sn < o.sn || sm < o.sm || heavy_chunks < o.heavy_chunks) return false;
+        if (sn < o.sn || sm < o.sm || heavy_chunks < o.heavy_chunks || heavy_rows < o.heavy_rows)
+            return false;
         for (int b = 0; b < NBIN; ++b)
             if (bin_cap[b] < o.bin_cap[b]) return false;
         return true;
@@ -98,6 +100,9 @@ struct Engine {
     int64_t bytes = 0;
     DevBuf bnd, cand, vflag, rflag, info, chg, dirty, dlist, dcount, ctl, touched, filt;
     DevBuf q[2][NBIN], hrec[2], hpart, hrng;
+    // grouped heavy rows of job slots (allocated on request)
+    int32_t grouped = 0;
+    DevBuf ghmask[2], ghrec[2], ghpart, ghlive, dmaskg;
     // captured graph of `graph_rounds` rounds for this engine's Params
     hipGraphExec_t graph = nullptr;
     int graph_rounds = 0;
@@ -126,7 +131,10 @@ struct bp_instance {
     DevBuf st_var, st_lb, st_ub, st_off, st_cnt, scratch_i32;
     DevBuf st_status, st_rounds, st_nnz, st_jobs;  // per-job results and descriptors
     int64_t st_cap = 0;
-    DevBuf box_d, ptr_d;  // per-call box-check results and changed-list offsets
+    DevBuf box_d, ptr_d, idflag_d;  // per-call box check, changed offsets, id check
+    // base expansions of the heavy rows (grouped heavy rows of probe slots)
+    DevBuf ghidx_d, ghbase_d;
+    int64_t gh_version = -1;  // base_version they were computed for
     // row bins (host)
     int64_t bin_count[NBIN] = {0};
     int64_t bin_start[NBIN + 1] = {0};
@@ -332,6 +340,7 @@ static int validate_options(const bp_options &o) {
 // schedule.
 static int bin_rows(bp_instance *h, hipStream_t st) {
     const int64_t m = h->m;
+    h->gh_version = -1;  // the heavy rows change with the threshold
     for (int b = 0; b < NBIN; ++b) h->bin_count[b] = 0;
     std::vector<uint8_t> rbin(m);
     for (int64_t k = 0; k < m; ++k) {
@@ -491,15 +500,17 @@ static Shape shape_of(const bp_instance *h) {
     sh.sm = h->m;
     for (int b = 0; b < NBIN; ++b) sh.bin_cap[b] = h->bin_count[b];
     sh.heavy_chunks = h->heavy_chunks;
+    sh.heavy_rows = h->bin_count[BIN_HEAVY];
     return sh;
 }
 
 // (Re)allocate `E` for `slots` bound vectors of shape `sh`; dirty: with the
-// overlay bookkeeping of jobs; count: with the distinct-record bitmap.
+// overlay bookkeeping of jobs; count: with the distinct-record bitmap;
+// grouped: with the grouped heavy-row tasks of job slots.
 static int engine_alloc(std::unique_ptr<Engine> &eng, const Shape &sh, int32_t slots, bool dirty,
-                        bool count, hipStream_t st) {
+                        bool count, hipStream_t st, bool grouped = false) {
     if (eng && eng->cap_slots >= slots && eng->shape.covers(sh) && (!dirty || eng->track_dirty) &&
-        (!count || eng->touched.p))
+        (!count || eng->touched.p) && (!grouped || eng->grouped))
         return 0;
     eng.reset();
     std::unique_ptr<Engine> E(new Engine());
@@ -537,6 +548,23 @@ static int engine_alloc(std::unique_ptr<Engine> &eng, const Shape &sh, int32_t s
         HIPTRY(hipMemsetAsync(E->dirty.p, 0, E->dirty.bytes, st));
         HIPTRY(hipMemsetAsync(E->dcount.p, 0, E->dcount.bytes, st));
     }
+    if (grouped) {
+        // groups of 64 slots; per parity every chunk of every heavy row of
+        // every group may be queued
+        const int64_t NG = (S + 63) / 64;
+        const int64_t H = std::max<int64_t>(sh.heavy_rows, 1);
+        const int64_t cap = std::max<int64_t>(NG * sh.heavy_chunks, 1);
+        for (int par = 0; par < 2; ++par) {
+            if ((rc = E->ghmask[par].alloc((size_t)NG * H * 8, B))) return rc;
+            if ((rc = E->ghrec[par].alloc((size_t)cap * sizeof(int4), B))) return rc;
+            HIPTRY(hipMemsetAsync(E->ghmask[par].p, 0, E->ghmask[par].bytes, st));
+        }
+        if ((rc = E->ghpart.alloc((size_t)cap * 128 * sizeof(Acc), B))) return rc;
+        if ((rc = E->ghlive.alloc((size_t)cap * 8, B))) return rc;
+        if ((rc = E->dmaskg.alloc((size_t)NG * n * 8, B))) return rc;
+        HIPTRY(hipMemsetAsync(E->dmaskg.p, 0, E->dmaskg.bytes, st));
+        E->grouped = 1;
+    }
     HIPTRY(hipMemsetAsync(E->vflag.p, 0, E->vflag.bytes, st));
     HIPTRY(hipMemsetAsync(E->rflag.p, 0, E->rflag.bytes, st));
     HIPTRY(hipMemsetAsync(E->info.p, 0, E->info.bytes, st));
@@ -546,9 +574,10 @@ static int engine_alloc(std::unique_ptr<Engine> &eng, const Shape &sh, int32_t s
     return 0;
 }
 
-static int engine_ensure(bp_instance *h, int32_t slots, bool dirty, hipStream_t st) {
+static int engine_ensure(bp_instance *h, int32_t slots, bool dirty, hipStream_t st,
+                         bool grouped = false) {
     return engine_alloc(h->eng, shape_of(h), slots, dirty, (h->opt.flags & BP_FLAG_COUNT_VARS) != 0,
-                        st);
+                        st, grouped);
 }
 
 static DInst dinst_of(const bp_instance *h) {
@@ -600,6 +629,7 @@ static Params engine_params(const Engine &E, const bp_options &opt, int32_t heav
     P.dirty = E.dirty.as<uint32_t>();
     P.dlist = E.dlist.as<int32_t>();
     P.dcount = E.dcount.as<int32_t>();
+    P.gh = 0;  // enabled by bp_probe
     return P;
 }
 
@@ -793,6 +823,29 @@ static void fill_result(const SlotInfo &S, int32_t box_bad, bp_result *r) {
     }
 }
 
+// Any id outside [0, n) sets *bad.
+__global__ void k_check_ids(const int32_t *ids, int64_t count, int32_t n, int32_t *bad) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < count;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = ids[j];
+        if (v < 0 || v >= n) atomicOr(bad, 1);
+    }
+}
+
+// Changed-variable ids of a call checked on the device (BP_EINVAL if any
+// is out of range); only a flag comes back to the host.
+static int check_ids(bp_instance *h, const int32_t *ids, int64_t count, hipStream_t st) {
+    if (int rc = h->idflag_d.grow(4, h->bytes)) return rc;
+    int32_t zero = 0, bad = 0;
+    HIPTRY(hipMemcpyAsync(h->idflag_d.p, &zero, 4, hipMemcpyHostToDevice, st));
+    k_check_ids<<<grid_for(count), 256, 0, st>>>(ids, count, h->n, h->idflag_d.as<int32_t>());
+    HIPTRY(hipGetLastError());
+    HIPTRY(hipMemcpyAsync(&bad, h->idflag_d.p, 4, hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+    if (bad) return fail(BP_EINVAL, "changed variable id out of range");
+    return 0;
+}
+
 // Shared driver of bp_propagate (B = 1, base update) and bp_propagate_batch.
 static int propagate_slots(bp_instance *h, int32_t Bv, double *lb, double *ub,
                            const int32_t *changed_idx, const int64_t *changed_ptr,
@@ -825,13 +878,8 @@ static int propagate_slots(bp_instance *h, int32_t Bv, double *lb, double *ub,
     for (int32_t j = 0; j < Bv; ++j)
         if (box[2 * j + 1]) return fail(BP_EINVAL, "NaN bound in vector " + std::to_string(j));
     // Validate changed ids.
-    if (!cold && n_changed_total > 0) {
-        std::vector<int32_t> ids(n_changed_total);
-        HIPTRY(hipMemcpyAsync(ids.data(), changed_idx, ids.size() * 4, hipMemcpyDeviceToHost, st));
-        HIPTRY(hipStreamSynchronize(st));
-        for (int32_t v : ids)
-            if (v < 0 || v >= n) return fail(BP_EINVAL, "changed variable id out of range");
-    }
+    if (!cold && n_changed_total > 0)
+        if (int rc = check_ids(h, changed_idx, n_changed_total, st)) return rc;
     if (int rc = start_slots(h, P, Bv, st, changed_idx, changed_ptr, n_changed_total, cold)) return rc;
     // A slot whose box is already crossed is infeasible before any round;
     // its queued rows drain without running.
@@ -930,6 +978,82 @@ extern "C" int bp_kernel_stats(bp_instance *h, bp_stats *out, int reset) {
     return BP_OK;
 }
 
+// Exact sum of one side of row [p0, p1) at the base bounds, as a
+// non-overlapping expansion of up to GH_COMPS doubles (largest first).
+// Returns false if it needs more components.
+__device__ __noinline__ bool exact_expansion(const DInst &I, int64_t p0, int64_t p1, bool maxside,
+                                             double *out) {
+    SuperAcc S;
+    sa_zero(S);
+    for (int64_t p = p0; p < p1; ++p) {
+        const double a = I.val[p];
+        const double2 b = I.base[I.col[p]];
+        const double bb = (a > 0.0) != maxside ? b.x : b.y;
+        if (!isinf(bb)) sa_add(S, a * bb);
+    }
+    for (int q = 0; q < GH_COMPS; ++q) out[q] = 0.0;
+    for (int q = 0; q < GH_COMPS; ++q) {
+        SuperAcc T = S;  // sa_round works in place (it negates a negative state)
+        const double x = sa_round(T);
+        if (x == 0.0) return true;
+        out[q] = x;
+        sa_add(S, -x);  // exact: the remainder stays on the fixed-point grid
+    }
+    return sa_is_zero(S);
+}
+
+// Base expansions, infinite counts and widths of the heavy rows (one
+// workgroup per row); ghidx[k] = the row's index, or -1 if its expansion
+// does not fit (the row then stays on per-slot chunks).
+__global__ void __launch_bounds__(WG) k_gh_base(DInst I, const int32_t *hrows, int32_t H, GhBase *out,
+                                                int32_t *ghidx) {
+    __shared__ double sw[WG / 64];
+    __shared__ int snmin[WG / 64], snmax[WG / 64];
+    __shared__ int ok_s;
+    for (int hi = blockIdx.x; hi < H; hi += gridDim.x) {
+        const int k = hrows[hi];
+        const int64_t p0 = I.row_ptr[k], p1 = I.row_ptr[k + 1];
+        double w = 0.0;
+        int nmin = 0, nmax = 0;
+        for (int64_t p = p0 + threadIdx.x; p < p1; p += WG) {
+            const double a = I.val[p];
+            const double2 b = I.base[I.col[p]];
+            w = fmax(w, nz_width(a, b.x, b.y));
+            nmin += isinf(a > 0.0 ? b.x : b.y) ? 1 : 0;
+            nmax += isinf(a > 0.0 ? b.y : b.x) ? 1 : 0;
+        }
+        w = group_max<64>(w);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            nmin += __shfl_xor(nmin, o, 64);
+            nmax += __shfl_xor(nmax, o, 64);
+        }
+        if (__lane_id() == 0) {
+            sw[threadIdx.x >> 6] = w;
+            snmin[threadIdx.x >> 6] = nmin;
+            snmax[threadIdx.x >> 6] = nmax;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            GhBase &G = out[hi];
+            double ww = sw[0];
+            int a0 = snmin[0], a1 = snmax[0];
+            for (int q = 1; q < WG / 64; ++q) {
+                ww = fmax(ww, sw[q]);
+                a0 += snmin[q];
+                a1 += snmax[q];
+            }
+            G.rng = ww;
+            G.nmin = a0;
+            G.nmax = a1;
+            bool ok = exact_expansion(I, p0, p1, false, G.emin);
+            ok = exact_expansion(I, p0, p1, true, G.emax) && ok;
+            ghidx[k] = ok ? hi : -1;
+        }
+        __syncthreads();
+    }
+}
+
 // Probe variables must be integers whose base bounds lie in [0, 1].
 __global__ void k_check_probe_vars(const int32_t *vars, int32_t k, int32_t n, const uint8_t *vtype,
                                    const double2 *base, int32_t *bad) {
@@ -997,8 +1121,20 @@ extern "C" int bp_probe(bp_instance *h, const int32_t *vars, int32_t k, bp_probe
                                        " is not an integer with base bounds inside [0, 1]");
     }
     const int32_t S = (int32_t)std::min<int64_t>(std::max(1, h->opt.probe_slots), jobs);
-    if (int rc = engine_ensure(h, S, true, st)) return rc;
+    const int64_t H = h->bin_count[BIN_HEAVY];
+    if (int rc = engine_ensure(h, S, true, st, H > 0)) return rc;
     Engine &E = *h->eng;
+    // Base expansions of the heavy rows, once per base.
+    if (H > 0 && h->gh_version != h->base_version) {
+        if (int rc = h->ghidx_d.grow((size_t)std::max<int64_t>(h->m, 1) * 4, h->bytes)) return rc;
+        if (int rc = h->ghbase_d.grow((size_t)H * sizeof(GhBase), h->bytes)) return rc;
+        k_fill_i32<<<grid_for(h->m), 256, 0, st>>>(h->ghidx_d.as<int32_t>(), -1, h->m);
+        k_gh_base<<<(int)std::min<int64_t>(H, 4096), WG, 0, st>>>(
+            dinst_of(h), h->cold_rows.as<int32_t>() + h->bin_start[BIN_HEAVY], (int32_t)H,
+            h->ghbase_d.as<GhBase>(), h->ghidx_d.as<int32_t>());
+        HIPTRY(hipGetLastError());
+        h->gh_version = h->base_version;
+    }
     // Probe slots read the base except where their dirty bits are set; a
     // retired probe clears its bits, so no slot needs initialising.
     // Staging for the implied lists.
@@ -1028,6 +1164,19 @@ extern "C" int bp_probe(bp_instance *h, const int32_t *vars, int32_t k, bp_probe
     IO.stage_cap = cap;
     Params P = make_params(h, S);
     P.overlay = 1;
+    if (H > 0) {
+        P.gh = 1;
+        P.gH = (int32_t)H;
+        P.ghidx = h->ghidx_d.as<int32_t>();
+        P.ghbase = h->ghbase_d.as<GhBase>();
+        for (int par = 0; par < 2; ++par) {
+            P.ghmask[par] = E.ghmask[par].as<uint64_t>();
+            P.ghrec[par] = E.ghrec[par].as<int4>();
+        }
+        P.ghpart = E.ghpart.as<Acc>();
+        P.ghlive = E.ghlive.as<uint64_t>();
+        P.dmaskg = E.dmaskg.as<uint64_t>();
+    }
     invalidate_graph(h, P, &IO);
     Ctl c;
     memset(&c, 0, sizeof(c));

@@ -85,6 +85,7 @@ struct Ctl {
     uint32_t done;
     uint32_t qcount[2][NBIN];   // queue lengths per parity
     uint32_t hchunks[2];        // heavy chunks per parity
+    uint32_t ghchunks[2];       // grouped heavy chunk tasks per parity
     uint32_t nchanged;          // (slot, var) entries of the current round
     uint32_t active;            // slots active or draining after the last round end
     uint32_t finished;          // slots finished at the last round end
@@ -133,6 +134,29 @@ struct Params {
     uint32_t *dirty;             // [nslots][snw]
     int32_t *dlist;              // [nslots][sn]
     int32_t *dcount;             // [nslots]
+    // grouped heavy rows (jobs of one instance): a heavy row queued by any
+    // slot of a group of 64 is one task per chunk for the whole group; a
+    // slot's activity is the base row's exact sum plus the corrections of
+    // its dirty variables
+    int32_t gh;                  // enabled
+    int32_t gH;                  // heavy rows with a base expansion
+    const int32_t *ghidx;        // [m] index of the row's base expansion, -1 if none
+    const struct GhBase *ghbase; // [gH]
+    uint64_t *ghmask[2];         // [groups][gH] slots that queued the row
+    int4 *ghrec[2];              // (group, row, chunk, chunks of the row)
+    Acc *ghpart;                 // [task][2][64] per-slot corrections of a chunk
+    uint64_t *ghlive;            // [task] the row's slot mask, as read by the chunk
+    uint64_t *dmaskg;            // [groups][sn] slots of the group with var i dirty
+};
+
+// Exact activities of a heavy row at the base bounds: each finite part as a
+// non-overlapping expansion (sum of the components = the exact sum), the
+// counts of infinite contributions, and the row's slack-filter width.
+constexpr int GH_COMPS = 8;
+struct GhBase {
+    double emin[GH_COMPS], emax[GH_COMPS];
+    int32_t nmin, nmax;
+    double rng;
 };
 
 // Instance of slot s (MULTI: slots mix instances; otherwise the kernel
@@ -725,6 +749,148 @@ __device__ void heavy_chunk_candidates(const Params &P, int par, uint32_t u) {
     }
 }
 
+// ------------------------------------------------------------------------
+// Grouped heavy rows (jobs of one instance): one wave per chunk task, lane
+// l standing for slot 64*g + l.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t rl_u64(uint64_t x, int t) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, t);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), t);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Activity pass of a chunk: for every slot of the group with the row
+// queued, the exact corrections (its term minus the base term, and the
+// change of the infinite count) of the chunk's variables it has dirty.
+__device__ void gh_chunk_corrections(const Params &P, int par, uint32_t t) {
+    const int4 rec = P.ghrec[par][t];
+    const int g = rec.x, k = rec.y, c = rec.z;
+    const int lane = __lane_id();
+    const int s = g * 64 + lane;
+    const uint64_t word = P.ghmask[par][(size_t)g * P.gH + P.ghidx[k]];
+    const bool live = ((word >> lane) & 1ull) && s < P.nslots && P.info[s].state == SLOT_ACTIVE;
+    if (lane == 0) P.ghlive[t] = word;
+    const DInst &I = P.I;
+    const int64_t r0 = I.row_ptr[k], r1 = I.row_ptr[k + 1];
+    const int64_t p0 = r0 + (int64_t)c * P.heavy_chunk, p1 = min(r1, p0 + (int64_t)P.heavy_chunk);
+    const double2 *own = P.bnd + (size_t)s * P.sn;
+    const uint64_t *dm = P.dmaskg + (size_t)g * P.sn;
+    Acc mn, mx;
+    acc_zero(mn);
+    acc_zero(mx);
+    for (int64_t b0 = p0; b0 < p1; b0 += 64) {
+        const int64_t j = b0 + lane;
+        int i = 0;
+        double a = 0.0;
+        uint64_t w = 0;
+        if (j < p1) {
+            i = I.col[j];
+            a = I.val[j];
+            w = dm[i];
+        }
+        uint64_t any = __ballot(w != 0);
+        while (any) {
+            const int q = __ffsll((long long)any) - 1;
+            any &= any - 1;
+            const uint64_t wq = rl_u64(w, q);
+            if (live && ((wq >> lane) & 1ull)) {
+                const int iq = __builtin_amdgcn_readlane(i, q);
+                const long long ab = __double_as_longlong(a);
+                const double aq = __longlong_as_double(
+                    ((long long)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(ab >> 32), q) << 32) |
+                    (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)ab, q));
+                const double2 bo = own[iq], bb = I.base[iq];
+                // min side: lb for a > 0, ub for a < 0; max side the other
+                const double on = aq > 0.0 ? bo.x : bo.y, bn = aq > 0.0 ? bb.x : bb.y;
+                const double ox = aq > 0.0 ? bo.y : bo.x, bx = aq > 0.0 ? bb.y : bb.x;
+                if (isinf(on)) mn.ninf += 1; else acc_add(mn, aq * on);
+                if (isinf(bn)) mn.ninf -= 1; else acc_add(mn, -(aq * bn));
+                if (isinf(ox)) mx.ninf += 1; else acc_add(mx, aq * ox);
+                if (isinf(bx)) mx.ninf -= 1; else acc_add(mx, -(aq * bx));
+            }
+        }
+    }
+    P.ghpart[(size_t)t * 128 + lane] = mn;
+    P.ghpart[(size_t)t * 128 + 64 + lane] = mx;
+}
+
+// Candidate pass of a chunk: each slot's row activity (base expansion plus
+// the corrections of every chunk, certified, exact fallback), row test,
+// slack filter, then the chunk's candidates for the slots that need them.
+template <bool MULTI>
+__device__ void gh_chunk_candidates(const Params &P, int par, uint32_t t) {
+    const int4 rec = P.ghrec[par][t];
+    const int g = rec.x, k = rec.y, c = rec.z, nch = rec.w;
+    const int lane = __lane_id();
+    const int s = g * 64 + lane;
+    const uint64_t word = P.ghlive[t];
+    const bool live = ((word >> lane) & 1ull) && s < P.nslots && P.info[s].state == SLOT_ACTIVE;
+    const DInst &I = P.I;
+    const int hi = P.ghidx[k];
+    if (c == 0 && lane == 0) P.ghmask[par][(size_t)g * P.gH + hi] = 0ull;
+    // every slot that queued the row (draining ones included) may queue it
+    // again from the next round on
+    if (c == 0 && ((word >> lane) & 1ull) && s < P.nslots) clear_rflag(P, s, k);
+    const GhBase &GB = P.ghbase[hi];
+    Acc A, B;
+    acc_zero(A);
+    acc_zero(B);
+#pragma unroll 1
+    for (int q = 0; q < GH_COMPS; ++q) {
+        if (GB.emin[q] != 0.0) acc_add(A, GB.emin[q]);
+        if (GB.emax[q] != 0.0) acc_add(B, GB.emax[q]);
+    }
+    A.ninf = GB.nmin;
+    B.ninf = GB.nmax;
+    const uint32_t u0 = t - (uint32_t)c;
+    for (int j = 0; j < nch; ++j) {
+        const Acc a = P.ghpart[(size_t)(u0 + j) * 128 + lane];
+        const Acc b = P.ghpart[(size_t)(u0 + j) * 128 + 64 + lane];
+        acc_merge(A, a.s, a.c, a.e, a.ninf);
+        acc_merge(B, b.s, b.c, b.e, b.ninf);
+    }
+    const int64_t r0 = I.row_ptr[k], r1 = I.row_ptr[k + 1];
+    const BView bnd = bview(P, s, I.base);
+    RowAct R;
+    R.nmin = A.ninf;
+    R.nmax = B.ninf;
+    R.minfin = 0.0;
+    R.maxfin = 0.0;
+    R.rng = GB.rng;  // the base width bounds every slot's (job bounds only shrink)
+    const double2 sd = I.side[k];
+    R.lo = sd.x;
+    R.hi = sd.y;
+    bool ok_min = live && !P.force_exact && acc_certify(A, R.minfin);
+    bool ok_max = live && !P.force_exact && acc_certify(B, R.maxfin);
+    if (live && !ok_min) R.minfin = exact_side(I, bnd, r0, r1, false);
+    if (live && !ok_max) R.maxfin = exact_side(I, bnd, r0, r1, true);
+    bool bad = false;
+    if (live) {
+        bad = row_bad(R, P.feastol);
+        if (bad && c == 0) report_bad_row(P, s, k);
+    }
+    const bool want = live && !bad && !row_quiet(R);
+    if (__ballot(want) == 0) return;
+    const int64_t p0 = r0 + (int64_t)c * P.heavy_chunk, p1 = min(r1, p0 + (int64_t)P.heavy_chunk);
+    const uint64_t *dm = P.dmaskg + (size_t)g * P.sn;
+    const double2 *own = P.bnd + (size_t)s * P.sn;
+    for (int64_t p = p0; p < p1; ++p) {
+        const int i = I.col[p];
+        const double a = I.val[p];
+        const uint64_t w = dm[i];
+        double2 b = I.base[i];
+        if ((w >> lane) & 1ull) b = own[i];
+        bool need = false;
+        if (want) {
+            const bool is_int = I.vtype[i] != 0;
+            double cl, cu;
+            nz_candidates(R, a, b.x, b.y, is_int, P.inttol, cl, cu);
+            need = scatter(P, s, i, cl, cu, b.x, b.y, is_int);
+        }
+        mark_var(P, need, s, i);
+    }
+}
+
 __device__ inline uint32_t light_units(uint32_t count, int b) {
     uint32_t G = (uint32_t)light_group(b);
     return (uint32_t)(((uint64_t)count * G + WG - 1) / WG);
@@ -739,10 +905,13 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(BP_ROWS
     const Ctl *C = P.ctl;
     if (C->done) return;
     const int par = C->round & 1;
-    // Work units: heavy chunks, block rows, then light bins 10..0.
+    // Work units: grouped heavy chunk tasks (four per unit, one per wave),
+    // heavy chunks, block rows, then light bins 10..0.
+    const uint32_t ngh = C->ghchunks[par];
+    const uint32_t gh_units = (ngh + (WG / 64) - 1) / (WG / 64);
     uint32_t start[NBIN + 2];
-    start[0] = 0;
-    start[1] = C->hchunks[par];
+    start[0] = gh_units;
+    start[1] = start[0] + C->hchunks[par];
     start[2] = start[1] + C->qcount[par][BIN_BLOCK];
     for (int j = 0; j < NLIGHT; ++j) {
         int b = NLIGHT - 1 - j;
@@ -750,8 +919,11 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(BP_ROWS
     }
     const uint32_t total = start[2 + NLIGHT];
     for (uint32_t u = blockIdx.x; u < total; u += gridDim.x) {
-        if (u < start[1]) {
-            heavy_chunk_activity<MULTI>(P, par, u, W);
+        if (u < start[0]) {
+            const uint32_t t = u * (WG / 64) + (threadIdx.x >> 6);
+            if (t < ngh) gh_chunk_corrections(P, par, t);
+        } else if (u < start[1]) {
+            heavy_chunk_activity<MULTI>(P, par, u - start[0], W);
         } else if (u < start[2]) {
             block_row<MULTI>(P, P.q[par][BIN_BLOCK], u - start[1], W);
         } else {
@@ -780,8 +952,17 @@ __global__ void __launch_bounds__(WG) k_heavy(Params P) {
     const Ctl *C = P.ctl;
     if (C->done) return;
     const int par = C->round & 1;
-    const uint32_t total = C->hchunks[par];
-    for (uint32_t u = blockIdx.x; u < total; u += gridDim.x) heavy_chunk_candidates<MULTI>(P, par, u);
+    const uint32_t ngh = C->ghchunks[par];
+    const uint32_t gh_units = (ngh + (WG / 64) - 1) / (WG / 64);
+    const uint32_t total = gh_units + C->hchunks[par];
+    for (uint32_t u = blockIdx.x; u < total; u += gridDim.x) {
+        if (u < gh_units) {
+            const uint32_t t = u * (WG / 64) + (threadIdx.x >> 6);
+            if (t < ngh) gh_chunk_candidates<MULTI>(P, par, t);
+        } else {
+            heavy_chunk_candidates<MULTI>(P, par, u - gh_units);
+        }
+    }
 }
 
 // ------------------------------------------------------------------------
@@ -818,9 +999,22 @@ __device__ __forceinline__ void append_rows(const Params &P, int par, bool first
     if (!__any(first)) return;
     const int lane = __lane_id();
     if (first && bin == BIN_HEAVY) {
-        int nch = (int)((len + P.heavy_chunk - 1) / P.heavy_chunk);
-        uint32_t cb = atomicAdd(&P.ctl->hchunks[par], (uint32_t)nch);
-        for (int c = 0; c < nch; ++c) P.hrec[par][cb + c] = make_int4(s, k, c, nch);
+        const int nch = (int)((len + P.heavy_chunk - 1) / P.heavy_chunk);
+        const int hi = P.gh ? P.ghidx[k] : -1;
+        if (hi >= 0) {
+            // grouped: the first slot of the group to queue the row adds
+            // the group's chunk tasks
+            const int g = s >> 6;
+            const uint64_t old = atomicOr((unsigned long long *)&P.ghmask[par][(size_t)g * P.gH + hi],
+                                          1ull << (s & 63));
+            if (old == 0) {
+                uint32_t cb = atomicAdd(&P.ctl->ghchunks[par], (uint32_t)nch);
+                for (int c = 0; c < nch; ++c) P.ghrec[par][cb + c] = make_int4(g, k, c, nch);
+            }
+        } else {
+            uint32_t cb = atomicAdd(&P.ctl->hchunks[par], (uint32_t)nch);
+            for (int c = 0; c < nch; ++c) P.hrec[par][cb + c] = make_int4(s, k, c, nch);
+        }
     }
     const bool lt = first && bin != BIN_HEAVY;
     uint32_t cnt = 0;
@@ -915,6 +1109,8 @@ __device__ void enqueue_columns(const Params &P, int par, bool want, int s, long
 __device__ __forceinline__ void mark_dirty(const Params &P, int s, int i) {
     uint32_t bit = 1u << (i & 31);
     uint32_t old = atomicOr(&P.dirty[(size_t)s * P.snw + (i >> 5)], bit);
+    if (P.gh && (old & bit) == 0)
+        atomicOr((unsigned long long *)&P.dmaskg[(size_t)(s >> 6) * P.sn + i], 1ull << (s & 63));
     uint32_t h = fhash(i);
     atomicOr(&P.filt[(size_t)s * FILT_WORDS + (h >> 5)], 1u << (h & 31));
     if ((old & bit) == 0) {
@@ -982,6 +1178,7 @@ __global__ void __launch_bounds__(WG) k_end(Params P) {
     if (threadIdx.x == 0) {
         for (int b = 0; b < NBIN; ++b) C->qcount[par][b] = 0;
         C->hchunks[par] = 0;
+        C->ghchunks[par] = 0;
         C->nchanged = 0;
         C->active = s_active;
         C->finished = s_finished;
@@ -1202,6 +1399,8 @@ __device__ void restore_slot(const Params &P, int s, int cnt) {
         // every set bit of these words belongs to this list
         dw[i >> 5] = 0u;
         fw[fhash(i) >> 5] = 0u;
+        if (P.gh)
+            atomicAnd((unsigned long long *)&P.dmaskg[(size_t)(s >> 6) * P.sn + i], ~(1ull << (s & 63)));
     }
     __syncthreads();
     if (threadIdx.x == 0) P.dcount[s] = 0;

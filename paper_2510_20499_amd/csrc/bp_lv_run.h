@@ -244,13 +244,8 @@ static int lv_piece(bp_instance *h, int32_t Bp, double *lb, double *ub, const in
     HIPTRY(hipStreamSynchronize(st));
     for (int32_t j = 0; j < Bp; ++j)
         if (box[2 * j + 1]) return fail(BP_EINVAL, "NaN bound in vector " + std::to_string(j));
-    if (!cold && ecount > 0) {
-        std::vector<int32_t> ids(ecount);
-        HIPTRY(hipMemcpyAsync(ids.data(), idx + e0, ids.size() * 4, hipMemcpyDeviceToHost, st));
-        HIPTRY(hipStreamSynchronize(st));
-        for (int32_t v : ids)
-            if (v < 0 || v >= n) return fail(BP_EINVAL, "changed variable id out of range");
-    }
+    if (!cold && ecount > 0)
+        if (int rc = check_ids(h, idx + e0, ecount, st)) return rc;
     // control block, vectors, seeds
     LvCtl c;
     memset(&c, 0, sizeof(c));

@@ -136,6 +136,7 @@ extern "C" int bp_server_create(bp_instance *const *instances, int32_t count, co
         sh.sm = std::max(sh.sm, s1.sm);
         for (int b = 0; b < NBIN; ++b) sh.bin_cap[b] = std::max(sh.bin_cap[b], s1.bin_cap[b]);
         sh.heavy_chunks = std::max(sh.heavy_chunks, s1.heavy_chunks);
+        sh.heavy_rows = std::max(sh.heavy_rows, s1.heavy_rows);
         sv->insts.push_back(h);
     }
     sv->bytes_per_slot = slot_bytes(sh);

@@ -176,6 +176,13 @@ __device__ __noinline__ void sa_add(SuperAcc &S, double x) {
     }
 }
 
+__device__ inline bool sa_is_zero(const SuperAcc &S) {
+    uint64_t x = 0;
+#pragma unroll 1
+    for (int i = 0; i < SA_WORDS; ++i) x |= S.w[i];
+    return x == 0;
+}
+
 // Bits [lo, lo+cnt) of the magnitude (cnt <= 64), lo may be negative.
 __device__ inline uint64_t sa_bits(const SuperAcc &S, int lo, int cnt) {
     uint64_t r = 0;
@@ -198,6 +205,8 @@ __device__ inline bool sa_any_below(const SuperAcc &S, int lim) {
     return false;
 }
 
+// Correctly rounded value of the accumulator.  Destroys the state: a
+// negative accumulator is negated in place.
 __device__ __noinline__ double sa_round(SuperAcc &S) {
     bool neg = (S.w[SA_WORDS - 1] >> 63) != 0;
     if (neg) {  // magnitude = two's complement negation

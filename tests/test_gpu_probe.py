@@ -93,6 +93,26 @@ def test_single_scaled_with_heavy_rows():
     _probe_both(inst, vs, slots=32, opts_kw=dict(heavy_threshold=1024))
 
 
+@pytest.mark.parametrize("slots,chunk", [(200, 256), (64, 1024)])
+def test_grouped_heavy_rows(slots, chunk):
+    """Heavy rows of probe slots are processed per group of 64 slots from
+    the base row's exact expansion plus each slot's dirty corrections:
+    several groups (the last one partial), several chunks per row."""
+    inst = gen.make("probe", 2, scale=0.05)
+    assert (np.diff(inst["row_ptr"]) > 1024).sum() > 20
+    _, lb, ub = oracle.propagate(inst)
+    vs = gen.pick_probe_vars(inst, lb, ub, 300, seed=2)
+    _probe_both(inst, vs, slots=slots, opts_kw=dict(heavy_threshold=1024, heavy_chunk=chunk))
+
+
+def test_grouped_heavy_rows_exact_path():
+    inst = gen.make("single", 4, scale=0.1)
+    _, lb, ub = oracle.propagate(inst)
+    vs = gen.pick_probe_vars(inst, lb, ub, 100, seed=4)
+    _probe_both(inst, vs, slots=128,
+                opts_kw=dict(heavy_threshold=1024, heavy_chunk=512, flags=bp().FLAG_FORCE_EXACT))
+
+
 def test_long_implication_list_uses_bitmap_path():
     # y + x_j <= 1 for 5000 binaries x_j: probing y = 1 fixes all of them.
     m = 5000
