@@ -24,6 +24,33 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E datasheet peak
 
 
+# HBM traffic of k_rows on the single-instance workload, from rocprofv3
+# --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of `bench.py --profile-steps 5`
+# (averages over its 400 launches), scaled by what the same counters read
+# for a 1 GiB device copy (FETCH_SIZE x2.0, WRITE_SIZE x1.0).  The figure
+# belongs to the kernel sources it was measured on: when any of them
+# differs, the bench line reports null.
+K_ROWS_TRAFFIC = {
+    "fetch_kib": 10909.5, "write_kib": 845.4, "fetch_scale": 2.0, "write_scale": 1.0,
+    "sources": {
+        "paper_2510_20499_amd/csrc/bp_kernels.h": "3908f4238343d5efadb1365e4ccb8afab6790c668ef217456da888bfc1a72ab0",
+        "paper_2510_20499_amd/csrc/bp_sum.h": "833f834eb740e1aaeae0a7fe22dd2566f3b231f64aa197bf2945502c9275c3e9",
+        "paper_2510_20499_amd/build.py": "c136435afc6346a2636062ac8e92ff4589056551b3201f87db712a04372cec3e",
+    },
+}
+
+
+def measured_traffic():
+    """HBM bytes per k_rows launch, or None when the sources changed."""
+    import hashlib
+    for rel, digest in K_ROWS_TRAFFIC["sources"].items():
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != digest:
+                return None
+    t = K_ROWS_TRAFFIC
+    return int((t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024)
+
+
 def log(msg):
     """Progress line on stderr (the JSON result goes to stdout)."""
     print(msg, file=sys.stderr, flush=True)
@@ -169,6 +196,7 @@ def main():
     value = total_nnz / dt
 
     roofline = kernel_roofline(bp, inst, lambda J: J.propagate(*fresh(lb0, ub0)))
+    roofline["traffic"] = measured_traffic()
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -978,19 +978,22 @@ extern "C" int bp_kernel_stats(bp_instance *h, bp_stats *out, int reset) {
     return BP_OK;
 }
 
-// Exact sum of one side of row [p0, p1) at the base bounds, as a
-// non-overlapping expansion of up to GH_COMPS doubles (largest first).
-// Returns false if it needs more components.
-__device__ __noinline__ bool exact_expansion(const DInst &I, int64_t p0, int64_t p1, bool maxside,
-                                             double *out) {
-    SuperAcc S;
+// One thread's share of the exact sum of one side of row [p0, p1) at the
+// base bounds: the nonzeros p0 + t, p0 + t + WG, ...
+__device__ __noinline__ void exact_share(const DInst &I, int64_t p0, int64_t p1, bool maxside,
+                                         SuperAcc &S) {
     sa_zero(S);
-    for (int64_t p = p0; p < p1; ++p) {
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += WG) {
         const double a = I.val[p];
         const double2 b = I.base[I.col[p]];
         const double bb = (a > 0.0) != maxside ? b.x : b.y;
         if (!isinf(bb)) sa_add(S, a * bb);
     }
+}
+
+// The accumulator's value as a non-overlapping expansion of up to GH_COMPS
+// doubles (largest first); false if it needs more.
+__device__ __noinline__ bool sa_expansion(SuperAcc &S, double *out) {
     for (int q = 0; q < GH_COMPS; ++q) out[q] = 0.0;
     for (int q = 0; q < GH_COMPS; ++q) {
         SuperAcc T = S;  // sa_round works in place (it negates a negative state)
@@ -1004,11 +1007,17 @@ __device__ __noinline__ bool exact_expansion(const DInst &I, int64_t p0, int64_t
 
 // Base expansions, infinite counts and widths of the heavy rows (one
 // workgroup per row); ghidx[k] = the row's index, or -1 if its expansion
-// does not fit (the row then stays on per-slot chunks).
+// does not fit (the row then stays on per-slot chunks).  Each thread sums
+// its share of the row exactly; the shares are added word by word in 32-bit
+// halves (the sum of the two's-complement words modulo 2^2176 is the
+// two's-complement sum) and one carry pass gives the row's accumulator.
 __global__ void __launch_bounds__(WG) k_gh_base(DInst I, const int32_t *hrows, int32_t H, GhBase *out,
                                                 int32_t *ghidx) {
+    __shared__ uint64_t words[SA_WORDS][WG];
+    __shared__ uint64_t lo_sum[SA_WORDS], hi_sum[SA_WORDS];
     __shared__ double sw[WG / 64];
     __shared__ int snmin[WG / 64], snmax[WG / 64];
+    __shared__ SuperAcc tot;
     __shared__ int ok_s;
     for (int hi = blockIdx.x; hi < H; hi += gridDim.x) {
         const int k = hrows[hi];
@@ -1033,9 +1042,10 @@ __global__ void __launch_bounds__(WG) k_gh_base(DInst I, const int32_t *hrows, i
             snmin[threadIdx.x >> 6] = nmin;
             snmax[threadIdx.x >> 6] = nmax;
         }
+        if (threadIdx.x == 0) ok_s = 1;
         __syncthreads();
+        GhBase &G = out[hi];
         if (threadIdx.x == 0) {
-            GhBase &G = out[hi];
             double ww = sw[0];
             int a0 = snmin[0], a1 = snmax[0];
             for (int q = 1; q < WG / 64; ++q) {
@@ -1046,10 +1056,39 @@ __global__ void __launch_bounds__(WG) k_gh_base(DInst I, const int32_t *hrows, i
             G.rng = ww;
             G.nmin = a0;
             G.nmax = a1;
-            bool ok = exact_expansion(I, p0, p1, false, G.emin);
-            ok = exact_expansion(I, p0, p1, true, G.emax) && ok;
-            ghidx[k] = ok ? hi : -1;
         }
+        for (int side = 0; side < 2; ++side) {
+            SuperAcc S;
+            exact_share(I, p0, p1, side == 1, S);
+            for (int q = 0; q < SA_WORDS; ++q) words[q][threadIdx.x] = S.w[q];
+            __syncthreads();
+            if (threadIdx.x < SA_WORDS) {
+                uint64_t l = 0, h = 0;  // at most 256 * 2^32 each: no overflow
+                for (int t = 0; t < WG; ++t) {
+                    const uint64_t x = words[threadIdx.x][t];
+                    l += x & 0xffffffffull;
+                    h += x >> 32;
+                }
+                lo_sum[threadIdx.x] = l;
+                hi_sum[threadIdx.x] = h;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                // word q of the total = lo + (hi << 32) + carry, modulo 2^64
+                unsigned __int128 carry = 0;
+                for (int q = 0; q < SA_WORDS; ++q) {
+                    const unsigned __int128 v =
+                        (unsigned __int128)lo_sum[q] + ((unsigned __int128)hi_sum[q] << 32) + carry;
+                    tot.w[q] = (uint64_t)v;
+                    carry = v >> 64;
+                }
+                SuperAcc T = tot;
+                const bool ok = sa_expansion(T, side == 0 ? G.emin : G.emax);
+                if (!ok) ok_s = 0;
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) ghidx[k] = ok_s ? hi : -1;
         __syncthreads();
     }
 }
