@@ -9,8 +9,13 @@ resident in device memory before the timed region; each step restores the
 initial bounds with a device-to-device copy and calls bp_propagate.
 
 Output: one JSON line with propagated nonzeros per second, the roofline of
-the activity kernel (algorithmic bytes per launch over its HIP-event time)
-and the CPU oracle timed on a bounded sample of the same workload.
+the activity kernel (algorithmic bytes per launch over its HIP-event time,
+with the measured HBM traffic when the kernel sources match) and the CPU
+oracle timed on a bounded sample of the same workload.  The same line
+carries the batched forms: double probing of 4096 binaries of the probe
+workload, bulk fix-and-propagate of 256 vectors of the bulk workload, and
+serving a Poisson request stream over 64 resident instances (p50/p99),
+each against its one-at-a-time baseline on the same GPU.
 """
 import argparse
 import json
@@ -106,8 +111,8 @@ def main():
     ap.add_argument("--probe-vars", type=int, default=4096)
     ap.add_argument("--probe-plain", type=int, default=256,
                     help="binaries probed one call at a time for the plain baseline")
-    ap.add_argument("--serving", action="store_true",
-                    help="also run the serving measurement (64-instance mix, Poisson requests)")
+    ap.add_argument("--skip-serving", action="store_true",
+                    help="skip the serving measurement (64-instance mix, Poisson requests)")
     ap.add_argument("--only-serving", action="store_true")
     ap.add_argument("--serve-instances", type=int, default=64)
     ap.add_argument("--serve-mmax", type=float, default=1e6)
@@ -129,7 +134,7 @@ def main():
                          "for profilers) and exit")
     ap.add_argument("--only-probe", action="store_true",
                     help="run only the double-probing measurement (for profilers)")
-    ap.add_argument("--probe-cpu", type=int, default=0,
+    ap.add_argument("--probe-cpu", type=int, default=16,
                     help="binaries the oracle probes for a CPU probing rate (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -217,7 +222,7 @@ def main():
 
     probe = None if args.skip_probe else bench_probe(args, bp, gen, torch, np)
     bulk = None if args.skip_bulk else bench_bulk(args, bp, gen, torch, np)
-    serving = bench_serving(args, bp, gen, torch, np) if args.serving else None
+    serving = None if args.skip_serving else bench_serving(args, bp, gen, torch, np)
 
     out = {
         "metric": "propagated nnz/s (plain cold propagation, single instance)",
@@ -309,7 +314,8 @@ def bench_probe(args, bp, gen, torch, np):
         tc = time.perf_counter() - tc
         res["cpu_baseline"] = {"value": 2 * kc / tc, "unit": "probes/s", "cores": 1,
                                "kind": "oracle", "nnz_per_s": float(O["nnz"].sum()) / tc,
-                               "sample": "%d binaries x {0,1}" % kc}
+                               "sample": "%d binaries x {0,1} of the same sample, around the "
+                                         "oracle's own root fixed point, one thread" % kc}
     return res
 
 
