@@ -541,11 +541,43 @@ fail:
     return rc;
 }
 
-/* PROBE (Section 2.2): for each listed binary j and v in {0, 1}, propagate
- * from the base (lb, ub) with j fixed to v.  Probe p = 2t + v.  Implied
- * list of a feasible (or round-limited) probe: every variable whose bounds
- * differ from the base, ascending.  Infeasible probes list nothing.
- * Returns ORC_ECAPACITY (with *required set) if cap is too small. */
+/* The box of probe h (0 or 1) of integer variable j with base bounds
+ * [l, u] (Section 2.2, probing cache):
+ *   - base inside [0, 1] (a binary): x = h;
+ *   - both bounds finite: x < (l + u) / 2, i.e. [l, ceil((l + u) / 2) - 1],
+ *     and x >= (l + u) / 2, i.e. [ceil((l + u) / 2), u];
+ *   - only l finite: x = l, and x >= l + 1;
+ *   - only u finite (the mirror case): x <= u - 1, and x = u.
+ * Returns 0, or -1 for a variable with no finite bound. */
+int orc_probe_box(double l, double u, int h, double *nl, double *nu) {
+    const double INF = HUGE_VAL;
+    if (l >= 0.0 && u <= 1.0) {
+        *nl = (double)h;
+        *nu = (double)h;
+    } else if (l > -INF && u < INF) {
+        double c = ceil((l + u) / 2.0);
+        if (h == 0) { *nl = l; *nu = c - 1.0; }
+        else { *nl = c; *nu = u; }
+    } else if (l > -INF) {
+        if (h == 0) { *nl = l; *nu = l; }
+        else { *nl = l + 1.0; *nu = u; }
+    } else if (u < INF) {
+        if (h == 0) { *nl = l; *nu = u - 1.0; }
+        else { *nl = u; *nu = u; }
+    } else {
+        return -1;
+    }
+    return 0;
+}
+
+/* PROBE (Section 2.2): for each listed integer variable j and h in {0, 1},
+ * propagate from the base (lb, ub) with j restricted to the box of probe h
+ * (orc_probe_box) intersected with its base bounds.  Probe p = 2t + h.  An
+ * empty box is infeasible before any round; a box equal to the base bounds
+ * changes nothing.  Implied list of a feasible (or round-limited) probe:
+ * every variable whose bounds differ from the base, ascending.  Infeasible
+ * probes list nothing.  Returns ORC_ECAPACITY (with *required set) if cap
+ * is too small. */
 int orc_probe(const orc_instance *I, const double *base_lb, const double *base_ub,
               const int32_t *vars, int32_t k, const orc_options *o, int mode,
               int8_t *status, int32_t *rounds, int64_t *nnz, int32_t *n_infeasible_rows,
@@ -560,27 +592,33 @@ int orc_probe(const orc_instance *I, const double *base_lb, const double *base_u
     int rc_all = 0;
     for (int32_t t = 0; t < k; ++t) {
         int32_t j = vars[t];
-        if (j < 0 || j >= n || I->vtype[j] == 0 || base_lb[j] < 0.0 || base_ub[j] > 1.0) {
+        double box[2][2];
+        if (j < 0 || j >= n || I->vtype[j] == 0 ||
+            orc_probe_box(base_lb[j], base_ub[j], 0, &box[0][0], &box[0][1]) != 0) {
             free(lb); free(ub);
             return ORC_EINVAL;
         }
-        for (int v = 0; v < 2; ++v) {
-            int64_t p = 2 * (int64_t)t + v;
-            double fv = (double)v;
+        orc_probe_box(base_lb[j], base_ub[j], 1, &box[1][0], &box[1][1]);
+        for (int h = 0; h < 2; ++h) {
+            int64_t p = 2 * (int64_t)t + h;
+            /* the box intersected with the base bounds */
+            double nl = box[h][0] > base_lb[j] ? box[h][0] : base_lb[j];
+            double nu = box[h][1] < base_ub[j] ? box[h][1] : base_ub[j];
+            int same = nl == base_lb[j] && nu == base_ub[j];
             orc_result r;
             memset(&r, 0, sizeof(r));
             r.infeasible_row = -1;
             r.infeasible_var = -1;
-            if (fv < base_lb[j] || fv > base_ub[j]) {
+            if (nl > nu) {
                 r.status = ORC_INFEASIBLE;
                 r.infeasible_var = j;
-            } else if (base_lb[j] == fv && base_ub[j] == fv) {
+            } else if (same) {
                 r.status = ORC_OK;
             } else {
                 memcpy(lb, base_lb, (size_t)n * sizeof(double));
                 memcpy(ub, base_ub, (size_t)n * sizeof(double));
-                lb[j] = fv;
-                ub[j] = fv;
+                lb[j] = nl;
+                ub[j] = nu;
                 int rc = orc_propagate(I, lb, ub, &j, 1, o, mode, &r);
                 if (rc < 0) { free(lb); free(ub); return rc; }
             }
@@ -589,7 +627,7 @@ int orc_probe(const orc_instance *I, const double *base_lb, const double *base_u
             nnz[p] = r.nnz_propagated;
             if (n_infeasible_rows) n_infeasible_rows[p] = r.n_infeasible_rows;
             int64_t cnt = 0;
-            if (r.status != ORC_INFEASIBLE && !(base_lb[j] == fv && base_ub[j] == fv)) {
+            if (r.status != ORC_INFEASIBLE && !same) {
                 for (int64_t i = 0; i < n; ++i) {
                     if (lb[i] != base_lb[i] || ub[i] != base_ub[i]) {
                         if (total + cnt < cap) {

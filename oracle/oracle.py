@@ -75,6 +75,9 @@ def bind(path: str):
     lib.orc_propagate.restype = C.c_int
     lib.orc_propagate.argtypes = [C.POINTER(_Inst), C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_int64, C.POINTER(_Opt), C.c_int, C.POINTER(_Res)]
+    lib.orc_probe_box.restype = C.c_int
+    lib.orc_probe_box.argtypes = [C.c_double, C.c_double, C.c_int, C.POINTER(C.c_double),
+                                  C.POINTER(C.c_double)]
     lib.orc_probe.restype = C.c_int
     lib.orc_probe.argtypes = [C.POINTER(_Inst), C.c_void_p, C.c_void_p, C.c_void_p,
                               C.c_int32, C.POINTER(_Opt), C.c_int] + [C.c_void_p] * 8 + \
@@ -152,9 +155,12 @@ def propagate(inst, lb=None, ub=None, changed=None, opts: Options = None,
 
 def probe(inst, base_lb, base_ub, vars_, opts: Options = None, mode: int = MODE_WORKLIST,
           lib=None):
-    """Double probing of binaries around the base.  Returns a dict of arrays:
-    status/rounds/nnz/n_infeasible_rows per probe (probe 2t+v is vars[t]=v),
-    off[2k+1] and the concatenated implied (var, lb, ub) lists."""
+    """Double probing of integer variables around the base (Section 2.2).
+    Probe 2t+h restricts vars[t] to probe_box(l, u, h): x = h for a binary,
+    the halves split at (l + u) / 2 for a boxed integer, x = l / x >= l + 1
+    (x <= u - 1 / x = u) for a one-sided one.  Returns a dict of arrays:
+    status/rounds/nnz/n_infeasible_rows per probe, off[2k+1] and the
+    concatenated implied (var, lb, ub) lists."""
     lib = lib or load()
     h = _Held(inst)
     base_lb = np.ascontiguousarray(base_lb, dtype=np.float64)
@@ -184,3 +190,14 @@ def probe(inst, base_lb, base_ub, vars_, opts: Options = None, mode: int = MODE_
         tot = int(off[-1])
         return dict(status=st, rounds=rd, nnz=nz, n_infeasible_rows=nir, off=off,
                     var=iv[:tot].copy(), lb=il[:tot].copy(), ub=iu[:tot].copy())
+
+
+def probe_box(l, u, h, lib=None):
+    """The box (lo, hi) probe h in {0, 1} restricts an integer variable with
+    base bounds [l, u] to, before intersecting with [l, u]; None for a
+    variable with no finite bound."""
+    lib = lib or load()
+    a, b = C.c_double(), C.c_double()
+    if lib.orc_probe_box(float(l), float(u), int(h), C.byref(a), C.byref(b)) != 0:
+        return None
+    return a.value, b.value

@@ -37,12 +37,14 @@ MUTANTS = {
         "for (int64_t p = w.col_ptr[i]; p < w.col_ptr[i + 1]; ++p) add_row(I, &w, w.col_row[p], &nrows);\n        }\n    }",
         "for (int64_t p = w.col_ptr[i] + 1; p < w.col_ptr[i + 1]; ++p) add_row(I, &w, w.col_row[p], &nrows);\n        }\n    }"),
     "division_operand": ("double c = v / a;", "double c = v / fabs(a);"),
+    "probe_split_rounded_down": ("double c = ceil((l + u) / 2.0);", "double c = floor((l + u) / 2.0);"),
+    "probe_one_sided_step": ("else { *nl = l + 1.0; *nu = u; }", "else { *nl = l; *nu = u; }"),
 }
 
 
 def _pins_hold(lib) -> bool:
     try:
-        for name in ("w1", "w2", "w3"):
+        for name in ("w1", "w2", "w3", "w4"):
             inst, d = load_golden(name)
             r, lb, ub = oracle.propagate(inst, lib=lib)
             c = d["cold"]

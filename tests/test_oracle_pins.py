@@ -27,7 +27,7 @@ INF = float("inf")
 
 
 # ------------------------------------------------------------------ golden
-@pytest.mark.parametrize("name", ["w1", "w2", "w3"])
+@pytest.mark.parametrize("name", ["w1", "w2", "w3", "w4"])
 @pytest.mark.parametrize("mode", [oracle.MODE_WORKLIST, oracle.MODE_DEFINITION])
 def test_golden_cold(name, mode):
     inst, d = load_golden(name)
@@ -44,7 +44,7 @@ def test_golden_cold(name, mode):
     assert (lb2 == lb).all() and (ub2 == ub).all()
 
 
-@pytest.mark.parametrize("name", ["w1", "w2", "w3"])
+@pytest.mark.parametrize("name", ["w1", "w2", "w3", "w4"])
 def test_golden_probes(name):
     inst, d = load_golden(name)
     _, lb, ub = oracle.propagate(inst)
@@ -58,6 +58,10 @@ def test_golden_probes(name):
         got = implied_dict(P, p)
         want = {int(v): (float(a), float(b)) for v, a, b in exp["implied"]}
         assert got == want, (p, got, want)
+        if "box" in exp:  # the hand-derived box of an integer probe
+            j = exp["var"]
+            box = oracle.probe_box(lb[j], ub[j], exp["half"])
+            assert box == tuple(float(x) for x in exp["box"]), (p, box)
 
 
 def test_golden_w1_infeasible_evidence():
@@ -333,3 +337,54 @@ def test_validate_rejects_malformed():
     assert oracle.validate(bad) == -1
     bad = dict(good); bad["lo"] = good["lo"].copy(); bad["lo"][0] = good["hi"][0] + 1
     assert oracle.validate(bad) == -1
+
+
+# ------------------------------------------------------- integer probing
+def test_probe_box_rules():
+    """Section 2.2: a binary is probed at 0 and 1, a boxed integer split at
+    (l + u) / 2 (x < mid, x >= mid), one with only a lower bound at x = l and
+    x >= l + 1, one with only an upper bound (mirror) at x <= u - 1 and
+    x = u; a variable with no finite bound is not probed."""
+    pb = oracle.probe_box
+    assert [pb(0, 1, h) for h in (0, 1)] == [(0, 0), (1, 1)]
+    assert [pb(1, 1, h) for h in (0, 1)] == [(0, 0), (1, 1)]
+    assert [pb(0, 10, h) for h in (0, 1)] == [(0, 4), (5, 10)]   # mid 5: x < 5, x >= 5
+    assert [pb(0, 9, h) for h in (0, 1)] == [(0, 4), (5, 9)]     # mid 4.5
+    assert [pb(-3, 4, h) for h in (0, 1)] == [(-3, 0), (1, 4)]   # mid 0.5
+    assert [pb(-7, -2, h) for h in (0, 1)] == [(-7, -5), (-4, -2)]  # mid -4.5
+    assert [pb(2, INF, h) for h in (0, 1)] == [(2, 2), (3, INF)]
+    assert [pb(-INF, 5, h) for h in (0, 1)] == [(-INF, 4), (5, 5)]
+    assert pb(-INF, INF, 0) is None
+
+
+@pytest.mark.parametrize("seed", range(200))
+def test_integer_probes_keep_every_feasible_point(seed):
+    """Brute force (domains inside {0..3}, so the halves apply): every
+    integer point that satisfies all rows and lies in a probe's box also
+    lies in the probe's implied box; a probe reported infeasible has no such
+    point; the two halves of a variable cover its base domain."""
+    inst = gen.make_micro(seed)
+    r, lb, ub = oracle.propagate(inst)
+    if r["status"] != oracle.BP_OK:
+        return
+    vs = [j for j in range(inst["n"]) if lb[j] < ub[j]]
+    if not vs:
+        return
+    pts = feasible_points(inst, lb, ub)
+    P = oracle.probe(inst, lb, ub, vs)
+    for t, j in enumerate(vs):
+        boxes = [oracle.probe_box(lb[j], ub[j], h) for h in (0, 1)]
+        assert boxes[0][0] <= lb[j] and boxes[1][1] >= ub[j]
+        assert boxes[0][1] + 1 == boxes[1][0]
+        for h in (0, 1):
+            p = 2 * t + h
+            lo, hi = max(boxes[h][0], lb[j]), min(boxes[h][1], ub[j])
+            inside = [x for x in pts if lo <= x[j] <= hi]
+            if P["status"][p] == oracle.BP_INFEASIBLE:
+                assert not inside, (seed, j, h)
+                continue
+            imp = implied_dict(P, p)
+            for x in inside:
+                for i in range(inst["n"]):
+                    a, b = imp.get(i, (lb[i], ub[i]))
+                    assert a <= x[i] <= b, (seed, j, h, i)
