@@ -201,10 +201,19 @@ int bp_propagate_batch(bp_instance *h, int32_t B, double *lb, double *ub,
                        const int64_t *changed_ptr, const int32_t *changed_idx,
                        bp_result *res, void *stream);
 
-/* Double probing: every binary vars[t] (DEVICE [k]) is fixed to 0 and to 1
- * and propagated from the base.  Returns BP_OK, BP_ESTATE without a base,
- * BP_EINVAL if a variable is not an integer with base bounds inside [0, 1],
- * or BP_ECAPACITY (out->required set, other outputs unspecified). */
+/* Double probing (the paper's Section 2.2 probing cache): every integer
+ * variable vars[t] (DEVICE [k]) is restricted in two ways and propagated
+ * from the base; probe 2t+h is restriction h.  With base bounds [l, u]:
+ *   - a binary (base inside [0, 1]): x = 0 (h = 0) and x = 1 (h = 1);
+ *   - a boxed integer: x < (l+u)/2, i.e. [l, ceil((l+u)/2) - 1], and
+ *     x >= (l+u)/2, i.e. [ceil((l+u)/2), u];
+ *   - only l finite: x = l and x >= l + 1;
+ *   - only u finite: x <= u - 1 and x = u.
+ * A restriction that leaves nothing of [l, u] is BP_INFEASIBLE before any
+ * round; one that contains [l, u] is BP_OK with no rounds and no list.
+ * Returns BP_OK, BP_ESTATE without a base, BP_EINVAL if a variable is not
+ * an integer with a finite base bound, or BP_ECAPACITY (out->required set,
+ * other outputs unspecified). */
 int bp_probe(bp_instance *h, const int32_t *vars, int32_t k, bp_probe_out *out,
              void *stream);
 
@@ -255,7 +264,7 @@ void bp_free(bp_instance *h);
  * (from the instance's base with the request's bounds applied) or bp_probe
  * would return for it alone.
  * ------------------------------------------------------------------------- */
-#define BP_REQ_PROBE 0      /* probe `count` binaries at 0 and at 1 */
+#define BP_REQ_PROBE 0      /* probe `count` integer variables as bp_probe does */
 #define BP_REQ_PROPAGATE 1  /* intersect `count` variables' bounds with
                                [lb, ub] and propagate from the base */
 

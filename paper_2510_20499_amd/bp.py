@@ -250,7 +250,8 @@ class Instance:
         return [res[j].as_dict() for j in range(B)]
 
     def probe(self, vars_: torch.Tensor, cap: int = None, stream=None) -> dict:
-        """bp_probe: double probing of the binaries in vars_ (int32 device)."""
+        """bp_probe: double probing of the integer variables in vars_ (int32
+        device): binaries at 0 and 1, other integers by two half-intervals."""
         k = vars_.numel()
         dev = vars_.device
         cap = cap if cap is not None else max(1024, 64 * 2 * k)

@@ -1093,15 +1093,16 @@ __global__ void __launch_bounds__(WG) k_gh_base(DInst I, const int32_t *hrows, i
     }
 }
 
-// Probe variables must be integers whose base bounds lie in [0, 1].
+// Probe variables must be integers with at least one finite base bound.
 __global__ void k_check_probe_vars(const int32_t *vars, int32_t k, int32_t n, const uint8_t *vtype,
                                    const double2 *base, int32_t *bad) {
+    const double INF = __builtin_inf();
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < k; t += gridDim.x * blockDim.x) {
         int j = vars[t];
         bool ok = j >= 0 && j < n;
         if (ok) {
             double2 b = base[j];
-            ok = vtype[j] != 0 && b.x >= 0.0 && b.y <= 1.0;
+            ok = vtype[j] != 0 && (b.x > -INF || b.y < INF);
         }
         if (!ok) atomicMin(bad, t);
     }
@@ -1157,7 +1158,7 @@ extern "C" int bp_probe(bp_instance *h, const int32_t *vars, int32_t k, bp_probe
         HIPTRY(hipStreamSynchronize(st));
         if (bad != NONE)
             return fail(BP_EINVAL, "probe variable at position " + std::to_string(bad) +
-                                       " is not an integer with base bounds inside [0, 1]");
+                                       " is not an integer with a finite base bound");
     }
     const int32_t S = (int32_t)std::min<int64_t>(std::max(1, h->opt.probe_slots), jobs);
     const int64_t H = h->bin_count[BIN_HEAVY];

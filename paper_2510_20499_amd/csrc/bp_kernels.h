@@ -1257,6 +1257,34 @@ __global__ void __launch_bounds__(WG) k_apply(Params P) {
 // ------------------------------------------------------------------------
 enum : int32_t { JOB_PROBE = 0, JOB_FIX = 1 };
 
+// The restriction a probe job applies to integer variable j with base
+// bounds [l, u] (Section 2.2, probing cache), side h in {0, 1}: a binary
+// (base inside [0, 1]) is fixed to h; a boxed integer takes the half below
+// or at and above (l + u) / 2, [l, ceil((l + u)/2) - 1] or
+// [ceil((l + u)/2), u]; an integer bounded below only takes x = l or
+// x >= l + 1, one bounded above only x <= u - 1 or x = u.  The result is
+// intersected with [l, u] by the caller.  False for a variable with no
+// finite bound (never admitted: the entry points reject it).
+__device__ __forceinline__ bool probe_restriction(double l, double u, int h, double &lo, double &hi) {
+    const double INF = __builtin_inf();
+    if (l >= 0.0 && u <= 1.0) {
+        lo = hi = (double)h;
+    } else if (l > -INF && u < INF) {
+        const double mid_up = ceil((l + u) / 2.0);
+        lo = h ? mid_up : l;
+        hi = h ? u : mid_up - 1.0;
+    } else if (l > -INF) {
+        lo = h ? l + 1.0 : l;
+        hi = h ? u : l;
+    } else if (u < INF) {
+        lo = h ? u : l;
+        hi = h ? u : u - 1.0;
+    } else {
+        return false;
+    }
+    return true;
+}
+
 struct Job {
     int32_t inst, kind, a, b;
 };
@@ -1421,15 +1449,18 @@ __device__ bool admit_job(const Params &P, const JobIO &IO, int s, int p, int pa
     DInst I;
     if constexpr (MULTI) I = P.insts[J.inst];
     else I = P.I;
+    double2 pbox = make_double2(0.0, 0.0);  // a probe's box, within the base
     if (J.kind == JOB_PROBE) {
         const int j = J.a;
-        const double v = (double)J.b;
         const double2 b = I.base[j];
-        if (v < b.x || v > b.y) {  // the value is outside the base box
+        double lo = 0.0, hi = 0.0;
+        probe_restriction(b.x, b.y, J.b, lo, hi);
+        pbox = make_double2(canon0(fmax(lo, b.x)), canon0(fmin(hi, b.y)));
+        if (pbox.x > pbox.y) {  // the restriction leaves nothing of the base box
             write_job(P, IO, p, 1, 0, 0ull, 0, -1, j, 0, R);
             return false;
         }
-        if (b.x == v && b.y == v) {  // the base already fixes j at v
+        if (pbox.x == b.x && pbox.y == b.y) {  // the base already lies in it
             write_job(P, IO, p, 0, 0, 0ull, 0, -1, -1, 0, R);
             return false;
         }
@@ -1454,7 +1485,7 @@ __device__ bool admit_job(const Params &P, const JobIO &IO, int s, int p, int pa
     // Apply the job's bounds (each changed variable becomes dirty).
     if (J.kind == JOB_PROBE) {
         if (threadIdx.x == 0) {
-            P.bnd[(size_t)s * P.sn + J.a] = make_double2((double)J.b, (double)J.b);
+            P.bnd[(size_t)s * P.sn + J.a] = pbox;
             mark_dirty(P, s, J.a);
         }
     } else {

@@ -255,8 +255,8 @@ extern "C" int bp_server_submit(bp_server *sv, const bp_request *req, int64_t *i
         for (int32_t t = 0; t < req->count; ++t) {
             int32_t j = req->vars[t];
             const double2 b = sv->base[req->instance][j];
-            if (!sv->vtype[req->instance][j] || b.x < 0.0 || b.y > 1.0)
-                return fail(BP_EINVAL, "probe variable is not a binary of the base");
+            if (!sv->vtype[req->instance][j] || (std::isinf(b.x) && std::isinf(b.y)))
+                return fail(BP_EINVAL, "probe variable is not an integer with a finite base bound");
         }
     } else {
         for (int32_t t = 0; t < req->count; ++t)

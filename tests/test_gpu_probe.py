@@ -158,3 +158,57 @@ def test_repeated_calls_keep_slots_clean():
     gpu_propagate(I, inst, lb, ub)
     G = I.probe(dev(vs, torch.int32))
     assert np.array_equal(G["var"].cpu().numpy(), O["var"])
+
+
+# --------------------------------------------------------- general integers
+def _integers(lb, ub, vtype):
+    return np.nonzero((vtype == 1) & (lb < ub) & (np.isfinite(lb) | np.isfinite(ub)))[0].astype(np.int32)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_tiny_all_integers(seed):
+    """Binaries at 0 and 1 and the integers in [0, 10] by their halves."""
+    inst = gen.make("tiny", seed)
+    _, lb, ub = oracle.propagate(inst)
+    vs = _integers(lb, ub, inst["vtype"])
+    assert ((ub[vs] - lb[vs]) > 1).sum() >= 20
+    _probe_both(inst, vs, slots=96)
+
+
+def test_one_sided_integers():
+    """Integers with only a lower or only an upper bound: x = l / x >= l + 1
+    and x <= u - 1 / x = u."""
+    inst = gen.make("tiny", 7)
+    rng = np.random.default_rng(7)
+    ints = np.nonzero((inst["vtype"] == 1) & (inst["ub"] > 1))[0]
+    pick = rng.choice(ints, size=40, replace=False)
+    inst["ub"][pick[:20]] = np.inf
+    inst["lb"][pick[20:]] = -np.inf
+    _, lb, ub = oracle.propagate(inst)
+    vs = _integers(lb, ub, inst["vtype"])
+    assert (np.isinf(lb[vs]) | np.isinf(ub[vs])).sum() >= 5
+    _probe_both(inst, vs, slots=64)
+
+
+def test_integers_of_the_single_workload_with_heavy_rows():
+    """Integers in [0, 100] of the scaled single workload, grouped heavy rows."""
+    inst = gen.make("single", 6, scale=0.05)
+    _, lb, ub = oracle.propagate(inst)
+    vs = _integers(lb, ub, inst["vtype"])
+    vs = vs[(ub[vs] - lb[vs]) > 1][:150]
+    assert vs.size >= 100
+    _probe_both(inst, vs, slots=128, opts_kw=dict(heavy_threshold=1024, heavy_chunk=512))
+
+
+def test_variables_without_finite_bounds_are_rejected():
+    inst = gen.make("tiny", 8)
+    j = int(np.nonzero(inst["vtype"] == 1)[0][0])
+    inst["lb"][j], inst["ub"][j] = -np.inf, np.inf
+    I = bp().Instance(inst)
+    r, lb, ub = gpu_propagate(I, inst)
+    if np.isinf(lb[j]) and np.isinf(ub[j]):
+        with pytest.raises(bp().BPError):
+            I.probe(dev(np.array([j], np.int32), torch.int32))
+    cont = np.nonzero(inst["vtype"] == 0)[0][:1].astype(np.int32)
+    with pytest.raises(bp().BPError):
+        I.probe(dev(cont, torch.int32))

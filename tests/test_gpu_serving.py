@@ -197,3 +197,25 @@ def test_serving_trickle_arrivals():
         jobs = 2 * vs.size if kind == bp().REQ_PROBE else 1
         _same(S.results(rid, jobs), _oracle_result(insts[t], bases[t], reqs[j]), insts[t],
               "trickle%d" % j, evidence=kind == bp().REQ_PROPAGATE)
+
+
+
+def test_serving_integer_probes():
+    """Probe requests of general integers (half-intervals) in the mix."""
+    insts, loaded, bases = _instances()
+    rng = np.random.default_rng(31)
+    reqs = []
+    for t in range(len(insts)):
+        lb, ub = bases[t]
+        ints = np.nonzero((insts[t]["vtype"] == 1) & (lb < ub) & (ub - lb > 1))[0]
+        if ints.size == 0:
+            continue
+        for _ in range(3):
+            k = int(min(ints.size, rng.integers(1, 40)))
+            vs = np.sort(rng.choice(ints, size=k, replace=False)).astype(np.int32)
+            reqs.append((t, bp().REQ_PROBE, vs, None, None))
+    assert len(reqs) >= 6
+    _, mix, _ = _serve(loaded, reqs, budget=128 << 20, waves=2)
+    for j, req in enumerate(reqs):
+        t = req[0]
+        _same(mix[j], _oracle_result(insts[t], bases[t], req), insts[t], "intprobe%d" % j)
