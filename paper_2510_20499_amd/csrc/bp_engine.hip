@@ -96,6 +96,7 @@ struct Shape {
 struct Engine {
     int32_t cap_slots = 0;
     int32_t track_dirty = 0;
+    int32_t nstripe = 1;  // changed-list stripes (NSTRIPE for one slot)
     Shape shape;
     int64_t bytes = 0;
     DevBuf bnd, cand, vflag, rflag, info, chg, dirty, dlist, dcount, ctl, touched, filt;
@@ -526,7 +527,8 @@ static int engine_alloc(std::unique_ptr<Engine> &eng, const Shape &sh, int32_t s
     if ((rc = E->vflag.alloc((size_t)S * nw_var * 4, B))) return rc;
     if ((rc = E->rflag.alloc((size_t)S * nw_row * 4, B))) return rc;
     if ((rc = E->info.alloc((size_t)S * sizeof(SlotInfo), B))) return rc;
-    if ((rc = E->chg.alloc((size_t)S * n * 8, B))) return rc;
+    E->nstripe = S == 1 ? NSTRIPE : 1;
+    if ((rc = E->chg.alloc((size_t)E->nstripe * S * n * 8, B))) return rc;
     if ((rc = E->ctl.alloc(sizeof(Ctl), B))) return rc;
     for (int par = 0; par < 2; ++par) {
         for (int b = 0; b < BIN_HEAVY; ++b)
@@ -622,6 +624,8 @@ static Params engine_params(const Engine &E, const bp_options &opt, int32_t heav
     P.hpart = E.hpart.as<Acc>();
     P.hrng = E.hrng.as<double>();
     P.chg = E.chg.as<uint64_t>();
+    P.nstripe = E.nstripe;
+    P.chg_stride = (int64_t)E.cap_slots * P.sn;
     P.ctl = E.ctl.as<Ctl>();
     P.touched = (opt.flags & BP_FLAG_COUNT_VARS) ? E.touched.as<uint32_t>() : nullptr;
     P.overlay = 0;  // jobs read bounds as an overlay on the base

@@ -46,6 +46,10 @@ constexpr int NBIN = 13;
 constexpr int WG = 256;             // workgroup size of every kernel
 constexpr int32_t NONE = 0x7fffffff;
 constexpr int FILT_WORDS = 1024;    // 32768-bit dirty filter per slot (4 KB)
+// A single bound vector spreads its changed list over this many stripes,
+// one counter each, chosen by workgroup index: every such counter is hit by
+// an eighth of the waves (same-address atomics serialise).
+constexpr int NSTRIPE = 8;
 
 enum : int32_t { SLOT_FREE = 0, SLOT_ACTIVE = 1, SLOT_DRAINING = 2 };
 
@@ -86,7 +90,7 @@ struct Ctl {
     uint32_t qcount[2][NBIN];   // queue lengths per parity
     uint32_t hchunks[2];        // heavy chunks per parity
     uint32_t ghchunks[2];       // grouped heavy chunk tasks per parity
-    uint32_t nchanged;          // (slot, var) entries of the current round
+    uint32_t nchanged[NSTRIPE]; // (slot, var) entries of the current round, per stripe
     uint32_t active;            // slots active or draining after the last round end
     uint32_t finished;          // slots finished at the last round end
     uint32_t max_rounds;
@@ -103,6 +107,38 @@ struct Ctl {
     unsigned long long stat_vars;    // distinct bound records read per round
     unsigned long long stat_written; // accepted bound changes
 };
+
+// The leading fields of Ctl for the round in progress (its parity's queue
+// lengths and chunk counts), read by the round kernels in one go: both
+// parities are loaded and selected without indexing.
+struct CtlHead {
+    uint32_t round, done;
+    uint32_t qcount[NBIN];
+    uint32_t hchunks, ghchunks;
+};
+
+// Keeps control loads ahead of the first branch on them, so that they are
+// issued together rather than one memory round trip after another.
+__device__ __forceinline__ void ctl_loaded(uint32_t a, uint32_t b, uint32_t c) {
+    asm volatile("" ::"s"(a), "s"(b), "s"(c));
+}
+
+__device__ __forceinline__ CtlHead ctl_head(const Ctl *C) {
+    CtlHead H;
+    H.round = C->round;
+    H.done = C->done;
+    const bool odd = (H.round & 1u) != 0;
+#pragma unroll
+    for (int b = 0; b < NBIN; ++b) {
+        const uint32_t q0 = C->qcount[0][b], q1 = C->qcount[1][b];
+        H.qcount[b] = odd ? q1 : q0;
+    }
+    const uint32_t h0 = C->hchunks[0], h1 = C->hchunks[1];
+    const uint32_t g0 = C->ghchunks[0], g1 = C->ghchunks[1];
+    H.hchunks = odd ? h1 : h0;
+    H.ghchunks = odd ? g1 : g0;
+    return H;
+}
 
 struct Params {
     DInst I;                     // the instance when there is one
@@ -123,7 +159,9 @@ struct Params {
     int4 *hrec[2];               // heavy chunks: (slot, row, chunk index, chunks of the row)
     Acc *hpart;                  // [chunks][2] partial (min, max) states
     double *hrng;                // [chunks] partial widths (slack filter)
-    uint64_t *chg;               // (slot << 32 | var) entries of the round
+    uint64_t *chg;               // (slot << 32 | var) entries of the round, nstripe lists
+    int32_t nstripe;             // 1, or NSTRIPE for an engine of one slot
+    int64_t chg_stride;          // entries per stripe
     Ctl *ctl;
     uint32_t *touched;           // [nslots][snw] bound records read this round
                                  // (only when counting them)
@@ -349,7 +387,9 @@ __device__ __forceinline__ void mark_var(const Params &P, bool want, int s, int 
         uint32_t old = atomicOr(&P.vflag[(size_t)s * P.snw + (i >> 5)], bit);
         first = (old & bit) == 0;
     }
-    wave_push(P.chg, &P.ctl->nchanged, first, ((uint64_t)(uint32_t)s << 32) | (uint32_t)i);
+    const int st = blockIdx.x & (P.nstripe - 1);
+    wave_push(P.chg + (size_t)st * P.chg_stride, &P.ctl->nchanged[st], first,
+              ((uint64_t)(uint32_t)s << 32) | (uint32_t)i);
 }
 
 // Scatter the significant candidates of one nonzero.  Returns whether the
@@ -902,22 +942,25 @@ template <bool MULTI>
 #endif
 __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(BP_ROWS_WAVES))) k_rows(Params P) {
     __shared__ WgScratch W;
-    const Ctl *C = P.ctl;
-    if (C->done) return;
-    const int par = C->round & 1;
+    // The round's counters of both parities are read together (one memory
+    // round trip) and selected afterwards; a finished run has no units.
+    const CtlHead H = ctl_head(P.ctl);
+    const int par = H.round & 1;
+    const uint32_t *qc = H.qcount;
+    const uint32_t C_ghchunks = H.ghchunks, C_hchunks = H.hchunks;
     // Work units: grouped heavy chunk tasks (four per unit, one per wave),
     // heavy chunks, block rows, then light bins 10..0.
-    const uint32_t ngh = C->ghchunks[par];
+    const uint32_t ngh = C_ghchunks;
     const uint32_t gh_units = (ngh + (WG / 64) - 1) / (WG / 64);
     uint32_t start[NBIN + 2];
     start[0] = gh_units;
-    start[1] = start[0] + C->hchunks[par];
-    start[2] = start[1] + C->qcount[par][BIN_BLOCK];
+    start[1] = start[0] + C_hchunks;
+    start[2] = start[1] + qc[BIN_BLOCK];
     for (int j = 0; j < NLIGHT; ++j) {
         int b = NLIGHT - 1 - j;
-        start[3 + j] = start[2 + j] + light_units(C->qcount[par][b], b);
+        start[3 + j] = start[2 + j] + light_units(qc[b], b);
     }
-    const uint32_t total = start[2 + NLIGHT];
+    const uint32_t total = H.done ? 0u : start[2 + NLIGHT];
     for (uint32_t u = blockIdx.x; u < total; u += gridDim.x) {
         if (u < start[0]) {
             const uint32_t t = u * (WG / 64) + (threadIdx.x >> 6);
@@ -932,7 +975,7 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(BP_ROWS
             int b = NLIGHT - 1 - j;
             uint32_t lu = u - start[2 + j];
             const uint64_t *q = P.q[par][b];
-            uint32_t cnt = C->qcount[par][b];
+            uint32_t cnt = qc[b];
             switch (b) {
                 case 0: light_rows<MULTI, 1>(P, q, cnt, lu); break;
                 case 1: light_rows<MULTI, 2>(P, q, cnt, lu); break;
@@ -949,12 +992,11 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(BP_ROWS
 
 template <bool MULTI>
 __global__ void __launch_bounds__(WG) k_heavy(Params P) {
-    const Ctl *C = P.ctl;
-    if (C->done) return;
-    const int par = C->round & 1;
-    const uint32_t ngh = C->ghchunks[par];
+    const CtlHead H = ctl_head(P.ctl);
+    const int par = H.round & 1;
+    const uint32_t ngh = H.ghchunks;
     const uint32_t gh_units = (ngh + (WG / 64) - 1) / (WG / 64);
-    const uint32_t total = gh_units + C->hchunks[par];
+    const uint32_t total = H.done ? 0u : gh_units + H.hchunks;
     for (uint32_t u = blockIdx.x; u < total; u += gridDim.x) {
         if (u < gh_units) {
             const uint32_t t = u * (WG / 64) + (threadIdx.x >> 6);
@@ -1122,8 +1164,13 @@ __device__ __forceinline__ void mark_dirty(const Params &P, int s, int i) {
 // Round end for every slot: outcome, counters, next round (one workgroup).
 __global__ void __launch_bounds__(WG) k_end(Params P) {
     Ctl *C = P.ctl;
-    if (C->done) return;
-    const int par = C->round & 1;
+    // Control fields read together, before the early exit.
+    const uint32_t c_done = C->done, c_round = C->round, c_max_rounds = C->max_rounds;
+    const uint32_t c_next_job = C->next_job, c_total_jobs = C->total_jobs;
+    ctl_loaded(c_done, c_round, c_max_rounds);
+    ctl_loaded(c_next_job, c_total_jobs, c_done);
+    if (c_done) return;
+    const int par = c_round & 1;
     __shared__ uint32_t s_active, s_finished;
     if (threadIdx.x == 0) {
         s_active = 0;
@@ -1147,7 +1194,7 @@ __global__ void __launch_bounds__(WG) k_end(Params P) {
             drain = S.pending_rows > 0;
         } else if (S.pending_rows == 0) {
             S.status = 0;
-        } else if ((uint32_t)S.rounds >= C->max_rounds) {
+        } else if ((uint32_t)S.rounds >= c_max_rounds) {
             S.status = 2;
             drain = true;
         } else {
@@ -1179,11 +1226,11 @@ __global__ void __launch_bounds__(WG) k_end(Params P) {
         for (int b = 0; b < NBIN; ++b) C->qcount[par][b] = 0;
         C->hchunks[par] = 0;
         C->ghchunks[par] = 0;
-        C->nchanged = 0;
+        for (int st = 0; st < NSTRIPE; ++st) C->nchanged[st] = 0;
         C->active = s_active;
         C->finished = s_finished;
-        C->round = C->round + 1;
-        if (s_active == 0 && C->next_job >= C->total_jobs) C->done = 1;
+        C->round = c_round + 1;
+        if (s_active == 0 && c_next_job >= c_total_jobs) C->done = 1;
     }
 }
 
@@ -1192,14 +1239,25 @@ constexpr int APPLY_V = 16;  // changed variables per wave and step in k_apply
 template <bool MULTI>
 __global__ void __launch_bounds__(WG) k_apply(Params P) {
     Ctl *C = P.ctl;
-    if (C->done) return;
-    const int par = C->round & 1;
+    // Control fields and the stripe lengths, read together.
+    const uint32_t c_round = C->round, c_done = C->done;
+    uint32_t pre[NSTRIPE + 1];
+    pre[0] = 0;
+#pragma unroll
+    for (int st = 0; st < NSTRIPE; ++st) pre[st + 1] = pre[st] + C->nchanged[st];
+    ctl_loaded(c_round, c_done, pre[NSTRIPE]);
+    const int par = c_round & 1;
     const int npar = par ^ 1;
-    const uint32_t total = C->nchanged;
+    const uint32_t total = c_done ? 0u : pre[NSTRIPE];
     const double INF = __builtin_inf();
     const int lane = __lane_id();
     const uint32_t nwaves = gridDim.x * (WG / 64);
     const uint32_t gw = blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
+    // One bound vector: the wave adds its accepted changes and queued rows
+    // to running totals, and the workgroup adds them to the counters once.
+    const bool single = P.nslots == 1;
+    uint32_t w_rows = 0;
+    unsigned long long w_nnz = 0, w_written = 0;
     // Wave-uniform trip count: whole waves reach the aggregated appends.
     for (uint32_t e0 = gw * APPLY_V; e0 < total; e0 += nwaves * APPLY_V) {
         uint32_t e = e0 + lane;
@@ -1209,7 +1267,10 @@ __global__ void __launch_bounds__(WG) k_apply(Params P) {
         long long c0 = 0;
         uint32_t clen = 0;
         if (has) {
-            uint64_t ent = P.chg[e];
+            int st = 0;
+#pragma unroll
+            for (int j = 1; j < NSTRIPE; ++j) st += e >= pre[j] ? 1 : 0;
+            uint64_t ent = P.chg[(size_t)st * P.chg_stride + (e - pre[st])];
             s = (int)(ent >> 32);
             i = (int)(uint32_t)ent;
             const DInst I = inst_of<MULTI>(P, s);
@@ -1242,9 +1303,41 @@ __global__ void __launch_bounds__(WG) k_apply(Params P) {
             }
         }
         uint64_t wm = __ballot(go);
-        if (wm && lane == __ffsll((long long)wm) - 1)
-            atomicAdd(&C->stat_written, (unsigned long long)__popcll(wm));
-        enqueue_columns<MULTI>(P, npar, go, s, c0, clen);
+        if (single) {
+            w_written += (unsigned long long)__popcll(wm);
+            uint32_t r = 0;
+            unsigned long long z = 0;
+            enqueue_columns<MULTI>(P, npar, go, s, c0, clen, false, &r, &z);
+            w_rows += r;
+            w_nnz += z;
+        } else {
+            if (wm && lane == __ffsll((long long)wm) - 1)
+                atomicAdd(&C->stat_written, (unsigned long long)__popcll(wm));
+            enqueue_columns<MULTI>(P, npar, go, s, c0, clen);
+        }
+    }
+    if (single) {
+        __shared__ unsigned long long a_rows[WG / 64], a_nnz[WG / 64], a_written[WG / 64];
+        const int wave = threadIdx.x >> 6;
+        if (lane == 0) {
+            a_rows[wave] = w_rows;
+            a_nnz[wave] = w_nnz;
+            a_written[wave] = w_written;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long r = 0, z = 0, w = 0;
+            for (int j = 0; j < WG / 64; ++j) {
+                r += a_rows[j];
+                z += a_nnz[j];
+                w += a_written[j];
+            }
+            if (r) {
+                atomicAdd(&P.info[0].pending_rows, (int32_t)r);
+                atomicAdd(&P.info[0].pending_nnz, z);
+            }
+            if (w) atomicAdd(&C->stat_written, w);
+        }
     }
 }
 
