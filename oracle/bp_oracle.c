@@ -22,6 +22,10 @@
  *   probing   a binary fixed to 0 and to 1, each propagated from the same
  *             base (Section 2.2), the implications being the bounds that
  *             differ from the base
+ *   scores    the probe priority (Section 2.2: rows violated when a
+ *             variable's contribution flips between its bounds, the largest
+ *             violation, the smallest unit slack) and the implied-slack score
+ *             S = sum of (a / slack)^2 (Section 2.3)
  *
  * Readings where the paper is silent (each one is also listed with the
  * design notes):
@@ -648,4 +652,179 @@ int orc_probe(const orc_instance *I, const double *base_lb, const double *base_u
     if (required) *required = total;
     if (total > cap) rc_all = ORC_ECAPACITY;
     return rc_all;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Probe priority and implied-slack scores.                                 */
+/* ------------------------------------------------------------------------ */
+/* SCORES at the bounds (lb, ub), for every variable j (Section 2.2, the
+ * three prioritisation criteria of the probing cache; Section 2.3, the unit
+ * slack consumption s = a / slack and S_j = sum of s^2).  Row activities are
+ * those of the propagation (correctly rounded sums of the finite terms and
+ * counts of the infinite ones).  For each nonzero (k, j, a):
+ *
+ *   flipped contribution (criteria 1 and 2), only when j's column holds
+ *   coefficients of both signs and both bounds of j are finite:
+ *     d = fl(fl(a*b_max) - fl(a*b_min)), b_min/b_max the bound giving j's
+ *         minimum/maximum contribution (lb/ub for a > 0, ub/lb for a < 0):
+ *         by how much moving j from one to the other raises the row's
+ *         minimum activity and lowers its maximum activity;
+ *     hi side (hi_k finite, no infinite minimum term): e = fl(d - fl(hi_k -
+ *         minfin_k)); lo side (lo_k finite, no infinite maximum term):
+ *         e = fl(d - fl(maxfin_k - lo_k));
+ *     the row is violated when some side has e > feastol; its violation is
+ *     the largest such e.  nviol_j counts the violated rows of j and
+ *     maxviol_j is their largest violation (0 when there is none);
+ *
+ *   unit slack (criterion 3 and the implied-slack sort), for each finite
+ *   side of row k without infinite terms on that side:
+ *     slack = fl(hi_k - minfin_k) or fl(maxfin_k - lo_k);
+ *     s = fl(a / slack), term fl(s*s); S_j is the correctly rounded sum of
+ *     the terms of j (+inf when some term is infinite, i.e. a zero slack;
+ *     0 without terms); minunit_j is the smallest fl(slack / |a|) (+inf
+ *     without terms).
+ *
+ * Any output pointer may be NULL. */
+int orc_scores(const orc_instance *I, const double *lb, const double *ub, const orc_options *o,
+               int32_t *nviol, double *maxviol, double *minunit, double *slack_score) {
+    const int64_t m = I->m, n = I->n, nnz = I->nnz;
+    const double INF = HUGE_VAL;
+    int rc = 0;
+    double *bmin = (double *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(double));
+    double *bmax = (double *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(double));
+    orc_activity *act = (orc_activity *)malloc((size_t)(m > 0 ? m : 1) * sizeof(orc_activity));
+    int64_t *tcount = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int8_t *sign = (int8_t *)calloc((size_t)(n > 0 ? n : 1), 1);
+    int32_t *nv = (int32_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
+    double *mv = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    double *mu = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    int8_t *sinf = (int8_t *)calloc((size_t)(n > 0 ? n : 1), 1);
+    double *terms = NULL;
+    int64_t *tfill = NULL;
+    if (!bmin || !bmax || !act || !tcount || !sign || !nv || !mv || !mu || !sinf) {
+        rc = ORC_ENOMEM;
+        goto done;
+    }
+    for (int64_t k = 0; k < m; ++k)
+        if ((rc = row_activity(I, k, lb, ub, bmin, bmax, &act[k])) != 0) goto done;
+    /* which variables have coefficients of both signs */
+    for (int64_t p = 0; p < nnz; ++p) sign[I->col[p]] |= I->val[p] > 0.0 ? 1 : 2;
+    for (int64_t j = 0; j < n; ++j) mu[j] = INF;
+    /* count the unit-slack terms of each variable, then collect them */
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int64_t k = 0; k < m; ++k) {
+            const orc_activity *A = &act[k];
+            const int hi_ok = I->hi[k] < INF && A->ninf_min == 0;
+            const int lo_ok = I->lo[k] > -INF && A->ninf_max == 0;
+            const double slack_hi = hi_ok ? I->hi[k] - A->minfin : 0.0;
+            const double slack_lo = lo_ok ? A->maxfin - I->lo[k] : 0.0;
+            for (int64_t p = I->row_ptr[k]; p < I->row_ptr[k + 1]; ++p) {
+                const int32_t j = I->col[p];
+                const double a = I->val[p];
+                if (pass == 0) {
+                    tcount[j + 1] += hi_ok + lo_ok;
+                    /* flipped contribution */
+                    if (sign[j] == 3 && !isinf(lb[j]) && !isinf(ub[j])) {
+                        const double b_min = a > 0.0 ? lb[j] : ub[j];
+                        const double b_max = a > 0.0 ? ub[j] : lb[j];
+                        const double d = a * b_max - a * b_min;
+                        int viol = 0;
+                        double worst = 0.0;
+                        if (hi_ok) {
+                            double e = d - slack_hi;
+                            if (e > o->feastol) { viol = 1; worst = e; }
+                        }
+                        if (lo_ok) {
+                            double e = d - slack_lo;
+                            if (e > o->feastol && (!viol || e > worst)) { viol = 1; worst = e; }
+                        }
+                        if (viol) {
+                            nv[j] += 1;
+                            if (worst > mv[j]) mv[j] = worst;
+                        }
+                    }
+                    /* smallest unit slack */
+                    if (hi_ok) {
+                        double u = slack_hi / fabs(a);
+                        if (u < mu[j]) mu[j] = u;
+                    }
+                    if (lo_ok) {
+                        double u = slack_lo / fabs(a);
+                        if (u < mu[j]) mu[j] = u;
+                    }
+                } else {
+                    for (int side = 0; side < 2; ++side) {
+                        if (side == 0 ? !hi_ok : !lo_ok) continue;
+                        double s = a / (side == 0 ? slack_hi : slack_lo);
+                        double t = s * s;
+                        if (isinf(t)) sinf[j] = 1;
+                        else terms[tfill[j]++] = t;
+                    }
+                }
+            }
+        }
+        if (pass == 0) {
+            for (int64_t j = 0; j < n; ++j) tcount[j + 1] += tcount[j];
+            terms = (double *)malloc((size_t)(tcount[n] > 0 ? tcount[n] : 1) * sizeof(double));
+            tfill = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+            if (!terms || !tfill) { rc = ORC_ENOMEM; goto done; }
+            for (int64_t j = 0; j < n; ++j) tfill[j] = tcount[j];
+        }
+    }
+    for (int64_t j = 0; j < n; ++j) {
+        if (nviol) nviol[j] = nv[j];
+        if (maxviol) maxviol[j] = canon(mv[j]);
+        if (minunit) minunit[j] = canon(mu[j]);
+        if (slack_score) {
+            if (sinf[j]) slack_score[j] = INF;
+            else slack_score[j] = canon(orc_exact_sum(terms + tcount[j], tfill[j] - tcount[j]));
+        }
+    }
+done:
+    free(bmin); free(bmax); free(act); free(tcount); free(sign); free(nv); free(mv); free(mu);
+    free(sinf); free(terms); free(tfill);
+    return rc;
+}
+
+/* Probe order (Section 2.2): the listed variables sorted by more violated
+ * rows first, then the larger maximum violation, then the smaller minimum
+ * unit slack, then the smaller index. */
+typedef struct {
+    int32_t var, nviol;
+    double maxviol, minunit;
+} orc_prio;
+
+static int prio_cmp(const void *x, const void *y) {
+    const orc_prio *a = (const orc_prio *)x, *b = (const orc_prio *)y;
+    if (a->nviol != b->nviol) return a->nviol > b->nviol ? -1 : 1;
+    if (a->maxviol != b->maxviol) return a->maxviol > b->maxviol ? -1 : 1;
+    if (a->minunit != b->minunit) return a->minunit < b->minunit ? -1 : 1;
+    if (a->var != b->var) return a->var < b->var ? -1 : 1;
+    return 0;
+}
+
+int orc_probe_order(const orc_instance *I, const double *lb, const double *ub,
+                    const orc_options *o, const int32_t *vars, int32_t k, int32_t *order) {
+    const int64_t n = I->n;
+    for (int32_t t = 0; t < k; ++t)
+        if (vars[t] < 0 || vars[t] >= n) return ORC_EINVAL;
+    int32_t *nv = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    double *mv = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    double *mu = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    orc_prio *P = (orc_prio *)malloc((size_t)(k > 0 ? k : 1) * sizeof(orc_prio));
+    int rc = ORC_ENOMEM;
+    if (nv && mv && mu && P) rc = orc_scores(I, lb, ub, o, nv, mv, mu, NULL);
+    if (rc == 0) {
+        for (int32_t t = 0; t < k; ++t) {
+            int32_t j = vars[t];
+            P[t].var = j;
+            P[t].nviol = nv[j];
+            P[t].maxviol = mv[j];
+            P[t].minunit = mu[j];
+        }
+        qsort(P, (size_t)k, sizeof(orc_prio), prio_cmp);
+        for (int32_t t = 0; t < k; ++t) order[t] = P[t].var;
+    }
+    free(nv); free(mv); free(mu); free(P);
+    return rc;
 }

@@ -82,6 +82,12 @@ def bind(path: str):
     lib.orc_probe.argtypes = [C.POINTER(_Inst), C.c_void_p, C.c_void_p, C.c_void_p,
                               C.c_int32, C.POINTER(_Opt), C.c_int] + [C.c_void_p] * 8 + \
                              [C.c_int64, C.POINTER(C.c_int64)]
+    lib.orc_scores.restype = C.c_int
+    lib.orc_scores.argtypes = [C.POINTER(_Inst), C.c_void_p, C.c_void_p, C.POINTER(_Opt)] + \
+                              [C.c_void_p] * 4
+    lib.orc_probe_order.restype = C.c_int
+    lib.orc_probe_order.argtypes = [C.POINTER(_Inst), C.c_void_p, C.c_void_p, C.POINTER(_Opt),
+                                    C.c_void_p, C.c_int32, C.c_void_p]
     return lib
 
 
@@ -201,3 +207,46 @@ def probe_box(l, u, h, lib=None):
     if lib.orc_probe_box(float(l), float(u), int(h), C.byref(a), C.byref(b)) != 0:
         return None
     return a.value, b.value
+
+
+def _bounds(inst, lb, ub):
+    lb = np.ascontiguousarray(inst["lb"] if lb is None else lb, dtype=np.float64)
+    ub = np.ascontiguousarray(inst["ub"] if ub is None else ub, dtype=np.float64)
+    return lb, ub
+
+
+def scores(inst, lb=None, ub=None, opts: Options = None, lib=None):
+    """Probe-priority and implied-slack scores of every variable at (lb, ub)
+    (Sections 2.2 and 2.3): nviol (rows violated when the variable's
+    contribution flips between its bounds; only variables whose column mixes
+    signs and whose bounds are finite), maxviol (the largest such violation),
+    minunit (smallest slack / |a| over the finite row sides without infinite
+    terms) and slack_score (S = sum of (a / slack)^2 over the same sides)."""
+    lib = lib or load()
+    h = _Held(inst)
+    lb, ub = _bounds(inst, lb, ub)
+    n = int(inst["n"])
+    out = dict(nviol=np.zeros(n, np.int32), maxviol=np.zeros(n), minunit=np.zeros(n),
+               slack_score=np.zeros(n))
+    rc = lib.orc_scores(C.byref(h.s), _ptr(lb), _ptr(ub), C.byref(_opt(opts)),
+                        _ptr(out["nviol"]), _ptr(out["maxviol"]), _ptr(out["minunit"]),
+                        _ptr(out["slack_score"]))
+    if rc < 0:
+        raise ValueError("oracle scores failed with code %d" % rc)
+    return out
+
+
+def probe_order(inst, vars_, lb=None, ub=None, opts: Options = None, lib=None):
+    """The listed variables in probe order (Section 2.2): more violated rows
+    first, then the larger maximum violation, the smaller minimum unit slack,
+    the smaller index."""
+    lib = lib or load()
+    h = _Held(inst)
+    lb, ub = _bounds(inst, lb, ub)
+    vs = np.ascontiguousarray(vars_, dtype=np.int32)
+    order = np.zeros(max(vs.size, 1), np.int32)
+    rc = lib.orc_probe_order(C.byref(h.s), _ptr(lb), _ptr(ub), C.byref(_opt(opts)), _ptr(vs),
+                             vs.size, _ptr(order))
+    if rc < 0:
+        raise ValueError("oracle probe order failed with code %d" % rc)
+    return order[:vs.size]

@@ -241,3 +241,66 @@ def keep_rows(inst, ks):
     rows = [(inst["col"][rp[k]:rp[k + 1]], inst["val"][rp[k]:rp[k + 1]]) for k in ks]
     return gen.from_rows(inst["n"], rows, inst["lo"][ks], inst["hi"][ks], inst["vtype"],
                          inst["lb"], inst["ub"])
+
+
+
+def box_extremes(inst, k, lb, ub, fix=None):
+    """Exact minimum and maximum of row k's activity over the box, with
+    variable fix = (j, value) held at value.  The activity is separable, so
+    each term ranges between its values at the two ends of its interval (a
+    product with an infinite end is infinite).  None for an unbounded side."""
+    rp = inst["row_ptr"]
+    lo, hi = Fraction(0), Fraction(0)
+    for i, a in zip(inst["col"][rp[k]:rp[k + 1]], inst["val"][rp[k]:rp[k + 1]]):
+        ends = [fix[1]] if fix is not None and i == fix[0] else [lb[i], ub[i]]
+        vals = [math.copysign(INF, a) * math.copysign(1.0, b) if math.isinf(b)
+                else Fraction(float(a)) * Fraction(float(b)) for b in ends]
+        tmin, tmax = min(vals), max(vals)
+        lo = None if lo is None or tmin == -INF else lo + tmin
+        hi = None if hi is None or tmax == INF else hi + tmax
+    return lo, hi
+
+
+def brute_scores(inst, lb, ub, feastol=1e-6):
+    """Scores from their meaning, in exact rationals: the row's extreme
+    activities over the box with the variable held at the bound that pushes
+    the row hardest; slack = distance from the extreme activity to the side."""
+    n, m = inst["n"], inst["m"]
+    rp, col, val = inst["row_ptr"], inst["col"], inst["val"]
+    signs = [set() for _ in range(n)]
+    for p in range(len(col)):
+        signs[col[p]].add(val[p] > 0)
+    nviol = [0] * n
+    maxviol = [Fraction(0)] * n
+    units = [[] for _ in range(n)]
+    terms = [[] for _ in range(n)]
+    for k in range(m):
+        mn, mx = box_extremes(inst, k, lb, ub)
+        hi, lo = inst["hi"][k], inst["lo"][k]
+        sides = []
+        if not math.isinf(hi) and mn is not None:
+            sides.append(Fraction(float(hi)) - mn)
+        if not math.isinf(lo) and mx is not None:
+            sides.append(mx - Fraction(float(lo)))
+        for p in range(rp[k], rp[k + 1]):
+            j, a = int(col[p]), float(val[p])
+            for sl in sides:
+                units[j].append(sl / abs(Fraction(a)))
+                terms[j].append(None if sl == 0 else (Fraction(a) / sl) ** 2)
+            if len(signs[j]) == 2 and not math.isinf(lb[j]) and not math.isinf(ub[j]):
+                push_up = ub[j] if a > 0 else lb[j]      # raises the minimum activity
+                push_down = lb[j] if a > 0 else ub[j]    # lowers the maximum activity
+                worst = None
+                if not math.isinf(hi):
+                    fmn, _ = box_extremes(inst, k, lb, ub, fix=(j, push_up))
+                    if fmn is not None and fmn - Fraction(float(hi)) > Fraction(feastol):
+                        worst = fmn - Fraction(float(hi))
+                if not math.isinf(lo):
+                    _, fmx = box_extremes(inst, k, lb, ub, fix=(j, push_down))
+                    if fmx is not None and Fraction(float(lo)) - fmx > Fraction(feastol):
+                        e = Fraction(float(lo)) - fmx
+                        worst = e if worst is None or e > worst else worst
+                if worst is not None:
+                    nviol[j] += 1
+                    maxviol[j] = max(maxviol[j], worst)
+    return nviol, maxviol, units, terms

@@ -8,13 +8,14 @@ and at least one must fail.
 """
 import math
 import os
+from fractions import Fraction
 import tempfile
 
 import numpy as np
 import pytest
 
 import oracle
-from helpers import exact_gs_fixed_point, feasible_points, implied_dict, load_golden
+from helpers import brute_scores, exact_gs_fixed_point, feasible_points, implied_dict, load_golden
 from paper_2510_20499_amd import gen
 
 SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle",
@@ -39,6 +40,15 @@ MUTANTS = {
     "division_operand": ("double c = v / a;", "double c = v / fabs(a);"),
     "probe_split_rounded_down": ("double c = ceil((l + u) / 2.0);", "double c = floor((l + u) / 2.0);"),
     "probe_one_sided_step": ("else { *nl = l + 1.0; *nu = u; }", "else { *nl = l; *nu = u; }"),
+    "flip_direction": ("const double d = a * b_max - a * b_min;",
+                       "const double d = a * b_min - a * b_max;"),
+    "flip_without_mixed_signs": ("if (sign[j] == 3 && !isinf(lb[j])", "if (sign[j] != 0 && !isinf(lb[j])"),
+    "slack_from_max_activity": ("const double slack_hi = hi_ok ? I->hi[k] - A->minfin : 0.0;",
+                                "const double slack_hi = hi_ok ? I->hi[k] - A->maxfin : 0.0;"),
+    "unit_slack_inverted": ("double u = slack_lo / fabs(a);", "double u = fabs(a) / slack_lo;"),
+    "square_dropped": ("double t = s * s;", "double t = fabs(s);"),
+    "order_violation_direction": ("if (a->maxviol != b->maxviol) return a->maxviol > b->maxviol ? -1 : 1;",
+                                  "if (a->maxviol != b->maxviol) return a->maxviol < b->maxviol ? -1 : 1;"),
 }
 
 
@@ -101,6 +111,30 @@ def _pins_hold(lib) -> bool:
         inst = gen.from_rows(1, [([0], [0.1])], [0.3], [math.inf], [1], [0.0], [10.0])
         if list(oracle.propagate(inst, lib=lib)[1]) != [3.0]:
             return False
+        # priority scores: the hand-computed fixture and their exact meaning
+        inst, d = load_golden("w5_scores")
+        S = oracle.scores(inst, lib=lib)
+        if (list(S["nviol"]) != d["nviol"] or list(S["maxviol"]) != [float(x) for x in d["maxviol"]]
+                or list(S["minunit"]) != [float(x) for x in d["minunit"]]
+                or list(S["slack_score"]) != [float(x) for x in d["slack_score"]]):
+            return False
+        for vs, exp in d["orders"]:
+            if list(oracle.probe_order(inst, vs, lib=lib)) != exp:
+                return False
+        for seed in range(40):
+            inst = gen.make_micro(seed)
+            S = oracle.scores(inst, lib=lib)
+            nviol, maxviol, units, terms = brute_scores(inst, inst["lb"], inst["ub"])
+            if list(S["nviol"]) != nviol or [Fraction(x) for x in S["maxviol"]] != maxviol:
+                return False
+            for j in range(inst["n"]):
+                if S["minunit"][j] != (float(min(units[j])) if units[j] else math.inf):
+                    return False
+                exact = None if any(t is None for t in terms[j]) else sum(terms[j], Fraction(0))
+                if (exact is None) != (S["slack_score"][j] == math.inf):
+                    return False
+                if exact is not None and abs(Fraction(S["slack_score"][j]) - exact) > exact / 2 ** 49:
+                    return False
     except (ValueError, ZeroDivisionError, OverflowError):
         return False
     return True

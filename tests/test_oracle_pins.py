@@ -20,7 +20,7 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import exact_gs_fixed_point, feasible_points, implied_dict, load_golden
+from helpers import brute_scores, exact_gs_fixed_point, feasible_points, implied_dict, load_golden
 from paper_2510_20499_amd import gen
 
 INF = float("inf")
@@ -388,3 +388,66 @@ def test_integer_probes_keep_every_feasible_point(seed):
                 for i in range(inst["n"]):
                     a, b = imp.get(i, (lb[i], ub[i]))
                     assert a <= x[i] <= b, (seed, j, h, i)
+
+
+# ------------------------------------------------------- priority scores
+def test_golden_w5_scores():
+    inst, d = load_golden("w5_scores")
+    S = oracle.scores(inst)
+    assert list(S["nviol"]) == d["nviol"]
+    assert list(S["maxviol"]) == [float(x) for x in d["maxviol"]]
+    assert list(S["minunit"]) == [float(x) for x in d["minunit"]]
+    assert list(S["slack_score"]) == [float(x) for x in d["slack_score"]]
+    for vs, exp in d["orders"]:
+        assert list(oracle.probe_order(inst, vs)) == exp
+
+
+@pytest.mark.parametrize("seed", range(120))
+def test_micro_scores_brute_force(seed):
+    """Integer data: every rounded step of the oracle is exact, so the
+    scores equal their exact-rational meaning."""
+    inst = gen.make_micro(seed)
+    lb, ub = inst["lb"], inst["ub"]
+    S = oracle.scores(inst)
+    nviol, maxviol, units, terms = brute_scores(inst, lb, ub)
+    assert list(S["nviol"]) == nviol
+    assert [Fraction(x) for x in S["maxviol"]] == maxviol
+    for j in range(inst["n"]):
+        assert S["minunit"][j] == (float(min(units[j])) if units[j] else INF)
+        if any(t is None for t in terms[j]):
+            assert S["slack_score"][j] == INF
+        elif terms[j]:
+            exact = sum(terms[j], Fraction(0))
+            assert abs(Fraction(S["slack_score"][j]) - exact) <= exact * Fraction(1, 2 ** 49)
+        else:
+            assert S["slack_score"][j] == 0.0
+
+
+@pytest.mark.parametrize("name,seed", [("tiny", 0), ("tiny", 3), ("tiny_inf", 1)])
+def test_tiny_scores_against_rationals(name, seed):
+    """Real coefficients: counts and slacks against exact rationals, with
+    room for the rounding of the few floating-point steps."""
+    inst = gen.make(name, seed)
+    lb, ub = inst["lb"], inst["ub"]
+    S = oracle.scores(inst)
+    nviol, maxviol, units, terms = brute_scores(inst, lb, ub)
+    for j in range(inst["n"]):
+        if S["nviol"][j] != nviol[j]:
+            # a violation within rounding of feastol may be counted either way
+            assert abs(int(S["nviol"][j]) - nviol[j]) <= 1
+        else:
+            assert abs(Fraction(S["maxviol"][j]) - maxviol[j]) <= Fraction(1, 10 ** 6) * (1 + abs(maxviol[j]))
+        if units[j]:
+            assert abs(Fraction(S["minunit"][j]) - min(units[j])) <= Fraction(1, 10 ** 7) * (1 + abs(min(units[j])))
+        else:
+            assert S["minunit"][j] == INF
+
+
+def test_probe_order_is_a_permutation_and_handles_repeats():
+    inst = gen.make("tiny", 2)
+    vs = np.array([5, 7, 5, 0, 299, 7], np.int32)
+    order = oracle.probe_order(inst, vs)
+    assert sorted(order) == sorted(vs)
+    assert list(oracle.probe_order(inst, [])) == []
+    with pytest.raises(ValueError):
+        oracle.probe_order(inst, [inst["n"]])
