@@ -217,6 +217,47 @@ int bp_propagate_batch(bp_instance *h, int32_t B, double *lb, double *ub,
 int bp_probe(bp_instance *h, const int32_t *vars, int32_t k, bp_probe_out *out,
              void *stream);
 
+/* Probe-priority and implied-slack scores of every variable j at the
+ * bounds DEVICE lb/ub [n] (any bounds: the instance's own, a base, ...).
+ * Row activities are those of propagation (correctly rounded sums of the
+ * finite terms a*b, counts of the infinite ones).  With d = a*b_max -
+ * a*b_min the amount by which moving j between its bounds moves row k's
+ * extreme activities (b_min/b_max: the bound giving j's smallest/largest
+ * contribution), and the slacks hi_k - minfin_k and maxfin_k - lo_k of the
+ * finite sides without infinite terms:
+ *   nviol[j]       rows whose d exceeds a slack by more than feastol
+ *                  (Section 2.2: the violations revealed by flipping j's
+ *                  contribution), counted only when j's coefficients have
+ *                  both signs and both its bounds are finite; else 0;
+ *   maxviol[j]     the largest such excess (0 if none);
+ *   minunit[j]     the smallest slack / |a| over j's row sides (Section 2.2,
+ *                  third criterion; +inf if none);
+ *   slack_score[j] S_j = correctly rounded sum of (a / slack)^2 over the
+ *                  same sides (Section 2.3, implied-slack sort; +inf if a
+ *                  slack is zero, 0 if no side).
+ * Each value is computed with a fixed operation order (no fused multiply-
+ * add), so results are reproducible bit for bit.  Outputs are DEVICE [n],
+ * caller-owned; any may be NULL.  Returns BP_OK, or BP_EINVAL for a null
+ * argument or a NaN bound (outputs untouched). */
+typedef struct {
+    int32_t *nviol;
+    double *maxviol;
+    double *minunit;
+    double *slack_score;
+} bp_scores_out;
+
+int bp_scores(bp_instance *h, const double *lb, const double *ub, bp_scores_out *out,
+              void *stream);
+
+/* Probe order (Section 2.2): the DEVICE variable ids vars [k] sorted by
+ * more violated rows first (nviol), then the larger maxviol, then the
+ * smaller minunit, then the smaller id -- scores at DEVICE lb/ub [n] as
+ * bp_scores computes them -- into DEVICE order [k] (caller-owned; ids may
+ * repeat).  Returns BP_OK, or BP_EINVAL for k < 0, an id outside [0, n), a
+ * null argument or a NaN bound (order untouched). */
+int bp_probe_order(bp_instance *h, const double *lb, const double *ub, const int32_t *vars,
+                   int32_t k, int32_t *order, void *stream);
+
 /* Schedule chosen by bp_autotune. */
 typedef struct {
     int32_t heavy_threshold;   /* rows longer than this split across workgroups */

@@ -23,7 +23,8 @@ FLAG_FORCE_EXACT, FLAG_TIME_KERNELS, FLAG_HOST_ROUNDS, FLAG_COUNT_VARS, FLAG_BAT
 EXPORTS = ["bp_options_default", "bp_load", "bp_propagate", "bp_propagate_batch", "bp_probe",
            "bp_get_base", "bp_kernel_stats", "bp_device_bytes", "bp_free", "bp_last_error",
            "bp_server_create", "bp_server_submit", "bp_server_run", "bp_server_poll",
-           "bp_server_results", "bp_server_info", "bp_server_destroy", "bp_autotune"]
+           "bp_server_results", "bp_server_info", "bp_server_destroy", "bp_autotune",
+           "bp_scores", "bp_probe_order"]
 REQ_PROBE, REQ_PROPAGATE = 0, 1
 
 
@@ -79,6 +80,11 @@ class Tuning(C.Structure):
                 ("ms", C.c_double), ("trials", C.c_int32), ("from_cache", C.c_int32)]
 
 
+class ScoresOut(C.Structure):
+    _fields_ = [("nviol", C.c_void_p), ("maxviol", C.c_void_p), ("minunit", C.c_void_p),
+                ("slack_score", C.c_void_p)]
+
+
 class BPError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("libbp error %d: %s" % (code, msg))
@@ -103,6 +109,11 @@ def load_library(path: str = LIB_PATH):
     lib.bp_propagate_batch.restype = C.c_int
     lib.bp_probe.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(ProbeOut), C.c_void_p]
     lib.bp_probe.restype = C.c_int
+    lib.bp_scores.restype = C.c_int
+    lib.bp_scores.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(ScoresOut), C.c_void_p]
+    lib.bp_probe_order.restype = C.c_int
+    lib.bp_probe_order.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                   C.c_void_p, C.c_void_p]
     lib.bp_get_base.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.bp_get_base.restype = C.c_int
     lib.bp_kernel_stats.argtypes = [C.c_void_p, C.POINTER(Stats), C.c_int]
@@ -276,6 +287,37 @@ class Instance:
             for key in ("var", "lb", "ub"):
                 o[key] = o[key][:tot]
             return o
+
+    def _bounds_ok(self, lb, ub):
+        for t in (lb, ub):
+            assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
+            assert t.numel() == self.n
+
+    def scores(self, lb: torch.Tensor, ub: torch.Tensor, stream=None) -> dict:
+        """bp_scores: probe-priority and implied-slack scores of every
+        variable at the float64 device bounds lb/ub."""
+        self._bounds_ok(lb, ub)
+        dev = lb.device
+        o = dict(nviol=torch.empty(self.n, dtype=torch.int32, device=dev),
+                 maxviol=torch.empty(self.n, dtype=torch.float64, device=dev),
+                 minunit=torch.empty(self.n, dtype=torch.float64, device=dev),
+                 slack_score=torch.empty(self.n, dtype=torch.float64, device=dev))
+        so = ScoresOut(o["nviol"].data_ptr(), o["maxviol"].data_ptr(), o["minunit"].data_ptr(),
+                       o["slack_score"].data_ptr())
+        _check(_LIB.bp_scores(self._h, _dptr(lb), _dptr(ub), C.byref(so), _stream_ptr(stream)))
+        return o
+
+    def probe_order(self, vars_: torch.Tensor, lb: torch.Tensor, ub: torch.Tensor,
+                    stream=None) -> torch.Tensor:
+        """bp_probe_order: vars_ (int32 device) sorted into probe order by
+        the scores at lb/ub."""
+        self._bounds_ok(lb, ub)
+        k = vars_.numel()
+        assert vars_.dtype == torch.int32 and vars_.is_cuda and vars_.is_contiguous()
+        order = torch.empty(max(k, 1), dtype=torch.int32, device=vars_.device)
+        _check(_LIB.bp_probe_order(self._h, _dptr(lb), _dptr(ub), _dptr(vars_) if k else None, k,
+                                   _dptr(order), _stream_ptr(stream)))
+        return order[:k]
 
     def autotune(self, lb: torch.Tensor, ub: torch.Tensor, vars_: torch.Tensor = None,
                  cache_path: str = None, stream=None) -> dict:

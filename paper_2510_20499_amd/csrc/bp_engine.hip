@@ -145,6 +145,11 @@ struct bp_instance {
     DevBuf cold_hbase_d;
     std::unique_ptr<Engine> eng;
     std::unique_ptr<LvEngine> lv;  // one-vector-per-lane batch engine
+    // priority scores: packed bounds, row activities, CSC values and the
+    // chunk table of the long rows (built on first use), sort keys
+    DevBuf sc_bnd, sc_act, sc_cval, sc_chunks, sc_rows, sc_first, sc_part, sc_tmp, sc_keys;
+    bool sc_ready = false;
+    int64_t sc_nchunks = 0, sc_nlong = 0;
     // stats
     bp_stats stats;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -1252,5 +1257,7 @@ extern "C" int bp_probe(bp_instance *h, const int32_t *vars, int32_t k, bp_probe
     return BP_OK;
 }
 
+#include "bp_scores.h"
+#include "bp_scores_run.h"
 #include "bp_server.h"
 #include "bp_tune.h"
