@@ -305,6 +305,7 @@ def bench_probe(args, bp, gen, torch, np):
         "implied_entries": int(G["off"][-1].item()),
         "infeasible_probes": int((G["status"] == bp.BP_INFEASIBLE).sum().item()),
     }
+    res["scores"] = bench_scores(args, bp, inst, I, lb, ub, torch, np)
     if args.probe_cpu:
         import oracle
         _, olb, oub = oracle.propagate(inst)
@@ -316,6 +317,52 @@ def bench_probe(args, bp, gen, torch, np):
                                "kind": "oracle", "nnz_per_s": float(O["nnz"].sum()) / tc,
                                "sample": "%d binaries x {0,1} of the same sample, around the "
                                          "oracle's own root fixed point, one thread" % kc}
+    return res
+
+
+def bench_scores(args, bp, inst, I, lb, ub, torch, np):
+    """Probe priority and implied-slack scores (bp_scores) of every variable
+    of the probe workload at its root fixed point, and the probe order
+    (bp_probe_order) of all its unfixed integer variables.  Algorithmic
+    bytes of a scores call: 24 per nonzero (column index and value read once
+    in the row pass and once more, as CSC row and value, in the column pass),
+    76 per row (row pointer, activity record written and read, row sides,
+    bin list) and 100 per variable (bounds read and packed, column pointer,
+    bounds again, the four outputs)."""
+    m, n, nnz = int(inst["m"]), int(inst["n"]), int(inst["row_ptr"][-1])
+    S = I.scores(lb, ub)  # warm: builds the CSC values and the chunk table
+    torch.cuda.synchronize()
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        S = I.scores(lb, ub)
+    torch.cuda.synchronize()
+    ts = (time.perf_counter() - t0) / reps
+    lbh, ubh = lb.cpu().numpy(), ub.cpu().numpy()
+    cand = np.nonzero((inst["vtype"] == 1) & (ubh > lbh))[0].astype(np.int32)
+    cand_d = torch.tensor(cand, dtype=torch.int32, device=lb.device)
+    order = I.probe_order(cand_d, lb, ub)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        order = I.probe_order(cand_d, lb, ub)
+    torch.cuda.synchronize()
+    to = (time.perf_counter() - t0) / 3
+    alg = 24 * nnz + 76 * m + 100 * n
+    res = {"workload": "scores of all %d variables (m=%d, nnz=%d) at the root fixed point; "
+                       "probe order of its %d unfixed integers" % (n, m, nnz, cand.size),
+           "scores_ms": ts * 1e3, "alg_bytes": alg, "effective_GBps": alg / ts / 1e9,
+           "frac_of_hbm": alg / ts / 8e12, "order_ms": to * 1e3, "order_vars": int(cand.size),
+           "vars_violating": int((S["nviol"] > 0).sum().item())}
+    if args.probe_cpu:
+        import oracle
+        tc = time.perf_counter()
+        oracle.scores(inst, lbh, ubh)
+        tc = time.perf_counter() - tc
+        res["cpu_baseline"] = {"value": tc * 1e3, "unit": "ms per scores call", "cores": 1,
+                               "kind": "oracle", "sample": "one scores call of the oracle on the "
+                                                           "same instance and bounds, one thread"}
+    log("scores: %.3f ms per call, order of %d vars %.3f ms" % (ts * 1e3, cand.size, to * 1e3))
     return res
 
 

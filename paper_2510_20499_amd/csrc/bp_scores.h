@@ -14,10 +14,12 @@
 //   rows  exact activities of every row (the same correctly rounded sums and
 //         infinite counts as propagation), light rows by the row bins of the
 //         instance (G lanes per row), longer rows by chunks of SC_CHUNK
-//         nonzeros whose partial sums a wave per row merges;
+//         nonzeros whose partial sums a wave per row merges; each row keeps
+//         only its two slacks (16 B, +inf for a side that has none);
 //   vars  one lane per variable walks its column (CSC values, built once per
-//         instance) and computes its four scores; the sum of s^2 is certified
-//         like the activities and falls back to the exact accumulator.
+//         instance) four entries at a time and computes its four scores; the
+//         sum of s^2 is certified like the activities and falls back to the
+//         exact accumulator.
 // The probe order sorts (nviol desc, maxviol desc, minunit asc, index asc)
 // keys with a bitonic network in global memory.
 #pragma once
@@ -26,10 +28,20 @@ namespace bp {
 
 constexpr int SC_CHUNK = 4096;  // nonzeros per partial sum of a row longer than 1024
 
-struct ScRowAct {
-    double minfin, maxfin;
-    int32_t nmin, nmax;
-};
+// Slacks of row k from its exact activities: (hi - minfin, maxfin - lo), +inf
+// for a side that is infinite or has an infinite term.  A usable side's
+// slack can only be +inf when its activity overflowed; it then adds nothing
+// to any score (zero term, infinite unit slack, no violation), exactly as
+// a side without slack.
+__device__ __forceinline__ double2 sc_slacks(double2 sd, double minfin, double maxfin, int nmin,
+                                             int nmax) {
+    const double INF = __builtin_inf();
+    const bool hi_ok = sd.y < INF && nmin == 0;
+    const bool lo_ok = sd.x > -INF && nmax == 0;
+    double sh = hi_ok ? sd.y - minfin : INF;
+    double sl = lo_ok ? maxfin - sd.x : INF;
+    return make_double2(sh, sl);
+}
 
 __device__ __forceinline__ BView sc_view(const double2 *bnd) {
     BView v;
@@ -41,80 +53,103 @@ __device__ __forceinline__ BView sc_view(const double2 *bnd) {
     return v;
 }
 
-// Activities of the rows rows[0..count) of one light bin, G lanes per row
-// (G == 64: one row per wave, several nonzeros per lane).
+// Activities of one unit (256 / G rows) of the rows rows[0..count) of a
+// light bin, G lanes per row (G == 64: one row per wave, several nonzeros
+// per lane); the row's slacks are stored.  Reached by whole waves.
 template <int G>
-__global__ void __launch_bounds__(WG) k_sc_light(DInst I, const double2 *bnd, const int32_t *rows,
-                                                 int64_t count, ScRowAct *act) {
+__device__ void sc_light_unit(const DInst &I, const double2 *bnd, const int32_t *rows,
+                              int64_t count, int64_t unit, double2 *slk) {
     const int lane = __lane_id();
     const int gl = lane & (G - 1);
     const int64_t per_wave = 64 / G;
-    const int64_t nwaves = (int64_t)gridDim.x * (WG / 64);
-    const BView view = sc_view(bnd);
-    // Wave-uniform trip count: the group reductions shuffle across the wave.
-    for (int64_t w = (int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6); w * per_wave < count;
-         w += nwaves) {
-        const int64_t t = w * per_wave + lane / G;
-        const bool valid = t < count;
-        int k = 0;
-        int64_t p0 = 0, p1 = 0;
-        if (valid) {
-            k = rows[t];
-            p0 = I.row_ptr[k];
-            p1 = I.row_ptr[k + 1];
+    const int64_t t = (unit * (WG / 64) + (threadIdx.x >> 6)) * per_wave + lane / G;
+    const bool valid = t < count;
+    int k = 0;
+    int64_t p0 = 0, p1 = 0;
+    if (valid) {
+        k = rows[t];
+        p0 = I.row_ptr[k];
+        p1 = I.row_ptr[k + 1];
+    }
+    Acc mn, mx;
+    acc_zero(mn);
+    acc_zero(mx);
+    const int iters = G < 64 ? 1 : (int)((p1 - p0 + 63) / 64);
+    for (int it = 0; it < iters; ++it) {
+        const int64_t p = p0 + gl + (int64_t)it * G;
+        if (p < p1) {
+            const double a = I.val[p];
+            const double2 b = bnd[I.col[p]];
+            add_terms(mn, mx, a, b.x, b.y);
         }
-        Acc mn, mx;
-        acc_zero(mn);
-        acc_zero(mx);
-        const int iters = G < 64 ? 1 : (int)((p1 - p0 + 63) / 64);
-        for (int it = 0; it < iters; ++it) {
-            const int64_t p = p0 + gl + (int64_t)it * G;
-            if (p < p1) {
-                const double a = I.val[p];
-                const double2 b = bnd[I.col[p]];
-                add_terms(mn, mx, a, b.x, b.y);
-            }
-        }
-        acc_group_reduce<G>(mn);
-        acc_group_reduce<G>(mx);
-        double vmin = 0.0, vmax = 0.0;
-        const bool okmin = acc_certify(mn, vmin);
-        const bool okmax = acc_certify(mx, vmax);
-        if (valid && gl == 0) {
-            if (!okmin) vmin = exact_side(I, view, p0, p1, false);
-            if (!okmax) vmax = exact_side(I, view, p0, p1, true);
-            ScRowAct r;
-            r.minfin = vmin;
-            r.maxfin = vmax;
-            r.nmin = mn.ninf;
-            r.nmax = mx.ninf;
-            act[k] = r;
-        }
+    }
+    acc_group_reduce<G>(mn);
+    acc_group_reduce<G>(mx);
+    double vmin = 0.0, vmax = 0.0;
+    const bool okmin = acc_certify(mn, vmin);
+    const bool okmax = acc_certify(mx, vmax);
+    if (valid && gl == 0) {
+        const BView view = sc_view(bnd);
+        if (!okmin) vmin = exact_side(I, view, p0, p1, false);
+        if (!okmax) vmax = exact_side(I, view, p0, p1, true);
+        slk[k] = sc_slacks(I.side[k], vmin, vmax, mn.ninf, mx.ninf);
     }
 }
 
-// Partial sums of the chunks of the long rows: chunk u is (row, chunk
-// index, chunks of the row, -); one workgroup per chunk.
-__global__ void __launch_bounds__(WG) k_sc_chunks(DInst I, const double2 *bnd, const int4 *chunks,
-                                                  int64_t nchunks, Acc *part) {
+// Partial sums of chunk u of the long rows (chunk record: row, chunk index,
+// chunks of the row); one workgroup.
+__device__ void sc_chunk_unit(const DInst &I, const double2 *bnd, const int4 *chunks, int64_t u,
+                              Acc *part, WgScratch &W) {
+    const int4 rec = chunks[u];
+    const int64_t r0 = I.row_ptr[rec.x], r1 = I.row_ptr[rec.x + 1];
+    const int64_t p0 = r0 + (int64_t)rec.y * SC_CHUNK;
+    const int64_t p1 = min(r1, p0 + (int64_t)SC_CHUNK);
+    Acc mn, mx;
+    acc_zero(mn);
+    acc_zero(mx);
+    double wmax = 0.0;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += WG) {
+        const double2 b = bnd[I.col[p]];
+        add_terms(mn, mx, I.val[p], b.x, b.y);
+    }
+    wg_reduce(mn, mx, wmax, W);
+    if (threadIdx.x == 0) {
+        part[2 * u] = mn;
+        part[2 * u + 1] = mx;
+    }
+}
+
+// Work of the row pass: the chunks of the long rows first (one unit each),
+// then the light bins 10..0 (256 / G rows per unit).
+struct ScRowsWork {
+    const int4 *chunks;
+    int64_t nchunks;
+    const int32_t *rows[NLIGHT];  // rows of light bin b
+    int64_t count[NLIGHT];
+    int64_t start[NLIGHT + 2];    // unit offsets: [0] chunks, [1 + j] bin 10 - j
+};
+
+__global__ void __launch_bounds__(WG) k_sc_rows(DInst I, const double2 *bnd, ScRowsWork R,
+                                                Acc *part, double2 *slk) {
     __shared__ WgScratch W;
-    for (int64_t u = blockIdx.x; u < nchunks; u += gridDim.x) {
-        const int4 rec = chunks[u];
-        const int64_t r0 = I.row_ptr[rec.x], r1 = I.row_ptr[rec.x + 1];
-        const int64_t p0 = r0 + (int64_t)rec.y * SC_CHUNK;
-        const int64_t p1 = min(r1, p0 + (int64_t)SC_CHUNK);
-        Acc mn, mx;
-        acc_zero(mn);
-        acc_zero(mx);
-        double wmax = 0.0;
-        for (int64_t p = p0 + threadIdx.x; p < p1; p += WG) {
-            const double2 b = bnd[I.col[p]];
-            add_terms(mn, mx, I.val[p], b.x, b.y);
+    const int64_t total = R.start[NLIGHT + 1];
+    for (int64_t u = blockIdx.x; u < total; u += gridDim.x) {
+        if (u < R.start[1]) {
+            sc_chunk_unit(I, bnd, R.chunks, u, part, W);
+            continue;
         }
-        wg_reduce(mn, mx, wmax, W);
-        if (threadIdx.x == 0) {
-            part[2 * u] = mn;
-            part[2 * u + 1] = mx;
+        int j = 0;
+        while (u >= R.start[2 + j]) ++j;
+        const int b = NLIGHT - 1 - j;
+        const int64_t lu = u - R.start[1 + j];
+        switch (b) {
+            case 0: sc_light_unit<1>(I, bnd, R.rows[0], R.count[0], lu, slk); break;
+            case 1: sc_light_unit<2>(I, bnd, R.rows[1], R.count[1], lu, slk); break;
+            case 2: sc_light_unit<4>(I, bnd, R.rows[2], R.count[2], lu, slk); break;
+            case 3: sc_light_unit<8>(I, bnd, R.rows[3], R.count[3], lu, slk); break;
+            case 4: sc_light_unit<16>(I, bnd, R.rows[4], R.count[4], lu, slk); break;
+            case 5: sc_light_unit<32>(I, bnd, R.rows[5], R.count[5], lu, slk); break;
+            default: sc_light_unit<64>(I, bnd, R.rows[b], R.count[b], lu, slk); break;
         }
     }
 }
@@ -123,7 +158,7 @@ __global__ void __launch_bounds__(WG) k_sc_chunks(DInst I, const double2 *bnd, c
 // takes chunks l, l + 64, ...), certified, else the exact accumulator.
 __global__ void __launch_bounds__(WG) k_sc_combine(DInst I, const double2 *bnd, const int32_t *rows,
                                                    const int64_t *first, int64_t nrows,
-                                                   const Acc *part, ScRowAct *act) {
+                                                   const Acc *part, double2 *slk) {
     const int lane = __lane_id();
     const int64_t nwaves = (int64_t)gridDim.x * (WG / 64);
     const BView view = sc_view(bnd);
@@ -147,12 +182,7 @@ __global__ void __launch_bounds__(WG) k_sc_combine(DInst I, const double2 *bnd, 
             const int64_t p0 = I.row_ptr[k], p1 = I.row_ptr[k + 1];
             if (!okmin) vmin = exact_side(I, view, p0, p1, false);
             if (!okmax) vmax = exact_side(I, view, p0, p1, true);
-            ScRowAct r;
-            r.minfin = vmin;
-            r.maxfin = vmax;
-            r.nmin = A.ninf;
-            r.nmax = B.ninf;
-            act[k] = r;
+            slk[k] = sc_slacks(I.side[k], vmin, vmax, A.ninf, B.ninf);
         }
     }
 }
@@ -175,34 +205,73 @@ __global__ void k_sc_cval(DInst I, double *cval) {
     }
 }
 
-// The two finite sides of row k usable for slack (no infinite term on that
-// side) and their slacks hi - minfin and maxfin - lo.
-struct ScSides {
-    bool hi_ok, lo_ok;
-    double slack_hi, slack_lo;
+// The terms of one column entry (coefficient a, row slacks sl) into the
+// running scores of its variable.
+struct ScVar {
+    bool pos, neg, sinf;
+    int32_t nv;
+    double mv, mu;
+    Acc A;
 };
 
-__device__ __forceinline__ ScSides sc_sides(const ScRowAct &R, double2 sd) {
-    ScSides S;
-    S.hi_ok = sd.y < __builtin_inf() && R.nmin == 0;
-    S.lo_ok = sd.x > -__builtin_inf() && R.nmax == 0;
-    S.slack_hi = S.hi_ok ? sd.y - R.minfin : 0.0;
-    S.slack_lo = S.lo_ok ? R.maxfin - sd.x : 0.0;
-    return S;
+__device__ __forceinline__ void sc_entry(ScVar &V, double a, double2 sl, bool finite, double bmin_lo,
+                                         double bmin_hi, double feastol) {
+    const double INF = __builtin_inf();
+    const bool hi_ok = sl.x < INF, lo_ok = sl.y < INF;
+    V.pos = V.pos || a > 0.0;
+    V.neg = V.neg || a < 0.0;
+    if (finite) {
+        // flipped contribution: how far moving the variable between its
+        // bounds pushes the row's extreme activities
+        const double bmin = a > 0.0 ? bmin_lo : bmin_hi;
+        const double bmax = a > 0.0 ? bmin_hi : bmin_lo;
+        const double d = a * bmax - a * bmin;
+        bool viol = false;
+        double worst = 0.0;
+        if (hi_ok) {
+            const double e = d - sl.x;
+            if (e > feastol) {
+                viol = true;
+                worst = e;
+            }
+        }
+        if (lo_ok) {
+            const double e = d - sl.y;
+            if (e > feastol && (!viol || e > worst)) {
+                viol = true;
+                worst = e;
+            }
+        }
+        if (viol) {
+            V.nv += 1;
+            if (worst > V.mv) V.mv = worst;
+        }
+    }
+    for (int side = 0; side < 2; ++side) {
+        if (side == 0 ? !hi_ok : !lo_ok) continue;
+        const double slack = side == 0 ? sl.x : sl.y;
+        const double u = slack / fabs(a);
+        if (u < V.mu) V.mu = u;
+        const double s = a / slack;
+        const double t = s * s;
+        if (isinf(t)) V.sinf = true;
+        else acc_add(V.A, t);
+    }
 }
 
 // Exact sum of the finite (a / slack)^2 terms of variable j (slow path).
 __device__ __noinline__ double sc_exact_score(const DInst &I, const double *cval,
-                                              const ScRowAct *act, int64_t j) {
+                                              const double2 *slk, int64_t j) {
+    const double INF = __builtin_inf();
     SuperAcc S;
     sa_zero(S);
     for (int64_t p = I.col_ptr[j]; p < I.col_ptr[j + 1]; ++p) {
-        const int k = I.col_row[p];
         const double a = cval[p];
-        const ScSides sd = sc_sides(act[k], I.side[k]);
+        const double2 sl = slk[I.col_row[p]];
         for (int side = 0; side < 2; ++side) {
-            if (side == 0 ? !sd.hi_ok : !sd.lo_ok) continue;
-            const double s = a / (side == 0 ? sd.slack_hi : sd.slack_lo);
+            const double slack = side == 0 ? sl.x : sl.y;
+            if (!(slack < INF)) continue;
+            const double s = a / slack;
             const double t = s * s;
             if (!isinf(t)) sa_add(S, t);
         }
@@ -210,75 +279,53 @@ __device__ __noinline__ double sc_exact_score(const DInst &I, const double *cval
     return canon0(sa_round(S));
 }
 
+constexpr int SC_UNROLL = 4;  // column entries whose loads a lane issues together
+
 // Scores of every variable, one lane per variable (any output may be null).
 __global__ void __launch_bounds__(WG) k_sc_vars(DInst I, const double2 *bnd, const double *cval,
-                                                const ScRowAct *act, double feastol, int32_t *nviol,
+                                                const double2 *slk, double feastol, int32_t *nviol,
                                                 double *maxviol, double *minunit, double *sscore) {
     const double INF = __builtin_inf();
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < I.n;
          j += (int64_t)gridDim.x * blockDim.x) {
         const double2 b = bnd[j];
         const bool finite = !isinf(b.x) && !isinf(b.y);
-        bool pos = false, neg = false, sinf = false;
-        int32_t nv = 0;
-        double mv = 0.0, mu = INF;
-        Acc A;
-        acc_zero(A);
-        for (int64_t p = I.col_ptr[j]; p < I.col_ptr[j + 1]; ++p) {
-            const int k = I.col_row[p];
-            const double a = cval[p];
-            const ScSides sd = sc_sides(act[k], I.side[k]);
-            pos = pos || a > 0.0;
-            neg = neg || a < 0.0;
-            if (finite) {
-                // flipped contribution: how far moving j between its bounds
-                // pushes the row's extreme activities
-                const double bmin = a > 0.0 ? b.x : b.y;
-                const double bmax = a > 0.0 ? b.y : b.x;
-                const double d = a * bmax - a * bmin;
-                bool viol = false;
-                double worst = 0.0;
-                if (sd.hi_ok) {
-                    const double e = d - sd.slack_hi;
-                    if (e > feastol) {
-                        viol = true;
-                        worst = e;
-                    }
-                }
-                if (sd.lo_ok) {
-                    const double e = d - sd.slack_lo;
-                    if (e > feastol && (!viol || e > worst)) {
-                        viol = true;
-                        worst = e;
-                    }
-                }
-                if (viol) {
-                    nv += 1;
-                    if (worst > mv) mv = worst;
+        ScVar V;
+        V.pos = V.neg = V.sinf = false;
+        V.nv = 0;
+        V.mv = 0.0;
+        V.mu = INF;
+        acc_zero(V.A);
+        const int64_t c0 = I.col_ptr[j], c1 = I.col_ptr[j + 1];
+        for (int64_t p = c0; p < c1; p += SC_UNROLL) {
+            int k[SC_UNROLL];
+            double a[SC_UNROLL];
+            double2 sl[SC_UNROLL];
+#pragma unroll
+            for (int q = 0; q < SC_UNROLL; ++q) {
+                if (p + q < c1) {
+                    k[q] = I.col_row[p + q];
+                    a[q] = cval[p + q];
                 }
             }
-            for (int side = 0; side < 2; ++side) {
-                if (side == 0 ? !sd.hi_ok : !sd.lo_ok) continue;
-                const double slack = side == 0 ? sd.slack_hi : sd.slack_lo;
-                const double u = slack / fabs(a);
-                if (u < mu) mu = u;
-                const double s = a / slack;
-                const double t = s * s;
-                if (isinf(t)) sinf = true;
-                else acc_add(A, t);
-            }
+#pragma unroll
+            for (int q = 0; q < SC_UNROLL; ++q)
+                if (p + q < c1) sl[q] = slk[k[q]];
+#pragma unroll
+            for (int q = 0; q < SC_UNROLL; ++q)
+                if (p + q < c1) sc_entry(V, a[q], sl[q], finite, b.x, b.y, feastol);
         }
-        if (!(pos && neg)) {
-            nv = 0;
-            mv = 0.0;
+        if (!(V.pos && V.neg)) {
+            V.nv = 0;
+            V.mv = 0.0;
         }
-        if (nviol) nviol[j] = nv;
-        if (maxviol) maxviol[j] = canon0(mv);
-        if (minunit) minunit[j] = canon0(mu);
+        if (nviol) nviol[j] = V.nv;
+        if (maxviol) maxviol[j] = canon0(V.mv);
+        if (minunit) minunit[j] = canon0(V.mu);
         if (sscore) {
             double v = 0.0;
-            if (sinf) v = INF;
-            else if (!acc_certify(A, v)) v = sc_exact_score(I, cval, act, j);
+            if (V.sinf) v = INF;
+            else if (!acc_certify(V.A, v)) v = sc_exact_score(I, cval, slk, j);
             sscore[j] = canon0(v);
         }
     }
@@ -342,6 +389,39 @@ __global__ void k_sc_bitonic(ScKey *keys, int64_t kpad, int64_t size, int64_t st
             keys[i] = B;
             keys[l] = A;
         }
+    }
+}
+
+// The same network inside LDS for the steps whose partners lie in one tile
+// of SC_TILE keys: sizes size_lo..size_hi, the first of them starting at
+// `stride0`, every later one at size / 2.  Directions come from the global
+// index, so tiles of one block of the network agree.
+constexpr int SC_TILE = 1024;
+
+__global__ void __launch_bounds__(WG) k_sc_bitonic_tile(ScKey *keys, int64_t kpad, int64_t size_lo,
+                                                        int64_t size_hi, int64_t stride0) {
+    __shared__ ScKey T[SC_TILE];
+    const int64_t tile = kpad < SC_TILE ? kpad : SC_TILE;
+    for (int64_t base = (int64_t)blockIdx.x * tile; base < kpad; base += (int64_t)gridDim.x * tile) {
+        for (int64_t t = threadIdx.x; t < tile; t += WG) T[t] = keys[base + t];
+        for (int64_t size = size_lo; size <= size_hi; size <<= 1) {
+            for (int64_t stride = size == size_lo ? stride0 : size >> 1; stride > 0; stride >>= 1) {
+                __syncthreads();
+                for (int64_t q = threadIdx.x; q < tile / 2; q += WG) {
+                    const int64_t i = 2 * stride * (q / stride) + (q % stride);
+                    const int64_t l = i + stride;
+                    const bool up = ((base + i) & size) == 0;
+                    const ScKey A = T[i], B = T[l];
+                    if (up ? sc_before(B, A) : sc_before(A, B)) {
+                        T[i] = B;
+                        T[l] = A;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        for (int64_t t = threadIdx.x; t < tile; t += WG) keys[base + t] = T[t];
+        __syncthreads();
     }
 }
 

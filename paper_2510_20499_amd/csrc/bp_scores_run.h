@@ -38,16 +38,11 @@ static int sc_build(bp_instance *h, hipStream_t st) {
                               hipMemcpyHostToDevice, st));
     }
     HIPTRY(hipMemcpyAsync(h->sc_first.p, first.data(), first.size() * 8, hipMemcpyHostToDevice, st));
-    if ((rc = h->sc_act.alloc((size_t)std::max<int32_t>(h->m, 1) * sizeof(ScRowAct), h->bytes))) return rc;
+    if ((rc = h->sc_act.alloc((size_t)std::max<int32_t>(h->m, 1) * sizeof(double2), h->bytes))) return rc;
     if ((rc = h->sc_bnd.alloc((size_t)std::max<int32_t>(h->n, 1) * 16, h->bytes))) return rc;
     HIPTRY(hipStreamSynchronize(st));
     h->sc_ready = true;
     return 0;
-}
-
-static int sc_light_blocks(int64_t count, int G) {
-    const int64_t waves = (count * G + 63) / 64;
-    return (int)std::max<int64_t>(1, std::min<int64_t>((waves + 3) / 4, 4096));
 }
 
 // Bounds in (NaN rejected), then the exact activity of every row.
@@ -67,29 +62,27 @@ static int sc_rows_pass(bp_instance *h, const double *lb, const double *ub, hipS
         HIPTRY(hipStreamSynchronize(st));
         if (bad) return fail(BP_EINVAL, "NaN bound");
     }
-    ScRowAct *act = h->sc_act.as<ScRowAct>();
+    double2 *act = h->sc_act.as<double2>();
     const int32_t *cold = h->cold_rows.as<int32_t>();
-    for (int b = 0; b < NLIGHT; ++b) {
-        const int64_t cnt = h->bin_count[b];
-        if (cnt == 0) continue;
-        const int32_t *rows = cold + h->bin_start[b];
-        switch (b) {
-            case 0: k_sc_light<1><<<sc_light_blocks(cnt, 1), WG, 0, st>>>(I, bnd, rows, cnt, act); break;
-            case 1: k_sc_light<2><<<sc_light_blocks(cnt, 2), WG, 0, st>>>(I, bnd, rows, cnt, act); break;
-            case 2: k_sc_light<4><<<sc_light_blocks(cnt, 4), WG, 0, st>>>(I, bnd, rows, cnt, act); break;
-            case 3: k_sc_light<8><<<sc_light_blocks(cnt, 8), WG, 0, st>>>(I, bnd, rows, cnt, act); break;
-            case 4: k_sc_light<16><<<sc_light_blocks(cnt, 16), WG, 0, st>>>(I, bnd, rows, cnt, act); break;
-            case 5: k_sc_light<32><<<sc_light_blocks(cnt, 32), WG, 0, st>>>(I, bnd, rows, cnt, act); break;
-            default: k_sc_light<64><<<sc_light_blocks(cnt, 64), WG, 0, st>>>(I, bnd, rows, cnt, act); break;
-        }
+    ScRowsWork R;
+    R.chunks = h->sc_chunks.as<int4>();
+    R.nchunks = h->sc_nchunks;
+    R.start[0] = 0;
+    R.start[1] = h->sc_nchunks;
+    for (int j = 0; j < NLIGHT; ++j) {
+        const int b = NLIGHT - 1 - j;
+        const int64_t G = b >= 6 ? 64 : (int64_t)1 << b;
+        R.rows[b] = cold + h->bin_start[b];
+        R.count[b] = h->bin_count[b];
+        R.start[2 + j] = R.start[1 + j] + (R.count[b] * G + WG - 1) / WG;
     }
-    if (h->sc_nchunks > 0) {
-        k_sc_chunks<<<(int)std::min<int64_t>(h->sc_nchunks, 4096), WG, 0, st>>>(
-            I, bnd, h->sc_chunks.as<int4>(), h->sc_nchunks, h->sc_part.as<Acc>());
+    const int64_t units = R.start[NLIGHT + 1];
+    if (units > 0)
+        k_sc_rows<<<(int)std::min<int64_t>(units, 8192), WG, 0, st>>>(I, bnd, R, h->sc_part.as<Acc>(), act);
+    if (h->sc_nlong > 0)
         k_sc_combine<<<(int)std::min<int64_t>((h->sc_nlong + 3) / 4, 4096), WG, 0, st>>>(
             I, bnd, h->sc_rows.as<int32_t>(), h->sc_first.as<int64_t>(), h->sc_nlong,
             h->sc_part.as<Acc>(), act);
-    }
     HIPTRY(hipGetLastError());
     return 0;
 }
@@ -102,7 +95,7 @@ extern "C" int bp_scores(bp_instance *h, const double *lb, const double *ub, bp_
     if (int rc = sc_rows_pass(h, lb, ub, st)) return rc;
     if (h->n > 0)
         k_sc_vars<<<grid_for(h->n), 256, 0, st>>>(dinst_of(h), h->sc_bnd.as<double2>(),
-                                                   h->sc_cval.as<double>(), h->sc_act.as<ScRowAct>(),
+                                                   h->sc_cval.as<double>(), h->sc_act.as<double2>(),
                                                    h->opt.feastol, out->nviol, out->maxviol,
                                                    out->minunit, out->slack_score);
     HIPTRY(hipGetLastError());
@@ -127,16 +120,23 @@ extern "C" int bp_probe_order(bp_instance *h, const double *lb, const double *ub
     double *mu = mv + n;
     int32_t *nv = (int32_t *)(mu + n);
     k_sc_vars<<<grid_for(n), 256, 0, st>>>(dinst_of(h), h->sc_bnd.as<double2>(), h->sc_cval.as<double>(),
-                                           h->sc_act.as<ScRowAct>(), h->opt.feastol, nv, mv, mu,
+                                           h->sc_act.as<double2>(), h->opt.feastol, nv, mv, mu,
                                            nullptr);
     int64_t kpad = 1;
     while (kpad < k) kpad <<= 1;
     if (int rc = h->sc_keys.grow((size_t)kpad * sizeof(ScKey), h->bytes)) return rc;
     ScKey *keys = h->sc_keys.as<ScKey>();
     k_sc_keys<<<grid_for(kpad), 256, 0, st>>>(vars, k, kpad, nv, mv, mu, keys);
-    for (int64_t size = 2; size <= kpad; size <<= 1)
-        for (int64_t stride = size >> 1; stride > 0; stride >>= 1)
+    // sizes up to one tile entirely in LDS; each larger size: the steps whose
+    // partners are a tile or more apart in global memory, the rest in LDS
+    const int64_t tile = std::min<int64_t>(kpad, SC_TILE);
+    const int tiles = (int)std::min<int64_t>(kpad / tile, 4096);
+    if (kpad > 1) k_sc_bitonic_tile<<<tiles, WG, 0, st>>>(keys, kpad, 2, tile, 1);
+    for (int64_t size = 2 * tile; size <= kpad; size <<= 1) {
+        for (int64_t stride = size >> 1; stride >= tile; stride >>= 1)
             k_sc_bitonic<<<grid_for(kpad), 256, 0, st>>>(keys, kpad, size, stride);
+        k_sc_bitonic_tile<<<tiles, WG, 0, st>>>(keys, kpad, size, size, tile >> 1);
+    }
     k_sc_order_out<<<grid_for(k), 256, 0, st>>>(keys, k, order);
     HIPTRY(hipGetLastError());
     HIPTRY(hipStreamSynchronize(st));
