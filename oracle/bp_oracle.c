@@ -22,6 +22,9 @@
  *   probing   a binary fixed to 0 and to 1, each propagated from the same
  *             base (Section 2.2), the implications being the bounds that
  *             differ from the base
+ *   rounding  bulk fix-and-propagate of the integer variables towards a
+ *             fractional point (Algorithm 1 and Section 2.3, without the
+ *             repair procedure and the LP polish)
  *   scores    the probe priority (Section 2.2: rows violated when a
  *             variable's contribution flips between its bounds, the largest
  *             violation, the smallest unit slack) and the implied-slack score
@@ -826,5 +829,265 @@ int orc_probe_order(const orc_instance *I, const double *lb, const double *ub,
         for (int32_t t = 0; t < k; ++t) order[t] = P[t].var;
     }
     free(nv); free(mv); free(mu); free(P);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Bound-propagation rounding (bulk fix-and-propagate).                     */
+/* ------------------------------------------------------------------------ */
+/* ROUND (the paper's Algorithm 1 and Section 2.3, without the repair
+ * procedure and the LP polish): fix every integer variable of the box
+ * (lb, ub) to a value drawn from the fractional point x, a bulk of
+ * variables at a time, propagating after each bulk.
+ *
+ *   unset     the integer variables with lb < ub at the start, sorted by
+ *             interval class (width 1, width 2, other), then by the distance
+ *             of x (clamped into the box) to the nearest integer, then index;
+ *   bulk      R unfixed variables left: 1 in recovery mode or when R <= 36,
+ *             else ceil(sqrt(R)).  A bulk larger than one first re-sorts the
+ *             unfixed variables by the implied-slack score S (orc_scores at
+ *             the current box) descending, stably;
+ *   values    two candidate values per member, h = 0 and 1, from the draw
+ *             u = draws[2j + h]: with x clamped into the current box and
+ *             f = x - floor(x), random rounding (up when u < f) for
+ *             0.25 < f < 0.75, else the nearest integer (f < 0.5 down);
+ *   cache     (optional probing cache of binaries: probe 2t + v fixes
+ *             cache_vars[t] to v) a member whose cached probe for its value
+ *             is infeasible is dropped; then a member whose value lies
+ *             outside the box implied by the cached lists of the remaining
+ *             members is dropped; the kept members' fixings and cached
+ *             implications form the warm start of the bulk;
+ *   propagate each of the two bulks from the current box with its fixings
+ *             and implications applied, the changed list holding the kept
+ *             members and the implied variables; a bulk that keeps no
+ *             member counts as failed;
+ *   accept    the first bulk that is not infeasible replaces the box and
+ *             ends recovery mode;
+ *   recover   when both fail: enter recovery mode (one variable per bulk)
+ *             unless already in it or the path is marked infeasible, else
+ *             mark the path infeasible; on a marked path a failed bulk's
+ *             members are fixed to their first values without propagation
+ *             and recovery mode ends.
+ *
+ * lb/ub (length n) are read and written in place.  draws has 2n entries in
+ * [0, 1).  res: status (ORC_OK, or ORC_INFEASIBLE for a marked path), then
+ * bulks, singles (propagation steps with more than one / one variable),
+ * recoveries, the number of variables fixed, nnz propagated. */
+typedef struct {
+    int32_t status, bulks, singles, recoveries, fixed, iterations;
+    int64_t nnz_propagated;
+} orc_round_result;
+
+typedef struct {
+    int32_t var, cls;
+    double frac, key;
+    int64_t pos;
+} orc_rkey;
+
+static int rkey_initial(const void *x, const void *y) {
+    const orc_rkey *a = (const orc_rkey *)x, *b = (const orc_rkey *)y;
+    if (a->cls != b->cls) return a->cls < b->cls ? -1 : 1;
+    if (a->frac != b->frac) return a->frac < b->frac ? -1 : 1;
+    return a->var < b->var ? -1 : (a->var > b->var ? 1 : 0);
+}
+
+static int rkey_slack(const void *x, const void *y) {
+    const orc_rkey *a = (const orc_rkey *)x, *b = (const orc_rkey *)y;
+    if (a->key != b->key) return a->key > b->key ? -1 : 1;
+    return a->pos < b->pos ? -1 : (a->pos > b->pos ? 1 : 0);
+}
+
+static double clampd(double v, double l, double u) { return v < l ? l : (v > u ? u : v); }
+
+/* Candidate value of variable j for draw u in the box [l, u_]. */
+static double round_value(double x, double l, double hi, double u) {
+    double xc = clampd(x, l, hi);
+    double fl = floor(xc);
+    double f = xc - fl;
+    double v;
+    if (f > 0.25 && f < 0.75) v = u < f ? fl + 1.0 : fl;
+    else v = f < 0.5 ? fl : fl + 1.0;
+    return clampd(v, l, hi);
+}
+
+int orc_round(const orc_instance *I, double *lb, double *ub, const double *x, const double *draws,
+              int32_t k, const int32_t *cache_vars, const int8_t *cstatus, const int64_t *coff,
+              const int32_t *cvar, const double *clb, const double *cub, const orc_options *o,
+              orc_round_result *res) {
+    const int64_t n = I->n;
+    memset(res, 0, sizeof(*res));
+    for (int64_t j = 0; j < n; ++j)
+        if (isnan(x[j]) || isnan(lb[j]) || isnan(ub[j])) return ORC_EINVAL;
+    for (int64_t j = 0; j < 2 * n; ++j)
+        if (!(draws[j] >= 0.0 && draws[j] < 1.0)) return ORC_EINVAL;
+    int rc = 0;
+    int64_t *cpos = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    orc_rkey *keys = (orc_rkey *)malloc((size_t)(n > 0 ? n : 1) * sizeof(orc_rkey));
+    int32_t *order = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    double *S = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    double *vl[2], *vu[2], *val[2], *box_l, *box_u;
+    int32_t *chg = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    int8_t *keep = (int8_t *)malloc((size_t)(n > 0 ? n : 1));
+    vl[0] = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    vl[1] = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    vu[0] = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    vu[1] = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    val[0] = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    val[1] = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    box_l = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    box_u = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    if (!cpos || !keys || !order || !S || !chg || !keep || !vl[0] || !vl[1] || !vu[0] || !vu[1] ||
+        !val[0] || !val[1] || !box_l || !box_u) {
+        rc = ORC_ENOMEM;
+        goto done;
+    }
+    /* cache lookup: cpos[j] = t of the cached binary j, or -1 */
+    for (int64_t j = 0; j < n; ++j) cpos[j] = -1;
+    for (int32_t t = 0; t < k; ++t) {
+        if (cache_vars[t] < 0 || cache_vars[t] >= n) { rc = ORC_EINVAL; goto done; }
+        cpos[cache_vars[t]] = t;
+    }
+    /* initial order */
+    int64_t nu = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        if (!I->vtype[j] || !(lb[j] < ub[j])) continue;
+        double w = ub[j] - lb[j];
+        double xc = clampd(x[j], lb[j], ub[j]);
+        double f = xc - floor(xc);
+        keys[nu].var = (int32_t)j;
+        keys[nu].cls = w == 1.0 ? 0 : (w == 2.0 ? 1 : 2);
+        keys[nu].frac = f < 1.0 - f ? f : 1.0 - f;
+        nu += 1;
+    }
+    qsort(keys, (size_t)nu, sizeof(orc_rkey), rkey_initial);
+    for (int64_t t = 0; t < nu; ++t) order[t] = keys[t].var;
+    int recovery = 0, infeasible = 0;
+    const int64_t cap_iter = 2 * nu + 16;
+    for (;;) {
+        /* the unfixed variables, in order */
+        int64_t R = 0;
+        for (int64_t t = 0; t < nu; ++t)
+            if (lb[order[t]] < ub[order[t]]) order[R++] = order[t];
+        nu = R;
+        if (R == 0) break;
+        if (res->iterations >= cap_iter) { rc = ORC_EINVAL; goto done; } /* cannot happen */
+        res->iterations += 1;
+        int64_t bulk = (recovery || R <= 36) ? 1 : (int64_t)ceil(sqrt((double)R));
+        if (bulk > 1) {
+            if ((rc = orc_scores(I, lb, ub, o, NULL, NULL, NULL, S)) != 0) goto done;
+            for (int64_t t = 0; t < R; ++t) {
+                keys[t].var = order[t];
+                keys[t].key = S[order[t]];
+                keys[t].pos = t;
+            }
+            qsort(keys, (size_t)R, sizeof(orc_rkey), rkey_slack);
+            for (int64_t t = 0; t < R; ++t) order[t] = keys[t].var;
+        }
+        if (bulk > R) bulk = R;
+        int ok[2] = {0, 0};
+        orc_result pr[2];
+        for (int h = 0; h < 2; ++h) {
+            /* values */
+            for (int64_t t = 0; t < bulk; ++t) {
+                int32_t j = order[t];
+                val[h][t] = round_value(x[j], lb[j], ub[j], draws[2 * (int64_t)j + h]);
+                keep[t] = 1;
+            }
+            /* cache: infeasible cached values, then values outside the box
+             * implied by the other members' cached lists */
+            for (int64_t t = 0; t < bulk; ++t) {
+                int32_t j = order[t];
+                int64_t c = cpos[j];
+                double v = val[h][t];
+                if (c >= 0 && (v == 0.0 || v == 1.0) && cstatus[2 * c + (int64_t)v] == ORC_INFEASIBLE)
+                    keep[t] = 0;
+            }
+            memcpy(box_l, lb, (size_t)n * sizeof(double));
+            memcpy(box_u, ub, (size_t)n * sizeof(double));
+            for (int64_t t = 0; t < bulk; ++t) {
+                int64_t c = cpos[order[t]];
+                double v = val[h][t];
+                if (!keep[t] || c < 0 || !(v == 0.0 || v == 1.0)) continue;
+                int64_t p = 2 * c + (int64_t)v;
+                for (int64_t e = coff[p]; e < coff[p + 1]; ++e) {
+                    if (clb[e] > box_l[cvar[e]]) box_l[cvar[e]] = clb[e];
+                    if (cub[e] < box_u[cvar[e]]) box_u[cvar[e]] = cub[e];
+                }
+            }
+            for (int64_t t = 0; t < bulk; ++t) {
+                int32_t j = order[t];
+                if (keep[t] && !(box_l[j] <= val[h][t] && val[h][t] <= box_u[j])) keep[t] = 0;
+            }
+            /* warm start: kept fixings and their cached implications; the
+             * changed list is every variable whose box moved */
+            memcpy(vl[h], lb, (size_t)n * sizeof(double));
+            memcpy(vu[h], ub, (size_t)n * sizeof(double));
+            int64_t nc = 0, kept = 0;
+            for (int64_t t = 0; t < bulk; ++t) {
+                if (!keep[t]) continue;
+                int32_t j = order[t];
+                double v = val[h][t];
+                kept += 1;
+                int64_t c = cpos[j];
+                if (c >= 0 && (v == 0.0 || v == 1.0)) {
+                    int64_t p = 2 * c + (int64_t)v;
+                    for (int64_t e = coff[p]; e < coff[p + 1]; ++e) {
+                        int32_t i = cvar[e];
+                        if (clb[e] > vl[h][i]) vl[h][i] = clb[e];
+                        if (cub[e] < vu[h][i]) vu[h][i] = cub[e];
+                    }
+                }
+            }
+            for (int64_t t = 0; t < bulk; ++t) {
+                if (!keep[t]) continue;
+                vl[h][order[t]] = val[h][t];
+                vu[h][order[t]] = val[h][t];
+            }
+            for (int64_t i = 0; i < n; ++i)
+                if (vl[h][i] != lb[i] || vu[h][i] != ub[i]) chg[nc++] = (int32_t)i;
+            memset(&pr[h], 0, sizeof(pr[h]));
+            if (kept == 0) {
+                pr[h].status = ORC_INFEASIBLE;
+                continue;
+            }
+            int prc = orc_propagate(I, vl[h], vu[h], chg, nc, o, ORC_MODE_WORKLIST, &pr[h]);
+            if (prc < 0) { rc = prc; goto done; }
+            res->nnz_propagated += pr[h].nnz_propagated;
+            ok[h] = pr[h].status != ORC_INFEASIBLE;
+        }
+        if (bulk > 1) res->bulks += 1;
+        else res->singles += 1;
+        if (ok[0] || ok[1]) {
+            int h = ok[0] ? 0 : 1;
+            memcpy(lb, vl[h], (size_t)n * sizeof(double));
+            memcpy(ub, vu[h], (size_t)n * sizeof(double));
+            recovery = 0;
+        } else {
+            if (!recovery && !infeasible) {
+                recovery = 1;
+                res->recoveries += 1;
+            } else {
+                infeasible = 1;
+            }
+            if (infeasible) {
+                for (int64_t t = 0; t < bulk; ++t) {
+                    int32_t j = order[t];
+                    lb[j] = val[0][t];
+                    ub[j] = val[0][t];
+                }
+                recovery = 0;
+            }
+        }
+    }
+    res->status = infeasible ? ORC_INFEASIBLE : ORC_OK;
+done:
+    if (rc == 0) {
+        int64_t fixed = 0;
+        for (int64_t j = 0; j < n; ++j) fixed += I->vtype[j] && lb[j] == ub[j];
+        res->fixed = (int32_t)fixed;
+    }
+    free(cpos); free(keys); free(order); free(S); free(chg); free(keep);
+    free(vl[0]); free(vl[1]); free(vu[0]); free(vu[1]); free(val[0]); free(val[1]);
+    free(box_l); free(box_u);
     return rc;
 }

@@ -46,6 +46,12 @@ class _Res(C.Structure):
                 ("infeasible_var", C.c_int32)]
 
 
+class _RoundRes(C.Structure):
+    _fields_ = [("status", C.c_int32), ("bulks", C.c_int32), ("singles", C.c_int32),
+                ("recoveries", C.c_int32), ("fixed", C.c_int32), ("iterations", C.c_int32),
+                ("nnz_propagated", C.c_int64)]
+
+
 _lib = None
 
 
@@ -88,6 +94,9 @@ def bind(path: str):
     lib.orc_probe_order.restype = C.c_int
     lib.orc_probe_order.argtypes = [C.POINTER(_Inst), C.c_void_p, C.c_void_p, C.POINTER(_Opt),
                                     C.c_void_p, C.c_int32, C.c_void_p]
+    lib.orc_round.restype = C.c_int
+    lib.orc_round.argtypes = [C.POINTER(_Inst), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                              C.c_int32] + [C.c_void_p] * 6 + [C.POINTER(_Opt), C.POINTER(_RoundRes)]
     return lib
 
 
@@ -250,3 +259,37 @@ def probe_order(inst, vars_, lb=None, ub=None, opts: Options = None, lib=None):
     if rc < 0:
         raise ValueError("oracle probe order failed with code %d" % rc)
     return order[:vs.size]
+
+
+def round_(inst, x, draws, lb=None, ub=None, cache=None, opts: Options = None, lib=None):
+    """Bound-propagation rounding (Algorithm 1 without repair and LP polish)
+    of the integer variables of the box (lb, ub) towards the point x, with
+    the uniform draws draws[2j + h] for the two candidate bulks, and an
+    optional probing cache of binaries (dict with vars and the probe()
+    output).  Returns (result dict, lb, ub)."""
+    lib = lib or load()
+    h = _Held(inst)
+    lb = np.array(inst["lb"] if lb is None else lb, dtype=np.float64, copy=True)
+    ub = np.array(inst["ub"] if ub is None else ub, dtype=np.float64, copy=True)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    draws = np.ascontiguousarray(draws, dtype=np.float64)
+    if cache is None:
+        k = 0
+        arrs = [np.zeros(1, np.int32), np.zeros(2, np.int8), np.zeros(3, np.int64),
+                np.zeros(1, np.int32), np.zeros(1), np.zeros(1)]
+    else:
+        vs = np.ascontiguousarray(cache["vars"], dtype=np.int32)
+        k = vs.size
+        arrs = [vs, np.ascontiguousarray(cache["status"], dtype=np.int8),
+                np.ascontiguousarray(cache["off"], dtype=np.int64),
+                np.ascontiguousarray(cache["var"], dtype=np.int32) if len(cache["var"]) else np.zeros(1, np.int32),
+                np.ascontiguousarray(cache["lb"], dtype=np.float64) if len(cache["lb"]) else np.zeros(1),
+                np.ascontiguousarray(cache["ub"], dtype=np.float64) if len(cache["ub"]) else np.zeros(1)]
+    r = _RoundRes()
+    rc = lib.orc_round(C.byref(h.s), _ptr(lb), _ptr(ub), _ptr(x), _ptr(draws), k,
+                       *[_ptr(a) for a in arrs], C.byref(_opt(opts)), C.byref(r))
+    if rc < 0:
+        raise ValueError("oracle round failed with code %d" % rc)
+    out = dict(status=r.status, bulks=r.bulks, singles=r.singles, recoveries=r.recoveries,
+               fixed=r.fixed, iterations=r.iterations, nnz_propagated=r.nnz_propagated)
+    return out, lb, ub

@@ -304,3 +304,35 @@ def brute_scores(inst, lb, ub, feastol=1e-6):
                     nviol[j] += 1
                     maxviol[j] = max(maxviol[j], worst)
     return nviol, maxviol, units, terms
+
+
+def round_scenarios():
+    """The hand-traced rounding scenarios of tests/golden/w6_round.json:
+    (name, instance, spec) with spec holding x, draws, the expected counts
+    and final values, and an optional hand-written cache."""
+    with open(os.path.join(GOLDEN, "w6_round.json")) as fh:
+        d = json.load(fh)
+    out = []
+    for key in ("A", "B", "C", "D"):
+        s = d[key]
+        inst = gen.from_rows(s["n"], [(c, v) for c, v in s["rows"]], [_f(x) for x in s["lo"]],
+                             [_f(x) for x in s["hi"]], s["vtype"], [_f(x) for x in s["lb"]],
+                             [_f(x) for x in s["ub"]])
+        if "cache" in s:
+            s = dict(s)
+            s["cache"] = {k: np.asarray(v) for k, v in s["cache"].items()}
+        out.append((key, inst, s))
+    return out
+
+
+def row_violations(inst, x, tol=0.0):
+    """Rows of inst violated at the point x (exact for integer data)."""
+    rp, col, val = inst["row_ptr"], inst["col"], inst["val"]
+    bad = []
+    for k in range(inst["m"]):
+        s = sum(Fraction(float(val[p])) * Fraction(float(x[col[p]])) for p in range(rp[k], rp[k + 1]))
+        lo, hi = inst["lo"][k], inst["hi"][k]
+        if (not math.isinf(lo) and s < Fraction(float(lo)) - Fraction(tol)) or \
+                (not math.isinf(hi) and s > Fraction(float(hi)) + Fraction(tol)):
+            bad.append(k)
+    return bad

@@ -15,7 +15,8 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import brute_scores, exact_gs_fixed_point, feasible_points, implied_dict, load_golden
+from helpers import (brute_scores, exact_gs_fixed_point, feasible_points, implied_dict, load_golden,
+                     round_scenarios)
 from paper_2510_20499_amd import gen
 
 SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle",
@@ -47,6 +48,15 @@ MUTANTS = {
                                 "const double slack_hi = hi_ok ? I->hi[k] - A->maxfin : 0.0;"),
     "unit_slack_inverted": ("double u = slack_lo / fabs(a);", "double u = fabs(a) / slack_lo;"),
     "square_dropped": ("double t = s * s;", "double t = fabs(s);"),
+    "bulk_last_singles": ("int64_t bulk = (recovery || R <= 36) ? 1", "int64_t bulk = (recovery || R <= 35) ? 1"),
+    "bulk_size_floor": ("(int64_t)ceil(sqrt((double)R))", "(int64_t)floor(sqrt((double)R))"),
+    "random_rounding_band": ("if (f > 0.25 && f < 0.75) v = u < f", "if (f > 0.35 && f < 0.75) v = u < f"),
+    "random_rounding_direction": ("v = u < f ? fl + 1.0 : fl;", "v = u < f ? fl : fl + 1.0;"),
+    "implied_slack_ascending": ("if (a->key != b->key) return a->key > b->key ? -1 : 1;",
+                                "if (a->key != b->key) return a->key < b->key ? -1 : 1;"),
+    "no_recovery_mode": ("if (!recovery && !infeasible) {", "if (0) {"),
+    "cache_conflicts_kept": ("if (keep[t] && !(box_l[j] <= val[h][t] && val[h][t] <= box_u[j])) keep[t] = 0;",
+                             "(void)j;"),
     "order_violation_direction": ("if (a->maxviol != b->maxviol) return a->maxviol > b->maxviol ? -1 : 1;",
                                   "if (a->maxviol != b->maxviol) return a->maxviol < b->maxviol ? -1 : 1;"),
 }
@@ -135,6 +145,24 @@ def _pins_hold(lib) -> bool:
                     return False
                 if exact is not None and abs(Fraction(S["slack_score"][j]) - exact) > exact / 2 ** 49:
                     return False
+        # rounding driver: the hand-traced scenarios, the planted point
+        for _, inst, s in round_scenarios():
+            r, lb, ub = oracle.round_(inst, s["x"], s["draws"], lib=lib)
+            if r != s["expect"] or list(lb) != [float(v) for v in s["final"]]:
+                return False
+            if "cache" in s:
+                r, lb, ub = oracle.round_(inst, s["x"], s["draws"], cache=s["cache"], lib=lib)
+                if r != s["expect_cache"]:
+                    return False
+        for seed in range(3):
+            inst = gen.make("tiny", seed)
+            r0, lb, ub = oracle.propagate(inst, lib=lib)
+            xs = inst["xstar"]
+            ints = inst["vtype"] == 1
+            d = np.random.default_rng(seed).random(2 * inst["n"])
+            r, l2, u2 = oracle.round_(inst, xs, d, lb, ub, lib=lib)
+            if r["status"] != oracle.BP_OK or not np.array_equal(l2[ints], xs[ints]):
+                return False
     except (ValueError, ZeroDivisionError, OverflowError):
         return False
     return True

@@ -20,7 +20,8 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import brute_scores, exact_gs_fixed_point, feasible_points, implied_dict, load_golden
+from helpers import (brute_scores, exact_gs_fixed_point, feasible_points, implied_dict, load_golden,
+                     round_scenarios, row_violations)
 from paper_2510_20499_amd import gen
 
 INF = float("inf")
@@ -451,3 +452,63 @@ def test_probe_order_is_a_permutation_and_handles_repeats():
     assert list(oracle.probe_order(inst, [])) == []
     with pytest.raises(ValueError):
         oracle.probe_order(inst, [inst["n"]])
+
+
+# ------------------------------------------------------ rounding driver
+@pytest.mark.parametrize("key", ["A", "B", "C", "D"])
+def test_golden_w6_round(key):
+    sc = {k: (inst, s) for k, inst, s in round_scenarios()}
+    inst, s = sc[key]
+    r, lb, ub = oracle.round_(inst, s["x"], s["draws"])
+    assert r == s["expect"]
+    assert list(lb) == [float(v) for v in s["final"]] and list(ub) == list(lb)
+    if "cache" in s:
+        r, lb, ub = oracle.round_(inst, s["x"], s["draws"], cache=s["cache"])
+        assert r == s["expect_cache"]
+        assert list(lb) == [float(v) for v in s["final"]]
+
+
+@pytest.mark.parametrize("name,seed", [("tiny", 0), ("tiny", 1), ("tiny", 2), ("tiny_inf", 3)])
+def test_round_keeps_the_planted_point(name, seed):
+    """Rounding towards a feasible integral point: every candidate value is
+    that point's, every propagation stays feasible (the point survives it),
+    so every integer variable ends at the planted value."""
+    inst = gen.make(name, seed)
+    r0, lb, ub = oracle.propagate(inst)
+    xs = inst["xstar"]
+    rng = np.random.default_rng(seed)
+    d = rng.random(2 * inst["n"])
+    ints = inst["vtype"] == 1
+    r, l2, u2 = oracle.round_(inst, xs, d, lb, ub)
+    assert r["status"] == oracle.BP_OK and r["recoveries"] == 0
+    assert np.array_equal(l2[ints], xs[ints]) and np.array_equal(u2[ints], xs[ints])
+    # continuous variables keep the planted value inside their box
+    assert ((l2 <= xs + 1e-6) & (xs <= u2 + 1e-6)).all()
+    # the same with a probing cache of some binaries at the root
+    cand = np.nonzero(ints & (lb == 0) & (ub == 1))[0][:40].astype(np.int32)
+    P = oracle.probe(inst, lb, ub, cand)
+    P["vars"] = cand
+    r2, l3, u3 = oracle.round_(inst, xs, d, lb, ub, cache=P)
+    assert r2["status"] == oracle.BP_OK
+    assert np.array_equal(l3[ints], xs[ints])
+
+
+@pytest.mark.parametrize("seed", range(150))
+def test_round_micro_brute_force(seed):
+    """Pure-integer micro instances: the result fixes every variable inside
+    the start box; an OK result is a feasible point; an instance without a
+    feasible point ends infeasible."""
+    inst = gen.make_micro(seed)
+    r0, lb, ub = oracle.propagate(inst)
+    if r0["status"] == oracle.BP_INFEASIBLE:
+        return
+    rng = np.random.default_rng(seed)
+    x = lb + rng.random(inst["n"]) * (ub - lb)
+    d = rng.random(2 * inst["n"])
+    r, l2, u2 = oracle.round_(inst, x, d, lb, ub)
+    assert np.array_equal(l2, u2)
+    assert ((lb <= l2) & (l2 <= ub)).all()
+    if r["status"] == oracle.BP_OK:
+        assert row_violations(inst, l2) == []
+    if not feasible_points(inst):
+        assert r["status"] == oracle.BP_INFEASIBLE
