@@ -136,6 +136,13 @@ def main():
                     help="run only the double-probing measurement (for profilers)")
     ap.add_argument("--probe-cpu", type=int, default=16,
                     help="binaries the oracle probes for a CPU probing rate (0: skip)")
+    ap.add_argument("--skip-round", action="store_true",
+                    help="skip the bound-propagation rounding measurement")
+    ap.add_argument("--only-round", action="store_true")
+    ap.add_argument("--round-reps", type=int, default=2)
+    ap.add_argument("--round-cpu-scale", type=float, default=0.2,
+                    help="scale of the single-instance workload the oracle rounds for the "
+                         "CPU baseline (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path.",
@@ -149,6 +156,9 @@ def main():
 
     if args.only_probe:
         print(json.dumps({"probe_batched": bench_probe(args, bp, gen, torch, np)}), flush=True)
+        return
+    if args.only_round:
+        print(json.dumps({"rounding": bench_round(args, bp, gen, torch, np)}), flush=True)
         return
     if args.copy_calibrate:
         nb = args.copy_calibrate << 20
@@ -220,6 +230,7 @@ def main():
                "sample": "%d cold propagation(s) of the full single-instance workload, "
                          "worklist mode, one thread" % reps_cpu}
 
+    rounding = None if args.skip_round else bench_round(args, bp, gen, torch, np, inst=inst, I=I)
     probe = None if args.skip_probe else bench_probe(args, bp, gen, torch, np)
     bulk = None if args.skip_bulk else bench_bulk(args, bp, gen, torch, np)
     serving = None if args.skip_serving else bench_serving(args, bp, gen, torch, np)
@@ -244,11 +255,97 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "rounding": rounding,
         "probe_batched": probe,
         "bulk_batched": bulk,
         "serving": serving,
     }
     print(json.dumps(out), flush=True)
+
+
+def _round_inputs(inst, lb, ub, seed, np):
+    """Seeded fractional point (the planted point plus N(0, 0.4) noise,
+    clipped into the root box; no LP relaxation is solved here) and draws."""
+    rng = np.random.default_rng(seed + 77)
+    x = np.clip(inst["xstar"] + rng.normal(0.0, 0.4, inst["n"]), lb, ub)
+    return x, rng.random(2 * inst["n"])
+
+
+def bench_round(args, bp, gen, torch, np, inst=None, I=None):
+    """Bound-propagation rounding (bp_round: Algorithm 1 without repair and
+    LP polish) of every integer variable of the single-instance workload from
+    its root fixed point, with a probing cache of 1024 binaries chosen by
+    bp_probe_order.  CPU baseline: the oracle's rounding of the same kind of
+    input on the workload scaled by --round-cpu-scale, timed beside the GPU
+    on that same scaled input."""
+    dev = torch.device("cuda:0")
+    if inst is None:
+        inst = gen.make("single", args.seed)
+        I = bp.Instance(inst)
+
+    def setup(inst, I, kc):
+        lb = torch.tensor(inst["lb"], dtype=torch.float64, device=dev)
+        ub = torch.tensor(inst["ub"], dtype=torch.float64, device=dev)
+        assert I.propagate(lb, ub)["status"] == bp.BP_OK
+        x, d = _round_inputs(inst, lb.cpu().numpy(), ub.cpu().numpy(), args.seed, np)
+        xd = torch.tensor(x, dtype=torch.float64, device=dev)
+        dd = torch.tensor(d, dtype=torch.float64, device=dev)
+        cache = None
+        if kc:
+            lbh, ubh = lb.cpu().numpy(), ub.cpu().numpy()
+            bins = np.nonzero((inst["vtype"] == 1) & (lbh == 0) & (ubh == 1))[0].astype(np.int32)
+            order = I.probe_order(torch.tensor(bins, device=dev), lb, ub)
+            pv = order[:min(kc, bins.size)].contiguous()
+            G = I.probe(pv)
+            cache = dict(vars=pv, status=G["status"], off=G["off"], var=G["var"], lb=G["lb"],
+                         ub=G["ub"])
+        return lb, ub, xd, dd, cache
+
+    lb0, ub0, xd, dd, cache = setup(inst, I, 1024)
+    lb, ub = lb0.clone(), ub0.clone()
+    R = I.round(lb, ub, xd, dd, cache)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.round_reps):
+        lb.copy_(lb0)
+        ub.copy_(ub0)
+        R = I.round(lb, ub, xd, dd, cache)
+    torch.cuda.synchronize()
+    tr = (time.perf_counter() - t0) / args.round_reps
+    res = {"workload": "rounding of the %d integer variables of the single-instance workload "
+                       "(m=%d, n=%d) from its root fixed point; cache of %d binaries"
+                       % (int((inst["vtype"] == 1).sum()), inst["m"], inst["n"],
+                          0 if cache is None else cache["vars"].numel()),
+           "round_ms": tr * 1e3, "result": R,
+           "nnz_propagated_per_s": R["nnz_propagated"] / tr,
+           "steps_per_s": R["iterations"] / tr}
+    log("rounding: %.1f ms per call, %d steps (%d bulk), status %d"
+        % (tr * 1e3, R["iterations"], R["bulks"], R["status"]))
+    if args.round_cpu_scale > 0:
+        import oracle
+        small = gen.make("single", args.seed, scale=args.round_cpu_scale)
+        Is = bp.Instance(small)
+        slb, sub, sx, sd, _ = setup(small, Is, 0)
+        l2, u2 = slb.clone(), sub.clone()
+        Is.round(l2, u2, sx, sd)
+        torch.cuda.synchronize()
+        l2.copy_(slb)
+        u2.copy_(sub)
+        tg = time.perf_counter()
+        Rg = Is.round(l2, u2, sx, sd)
+        torch.cuda.synchronize()
+        tg = time.perf_counter() - tg
+        _, olb, oub = oracle.propagate(small)
+        tc = time.perf_counter()
+        Ro, _, _ = oracle.round_(small, sx.cpu().numpy(), sd.cpu().numpy(), olb, oub)
+        tc = time.perf_counter() - tc
+        assert Ro == Rg, (Ro, Rg)
+        res["cpu_baseline"] = {"value": tc * 1e3, "unit": "ms per rounding call", "cores": 1,
+                               "kind": "oracle", "gpu_ms_same_input": tg * 1e3,
+                               "sample": "one rounding of the single-instance workload scaled by "
+                                         "%g (n=%d), no cache, one thread; the GPU result on that "
+                                         "input is identical" % (args.round_cpu_scale, small["n"])}
+    return res
 
 
 def bench_probe(args, bp, gen, torch, np):

@@ -258,6 +258,60 @@ int bp_scores(bp_instance *h, const double *lb, const double *ub, bp_scores_out 
 int bp_probe_order(bp_instance *h, const double *lb, const double *ub, const int32_t *vars,
                    int32_t k, int32_t *order, void *stream);
 
+/* Probing cache of binaries for bp_round: bp_probe's output for the DEVICE
+ * variable ids vars [k], each a binary of the box the cache was computed
+ * around (probe 2t + v fixed vars[t] to v); status [2k], off [2k + 1] and
+ * the implied lists var / lb / ub [off[2k]] as bp_probe_out holds them.
+ * The box given to bp_round must lie inside the cache's box. */
+typedef struct {
+    const int32_t *vars;
+    int32_t k;
+    const int8_t *status;
+    const int64_t *off;
+    const int32_t *var;
+    const double *lb, *ub;
+} bp_cache;
+
+typedef struct {
+    int32_t status;       /* BP_OK, or BP_INFEASIBLE for a path marked infeasible */
+    int32_t bulks;        /* propagation steps with more than one variable */
+    int32_t singles;      /* steps with one variable (recovery mode, last 36) */
+    int32_t recoveries;   /* times recovery mode was entered */
+    int32_t fixed;        /* integer variables fixed at the end */
+    int32_t iterations;   /* steps in all */
+    int64_t nnz_propagated; /* over every propagation of both bulks */
+} bp_round_result;
+
+/* Bound-propagation rounding (the paper's Algorithm 1 with Section 2.3,
+ * without the repair procedure and the LP polish): every integer variable of
+ * the box DEVICE lb/ub [n] with lb < ub is fixed towards the fractional
+ * point DEVICE x [n], a bulk at a time, each bulk propagated.
+ *   - order: interval width 1, then 2, then wider; then the distance of x
+ *     (clamped into the box) to the nearest integer; then index;
+ *   - bulk size: with R variables unfixed, 1 in recovery mode or when
+ *     R <= 36, else ceil(sqrt(R)); a bulk of more than one first re-sorts the
+ *     unfixed variables by the implied-slack score S (bp_scores at the
+ *     current box) descending, stably;
+ *   - two candidate values per member, h = 0 and 1, from the caller's draws
+ *     DEVICE draws [2n] in [0, 1) (draws[2j + h]): with x clamped into the
+ *     box and f = x - floor(x), random rounding (up when the draw is below
+ *     f) for 0.25 < f < 0.75, else the nearest integer;
+ *   - with a cache: a member whose cached probe for its value is infeasible
+ *     is dropped, then one whose value lies outside the box implied by the
+ *     other members' cached lists; the kept members' fixings and cached
+ *     implications start the bulk (warm start);
+ *   - both bulks propagate as one bp_propagate_batch; the first not
+ *     infeasible one is accepted (a bulk keeping no member fails); when both
+ *     fail, recovery mode (one variable per bulk) is entered, or, if already
+ *     in it, the path is marked infeasible and from then on a failed bulk's
+ *     members are fixed to their first values without propagation.
+ * lb/ub hold the final box on return (every such integer variable fixed).
+ * The result is the same bit for bit as the plain sequential procedure.
+ * Returns BP_OK (res set), or BP_EINVAL for a null argument, NaN in x or the
+ * box, a draw outside [0, 1) or a cached id out of range (lb/ub untouched). */
+int bp_round(bp_instance *h, double *lb, double *ub, const double *x, const double *draws,
+             const bp_cache *cache, bp_round_result *res, void *stream);
+
 /* Schedule chosen by bp_autotune. */
 typedef struct {
     int32_t heavy_threshold;   /* rows longer than this split across workgroups */

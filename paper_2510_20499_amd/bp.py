@@ -24,7 +24,7 @@ EXPORTS = ["bp_options_default", "bp_load", "bp_propagate", "bp_propagate_batch"
            "bp_get_base", "bp_kernel_stats", "bp_device_bytes", "bp_free", "bp_last_error",
            "bp_server_create", "bp_server_submit", "bp_server_run", "bp_server_poll",
            "bp_server_results", "bp_server_info", "bp_server_destroy", "bp_autotune",
-           "bp_scores", "bp_probe_order"]
+           "bp_scores", "bp_probe_order", "bp_round"]
 REQ_PROBE, REQ_PROPAGATE = 0, 1
 
 
@@ -85,6 +85,20 @@ class ScoresOut(C.Structure):
                 ("slack_score", C.c_void_p)]
 
 
+class Cache(C.Structure):
+    _fields_ = [("vars", C.c_void_p), ("k", C.c_int32), ("status", C.c_void_p), ("off", C.c_void_p),
+                ("var", C.c_void_p), ("lb", C.c_void_p), ("ub", C.c_void_p)]
+
+
+class RoundResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("bulks", C.c_int32), ("singles", C.c_int32),
+                ("recoveries", C.c_int32), ("fixed", C.c_int32), ("iterations", C.c_int32),
+                ("nnz_propagated", C.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class BPError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("libbp error %d: %s" % (code, msg))
@@ -114,6 +128,9 @@ def load_library(path: str = LIB_PATH):
     lib.bp_probe_order.restype = C.c_int
     lib.bp_probe_order.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                    C.c_void_p, C.c_void_p]
+    lib.bp_round.restype = C.c_int
+    lib.bp_round.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                             C.POINTER(Cache), C.POINTER(RoundResult), C.c_void_p]
     lib.bp_get_base.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.bp_get_base.restype = C.c_int
     lib.bp_kernel_stats.argtypes = [C.c_void_p, C.POINTER(Stats), C.c_int]
@@ -318,6 +335,30 @@ class Instance:
         _check(_LIB.bp_probe_order(self._h, _dptr(lb), _dptr(ub), _dptr(vars_) if k else None, k,
                                    _dptr(order), _stream_ptr(stream)))
         return order[:k]
+
+    def round(self, lb: torch.Tensor, ub: torch.Tensor, x: torch.Tensor, draws: torch.Tensor,
+              cache: dict = None, stream=None) -> dict:
+        """bp_round: bound-propagation rounding of the integer variables of
+        the box lb/ub (updated in place) towards x with the draws [2n]; cache
+        is an optional dict of device tensors vars, status, off, var, lb, ub
+        (bp_probe's output for vars)."""
+        self._bounds_ok(lb, ub)
+        for t in (x, draws):
+            assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
+        assert x.numel() == self.n and draws.numel() == 2 * self.n
+        cp = None
+        if cache is not None:
+            k = cache["vars"].numel()
+            cs = Cache(cache["vars"].data_ptr() if k else None, k, cache["status"].data_ptr(),
+                       cache["off"].data_ptr(),
+                       cache["var"].data_ptr() if cache["var"].numel() else None,
+                       cache["lb"].data_ptr() if cache["lb"].numel() else None,
+                       cache["ub"].data_ptr() if cache["ub"].numel() else None)
+            cp = C.byref(cs)
+        r = RoundResult()
+        _check(_LIB.bp_round(self._h, _dptr(lb), _dptr(ub), _dptr(x), _dptr(draws), cp, C.byref(r),
+                             _stream_ptr(stream)))
+        return r.as_dict()
 
     def autotune(self, lb: torch.Tensor, ub: torch.Tensor, vars_: torch.Tensor = None,
                  cache_path: str = None, stream=None) -> dict:

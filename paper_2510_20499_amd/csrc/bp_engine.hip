@@ -150,6 +150,9 @@ struct bp_instance {
     DevBuf sc_bnd, sc_act, sc_cval, sc_chunks, sc_rows, sc_first, sc_part, sc_tmp, sc_keys;
     bool sc_ready = false;
     int64_t sc_nchunks = 0, sc_nlong = 0;
+    // bound-propagation rounding work buffers
+    DevBuf rd_order, rd_order2, rd_flags, rd_small, rd_S, rd_keys, rd_val, rd_keep, rd_mpos;
+    DevBuf rd_mbox, rd_vk, rd_vl, rd_vu, rd_chg, rd_cpos, rd_bcnt;
     // stats
     bp_stats stats;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -858,7 +861,8 @@ static int check_ids(bp_instance *h, const int32_t *ids, int64_t count, hipStrea
 // Shared driver of bp_propagate (B = 1, base update) and bp_propagate_batch.
 static int propagate_slots(bp_instance *h, int32_t Bv, double *lb, double *ub,
                            const int32_t *changed_idx, const int64_t *changed_ptr,
-                           int64_t n_changed_total, bool cold, bp_result *res, hipStream_t st) {
+                           int64_t n_changed_total, bool cold, bp_result *res, hipStream_t st,
+                           bool ids_known_valid = false) {
     const int64_t n = h->n;
     if (int rc = engine_ensure(h, Bv, false, st)) return rc;
     Params P = make_params(h, Bv);
@@ -887,7 +891,7 @@ static int propagate_slots(bp_instance *h, int32_t Bv, double *lb, double *ub,
     for (int32_t j = 0; j < Bv; ++j)
         if (box[2 * j + 1]) return fail(BP_EINVAL, "NaN bound in vector " + std::to_string(j));
     // Validate changed ids.
-    if (!cold && n_changed_total > 0)
+    if (!cold && n_changed_total > 0 && !ids_known_valid)
         if (int rc = check_ids(h, changed_idx, n_changed_total, st)) return rc;
     if (int rc = start_slots(h, P, Bv, st, changed_idx, changed_ptr, n_changed_total, cold)) return rc;
     // A slot whose box is already crossed is infeasible before any round;
@@ -1259,5 +1263,7 @@ extern "C" int bp_probe(bp_instance *h, const int32_t *vars, int32_t k, bp_probe
 
 #include "bp_scores.h"
 #include "bp_scores_run.h"
+#include "bp_round.h"
+#include "bp_round_run.h"
 #include "bp_server.h"
 #include "bp_tune.h"

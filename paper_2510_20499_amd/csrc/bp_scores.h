@@ -397,17 +397,19 @@ __global__ void k_sc_bitonic(ScKey *keys, int64_t kpad, int64_t size, int64_t st
 // `stride0`, every later one at size / 2.  Directions come from the global
 // index, so tiles of one block of the network agree.
 constexpr int SC_TILE = 1024;
+constexpr int SC_TILE_THREADS = SC_TILE / 2;  // one compare-exchange per thread and step
 
-__global__ void __launch_bounds__(WG) k_sc_bitonic_tile(ScKey *keys, int64_t kpad, int64_t size_lo,
-                                                        int64_t size_hi, int64_t stride0) {
+__global__ void __launch_bounds__(SC_TILE_THREADS) k_sc_bitonic_tile(ScKey *keys, int64_t kpad,
+                                                                     int64_t size_lo, int64_t size_hi,
+                                                                     int64_t stride0) {
     __shared__ ScKey T[SC_TILE];
     const int64_t tile = kpad < SC_TILE ? kpad : SC_TILE;
     for (int64_t base = (int64_t)blockIdx.x * tile; base < kpad; base += (int64_t)gridDim.x * tile) {
-        for (int64_t t = threadIdx.x; t < tile; t += WG) T[t] = keys[base + t];
+        for (int64_t t = threadIdx.x; t < tile; t += SC_TILE_THREADS) T[t] = keys[base + t];
         for (int64_t size = size_lo; size <= size_hi; size <<= 1) {
             for (int64_t stride = size == size_lo ? stride0 : size >> 1; stride > 0; stride >>= 1) {
                 __syncthreads();
-                for (int64_t q = threadIdx.x; q < tile / 2; q += WG) {
+                for (int64_t q = threadIdx.x; q < tile / 2; q += SC_TILE_THREADS) {
                     const int64_t i = 2 * stride * (q / stride) + (q % stride);
                     const int64_t l = i + stride;
                     const bool up = ((base + i) & size) == 0;
@@ -420,7 +422,7 @@ __global__ void __launch_bounds__(WG) k_sc_bitonic_tile(ScKey *keys, int64_t kpa
             }
         }
         __syncthreads();
-        for (int64_t t = threadIdx.x; t < tile; t += WG) keys[base + t] = T[t];
+        for (int64_t t = threadIdx.x; t < tile; t += SC_TILE_THREADS) keys[base + t] = T[t];
         __syncthreads();
     }
 }

@@ -87,6 +87,20 @@ static int sc_rows_pass(bp_instance *h, const double *lb, const double *ub, hipS
     return 0;
 }
 
+// Bitonic sort of kpad (a power of two) keys: sizes up to one tile entirely
+// in LDS; each larger size runs the steps whose partners are a tile or more
+// apart in global memory, then the rest in LDS.
+static void sc_sort(ScKey *keys, int64_t kpad, hipStream_t st) {
+    const int64_t tile = std::min<int64_t>(kpad, SC_TILE);
+    const int tiles = (int)std::min<int64_t>(kpad / tile, 4096);
+    if (kpad > 1) k_sc_bitonic_tile<<<tiles, SC_TILE_THREADS, 0, st>>>(keys, kpad, 2, tile, 1);
+    for (int64_t size = 2 * tile; size <= kpad; size <<= 1) {
+        for (int64_t stride = size >> 1; stride >= tile; stride >>= 1)
+            k_sc_bitonic<<<grid_for(kpad), 256, 0, st>>>(keys, kpad, size, stride);
+        k_sc_bitonic_tile<<<tiles, SC_TILE_THREADS, 0, st>>>(keys, kpad, size, size, tile >> 1);
+    }
+}
+
 extern "C" int bp_scores(bp_instance *h, const double *lb, const double *ub, bp_scores_out *out,
                          void *stream) {
     if (!h || !out) return fail(BP_EINVAL, "null argument");
@@ -127,16 +141,7 @@ extern "C" int bp_probe_order(bp_instance *h, const double *lb, const double *ub
     if (int rc = h->sc_keys.grow((size_t)kpad * sizeof(ScKey), h->bytes)) return rc;
     ScKey *keys = h->sc_keys.as<ScKey>();
     k_sc_keys<<<grid_for(kpad), 256, 0, st>>>(vars, k, kpad, nv, mv, mu, keys);
-    // sizes up to one tile entirely in LDS; each larger size: the steps whose
-    // partners are a tile or more apart in global memory, the rest in LDS
-    const int64_t tile = std::min<int64_t>(kpad, SC_TILE);
-    const int tiles = (int)std::min<int64_t>(kpad / tile, 4096);
-    if (kpad > 1) k_sc_bitonic_tile<<<tiles, WG, 0, st>>>(keys, kpad, 2, tile, 1);
-    for (int64_t size = 2 * tile; size <= kpad; size <<= 1) {
-        for (int64_t stride = size >> 1; stride >= tile; stride >>= 1)
-            k_sc_bitonic<<<grid_for(kpad), 256, 0, st>>>(keys, kpad, size, stride);
-        k_sc_bitonic_tile<<<tiles, WG, 0, st>>>(keys, kpad, size, size, tile >> 1);
-    }
+    sc_sort(keys, kpad, st);
     k_sc_order_out<<<grid_for(k), 256, 0, st>>>(keys, k, order);
     HIPTRY(hipGetLastError());
     HIPTRY(hipStreamSynchronize(st));
