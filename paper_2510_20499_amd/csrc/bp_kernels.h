@@ -430,7 +430,7 @@ __device__ __forceinline__ void add_terms(Acc &mn, Acc &mx, double a, double lb,
 // Exact activity of one side of a row over [p0, p1) by one lane.  Kept out
 // of line so its accumulator lives in scratch memory and does not raise the
 // register count of the kernels that may call it.
-__device__ __noinline__ double exact_side(const DInst &I, const BView &bnd, int64_t p0, int64_t p1,
+__device__ __noinline__ double exact_side(const DInst &I, const BView bnd, int64_t p0, int64_t p1,
                                           bool maxside) {
     SuperAcc S;
     sa_zero(S);
@@ -970,12 +970,20 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(BP_ROWS
         } else if (u < start[2]) {
             block_row<MULTI>(P, P.q[par][BIN_BLOCK], u - start[1], W);
         } else {
+            // bin of unit u by constant-index selects (start[] stays in
+            // registers; a dynamic index would place it in scratch memory)
             int j = 0;
-            while (u >= start[3 + j]) ++j;
+            uint32_t ubase = start[2], cnt = qc[NLIGHT - 1];
+#pragma unroll
+            for (int t = 0; t < NLIGHT - 1; ++t) {
+                const bool past = u >= start[3 + t];
+                j += past ? 1 : 0;
+                ubase = past ? start[3 + t] : ubase;
+                cnt = past ? qc[NLIGHT - 2 - t] : cnt;
+            }
             int b = NLIGHT - 1 - j;
-            uint32_t lu = u - start[2 + j];
+            uint32_t lu = u - ubase;
             const uint64_t *q = P.q[par][b];
-            uint32_t cnt = qc[b];
             switch (b) {
                 case 0: light_rows<MULTI, 1>(P, q, cnt, lu); break;
                 case 1: light_rows<MULTI, 2>(P, q, cnt, lu); break;
@@ -1164,11 +1172,17 @@ __device__ __forceinline__ void mark_dirty(const Params &P, int s, int i) {
 // Round end for every slot: outcome, counters, next round (one workgroup).
 __global__ void __launch_bounds__(WG) k_end(Params P) {
     Ctl *C = P.ctl;
-    // Control fields read together, before the early exit.
+    // Control fields and this thread's first slot record read together,
+    // before the early exit.
     const uint32_t c_done = C->done, c_round = C->round, c_max_rounds = C->max_rounds;
     const uint32_t c_next_job = C->next_job, c_total_jobs = C->total_jobs;
+    const int s_first = threadIdx.x;
+    SlotInfo first;
+    if (s_first < P.nslots) first = P.info[s_first];
+    else first.state = SLOT_FREE;
     ctl_loaded(c_done, c_round, c_max_rounds);
     ctl_loaded(c_next_job, c_total_jobs, c_done);
+    asm volatile("" ::"v"(first.state));
     if (c_done) return;
     const int par = c_round & 1;
     __shared__ uint32_t s_active, s_finished;
@@ -1179,30 +1193,31 @@ __global__ void __launch_bounds__(WG) k_end(Params P) {
     __syncthreads();
     for (int s = threadIdx.x; s < P.nslots; s += WG) {
         SlotInfo &S = P.info[s];
-        if (S.state == SLOT_DRAINING) {
+        const SlotInfo V = s == s_first ? first : S;  // values at the round end
+        if (V.state == SLOT_DRAINING) {
             S.state = SLOT_FREE;
             continue;
         }
-        if (S.state != SLOT_ACTIVE) continue;
+        if (V.state != SLOT_ACTIVE) continue;
         bool fin = true;
         bool drain = false;
-        if (S.row_bad_count > 0) {
+        if (V.row_bad_count > 0) {
             S.status = 1;
-            drain = S.pending_rows > 0;
-        } else if (S.var_bad_min != NONE) {
+            drain = V.pending_rows > 0;
+        } else if (V.var_bad_min != NONE) {
             S.status = 1;
-            drain = S.pending_rows > 0;
-        } else if (S.pending_rows == 0) {
+            drain = V.pending_rows > 0;
+        } else if (V.pending_rows == 0) {
             S.status = 0;
-        } else if ((uint32_t)S.rounds >= c_max_rounds) {
+        } else if ((uint32_t)V.rounds >= c_max_rounds) {
             S.status = 2;
             drain = true;
         } else {
             fin = false;
-            S.rounds += 1;
-            S.nnz += S.pending_nnz;
-            atomicAdd(&C->stat_rows, (unsigned long long)S.pending_rows);
-            atomicAdd(&C->stat_nnz, S.pending_nnz);
+            S.rounds = V.rounds + 1;
+            S.nnz = V.nnz + V.pending_nnz;
+            atomicAdd(&C->stat_rows, (unsigned long long)V.pending_rows);
+            atomicAdd(&C->stat_nnz, V.pending_nnz);
             S.pending_rows = 0;
             S.pending_nnz = 0;
             S.row_bad_min = NONE;

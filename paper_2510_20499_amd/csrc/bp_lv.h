@@ -116,13 +116,16 @@ __device__ __forceinline__ void wbuf_push(WaveBuf &w, int32_t x, uint32_t *count
 }
 
 // Exact activity of one side of row [p0, p1) for the vector of this lane.
-__device__ __noinline__ double lv_exact_side(const LvParams &P, int v, int64_t p0, int64_t p1,
-                                             bool maxside) {
+// The arrays come by value (not the parameter block by reference, which
+// would make every lane copy it to scratch memory on entry).
+__device__ __noinline__ double lv_exact_side(const double *val, const int32_t *col,
+                                             const double2 *bnd, int64_t V, int v, int64_t p0,
+                                             int64_t p1, bool maxside) {
     SuperAcc S;
     sa_zero(S);
     for (int64_t p = p0; p < p1; ++p) {
-        double a = P.I.val[p];
-        double2 b = P.bnd[(size_t)P.I.col[p] * P.V + v];
+        double a = val[p];
+        double2 b = bnd[(size_t)col[p] * V + v];
         double bb = (a > 0.0) != maxside ? b.x : b.y;
         if (!isinf(bb)) sa_add(S, a * bb);
     }
@@ -263,8 +266,8 @@ __device__ __forceinline__ void lv_finish_act(const LvParams &P, int v, bool liv
     R.maxfin = 0.0;
     bool ok_min = live && !P.force_exact && acc_certify(mn, R.minfin);
     bool ok_max = live && !P.force_exact && acc_certify(mx, R.maxfin);
-    if (live && !ok_min) R.minfin = lv_exact_side(P, v, p0, p1, false);
-    if (live && !ok_max) R.maxfin = lv_exact_side(P, v, p0, p1, true);
+    if (live && !ok_min) R.minfin = lv_exact_side(P.I.val, P.I.col, P.bnd, P.V, v, p0, p1, false);
+    if (live && !ok_max) R.maxfin = lv_exact_side(P.I.val, P.I.col, P.bnd, P.V, v, p0, p1, true);
 }
 
 // One short row for the 64 vectors of group g: activity, row test and

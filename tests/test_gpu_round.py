@@ -141,3 +141,19 @@ def test_edge_cases_and_errors():
     rg = I.propagate(tl, tu)
     ro, lo, uo = oracle.propagate(inst)
     assert (rg["status"], rg["rounds"], rg["nnz_propagated"]) == (ro["status"], ro["rounds"], ro["nnz_propagated"])
+
+
+def test_round_limit_counts_as_not_infeasible():
+    """With two rounds per propagation many bulks stop at the round limit;
+    such a bulk is accepted like a feasible one, on both sides."""
+    inst = gen.make("single", 6, scale=0.02)
+    r0, lb, ub = oracle.propagate(inst)
+    x, d = _point(inst, lb, ub, 6)
+    I = bp().Instance(inst, bp().default_options(max_rounds=2))
+    rg, lg, ug = _gpu_round(I, lb, ub, x, d)
+    oo = oracle.Options()
+    oo.max_rounds = 2
+    ro, lo, uo = oracle.round_(inst, x, d, lb, ub, opts=oo)
+    assert rg == ro
+    assert np.array_equal(lg.view(np.int64), lo.view(np.int64))
+    assert np.array_equal(ug.view(np.int64), uo.view(np.int64))
