@@ -97,6 +97,8 @@ struct Engine {
     int32_t cap_slots = 0;
     int32_t track_dirty = 0;
     int32_t nstripe = 1;  // changed-list stripes (NSTRIPE for one slot)
+    // scan rounds of one plain vector (engines of one slot)
+    DevBuf cbits, hhit, allhrec;
     Shape shape;
     int64_t bytes = 0;
     DevBuf bnd, cand, vflag, rflag, info, chg, dirty, dlist, dcount, ctl, touched, filt;
@@ -265,6 +267,19 @@ __global__ void k_seed_all(Params P, SeedAll S) {
         } else {
             P.q[0][b][idx] = ((uint64_t)(uint32_t)s << 32) | (uint32_t)row;
         }
+    }
+}
+
+// Chunk records of every heavy row in the cold-start layout (slot 0): the
+// fixed list a scan round walks.
+__global__ void k_fill_allhrec(DInst I, const int32_t *hrows, const int32_t *hbase, int64_t nheavy,
+                               int32_t chunk, int4 *out) {
+    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < nheavy;
+         w += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t row = hrows[w];
+        const int64_t len = I.row_ptr[row + 1] - I.row_ptr[row];
+        const int32_t nch = (int32_t)((len + chunk - 1) / chunk);
+        for (int32_t c = 0; c < nch; ++c) out[hbase[w] + c] = make_int4(0, row, c, nch);
     }
 }
 
@@ -537,6 +552,12 @@ static int engine_alloc(std::unique_ptr<Engine> &eng, const Shape &sh, int32_t s
     if ((rc = E->info.alloc((size_t)S * sizeof(SlotInfo), B))) return rc;
     E->nstripe = S == 1 ? NSTRIPE : 1;
     if ((rc = E->chg.alloc((size_t)E->nstripe * S * n * 8, B))) return rc;
+    if (S == 1) {
+        if ((rc = E->cbits.alloc((size_t)2 * nw_var * 4, B))) return rc;
+        if ((rc = E->hhit.alloc((size_t)m * 4, B))) return rc;
+        if ((rc = E->allhrec.alloc((size_t)std::max<int64_t>(sh.heavy_chunks, 1) * sizeof(int4), B)))
+            return rc;
+    }
     if ((rc = E->ctl.alloc(sizeof(Ctl), B))) return rc;
     for (int par = 0; par < 2; ++par) {
         for (int b = 0; b < BIN_HEAVY; ++b)
@@ -866,6 +887,26 @@ static int propagate_slots(bp_instance *h, int32_t Bv, double *lb, double *ub,
     const int64_t n = h->n;
     if (int rc = engine_ensure(h, Bv, false, st)) return rc;
     Params P = make_params(h, Bv);
+    if (Bv == 1 && h->eng->cbits.p) {
+        // one plain vector: large bound updates switch the next round to a
+        // scan of every row
+        Engine &E1 = *h->eng;
+        P.scan_ok = 1;
+        P.scan_min = (uint32_t)std::max<int64_t>(1, h->n / 8);
+        P.cbits = E1.cbits.as<uint32_t>();
+        P.hhit = E1.hhit.as<uint32_t>();
+        P.allrows = h->cold_rows.as<int32_t>();
+        for (int b = 0; b <= NBIN; ++b) P.allstart[b] = h->bin_start[b];
+        P.allhrec = E1.allhrec.as<int4>();
+        P.allhchunks = (int32_t)h->heavy_chunks;
+        HIPTRY(hipMemsetAsync(E1.cbits.p, 0, E1.cbits.bytes, st));
+        HIPTRY(hipMemsetAsync(E1.hhit.p, 0, E1.hhit.bytes, st));
+        const int64_t nh = h->bin_count[BIN_HEAVY];
+        if (nh > 0)
+            k_fill_allhrec<<<grid_for(nh), 256, 0, st>>>(dinst_of(h), h->cold_rows.as<int32_t>() + h->bin_start[BIN_HEAVY],
+                                                         h->cold_hbase_d.as<int32_t>(), nh, h->heavy_chunk,
+                                                         E1.allhrec.as<int4>());
+    }
     invalidate_graph(h, P, nullptr);
     Engine &E = *h->eng;
     // Bounds in, box check.

@@ -106,6 +106,11 @@ struct Ctl {
     unsigned long long stat_nnz;     // their nonzeros
     unsigned long long stat_vars;    // distinct bound records read per round
     unsigned long long stat_written; // accepted bound changes
+    // scan rounds of one vector (see Params::scan_ok)
+    uint32_t scan[2];                // the round of this parity scans every row
+    uint32_t scan_go;                // a bound moved in the last scan-seeding bound update
+    uint32_t pad2_;
+    unsigned long long scan_rows[NSTRIPE], scan_nnz[NSTRIPE];  // rows a scan round processed
 };
 
 // The leading fields of Ctl for the round in progress (its parity's queue
@@ -115,6 +120,7 @@ struct CtlHead {
     uint32_t round, done;
     uint32_t qcount[NBIN];
     uint32_t hchunks, ghchunks;
+    uint32_t scan;
 };
 
 // Keeps control loads ahead of the first branch on them, so that they are
@@ -137,6 +143,8 @@ __device__ __forceinline__ CtlHead ctl_head(const Ctl *C) {
     const uint32_t g0 = C->ghchunks[0], g1 = C->ghchunks[1];
     H.hchunks = odd ? h1 : h0;
     H.ghchunks = odd ? g1 : g0;
+    const uint32_t sc0 = C->scan[0], sc1 = C->scan[1];
+    H.scan = odd ? sc1 : sc0;
     return H;
 }
 
@@ -185,6 +193,18 @@ struct Params {
     Acc *ghpart;                 // [task][2][64] per-slot corrections of a chunk
     uint64_t *ghlive;            // [task] the row's slot mask, as read by the chunk
     uint64_t *dmaskg;            // [groups][sn] slots of the group with var i dirty
+    // Scan rounds (one plain vector): when a bound update changes many
+    // variables, the next round does not queue rows through the columns;
+    // instead the row kernel walks every row and processes those holding a
+    // variable of the changed bitmap.  The set of rows is the same.
+    int32_t scan_ok;             // the engine runs one plain vector
+    uint32_t scan_min;           // changed entries from which the next round scans
+    uint32_t *cbits;             // [2][snw] variables changed by the update feeding parity p
+    const int32_t *allrows;      // every row, grouped by bin
+    int64_t allstart[NBIN + 1];  // bin offsets in allrows
+    const int4 *allhrec;         // chunk records of every heavy row
+    int32_t allhchunks;
+    uint32_t *hhit;              // [m] heavy row holds a changed variable (scan rounds)
 };
 
 // Exact activities of a heavy row at the base bounds: each finite part as a
@@ -459,12 +479,50 @@ __device__ __forceinline__ void clear_rflag(const Params &P, int s, int k) {
     atomicAnd(&P.rflag[(size_t)s * P.srw + (k >> 5)], ~bit);
 }
 
+// Scan rounds: does variable i hold a change of the update feeding par?
+__device__ __forceinline__ bool scan_hit(const Params &P, int par, int i) {
+    return (P.cbits[(size_t)par * P.snw + (i >> 5)] >> (i & 31)) & 1u;
+}
+
+// Rows and nonzeros a workgroup processed in a scan round, added once per
+// workgroup to its stripe of the round's totals.  Reached by the whole
+// workgroup.
+__device__ void scan_count_flush(const Params &P, unsigned long long rows, unsigned long long nnz) {
+    __shared__ unsigned long long sr[WG / 64], sz[WG / 64];
+#pragma unroll
+    for (int w = 1; w < 64; w <<= 1) {
+        rows += __shfl_xor(rows, w, 64);
+        nnz += __shfl_xor(nnz, w, 64);
+    }
+    if (__lane_id() == 0) {
+        sr[threadIdx.x >> 6] = rows;
+        sz[threadIdx.x >> 6] = nnz;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long r = 0, z = 0;
+        for (int j = 0; j < WG / 64; ++j) {
+            r += sr[j];
+            z += sz[j];
+        }
+        const int st = blockIdx.x & (NSTRIPE - 1);
+        if (r) {
+            atomicAdd(&P.ctl->scan_rows[st], r);
+            atomicAdd(&P.ctl->scan_nnz[st], z);
+        }
+    }
+}
+
 // ------------------------------------------------------------------------
 // Light rows: G lanes per row, len <= G (bins 0..6) or one wave per row
-// with several nonzeros per lane (bins 7..10).
+// with several nonzeros per lane (bins 7..10).  In a scan round the rows
+// come from the list of every row (rows32) and a row holding no changed
+// variable is skipped; the processed rows are counted in sc_rows/sc_nnz.
 // ------------------------------------------------------------------------
 template <bool MULTI, int G>
-__device__ void light_rows(const Params &P, const uint64_t *q, uint32_t count, uint32_t unit) {
+__device__ void light_rows(const Params &P, const uint64_t *q, uint32_t count, uint32_t unit,
+                           const int32_t *rows32, int par, unsigned long long &sc_rows,
+                           unsigned long long &sc_nnz) {
     const int lane = __lane_id();
     const int wave = threadIdx.x >> 6;
     const int per_wave = 64 / G;
@@ -477,9 +535,13 @@ __device__ void light_rows(const Params &P, const uint64_t *q, uint32_t count, u
     double2 sd = make_double2(0.0, 0.0);
     DInst I = P.I;
     if (valid) {
-        uint64_t task = q[t];
-        s = (int)(task >> 32);
-        k = (int)(uint32_t)task;
+        if (rows32) {
+            k = rows32[t];
+        } else {
+            uint64_t task = q[t];
+            s = (int)(task >> 32);
+            k = (int)(uint32_t)task;
+        }
         I = inst_of<MULTI>(P, s);
         // independent loads, issued together
         int32_t state = P.info[s].state;
@@ -487,7 +549,23 @@ __device__ void light_rows(const Params &P, const uint64_t *q, uint32_t count, u
         p1 = I.row_ptr[k + 1];
         sd = I.side[k];
         live = state == SLOT_ACTIVE;
-        if (gl == 0) clear_rflag(P, s, k);
+        if (gl == 0 && !rows32) clear_rflag(P, s, k);
+    }
+    if (rows32) {
+        // scan round: keep the row only if one of its variables changed
+        bool mine = false;
+        const int it_hit = G < 64 ? 1 : (int)((p1 - p0 + 63) / 64);
+        for (int it = 0; it < it_hit; ++it) {
+            const int64_t p = p0 + gl + (int64_t)it * G;
+            if (live && p < p1) mine = mine || scan_hit(P, par, I.col[p]);
+        }
+        const uint64_t hm = __ballot(mine);
+        const uint64_t gmask = (G == 64 ? ~0ull : ((1ull << G) - 1)) << ((lane / G) * G);
+        live = live && (hm & gmask) != 0;
+        if (live && gl == 0) {
+            sc_rows += 1;
+            sc_nnz += (unsigned long long)(p1 - p0);
+        }
     }
     if (!live) p1 = p0;
     const BView bnd = bview(P, s, I.base);
@@ -623,15 +701,32 @@ __device__ inline void wg_reduce(Acc &mn, Acc &mx, double &wmax, WgScratch &W) {
 
 // Block rows: one workgroup per row (1024 < len <= heavy threshold).
 template <bool MULTI>
-__device__ void block_row(const Params &P, const uint64_t *q, uint32_t t, WgScratch &W) {
-    uint64_t task = q[t];
-    int s = (int)(task >> 32);
-    int k = (int)(uint32_t)task;
+__device__ void block_row(const Params &P, const uint64_t *q, uint32_t t, WgScratch &W,
+                          const int32_t *rows32, int par, unsigned long long &sc_rows,
+                          unsigned long long &sc_nnz) {
+    int s = 0, k = 0;
+    if (rows32) {
+        k = rows32[t];
+    } else {
+        uint64_t task = q[t];
+        s = (int)(task >> 32);
+        k = (int)(uint32_t)task;
+    }
     bool live = P.info[s].state == SLOT_ACTIVE;
-    if (threadIdx.x == 0) clear_rflag(P, s, k);
+    if (threadIdx.x == 0 && !rows32) clear_rflag(P, s, k);
     if (!live) return;  // workgroup-uniform
     const DInst I = inst_of<MULTI>(P, s);
     int64_t p0 = I.row_ptr[k], p1 = I.row_ptr[k + 1];
+    if (rows32) {
+        // scan round: keep the row only if one of its variables changed
+        bool mine = false;
+        for (int64_t p = p0 + threadIdx.x; p < p1; p += WG) mine = mine || scan_hit(P, par, I.col[p]);
+        if (!__syncthreads_or(mine)) return;  // workgroup-uniform
+        if (threadIdx.x == 0) {
+            sc_rows += 1;
+            sc_nnz += (unsigned long long)(p1 - p0);
+        }
+    }
     const BView bnd = bview(P, s, I.base);
     Acc mn, mx;
     acc_zero(mn);
@@ -692,11 +787,12 @@ __device__ void block_row(const Params &P, const uint64_t *q, uint32_t t, WgScra
 // row.  The chunks of a row are contiguous; the candidate kernel of the
 // same round combines them (the kernel boundary makes them visible).
 template <bool MULTI>
-__device__ void heavy_chunk_activity(const Params &P, int par, uint32_t u, WgScratch &W) {
-    const int4 rec = P.hrec[par][u];
+__device__ void heavy_chunk_activity(const Params &P, int par, uint32_t u, WgScratch &W,
+                                     bool scan) {
+    const int4 rec = scan ? P.allhrec[u] : P.hrec[par][u];
     const int s = rec.x, k = rec.y, c = rec.z;
     const bool live = P.info[s].state == SLOT_ACTIVE;
-    if (c == 0 && threadIdx.x == 0) clear_rflag(P, s, k);
+    if (c == 0 && threadIdx.x == 0 && !scan) clear_rflag(P, s, k);
     if (!live) return;  // workgroup-uniform
     const DInst I = inst_of<MULTI>(P, s);
     const int64_t r0 = I.row_ptr[k], r1 = I.row_ptr[k + 1];
@@ -707,13 +803,18 @@ __device__ void heavy_chunk_activity(const Params &P, int par, uint32_t u, WgScr
     acc_zero(mn);
     acc_zero(mx);
     double wmax = 0.0;
+    bool mine = false;
     for (int64_t p = p0 + threadIdx.x; p < p1; p += WG) {
-        double2 b = bnd[I.col[p]];
+        const int i = I.col[p];
+        double2 b = bnd[i];
         double a = I.val[p];
         add_terms(mn, mx, a, b.x, b.y);
         wmax = fmax(wmax, nz_width(a, b.x, b.y));
-        count_read(P, s, I.col[p]);
+        count_read(P, s, i);
+        if (scan) mine = mine || scan_hit(P, par, i);
     }
+    // scan round: the row is processed if any of its chunks holds a change
+    if (scan && __syncthreads_or(mine) && threadIdx.x == 0) atomicOr(&P.hhit[k], 1u);
     wg_reduce(mn, mx, wmax, W);
     if (threadIdx.x == 0) {
         P.hpart[2 * (size_t)u] = mn;
@@ -726,11 +827,20 @@ __device__ void heavy_chunk_activity(const Params &P, int par, uint32_t u, WgScr
 // (lane l takes chunks l, l+64, ... in order, then a butterfly), certifies
 // the sums and tests the row; the chunk's nonzeros then give candidates.
 template <bool MULTI>
-__device__ void heavy_chunk_candidates(const Params &P, int par, uint32_t u) {
-    const int4 rec = P.hrec[par][u];
+__device__ void heavy_chunk_candidates(const Params &P, int par, uint32_t u, bool scan) {
+    const int4 rec = scan ? P.allhrec[u] : P.hrec[par][u];
     const int s = rec.x, k = rec.y, c = rec.z, nch = rec.w;
     if (P.info[s].state != SLOT_ACTIVE) return;  // workgroup-uniform
     const DInst I = inst_of<MULTI>(P, s);
+    if (scan) {
+        // scan round: rows without a changed variable are not processed
+        if (!P.hhit[k]) return;  // workgroup-uniform
+        if (c == 0 && threadIdx.x == 0) {
+            const int st = blockIdx.x & (NSTRIPE - 1);
+            atomicAdd(&P.ctl->scan_rows[st], 1ull);
+            atomicAdd(&P.ctl->scan_nnz[st], (unsigned long long)(I.row_ptr[k + 1] - I.row_ptr[k]));
+        }
+    }
     const int lane = __lane_id();
     const int64_t r0 = I.row_ptr[k], r1 = I.row_ptr[k + 1];
     const double2 sd = I.side[k];
@@ -946,8 +1056,16 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(BP_ROWS
     // round trip) and selected afterwards; a finished run has no units.
     const CtlHead H = ctl_head(P.ctl);
     const int par = H.round & 1;
-    const uint32_t *qc = H.qcount;
-    const uint32_t C_ghchunks = H.ghchunks, C_hchunks = H.hchunks;
+    // A scan round walks every row (the instance's bin lists) instead of the
+    // queues.
+    const bool scan = P.scan_ok && H.scan;
+    uint32_t qc[NBIN];
+#pragma unroll
+    for (int b = 0; b < NBIN; ++b)
+        qc[b] = scan ? (uint32_t)(P.allstart[b + 1] - P.allstart[b]) : H.qcount[b];
+    const uint32_t C_ghchunks = scan ? 0u : H.ghchunks;
+    const uint32_t C_hchunks = scan ? (uint32_t)P.allhchunks : H.hchunks;
+    unsigned long long sc_rows = 0, sc_nnz = 0;
     // Work units: grouped heavy chunk tasks (four per unit, one per wave),
     // heavy chunks, block rows, then light bins 10..0.
     const uint32_t ngh = C_ghchunks;
@@ -966,9 +1084,10 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(BP_ROWS
             const uint32_t t = u * (WG / 64) + (threadIdx.x >> 6);
             if (t < ngh) gh_chunk_corrections(P, par, t);
         } else if (u < start[1]) {
-            heavy_chunk_activity<MULTI>(P, par, u - start[0], W);
+            heavy_chunk_activity<MULTI>(P, par, u - start[0], W, scan);
         } else if (u < start[2]) {
-            block_row<MULTI>(P, P.q[par][BIN_BLOCK], u - start[1], W);
+            block_row<MULTI>(P, P.q[par][BIN_BLOCK], u - start[1], W,
+                             scan ? P.allrows + P.allstart[BIN_BLOCK] : nullptr, par, sc_rows, sc_nnz);
         } else {
             // bin of unit u by constant-index selects (start[] stays in
             // registers; a dynamic index would place it in scratch memory)
@@ -984,33 +1103,36 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(BP_ROWS
             int b = NLIGHT - 1 - j;
             uint32_t lu = u - ubase;
             const uint64_t *q = P.q[par][b];
+            const int32_t *r32 = scan ? P.allrows + P.allstart[b] : nullptr;
             switch (b) {
-                case 0: light_rows<MULTI, 1>(P, q, cnt, lu); break;
-                case 1: light_rows<MULTI, 2>(P, q, cnt, lu); break;
-                case 2: light_rows<MULTI, 4>(P, q, cnt, lu); break;
-                case 3: light_rows<MULTI, 8>(P, q, cnt, lu); break;
-                case 4: light_rows<MULTI, 16>(P, q, cnt, lu); break;
-                case 5: light_rows<MULTI, 32>(P, q, cnt, lu); break;
-                default: light_rows<MULTI, 64>(P, q, cnt, lu); break;
+                case 0: light_rows<MULTI, 1>(P, q, cnt, lu, r32, par, sc_rows, sc_nnz); break;
+                case 1: light_rows<MULTI, 2>(P, q, cnt, lu, r32, par, sc_rows, sc_nnz); break;
+                case 2: light_rows<MULTI, 4>(P, q, cnt, lu, r32, par, sc_rows, sc_nnz); break;
+                case 3: light_rows<MULTI, 8>(P, q, cnt, lu, r32, par, sc_rows, sc_nnz); break;
+                case 4: light_rows<MULTI, 16>(P, q, cnt, lu, r32, par, sc_rows, sc_nnz); break;
+                case 5: light_rows<MULTI, 32>(P, q, cnt, lu, r32, par, sc_rows, sc_nnz); break;
+                default: light_rows<MULTI, 64>(P, q, cnt, lu, r32, par, sc_rows, sc_nnz); break;
             }
         }
         __syncthreads();
     }
+    if (scan) scan_count_flush(P, sc_rows, sc_nnz);
 }
 
 template <bool MULTI>
 __global__ void __launch_bounds__(WG) k_heavy(Params P) {
     const CtlHead H = ctl_head(P.ctl);
     const int par = H.round & 1;
-    const uint32_t ngh = H.ghchunks;
+    const bool scan = P.scan_ok && H.scan;
+    const uint32_t ngh = scan ? 0u : H.ghchunks;
     const uint32_t gh_units = (ngh + (WG / 64) - 1) / (WG / 64);
-    const uint32_t total = H.done ? 0u : gh_units + H.hchunks;
+    const uint32_t total = H.done ? 0u : gh_units + (scan ? (uint32_t)P.allhchunks : H.hchunks);
     for (uint32_t u = blockIdx.x; u < total; u += gridDim.x) {
         if (u < gh_units) {
             const uint32_t t = u * (WG / 64) + (threadIdx.x >> 6);
             if (t < ngh) gh_chunk_candidates<MULTI>(P, par, t);
         } else {
-            heavy_chunk_candidates<MULTI>(P, par, u - gh_units);
+            heavy_chunk_candidates<MULTI>(P, par, u - gh_units, scan);
         }
     }
 }
@@ -1176,6 +1298,7 @@ __global__ void __launch_bounds__(WG) k_end(Params P) {
     // before the early exit.
     const uint32_t c_done = C->done, c_round = C->round, c_max_rounds = C->max_rounds;
     const uint32_t c_next_job = C->next_job, c_total_jobs = C->total_jobs;
+    const uint32_t c_scan_go = C->scan_go;
     const int s_first = threadIdx.x;
     SlotInfo first;
     if (s_first < P.nslots) first = P.info[s_first];
@@ -1185,6 +1308,16 @@ __global__ void __launch_bounds__(WG) k_end(Params P) {
     asm volatile("" ::"v"(first.state));
     if (c_done) return;
     const int par = c_round & 1;
+    // A scan round counted its processed rows itself (they were not queued);
+    // a scan-seeding update marks pending work with scan_go.
+    unsigned long long sc_rows = 0, sc_nnz = 0;
+    if (P.scan_ok) {
+#pragma unroll
+        for (int st = 0; st < NSTRIPE; ++st) {
+            sc_rows += C->scan_rows[st];
+            sc_nnz += C->scan_nnz[st];
+        }
+    }
     __shared__ uint32_t s_active, s_finished;
     if (threadIdx.x == 0) {
         s_active = 0;
@@ -1199,6 +1332,10 @@ __global__ void __launch_bounds__(WG) k_end(Params P) {
             continue;
         }
         if (V.state != SLOT_ACTIVE) continue;
+        // nonzeros of this round's scanned rows (one vector: slot 0)
+        const unsigned long long nnz0 = V.nnz + (s == 0 ? sc_nnz : 0ull);
+        if (nnz0 != V.nnz) S.nnz = nnz0;
+        const int32_t pending = V.pending_rows + (s == 0 && c_scan_go ? 1 : 0);
         bool fin = true;
         bool drain = false;
         if (V.row_bad_count > 0) {
@@ -1207,7 +1344,7 @@ __global__ void __launch_bounds__(WG) k_end(Params P) {
         } else if (V.var_bad_min != NONE) {
             S.status = 1;
             drain = V.pending_rows > 0;
-        } else if (V.pending_rows == 0) {
+        } else if (pending == 0) {
             S.status = 0;
         } else if ((uint32_t)V.rounds >= c_max_rounds) {
             S.status = 2;
@@ -1215,7 +1352,7 @@ __global__ void __launch_bounds__(WG) k_end(Params P) {
         } else {
             fin = false;
             S.rounds = V.rounds + 1;
-            S.nnz = V.nnz + V.pending_nnz;
+            S.nnz = nnz0 + V.pending_nnz;
             atomicAdd(&C->stat_rows, (unsigned long long)V.pending_rows);
             atomicAdd(&C->stat_nnz, V.pending_nnz);
             S.pending_rows = 0;
@@ -1242,6 +1379,18 @@ __global__ void __launch_bounds__(WG) k_end(Params P) {
         C->hchunks[par] = 0;
         C->ghchunks[par] = 0;
         for (int st = 0; st < NSTRIPE; ++st) C->nchanged[st] = 0;
+        if (P.scan_ok) {
+            if (sc_rows) {
+                atomicAdd(&C->stat_rows, sc_rows);
+                atomicAdd(&C->stat_nnz, sc_nnz);
+            }
+            for (int st = 0; st < NSTRIPE; ++st) {
+                C->scan_rows[st] = 0;
+                C->scan_nnz[st] = 0;
+            }
+            C->scan[par] = 0;
+            C->scan_go = 0;
+        }
         C->active = s_active;
         C->finished = s_finished;
         C->round = c_round + 1;
@@ -1256,14 +1405,26 @@ __global__ void __launch_bounds__(WG) k_apply(Params P) {
     Ctl *C = P.ctl;
     // Control fields and the stripe lengths, read together.
     const uint32_t c_round = C->round, c_done = C->done;
+    const uint32_t c_scan0 = C->scan[0], c_scan1 = C->scan[1];
     uint32_t pre[NSTRIPE + 1];
     pre[0] = 0;
 #pragma unroll
     for (int st = 0; st < NSTRIPE; ++st) pre[st + 1] = pre[st] + C->nchanged[st];
     ctl_loaded(c_round, c_done, pre[NSTRIPE]);
+    ctl_loaded(c_scan0, c_scan1, c_done);
     const int par = c_round & 1;
     const int npar = par ^ 1;
     const uint32_t total = c_done ? 0u : pre[NSTRIPE];
+    // Scan rounds (one plain vector): this round's changed bitmap and heavy
+    // hits are cleared once the round's row kernels have read them; a large
+    // update makes the next round scan every row instead of queueing rows.
+    const bool scan_now = P.scan_ok && (par ? c_scan1 : c_scan0) && !c_done;
+    const bool scan_next = P.scan_ok && total >= P.scan_min;
+    if (scan_now) {
+        const size_t g = (size_t)blockIdx.x * WG + threadIdx.x, G = (size_t)gridDim.x * WG;
+        for (size_t w = g; w < (size_t)P.snw; w += G) P.cbits[(size_t)par * P.snw + w] = 0u;
+        for (size_t u = g; u < (size_t)P.allhchunks; u += G) P.hhit[P.allhrec[u].y] = 0u;
+    }
     const double INF = __builtin_inf();
     const int lane = __lane_id();
     const uint32_t nwaves = gridDim.x * (WG / 64);
@@ -1318,7 +1479,11 @@ __global__ void __launch_bounds__(WG) k_apply(Params P) {
             }
         }
         uint64_t wm = __ballot(go);
-        if (single) {
+        if (scan_next) {
+            // the next round scans every row for these variables
+            w_written += (unsigned long long)__popcll(wm);
+            if (go) atomicOr(&P.cbits[(size_t)npar * P.snw + (i >> 5)], 1u << (i & 31));
+        } else if (single) {
             w_written += (unsigned long long)__popcll(wm);
             uint32_t r = 0;
             unsigned long long z = 0;
@@ -1352,6 +1517,8 @@ __global__ void __launch_bounds__(WG) k_apply(Params P) {
                 atomicAdd(&P.info[0].pending_nnz, z);
             }
             if (w) atomicAdd(&C->stat_written, w);
+            if (scan_next && w) C->scan_go = 1u;
+            if (scan_next && blockIdx.x == 0) C->scan[npar] = 1u;
         }
     }
 }
