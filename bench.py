@@ -36,11 +36,11 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E datasheet peak
 # belongs to the kernel sources it was measured on: when any of them
 # differs, the bench line reports null.
 K_ROWS_TRAFFIC = {
-    "fetch_kib": 10909.5, "write_kib": 845.4, "fetch_scale": 2.0, "write_scale": 1.0,
+    "fetch_kib": 10631.9, "write_kib": 232.8, "fetch_scale": 2.0, "write_scale": 1.0,
     "sources": {
-        "paper_2510_20499_amd/csrc/bp_kernels.h": "3908f4238343d5efadb1365e4ccb8afab6790c668ef217456da888bfc1a72ab0",
+        "paper_2510_20499_amd/csrc/bp_kernels.h": "b3dce6ec8e33d54df3e97735097f2c6ee742e7b990bf9660d258063492669c59",
         "paper_2510_20499_amd/csrc/bp_sum.h": "833f834eb740e1aaeae0a7fe22dd2566f3b231f64aa197bf2945502c9275c3e9",
-        "paper_2510_20499_amd/build.py": "c136435afc6346a2636062ac8e92ff4589056551b3201f87db712a04372cec3e",
+        "paper_2510_20499_amd/build.py": "2b907a883848d04e156f5dd7ba1f49df479651c7e7c715a833f348226ba0bcb8",
     },
 }
 
