@@ -47,6 +47,21 @@ def assert_same(inst, rg, lg, ug, ro, lo, uo, what=""):
     assert rel_close(ug[~integ], uo[~integ]), (what, "continuous ub")
 
 
+def gpu_base(I, lb, ub):
+    """Make bounds the oracle computed the instance's base: a warm start
+    with an empty change list propagates nothing and keeps them.  The
+    stored base is read back and checked bit for bit, so both sides start
+    from the same input."""
+    tl = dev(lb, torch.float64)
+    tu = dev(ub, torch.float64)
+    r = I.propagate(tl, tu, torch.zeros(0, dtype=torch.int32, device="cuda"))
+    assert r["status"] == 0 and r["rounds"] == 0, r
+    bl, bu = I.base()
+    torch.cuda.synchronize()
+    assert np.array_equal(bl.cpu().numpy().view(np.int64), np.asarray(lb, np.float64).view(np.int64))
+    assert np.array_equal(bu.cpu().numpy().view(np.int64), np.asarray(ub, np.float64).view(np.int64))
+
+
 def both(I, inst, lb=None, ub=None, changed=None, opts=None, what=""):
     rg, lg, ug = gpu_propagate(I, inst, lb, ub, changed)
     ro, lo, uo = oracle.propagate(inst, lb, ub, changed=changed, opts=opts)

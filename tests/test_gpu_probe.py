@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_util import bp, dev, gpu_propagate
+from gpu_util import bp, dev, gpu_base, gpu_propagate
 from helpers import load_golden, rel_close
 from paper_2510_20499_amd import gen
 
@@ -21,8 +21,10 @@ def _probe_both(inst, vars_, slots=None, cap=None, opts_kw=None):
     if slots is not None:
         kw["probe_slots"] = slots
     I = bp().Instance(inst, bp().default_options(**kw))
-    r, lb, ub = gpu_propagate(I, inst)
-    assert r["status"] == bp().BP_OK
+    # the base is the oracle's root fixed point, given to both sides
+    ro, lb, ub = oracle.propagate(inst)
+    assert ro["status"] == oracle.BP_OK
+    gpu_base(I, lb, ub)
     vs = np.asarray(vars_, np.int32)
     G = I.probe(dev(vs, torch.int32), cap=cap)
     torch.cuda.synchronize()
@@ -130,7 +132,8 @@ def test_capacity_two_phase_and_states():
     with pytest.raises(bp().BPError) as e:  # no base yet
         I.probe(vs)
     assert e.value.code == bp().BP_ESTATE
-    _, lb, ub = gpu_propagate(I, inst)
+    _, lb, ub = oracle.propagate(inst)
+    gpu_base(I, lb, ub)
     bins = _binaries(inst, lb, ub)
     G = I.probe(dev(bins[:20].astype(np.int32), torch.int32), cap=1)  # grows via required
     O = oracle.probe(inst, lb, ub, bins[:20])
@@ -147,7 +150,8 @@ def test_capacity_two_phase_and_states():
 def test_repeated_calls_keep_slots_clean():
     inst = gen.make("tiny", 4)
     I = bp().Instance(inst, bp().default_options(probe_slots=16))
-    _, lb, ub = gpu_propagate(I, inst)
+    _, lb, ub = oracle.propagate(inst)
+    gpu_base(I, lb, ub)
     vs = _binaries(inst, lb, ub).astype(np.int32)
     O = oracle.probe(inst, lb, ub, vs)
     for _ in range(3):
