@@ -82,6 +82,11 @@ extern "C" {
 #define BP_FLAG_BATCH_SLOTS 16u /* run bp_propagate_batch on the slot engine
                                    (one slot per vector) whatever the batch
                                    size; results are identical */
+#define BP_FLAG_FULL_ROWS 32u   /* bp_propagate: recompute every queued heavy
+                                   row from its nonzeros each round instead of
+                                   keeping its exact activities up to date
+                                   through the bound changes; results are
+                                   identical */
 
 /* A sparse matrix in compressed form: CSR (ptr over m rows, idx = column
  * indices ascending in each row) or CSC (ptr over n columns, idx = row

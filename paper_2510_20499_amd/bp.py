@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libbp.so")
 BP_OK, BP_INFEASIBLE, BP_ROUND_LIMIT = 0, 1, 2
 BP_EINVAL, BP_ENOMEM, BP_EDEVICE, BP_ECAPACITY, BP_ESTATE = -1, -2, -3, -4, -5
 FLAG_FORCE_EXACT, FLAG_TIME_KERNELS, FLAG_HOST_ROUNDS, FLAG_COUNT_VARS, FLAG_BATCH_SLOTS = 1, 2, 4, 8, 16
+FLAG_FULL_ROWS = 32
 
 EXPORTS = ["bp_options_default", "bp_load", "bp_propagate", "bp_propagate_batch", "bp_probe",
            "bp_get_base", "bp_kernel_stats", "bp_device_bytes", "bp_free", "bp_last_error",

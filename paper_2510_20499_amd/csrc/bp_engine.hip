@@ -97,8 +97,9 @@ struct Engine {
     int32_t cap_slots = 0;
     int32_t track_dirty = 0;
     int32_t nstripe = 1;  // changed-list stripes (NSTRIPE for one slot)
-    // scan rounds of one plain vector (engines of one slot)
-    DevBuf cbits, hhit, allhrec;
+    // scan rounds and incremental heavy rows of one plain vector (engines
+    // of one slot)
+    DevBuf cbits, hhit, allhrec, hacc, hinf, hwid, hact;
     Shape shape;
     int64_t bytes = 0;
     DevBuf bnd, cand, vflag, rflag, info, chg, dirty, dlist, dcount, ctl, touched, filt;
@@ -126,7 +127,8 @@ struct bp_instance {
     int64_t heavy_threshold = 8192;
     int32_t heavy_chunk = 4096;
     // device copies
-    DevBuf row_ptr, col, val, side, col_ptr, col_row, vtype, rbin, cold_rows, base;
+    DevBuf row_ptr, col, val, side, col_ptr, col_row, col_val, vtype, rbin, cold_rows, base;
+    DevBuf hidx_d;  // [m] heavy index of each row (-1: not heavy), bin order
     int64_t bytes = 0;
     bool have_base = false;
     int64_t base_version = 0;
@@ -379,6 +381,9 @@ static int bin_rows(bp_instance *h, hipStream_t st) {
         std::vector<int64_t> fill(h->bin_start, h->bin_start + NBIN);
         for (int64_t k = 0; k < m; ++k) cold[fill[rbin[k]]++] = (int32_t)k;
     }
+    std::vector<int32_t> hidx(m, -1);
+    for (int64_t j = h->bin_start[BIN_HEAVY]; j < h->bin_start[BIN_HEAVY + 1]; ++j)
+        hidx[cold[j]] = (int32_t)(j - h->bin_start[BIN_HEAVY]);
     h->heavy_chunks = 0;
     h->cold_hbase.clear();
     for (int64_t j = h->bin_start[BIN_HEAVY]; j < h->bin_start[BIN_HEAVY + 1]; ++j) {
@@ -391,7 +396,9 @@ static int bin_rows(bp_instance *h, hipStream_t st) {
     if ((rc = h->rbin.alloc((size_t)m, h->bytes))) return rc;
     if ((rc = h->cold_rows.alloc((size_t)m * 4, h->bytes))) return rc;
     if ((rc = h->cold_hbase_d.alloc(h->cold_hbase.size() * 4, h->bytes))) return rc;
+    if ((rc = h->hidx_d.alloc((size_t)m * 4, h->bytes))) return rc;
     if (m) {
+        HIPTRY(hipMemcpyAsync(h->hidx_d.p, hidx.data(), (size_t)m * 4, hipMemcpyHostToDevice, st));
         HIPTRY(hipMemcpyAsync(h->rbin.p, rbin.data(), (size_t)m, hipMemcpyHostToDevice, st));
         HIPTRY(hipMemcpyAsync(h->cold_rows.p, cold.data(), (size_t)m * 4, hipMemcpyHostToDevice, st));
     }
@@ -446,12 +453,17 @@ extern "C" int bp_load(const bp_sparse *csr, const bp_sparse *csc, const double 
     // CSC: build, or check a given one against the transpose.
     std::vector<int64_t> cptr(n + 1, 0);
     std::vector<int32_t> crow(nnz);
+    std::vector<double> cval(nnz);
     for (int64_t p = 0; p < nnz; ++p) cptr[csr->idx[p] + 1] += 1;
     for (int64_t i = 0; i < n; ++i) cptr[i + 1] += cptr[i];
     {
         std::vector<int64_t> fill(cptr.begin(), cptr.end() - 1);
         for (int64_t k = 0; k < m; ++k)
-            for (int64_t p = csr->ptr[k]; p < csr->ptr[k + 1]; ++p) crow[fill[csr->idx[p]]++] = (int32_t)k;
+            for (int64_t p = csr->ptr[k]; p < csr->ptr[k + 1]; ++p) {
+                const int64_t e = fill[csr->idx[p]]++;
+                crow[e] = (int32_t)k;
+                cval[e] = csr->val[p];
+            }
     }
     if (csc) {
         if (csc->m != m || csc->n != n || csc->nnz != nnz || !csc->ptr || (nnz && !csc->idx))
@@ -497,6 +509,7 @@ extern "C" int bp_load(const bp_sparse *csr, const bp_sparse *csc, const double 
     ALLOC_UP(side, side.data(), (size_t)m * 16);
     ALLOC_UP(col_ptr, cptr.data(), (size_t)(n + 1) * 8);
     ALLOC_UP(col_row, crow.data(), (size_t)nnz * 4);
+    ALLOC_UP(col_val, cval.data(), (size_t)nnz * 8);
     ALLOC_UP(vtype, vartype, (size_t)n);
 #undef ALLOC_UP
     if ((rc = bin_rows(h.get(), st))) return rc;
@@ -556,6 +569,10 @@ static int engine_alloc(std::unique_ptr<Engine> &eng, const Shape &sh, int32_t s
         if ((rc = E->cbits.alloc((size_t)2 * nw_var * 4, B))) return rc;
         if ((rc = E->hhit.alloc((size_t)m * 4, B))) return rc;
         if ((rc = E->allhrec.alloc((size_t)std::max<int64_t>(sh.heavy_chunks, 1) * sizeof(int4), B)))
+            return rc;
+        const int64_t H = std::max<int64_t>(sh.heavy_rows, 1);
+        if ((rc = E->hacc.alloc((size_t)H * 2 * HL * 8, B)) || (rc = E->hinf.alloc((size_t)H * 8, B)) ||
+            (rc = E->hwid.alloc((size_t)H * 8, B)) || (rc = E->hact.alloc((size_t)H * 16, B)))
             return rc;
     }
     if ((rc = E->ctl.alloc(sizeof(Ctl), B))) return rc;
@@ -674,6 +691,11 @@ static Params make_params(const bp_instance *h, int32_t nslots) {
     return P;
 }
 
+// A round with at least n / BP_INC_DIV changed variables hands the heavy-row
+// accumulators to a rebuild in the next round instead of correcting them.
+#ifndef BP_INC_DIV
+#define BP_INC_DIV 256
+#endif
 static const int GRID_ROWS = 2048;
 static const int GRID_HEAVY = 1024;
 static const int GRID_APPLY = 512;
@@ -794,6 +816,7 @@ static int start_slots(bp_instance *h, const Params &P, int32_t ns, hipStream_t 
     memset(&c, 0, sizeof(c));
     c.max_rounds = (uint32_t)h->opt.max_rounds;
     c.nslots = (uint32_t)ns;
+    c.hbuild[0] = P.inc ? 1u : 0u;  // the first round builds the heavy-row accumulators
     if (cold) {
         for (int b = 0; b < NBIN; ++b) c.qcount[0][b] = (uint32_t)(h->bin_count[b] * ns);
         c.hchunks[0] = (uint32_t)(h->heavy_chunks * ns);
@@ -899,6 +922,21 @@ static int propagate_slots(bp_instance *h, int32_t Bv, double *lb, double *ub,
         for (int b = 0; b <= NBIN; ++b) P.allstart[b] = h->bin_start[b];
         P.allhrec = E1.allhrec.as<int4>();
         P.allhchunks = (int32_t)h->heavy_chunks;
+        const int64_t nheavy = h->bin_count[BIN_HEAVY];
+        if (nheavy > 0 && !(h->opt.flags & BP_FLAG_FULL_ROWS)) {
+            P.inc = 1;
+            P.nheavy = (int32_t)nheavy;
+            P.hacc = E1.hacc.as<long long>();
+            P.hinf = E1.hinf.as<int32_t>();
+            P.hwid = E1.hwid.as<unsigned long long>();
+            P.hidx = h->hidx_d.as<int32_t>();
+            P.cval = h->col_val.as<double>();
+            P.hact = E1.hact.as<double2>();
+            P.inc_max = (uint32_t)std::max<int64_t>(64, h->n / BP_INC_DIV);
+            HIPTRY(hipMemsetAsync(E1.hacc.p, 0, (size_t)nheavy * 2 * HL * 8, st));
+            HIPTRY(hipMemsetAsync(E1.hinf.p, 0, (size_t)nheavy * 8, st));
+            HIPTRY(hipMemsetAsync(E1.hwid.p, 0, (size_t)nheavy * 8, st));
+        }
         HIPTRY(hipMemsetAsync(E1.cbits.p, 0, E1.cbits.bytes, st));
         HIPTRY(hipMemsetAsync(E1.hhit.p, 0, E1.hhit.bytes, st));
         const int64_t nh = h->bin_count[BIN_HEAVY];

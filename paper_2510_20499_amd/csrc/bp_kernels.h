@@ -111,6 +111,8 @@ struct Ctl {
     uint32_t scan_go;                // a bound moved in the last scan-seeding bound update
     uint32_t pad2_;
     unsigned long long scan_rows[NSTRIPE], scan_nnz[NSTRIPE];  // rows a scan round processed
+    // incremental heavy-row activities (see Params::inc)
+    uint32_t hbuild[2];              // the round of this parity rebuilds them from the bounds
 };
 
 // The leading fields of Ctl for the round in progress (its parity's queue
@@ -121,6 +123,7 @@ struct CtlHead {
     uint32_t qcount[NBIN];
     uint32_t hchunks, ghchunks;
     uint32_t scan;
+    uint32_t hbuild;
 };
 
 // Keeps control loads ahead of the first branch on them, so that they are
@@ -145,6 +148,8 @@ __device__ __forceinline__ CtlHead ctl_head(const Ctl *C) {
     H.ghchunks = odd ? g1 : g0;
     const uint32_t sc0 = C->scan[0], sc1 = C->scan[1];
     H.scan = odd ? sc1 : sc0;
+    const uint32_t hb0 = C->hbuild[0], hb1 = C->hbuild[1];
+    H.hbuild = odd ? hb1 : hb0;
     return H;
 }
 
@@ -205,6 +210,21 @@ struct Params {
     const int4 *allhrec;         // chunk records of every heavy row
     int32_t allhchunks;
     uint32_t *hhit;              // [m] heavy row holds a changed variable (scan rounds)
+    // Incremental heavy rows (one plain vector): the exact finite parts of
+    // each heavy row's min and max activity live in carry-save fixed-point
+    // accumulators that every accepted bound change corrects (its old term
+    // out, its new term in, both exact), so a queued heavy row is tested
+    // without reading its nonzeros.  The round after a scan-seeding update,
+    // and the first round, rebuild them from the bounds instead.
+    int32_t inc;                 // enabled
+    int32_t nheavy;              // heavy rows
+    long long *hacc;             // [nheavy][2][HL] limbs (min side, max side)
+    int32_t *hinf;               // [nheavy][2] infinite contributions
+    unsigned long long *hwid;    // [nheavy] slack-filter width bound (bits of a double >= 0)
+    const int32_t *hidx;         // [m] heavy index of a row, -1 for the others
+    const double *cval;          // [nnz] coefficients in column order
+    double2 *hact;               // [nheavy] the round's rounded (min, max) finite parts
+    uint32_t inc_max;            // changed entries from which the next round rebuilds
 };
 
 // Exact activities of a heavy row at the base bounds: each finite part as a
@@ -461,6 +481,145 @@ __device__ __noinline__ double exact_side(const DInst &I, const BView bnd, int64
         if (!isinf(bb)) sa_add(S, a * bb);
     }
     return canon0(sa_round(S));
+}
+
+// Carry-save form of the exact fixed-point accumulator: HL signed 64-bit
+// limbs, limb j holding multiples of 2^(32 j - 1074).  A double is placed as
+// the exact accumulator places it (mantissa at bit `pos`) and split into
+// three 32-bit pieces added to consecutive limbs, so concurrent integer
+// atomics build the exact sum in any order.
+constexpr int HL = 2 * SA_WORDS;
+
+// The three signed pieces of +-x and the limb of the first one.
+__device__ __forceinline__ void inc_pieces(double x, bool negate, int &d0, long long &q0, long long &q1,
+                                           long long &q2) {
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const bool neg = ((b >> 63) != 0) != negate;
+    const uint64_t be = (b >> 52) & 0x7FF;
+    uint64_t mant = b & ((1ull << 52) - 1);
+    int pos = 0;
+    if (be != 0) {
+        mant |= 1ull << 52;
+        pos = (int)be - 1;
+    }
+    d0 = pos >> 5;
+    const int sh = pos & 31;
+    const uint64_t lo = mant << sh;
+    const uint64_t hi = sh ? (mant >> (64 - sh)) : 0ull;
+    q0 = (long long)(lo & 0xffffffffull);
+    q1 = (long long)(lo >> 32);
+    q2 = (long long)hi;
+    if (neg) {
+        q0 = -q0;
+        q1 = -q1;
+        q2 = -q2;
+    }
+}
+
+__device__ __forceinline__ void inc_add(long long *L, double x, bool negate) {
+    if (x == 0.0) return;
+    int d0;
+    long long q0, q1, q2;
+    inc_pieces(x, negate, d0, q0, q1, q2);
+    if (q0) atomicAdd((unsigned long long *)&L[d0], (unsigned long long)q0);
+    if (q1) atomicAdd((unsigned long long *)&L[d0 + 1], (unsigned long long)q1);
+    if (q2) atomicAdd((unsigned long long *)&L[d0 + 2], (unsigned long long)q2);
+}
+
+// Wave form (reached by every lane): the pieces of the lanes whose first
+// limb is the same are summed across the wave first, so each distinct limb
+// position costs three atomics by one lane instead of one per lane.
+__device__ __forceinline__ void inc_add_wave(long long *L, double x, bool act) {
+    int d0 = 0;
+    long long q0 = 0, q1 = 0, q2 = 0;
+    act = act && x != 0.0;
+    if (act) inc_pieces(x, false, d0, q0, q1, q2);
+    uint64_t pend = __ballot(act);
+    while (pend) {
+        const int leader = __ffsll((long long)pend) - 1;
+        const int d = __shfl(d0, leader, 64);
+        const bool mine = act && d0 == d;
+        long long s0 = mine ? q0 : 0, s1 = mine ? q1 : 0, s2 = mine ? q2 : 0;
+#pragma unroll
+        for (int w = 1; w < 64; w <<= 1) {
+            s0 += __shfl_xor(s0, w, 64);
+            s1 += __shfl_xor(s1, w, 64);
+            s2 += __shfl_xor(s2, w, 64);
+        }
+        if (__lane_id() == leader) {
+            if (s0) atomicAdd((unsigned long long *)&L[d], (unsigned long long)s0);
+            if (s1) atomicAdd((unsigned long long *)&L[d + 1], (unsigned long long)s1);
+            if (s2) atomicAdd((unsigned long long *)&L[d + 2], (unsigned long long)s2);
+        }
+        pend &= ~__ballot(mine);
+        act = act && !mine;
+    }
+}
+
+// A bound change of one contribution: the term at the old bound out, the
+// term at the new one in (an infinite bound is counted instead).
+__device__ __forceinline__ void inc_move(long long *L, int32_t *ninf, double a, double bo, double bn) {
+    if (bo == bn) return;
+    if (isinf(bo)) atomicSub(ninf, 1);
+    else inc_add(L, a * bo, true);
+    if (isinf(bn)) atomicAdd(ninf, 1);
+    else inc_add(L, a * bn, false);
+}
+
+// Correctly rounded value of carry-save limbs held in LDS, by one lane
+// (destroys them).  Carries are propagated digit by digit; a negative sum
+// is negated; the 53 bits below the leading one, the next (guard) bit and
+// whether any lower bit is set then give the round-to-nearest-even result,
+// the same value the exact accumulator's rounding gives.
+// Only limbs [lo, hi] are nonzero (lo > hi: none): limbs below lo stay
+// zero, and since every limb is below 2^62 in magnitude the carries settle
+// within two limbs above hi, where the sign is read.
+__device__ double inc_round(long long *L, int lo, int hi) {
+    if (lo > hi) return 0.0;
+    const int last = min(HL - 1, hi + 2);
+    long long carry = 0;
+    for (int j = lo; j <= last; ++j) {
+        const long long t = L[j] + carry;
+        L[j] = t & 0xffffffffll;
+        carry = t >> 32;
+    }
+    const bool neg = carry < 0;
+    if (neg) {  // magnitude: the two's complement negation of the digits
+        long long borrow = 0;
+        for (int j = lo; j <= last; ++j) {
+            const long long t = -L[j] - borrow;
+            L[j] = t & 0xffffffffll;
+            borrow = t < 0 ? 1 : 0;
+        }
+    }
+    int T = last;
+    while (T >= lo && L[T] == 0) --T;
+    if (T < lo) return 0.0;
+    const uint64_t dT = (uint64_t)L[T];
+    const uint64_t d1 = T >= 1 ? (uint64_t)L[T - 1] : 0ull;
+    const uint64_t d2 = T >= 2 ? (uint64_t)L[T - 2] : 0ull;
+    const int b = 31 - __clz((int)(uint32_t)dT);  // leading bit within digit T
+    const int top = 32 * T + b;                     // in units of 2^-1074
+    double mag;
+    if (top <= 52) {  // below 2^53 units: exact (digits 0 and 1 only)
+        mag = ldexp((double)(T == 1 ? (dT << 32) | d1 : dT), -1074);
+    } else {
+        const uint64_t win = (d1 << 32) | d2;  // the two digits below digit T
+        uint64_t M = (dT << (52 - b)) | (win >> (b + 12));
+        const uint64_t guard = (win >> (b + 11)) & 1ull;
+        bool sticky = (win & ((1ull << (b + 11)) - 1ull)) != 0ull;
+        for (int j = T - 3; j >= lo && !sticky; --j) sticky = L[j] != 0;
+        int e = top - 52 - 1074;
+        if (guard && (sticky || (M & 1ull))) {
+            M += 1;
+            if (M == (1ull << 53)) {
+                M >>= 1;
+                e += 1;
+            }
+        }
+        mag = e > 971 ? __builtin_inf() : ldexp((double)M, e);
+    }
+    return canon0(neg ? -mag : mag);
 }
 
 __device__ __forceinline__ bool row_bad(const RowAct &R, double feastol) {
@@ -823,11 +982,116 @@ __device__ void heavy_chunk_activity(const Params &P, int par, uint32_t u, WgScr
     }
 }
 
+// Heavy chunk, rebuild of the incremental accumulators (one plain vector):
+// the chunk's exact terms at the current bounds are summed into workgroup
+// limbs and added to the row's accumulators (zeroed by the previous round's
+// end), with the infinite counts and the largest nonzero width.  Every heavy
+// row takes part, queued or not.  In a scan round the chunk also marks its
+// row when it holds a changed variable.
+__device__ void inc_build_chunk(const Params &P, int par, uint32_t u, bool scan) {
+    __shared__ long long L[2 * HL];
+    __shared__ int32_t ninf[2];
+    __shared__ unsigned long long wbits;
+    const int4 rec = P.allhrec[u];
+    const int k = rec.y, c = rec.z;
+    for (int j = threadIdx.x; j < 2 * HL; j += WG) L[j] = 0;
+    if (threadIdx.x == 0) {
+        ninf[0] = 0;
+        ninf[1] = 0;
+        wbits = 0ull;
+    }
+    __syncthreads();
+    const DInst &I = P.I;
+    const int64_t r0 = I.row_ptr[k], r1 = I.row_ptr[k + 1];
+    const int64_t p0 = r0 + (int64_t)c * P.heavy_chunk;
+    const int64_t p1 = min(r1, p0 + (int64_t)P.heavy_chunk);
+    const BView bnd = bview(P, 0, I.base);
+    int nmin = 0, nmax = 0;
+    double wmax = 0.0;
+    bool mine = false;
+    const int iters = (int)((p1 - p0 + WG - 1) / WG);  // uniform: whole waves add together
+    for (int it = 0; it < iters; ++it) {
+        const int64_t p = p0 + threadIdx.x + (int64_t)it * WG;
+        const bool in = p < p1;
+        double tmin = 0.0, tmax = 0.0;
+        if (in) {
+            const int i = I.col[p];
+            const double2 b = bnd[i];
+            const double a = I.val[p];
+            const double bmin = a > 0.0 ? b.x : b.y;
+            const double bmax = a > 0.0 ? b.y : b.x;
+            if (isinf(bmin)) nmin += 1;
+            else tmin = a * bmin;
+            if (isinf(bmax)) nmax += 1;
+            else tmax = a * bmax;
+            wmax = fmax(wmax, nz_width(a, b.x, b.y));
+            count_read(P, 0, i);
+            if (scan) mine = mine || scan_hit(P, par, i);
+        }
+        inc_add_wave(L, tmin, in);
+        inc_add_wave(L + HL, tmax, in);
+    }
+    if (nmin) atomicAdd(&ninf[0], nmin);
+    if (nmax) atomicAdd(&ninf[1], nmax);
+    if (wmax > 0.0) atomicMax(&wbits, (unsigned long long)__double_as_longlong(wmax));
+    if (scan && __syncthreads_or(mine) && threadIdx.x == 0) atomicOr(&P.hhit[k], 1u);
+    __syncthreads();
+    const int h = P.hidx[k];
+    long long *G = P.hacc + (size_t)h * 2 * HL;
+    for (int j = threadIdx.x; j < 2 * HL; j += WG)
+        if (L[j]) atomicAdd((unsigned long long *)&G[j], (unsigned long long)L[j]);
+    if (threadIdx.x == 0) {
+        if (ninf[0]) atomicAdd(&P.hinf[2 * h], ninf[0]);
+        if (ninf[1]) atomicAdd(&P.hinf[2 * h + 1], ninf[1]);
+        if (wbits) atomicMax(&P.hwid[h], wbits);
+    }
+}
+
+// The rounded finite parts of heavy row h from its accumulators, by the
+// whole workgroup: limbs staged in LDS, one lane per side rounds them.
+__device__ double2 inc_row_activity(const Params &P, int h) {
+    __shared__ long long L[2 * HL];
+    __shared__ double act[2];
+    __shared__ int range[4];  // lowest and highest nonzero limb of each side
+    if (threadIdx.x < 4) range[threadIdx.x] = (threadIdx.x & 1) ? -1 : HL;
+    __syncthreads();
+    for (int j = threadIdx.x; j < 2 * HL; j += WG) {
+        const long long v = P.hacc[(size_t)h * 2 * HL + j];
+        L[j] = v;
+        if (v) {
+            const int side = j >= HL ? 2 : 0, d = j >= HL ? j - HL : j;
+            atomicMin(&range[side], d);
+            atomicMax(&range[side + 1], d);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) act[0] = inc_round(L, range[0], range[1]);
+    if (threadIdx.x == 64) act[1] = inc_round(L + HL, range[2], range[3]);
+    __syncthreads();
+    const double2 r = make_double2(act[0], act[1]);
+    __syncthreads();  // L and act are reused by the next task
+    return r;
+}
+
+// Heavy row head (round without a rebuild): chunk 0 of each queued heavy
+// row rounds the row's accumulators once for all its chunks.
+__device__ void inc_head(const Params &P, int par, uint32_t u) {
+    const int4 rec = P.hrec[par][u];
+    const int s = rec.x, k = rec.y, c = rec.z;
+    if (c != 0) return;  // workgroup-uniform
+    if (threadIdx.x == 0) clear_rflag(P, s, k);
+    if (P.info[s].state != SLOT_ACTIVE) return;  // workgroup-uniform
+    const int h = P.hidx[k];
+    const double2 a = inc_row_activity(P, h);
+    if (threadIdx.x == 0) P.hact[h] = a;
+}
+
 // Heavy chunk, candidate part.  Every wave combines the row's partials
 // (lane l takes chunks l, l+64, ... in order, then a butterfly), certifies
 // the sums and tests the row; the chunk's nonzeros then give candidates.
 template <bool MULTI>
-__device__ void heavy_chunk_candidates(const Params &P, int par, uint32_t u, bool scan) {
+__device__ void heavy_chunk_candidates(const Params &P, int par, uint32_t u, bool scan,
+                                       bool rebuild) {
     const int4 rec = scan ? P.allhrec[u] : P.hrec[par][u];
     const int s = rec.x, k = rec.y, c = rec.z, nch = rec.w;
     if (P.info[s].state != SLOT_ACTIVE) return;  // workgroup-uniform
@@ -845,32 +1109,47 @@ __device__ void heavy_chunk_candidates(const Params &P, int par, uint32_t u, boo
     const int64_t r0 = I.row_ptr[k], r1 = I.row_ptr[k + 1];
     const double2 sd = I.side[k];
     const BView bnd = bview(P, s, I.base);
-    const uint32_t u0 = u - (uint32_t)c;
-    Acc A, B;
-    acc_zero(A);
-    acc_zero(B);
-    double wmax = 0.0;
-    for (int j = lane; j < nch; j += 64) {
-        Acc a = P.hpart[2 * (size_t)(u0 + j)], b = P.hpart[2 * (size_t)(u0 + j) + 1];
-        acc_merge(A, a.s, a.c, a.e, a.ninf);
-        acc_merge(B, b.s, b.c, b.e, b.ninf);
-        wmax = fmax(wmax, P.hrng[u0 + j]);
-    }
-    acc_group_reduce<64>(A);
-    acc_group_reduce<64>(B);
     RowAct R;
     R.minfin = 0.0;
     R.maxfin = 0.0;
-    R.nmin = A.ninf;
-    R.nmax = B.ninf;
-    R.rng = group_max<64>(wmax);
     R.lo = sd.x;
     R.hi = sd.y;
-    bool ok_min = !P.force_exact && acc_certify(A, R.minfin);
-    bool ok_max = !P.force_exact && acc_certify(B, R.maxfin);
-    if (lane == 0) {
-        if (!ok_min) R.minfin = exact_side(I, bnd, r0, r1, false);
-        if (!ok_max) R.maxfin = exact_side(I, bnd, r0, r1, true);
+    if (P.inc) {
+        // incremental accumulators: exact sums rounded once, by the row's
+        // head in the row kernel, or here in a rebuild round (the row
+        // kernel built them); the stored width bounds the current one
+        // (bounds only shrink)
+        const int h = P.hidx[k];
+        if (c == 0 && threadIdx.x == 0 && !scan) clear_rflag(P, s, k);
+        R.nmin = P.hinf[2 * h];
+        R.nmax = P.hinf[2 * h + 1];
+        R.rng = __longlong_as_double((long long)P.hwid[h]);
+        const double2 a = rebuild ? inc_row_activity(P, h) : P.hact[h];
+        R.minfin = a.x;
+        R.maxfin = a.y;
+    } else {
+        const uint32_t u0 = u - (uint32_t)c;
+        Acc A, B;
+        acc_zero(A);
+        acc_zero(B);
+        double wmax = 0.0;
+        for (int j = lane; j < nch; j += 64) {
+            Acc a = P.hpart[2 * (size_t)(u0 + j)], b = P.hpart[2 * (size_t)(u0 + j) + 1];
+            acc_merge(A, a.s, a.c, a.e, a.ninf);
+            acc_merge(B, b.s, b.c, b.e, b.ninf);
+            wmax = fmax(wmax, P.hrng[u0 + j]);
+        }
+        acc_group_reduce<64>(A);
+        acc_group_reduce<64>(B);
+        R.nmin = A.ninf;
+        R.nmax = B.ninf;
+        R.rng = group_max<64>(wmax);
+        bool ok_min = !P.force_exact && acc_certify(A, R.minfin);
+        bool ok_max = !P.force_exact && acc_certify(B, R.maxfin);
+        if (lane == 0) {
+            if (!ok_min) R.minfin = exact_side(I, bnd, r0, r1, false);
+            if (!ok_max) R.maxfin = exact_side(I, bnd, r0, r1, true);
+        }
     }
     R.minfin = __shfl(R.minfin, 0, 64);
     R.maxfin = __shfl(R.maxfin, 0, 64);
@@ -1064,7 +1343,11 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(BP_ROWS
     for (int b = 0; b < NBIN; ++b)
         qc[b] = scan ? (uint32_t)(P.allstart[b + 1] - P.allstart[b]) : H.qcount[b];
     const uint32_t C_ghchunks = scan ? 0u : H.ghchunks;
-    const uint32_t C_hchunks = scan ? (uint32_t)P.allhchunks : H.hchunks;
+    // Heavy chunks: partial states of the queued chunks, or, with
+    // incremental accumulators, every chunk in a rebuild round and none
+    // otherwise.
+    const uint32_t C_hchunks = P.inc ? (H.hbuild ? (uint32_t)P.allhchunks : H.hchunks)
+                                     : (scan ? (uint32_t)P.allhchunks : H.hchunks);
     unsigned long long sc_rows = 0, sc_nnz = 0;
     // Work units: grouped heavy chunk tasks (four per unit, one per wave),
     // heavy chunks, block rows, then light bins 10..0.
@@ -1084,7 +1367,9 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(BP_ROWS
             const uint32_t t = u * (WG / 64) + (threadIdx.x >> 6);
             if (t < ngh) gh_chunk_corrections(P, par, t);
         } else if (u < start[1]) {
-            heavy_chunk_activity<MULTI>(P, par, u - start[0], W, scan);
+            if (P.inc && H.hbuild) inc_build_chunk(P, par, u - start[0], scan);
+            else if (P.inc) inc_head(P, par, u - start[0]);
+            else heavy_chunk_activity<MULTI>(P, par, u - start[0], W, scan);
         } else if (u < start[2]) {
             block_row<MULTI>(P, P.q[par][BIN_BLOCK], u - start[1], W,
                              scan ? P.allrows + P.allstart[BIN_BLOCK] : nullptr, par, sc_rows, sc_nnz);
@@ -1132,7 +1417,7 @@ __global__ void __launch_bounds__(WG) k_heavy(Params P) {
             const uint32_t t = u * (WG / 64) + (threadIdx.x >> 6);
             if (t < ngh) gh_chunk_candidates<MULTI>(P, par, t);
         } else {
-            heavy_chunk_candidates<MULTI>(P, par, u - gh_units, scan);
+            heavy_chunk_candidates<MULTI>(P, par, u - gh_units, scan, P.inc && H.hbuild);
         }
     }
 }
@@ -1209,11 +1494,15 @@ __device__ __forceinline__ void append_rows(const Params &P, int par, bool first
 // of the whole wave are walked 64 at a time.  A row is queued once per
 // slot: the first lane to set its bit in the slot's row bitmap appends it.
 // With count == false the slot counters are left alone and the wave totals
-// (rows, nonzeros) are returned instead.  Reached by every lane of the wave.
+// (rows, nonzeros) are returned instead.  With incremental heavy rows, the
+// lane's bound change (old bl/bu, new nl/nu) also corrects the accumulators
+// of every heavy row of its column.  Reached by every lane of the wave.
 template <bool MULTI>
 __device__ void enqueue_columns(const Params &P, int par, bool want, int s, long long c0,
                                 uint32_t len, bool count = true, uint32_t *rows_out = nullptr,
-                                unsigned long long *nnz_out = nullptr) {
+                                unsigned long long *nnz_out = nullptr, bool correct = false,
+                                double bl = 0.0, double bu = 0.0, double nl = 0.0,
+                                double nu = 0.0) {
     uint32_t tot_rows = 0;
     unsigned long long tot_nnz = 0;
     const int lane = __lane_id();
@@ -1248,9 +1537,12 @@ __device__ void enqueue_columns(const Params &P, int par, bool want, int s, long
         int bin = 0;
         int64_t rlen = 0;
         bool first = false;
+        const double obl = __shfl(bl, lo, 64), obu = __shfl(bu, lo, 64);
+        const double onl = __shfl(nl, lo, 64), onu = __shfl(nu, lo, 64);
         if (has) {
             const DInst I = inst_of<MULTI>(P, os);
-            k = I.col_row[oc0 + (long long)(j - (oincl - olen))];
+            const long long e = oc0 + (long long)(j - (oincl - olen));
+            k = I.col_row[e];
             uint32_t bit = 1u << (k & 31);
             uint32_t *wp = &P.rflag[(size_t)os * P.srw + (k >> 5)];
             // Independent loads issued together.  Rows shared by many changed
@@ -1261,6 +1553,13 @@ __device__ void enqueue_columns(const Params &P, int par, bool want, int s, long
             int64_t rp0 = I.row_ptr[k], rp1 = I.row_ptr[k + 1];
             if ((cur & bit) == 0) first = (atomicOr(wp, bit) & bit) == 0;
             rlen = rp1 - rp0;
+            if (correct && bin == BIN_HEAVY) {
+                const double a = P.cval[e];
+                const int h = P.hidx[k];
+                long long *Lh = P.hacc + (size_t)h * 2 * HL;
+                inc_move(Lh, &P.hinf[2 * h], a, a > 0.0 ? obl : obu, a > 0.0 ? onl : onu);
+                inc_move(Lh + HL, &P.hinf[2 * h + 1], a, a > 0.0 ? obu : obl, a > 0.0 ? onu : onl);
+            }
         }
         if (count) {
             count_pending(P, first, os, first ? rlen : 0);
@@ -1299,6 +1598,7 @@ __global__ void __launch_bounds__(WG) k_end(Params P) {
     const uint32_t c_done = C->done, c_round = C->round, c_max_rounds = C->max_rounds;
     const uint32_t c_next_job = C->next_job, c_total_jobs = C->total_jobs;
     const uint32_t c_scan_go = C->scan_go;
+    const uint32_t c_hb0 = C->hbuild[0], c_hb1 = C->hbuild[1];
     const int s_first = threadIdx.x;
     SlotInfo first;
     if (s_first < P.nslots) first = P.info[s_first];
@@ -1373,6 +1673,13 @@ __global__ void __launch_bounds__(WG) k_end(Params P) {
         size_t words = (size_t)P.nslots * P.snw;
         for (size_t w = threadIdx.x; w < words; w += WG) P.touched[w] = 0u;
     }
+    // the next round rebuilds the heavy-row accumulators: start from zero
+    if (P.inc && (par ? c_hb0 : c_hb1)) {
+        const size_t nl = (size_t)P.nheavy * 2 * HL;
+        for (size_t w = threadIdx.x; w < nl; w += WG) P.hacc[w] = 0;
+        for (int w = threadIdx.x; w < 2 * P.nheavy; w += WG) P.hinf[w] = 0;
+        for (int w = threadIdx.x; w < P.nheavy; w += WG) P.hwid[w] = 0ull;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int b = 0; b < NBIN; ++b) C->qcount[par][b] = 0;
@@ -1390,6 +1697,7 @@ __global__ void __launch_bounds__(WG) k_end(Params P) {
             }
             C->scan[par] = 0;
             C->scan_go = 0;
+            C->hbuild[par] = 0;
         }
         C->active = s_active;
         C->finished = s_finished;
@@ -1420,6 +1728,9 @@ __global__ void __launch_bounds__(WG) k_apply(Params P) {
     // update makes the next round scan every row instead of queueing rows.
     const bool scan_now = P.scan_ok && (par ? c_scan1 : c_scan0) && !c_done;
     const bool scan_next = P.scan_ok && total >= P.scan_min;
+    // many changes: the next round rebuilds the heavy-row accumulators
+    // rather than taking that many corrections
+    const bool rebuild_next = P.inc && (scan_next || total >= P.inc_max);
     if (scan_now) {
         const size_t g = (size_t)blockIdx.x * WG + threadIdx.x, G = (size_t)gridDim.x * WG;
         for (size_t w = g; w < (size_t)P.snw; w += G) P.cbits[(size_t)par * P.snw + w] = 0u;
@@ -1442,6 +1753,7 @@ __global__ void __launch_bounds__(WG) k_apply(Params P) {
         bool go = false;
         long long c0 = 0;
         uint32_t clen = 0;
+        double ol = 0.0, ou = 0.0, wl = 0.0, wu = 0.0;  // old and written bounds
         if (has) {
             int st = 0;
 #pragma unroll
@@ -1475,6 +1787,10 @@ __global__ void __launch_bounds__(WG) k_apply(Params P) {
                     *bp = make_double2(nl, nu);
                     go = true;
                     if (P.overlay) mark_dirty(P, s, i);
+                    ol = b.x;
+                    ou = b.y;
+                    wl = nl;
+                    wu = nu;
                 }
             }
         }
@@ -1487,7 +1803,8 @@ __global__ void __launch_bounds__(WG) k_apply(Params P) {
             w_written += (unsigned long long)__popcll(wm);
             uint32_t r = 0;
             unsigned long long z = 0;
-            enqueue_columns<MULTI>(P, npar, go, s, c0, clen, false, &r, &z);
+            enqueue_columns<MULTI>(P, npar, go, s, c0, clen, false, &r, &z, P.inc && !rebuild_next, ol, ou,
+                                   wl, wu);
             w_rows += r;
             w_nnz += z;
         } else {
@@ -1519,6 +1836,9 @@ __global__ void __launch_bounds__(WG) k_apply(Params P) {
             if (w) atomicAdd(&C->stat_written, w);
             if (scan_next && w) C->scan_go = 1u;
             if (scan_next && blockIdx.x == 0) C->scan[npar] = 1u;
+            // a scan-seeding update leaves the heavy-row accumulators to a
+            // rebuild in the next round
+            if (rebuild_next && blockIdx.x == 0) C->hbuild[npar] = 1u;
         }
     }
 }

@@ -33,6 +33,12 @@ static std::string tune_key(const bp_instance *h) {
     return os.str();
 }
 
+// Schedules the engine supports; a cache line outside them is ignored.
+static bool tuning_valid(const bp_tuning &t) {
+    return t.heavy_threshold >= 1024 && t.heavy_chunk >= WG && t.heavy_chunk % WG == 0 &&
+           t.rounds_per_launch >= 1 && t.probe_slots >= 0;
+}
+
 static bool tune_lookup(const char *path, const std::string &key, bp_tuning *t) {
     if (!path) return false;
     std::ifstream f(path);
@@ -46,7 +52,7 @@ static bool tune_lookup(const char *path, const std::string &key, bp_tuning *t) 
         memset(&x, 0, sizeof(x));
         if (!(is >> k >> x.heavy_threshold >> x.heavy_chunk >> x.rounds_per_launch >> x.probe_slots >> x.ms))
             continue;
-        if (k == key) {
+        if (k == key && tuning_valid(x)) {
             *t = x;
             found = true;  // the last entry for a key wins
         }
@@ -64,6 +70,7 @@ static void tune_store(const char *path, const std::string &key, const bp_tuning
 }
 
 static int tune_apply(bp_instance *h, const bp_tuning &t, hipStream_t st) {
+    if (!tuning_valid(t)) return fail(BP_EINVAL, "tuning outside the supported schedule range");
     h->opt.heavy_threshold = t.heavy_threshold;
     h->opt.heavy_chunk = t.heavy_chunk;
     h->opt.rounds_per_launch = t.rounds_per_launch;

@@ -1,0 +1,148 @@
+"""Incremental activities of heavy rows (bp_propagate of one vector): the
+exact sums of each heavy row are corrected by every accepted bound change
+instead of being recomputed from the row's nonzeros.  Outcome, rounds,
+propagated nonzeros, evidence and bounds must match the oracle, and be
+bit-identical to the full recomputation (BP_FLAG_FULL_ROWS)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import assert_same, bp, gpu_propagate
+from paper_2510_20499_amd import gen
+
+pytestmark = pytest.mark.gpu
+INF = math.inf
+
+
+def _dense_instance(seed, n=3000, dense=4, m_short=2500, frac_inf=0.25):
+    """A few rows longer than the smallest heavy threshold (1024) with mixed
+    signs and sides close to their activity range, so that they tighten
+    bounds and are not filtered as quiet; many short rows; a quarter of the
+    variables with one infinite bound, tightened to finite values as the
+    rounds go."""
+    rng = np.random.default_rng(seed)
+    vtype = (rng.random(n) < 0.6).astype(np.uint8)
+    lb = np.where(vtype == 1, 0.0, -50.0)
+    ub = np.where(vtype == 1, rng.integers(1, 11, n).astype(float), 50.0)
+    inf = rng.random(n) < frac_inf
+    side = rng.random(n) < 0.5
+    lb[inf & side] = -INF
+    ub[inf & ~side] = INF
+    x = np.where(np.isfinite(lb), lb, ub - 3.0) + rng.random(n) * 2.0  # a point the rows keep
+    x = np.where(vtype == 1, np.clip(np.round(x), lb, ub), np.clip(x, lb, ub))
+    rows, lo, hi = [], [], []
+    for _ in range(dense):
+        L = int(rng.integers(1100, 2600))
+        cols = np.sort(rng.choice(n, size=L, replace=False))
+        vals = rng.choice([-1.0, 1.0], L) * rng.uniform(0.5, 4.0, L)
+        act = float(vals @ x[cols])
+        rows.append((cols, vals))
+        lo.append(act - rng.uniform(1.0, 20.0) if rng.random() < 0.5 else -INF)
+        hi.append(act + rng.uniform(1.0, 20.0))
+    for _ in range(m_short):
+        L = int(rng.integers(2, 7))
+        cols = np.sort(rng.choice(n, size=L, replace=False))
+        vals = rng.choice([-1.0, 1.0], L) * rng.integers(1, 6, L).astype(float)
+        act = float(vals @ x[cols])
+        rows.append((cols, vals))
+        lo.append(act - rng.uniform(0.0, 3.0) if rng.random() < 0.3 else -INF)
+        hi.append(act + rng.uniform(0.0, 3.0))
+    return gen.from_rows(n, rows, lo, hi, vtype, lb, ub)
+
+
+def _orc(o):
+    return oracle.Options(feastol=o.feastol, inttol=o.inttol, tau=o.tau, max_rounds=o.max_rounds)
+
+
+def _three_ways(inst, lb=None, ub=None, changed=None, what="", **kw):
+    """Incremental, full recomputation and the oracle on the same input."""
+    o_inc = bp().default_options(heavy_threshold=1024, **kw)
+    o_full = bp().default_options(heavy_threshold=1024, **kw)
+    o_full.flags |= bp().FLAG_FULL_ROWS
+    ri, li, ui = gpu_propagate(bp().Instance(inst, o_inc), inst, lb, ub, changed)
+    rf, lf, uf = gpu_propagate(bp().Instance(inst, o_full), inst, lb, ub, changed)
+    ro, lo, uo = oracle.propagate(inst, lb, ub, changed=changed, opts=_orc(o_inc))
+    assert_same(inst, ri, li, ui, ro, lo, uo, what + " incremental")
+    assert ri == rf, (what, ri, rf)
+    if ri["status"] != bp().BP_INFEASIBLE:
+        assert np.array_equal(li.view(np.int64), lf.view(np.int64)), what
+        assert np.array_equal(ui.view(np.int64), uf.view(np.int64)), what
+    return ri, li, ui
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_dense_rows_cold(seed):
+    inst = _dense_instance(seed)
+    assert (np.diff(inst["row_ptr"]) > 1024).sum() >= 3
+    r, _, _ = _three_ways(inst, what="dense%d" % seed)
+    assert r["rounds"] >= 2
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_dense_rows_warm_fixings(seed):
+    """Warm starts from the oracle's fixed point with a few variables fixed:
+    the first round builds the accumulators, later rounds correct them."""
+    inst = _dense_instance(10 + seed)
+    r0, lb, ub = oracle.propagate(inst)
+    if r0["status"] != oracle.BP_OK:
+        pytest.skip("infeasible root")
+    rng = np.random.default_rng(seed)
+    ints = np.nonzero((inst["vtype"] == 1) & (lb < ub) & np.isfinite(lb) & np.isfinite(ub))[0]
+    for count in (1, 5, 40):
+        pick = np.sort(rng.choice(ints, size=min(count, ints.size), replace=False)).astype(np.int32)
+        l2, u2 = lb.copy(), ub.copy()
+        v = np.round(rng.uniform(lb[pick], ub[pick]))
+        l2[pick] = v
+        u2[pick] = v
+        _three_ways(inst, l2, u2, pick, what="warm%d/%d" % (seed, count))
+
+
+@pytest.mark.parametrize("max_rounds", [1, 2, 3, 7])
+def test_round_limit(max_rounds):
+    inst = _dense_instance(21)
+    _three_ways(inst, what="limit%d" % max_rounds, max_rounds=max_rounds)
+
+
+def test_force_exact_with_incremental_rows():
+    inst = _dense_instance(22)
+    o = bp().default_options(heavy_threshold=1024)
+    o.flags |= bp().FLAG_FORCE_EXACT
+    r, l, u = gpu_propagate(bp().Instance(inst, o), inst)
+    ro, lo, uo = oracle.propagate(inst)
+    assert_same(inst, r, l, u, ro, lo, uo, "force-exact")
+
+
+@pytest.mark.parametrize("scale,chunk", [(0.05, 256), (0.2, 1024)])
+def test_single_workload_scaled_many_heavy_rows(scale, chunk):
+    """Scan rounds (large first updates) rebuild the accumulators; later
+    rounds correct them; many chunks per row."""
+    inst = gen.make("single", 3, scale=scale)
+    _three_ways(inst, what="single %.2f" % scale, heavy_chunk=chunk)
+
+
+def test_infeasible_after_fixings():
+    inst = _dense_instance(30)
+    r0, lb, ub = oracle.propagate(inst)
+    if r0["status"] != oracle.BP_OK:
+        pytest.skip("infeasible root")
+    ints = np.nonzero((inst["vtype"] == 1) & (lb < ub) & np.isfinite(ub))[0][:400].astype(np.int32)
+    l2, u2 = lb.copy(), ub.copy()
+    l2[ints] = ub[ints]
+    r, _, _ = _three_ways(inst, l2, ub.copy(), ints, what="infeasible")
+    assert r["status"] in (bp().BP_INFEASIBLE, bp().BP_OK)
+
+
+def test_repeated_calls_reuse_the_engine():
+    """Accumulators start from zero in every call (cold after warm, warm
+    after cold)."""
+    inst = _dense_instance(40)
+    I = bp().Instance(inst, bp().default_options(heavy_threshold=1024))
+    ro, lo, uo = oracle.propagate(inst)
+    for _ in range(3):
+        r, l, u = gpu_propagate(I, inst)
+        assert_same(inst, r, l, u, ro, lo, uo, "repeat")
+        if ro["status"] == oracle.BP_OK:
+            r2, l2, u2 = gpu_propagate(I, inst, lo, uo, np.zeros(0, np.int32))
+            assert r2["rounds"] == 0

@@ -56,3 +56,14 @@ def test_autotune_and_cache():
             assert t2[key] == t[key]
         r2, lg2, ug2 = gpu_propagate(I2, inst)
         assert_same(inst, r2, lg2, ug2, ro, lo, uo, "cached")
+        # later lines for the same key with schedules the engine does not
+        # support (zero or unaligned chunks, a tiny threshold) are ignored
+        with open(path) as f:
+            key = f.readline().split()[0]
+        with open(path, "a") as f:
+            f.write("%s 4096 0 8 512 1.0\n%s 4096 300 8 512 1.0\n%s 16 1024 8 512 1.0\n" % (key, key, key))
+        I3 = bp().Instance(inst)
+        t3 = I3.autotune(lb, ub, dev(vs, torch.int32), cache_path=path)
+        assert t3["from_cache"]
+        for k in ("heavy_threshold", "heavy_chunk", "rounds_per_launch", "probe_slots"):
+            assert t3[k] == t[k]
