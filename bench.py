@@ -36,10 +36,11 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E datasheet peak
 # belongs to the kernel sources it was measured on: when any of them
 # differs, the bench line reports null.
 K_ROWS_TRAFFIC = {
-    "fetch_kib": 10631.9, "write_kib": 232.8, "fetch_scale": 2.0, "write_scale": 1.0,
+    "fetch_kib": 1855.3, "write_kib": 191.7, "fetch_scale": 2.0, "write_scale": 1.0,
     "sources": {
-        "paper_2510_20499_amd/csrc/bp_kernels.h": "b3dce6ec8e33d54df3e97735097f2c6ee742e7b990bf9660d258063492669c59",
+        "paper_2510_20499_amd/csrc/bp_kernels.h": "b020fa7d1ed668caddf145c25f9b78cad3ae7513dbda9bc10b3d23615efdaa9d",
         "paper_2510_20499_amd/csrc/bp_sum.h": "833f834eb740e1aaeae0a7fe22dd2566f3b231f64aa197bf2945502c9275c3e9",
+        "paper_2510_20499_amd/csrc/bp_engine.hip": "64bd69e455c51d169651a8c3dbafac3f2f553250292139b814559e6c2433ca96",
         "paper_2510_20499_amd/build.py": "2b907a883848d04e156f5dd7ba1f49df479651c7e7c715a833f348226ba0bcb8",
     },
 }
@@ -74,7 +75,10 @@ def kernel_roofline(bp, inst, call, reps=5, **opt):
     Bytes: what the method must move per launch -- 12 B per nonzero (int32
     column + f64 coefficient), 24 B per row (row pointer + two sides), 16 B
     per distinct bound record read -- counted by an instrumented run of the
-    same call and divided by the launches per call."""
+    same call and divided by the launches per call.  A queued heavy row
+    tested from its incremental accumulators costs their 2 x 68 limbs
+    (1088 B) instead, and its nonzeros count only when its candidates had
+    to read them."""
     Ic = bp.Instance(inst, bp.default_options(flags=bp.FLAG_COUNT_VARS, **opt))
     call(Ic)
     cs = Ic.kernel_stats(reset=True)
@@ -87,7 +91,8 @@ def kernel_roofline(bp, inst, call, reps=5, **opt):
     ts = It.kernel_stats(reset=True)
     del It
     launches = ts["launches"] / reps
-    alg_bytes_per_call = 12 * cs["nnz"] + 24 * cs["rows"] + 16 * cs["vars_read"]
+    alg_bytes_per_call = (12 * (cs["nnz"] - cs["nnz_kept"]) + 24 * cs["rows"] + 16 * cs["vars_read"]
+                          + 1088 * cs["rows_kept"])
     bytes_per_launch = alg_bytes_per_call / max(launches, 1)
     avg_launch_ms = ts["ms"] / max(ts["launches"], 1)
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9

@@ -155,6 +155,10 @@ typedef struct {
     int64_t vars_read;    /* distinct (vector, variable) bound records read per
                              round, summed over rounds */
     int64_t vars_written; /* bound records written (accepted changes) */
+    int64_t rows_kept;    /* queued heavy rows of a single vector tested from
+                             their incremental accumulators (BP_FLAG_COUNT_VARS) */
+    int64_t nnz_kept;     /* nonzeros of those rows never read in their round
+                             (no candidates were needed; BP_FLAG_COUNT_VARS) */
 } bp_stats;
 
 /* Fill *opt with the defaults. */

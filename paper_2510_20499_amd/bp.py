@@ -60,7 +60,8 @@ class ProbeOut(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("ms", C.c_double), ("launches", C.c_int64), ("rows", C.c_int64),
-                ("nnz", C.c_int64), ("vars_read", C.c_int64), ("vars_written", C.c_int64)]
+                ("nnz", C.c_int64), ("vars_read", C.c_int64), ("vars_written", C.c_int64),
+                ("rows_kept", C.c_int64), ("nnz_kept", C.c_int64)]
 
 
 class Request(C.Structure):
@@ -385,7 +386,8 @@ class Instance:
         s = Stats()
         _check(_LIB.bp_kernel_stats(self._h, C.byref(s), 1 if reset else 0))
         return dict(ms=s.ms, launches=s.launches, rows=s.rows, nnz=s.nnz,
-                    vars_read=s.vars_read, vars_written=s.vars_written)
+                    vars_read=s.vars_read, vars_written=s.vars_written,
+                    rows_kept=s.rows_kept, nnz_kept=s.nnz_kept)
 
 
 class Server:

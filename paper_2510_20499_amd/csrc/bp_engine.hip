@@ -773,6 +773,8 @@ static int run_rounds(bp_instance *h, const Params &P, const JobIO *io, int64_t 
     h->stats.nnz += (int64_t)hc.stat_nnz;
     h->stats.vars_read += (int64_t)hc.stat_vars;
     h->stats.vars_written += (int64_t)hc.stat_written;
+    h->stats.rows_kept += (int64_t)hc.stat_kept_rows;
+    h->stats.nnz_kept += (int64_t)hc.stat_kept_nnz;
     return 0;
 }
 

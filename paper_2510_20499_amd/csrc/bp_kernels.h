@@ -106,6 +106,8 @@ struct Ctl {
     unsigned long long stat_nnz;     // their nonzeros
     unsigned long long stat_vars;    // distinct bound records read per round
     unsigned long long stat_written; // accepted bound changes
+    unsigned long long stat_kept_rows;  // queued heavy rows tested from their accumulators
+    unsigned long long stat_kept_nnz;   // nonzeros of those rows left unread (no candidates)
     // scan rounds of one vector (see Params::scan_ok)
     uint32_t scan[2];                // the round of this parity scans every row
     uint32_t scan_go;                // a bound moved in the last scan-seeding bound update
@@ -1153,13 +1155,20 @@ __device__ void heavy_chunk_candidates(const Params &P, int par, uint32_t u, boo
     }
     R.minfin = __shfl(R.minfin, 0, 64);
     R.maxfin = __shfl(R.maxfin, 0, 64);
-    if (row_bad(R, P.feastol)) {  // uniform across the workgroup
+    int64_t p0 = r0 + (int64_t)c * P.heavy_chunk;
+    int64_t p1 = min(r1, p0 + (int64_t)P.heavy_chunk);
+    const bool bad = row_bad(R, P.feastol), quiet = !bad && row_quiet(R);  // uniform
+    if (P.touched && P.inc && !rebuild && threadIdx.x == 0) {
+        // byte accounting: the row was tested from its accumulators, and
+        // without candidates its nonzeros are not read at all
+        if (c == 0) atomicAdd(&P.ctl->stat_kept_rows, 1ull);
+        if (bad || quiet) atomicAdd(&P.ctl->stat_kept_nnz, (unsigned long long)(p1 - p0));
+    }
+    if (bad) {
         if (c == 0 && threadIdx.x == 0) report_bad_row(P, s, k);
         return;
     }
-    if (row_quiet(R)) return;  // uniform across the workgroup
-    int64_t p0 = r0 + (int64_t)c * P.heavy_chunk;
-    int64_t p1 = min(r1, p0 + (int64_t)P.heavy_chunk);
+    if (quiet) return;
     const int iters = (int)((p1 - p0 + WG - 1) / WG);
     for (int it = 0; it < iters; ++it) {
         int64_t p = p0 + threadIdx.x + (int64_t)it * WG;
