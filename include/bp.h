@@ -145,8 +145,9 @@ typedef struct {
 typedef struct bp_instance bp_instance;
 
 /* Counters since load or the last reset.  ms and launches cover the
- * activity kernel (k_rows) when BP_FLAG_TIME_KERNELS is set; the other
- * fields are kept always except vars_read (BP_FLAG_COUNT_VARS). */
+ * activity kernel (k_rows) and apply_ms the bound-update kernel (k_apply)
+ * when BP_FLAG_TIME_KERNELS is set; vars_read, the kept-row counts and the
+ * apply_* counts need BP_FLAG_COUNT_VARS; the other fields are kept always. */
 typedef struct {
     double ms;            /* summed HIP-event time of the activity kernel */
     int64_t launches;     /* activity-kernel launches timed */
@@ -159,6 +160,10 @@ typedef struct {
                              their incremental accumulators (BP_FLAG_COUNT_VARS) */
     int64_t nnz_kept;     /* nonzeros of those rows never read in their round
                              (no candidates were needed; BP_FLAG_COUNT_VARS) */
+    double apply_ms;        /* summed HIP-event time of the bound-update kernel */
+    int64_t apply_entries;  /* changed-list entries it took */
+    int64_t apply_colent;   /* column entries it walked for accepted changes */
+    int64_t apply_corr;     /* heavy-row accumulator corrections it made */
 } bp_stats;
 
 /* Fill *opt with the defaults. */

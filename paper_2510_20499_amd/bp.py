@@ -61,7 +61,8 @@ class ProbeOut(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("ms", C.c_double), ("launches", C.c_int64), ("rows", C.c_int64),
                 ("nnz", C.c_int64), ("vars_read", C.c_int64), ("vars_written", C.c_int64),
-                ("rows_kept", C.c_int64), ("nnz_kept", C.c_int64)]
+                ("rows_kept", C.c_int64), ("nnz_kept", C.c_int64), ("apply_ms", C.c_double),
+                ("apply_entries", C.c_int64), ("apply_colent", C.c_int64), ("apply_corr", C.c_int64)]
 
 
 class Request(C.Structure):
@@ -387,7 +388,9 @@ class Instance:
         _check(_LIB.bp_kernel_stats(self._h, C.byref(s), 1 if reset else 0))
         return dict(ms=s.ms, launches=s.launches, rows=s.rows, nnz=s.nnz,
                     vars_read=s.vars_read, vars_written=s.vars_written,
-                    rows_kept=s.rows_kept, nnz_kept=s.nnz_kept)
+                    rows_kept=s.rows_kept, nnz_kept=s.nnz_kept, apply_ms=s.apply_ms,
+                    apply_entries=s.apply_entries, apply_colent=s.apply_colent,
+                    apply_corr=s.apply_corr)
 
 
 class Server:

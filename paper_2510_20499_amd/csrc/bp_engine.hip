@@ -159,12 +159,14 @@ struct bp_instance {
     DevBuf rd_mbox, rd_vk, rd_vl, rd_vu, rd_chg, rd_cpos, rd_bcnt;
     // stats
     bp_stats stats;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
     ~bp_instance() {
         eng.reset();
         lv.reset();
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
+        if (ev2) (void)hipEventDestroy(ev2);
+        if (ev3) (void)hipEventDestroy(ev3);
     }
 };
 
@@ -517,6 +519,8 @@ extern "C" int bp_load(const bp_sparse *csr, const bp_sparse *csc, const double 
     HIPTRY(hipStreamSynchronize(st));
     HIPTRY(hipEventCreate(&h->ev0));
     HIPTRY(hipEventCreate(&h->ev1));
+    HIPTRY(hipEventCreate(&h->ev2));
+    HIPTRY(hipEventCreate(&h->ev3));
     *out = h.release();
     return BP_OK;
 }
@@ -710,7 +714,8 @@ static int launch_round(bp_instance *h, const Params &P, const JobIO *io, hipStr
         k_rows<false><<<GRID_ROWS, WG, 0, st>>>(P);
     }
     k_heavy<false><<<GRID_HEAVY, WG, 0, st>>>(P);
-    k_apply<false><<<GRID_APPLY, WG, 0, st>>>(P);
+    if (timed) hipExtLaunchKernelGGL(k_apply<false>, dim3(GRID_APPLY), dim3(WG), 0, st, h->ev2, h->ev3, 0, P);
+    else k_apply<false><<<GRID_APPLY, WG, 0, st>>>(P);
     k_end<<<1, WG, 0, st>>>(P);
     if (io) k_retire<false><<<std::min(P.nslots, 4096), WG, 0, st>>>(P, *io);
     HIPTRY(hipGetLastError());
@@ -736,6 +741,9 @@ static int run_rounds(bp_instance *h, const Params &P, const JobIO *io, int64_t 
                 HIPTRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
                 h->stats.ms += ms;
                 h->stats.launches += 1;
+                HIPTRY(hipEventSynchronize(h->ev3));
+                HIPTRY(hipEventElapsedTime(&ms, h->ev2, h->ev3));
+                h->stats.apply_ms += ms;
             }
         } else {
             if (!E.graph || E.graph_rounds != K) {
@@ -775,6 +783,9 @@ static int run_rounds(bp_instance *h, const Params &P, const JobIO *io, int64_t 
     h->stats.vars_written += (int64_t)hc.stat_written;
     h->stats.rows_kept += (int64_t)hc.stat_kept_rows;
     h->stats.nnz_kept += (int64_t)hc.stat_kept_nnz;
+    h->stats.apply_entries += (int64_t)hc.stat_apply_entries;
+    h->stats.apply_colent += (int64_t)hc.stat_apply_colent;
+    h->stats.apply_corr += (int64_t)hc.stat_apply_corr;
     return 0;
 }
 

@@ -108,6 +108,9 @@ struct Ctl {
     unsigned long long stat_written; // accepted bound changes
     unsigned long long stat_kept_rows;  // queued heavy rows tested from their accumulators
     unsigned long long stat_kept_nnz;   // nonzeros of those rows left unread (no candidates)
+    unsigned long long stat_apply_entries;  // changed-list entries the update kernel took
+    unsigned long long stat_apply_colent;   // column entries it walked for accepted changes
+    unsigned long long stat_apply_corr;     // heavy-row accumulator corrections it made
     // scan rounds of one vector (see Params::scan_ok)
     uint32_t scan[2];                // the round of this parity scans every row
     uint32_t scan_go;                // a bound moved in the last scan-seeding bound update
@@ -1513,7 +1516,7 @@ __device__ void enqueue_columns(const Params &P, int par, bool want, int s, long
                                 double bl = 0.0, double bu = 0.0, double nl = 0.0,
                                 double nu = 0.0) {
     uint32_t tot_rows = 0;
-    unsigned long long tot_nnz = 0;
+    unsigned long long tot_nnz = 0, tot_corr = 0;
     const int lane = __lane_id();
     if (!want) {
         c0 = 0;
@@ -1563,6 +1566,7 @@ __device__ void enqueue_columns(const Params &P, int par, bool want, int s, long
             if ((cur & bit) == 0) first = (atomicOr(wp, bit) & bit) == 0;
             rlen = rp1 - rp0;
             if (correct && bin == BIN_HEAVY) {
+                tot_corr += 1;
                 const double a = P.cval[e];
                 const int h = P.hidx[k];
                 long long *Lh = P.hacc + (size_t)h * 2 * HL;
@@ -1583,6 +1587,11 @@ __device__ void enqueue_columns(const Params &P, int par, bool want, int s, long
     }
     if (rows_out) *rows_out = tot_rows;
     if (nnz_out) *nnz_out = tot_nnz;
+    if (P.touched && correct) {  // byte accounting only
+#pragma unroll
+        for (int w = 1; w < 64; w <<= 1) tot_corr += __shfl_xor(tot_corr, w, 64);
+        if (lane == 0 && tot_corr) atomicAdd(&P.ctl->stat_apply_corr, tot_corr);
+    }
 }
 
 // Dirty tracking for jobs: first change of var i in slot s.
@@ -1804,6 +1813,16 @@ __global__ void __launch_bounds__(WG) k_apply(Params P) {
             }
         }
         uint64_t wm = __ballot(go);
+        if (P.touched) {  // byte accounting only
+            unsigned long long ce = go ? (unsigned long long)clen : 0ull;
+#pragma unroll
+            for (int w = 1; w < 64; w <<= 1) ce += __shfl_xor(ce, w, 64);
+            const unsigned long long ne = (unsigned long long)__popcll(__ballot(has));
+            if (lane == 0) {
+                atomicAdd(&C->stat_apply_entries, ne);
+                if (!scan_next && ce) atomicAdd(&C->stat_apply_colent, ce);
+            }
+        }
         if (scan_next) {
             // the next round scans every row for these variables
             w_written += (unsigned long long)__popcll(wm);
