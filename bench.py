@@ -71,8 +71,9 @@ def fresh(*ts):
     return tuple(t.clone() for t in ts)
 
 
-def kernel_roofline(bp, inst, call, reps=5, **opt):
-    """Roofline of the activity kernel k_rows for one call `call(I)`.
+def kernel_roofline(bp, inst, call, reps=5, kernel="k_rows", **opt):
+    """Roofline of the activity kernel (k_rows, or k_lv_rows for batches of
+    one vector per lane) for one call `call(I)`.
 
     Time: HIP events recorded around each k_rows launch (rounds driven from
     the host so every launch is bracketed), averaged over `reps` calls.
@@ -102,7 +103,7 @@ def kernel_roofline(bp, inst, call, reps=5, **opt):
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
     out = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 5), "traffic": None,
-           "kernel": "k_rows", "avg_launch_us": round(avg_launch_ms * 1e3, 3),
+           "kernel": kernel, "avg_launch_us": round(avg_launch_ms * 1e3, 3),
            "launches_per_call": launches, "alg_bytes_per_launch": int(bytes_per_launch)}
     if ts.get("apply_ms", 0.0) > 0.0:
         # k_apply: per changed-list entry 73 B (entry, candidate keys read and
@@ -602,7 +603,7 @@ def bench_bulk(args, bp, gen, torch, np):
             nnz_p += r1[0]["nnz_propagated"]
             assert r1[0] == res[v], (v, r1[0], res[v])
     log("bulk: plain %.2f ms per vector" % (tp / kp * 1e3))
-    roof = kernel_roofline(bp, inst, batch_call, reps=2, **opt_kw)
+    roof = kernel_roofline(bp, inst, batch_call, reps=2, kernel="k_lv_rows", **opt_kw)
     return {
         "workload": "bulk rounding: m=%d, n=%d, nnz=%d; %d vectors per call, each fixing %d "
                     "integer variables (5%%) and propagating"
