@@ -572,9 +572,11 @@ static int engine_alloc(std::unique_ptr<Engine> &eng, const Shape &sh, int32_t s
     if (S == 1) {
         if ((rc = E->cbits.alloc((size_t)2 * nw_var * 4, B))) return rc;
         if ((rc = E->hhit.alloc((size_t)m * 4, B))) return rc;
-        if ((rc = E->allhrec.alloc((size_t)std::max<int64_t>(sh.heavy_chunks, 1) * sizeof(int4), B)))
-            return rc;
-        const int64_t H = std::max<int64_t>(sh.heavy_rows, 1);
+    }
+    if ((rc = E->allhrec.alloc((size_t)std::max<int64_t>(sh.heavy_chunks, 1) * sizeof(int4), B))) return rc;
+    if (sh.heavy_rows > 0) {
+        // incremental heavy rows of the first INC_SLOTS slots
+        const int64_t H = sh.heavy_rows * std::min<int64_t>(S, INC_SLOTS);
         if ((rc = E->hacc.alloc((size_t)H * 2 * HL * 8, B)) || (rc = E->hinf.alloc((size_t)H * 8, B)) ||
             (rc = E->hwid.alloc((size_t)H * 8, B)) || (rc = E->hact.alloc((size_t)H * 16, B)))
             return rc;
@@ -933,30 +935,42 @@ static int propagate_slots(bp_instance *h, int32_t Bv, double *lb, double *ub,
         P.hhit = E1.hhit.as<uint32_t>();
         P.allrows = h->cold_rows.as<int32_t>();
         for (int b = 0; b <= NBIN; ++b) P.allstart[b] = h->bin_start[b];
+        HIPTRY(hipMemsetAsync(E1.cbits.p, 0, E1.cbits.bytes, st));
+        HIPTRY(hipMemsetAsync(E1.hhit.p, 0, E1.hhit.bytes, st));
+    }
+    {
+        // every heavy chunk (the list scan rounds and accumulator rebuilds
+        // walk), and incremental heavy rows for one plain vector or a cold
+        // start of up to INC_SLOTS
+        Engine &E1 = *h->eng;
+        const int64_t nheavy = h->bin_count[BIN_HEAVY];
         P.allhrec = E1.allhrec.as<int4>();
         P.allhchunks = (int32_t)h->heavy_chunks;
-        const int64_t nheavy = h->bin_count[BIN_HEAVY];
-        if (nheavy > 0 && !(h->opt.flags & BP_FLAG_FULL_ROWS)) {
+        // The first round builds every heavy row of every vector: worth it
+        // for one vector, and for several on a cold start (where the first
+        // round reads every row anyway); several warm vectors, as in the
+        // rounding steps, recompute the few heavy rows they queue.
+        if (nheavy > 0 && Bv <= INC_SLOTS && (Bv == 1 || cold) && E1.hacc.p &&
+            !(h->opt.flags & BP_FLAG_FULL_ROWS)) {
+            const size_t nh = (size_t)nheavy * Bv;
             P.inc = 1;
             P.nheavy = (int32_t)nheavy;
+            P.inc_slots = Bv;
             P.hacc = E1.hacc.as<long long>();
             P.hinf = E1.hinf.as<int32_t>();
             P.hwid = E1.hwid.as<unsigned long long>();
             P.hidx = h->hidx_d.as<int32_t>();
             P.cval = h->col_val.as<double>();
             P.hact = E1.hact.as<double2>();
-            P.inc_max = (uint32_t)std::max<int64_t>(64, h->n / BP_INC_DIV);
-            HIPTRY(hipMemsetAsync(E1.hacc.p, 0, (size_t)nheavy * 2 * HL * 8, st));
-            HIPTRY(hipMemsetAsync(E1.hinf.p, 0, (size_t)nheavy * 8, st));
-            HIPTRY(hipMemsetAsync(E1.hwid.p, 0, (size_t)nheavy * 8, st));
+            P.inc_max = (uint32_t)std::max<int64_t>(64, (int64_t)h->n * Bv / BP_INC_DIV);
+            HIPTRY(hipMemsetAsync(E1.hacc.p, 0, nh * 2 * HL * 8, st));
+            HIPTRY(hipMemsetAsync(E1.hinf.p, 0, nh * 8, st));
+            HIPTRY(hipMemsetAsync(E1.hwid.p, 0, nh * 8, st));
         }
-        HIPTRY(hipMemsetAsync(E1.cbits.p, 0, E1.cbits.bytes, st));
-        HIPTRY(hipMemsetAsync(E1.hhit.p, 0, E1.hhit.bytes, st));
-        const int64_t nh = h->bin_count[BIN_HEAVY];
-        if (nh > 0)
-            k_fill_allhrec<<<grid_for(nh), 256, 0, st>>>(dinst_of(h), h->cold_rows.as<int32_t>() + h->bin_start[BIN_HEAVY],
-                                                         h->cold_hbase_d.as<int32_t>(), nh, h->heavy_chunk,
-                                                         E1.allhrec.as<int4>());
+        if (nheavy > 0 && (P.scan_ok || P.inc))
+            k_fill_allhrec<<<grid_for(nheavy), 256, 0, st>>>(dinst_of(h), h->cold_rows.as<int32_t>() + h->bin_start[BIN_HEAVY],
+                                                             h->cold_hbase_d.as<int32_t>(), nheavy, h->heavy_chunk,
+                                                             E1.allhrec.as<int4>());
     }
     invalidate_graph(h, P, nullptr);
     Engine &E = *h->eng;

@@ -221,14 +221,15 @@ struct Params {
     // out, its new term in, both exact), so a queued heavy row is tested
     // without reading its nonzeros.  The round after a scan-seeding update,
     // and the first round, rebuild them from the bounds instead.
-    int32_t inc;                 // enabled
+    int32_t inc;                 // enabled (plain propagations of up to INC_SLOTS vectors)
     int32_t nheavy;              // heavy rows
-    long long *hacc;             // [nheavy][2][HL] limbs (min side, max side)
-    int32_t *hinf;               // [nheavy][2] infinite contributions
-    unsigned long long *hwid;    // [nheavy] slack-filter width bound (bits of a double >= 0)
+    int32_t inc_slots;           // slots with accumulators (the vectors of the call)
+    long long *hacc;             // [slot][nheavy][2][HL] limbs (min side, max side)
+    int32_t *hinf;               // [slot][nheavy][2] infinite contributions
+    unsigned long long *hwid;    // [slot][nheavy] slack-filter width bound (bits of a double >= 0)
     const int32_t *hidx;         // [m] heavy index of a row, -1 for the others
     const double *cval;          // [nnz] coefficients in column order
-    double2 *hact;               // [nheavy] the round's rounded (min, max) finite parts
+    double2 *hact;               // [slot][nheavy] the round's rounded (min, max) finite parts
     uint32_t inc_max;            // changed entries from which the next round rebuilds
 };
 
@@ -494,6 +495,7 @@ __device__ __noinline__ double exact_side(const DInst &I, const BView bnd, int64
 // three 32-bit pieces added to consecutive limbs, so concurrent integer
 // atomics build the exact sum in any order.
 constexpr int HL = 2 * SA_WORDS;
+constexpr int INC_SLOTS = 16;  // vectors of one call that keep incremental heavy rows
 
 // The three signed pieces of +-x and the limb of the first one.
 __device__ __forceinline__ void inc_pieces(double x, bool negate, int &d0, long long &q0, long long &q1,
@@ -997,8 +999,11 @@ __device__ void inc_build_chunk(const Params &P, int par, uint32_t u, bool scan)
     __shared__ long long L[2 * HL];
     __shared__ int32_t ninf[2];
     __shared__ unsigned long long wbits;
-    const int4 rec = P.allhrec[u];
+    const uint32_t na = (uint32_t)P.allhchunks;
+    const int s = (int)(u / na);  // every slot rebuilds every heavy chunk
+    const int4 rec = P.allhrec[u % na];
     const int k = rec.y, c = rec.z;
+    if (P.info[s].state != SLOT_ACTIVE) return;  // workgroup-uniform
     for (int j = threadIdx.x; j < 2 * HL; j += WG) L[j] = 0;
     if (threadIdx.x == 0) {
         ninf[0] = 0;
@@ -1010,7 +1015,7 @@ __device__ void inc_build_chunk(const Params &P, int par, uint32_t u, bool scan)
     const int64_t r0 = I.row_ptr[k], r1 = I.row_ptr[k + 1];
     const int64_t p0 = r0 + (int64_t)c * P.heavy_chunk;
     const int64_t p1 = min(r1, p0 + (int64_t)P.heavy_chunk);
-    const BView bnd = bview(P, 0, I.base);
+    const BView bnd = bview(P, s, I.base);
     int nmin = 0, nmax = 0;
     double wmax = 0.0;
     bool mine = false;
@@ -1030,7 +1035,7 @@ __device__ void inc_build_chunk(const Params &P, int par, uint32_t u, bool scan)
             if (isinf(bmax)) nmax += 1;
             else tmax = a * bmax;
             wmax = fmax(wmax, nz_width(a, b.x, b.y));
-            count_read(P, 0, i);
+            count_read(P, s, i);
             if (scan) mine = mine || scan_hit(P, par, i);
         }
         inc_add_wave(L, tmin, in);
@@ -1041,27 +1046,27 @@ __device__ void inc_build_chunk(const Params &P, int par, uint32_t u, bool scan)
     if (wmax > 0.0) atomicMax(&wbits, (unsigned long long)__double_as_longlong(wmax));
     if (scan && __syncthreads_or(mine) && threadIdx.x == 0) atomicOr(&P.hhit[k], 1u);
     __syncthreads();
-    const int h = P.hidx[k];
-    long long *G = P.hacc + (size_t)h * 2 * HL;
+    const size_t hs = (size_t)s * P.nheavy + P.hidx[k];
+    long long *G = P.hacc + hs * 2 * HL;
     for (int j = threadIdx.x; j < 2 * HL; j += WG)
         if (L[j]) atomicAdd((unsigned long long *)&G[j], (unsigned long long)L[j]);
     if (threadIdx.x == 0) {
-        if (ninf[0]) atomicAdd(&P.hinf[2 * h], ninf[0]);
-        if (ninf[1]) atomicAdd(&P.hinf[2 * h + 1], ninf[1]);
-        if (wbits) atomicMax(&P.hwid[h], wbits);
+        if (ninf[0]) atomicAdd(&P.hinf[2 * hs], ninf[0]);
+        if (ninf[1]) atomicAdd(&P.hinf[2 * hs + 1], ninf[1]);
+        if (wbits) atomicMax(&P.hwid[hs], wbits);
     }
 }
 
 // The rounded finite parts of heavy row h from its accumulators, by the
 // whole workgroup: limbs staged in LDS, one lane per side rounds them.
-__device__ double2 inc_row_activity(const Params &P, int h) {
+__device__ double2 inc_row_activity(const Params &P, size_t hs) {
     __shared__ long long L[2 * HL];
     __shared__ double act[2];
     __shared__ int range[4];  // lowest and highest nonzero limb of each side
     if (threadIdx.x < 4) range[threadIdx.x] = (threadIdx.x & 1) ? -1 : HL;
     __syncthreads();
     for (int j = threadIdx.x; j < 2 * HL; j += WG) {
-        const long long v = P.hacc[(size_t)h * 2 * HL + j];
+        const long long v = P.hacc[hs * 2 * HL + j];
         L[j] = v;
         if (v) {
             const int side = j >= HL ? 2 : 0, d = j >= HL ? j - HL : j;
@@ -1086,9 +1091,9 @@ __device__ void inc_head(const Params &P, int par, uint32_t u) {
     if (c != 0) return;  // workgroup-uniform
     if (threadIdx.x == 0) clear_rflag(P, s, k);
     if (P.info[s].state != SLOT_ACTIVE) return;  // workgroup-uniform
-    const int h = P.hidx[k];
-    const double2 a = inc_row_activity(P, h);
-    if (threadIdx.x == 0) P.hact[h] = a;
+    const size_t hs = (size_t)s * P.nheavy + P.hidx[k];
+    const double2 a = inc_row_activity(P, hs);
+    if (threadIdx.x == 0) P.hact[hs] = a;
 }
 
 // Heavy chunk, candidate part.  Every wave combines the row's partials
@@ -1099,6 +1104,10 @@ __device__ void heavy_chunk_candidates(const Params &P, int par, uint32_t u, boo
                                        bool rebuild) {
     const int4 rec = scan ? P.allhrec[u] : P.hrec[par][u];
     const int s = rec.x, k = rec.y, c = rec.z, nch = rec.w;
+    // With incremental heavy rows a rebuild round does not walk the queued
+    // chunks in the row kernel: the queue flag of the row is cleared here,
+    // for draining slots too, so no flag outlives its round.
+    if (P.inc && c == 0 && threadIdx.x == 0 && !scan) clear_rflag(P, s, k);
     if (P.info[s].state != SLOT_ACTIVE) return;  // workgroup-uniform
     const DInst I = inst_of<MULTI>(P, s);
     if (scan) {
@@ -1124,12 +1133,11 @@ __device__ void heavy_chunk_candidates(const Params &P, int par, uint32_t u, boo
         // head in the row kernel, or here in a rebuild round (the row
         // kernel built them); the stored width bounds the current one
         // (bounds only shrink)
-        const int h = P.hidx[k];
-        if (c == 0 && threadIdx.x == 0 && !scan) clear_rflag(P, s, k);
-        R.nmin = P.hinf[2 * h];
-        R.nmax = P.hinf[2 * h + 1];
-        R.rng = __longlong_as_double((long long)P.hwid[h]);
-        const double2 a = rebuild ? inc_row_activity(P, h) : P.hact[h];
+        const size_t hs = (size_t)s * P.nheavy + P.hidx[k];
+        R.nmin = P.hinf[2 * hs];
+        R.nmax = P.hinf[2 * hs + 1];
+        R.rng = __longlong_as_double((long long)P.hwid[hs]);
+        const double2 a = rebuild ? inc_row_activity(P, hs) : P.hact[hs];
         R.minfin = a.x;
         R.maxfin = a.y;
     } else {
@@ -1358,7 +1366,7 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(BP_ROWS
     // Heavy chunks: partial states of the queued chunks, or, with
     // incremental accumulators, every chunk in a rebuild round and none
     // otherwise.
-    const uint32_t C_hchunks = P.inc ? (H.hbuild ? (uint32_t)P.allhchunks : H.hchunks)
+    const uint32_t C_hchunks = P.inc ? (H.hbuild ? (uint32_t)P.allhchunks * (uint32_t)P.inc_slots : H.hchunks)
                                      : (scan ? (uint32_t)P.allhchunks : H.hchunks);
     unsigned long long sc_rows = 0, sc_nnz = 0;
     // Work units: grouped heavy chunk tasks (four per unit, one per wave),
@@ -1568,10 +1576,10 @@ __device__ void enqueue_columns(const Params &P, int par, bool want, int s, long
             if (correct && bin == BIN_HEAVY) {
                 tot_corr += 1;
                 const double a = P.cval[e];
-                const int h = P.hidx[k];
-                long long *Lh = P.hacc + (size_t)h * 2 * HL;
-                inc_move(Lh, &P.hinf[2 * h], a, a > 0.0 ? obl : obu, a > 0.0 ? onl : onu);
-                inc_move(Lh + HL, &P.hinf[2 * h + 1], a, a > 0.0 ? obu : obl, a > 0.0 ? onu : onl);
+                const size_t hs = (size_t)os * P.nheavy + P.hidx[k];
+                long long *Lh = P.hacc + hs * 2 * HL;
+                inc_move(Lh, &P.hinf[2 * hs], a, a > 0.0 ? obl : obu, a > 0.0 ? onl : onu);
+                inc_move(Lh + HL, &P.hinf[2 * hs + 1], a, a > 0.0 ? obu : obl, a > 0.0 ? onu : onl);
             }
         }
         if (count) {
@@ -1693,10 +1701,10 @@ __global__ void __launch_bounds__(WG) k_end(Params P) {
     }
     // the next round rebuilds the heavy-row accumulators: start from zero
     if (P.inc && (par ? c_hb0 : c_hb1)) {
-        const size_t nl = (size_t)P.nheavy * 2 * HL;
-        for (size_t w = threadIdx.x; w < nl; w += WG) P.hacc[w] = 0;
-        for (int w = threadIdx.x; w < 2 * P.nheavy; w += WG) P.hinf[w] = 0;
-        for (int w = threadIdx.x; w < P.nheavy; w += WG) P.hwid[w] = 0ull;
+        const size_t nh = (size_t)P.inc_slots * P.nheavy;
+        for (size_t w = threadIdx.x; w < nh * 2 * HL; w += WG) P.hacc[w] = 0;
+        for (size_t w = threadIdx.x; w < 2 * nh; w += WG) P.hinf[w] = 0;
+        for (size_t w = threadIdx.x; w < nh; w += WG) P.hwid[w] = 0ull;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1715,8 +1723,8 @@ __global__ void __launch_bounds__(WG) k_end(Params P) {
             }
             C->scan[par] = 0;
             C->scan_go = 0;
-            C->hbuild[par] = 0;
         }
+        if (P.inc) C->hbuild[par] = 0;
         C->active = s_active;
         C->finished = s_finished;
         C->round = c_round + 1;
@@ -1838,9 +1846,12 @@ __global__ void __launch_bounds__(WG) k_apply(Params P) {
         } else {
             if (wm && lane == __ffsll((long long)wm) - 1)
                 atomicAdd(&C->stat_written, (unsigned long long)__popcll(wm));
-            enqueue_columns<MULTI>(P, npar, go, s, c0, clen);
+            enqueue_columns<MULTI>(P, npar, go, s, c0, clen, true, nullptr, nullptr, P.inc && !rebuild_next,
+                                   ol, ou, wl, wu);
         }
     }
+    // many changes: the next round rebuilds the heavy-row accumulators
+    if (rebuild_next && blockIdx.x == 0 && threadIdx.x == 0) C->hbuild[npar] = 1u;
     if (single) {
         __shared__ unsigned long long a_rows[WG / 64], a_nnz[WG / 64], a_written[WG / 64];
         const int wave = threadIdx.x >> 6;
@@ -1864,9 +1875,6 @@ __global__ void __launch_bounds__(WG) k_apply(Params P) {
             if (w) atomicAdd(&C->stat_written, w);
             if (scan_next && w) C->scan_go = 1u;
             if (scan_next && blockIdx.x == 0) C->scan[npar] = 1u;
-            // a scan-seeding update leaves the heavy-row accumulators to a
-            // rebuild in the next round
-            if (rebuild_next && blockIdx.x == 0) C->hbuild[npar] = 1u;
         }
     }
 }

@@ -146,3 +146,86 @@ def test_repeated_calls_reuse_the_engine():
         if ro["status"] == oracle.BP_OK:
             r2, l2, u2 = gpu_propagate(I, inst, lo, uo, np.zeros(0, np.int32))
             assert r2["rounds"] == 0
+
+
+@pytest.mark.parametrize("B,flags", [(2, 0), (5, 0), (16, "slots")])
+@pytest.mark.parametrize("cold", [True, False])
+def test_several_vectors_keep_their_own_accumulators(B, flags, cold):
+    """Calls of up to 16 vectors on the slot engine: on a cold start every
+    vector's heavy rows keep accumulators of their own (warm starts of
+    several vectors recompute their rows); results per vector match the
+    oracle and the full recomputation."""
+    import torch
+    from gpu_util import dev
+    inst = _dense_instance(50 + B)
+    r0, lb, ub = oracle.propagate(inst)
+    if r0["status"] != oracle.BP_OK:
+        pytest.skip("infeasible root")
+    LB, UB, changed = gen.bulk_fix_vectors(inst, lb, ub, count=B, frac=0.01, seed=B)
+    ptr = np.zeros(B + 1, np.int64)
+    ptr[1:] = np.cumsum([c.size for c in changed])
+    idx = np.concatenate(changed).astype(np.int32)
+    outs = []
+    for full in (False, True):
+        o = bp().default_options(heavy_threshold=1024)
+        if flags == "slots":
+            o.flags |= bp().FLAG_BATCH_SLOTS
+        if full:
+            o.flags |= bp().FLAG_FULL_ROWS
+        I = bp().Instance(inst, o)
+        tl, tu = dev(LB, torch.float64), dev(UB, torch.float64)
+        if cold:
+            res = I.propagate_batch(tl, tu)
+        else:
+            res = I.propagate_batch(tl, tu, dev(ptr, torch.int64), dev(idx, torch.int32))
+        torch.cuda.synchronize()
+        outs.append((res, tl.cpu().numpy(), tu.cpu().numpy()))
+    (ri, li, ui), (rf, lf, uf) = outs
+    assert ri == rf
+    for v in range(B):
+        ro, lo, uo = oracle.propagate(inst, LB[v], UB[v], changed=None if cold else changed[v])
+        assert_same(inst, ri[v], li[v], ui[v], ro, lo, uo, "batch %d v%d" % (B, v))
+        if ri[v]["status"] != bp().BP_INFEASIBLE:
+            assert np.array_equal(li[v].view(np.int64), lf[v].view(np.int64))
+            assert np.array_equal(ui[v].view(np.int64), uf[v].view(np.int64))
+
+
+@pytest.mark.parametrize("name", ["dense", "single"])
+def test_successive_calls_on_one_instance(name):
+    """Many calls on one instance, one and two vectors, some ending
+    infeasible (a crossed variable leaves queued rows to drain, possibly in
+    a rebuild round): no queue flag or accumulator state may leak into the
+    next call."""
+    import torch
+    from gpu_util import dev
+    inst = _dense_instance(60) if name == "dense" else gen.make("single", 0, scale=0.2)
+    thr = 1024 if name == "dense" else 8192
+    r0, lb, ub = oracle.propagate(inst)
+    if r0["status"] != oracle.BP_OK:
+        pytest.skip("infeasible root")
+    I = bp().Instance(inst, bp().default_options(heavy_threshold=thr))
+    rng = np.random.default_rng(7)
+    ints = np.nonzero((inst["vtype"] == 1) & (lb < ub) & np.isfinite(lb) & np.isfinite(ub))[0]
+    for t in range(24):
+        B = 1 + t % 2
+        k = [3, 40, 300, 1200][t % 4]
+        LB, UB, changed = [], [], []
+        for v in range(B):
+            pick = np.sort(rng.choice(ints, size=min(k, ints.size), replace=False)).astype(np.int32)
+            l2, u2 = lb.copy(), ub.copy()
+            val = np.round(rng.uniform(lb[pick], ub[pick]))
+            l2[pick] = val
+            u2[pick] = val
+            changed.append(pick)
+            LB.append(l2)
+            UB.append(u2)
+        LB, UB = np.array(LB), np.array(UB)
+        ptr = np.zeros(B + 1, np.int64)
+        ptr[1:] = np.cumsum([c.size for c in changed])
+        tl, tu = dev(LB, torch.float64), dev(UB, torch.float64)
+        res = I.propagate_batch(tl, tu, dev(ptr, torch.int64), dev(np.concatenate(changed), torch.int32))
+        torch.cuda.synchronize()
+        gl, gu = tl.cpu().numpy(), tu.cpu().numpy()
+        for v in range(B):
+            ro, lo, uo = oracle.propagate(inst, LB[v], UB[v], changed=changed[v])
+            assert_same(inst, res[v], gl[v], gu[v], ro, lo, uo, "call %d v%d" % (t, v))
