@@ -225,6 +225,12 @@ __global__ void k_box_check(const double2 *bnd, const uint8_t *vtype, int64_t n,
     }
 }
 
+// Slots whose box is crossed before any round drain without running.
+__global__ void k_box_drain(SlotInfo *info, const int32_t *box, int32_t B) {
+    for (int j = threadIdx.x; j < B; j += blockDim.x)
+        if (box[2 * j] != NONE) info[j].state = SLOT_DRAINING;
+}
+
 __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
          j += (int64_t)gridDim.x * blockDim.x)
@@ -991,27 +997,38 @@ static int propagate_slots(bp_instance *h, int32_t Bv, double *lb, double *ub,
         k_box_check<<<grid_for(n * Bv), 256, 0, st>>>(E.bnd.as<double2>(), h->vtype.as<uint8_t>(),
                                                       n, Bv, h->opt.feastol, boxd.as<int32_t>());
     HIPTRY(hipGetLastError());
+    // Calls from inside the library (ids_known_valid: the bound-propagation
+    // rounding) pass bounds its own kernels made, free of NaN: their crossed
+    // boxes are handled on the device and read back with the results, which
+    // spares a host round trip per call.
     std::vector<int32_t> box(2 * (size_t)Bv);
-    HIPTRY(hipMemcpyAsync(box.data(), boxd.p, box.size() * 4, hipMemcpyDeviceToHost, st));
-    HIPTRY(hipStreamSynchronize(st));
-    for (int32_t j = 0; j < Bv; ++j)
-        if (box[2 * j + 1]) return fail(BP_EINVAL, "NaN bound in vector " + std::to_string(j));
+    if (!ids_known_valid) {
+        HIPTRY(hipMemcpyAsync(box.data(), boxd.p, box.size() * 4, hipMemcpyDeviceToHost, st));
+        HIPTRY(hipStreamSynchronize(st));
+        for (int32_t j = 0; j < Bv; ++j)
+            if (box[2 * j + 1]) return fail(BP_EINVAL, "NaN bound in vector " + std::to_string(j));
+    }
     // Validate changed ids.
     if (!cold && n_changed_total > 0 && !ids_known_valid)
         if (int rc = check_ids(h, changed_idx, n_changed_total, st)) return rc;
     if (int rc = start_slots(h, P, Bv, st, changed_idx, changed_ptr, n_changed_total, cold)) return rc;
     // A slot whose box is already crossed is infeasible before any round;
     // its queued rows drain without running.
-    for (int32_t j = 0; j < Bv; ++j) {
-        if (box[2 * j] == NONE) continue;
-        int32_t dr = SLOT_DRAINING;
-        HIPTRY(hipMemcpyAsync(&P.info[j].state, &dr, 4, hipMemcpyHostToDevice, st));
+    if (ids_known_valid) {
+        k_box_drain<<<1, 256, 0, st>>>(P.info, boxd.as<int32_t>(), Bv);
+    } else {
+        for (int32_t j = 0; j < Bv; ++j) {
+            if (box[2 * j] == NONE) continue;
+            int32_t dr = SLOT_DRAINING;
+            HIPTRY(hipMemcpyAsync(&P.info[j].state, &dr, 4, hipMemcpyHostToDevice, st));
+        }
     }
     k_check_any_active<<<1, 256, 0, st>>>(P, Bv);
     HIPTRY(hipGetLastError());
     if (int rc = run_rounds(h, P, nullptr, (int64_t)h->opt.max_rounds + 2, st)) return rc;
     std::vector<SlotInfo> info(Bv);
     HIPTRY(hipMemcpyAsync(info.data(), P.info, Bv * sizeof(SlotInfo), hipMemcpyDeviceToHost, st));
+    if (ids_known_valid) HIPTRY(hipMemcpyAsync(box.data(), boxd.p, box.size() * 4, hipMemcpyDeviceToHost, st));
     if (n > 0) k_unpack<<<grid_for(n * Bv), 256, 0, st>>>(E.bnd.as<double2>(), lb, ub, n * Bv);
     HIPTRY(hipGetLastError());
     HIPTRY(hipStreamSynchronize(st));
