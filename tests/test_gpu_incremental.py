@@ -229,3 +229,29 @@ def test_successive_calls_on_one_instance(name):
         for v in range(B):
             ro, lo, uo = oracle.propagate(inst, LB[v], UB[v], changed=changed[v])
             assert_same(inst, res[v], gl[v], gu[v], ro, lo, uo, "call %d v%d" % (t, v))
+
+
+def test_byte_accounting_counters():
+    """The counters behind the roofline figures: heavy rows tested from
+    their accumulators and their unread nonzeros (zero with the full
+    recomputation), the update kernel's entries, column entries and
+    corrections, and both kernels' event times."""
+    import torch
+    from gpu_util import dev
+    inst = gen.make("single", 3, scale=0.2)
+    stats = {}
+    for full in (False, True):
+        flags = bp().FLAG_COUNT_VARS | bp().FLAG_TIME_KERNELS | (bp().FLAG_FULL_ROWS if full else 0)
+        I = bp().Instance(inst, bp().default_options(flags=flags))
+        tl, tu = dev(inst["lb"], torch.float64), dev(inst["ub"], torch.float64)
+        r = I.propagate(tl, tu)
+        stats[full] = (r, I.kernel_stats(reset=True))
+    (ri, si), (rf, sf) = stats[False], stats[True]
+    assert ri == rf
+    assert si["rows"] == sf["rows"] and si["nnz"] == sf["nnz"] == ri["nnz_propagated"]
+    assert sf["rows_kept"] == 0 and sf["nnz_kept"] == 0 and sf["apply_corr"] == 0
+    assert 0 < si["rows_kept"] <= si["rows"] and 0 < si["nnz_kept"] <= si["nnz"]
+    assert si["apply_corr"] > 0 and si["vars_read"] < sf["vars_read"]
+    for s in (si, sf):
+        assert s["apply_entries"] >= s["vars_written"] > 0 and s["apply_colent"] > 0
+        assert s["launches"] >= ri["rounds"] and s["ms"] > 0 and s["apply_ms"] > 0
