@@ -99,7 +99,7 @@ struct Engine {
     int32_t nstripe = 1;  // changed-list stripes (NSTRIPE for one slot)
     // scan rounds and incremental heavy rows of one plain vector (engines
     // of one slot)
-    DevBuf cbits, hhit, allhrec, hacc, hinf, hwid, hact;
+    DevBuf cbits, hhit, allhrec, hacc, hinf, hwid, hact, hcrec[2];
     Shape shape;
     int64_t bytes = 0;
     DevBuf bnd, cand, vflag, rflag, info, chg, dirty, dlist, dcount, ctl, touched, filt;
@@ -583,8 +583,11 @@ static int engine_alloc(std::unique_ptr<Engine> &eng, const Shape &sh, int32_t s
     if (sh.heavy_rows > 0) {
         // incremental heavy rows of the first INC_SLOTS slots
         const int64_t H = sh.heavy_rows * std::min<int64_t>(S, INC_SLOTS);
+        const int64_t HC = std::max<int64_t>(sh.heavy_chunks, 1) * std::min<int64_t>(S, INC_SLOTS);
         if ((rc = E->hacc.alloc((size_t)H * 2 * HL * 8, B)) || (rc = E->hinf.alloc((size_t)H * 8, B)) ||
-            (rc = E->hwid.alloc((size_t)H * 8, B)) || (rc = E->hact.alloc((size_t)H * 16, B)))
+            (rc = E->hwid.alloc((size_t)H * 8, B)) || (rc = E->hact.alloc((size_t)H * 16, B)) ||
+            (rc = E->hcrec[0].alloc((size_t)HC * sizeof(int4), B)) ||
+            (rc = E->hcrec[1].alloc((size_t)HC * sizeof(int4), B)))
             return rc;
     }
     if ((rc = E->ctl.alloc(sizeof(Ctl), B))) return rc;
@@ -968,6 +971,8 @@ static int propagate_slots(bp_instance *h, int32_t Bv, double *lb, double *ub,
             P.hidx = h->hidx_d.as<int32_t>();
             P.cval = h->col_val.as<double>();
             P.hact = E1.hact.as<double2>();
+            P.hcrec[0] = E1.hcrec[0].as<int4>();
+            P.hcrec[1] = E1.hcrec[1].as<int4>();
             P.inc_max = (uint32_t)std::max<int64_t>(64, (int64_t)h->n * Bv / BP_INC_DIV);
             HIPTRY(hipMemsetAsync(E1.hacc.p, 0, nh * 2 * HL * 8, st));
             HIPTRY(hipMemsetAsync(E1.hinf.p, 0, nh * 8, st));

@@ -118,6 +118,7 @@ struct Ctl {
     unsigned long long scan_rows[NSTRIPE], scan_nnz[NSTRIPE];  // rows a scan round processed
     // incremental heavy-row activities (see Params::inc)
     uint32_t hbuild[2];              // the round of this parity rebuilds them from the bounds
+    uint32_t hcand[2];               // heavy chunk tasks that need candidates (heads decided)
 };
 
 // The leading fields of Ctl for the round in progress (its parity's queue
@@ -129,6 +130,7 @@ struct CtlHead {
     uint32_t hchunks, ghchunks;
     uint32_t scan;
     uint32_t hbuild;
+    uint32_t hcand;
 };
 
 // Keeps control loads ahead of the first branch on them, so that they are
@@ -155,6 +157,8 @@ __device__ __forceinline__ CtlHead ctl_head(const Ctl *C) {
     H.scan = odd ? sc1 : sc0;
     const uint32_t hb0 = C->hbuild[0], hb1 = C->hbuild[1];
     H.hbuild = odd ? hb1 : hb0;
+    const uint32_t hc0 = C->hcand[0], hc1 = C->hcand[1];
+    H.hcand = odd ? hc1 : hc0;
     return H;
 }
 
@@ -230,6 +234,7 @@ struct Params {
     const int32_t *hidx;         // [m] heavy index of a row, -1 for the others
     const double *cval;          // [nnz] coefficients in column order
     double2 *hact;               // [slot][nheavy] the round's rounded (min, max) finite parts
+    int4 *hcrec[2];              // chunk tasks of heavy rows whose head found candidates needed
     uint32_t inc_max;            // changed entries from which the next round rebuilds
 };
 
@@ -1085,15 +1090,40 @@ __device__ double2 inc_row_activity(const Params &P, size_t hs) {
 
 // Heavy row head (round without a rebuild): chunk 0 of each queued heavy
 // row rounds the row's accumulators once for all its chunks.
+// It also tests the row: an infeasible row is reported, a quiet one ends
+// here, and only the chunks of the others become candidate tasks for the
+// heavy kernel, so a round whose heavy rows are all quiet leaves it idle.
 __device__ void inc_head(const Params &P, int par, uint32_t u) {
     const int4 rec = P.hrec[par][u];
-    const int s = rec.x, k = rec.y, c = rec.z;
+    const int s = rec.x, k = rec.y, c = rec.z, nch = rec.w;
     if (c != 0) return;  // workgroup-uniform
     if (threadIdx.x == 0) clear_rflag(P, s, k);
     if (P.info[s].state != SLOT_ACTIVE) return;  // workgroup-uniform
     const size_t hs = (size_t)s * P.nheavy + P.hidx[k];
     const double2 a = inc_row_activity(P, hs);
-    if (threadIdx.x == 0) P.hact[hs] = a;
+    if (threadIdx.x == 0) {
+        P.hact[hs] = a;
+        const double2 sd = P.I.side[k];
+        RowAct R;
+        R.minfin = a.x;
+        R.maxfin = a.y;
+        R.nmin = P.hinf[2 * hs];
+        R.nmax = P.hinf[2 * hs + 1];
+        R.rng = __longlong_as_double((long long)P.hwid[hs]);
+        R.lo = sd.x;
+        R.hi = sd.y;
+        const bool bad = row_bad(R, P.feastol), quiet = !bad && row_quiet(R);
+        if (bad) report_bad_row(P, s, k);
+        if (P.touched) {  // byte accounting: tested from the accumulators
+            atomicAdd(&P.ctl->stat_kept_rows, 1ull);
+            if (bad || quiet)
+                atomicAdd(&P.ctl->stat_kept_nnz, (unsigned long long)(P.I.row_ptr[k + 1] - P.I.row_ptr[k]));
+        }
+        if (!bad && !quiet) {
+            const uint32_t at = atomicAdd(&P.ctl->hcand[par], (uint32_t)nch);
+            for (int j = 0; j < nch; ++j) P.hcrec[par][at + j] = make_int4(s, k, j, nch);
+        }
+    }
 }
 
 // Heavy chunk, candidate part.  Every wave combines the row's partials
@@ -1101,13 +1131,15 @@ __device__ void inc_head(const Params &P, int par, uint32_t u) {
 // the sums and tests the row; the chunk's nonzeros then give candidates.
 template <bool MULTI>
 __device__ void heavy_chunk_candidates(const Params &P, int par, uint32_t u, bool scan,
-                                       bool rebuild) {
-    const int4 rec = scan ? P.allhrec[u] : P.hrec[par][u];
+                                       bool rebuild, bool decided) {
+    // decided: a task of a row its head already tested (not infeasible, not
+    // quiet), from the head's list
+    const int4 rec = decided ? P.hcrec[par][u] : (scan ? P.allhrec[u] : P.hrec[par][u]);
     const int s = rec.x, k = rec.y, c = rec.z, nch = rec.w;
     // With incremental heavy rows a rebuild round does not walk the queued
     // chunks in the row kernel: the queue flag of the row is cleared here,
     // for draining slots too, so no flag outlives its round.
-    if (P.inc && c == 0 && threadIdx.x == 0 && !scan) clear_rflag(P, s, k);
+    if (P.inc && !decided && c == 0 && threadIdx.x == 0 && !scan) clear_rflag(P, s, k);
     if (P.info[s].state != SLOT_ACTIVE) return;  // workgroup-uniform
     const DInst I = inst_of<MULTI>(P, s);
     if (scan) {
@@ -1168,8 +1200,9 @@ __device__ void heavy_chunk_candidates(const Params &P, int par, uint32_t u, boo
     R.maxfin = __shfl(R.maxfin, 0, 64);
     int64_t p0 = r0 + (int64_t)c * P.heavy_chunk;
     int64_t p1 = min(r1, p0 + (int64_t)P.heavy_chunk);
-    const bool bad = row_bad(R, P.feastol), quiet = !bad && row_quiet(R);  // uniform
-    if (P.touched && P.inc && !rebuild && threadIdx.x == 0) {
+    const bool bad = !decided && row_bad(R, P.feastol);
+    const bool quiet = !decided && !bad && row_quiet(R);  // uniform
+    if (P.touched && P.inc && !rebuild && !decided && threadIdx.x == 0) {
         // byte accounting: the row was tested from its accumulators, and
         // without candidates its nonzeros are not read at all
         if (c == 0) atomicAdd(&P.ctl->stat_kept_rows, 1ull);
@@ -1431,13 +1464,17 @@ __global__ void __launch_bounds__(WG) k_heavy(Params P) {
     const bool scan = P.scan_ok && H.scan;
     const uint32_t ngh = scan ? 0u : H.ghchunks;
     const uint32_t gh_units = (ngh + (WG / 64) - 1) / (WG / 64);
-    const uint32_t total = H.done ? 0u : gh_units + (scan ? (uint32_t)P.allhchunks : H.hchunks);
+    // with incremental heavy rows, a round without a rebuild takes only the
+    // chunks whose row head asked for candidates
+    const bool decided = P.inc && !H.hbuild;
+    const uint32_t nh = decided ? H.hcand : (scan ? (uint32_t)P.allhchunks : H.hchunks);
+    const uint32_t total = H.done ? 0u : gh_units + nh;
     for (uint32_t u = blockIdx.x; u < total; u += gridDim.x) {
         if (u < gh_units) {
             const uint32_t t = u * (WG / 64) + (threadIdx.x >> 6);
             if (t < ngh) gh_chunk_candidates<MULTI>(P, par, t);
         } else {
-            heavy_chunk_candidates<MULTI>(P, par, u - gh_units, scan, P.inc && H.hbuild);
+            heavy_chunk_candidates<MULTI>(P, par, u - gh_units, scan, P.inc && H.hbuild, decided);
         }
     }
 }
@@ -1711,6 +1748,7 @@ __global__ void __launch_bounds__(WG) k_end(Params P) {
         for (int b = 0; b < NBIN; ++b) C->qcount[par][b] = 0;
         C->hchunks[par] = 0;
         C->ghchunks[par] = 0;
+        C->hcand[par] = 0;
         for (int st = 0; st < NSTRIPE; ++st) C->nchanged[st] = 0;
         if (P.scan_ok) {
             if (sc_rows) {
