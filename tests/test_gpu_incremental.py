@@ -255,3 +255,40 @@ def test_byte_accounting_counters():
     for s in (si, sf):
         assert s["apply_entries"] >= s["vars_written"] > 0 and s["apply_colent"] > 0
         assert s["launches"] >= ri["rounds"] and s["ms"] > 0 and s["apply_ms"] > 0
+
+
+def test_host_rounds_and_probe_engine_reuse():
+    """Host-driven rounds, and a plain propagation on the engine a probe
+    call sized for its slots (no scan rounds there): both keep incremental
+    heavy rows and match the oracle."""
+    import torch
+    from gpu_util import dev, gpu_base
+    inst = _dense_instance(70)
+    ro, lo, uo = oracle.propagate(inst)
+    o = bp().default_options(heavy_threshold=1024)
+    o.flags |= bp().FLAG_HOST_ROUNDS
+    r, l, u = gpu_propagate(bp().Instance(inst, o), inst)
+    assert_same(inst, r, l, u, ro, lo, uo, "host rounds")
+    if ro["status"] != oracle.BP_OK:
+        return
+    I = bp().Instance(inst, bp().default_options(heavy_threshold=1024, probe_slots=64))
+    gpu_base(I, lo, uo)
+    bins = np.nonzero((inst["vtype"] == 1) & (lo == 0) & (uo == 1))[0][:40].astype(np.int32)
+    G = I.probe(dev(bins, torch.int32))
+    torch.cuda.synchronize()
+    O = oracle.probe(inst, lo, uo, bins)
+    assert np.array_equal(G["status"].cpu().numpy(), O["status"])
+    assert np.array_equal(G["nnz"].cpu().numpy(), O["nnz"])
+    for seed in range(3):
+        rng = np.random.default_rng(seed)
+        ints = np.nonzero((inst["vtype"] == 1) & (lo < uo) & np.isfinite(lo) & np.isfinite(uo))[0]
+        pick = np.sort(rng.choice(ints, size=25, replace=False)).astype(np.int32)
+        l2, u2 = lo.copy(), uo.copy()
+        l2[pick] = np.round(rng.uniform(lo[pick], uo[pick]))
+        u2[pick] = l2[pick]
+        rg, lg, ug = gpu_propagate(I, inst, l2, u2, pick)
+        r2, lo2, uo2 = oracle.propagate(inst, l2, u2, changed=pick)
+        assert_same(inst, rg, lg, ug, r2, lo2, uo2, "after probe %d" % seed)
+        rg, lg, ug = gpu_propagate(I, inst, l2, u2)
+        r2, lo2, uo2 = oracle.propagate(inst, l2, u2)
+        assert_same(inst, rg, lg, ug, r2, lo2, uo2, "cold after probe %d" % seed)
