@@ -36,9 +36,9 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E datasheet peak
 # belongs to the kernel sources it was measured on: when any of them
 # differs, the bench line reports null.
 K_ROWS_TRAFFIC = {
-    "fetch_kib": 1871.9, "write_kib": 191.7, "fetch_scale": 2.0, "write_scale": 1.0,
+    "fetch_kib": 1872.0, "write_kib": 191.7, "fetch_scale": 2.0, "write_scale": 1.0,
     "sources": {
-        "paper_2510_20499_amd/csrc/bp_kernels.h": "5ad03d73607fe0aa85d1acb5a36086348d535b924b2acff0d6f528d1c0c24a9a",
+        "paper_2510_20499_amd/csrc/bp_kernels.h": "fbd69ec6c40f8130123d9b4436d13cdd994899a514f044b602ff5baf90b0c8a4",
         "paper_2510_20499_amd/csrc/bp_sum.h": "833f834eb740e1aaeae0a7fe22dd2566f3b231f64aa197bf2945502c9275c3e9",
         "paper_2510_20499_amd/csrc/bp_engine.hip": "f744540542cfb47807e7c385ad294e73e1741b1b1f5b0b702681e1e88c38c025",
         "paper_2510_20499_amd/build.py": "2b907a883848d04e156f5dd7ba1f49df479651c7e7c715a833f348226ba0bcb8",
@@ -47,7 +47,7 @@ K_ROWS_TRAFFIC = {
 
 
 # The bound-update kernel k_apply in the same counter runs.
-K_APPLY_TRAFFIC = dict(K_ROWS_TRAFFIC, fetch_kib=398.4, write_kib=185.3)
+K_APPLY_TRAFFIC = dict(K_ROWS_TRAFFIC, fetch_kib=398.2, write_kib=186.1)
 
 
 def measured_traffic(t=K_ROWS_TRAFFIC):

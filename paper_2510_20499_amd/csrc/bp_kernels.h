@@ -219,13 +219,15 @@ struct Params {
     const int4 *allhrec;         // chunk records of every heavy row
     int32_t allhchunks;
     uint32_t *hhit;              // [m] heavy row holds a changed variable (scan rounds)
-    // Incremental heavy rows (one plain vector): the exact finite parts of
-    // each heavy row's min and max activity live in carry-save fixed-point
-    // accumulators that every accepted bound change corrects (its old term
-    // out, its new term in, both exact), so a queued heavy row is tested
-    // without reading its nonzeros.  The round after a scan-seeding update,
-    // and the first round, rebuild them from the bounds instead.
-    int32_t inc;                 // enabled (plain propagations of up to INC_SLOTS vectors)
+    // Incremental heavy rows (one plain vector, or a cold start of up to
+    // INC_SLOTS): the exact finite parts of each heavy row's min and max
+    // activity live in carry-save fixed-point accumulators that every
+    // accepted bound change corrects (its old term out, its new term in,
+    // both exact), so a queued heavy row is tested without reading its
+    // nonzeros.  The first round, and the round after an update of at least
+    // inc_max changed entries (a scan-seeding one included), rebuild them
+    // from the bounds instead.
+    int32_t inc;                 // enabled
     int32_t nheavy;              // heavy rows
     int32_t inc_slots;           // slots with accumulators (the vectors of the call)
     long long *hacc;             // [slot][nheavy][2][HL] limbs (min side, max side)
