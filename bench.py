@@ -36,18 +36,19 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E datasheet peak
 # belongs to the kernel sources it was measured on: when any of them
 # differs, the bench line reports null.
 K_ROWS_TRAFFIC = {
-    "fetch_kib": 1872.0, "write_kib": 191.7, "fetch_scale": 2.0, "write_scale": 1.0,
+    "fetch_kib": 1869.6, "write_kib": 191.7, "fetch_scale": 2.0, "write_scale": 1.0,
     "sources": {
-        "paper_2510_20499_amd/csrc/bp_kernels.h": "fbd69ec6c40f8130123d9b4436d13cdd994899a514f044b602ff5baf90b0c8a4",
+        "paper_2510_20499_amd/csrc/bp_kernels.h": "9d05fedec86ef73f51f4a8e444b698433815339ce87a4e83f89a95a1faa6500a",
+        "paper_2510_20499_amd/csrc/bp_carry.h": "b1eff190d608e908e8c3f26c2e243dacd0c147e4c4fcbfc82bb1cfff34e98925",
         "paper_2510_20499_amd/csrc/bp_sum.h": "833f834eb740e1aaeae0a7fe22dd2566f3b231f64aa197bf2945502c9275c3e9",
         "paper_2510_20499_amd/csrc/bp_engine.hip": "f744540542cfb47807e7c385ad294e73e1741b1b1f5b0b702681e1e88c38c025",
-        "paper_2510_20499_amd/build.py": "2b907a883848d04e156f5dd7ba1f49df479651c7e7c715a833f348226ba0bcb8",
+        "paper_2510_20499_amd/build.py": "59ebd25b1830763aa61f6bec85069db133f4df462c1f98ccd7131cf909bc6407",
     },
 }
 
 
 # The bound-update kernel k_apply in the same counter runs.
-K_APPLY_TRAFFIC = dict(K_ROWS_TRAFFIC, fetch_kib=398.2, write_kib=186.1)
+K_APPLY_TRAFFIC = dict(K_ROWS_TRAFFIC, fetch_kib=397.4, write_kib=188.4)
 
 
 def measured_traffic(t=K_ROWS_TRAFFIC):

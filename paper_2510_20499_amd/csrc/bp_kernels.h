@@ -36,6 +36,7 @@
 #include <stdint.h>
 
 #include "bp_sum.h"
+#include "bp_carry.h"
 
 namespace bp {
 
@@ -496,45 +497,16 @@ __device__ __noinline__ double exact_side(const DInst &I, const BView bnd, int64
     return canon0(sa_round(S));
 }
 
-// Carry-save form of the exact fixed-point accumulator: HL signed 64-bit
-// limbs, limb j holding multiples of 2^(32 j - 1074).  A double is placed as
-// the exact accumulator places it (mantissa at bit `pos`) and split into
-// three 32-bit pieces added to consecutive limbs, so concurrent integer
-// atomics build the exact sum in any order.
-constexpr int HL = 2 * SA_WORDS;
+// Incremental heavy rows keep carry-save accumulators (bp_carry.h); these
+// are the atomic adds into them.
 constexpr int INC_SLOTS = 16;  // vectors of one call that keep incremental heavy rows
-
-// The three signed pieces of +-x and the limb of the first one.
-__device__ __forceinline__ void inc_pieces(double x, bool negate, int &d0, long long &q0, long long &q1,
-                                           long long &q2) {
-    const uint64_t b = (uint64_t)__double_as_longlong(x);
-    const bool neg = ((b >> 63) != 0) != negate;
-    const uint64_t be = (b >> 52) & 0x7FF;
-    uint64_t mant = b & ((1ull << 52) - 1);
-    int pos = 0;
-    if (be != 0) {
-        mant |= 1ull << 52;
-        pos = (int)be - 1;
-    }
-    d0 = pos >> 5;
-    const int sh = pos & 31;
-    const uint64_t lo = mant << sh;
-    const uint64_t hi = sh ? (mant >> (64 - sh)) : 0ull;
-    q0 = (long long)(lo & 0xffffffffull);
-    q1 = (long long)(lo >> 32);
-    q2 = (long long)hi;
-    if (neg) {
-        q0 = -q0;
-        q1 = -q1;
-        q2 = -q2;
-    }
-}
+static_assert(CARRY_WORDS == SA_WORDS, "carry-save and exact accumulators differ in width");
 
 __device__ __forceinline__ void inc_add(long long *L, double x, bool negate) {
     if (x == 0.0) return;
     int d0;
     long long q0, q1, q2;
-    inc_pieces(x, negate, d0, q0, q1, q2);
+    carry_pieces(x, negate, d0, q0, q1, q2);
     if (q0) atomicAdd((unsigned long long *)&L[d0], (unsigned long long)q0);
     if (q1) atomicAdd((unsigned long long *)&L[d0 + 1], (unsigned long long)q1);
     if (q2) atomicAdd((unsigned long long *)&L[d0 + 2], (unsigned long long)q2);
@@ -547,7 +519,7 @@ __device__ __forceinline__ void inc_add_wave(long long *L, double x, bool act) {
     int d0 = 0;
     long long q0 = 0, q1 = 0, q2 = 0;
     act = act && x != 0.0;
-    if (act) inc_pieces(x, false, d0, q0, q1, q2);
+    if (act) carry_pieces(x, false, d0, q0, q1, q2);
     uint64_t pend = __ballot(act);
     while (pend) {
         const int leader = __ffsll((long long)pend) - 1;
@@ -578,62 +550,6 @@ __device__ __forceinline__ void inc_move(long long *L, int32_t *ninf, double a, 
     else inc_add(L, a * bo, true);
     if (isinf(bn)) atomicAdd(ninf, 1);
     else inc_add(L, a * bn, false);
-}
-
-// Correctly rounded value of carry-save limbs held in LDS, by one lane
-// (destroys them).  Carries are propagated digit by digit; a negative sum
-// is negated; the 53 bits below the leading one, the next (guard) bit and
-// whether any lower bit is set then give the round-to-nearest-even result,
-// the same value the exact accumulator's rounding gives.
-// Only limbs [lo, hi] are nonzero (lo > hi: none): limbs below lo stay
-// zero, and since every limb is below 2^62 in magnitude the carries settle
-// within two limbs above hi, where the sign is read.
-__device__ double inc_round(long long *L, int lo, int hi) {
-    if (lo > hi) return 0.0;
-    const int last = min(HL - 1, hi + 2);
-    long long carry = 0;
-    for (int j = lo; j <= last; ++j) {
-        const long long t = L[j] + carry;
-        L[j] = t & 0xffffffffll;
-        carry = t >> 32;
-    }
-    const bool neg = carry < 0;
-    if (neg) {  // magnitude: the two's complement negation of the digits
-        long long borrow = 0;
-        for (int j = lo; j <= last; ++j) {
-            const long long t = -L[j] - borrow;
-            L[j] = t & 0xffffffffll;
-            borrow = t < 0 ? 1 : 0;
-        }
-    }
-    int T = last;
-    while (T >= lo && L[T] == 0) --T;
-    if (T < lo) return 0.0;
-    const uint64_t dT = (uint64_t)L[T];
-    const uint64_t d1 = T >= 1 ? (uint64_t)L[T - 1] : 0ull;
-    const uint64_t d2 = T >= 2 ? (uint64_t)L[T - 2] : 0ull;
-    const int b = 31 - __clz((int)(uint32_t)dT);  // leading bit within digit T
-    const int top = 32 * T + b;                     // in units of 2^-1074
-    double mag;
-    if (top <= 52) {  // below 2^53 units: exact (digits 0 and 1 only)
-        mag = ldexp((double)(T == 1 ? (dT << 32) | d1 : dT), -1074);
-    } else {
-        const uint64_t win = (d1 << 32) | d2;  // the two digits below digit T
-        uint64_t M = (dT << (52 - b)) | (win >> (b + 12));
-        const uint64_t guard = (win >> (b + 11)) & 1ull;
-        bool sticky = (win & ((1ull << (b + 11)) - 1ull)) != 0ull;
-        for (int j = T - 3; j >= lo && !sticky; --j) sticky = L[j] != 0;
-        int e = top - 52 - 1074;
-        if (guard && (sticky || (M & 1ull))) {
-            M += 1;
-            if (M == (1ull << 53)) {
-                M >>= 1;
-                e += 1;
-            }
-        }
-        mag = e > 971 ? __builtin_inf() : ldexp((double)M, e);
-    }
-    return canon0(neg ? -mag : mag);
 }
 
 __device__ __forceinline__ bool row_bad(const RowAct &R, double feastol) {
@@ -1082,8 +998,8 @@ __device__ double2 inc_row_activity(const Params &P, size_t hs) {
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) act[0] = inc_round(L, range[0], range[1]);
-    if (threadIdx.x == 64) act[1] = inc_round(L + HL, range[2], range[3]);
+    if (threadIdx.x == 0) act[0] = carry_round(L, range[0], range[1]);
+    if (threadIdx.x == 64) act[1] = carry_round(L + HL, range[2], range[3]);
     __syncthreads();
     const double2 r = make_double2(act[0], act[1]);
     __syncthreads();  // L and act are reused by the next task
