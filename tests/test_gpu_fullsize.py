@@ -238,3 +238,29 @@ def test_serving_mix_full_size():
         assert rel_close(gl[~iv], np.asarray(want["lb"])[~iv]), what
         assert rel_close(gu[~iv], np.asarray(want["ub"])[~iv]), what
     S.close()
+
+
+@pytest.mark.parametrize("name", ["single", "bulk"])
+def test_incremental_rows_over_long_runs(name):
+    """The cold root of the full single-instance workload (79 rounds) and of
+    the bulk workload (1000 rounds, the round limit): incremental heavy rows
+    and the full recomputation (BP_FLAG_FULL_ROWS) give the same outcome,
+    rounds and propagated nonzeros, and the same bounds bit for bit, after
+    every correction of a long run."""
+    _say("full size: incremental rows over a long run, %s" % name)
+    inst = gen.make(name, 0)
+    out = []
+    for full in (False, True):
+        o = bp().default_options()
+        if full:
+            o.flags |= bp().FLAG_FULL_ROWS
+        I = bp().Instance(inst, o)
+        out.append(gpu_propagate(I, inst))
+        del I
+    (ri, li, ui), (rf, lf, uf) = out
+    assert ri == rf, (ri, rf)
+    assert np.array_equal(li.view(np.int64), lf.view(np.int64))
+    assert np.array_equal(ui.view(np.int64), uf.view(np.int64))
+    if name == "single":
+        ro, lo, uo = oracle.propagate(inst)
+        assert_same(inst, ri, li, ui, ro, lo, uo, "single full, incremental")
