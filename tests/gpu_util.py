@@ -6,7 +6,7 @@ import numpy as np
 import torch
 
 import oracle
-from helpers import rel_close
+from helpers import bits, rel_close
 
 INT_FIELDS = ("status", "rounds", "nnz_propagated", "n_infeasible_rows", "infeasible_row",
               "infeasible_var")
@@ -41,10 +41,14 @@ def assert_same(inst, rg, lg, ug, ro, lo, uo, what=""):
     if ro["status"] == oracle.BP_INFEASIBLE:
         return
     integ = inst["vtype"] == 1
-    assert np.array_equal(lg[integ], lo[integ]), (what, "integer lb")
-    assert np.array_equal(ug[integ], uo[integ]), (what, "integer ub")
+    # bit patterns, so that a stored -0.0 differs from +0.0
+    assert np.array_equal(bits(lg[integ]), bits(lo[integ])), (what, "integer lb")
+    assert np.array_equal(bits(ug[integ]), bits(uo[integ])), (what, "integer ub")
     assert rel_close(lg[~integ], lo[~integ]), (what, "continuous lb")
     assert rel_close(ug[~integ], uo[~integ]), (what, "continuous ub")
+    for g, o in ((lg[~integ], lo[~integ]), (ug[~integ], uo[~integ])):
+        z = o == 0.0
+        assert np.array_equal(np.signbit(g[z]), np.signbit(o[z])), (what, "sign of a zero bound")
 
 
 def gpu_base(I, lb, ub):

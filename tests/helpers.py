@@ -28,6 +28,44 @@ def load_golden(name):
     return inst, d
 
 
+def load_golden_cases(name):
+    """A fixture holding several small hand-computed cases: [(inst, case)]."""
+    with open(os.path.join(GOLDEN, name + ".json")) as fh:
+        d = json.load(fh)
+    out = []
+    for c in d["cases"]:
+        inst = gen.from_rows(c["n"], [(cc, v) for cc, v in c["rows"]],
+                             [_f(x) for x in c["lo"]], [_f(x) for x in c["hi"]], c["vtype"],
+                             [_f(x) for x in c["lb"]], [_f(x) for x in c["ub"]])
+        out.append((inst, c))
+    return out
+
+
+def bits(a):
+    """Bit patterns of doubles (tells +0.0 from -0.0)."""
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64)).view(np.int64)
+
+
+RESULT_FIELDS = ("status", "rounds", "nnz_propagated", "n_infeasible_rows", "infeasible_row",
+                 "infeasible_var")
+
+
+def case_mismatch(c, r, lb, ub):
+    """None if a propagation result (r, lb, ub) is the hand-computed cold
+    result of fixture case c (bounds bit for bit when feasible), else a
+    description of the first difference."""
+    exp = c["cold"]
+    for f in RESULT_FIELDS:
+        if r[f] != exp[f]:
+            return "%s: %s got %r want %r" % (c["name"], f, r[f], exp[f])
+    if "lb" in exp:
+        if not np.array_equal(bits(lb), bits([_f(x) for x in exp["lb"]])):
+            return "%s: lb %r want %r" % (c["name"], list(lb), exp["lb"])
+        if not np.array_equal(bits(ub), bits([_f(x) for x in exp["ub"]])):
+            return "%s: ub %r want %r" % (c["name"], list(ub), exp["ub"])
+    return None
+
+
 def rows_of(inst):
     rp, c, v = inst["row_ptr"], inst["col"], inst["val"]
     return [(c[rp[k]:rp[k + 1]], v[rp[k]:rp[k + 1]]) for k in range(inst["m"])]

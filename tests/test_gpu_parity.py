@@ -10,7 +10,8 @@ import torch
 
 import oracle
 from gpu_util import assert_same, both, bp, dev, gpu_propagate
-from helpers import keep_rows, load_golden, row_instance, slack_edge_instance, stack_instances
+from helpers import (case_mismatch, keep_rows, load_golden, load_golden_cases, row_instance,
+                     slack_edge_instance, stack_instances)
 from paper_2510_20499_amd import gen
 
 pytestmark = pytest.mark.gpu
@@ -38,6 +39,17 @@ def test_golden_cold_and_second_call(name, rounds):
     assert list(ug) == [float(x) for x in d["cold"]["ub"]]
     r2, _, _ = both(I, inst, lg, ug, what=name + " second")
     assert r2["rounds"] == d["second_cold"]["rounds"]
+
+
+@pytest.mark.parametrize("rounds", ["graph", "host"])
+def test_golden_w7_crossing_evidence_and_signed_zeros(rounds):
+    # Hand-computed crossing, evidence and signed-zero cases: the GPU gives
+    # the fixture's result itself (bounds bit for bit) and the oracle's.
+    flags = bp().FLAG_HOST_ROUNDS if rounds == "host" else 0
+    for inst, c in load_golden_cases("w7"):
+        I = bp().Instance(inst, _opts(flags=flags))
+        rg, lg, ug = both(I, inst, what=c["name"])
+        assert case_mismatch(c, rg, lg, ug) is None, case_mismatch(c, rg, lg, ug)
 
 
 @pytest.mark.parametrize("seed", range(10))

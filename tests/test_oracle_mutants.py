@@ -15,8 +15,8 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import (brute_scores, exact_gs_fixed_point, feasible_points, implied_dict, load_golden,
-                     round_scenarios)
+from helpers import (brute_scores, case_mismatch, exact_gs_fixed_point, feasible_points, implied_dict,
+                     load_golden, load_golden_cases, round_scenarios)
 from paper_2510_20499_amd import gen
 
 SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle",
@@ -57,6 +57,24 @@ MUTANTS = {
     "no_recovery_mode": ("if (!recovery && !infeasible) {", "if (0) {"),
     "cache_conflicts_kept": ("if (keep[t] && !(box_l[j] <= val[h][t] && val[h][t] <= box_u[j])) keep[t] = 0;",
                              "(void)j;"),
+    # crossing rule, infeasibility evidence and signed zeros (fixture w7)
+    "snap_deleted": ("} else {\n                    nl = nu;\n                }", "} else {\n                }"),
+    "snap_reversed": ("} else {\n                    nl = nu;\n                }",
+                      "} else {\n                    nu = nl;\n                }"),
+    "crossing_without_feastol": ("if (is_int || nl - nu > o->feastol) {", "if (is_int || nl - nu > 0.0) {"),
+    "integer_crossing_snapped": ("if (is_int || nl - nu > o->feastol) {", "if (nl - nu > o->feastol) {"),
+    "largest_bad_row_worklist": (
+        "if (row_infeasible(I, k, &act, o)) {\n                    n_bad += 1;\n                    if (bad_row < 0 || k < bad_row) bad_row = k;",
+        "if (row_infeasible(I, k, &act, o)) {\n                    n_bad += 1;\n                    if (bad_row < 0 || k > bad_row) bad_row = k;"),
+    "largest_bad_row_definition": (
+        "if (row_infeasible(I, k, &acts[k], o)) {\n                    n_bad += 1;\n                    if (bad_row < 0 || k < bad_row) bad_row = k;",
+        "if (row_infeasible(I, k, &acts[k], o)) {\n                    n_bad += 1;\n                    if (bad_row < 0 || k > bad_row) bad_row = k;"),
+    "largest_crossed_var": ("if (bad_var < 0 || i < bad_var) bad_var = i;", "if (bad_var < 0 || i > bad_var) bad_var = i;"),
+    "infeasible_row_count_one": ("res->n_infeasible_rows = (int32_t)n_bad;", "res->n_infeasible_rows = 1;"),
+    "no_canonical_zero": ("static double canon(double x) { return x == 0.0 ? 0.0 : x; }",
+                          "static double canon(double x) { return x; }"),
+    "row_precedence_dropped": ("if (n_bad) {\n            /* Step 3: the round ends with the row evidence. */",
+                               "if (0) {\n            /* Step 3: the round ends with the row evidence. */"),
     "order_violation_direction": ("if (a->maxviol != b->maxviol) return a->maxviol > b->maxviol ? -1 : 1;",
                                   "if (a->maxviol != b->maxviol) return a->maxviol < b->maxviol ? -1 : 1;"),
 }
@@ -64,6 +82,11 @@ MUTANTS = {
 
 def _pins_hold(lib) -> bool:
     try:
+        for mode in (oracle.MODE_WORKLIST, oracle.MODE_DEFINITION):
+            for inst, c in load_golden_cases("w7"):
+                r, lb, ub = oracle.propagate(inst, mode=mode, lib=lib)
+                if case_mismatch(c, r, lb, ub) is not None:
+                    return False
         for name in ("w1", "w2", "w3", "w4"):
             inst, d = load_golden(name)
             r, lb, ub = oracle.propagate(inst, lib=lib)

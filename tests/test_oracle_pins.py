@@ -20,8 +20,8 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import (brute_scores, exact_gs_fixed_point, feasible_points, implied_dict, load_golden,
-                     round_scenarios, row_violations)
+from helpers import (brute_scores, case_mismatch, exact_gs_fixed_point, feasible_points, implied_dict,
+                     load_golden, load_golden_cases, round_scenarios, row_violations)
 from paper_2510_20499_amd import gen
 
 INF = float("inf")
@@ -63,6 +63,19 @@ def test_golden_probes(name):
             j = exp["var"]
             box = oracle.probe_box(lb[j], ub[j], exp["half"])
             assert box == tuple(float(x) for x in exp["box"]), (p, box)
+
+
+@pytest.mark.parametrize("mode", [oracle.MODE_WORKLIST, oracle.MODE_DEFINITION])
+def test_golden_w7_crossing_evidence_and_signed_zeros(mode):
+    # Hand-computed cases for the crossing rule (snap within feastol for a
+    # continuous variable, infeasible otherwise and for any integer
+    # crossing), the infeasibility evidence (smallest row, count of rows,
+    # rows before variables, smallest variable) and -0.0 stored as +0.0.
+    cases = load_golden_cases("w7")
+    assert len(cases) == 7
+    for inst, c in cases:
+        r, lb, ub = oracle.propagate(inst, mode=mode)
+        assert case_mismatch(c, r, lb, ub) is None, case_mismatch(c, r, lb, ub)
 
 
 def test_golden_w1_infeasible_evidence():
