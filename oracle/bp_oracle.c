@@ -23,8 +23,12 @@
  *             base (Section 2.2), the implications being the bounds that
  *             differ from the base
  *   rounding  bulk fix-and-propagate of the integer variables towards a
- *             fractional point (Algorithm 1 and Section 2.3, without the
- *             repair procedure and the LP polish)
+ *             fractional point (Algorithm 1 and Section 2.3, without the LP
+ *             polish)
+ *   repair    bound shifts that remove row violations one row at a time,
+ *             then propagation of the fixed variables from the original
+ *             bounds (Section 2.3, the repair passage; Algorithm 1's
+ *             Run-Repair-Procedure)
  *   scores    the probe priority (Section 2.2: rows violated when a
  *             variable's contribution flips between its bounds, the largest
  *             violation, the smallest unit slack) and the implied-slack score
@@ -833,6 +837,219 @@ int orc_probe_order(const orc_instance *I, const double *lb, const double *ub,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Repair procedure.                                                        */
+/* ------------------------------------------------------------------------ */
+/* REPAIR (Section 2.3, the repair passage; Algorithm 1 calls it as
+ * Run-Repair-Procedure).  The paper gives the outline: remove the violation
+ * of a row by shifting the bounds of one of its variables, a variable at a
+ * time, with a shift computed for every variable of the row that would make
+ * the row feasible; then propagate the fixed variables from the original
+ * bounds; repeat until that propagation is feasible or a limit is reached.
+ * Readings (the paper leaves them open):
+ *
+ *   fixed     F = the integer variables with lb == ub in the given box: the
+ *             repair searches values for them ("given fixed variables"); the
+ *             other variables' bounds are what propagation from F implies,
+ *             so they are not shifted, and only F's values carry into the
+ *             propagation from the original box (lb0, ub0), which must
+ *             contain the given box;
+ *   violation of row k at a box: with the propagation's activities, the
+ *             hi side is violated when no minimum term is infinite and
+ *             minfin > fl(hi + feastol), by e = fl(minfin - hi); the lo side
+ *             when no maximum term is infinite and maxfin < fl(lo - feastol),
+ *             by e = fl(lo - maxfin) (at most one side can be); else e = 0;
+ *   row       the most violated row (largest e, then smallest index);
+ *   shift     of a variable j of F with value v and coefficient a in that
+ *             row: v moves by d (both bounds of j).  The hi side needs
+ *             a*d <= -e: r = fl(-e / a); the lo side needs a*d >= e:
+ *             r = fl(e / a); |d| = max(1, ceil(|r| - inttol)) with the sign
+ *             of r, so that the row's violation goes (up to inttol) in one
+ *             shift.  The value stays inside the original box: d >=
+ *             lb0 - v when shifting down, d <= ub0 - v when shifting up (an
+ *             infinite original bound sets no limit); j is no candidate
+ *             when d = 0;
+ *   score     of candidate j: the change of the total violation, the
+ *             correctly rounded sum over j's rows r of fl(e_r' - e_r), where
+ *             e_r' is r's violation with j's terms replaced: minfin' =
+ *             fl(fl(minfin - fl(c*v)) + fl(c*v')) for the coefficient c of
+ *             j in r and v' = v + d, and the same for maxfin;
+ *   choice    the candidate with the lowest score, then the smallest index,
+ *             applied when its score is negative; its rows' activities are
+ *             then recomputed exactly.  No candidate with a negative score:
+ *             the repair fails;
+ *   attempt   shifts until no row is violated (at most max_shifts in one
+ *             attempt, else the repair fails); then F's current values are
+ *             fixed in a copy of the original box and propagated cold.  A
+ *             propagation that is not infeasible ends the repair: the box
+ *             becomes its result.  One infeasible in round d ends the repair
+ *             after max_attempts (>= 1) such propagations; otherwise the next
+ *             attempt starts from the state of the same propagation after
+ *             d - 1 rounds, where the row conflicts that stopped it show as
+ *             violations.
+ *
+ * lb/ub are replaced by the repaired box, or left as given when the repair
+ * fails.  res: status ORC_OK (repaired) or ORC_INFEASIBLE (failed), the
+ * attempts (propagations from the original box), the shifts applied, the
+ * reason a failed repair stopped (1: no candidate lowers the violation,
+ * 2: shift limit, 3: attempt limit) and the nonzeros propagated. */
+typedef struct {
+    int32_t status, attempts, shifts, reason;
+    int64_t nnz_propagated;
+} orc_repair_result;
+
+static double row_violation(const orc_instance *I, int64_t k, double minfin, double maxfin,
+                            int64_t ninf_min, int64_t ninf_max, const orc_options *o) {
+    if (ninf_min == 0 && !isinf(I->hi[k]) && minfin > I->hi[k] + o->feastol)
+        return minfin - I->hi[k];
+    if (ninf_max == 0 && !isinf(I->lo[k]) && maxfin < I->lo[k] - o->feastol)
+        return I->lo[k] - maxfin;
+    return 0.0;
+}
+
+/* The shifted value of a fixed integer variable (value v, coefficient a)
+ * for a violation e of the hi side (hi_side = 1) or the lo side, inside
+ * [l0, u0]; returns 0 when it cannot move. */
+static int repair_shift(double a, double e, int hi_side, double v, double l0, double u0,
+                        const orc_options *o, double *nv) {
+    double r = hi_side ? (-e) / a : e / a;
+    double mag = ceil(fabs(r) - o->inttol);
+    if (mag < 1.0) mag = 1.0;
+    double d = r < 0.0 ? -mag : mag;
+    if (d < 0.0 && !isinf(l0) && d < l0 - v) d = l0 - v;
+    if (d > 0.0 && !isinf(u0) && d > u0 - v) d = u0 - v;
+    if (d == 0.0) return 0;
+    *nv = canon(v + d);
+    return 1;
+}
+
+int orc_repair(const orc_instance *I, double *lb, double *ub, const double *lb0, const double *ub0,
+               int32_t max_shifts, int32_t max_attempts, const orc_options *o,
+               orc_repair_result *res) {
+    const int64_t m = I->m, n = I->n, nnz = I->nnz;
+    memset(res, 0, sizeof(*res));
+    res->status = ORC_INFEASIBLE;
+    for (int64_t j = 0; j < n; ++j) {
+        if (isnan(lb[j]) || isnan(ub[j]) || isnan(lb0[j]) || isnan(ub0[j])) return ORC_EINVAL;
+        if (lb[j] < lb0[j] || ub[j] > ub0[j] || lb0[j] > ub0[j]) return ORC_EINVAL;
+    }
+    if (max_shifts < 0 || max_attempts < 1) return ORC_EINVAL;
+    int rc = 0;
+    const size_t N1 = (size_t)(n > 0 ? n : 1), M1 = (size_t)(m > 0 ? m : 1);
+    const size_t Z1 = (size_t)(nnz > 0 ? nnz : 1);
+    double *cl = (double *)malloc(N1 * sizeof(double));
+    double *cu = (double *)malloc(N1 * sizeof(double));
+    double *pl = (double *)malloc(N1 * sizeof(double));
+    double *pu = (double *)malloc(N1 * sizeof(double));
+    int8_t *fixed = (int8_t *)malloc(N1);
+    orc_activity *act = (orc_activity *)malloc(M1 * sizeof(orc_activity));
+    double *bmin = (double *)malloc(Z1 * sizeof(double));
+    double *bmax = (double *)malloc(Z1 * sizeof(double));
+    double *diffs = (double *)malloc(M1 * sizeof(double));
+    int64_t *cptr = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int32_t *crow = (int32_t *)malloc(Z1 * sizeof(int32_t));
+    double *cval = (double *)malloc(Z1 * sizeof(double));
+    int64_t *cfill = (int64_t *)malloc(N1 * sizeof(int64_t));
+    if (!cl || !cu || !pl || !pu || !fixed || !act || !bmin || !bmax || !diffs || !cptr || !crow ||
+        !cval || !cfill) {
+        rc = ORC_ENOMEM;
+        goto done;
+    }
+    /* columns (row indices ascending) */
+    for (int64_t p = 0; p < nnz; ++p) cptr[I->col[p] + 1] += 1;
+    for (int64_t j = 0; j < n; ++j) cptr[j + 1] += cptr[j];
+    for (int64_t j = 0; j < n; ++j) cfill[j] = cptr[j];
+    for (int64_t k = 0; k < m; ++k)
+        for (int64_t p = I->row_ptr[k]; p < I->row_ptr[k + 1]; ++p) {
+            int64_t e = cfill[I->col[p]]++;
+            crow[e] = (int32_t)k;
+            cval[e] = I->val[p];
+        }
+    memcpy(cl, lb, (size_t)n * sizeof(double));
+    memcpy(cu, ub, (size_t)n * sizeof(double));
+    for (int64_t j = 0; j < n; ++j) fixed[j] = I->vtype[j] && lb[j] == ub[j];
+    for (;;) {
+        /* shifts */
+        for (int64_t k = 0; k < m; ++k)
+            if ((rc = row_activity(I, k, cl, cu, bmin, bmax, &act[k])) != 0) goto done;
+        int32_t shifts = 0;
+        for (;;) {
+            int64_t kb = -1;
+            double eb = 0.0;
+            for (int64_t k = 0; k < m; ++k) {
+                double e = row_violation(I, k, act[k].minfin, act[k].maxfin, act[k].ninf_min,
+                                         act[k].ninf_max, o);
+                if (e > eb) { eb = e; kb = k; }
+            }
+            if (kb < 0) break;
+            if (shifts >= max_shifts) { res->reason = 2; goto done; }
+            const int hi_side = act[kb].ninf_min == 0 && !isinf(I->hi[kb]) &&
+                                act[kb].minfin > I->hi[kb] + o->feastol;
+            int32_t jb = -1;
+            double sb = 0.0, vbest = 0.0;
+            for (int64_t p = I->row_ptr[kb]; p < I->row_ptr[kb + 1]; ++p) {
+                const int32_t j = I->col[p];
+                double nv;
+                if (!fixed[j] || !repair_shift(I->val[p], eb, hi_side, cl[j], lb0[j], ub0[j], o, &nv))
+                    continue;
+                int64_t nd = 0;
+                for (int64_t q = cptr[j]; q < cptr[j + 1]; ++q) {
+                    const int64_t r = crow[q];
+                    const double c = cval[q];
+                    const orc_activity *A = &act[r];
+                    const double mn = canon((A->minfin - c * cl[j]) + c * nv);
+                    const double mx = canon((A->maxfin - c * cl[j]) + c * nv);
+                    double e0 = row_violation(I, r, A->minfin, A->maxfin, A->ninf_min, A->ninf_max, o);
+                    double e1 = row_violation(I, r, mn, mx, A->ninf_min, A->ninf_max, o);
+                    diffs[nd++] = e1 - e0;
+                }
+                double score = canon(orc_exact_sum(diffs, nd));
+                if (jb < 0 || score < sb) { jb = j; sb = score; vbest = nv; }
+            }
+            if (jb < 0 || !(sb < 0.0)) { res->reason = 1; goto done; }
+            cl[jb] = vbest;
+            cu[jb] = vbest;
+            shifts += 1;
+            res->shifts += 1;
+            for (int64_t q = cptr[jb]; q < cptr[jb + 1]; ++q)
+                if ((rc = row_activity(I, crow[q], cl, cu, bmin, bmax, &act[crow[q]])) != 0) goto done;
+        }
+        /* propagation of the fixed variables from the original box */
+        memcpy(pl, lb0, (size_t)n * sizeof(double));
+        memcpy(pu, ub0, (size_t)n * sizeof(double));
+        for (int64_t j = 0; j < n; ++j)
+            if (fixed[j]) { pl[j] = cl[j]; pu[j] = cl[j]; }
+        memcpy(cl, pl, (size_t)n * sizeof(double));
+        memcpy(cu, pu, (size_t)n * sizeof(double));
+        orc_result pr;
+        int prc = orc_propagate(I, pl, pu, NULL, -1, o, ORC_MODE_WORKLIST, &pr);
+        if (prc < 0) { rc = prc; goto done; }
+        res->attempts += 1;
+        res->nnz_propagated += pr.nnz_propagated;
+        if (pr.status != ORC_INFEASIBLE) {
+            memcpy(lb, pl, (size_t)n * sizeof(double));
+            memcpy(ub, pu, (size_t)n * sizeof(double));
+            res->status = ORC_OK;
+            res->reason = 0;
+            goto done;
+        }
+        if (res->attempts >= max_attempts) { res->reason = 3; goto done; }
+        if (pr.rounds > 1) {
+            /* the same propagation stopped before its detecting round */
+            orc_options o2 = *o;
+            o2.max_rounds = pr.rounds - 1;
+            orc_result pr2;
+            prc = orc_propagate(I, cl, cu, NULL, -1, &o2, ORC_MODE_WORKLIST, &pr2);
+            if (prc < 0) { rc = prc; goto done; }
+            res->nnz_propagated += pr2.nnz_propagated;
+        }
+    }
+done:
+    free(cl); free(cu); free(pl); free(pu); free(fixed); free(act); free(bmin); free(bmax);
+    free(diffs); free(cptr); free(crow); free(cval); free(cfill);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Bound-propagation rounding (bulk fix-and-propagate).                     */
 /* ------------------------------------------------------------------------ */
 /* ROUND (the paper's Algorithm 1 and Section 2.3, without the repair
@@ -867,16 +1084,31 @@ int orc_probe_order(const orc_instance *I, const double *lb, const double *ub,
  *             unless already in it or the path is marked infeasible, else
  *             mark the path infeasible; on a marked path a failed bulk's
  *             members are fixed to their first values without propagation
- *             and recovery mode ends.
+ *             and recovery mode ends;
+ *   repair    (optional, limits rp) while the path is marked infeasible,
+ *             each step ends with the repair procedure (orc_repair) on the
+ *             current box, with the box the rounding started from as the
+ *             original box, until one succeeds (its box replaces the
+ *             current one and the mark is cleared) or rp->calls repairs
+ *             have run; after that the marked path continues without
+ *             repair (Algorithm 1; Section 2.3, the repair passage).
  *
  * lb/ub (length n) are read and written in place.  draws has 2n entries in
  * [0, 1).  res: status (ORC_OK, or ORC_INFEASIBLE for a marked path), then
  * bulks, singles (propagation steps with more than one / one variable),
- * recoveries, the number of variables fixed, nnz propagated. */
+ * recoveries, the number of variables fixed, nnz propagated (repairs'
+ * propagations included), repairs run and repairs that succeeded. */
 typedef struct {
     int32_t status, bulks, singles, recoveries, fixed, iterations;
     int64_t nnz_propagated;
+    int32_t repairs, repaired;
 } orc_round_result;
+
+/* Repair inside the rounding: at most `calls` repair procedures per
+ * rounding, each with the attempt and shift limits of orc_repair. */
+typedef struct {
+    int32_t calls, attempts, shifts;
+} orc_repair_limits;
 
 typedef struct {
     int32_t var, cls;
@@ -913,7 +1145,7 @@ static double round_value(double x, double l, double hi, double u) {
 int orc_round(const orc_instance *I, double *lb, double *ub, const double *x, const double *draws,
               int32_t k, const int32_t *cache_vars, const int8_t *cstatus, const int64_t *coff,
               const int32_t *cvar, const double *clb, const double *cub, const orc_options *o,
-              orc_round_result *res) {
+              const orc_repair_limits *rp, orc_round_result *res) {
     const int64_t n = I->n;
     memset(res, 0, sizeof(*res));
     for (int64_t j = 0; j < n; ++j)
@@ -936,11 +1168,15 @@ int orc_round(const orc_instance *I, double *lb, double *ub, const double *x, co
     val[1] = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
     box_l = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
     box_u = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    double *start_l = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    double *start_u = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
     if (!cpos || !keys || !order || !S || !chg || !keep || !vl[0] || !vl[1] || !vu[0] || !vu[1] ||
-        !val[0] || !val[1] || !box_l || !box_u) {
+        !val[0] || !val[1] || !box_l || !box_u || !start_l || !start_u) {
         rc = ORC_ENOMEM;
         goto done;
     }
+    memcpy(start_l, lb, (size_t)n * sizeof(double));
+    memcpy(start_u, ub, (size_t)n * sizeof(double));
     /* cache lookup: cpos[j] = t of the cached binary j, or -1 */
     for (int64_t j = 0; j < n; ++j) cpos[j] = -1;
     for (int32_t t = 0; t < k; ++t) {
@@ -1078,6 +1314,17 @@ int orc_round(const orc_instance *I, double *lb, double *ub, const double *x, co
                 recovery = 0;
             }
         }
+        if (infeasible && rp && res->repairs < rp->calls) {
+            orc_repair_result rr;
+            int rrc = orc_repair(I, lb, ub, start_l, start_u, rp->shifts, rp->attempts, o, &rr);
+            if (rrc < 0) { rc = rrc; goto done; }
+            res->repairs += 1;
+            res->nnz_propagated += rr.nnz_propagated;
+            if (rr.status == ORC_OK) {
+                res->repaired += 1;
+                infeasible = 0;
+            }
+        }
     }
     res->status = infeasible ? ORC_INFEASIBLE : ORC_OK;
 done:
@@ -1088,6 +1335,6 @@ done:
     }
     free(cpos); free(keys); free(order); free(S); free(chg); free(keep);
     free(vl[0]); free(vl[1]); free(vu[0]); free(vu[1]); free(val[0]); free(val[1]);
-    free(box_l); free(box_u);
+    free(box_l); free(box_u); free(start_l); free(start_u);
     return rc;
 }

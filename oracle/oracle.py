@@ -49,7 +49,16 @@ class _Res(C.Structure):
 class _RoundRes(C.Structure):
     _fields_ = [("status", C.c_int32), ("bulks", C.c_int32), ("singles", C.c_int32),
                 ("recoveries", C.c_int32), ("fixed", C.c_int32), ("iterations", C.c_int32),
-                ("nnz_propagated", C.c_int64)]
+                ("nnz_propagated", C.c_int64), ("repairs", C.c_int32), ("repaired", C.c_int32)]
+
+
+class _RepairLimits(C.Structure):
+    _fields_ = [("calls", C.c_int32), ("attempts", C.c_int32), ("shifts", C.c_int32)]
+
+
+class _RepairRes(C.Structure):
+    _fields_ = [("status", C.c_int32), ("attempts", C.c_int32), ("shifts", C.c_int32),
+                ("reason", C.c_int32), ("nnz_propagated", C.c_int64)]
 
 
 _lib = None
@@ -96,7 +105,12 @@ def bind(path: str):
                                     C.c_void_p, C.c_int32, C.c_void_p]
     lib.orc_round.restype = C.c_int
     lib.orc_round.argtypes = [C.POINTER(_Inst), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                              C.c_int32] + [C.c_void_p] * 6 + [C.POINTER(_Opt), C.POINTER(_RoundRes)]
+                              C.c_int32] + [C.c_void_p] * 6 + [C.POINTER(_Opt),
+                                                                C.POINTER(_RepairLimits),
+                                                                C.POINTER(_RoundRes)]
+    lib.orc_repair.restype = C.c_int
+    lib.orc_repair.argtypes = [C.POINTER(_Inst), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_int32, C.c_int32, C.POINTER(_Opt), C.POINTER(_RepairRes)]
     return lib
 
 
@@ -261,12 +275,36 @@ def probe_order(inst, vars_, lb=None, ub=None, opts: Options = None, lib=None):
     return order[:vs.size]
 
 
-def round_(inst, x, draws, lb=None, ub=None, cache=None, opts: Options = None, lib=None):
-    """Bound-propagation rounding (Algorithm 1 without repair and LP polish)
-    of the integer variables of the box (lb, ub) towards the point x, with
-    the uniform draws draws[2j + h] for the two candidate bulks, and an
-    optional probing cache of binaries (dict with vars and the probe()
-    output).  Returns (result dict, lb, ub)."""
+def repair(inst, lb, ub, lb0=None, ub0=None, max_shifts: int = 64, max_attempts: int = 8,
+           opts: Options = None, lib=None):
+    """Repair procedure (Section 2.3; Algorithm 1's Run-Repair-Procedure) of
+    the box (lb, ub) inside the original box (lb0, ub0), default the
+    instance's bounds.  Returns (result dict, lb, ub): the repaired box, or
+    the given one when the repair fails."""
+    lib = lib or load()
+    h = _Held(inst)
+    lb = np.array(lb, dtype=np.float64, copy=True)
+    ub = np.array(ub, dtype=np.float64, copy=True)
+    lb0 = np.ascontiguousarray(inst["lb"] if lb0 is None else lb0, dtype=np.float64)
+    ub0 = np.ascontiguousarray(inst["ub"] if ub0 is None else ub0, dtype=np.float64)
+    r = _RepairRes()
+    rc = lib.orc_repair(C.byref(h.s), _ptr(lb), _ptr(ub), _ptr(lb0), _ptr(ub0), int(max_shifts),
+                        int(max_attempts), C.byref(_opt(opts)), C.byref(r))
+    if rc < 0:
+        raise ValueError("oracle repair failed with code %d" % rc)
+    out = dict(status=r.status, attempts=r.attempts, shifts=r.shifts, reason=r.reason,
+               nnz_propagated=r.nnz_propagated)
+    return out, lb, ub
+
+
+def round_(inst, x, draws, lb=None, ub=None, cache=None, opts: Options = None, lib=None,
+           repair=None):
+    """Bound-propagation rounding (Algorithm 1 without the LP polish) of the
+    integer variables of the box (lb, ub) towards the point x, with the
+    uniform draws draws[2j + h] for the two candidate bulks, an optional
+    probing cache of binaries (dict with vars and the probe() output) and
+    optional repair limits (calls, attempts, shifts); without them no
+    repair runs.  Returns (result dict, lb, ub)."""
     lib = lib or load()
     h = _Held(inst)
     lb = np.array(inst["lb"] if lb is None else lb, dtype=np.float64, copy=True)
@@ -286,10 +324,13 @@ def round_(inst, x, draws, lb=None, ub=None, cache=None, opts: Options = None, l
                 np.ascontiguousarray(cache["lb"], dtype=np.float64) if len(cache["lb"]) else np.zeros(1),
                 np.ascontiguousarray(cache["ub"], dtype=np.float64) if len(cache["ub"]) else np.zeros(1)]
     r = _RoundRes()
+    rp = None if repair is None else C.byref(_RepairLimits(*[int(v) for v in repair]))
     rc = lib.orc_round(C.byref(h.s), _ptr(lb), _ptr(ub), _ptr(x), _ptr(draws), k,
-                       *[_ptr(a) for a in arrs], C.byref(_opt(opts)), C.byref(r))
+                       *[_ptr(a) for a in arrs], C.byref(_opt(opts)), rp, C.byref(r))
     if rc < 0:
         raise ValueError("oracle round failed with code %d" % rc)
     out = dict(status=r.status, bulks=r.bulks, singles=r.singles, recoveries=r.recoveries,
                fixed=r.fixed, iterations=r.iterations, nnz_propagated=r.nnz_propagated)
+    if repair is not None:
+        out.update(repairs=r.repairs, repaired=r.repaired)
     return out, lb, ub

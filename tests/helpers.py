@@ -374,3 +374,97 @@ def row_violations(inst, x, tol=0.0):
                 (not math.isinf(hi) and s > Fraction(float(hi)) + Fraction(tol)):
             bad.append(k)
     return bad
+
+
+def repair_cases():
+    """The hand-traced repair cases of tests/golden/w8_repair.json:
+    [(instance, case)]; the instance's bounds are the original box, the
+    case holds the given box, the limits and the expected result."""
+    return load_golden_cases("w8_repair")
+
+
+def repair_round_scenario():
+    """The hand-traced rounding-with-repair scenario of w8_repair.json:
+    (instance, spec)."""
+    with open(os.path.join(GOLDEN, "w8_repair.json")) as fh:
+        s = json.load(fh)["rounding"]
+    inst = gen.from_rows(s["n"], [(c, v) for c, v in s["rows"]], [_f(x) for x in s["lo"]],
+                         [_f(x) for x in s["hi"]], s["vtype"], [_f(x) for x in s["lb"]],
+                         [_f(x) for x in s["ub"]])
+    return inst, s
+
+
+def repair_case_mismatch(c, r, lb, ub):
+    """None if a repair result matches hand-traced case c, else the first
+    difference."""
+    if r != c["result"]:
+        return "%s: result %r want %r" % (c["name"], r, c["result"])
+    if not np.array_equal(bits(lb), bits([_f(x) for x in c["final_lb"]])):
+        return "%s: lb %r want %r" % (c["name"], list(lb), c["final_lb"])
+    if not np.array_equal(bits(ub), bits([_f(x) for x in c["final_ub"]])):
+        return "%s: ub %r want %r" % (c["name"], list(ub), c["final_ub"])
+    return None
+
+
+def single_row_repair_instance(seed):
+    """A pure-integer instance of one row (2-5 variables, coefficients in
+    [-5, 5] without 0, original domains inside {0..6}) and a point of the
+    domains that violates the row: (instance, point)."""
+    rng = np.random.default_rng(1000 + seed)
+    while True:
+        n = int(rng.integers(2, 6))
+        lb = rng.integers(0, 3, size=n).astype(np.float64)
+        ub = lb + rng.integers(1, 5, size=n)
+        a = (rng.integers(1, 6, size=n) * np.where(rng.integers(0, 2, size=n) == 0, -1, 1)).astype(np.float64)
+        x = np.array([rng.integers(int(lb[i]), int(ub[i]) + 1) for i in range(n)], dtype=np.float64)
+        s = float(np.dot(a, x))
+        gap = float(rng.integers(1, 7))
+        if rng.integers(0, 2) == 0:
+            lo, hi = -math.inf, s - gap
+        else:
+            lo, hi = s + gap, math.inf
+        inst = gen.from_rows(n, [(list(range(n)), a)], [lo], [hi], [1] * n, lb, ub)
+        return inst, x
+
+
+def brute_single_row_repair(inst, x):
+    """What one shift must do on a single violated row, by enumeration with
+    exact integers: for each variable, the move towards feasibility by the
+    fewest units that makes the row hold, or the farthest one the original
+    domain allows; its score is the exact change of the row's violation.
+    Returns (index, new value) of the lowest negative score (smallest index
+    on ties) or None."""
+    a = [int(v) for v in inst["val"]]
+    lo, hi = inst["lo"][0], inst["hi"][0]
+    X = [int(v) for v in x]
+    s = sum(ai * xi for ai, xi in zip(a, X))
+
+    def viol(t):
+        if not math.isinf(hi) and t > hi:
+            return t - int(hi)
+        if not math.isinf(lo) and t < lo:
+            return int(lo) - t
+        return 0
+
+    e = viol(s)
+    best = None
+    for j, aj in enumerate(a):
+        # the direction that lowers the violation
+        want_down = (not math.isinf(hi) and s > hi)
+        step = -1 if (aj > 0) == want_down else 1
+        v = X[j]
+        lim = int(inst["lb"][j]) if step < 0 else int(inst["ub"][j])
+        moves = []
+        w = v + step
+        while (w >= lim) if step < 0 else (w <= lim):
+            moves.append(w)
+            if viol(s + aj * (w - v)) == 0:
+                break
+            w += step
+        if not moves:
+            continue
+        w = moves[-1]
+        score = viol(s + aj * (w - v)) - e
+        if score < 0 and (best is None or score < best[0]):
+            best = (score, j, w)
+    return None if best is None else (best[1], float(best[2]))

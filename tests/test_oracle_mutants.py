@@ -15,8 +15,10 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import (brute_scores, case_mismatch, exact_gs_fixed_point, feasible_points, implied_dict,
-                     load_golden, load_golden_cases, round_scenarios)
+from helpers import (_f, brute_scores, brute_single_row_repair, case_mismatch, exact_gs_fixed_point,
+                     feasible_points, implied_dict, load_golden, load_golden_cases, repair_case_mismatch,
+                     repair_cases, repair_round_scenario, round_scenarios, row_violations,
+                     single_row_repair_instance)
 from paper_2510_20499_amd import gen
 
 SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle",
@@ -77,6 +79,29 @@ MUTANTS = {
                                "if (0) {\n            /* Step 3: the round ends with the row evidence. */"),
     "order_violation_direction": ("if (a->maxviol != b->maxviol) return a->maxviol > b->maxviol ? -1 : 1;",
                                   "if (a->maxviol != b->maxviol) return a->maxviol < b->maxviol ? -1 : 1;"),
+    # repair procedure (fixture w8_repair, single-row brute force, micro invariants)
+    "repair_first_violated_row": ("if (e > eb) { eb = e; kb = k; }", "if (e > 0.0 && kb < 0) { eb = e; kb = k; }"),
+    "repair_shift_sign": ("double r = hi_side ? (-e) / a : e / a;", "double r = hi_side ? e / a : e / a;"),
+    "repair_no_unit_minimum": ("if (mag < 1.0) mag = 1.0;", "(void)0;"),
+    "repair_inttol_sign": ("double mag = ceil(fabs(r) - o->inttol);", "double mag = ceil(fabs(r) + o->inttol);"),
+    "repair_no_upper_limit": ("if (d > 0.0 && !isinf(u0) && d > u0 - v) d = u0 - v;", "(void)u0;"),
+    "repair_no_lower_limit": ("if (d < 0.0 && !isinf(l0) && d < l0 - v) d = l0 - v;", "(void)l0;"),
+    "repair_ties_to_larger_index": ("if (jb < 0 || score < sb) { jb = j; sb = score; vbest = nv; }",
+                                    "if (jb < 0 || score <= sb) { jb = j; sb = score; vbest = nv; }"),
+    "repair_zero_score_accepted": ("if (jb < 0 || !(sb < 0.0)) { res->reason = 1; goto done; }",
+                                   "if (jb < 0 || !(sb <= 0.0)) { res->reason = 1; goto done; }"),
+    "repair_score_ignores_other_rows": ("diffs[nd++] = e1 - e0;", "if (r == kb) diffs[nd++] = e1 - e0;"),
+    "repair_shifts_unfixed": ("if (!fixed[j] || !repair_shift(", "if (!I->vtype[j] || !repair_shift("),
+    "repair_restart_from_the_box": ("if (pr.rounds > 1) {\n            /* the same propagation stopped",
+                                    "if (0) {\n            /* the same propagation stopped"),
+    "repair_restart_after_d_rounds": ("o2.max_rounds = pr.rounds - 1;", "o2.max_rounds = pr.rounds;"),
+    "repair_attempt_limit_late": ("if (res->attempts >= max_attempts) { res->reason = 3; goto done; }",
+                                  "if (res->attempts > max_attempts) { res->reason = 3; goto done; }"),
+    "round_repair_never_called": ("if (infeasible && rp && res->repairs < rp->calls) {",
+                                  "if (0 && infeasible && rp && res->repairs < rp->calls) {"),
+    "round_repair_keeps_mark": ("res->repaired += 1;\n                infeasible = 0;",
+                                "res->repaired += 1;"),
+    "round_repair_from_current_box": ("orc_repair(I, lb, ub, start_l, start_u,", "orc_repair(I, lb, ub, lb, ub,"),
 }
 
 
@@ -185,6 +210,45 @@ def _pins_hold(lib) -> bool:
             d = np.random.default_rng(seed).random(2 * inst["n"])
             r, l2, u2 = oracle.round_(inst, xs, d, lb, ub, lib=lib)
             if r["status"] != oracle.BP_OK or not np.array_equal(l2[ints], xs[ints]):
+                return False
+        # repair: the hand-traced cases and rounding, single-row brute force,
+        # micro invariants
+        for inst, c in repair_cases():
+            r, lb, ub = oracle.repair(inst, [_f(x) for x in c["box_lb"]], [_f(x) for x in c["box_ub"]],
+                                      max_shifts=c["max_shifts"], max_attempts=c["max_attempts"], lib=lib)
+            if repair_case_mismatch(c, r, lb, ub) is not None:
+                return False
+        inst, s = repair_round_scenario()
+        r0, lb, ub = oracle.propagate(inst, lib=lib)
+        r, l2, u2 = oracle.round_(inst, s["x"], s["draws"], lb, ub, repair=s["repair_limits"], lib=lib)
+        if r != s["expect"] or list(l2) != s["final_lb"] or list(u2) != s["final_ub"]:
+            return False
+        for seed in range(200):
+            inst, x = single_row_repair_instance(seed)
+            r, lb, ub = oracle.repair(inst, x, x, max_shifts=1, max_attempts=1, lib=lib)
+            want = brute_single_row_repair(inst, x)
+            if want is None:
+                if r["status"] != oracle.BP_INFEASIBLE or r["reason"] != 1:
+                    return False
+                continue
+            y = x.copy()
+            y[want[0]] = want[1]
+            if not row_violations(inst, y):
+                if r["status"] != oracle.BP_OK or list(lb) != list(y):
+                    return False
+            elif r["status"] != oracle.BP_INFEASIBLE or r["reason"] != 2:
+                return False
+        for seed in range(120):
+            inst = gen.make_micro(seed)
+            n = inst["n"]
+            rng = np.random.default_rng(seed)
+            x = np.array([rng.integers(int(inst["lb"][i]), int(inst["ub"][i]) + 1) for i in range(n)],
+                         dtype=np.float64)
+            r, lb, ub = oracle.repair(inst, x, x, lib=lib)
+            if r["status"] == oracle.BP_OK:
+                if row_violations(inst, lb) or (not row_violations(inst, x) and r["shifts"] != 0):
+                    return False
+            elif not np.array_equal(lb, x):
                 return False
     except (ValueError, ZeroDivisionError, OverflowError):
         return False

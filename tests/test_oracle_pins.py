@@ -525,3 +525,101 @@ def test_round_micro_brute_force(seed):
         assert row_violations(inst, l2) == []
     if not feasible_points(inst):
         assert r["status"] == oracle.BP_INFEASIBLE
+
+
+# ------------------------------------------------------------------ repair
+def test_golden_w8_repair():
+    """The hand-traced repair cases (Section 2.3 repair passage)."""
+    from helpers import repair_case_mismatch, repair_cases
+    from helpers import _f
+    for inst, c in repair_cases():
+        r, lb, ub = oracle.repair(inst, [_f(x) for x in c["box_lb"]], [_f(x) for x in c["box_ub"]],
+                                  max_shifts=c["max_shifts"], max_attempts=c["max_attempts"])
+        assert repair_case_mismatch(c, r, lb, ub) is None, repair_case_mismatch(c, r, lb, ub)
+
+
+def test_golden_w8_rounding_with_repair():
+    """Algorithm 1 with Run-Repair-Procedure on a hand-traced marked path."""
+    from helpers import repair_round_scenario
+    inst, s = repair_round_scenario()
+    r0, lb, ub = oracle.propagate(inst)
+    assert (r0["status"], r0["rounds"], r0["nnz_propagated"]) == (0, 3, 17)
+    r, l2, u2 = oracle.round_(inst, s["x"], s["draws"], lb, ub, repair=s["repair_limits"])
+    assert r == s["expect"]
+    assert list(l2) == s["final_lb"] and list(u2) == s["final_ub"]
+    r, l2, u2 = oracle.round_(inst, s["x"], s["draws"], lb, ub)
+    assert r == s["expect_no_repair"]
+    assert list(l2) == s["final_lb_no_repair"] and list(u2) == s["final_ub_no_repair"]
+
+
+@pytest.mark.parametrize("seed", range(200))
+def test_repair_single_row_brute_force(seed):
+    """One violated row, every variable fixed: the shift the repair applies
+    is the one enumeration finds (fewest units that make the row hold, else
+    the farthest move inside the original domain; lowest exact score, then
+    the smaller index), and the repair succeeds exactly when that shift
+    makes the row hold."""
+    from helpers import brute_single_row_repair, single_row_repair_instance
+    inst, x = single_row_repair_instance(seed)
+    r, lb, ub = oracle.repair(inst, x, x, max_shifts=1, max_attempts=1)
+    want = brute_single_row_repair(inst, x)
+    if want is None:
+        assert r["status"] == oracle.BP_INFEASIBLE and r["reason"] == 1 and r["shifts"] == 0
+        return
+    j, v = want
+    y = x.copy()
+    y[j] = v
+    holds = not row_violations(inst, y)
+    if holds:
+        assert r["status"] == oracle.BP_OK and r["shifts"] == 1 and r["attempts"] == 1
+        assert list(lb) == list(y) and list(ub) == list(y)
+    else:
+        assert r["status"] == oracle.BP_INFEASIBLE and r["reason"] == 2 and r["shifts"] == 1
+        assert list(lb) == list(x)
+
+
+@pytest.mark.parametrize("seed", range(120))
+def test_repair_micro_invariants(seed):
+    """Pure-integer micro instances, every variable fixed at a point of the
+    domains: a repaired point satisfies every row (exact check) and lies in
+    the original box; a point that already satisfies every row comes back
+    unchanged with no shift; a failed repair leaves the point as given.
+    With only some variables fixed, a repaired box holds every feasible
+    integer point that agrees with its fixed values (brute force)."""
+    inst = gen.make_micro(seed)
+    n = inst["n"]
+    rng = np.random.default_rng(seed)
+    x = np.array([rng.integers(int(inst["lb"][i]), int(inst["ub"][i]) + 1) for i in range(n)],
+                 dtype=np.float64)
+    r, lb, ub = oracle.repair(inst, x, x)
+    if r["status"] == oracle.BP_OK:
+        assert np.array_equal(lb, ub)
+        assert not row_violations(inst, lb)
+        assert (lb >= inst["lb"]).all() and (ub <= inst["ub"]).all()
+        if not row_violations(inst, x):
+            assert r["shifts"] == 0 and np.array_equal(lb, x)
+    else:
+        assert np.array_equal(lb, x) and np.array_equal(ub, x)
+        assert r["reason"] in (1, 2, 3)
+    # a partial fixing: the first half of the variables
+    k = max(1, n // 2)
+    bl, bu = inst["lb"].copy(), inst["ub"].copy()
+    bl[:k] = x[:k]
+    bu[:k] = x[:k]
+    r, lb, ub = oracle.repair(inst, bl, bu)
+    if r["status"] == oracle.BP_OK:
+        assert (lb[:k] == ub[:k]).all()
+        for p in feasible_points(inst):
+            if all(p[i] == lb[i] for i in range(k)):
+                assert all(lb[i] <= p[i] <= ub[i] for i in range(n)), (p, lb, ub)
+    else:
+        assert np.array_equal(lb, bl) and np.array_equal(ub, bu)
+
+
+def test_repair_rejects_a_box_outside_the_original():
+    inst = gen.make_micro(3)
+    bl, bu = inst["lb"] - 1.0, inst["ub"].copy()
+    with pytest.raises(ValueError):
+        oracle.repair(inst, bl, bu)
+    with pytest.raises(ValueError):
+        oracle.repair(inst, inst["lb"], inst["ub"], max_attempts=0)
