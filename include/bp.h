@@ -263,6 +263,24 @@ typedef struct {
 int bp_scores(bp_instance *h, const double *lb, const double *ub, bp_scores_out *out,
               void *stream);
 
+/* bp_scores for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments and results as bp_scores, bit for bit; the call allocates
+ * nothing: its work buffers (packed bounds, 16 B per variable; row
+ * activities, 16 B per row; the partial sums of the rows longer than 1024
+ * nonzeros; each part rounded up to 256 B, plus 256 B) live in a static
+ * device array of BP_SCORES_NOALLOC_MAX_BYTES that every device running the
+ * library holds until the process ends.  An instance needing more returns
+ * BP_EINVAL (outputs untouched).  All calls on one device share that array:
+ * calls that overlap on one device (distinct streams or threads) race, and
+ * the caller must order them.  The first call on a device also looks up the
+ * array's device address (no allocation).  The instance's other entry
+ * points are unaffected. */
+#define BP_SCORES_NOALLOC_MAX_BYTES (64ll << 20)
+
+int bp_scores_noalloc(bp_instance *h, const double *lb, const double *ub, bp_scores_out *out,
+                      void *stream);
+
 /* Probe order (Section 2.2): the DEVICE variable ids vars [k] sorted by
  * more violated rows first (nviol), then the larger maxviol, then the
  * smaller minunit, then the smaller id -- scores at DEVICE lb/ub [n] as

@@ -25,7 +25,7 @@ EXPORTS = ["bp_options_default", "bp_load", "bp_propagate", "bp_propagate_batch"
            "bp_get_base", "bp_kernel_stats", "bp_device_bytes", "bp_free", "bp_last_error",
            "bp_server_create", "bp_server_submit", "bp_server_run", "bp_server_poll",
            "bp_server_results", "bp_server_info", "bp_server_destroy", "bp_autotune",
-           "bp_scores", "bp_probe_order", "bp_round"]
+           "bp_scores", "bp_probe_order", "bp_round", "bp_scores_noalloc"]
 REQ_PROBE, REQ_PROPAGATE = 0, 1
 
 
@@ -128,6 +128,9 @@ def load_library(path: str = LIB_PATH):
     lib.bp_probe.restype = C.c_int
     lib.bp_scores.restype = C.c_int
     lib.bp_scores.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(ScoresOut), C.c_void_p]
+    lib.bp_scores_noalloc.restype = C.c_int
+    lib.bp_scores_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(ScoresOut),
+                                      C.c_void_p]
     lib.bp_probe_order.restype = C.c_int
     lib.bp_probe_order.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                    C.c_void_p, C.c_void_p]
@@ -313,19 +316,28 @@ class Instance:
             assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
             assert t.numel() == self.n
 
-    def scores(self, lb: torch.Tensor, ub: torch.Tensor, stream=None) -> dict:
-        """bp_scores: probe-priority and implied-slack scores of every
-        variable at the float64 device bounds lb/ub."""
+    def scores(self, lb: torch.Tensor, ub: torch.Tensor, stream=None, out: dict = None,
+               noalloc: bool = False) -> dict:
+        """bp_scores (bp_scores_noalloc with noalloc=True): probe-priority and
+        implied-slack scores of every variable at the float64 device bounds
+        lb/ub, into `out` (nviol int32, maxviol / minunit / slack_score
+        float64, each [n] on the device) or new tensors."""
         self._bounds_ok(lb, ub)
         dev = lb.device
-        o = dict(nviol=torch.empty(self.n, dtype=torch.int32, device=dev),
-                 maxviol=torch.empty(self.n, dtype=torch.float64, device=dev),
-                 minunit=torch.empty(self.n, dtype=torch.float64, device=dev),
-                 slack_score=torch.empty(self.n, dtype=torch.float64, device=dev))
-        so = ScoresOut(o["nviol"].data_ptr(), o["maxviol"].data_ptr(), o["minunit"].data_ptr(),
-                       o["slack_score"].data_ptr())
-        _check(_LIB.bp_scores(self._h, _dptr(lb), _dptr(ub), C.byref(so), _stream_ptr(stream)))
-        return o
+        if out is None:
+            out = dict(nviol=torch.empty(self.n, dtype=torch.int32, device=dev),
+                       maxviol=torch.empty(self.n, dtype=torch.float64, device=dev),
+                       minunit=torch.empty(self.n, dtype=torch.float64, device=dev),
+                       slack_score=torch.empty(self.n, dtype=torch.float64, device=dev))
+        for key, dt in (("nviol", torch.int32), ("maxviol", torch.float64),
+                        ("minunit", torch.float64), ("slack_score", torch.float64)):
+            t = out[key]
+            assert t.dtype == dt and t.is_cuda and t.is_contiguous() and t.numel() == self.n
+        so = ScoresOut(out["nviol"].data_ptr(), out["maxviol"].data_ptr(),
+                       out["minunit"].data_ptr(), out["slack_score"].data_ptr())
+        fn = _LIB.bp_scores_noalloc if noalloc else _LIB.bp_scores
+        _check(fn(self._h, _dptr(lb), _dptr(ub), C.byref(so), _stream_ptr(stream)))
+        return out
 
     def probe_order(self, vars_: torch.Tensor, lb: torch.Tensor, ub: torch.Tensor,
                     stream=None) -> torch.Tensor:

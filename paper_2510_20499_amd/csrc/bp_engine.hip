@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -149,10 +150,10 @@ struct bp_instance {
     DevBuf cold_hbase_d;
     std::unique_ptr<Engine> eng;
     std::unique_ptr<LvEngine> lv;  // one-vector-per-lane batch engine
-    // priority scores: packed bounds, row activities, CSC values and the
-    // chunk table of the long rows (built on first use), sort keys
-    DevBuf sc_bnd, sc_act, sc_cval, sc_chunks, sc_rows, sc_first, sc_part, sc_tmp, sc_keys;
-    bool sc_ready = false;
+    // priority scores: the chunk table of the long rows (built with the row
+    // bins), the per-call work (packed bounds, row activities, long-row
+    // partials; allocated on first use) and sort buffers
+    DevBuf sc_chunks, sc_rows, sc_first, sc_work, sc_tmp, sc_keys;
     int64_t sc_nchunks = 0, sc_nlong = 0;
     // bound-propagation rounding work buffers
     DevBuf rd_order, rd_order2, rd_flags, rd_small, rd_S, rd_keys, rd_val, rd_keep, rd_mpos;
@@ -367,6 +368,8 @@ static int validate_options(const bp_options &o) {
     return 0;
 }
 
+static int sc_tables(bp_instance *h, const std::vector<int32_t> &cold, hipStream_t st);
+
 // Row bins (logarithmic radix binning, the paper's Section 2.1 load
 // balancing) for the instance's heavy threshold and chunk size: the bin of
 // every row, the cold-start row order grouped by bin, and the chunk table
@@ -413,6 +416,7 @@ static int bin_rows(bp_instance *h, hipStream_t st) {
     if (!h->cold_hbase.empty())
         HIPTRY(hipMemcpyAsync(h->cold_hbase_d.p, h->cold_hbase.data(), h->cold_hbase.size() * 4,
                               hipMemcpyHostToDevice, st));
+    if ((rc = sc_tables(h, cold, st))) return rc;
     HIPTRY(hipStreamSynchronize(st));
     return 0;
 }

@@ -150,9 +150,9 @@ static int round_impl(bp_instance *h, double *lb, double *ub, const double *x, c
         int64_t bulk = (recovery || R <= 36) ? 1 : (int64_t)std::ceil(std::sqrt((double)R));
         if (bulk > 1) {
             // implied-slack re-sort (stable): S at the current box
-            if ((rc = sc_rows_pass(h, lb, ub, st))) return rc;
-            k_sc_vars<<<grid_for(n), 256, 0, st>>>(dinst_of(h), h->sc_bnd.as<double2>(),
-                                                   h->sc_cval.as<double>(), h->sc_act.as<double2>(),
+            ScWork W;
+            if ((rc = sc_work_own(h, W)) || (rc = sc_rows_pass(h, lb, ub, W, st))) return rc;
+            k_sc_vars<<<grid_for(n), 256, 0, st>>>(dinst_of(h), W.bnd, h->col_val.as<double>(), W.act,
                                                    h->opt.feastol, nullptr, nullptr, nullptr, S);
             const int64_t kpad = pow2_at_least(R);
             k_rd_slack_keys<<<grid_for(kpad), 256, 0, st>>>(order, R, kpad, S, keys);

@@ -16,8 +16,8 @@
 //         instance (G lanes per row), longer rows by chunks of SC_CHUNK
 //         nonzeros whose partial sums a wave per row merges; each row keeps
 //         only its two slacks (16 B, +inf for a side that has none);
-//   vars  one lane per variable walks its column (CSC values, built once per
-//         instance) four entries at a time and computes its four scores; the
+//   vars  one lane per variable walks its column (the instance's CSC
+//         coefficients) four entries at a time and computes its four scores; the
 //         sum of s^2 is certified like the activities and falls back to the
 //         exact accumulator.
 // The probe order sorts (nviol desc, maxviol desc, minunit asc, index asc)
@@ -183,24 +183,6 @@ __global__ void __launch_bounds__(WG) k_sc_combine(DInst I, const double2 *bnd, 
             if (!okmin) vmin = exact_side(I, view, p0, p1, false);
             if (!okmax) vmax = exact_side(I, view, p0, p1, true);
             slk[k] = sc_slacks(I.side[k], vmin, vmax, A.ninf, B.ninf);
-        }
-    }
-}
-
-// CSC values: entry p of column j is row k = col_row[p]; its coefficient is
-// found by binary search of j in row k (column indices ascend in a row).
-__global__ void k_sc_cval(DInst I, double *cval) {
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < I.n;
-         j += (int64_t)gridDim.x * blockDim.x) {
-        for (int64_t p = I.col_ptr[j]; p < I.col_ptr[j + 1]; ++p) {
-            const int k = I.col_row[p];
-            int64_t lo = I.row_ptr[k], hi = I.row_ptr[k + 1] - 1;
-            while (lo < hi) {
-                const int64_t mid = lo + ((hi - lo) >> 1);
-                if (I.col[mid] < j) lo = mid + 1;
-                else hi = mid;
-            }
-            cval[p] = I.val[lo];
         }
     }
 }

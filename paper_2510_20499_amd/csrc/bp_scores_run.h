@@ -2,19 +2,55 @@
 // bp_engine.hip after the kernels of bp_scores.h).
 #pragma once
 
-// CSC values and the chunk table of the rows longer than 1024 nonzeros (the
-// block and heavy bins), built once per instance.
-static int sc_build(bp_instance *h, hipStream_t st) {
-    if (h->sc_ready) return 0;
-    const DInst I = dinst_of(h);
-    if (int rc = h->sc_cval.alloc((size_t)std::max<int64_t>(h->nnz, 1) * 8, h->bytes)) return rc;
-    if (h->n > 0) k_sc_cval<<<grid_for(h->n), 256, 0, st>>>(I, h->sc_cval.as<double>());
-    HIPTRY(hipGetLastError());
-    // long rows in bin order, from the cold-start row list
-    std::vector<int32_t> cold((size_t)std::max<int32_t>(h->m, 1));
-    if (h->m > 0)
-        HIPTRY(hipMemcpyAsync(cold.data(), h->cold_rows.p, (size_t)h->m * 4, hipMemcpyDeviceToHost, st));
-    HIPTRY(hipStreamSynchronize(st));
+// Per-call work of the scores: packed bounds, row activities (slacks),
+// partial sums of the chunks of the long rows, and a NaN flag.
+struct ScWork {
+    double2 *bnd;
+    double2 *act;
+    Acc *part;
+    int32_t *flag;
+};
+
+// Bytes of each part of ScWork for an instance (each a multiple of 256).
+struct ScWorkSize {
+    size_t flag, bnd, act, part;
+    size_t total() const { return flag + bnd + act + part; }
+};
+
+static size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+static ScWorkSize sc_work_size(const bp_instance *h) {
+    ScWorkSize z;
+    z.flag = 256;
+    z.bnd = round256((size_t)std::max<int32_t>(h->n, 1) * sizeof(double2));
+    z.act = round256((size_t)std::max<int32_t>(h->m, 1) * sizeof(double2));
+    z.part = round256((size_t)std::max<int64_t>(h->sc_nchunks, 1) * 2 * sizeof(Acc));
+    return z;
+}
+
+// ScWork carved out of one block of device memory of sc_work_size bytes.
+static ScWork sc_work_at(const bp_instance *h, void *base) {
+    const ScWorkSize z = sc_work_size(h);
+    char *p = (char *)base;
+    ScWork W;
+    W.flag = (int32_t *)p;
+    W.bnd = (double2 *)(p + z.flag);
+    W.act = (double2 *)(p + z.flag + z.bnd);
+    W.part = (Acc *)(p + z.flag + z.bnd + z.act);
+    return W;
+}
+
+// The instance's own ScWork (allocated on first use, kept).
+static int sc_work_own(bp_instance *h, ScWork &W) {
+    if (int rc = h->sc_work.grow(sc_work_size(h).total(), h->bytes)) return rc;
+    W = sc_work_at(h, h->sc_work.p);
+    return 0;
+}
+
+// Chunk table of the rows longer than 1024 nonzeros (the block and heavy
+// bins) from the cold-start row order `cold` (host): rows, their first
+// chunk and the (row, chunk, chunks) records.  Built with the row bins.
+static int sc_tables(bp_instance *h, const std::vector<int32_t> &cold, hipStream_t st) {
     std::vector<int32_t> rows;
     std::vector<int64_t> first(1, 0);
     std::vector<int4> chunks;
@@ -31,38 +67,30 @@ static int sc_build(bp_instance *h, hipStream_t st) {
     if ((rc = h->sc_rows.alloc(std::max<size_t>(rows.size(), 1) * 4, h->bytes))) return rc;
     if ((rc = h->sc_first.alloc(first.size() * 8, h->bytes))) return rc;
     if ((rc = h->sc_chunks.alloc(std::max<size_t>(chunks.size(), 1) * sizeof(int4), h->bytes))) return rc;
-    if ((rc = h->sc_part.alloc(std::max<size_t>(chunks.size(), 1) * 2 * sizeof(Acc), h->bytes))) return rc;
     if (!rows.empty()) {
         HIPTRY(hipMemcpyAsync(h->sc_rows.p, rows.data(), rows.size() * 4, hipMemcpyHostToDevice, st));
         HIPTRY(hipMemcpyAsync(h->sc_chunks.p, chunks.data(), chunks.size() * sizeof(int4),
                               hipMemcpyHostToDevice, st));
     }
     HIPTRY(hipMemcpyAsync(h->sc_first.p, first.data(), first.size() * 8, hipMemcpyHostToDevice, st));
-    if ((rc = h->sc_act.alloc((size_t)std::max<int32_t>(h->m, 1) * sizeof(double2), h->bytes))) return rc;
-    if ((rc = h->sc_bnd.alloc((size_t)std::max<int32_t>(h->n, 1) * 16, h->bytes))) return rc;
-    HIPTRY(hipStreamSynchronize(st));
-    h->sc_ready = true;
     return 0;
 }
 
-// Bounds in (NaN rejected), then the exact activity of every row.
-static int sc_rows_pass(bp_instance *h, const double *lb, const double *ub, hipStream_t st) {
+// Bounds in (NaN rejected), then the exact activity of every row, into W.
+static int sc_rows_pass(bp_instance *h, const double *lb, const double *ub, const ScWork &W,
+                        hipStream_t st) {
     const int64_t n = h->n;
-    if (int rc = sc_build(h, st)) return rc;
     const DInst I = dinst_of(h);
-    double2 *bnd = h->sc_bnd.as<double2>();
     if (n > 0) {
-        k_pack<<<grid_for(n), 256, 0, st>>>(lb, ub, bnd, n, 1);
-        if (int rc = h->idflag_d.grow(4, h->bytes)) return rc;
-        int32_t zero = 0, bad = 0;
-        HIPTRY(hipMemcpyAsync(h->idflag_d.p, &zero, 4, hipMemcpyHostToDevice, st));
-        k_sc_nan<<<grid_for(n), 256, 0, st>>>(bnd, n, h->idflag_d.as<int32_t>());
+        k_pack<<<grid_for(n), 256, 0, st>>>(lb, ub, W.bnd, n, 1);
+        k_fill_i32<<<1, 64, 0, st>>>(W.flag, 0, 1);
+        k_sc_nan<<<grid_for(n), 256, 0, st>>>(W.bnd, n, W.flag);
         HIPTRY(hipGetLastError());
-        HIPTRY(hipMemcpyAsync(&bad, h->idflag_d.p, 4, hipMemcpyDeviceToHost, st));
+        int32_t bad = 0;
+        HIPTRY(hipMemcpyAsync(&bad, W.flag, 4, hipMemcpyDeviceToHost, st));
         HIPTRY(hipStreamSynchronize(st));
         if (bad) return fail(BP_EINVAL, "NaN bound");
     }
-    double2 *act = h->sc_act.as<double2>();
     const int32_t *cold = h->cold_rows.as<int32_t>();
     ScRowsWork R;
     R.chunks = h->sc_chunks.as<int4>();
@@ -78,11 +106,11 @@ static int sc_rows_pass(bp_instance *h, const double *lb, const double *ub, hipS
     }
     const int64_t units = R.start[NLIGHT + 1];
     if (units > 0)
-        k_sc_rows<<<(int)std::min<int64_t>(units, 8192), WG, 0, st>>>(I, bnd, R, h->sc_part.as<Acc>(), act);
+        k_sc_rows<<<(int)std::min<int64_t>(units, 8192), WG, 0, st>>>(I, W.bnd, R, W.part, W.act);
     if (h->sc_nlong > 0)
         k_sc_combine<<<(int)std::min<int64_t>((h->sc_nlong + 3) / 4, 4096), WG, 0, st>>>(
-            I, bnd, h->sc_rows.as<int32_t>(), h->sc_first.as<int64_t>(), h->sc_nlong,
-            h->sc_part.as<Acc>(), act);
+            I, W.bnd, h->sc_rows.as<int32_t>(), h->sc_first.as<int64_t>(), h->sc_nlong, W.part,
+            W.act);
     HIPTRY(hipGetLastError());
     return 0;
 }
@@ -101,20 +129,74 @@ static void sc_sort(ScKey *keys, int64_t kpad, hipStream_t st) {
     }
 }
 
-extern "C" int bp_scores(bp_instance *h, const double *lb, const double *ub, bp_scores_out *out,
-                         void *stream) {
-    if (!h || !out) return fail(BP_EINVAL, "null argument");
-    if (h->n > 0 && (!lb || !ub)) return fail(BP_EINVAL, "null bounds");
-    hipStream_t st = as_stream(stream);
-    if (int rc = sc_rows_pass(h, lb, ub, st)) return rc;
+// Scores at lb/ub with the work buffers W (shared by bp_scores and
+// bp_scores_noalloc).
+static int sc_scores(bp_instance *h, const double *lb, const double *ub, bp_scores_out *out,
+                     const ScWork &W, hipStream_t st) {
+    if (int rc = sc_rows_pass(h, lb, ub, W, st)) return rc;
     if (h->n > 0)
-        k_sc_vars<<<grid_for(h->n), 256, 0, st>>>(dinst_of(h), h->sc_bnd.as<double2>(),
-                                                   h->sc_cval.as<double>(), h->sc_act.as<double2>(),
+        k_sc_vars<<<grid_for(h->n), 256, 0, st>>>(dinst_of(h), W.bnd, h->col_val.as<double>(), W.act,
                                                    h->opt.feastol, out->nviol, out->maxviol,
                                                    out->minunit, out->slack_score);
     HIPTRY(hipGetLastError());
     HIPTRY(hipStreamSynchronize(st));
     return BP_OK;
+}
+
+extern "C" int bp_scores(bp_instance *h, const double *lb, const double *ub, bp_scores_out *out,
+                         void *stream) {
+    if (!h || !out) return fail(BP_EINVAL, "null argument");
+    if (h->n > 0 && (!lb || !ub)) return fail(BP_EINVAL, "null bounds");
+    hipStream_t st = as_stream(stream);
+    ScWork W;
+    if (int rc = sc_work_own(h, W)) return rc;
+    return sc_scores(h, lb, ub, out, W, st);
+}
+
+// ---------------------------------------------------------------------------
+// Scores without device allocation.  The work buffers live in one static
+// device array; each device that runs the library holds its own copy for
+// the life of the process.  Host code never passes the array's name to a
+// kernel (on the host it is only a stand-in for the symbol): it uses the
+// device address that hipGetSymbolAddress returns, taken once per device
+// on the first call there.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[BP_SCORES_NOALLOC_MAX_BYTES];
+
+static const int SCRATCH_MAX_DEVICES = 64;
+static void *g_scratch_ptr[SCRATCH_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+// Device address of `scratch` on the current device (taken on first use).
+static int scratch_ptr(void **out) {
+    int dev = -1;
+    HIPTRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return fail(BP_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(BP_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return 0;
+}
+
+extern "C" int bp_scores_noalloc(bp_instance *h, const double *lb, const double *ub,
+                                 bp_scores_out *out, void *stream) {
+    if (!h || !out) return fail(BP_EINVAL, "null argument");
+    if (h->n > 0 && (!lb || !ub)) return fail(BP_EINVAL, "null bounds");
+    const size_t need = sc_work_size(h).total();
+    if (need > (size_t)BP_SCORES_NOALLOC_MAX_BYTES)
+        return fail(BP_EINVAL, "bp_scores_noalloc: the instance needs " + std::to_string(need) +
+                                   " bytes of work space, more than the " +
+                                   std::to_string((long long)BP_SCORES_NOALLOC_MAX_BYTES) +
+                                   " the static array holds");
+    void *base = nullptr;
+    if (int rc = scratch_ptr(&base)) return rc;
+    return sc_scores(h, lb, ub, out, sc_work_at(h, base), as_stream(stream));
 }
 
 extern "C" int bp_probe_order(bp_instance *h, const double *lb, const double *ub,
@@ -125,7 +207,9 @@ extern "C" int bp_probe_order(bp_instance *h, const double *lb, const double *ub
     hipStream_t st = as_stream(stream);
     if (k > 0)
         if (int rc = check_ids(h, vars, k, st)) return rc;
-    if (int rc = sc_rows_pass(h, lb, ub, st)) return rc;
+    ScWork W;
+    if (int rc = sc_work_own(h, W)) return rc;
+    if (int rc = sc_rows_pass(h, lb, ub, W, st)) return rc;
     if (k == 0) return BP_OK;
     const int64_t n = h->n;
     // nviol | maxviol | minunit of every variable
@@ -133,9 +217,8 @@ extern "C" int bp_probe_order(bp_instance *h, const double *lb, const double *ub
     double *mv = h->sc_tmp.as<double>();
     double *mu = mv + n;
     int32_t *nv = (int32_t *)(mu + n);
-    k_sc_vars<<<grid_for(n), 256, 0, st>>>(dinst_of(h), h->sc_bnd.as<double2>(), h->sc_cval.as<double>(),
-                                           h->sc_act.as<double2>(), h->opt.feastol, nv, mv, mu,
-                                           nullptr);
+    k_sc_vars<<<grid_for(n), 256, 0, st>>>(dinst_of(h), W.bnd, h->col_val.as<double>(), W.act,
+                                           h->opt.feastol, nv, mv, mu, nullptr);
     int64_t kpad = 1;
     while (kpad < k) kpad <<= 1;
     if (int rc = h->sc_keys.grow((size_t)kpad * sizeof(ScKey), h->bytes)) return rc;
