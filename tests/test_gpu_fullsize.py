@@ -63,11 +63,12 @@ def test_probe_workload_full_size():
         assert vs[t] in v and l[v == vs[t]][0] == h and u[v == vs[t]][0] == h, p
         iv = integ[v]
         assert np.all(l[iv] == np.round(l[iv])) and np.all(u[iv] == np.round(u[iv])), p
-    # sampled probes, one by one in the oracle: a seeded draw, the probes
-    # found infeasible and the longest one
+    # sampled probes, one by one in the oracle: a seeded draw of 64
+    # binaries, every binary with a probe found infeasible and the one with
+    # the most rounds
     rng = np.random.default_rng(11)
-    pick = set(rng.choice(vs.size, size=8, replace=False).tolist())
-    pick |= set((np.nonzero(st == bp().BP_INFEASIBLE)[0] // 2)[:2].tolist())
+    pick = set(rng.choice(vs.size, size=64, replace=False).tolist())
+    pick |= set((np.nonzero(st == bp().BP_INFEASIBLE)[0] // 2).tolist())
     pick.add(int(np.argmax(G["rounds"]) // 2))
     pick = sorted(pick)
     O = oracle.probe(inst, olb, oub, vs[pick])
@@ -130,6 +131,7 @@ def test_bulk_workload_full_size():
     idx = np.concatenate([p for p, _ in lists])
     vals = np.concatenate([v for _, v in lists])
     I = bp().Instance(inst)
+    gpu_base(I, olb, oub)  # the lanes read the vectors as overlays on it
     d = torch.device("cuda:0")
     LB = dev(olb, torch.float64).expand(B, -1).contiguous()
     UB = dev(oub, torch.float64).expand(B, -1).contiguous()
@@ -149,8 +151,8 @@ def test_bulk_workload_full_size():
             assert (0 <= r["infeasible_row"] < inst["m"]) or (0 <= r["infeasible_var"] < n), r
         if r["rounds"] == 1:
             assert r["nnz_propagated"] == _first_round_nnz(inst, rowid, lists[v][0]), v
-    # sampled vectors, one by one in the oracle
-    for v in (0, 97, 255):
+    # sampled vectors, one by one in the oracle: every sixteenth and the last
+    for v in list(range(0, B, 16)) + [B - 1]:
         p, val = lists[v]
         lb, ub = olb.copy(), oub.copy()
         lb[p] = val
@@ -158,6 +160,42 @@ def test_bulk_workload_full_size():
         rv, lv, uv = oracle.propagate(inst, lb, ub, changed=p)
         assert_same(inst, res[v], LB[v].cpu().numpy(), UB[v].cpu().numpy(), rv, lv, uv,
                     "bulk vector %d" % v)
+
+
+def test_bulk_root_against_the_oracle_record():
+    """The benchmark's bulk root: a cold propagation of the full bulk
+    workload from its initial bounds, 1000 rounds (the round limit), against
+    what the oracle computed once (tests/golden/bulk_root.json, written by
+    make_bulk_root.py): outcome, rounds, propagated nonzeros and evidence
+    equal; integer bounds bit for bit through their sha256; continuous
+    bounds bit for bit through theirs, else a seeded sample of 4096 within
+    1e-9 relative."""
+    import hashlib
+    import json
+    import os
+    _say("full size: bulk root against the oracle's record")
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "bulk_root.json")) as fh:
+        rec = json.load(fh)
+
+    def digest(lb, ub):
+        h = hashlib.sha256()
+        h.update(np.ascontiguousarray(lb, dtype="<f8").tobytes())
+        h.update(np.ascontiguousarray(ub, dtype="<f8").tobytes())
+        return h.hexdigest()
+
+    inst = gen.make("bulk", 0)
+    assert digest(inst["lb"], inst["ub"]) == rec["input_sha256"], "generator output changed"
+    assert int(inst["col"].size) == rec["nnz"]
+    I = bp().Instance(inst)
+    rg, glb, gub = gpu_propagate(I, inst)
+    for f, v in rec["result"].items():
+        assert rg[f] == v, (f, rg, rec["result"])
+    integ = inst["vtype"] == 1
+    assert digest(glb[integ], gub[integ]) == rec["integer_bounds_sha256"]
+    if digest(glb[~integ], gub[~integ]) != rec["continuous_bounds_sha256"]:
+        smp = rec["continuous_sample"]
+        v = np.asarray(smp["var"])
+        assert rel_close(glb[v], np.asarray(smp["lb"])) and rel_close(gub[v], np.asarray(smp["ub"]))
 
 
 def test_serving_mix_full_size():
