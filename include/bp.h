@@ -63,7 +63,8 @@ extern "C" {
 #define BP_ROUND_LIMIT 2
 #define BP_EINVAL (-1)     /* malformed input: NaN, lo > hi, unsorted or duplicate
                               columns, explicit zero, index out of range, CSC not
-                              the transpose, probe variable not binary in the base */
+                              the transpose, probe variable not an integer with a
+                              finite base bound */
 #define BP_ENOMEM (-2)     /* device or host allocation failed */
 #define BP_EDEVICE (-3)    /* a HIP call failed */
 #define BP_ECAPACITY (-4)  /* an output buffer is too small (see bp_probe_out) */
@@ -82,6 +83,10 @@ extern "C" {
 #define BP_FLAG_BATCH_SLOTS 16u /* run bp_propagate_batch on the slot engine
                                    (one slot per vector) whatever the batch
                                    size; results are identical */
+#define BP_FLAG_LV_DENSE 64u    /* bp_propagate_batch (one vector per lane): keep
+                                   every vector's records whole even when the
+                                   instance has a base (no overlay on it);
+                                   results are identical */
 #define BP_FLAG_FULL_ROWS 32u   /* bp_propagate: recompute every queued heavy
                                    row from its nonzeros each round instead of
                                    keeping its exact activities up to date
@@ -111,6 +116,10 @@ typedef struct {
     int32_t probe_slots; /* bound vectors in flight during bp_probe; default 512 */
     int32_t heavy_chunk; /* nonzeros per workgroup of a heavy row; default 1024,
                             rounded up to a multiple of 256 */
+    int32_t repair_calls;    /* bp_round: repair procedures per rounding on a
+                                marked path; default 0 (no repair) */
+    int32_t repair_attempts; /* bp_round: attempts per repair; default 8 (0: default) */
+    int32_t repair_shifts;   /* bp_round: shifts per attempt; default 64 (0: default) */
 } bp_options;
 
 typedef struct {
@@ -164,6 +173,11 @@ typedef struct {
     int64_t apply_entries;  /* changed-list entries it took */
     int64_t apply_colent;   /* column entries it walked for accepted changes */
     int64_t apply_corr;     /* heavy-row accumulator corrections it made */
+    int64_t rows_union;     /* distinct rows read per round over all vectors of
+                               a call, summed over rounds (BP_FLAG_COUNT_VARS;
+                               bp_propagate, bp_propagate_batch on the slot
+                               engine and bp_probe; scan rounds not counted) */
+    int64_t nnz_union;      /* nonzeros of those rows */
 } bp_stats;
 
 /* Fill *opt with the defaults. */
@@ -209,8 +223,13 @@ int bp_propagate(bp_instance *h, double *lb, double *ub, const int32_t *changed,
  * is BP_INFEASIBLE are unspecified (with 16 or more vectors they keep the
  * input).  Batches of 16 or more vectors run one vector per lane (bounds
  * stored [variable][vector] in device memory the instance keeps; about
- * 32 B per variable and vector); BP_FLAG_BATCH_SLOTS keeps the slot
- * engine.  Results are the same either way. */
+ * 40 B per variable and vector); BP_FLAG_BATCH_SLOTS keeps the slot
+ * engine.  When the instance has a base (a BP_OK bp_propagate, which may
+ * be a warm start with an empty change list from any box), the lanes read
+ * each vector as an overlay on it: only the records that differ from the
+ * base are stored and read per vector, which suits vectors that are the
+ * base with a few changes (bulk rounding); BP_FLAG_LV_DENSE turns this
+ * off.  Results are the same either way. */
 int bp_propagate_batch(bp_instance *h, int32_t B, double *lb, double *ub,
                        const int64_t *changed_ptr, const int32_t *changed_idx,
                        bp_result *res, void *stream);
@@ -311,11 +330,14 @@ typedef struct {
     int32_t recoveries;   /* times recovery mode was entered */
     int32_t fixed;        /* integer variables fixed at the end */
     int32_t iterations;   /* steps in all */
-    int64_t nnz_propagated; /* over every propagation of both bulks */
+    int64_t nnz_propagated; /* over every propagation of both bulks and of
+                               the repairs */
+    int32_t repairs;      /* repair procedures run (opt.repair_calls at most) */
+    int32_t repaired;     /* of them, the ones that succeeded */
 } bp_round_result;
 
 /* Bound-propagation rounding (the paper's Algorithm 1 with Section 2.3,
- * without the repair procedure and the LP polish): every integer variable of
+ * without the LP polish): every integer variable of
  * the box DEVICE lb/ub [n] with lb < ub is fixed towards the fractional
  * point DEVICE x [n], a bulk at a time, each bulk propagated.
  *   - order: interval width 1, then 2, then wider; then the distance of x
@@ -336,13 +358,63 @@ typedef struct {
  *     infeasible one is accepted (a bulk keeping no member fails); when both
  *     fail, recovery mode (one variable per bulk) is entered, or, if already
  *     in it, the path is marked infeasible and from then on a failed bulk's
- *     members are fixed to their first values without propagation.
+ *     members are fixed to their first values without propagation;
+ *   - with opt.repair_calls > 0 (instance options): while the path is
+ *     marked, each step ends with bp_repair of the current box, with the
+ *     box the call started from as the original box and the attempt and
+ *     shift limits opt.repair_attempts / opt.repair_shifts, until a repair
+ *     succeeds (its box replaces the current one and the mark is cleared)
+ *     or repair_calls repairs have run (Algorithm 1's Run-Repair-Procedure).
  * lb/ub hold the final box on return (every such integer variable fixed).
  * The result is the same bit for bit as the plain sequential procedure.
  * Returns BP_OK (res set), or BP_EINVAL for a null argument, NaN in x or the
  * box, a draw outside [0, 1) or a cached id out of range (lb/ub untouched). */
 int bp_round(bp_instance *h, double *lb, double *ub, const double *x, const double *draws,
              const bp_cache *cache, bp_round_result *res, void *stream);
+
+/* Repair procedure (the paper's Section 2.3, repair passage; Algorithm 1's
+ * Run-Repair-Procedure).  Given a box DEVICE lb/ub [n] whose fixed integer
+ * variables (lb == ub) form a tentative assignment F, and the original box
+ * DEVICE lb0/ub0 [n] containing it, search new values for F:
+ *   - violation of row k at a box: with the activities of propagation,
+ *     fl(minfin - hi) when no minimum term is infinite and minfin >
+ *     fl(hi + feastol); fl(lo - maxfin) when no maximum term is infinite and
+ *     maxfin < fl(lo - feastol); else 0;
+ *   - a shift takes the most violated row (largest violation, then smallest
+ *     index); each F variable j of it with value v and coefficient a gets
+ *     r = fl(-e / a) (hi side) or fl(e / a) (lo side) and the move d of
+ *     magnitude max(1, ceil(|r| - inttol)) with the sign of r, limited to
+ *     lb0 - v <= d <= ub0 - v (an infinite original bound sets no limit);
+ *     d = 0: no candidate.  Its score is the correctly rounded sum, over
+ *     j's rows, of the change of the row's violation when j's terms
+ *     fl(c*v) become fl(c*(v + d)) in fl(fl(act - fl(c*v)) + fl(c*(v+d)));
+ *     the lowest score (then the smallest j) is applied when negative, else
+ *     the repair fails (reason 1);
+ *   - an attempt shifts until no row is violated (more than max_shifts
+ *     shifts: failure, reason 2), then propagates (cold) the original box
+ *     with F's current values.  A result that is not infeasible ends the
+ *     repair: lb/ub become it.  An infeasible one detected in round d ends
+ *     the repair after max_attempts such propagations (reason 3), else the
+ *     next attempt starts from the state of the same propagation after
+ *     d - 1 rounds.
+ * The variables outside F never shift: their bounds are what propagation
+ * from F implies.  A failed repair leaves lb/ub as given.  The result is
+ * the same bit for bit as the plain sequential procedure.
+ * Returns BP_OK (res set: status BP_OK if repaired, BP_INFEASIBLE if not;
+ * reason 0 when repaired), or BP_EINVAL for a null argument, a NaN, lb0 >
+ * ub0, a box outside the original box, max_shifts < 0 or max_attempts < 1
+ * (lb/ub untouched). */
+typedef struct {
+    int32_t status;   /* BP_OK (repaired) or BP_INFEASIBLE */
+    int32_t attempts; /* propagations from the original box */
+    int32_t shifts;   /* shifts applied */
+    int32_t reason;   /* 0 repaired, 1 no shift lowers the violation, 2 shift
+                         limit, 3 attempt limit */
+    int64_t nnz_propagated; /* over the repair's propagations */
+} bp_repair_result;
+
+int bp_repair(bp_instance *h, double *lb, double *ub, const double *lb0, const double *ub0,
+              int32_t max_shifts, int32_t max_attempts, bp_repair_result *res, void *stream);
 
 /* Schedule chosen by bp_autotune. */
 typedef struct {
@@ -419,7 +491,12 @@ typedef struct {
 /* Create a server over `count` loaded instances, each with a base (a
  * feasible bp_propagate was run on it; BP_ESTATE otherwise).  The slot pool
  * holds as many bound vectors as fit in `budget_bytes` of device memory,
- * at most opt->probe_slots (opt NULL: the first instance's options).  The
+ * at most opt->probe_slots (opt NULL: the first instance's options).  Every
+ * slot is sized for the largest instance (its variables, rows, row bins and
+ * heavy chunks), so a request holds one slot whatever its instance: the
+ * budget bounds the slot pool, not each request's own footprint.  The
+ * request queue and the result staging (about 1.2 GB: 2^21 jobs, 2^24
+ * fixings, 2^25 staged implications) are allocated beside the budget.  The
  * instances must outlive the server. */
 int bp_server_create(bp_instance *const *instances, int32_t count, const bp_options *opt,
                      int64_t budget_bytes, void *stream, bp_server **out);

@@ -20,12 +20,13 @@ BP_OK, BP_INFEASIBLE, BP_ROUND_LIMIT = 0, 1, 2
 BP_EINVAL, BP_ENOMEM, BP_EDEVICE, BP_ECAPACITY, BP_ESTATE = -1, -2, -3, -4, -5
 FLAG_FORCE_EXACT, FLAG_TIME_KERNELS, FLAG_HOST_ROUNDS, FLAG_COUNT_VARS, FLAG_BATCH_SLOTS = 1, 2, 4, 8, 16
 FLAG_FULL_ROWS = 32
+FLAG_LV_DENSE = 64
 
 EXPORTS = ["bp_options_default", "bp_load", "bp_propagate", "bp_propagate_batch", "bp_probe",
            "bp_get_base", "bp_kernel_stats", "bp_device_bytes", "bp_free", "bp_last_error",
            "bp_server_create", "bp_server_submit", "bp_server_run", "bp_server_poll",
            "bp_server_results", "bp_server_info", "bp_server_destroy", "bp_autotune",
-           "bp_scores", "bp_probe_order", "bp_round", "bp_scores_noalloc"]
+           "bp_scores", "bp_probe_order", "bp_round", "bp_scores_noalloc", "bp_repair"]
 REQ_PROBE, REQ_PROPAGATE = 0, 1
 
 
@@ -38,7 +39,9 @@ class Options(C.Structure):
     _fields_ = [("feastol", C.c_double), ("inttol", C.c_double), ("tau", C.c_double),
                 ("max_rounds", C.c_int32), ("flags", C.c_uint32),
                 ("heavy_threshold", C.c_int32), ("rounds_per_launch", C.c_int32),
-                ("probe_slots", C.c_int32), ("heavy_chunk", C.c_int32)]
+                ("probe_slots", C.c_int32), ("heavy_chunk", C.c_int32),
+                ("repair_calls", C.c_int32), ("repair_attempts", C.c_int32),
+                ("repair_shifts", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -62,7 +65,8 @@ class Stats(C.Structure):
     _fields_ = [("ms", C.c_double), ("launches", C.c_int64), ("rows", C.c_int64),
                 ("nnz", C.c_int64), ("vars_read", C.c_int64), ("vars_written", C.c_int64),
                 ("rows_kept", C.c_int64), ("nnz_kept", C.c_int64), ("apply_ms", C.c_double),
-                ("apply_entries", C.c_int64), ("apply_colent", C.c_int64), ("apply_corr", C.c_int64)]
+                ("apply_entries", C.c_int64), ("apply_colent", C.c_int64), ("apply_corr", C.c_int64),
+                ("rows_union", C.c_int64), ("nnz_union", C.c_int64)]
 
 
 class Request(C.Structure):
@@ -96,7 +100,15 @@ class Cache(C.Structure):
 class RoundResult(C.Structure):
     _fields_ = [("status", C.c_int32), ("bulks", C.c_int32), ("singles", C.c_int32),
                 ("recoveries", C.c_int32), ("fixed", C.c_int32), ("iterations", C.c_int32),
-                ("nnz_propagated", C.c_int64)]
+                ("nnz_propagated", C.c_int64), ("repairs", C.c_int32), ("repaired", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class RepairResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("attempts", C.c_int32), ("shifts", C.c_int32),
+                ("reason", C.c_int32), ("nnz_propagated", C.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -128,6 +140,9 @@ def load_library(path: str = LIB_PATH):
     lib.bp_probe.restype = C.c_int
     lib.bp_scores.restype = C.c_int
     lib.bp_scores.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(ScoresOut), C.c_void_p]
+    lib.bp_repair.restype = C.c_int
+    lib.bp_repair.argtypes = [C.c_void_p] + [C.c_void_p] * 4 + [C.c_int32, C.c_int32,
+                                                                 C.POINTER(RepairResult), C.c_void_p]
     lib.bp_scores_noalloc.restype = C.c_int
     lib.bp_scores_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(ScoresOut),
                                       C.c_void_p]
@@ -373,6 +388,21 @@ class Instance:
         r = RoundResult()
         _check(_LIB.bp_round(self._h, _dptr(lb), _dptr(ub), _dptr(x), _dptr(draws), cp, C.byref(r),
                              _stream_ptr(stream)))
+        d = r.as_dict()
+        if self.options.repair_calls == 0:
+            # no repair configured: the counts are always 0
+            del d["repairs"], d["repaired"]
+        return d
+
+    def repair(self, lb: torch.Tensor, ub: torch.Tensor, lb0: torch.Tensor, ub0: torch.Tensor,
+               max_shifts: int = 64, max_attempts: int = 8, stream=None) -> dict:
+        """bp_repair: the repair procedure on the box lb/ub (updated in place
+        when repaired) inside the original box lb0/ub0."""
+        self._bounds_ok(lb, ub)
+        self._bounds_ok(lb0, ub0)
+        r = RepairResult()
+        _check(_LIB.bp_repair(self._h, _dptr(lb), _dptr(ub), _dptr(lb0), _dptr(ub0), int(max_shifts),
+                              int(max_attempts), C.byref(r), _stream_ptr(stream)))
         return r.as_dict()
 
     def autotune(self, lb: torch.Tensor, ub: torch.Tensor, vars_: torch.Tensor = None,
@@ -402,7 +432,7 @@ class Instance:
                     vars_read=s.vars_read, vars_written=s.vars_written,
                     rows_kept=s.rows_kept, nnz_kept=s.nnz_kept, apply_ms=s.apply_ms,
                     apply_entries=s.apply_entries, apply_colent=s.apply_colent,
-                    apply_corr=s.apply_corr)
+                    apply_corr=s.apply_corr, rows_union=s.rows_union, nnz_union=s.nnz_union)
 
 
 class Server:

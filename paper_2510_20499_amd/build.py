@@ -11,7 +11,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbp.so")
 SOURCES = ["bp_engine.hip"]
 HEADERS = ["bp_kernels.h", "bp_sum.h", "bp_carry.h", "bp_server.h", "bp_tune.h", "bp_lv.h", "bp_lv_run.h",
-           "bp_scores.h", "bp_scores_run.h", "bp_round.h", "bp_round_run.h"]
+           "bp_scores.h", "bp_scores_run.h", "bp_repair.h", "bp_repair_run.h", "bp_round.h",
+           "bp_round_run.h"]
 
 # -ffp-contract=off: the candidate and sum formulas are evaluated operation
 # by operation (no fused multiply-add), as the parity with the CPU reference

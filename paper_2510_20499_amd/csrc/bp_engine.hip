@@ -103,7 +103,7 @@ struct Engine {
     DevBuf cbits, hhit, allhrec, hacc, hinf, hwid, hact, hcrec[2];
     Shape shape;
     int64_t bytes = 0;
-    DevBuf bnd, cand, vflag, rflag, info, chg, dirty, dlist, dcount, ctl, touched, filt;
+    DevBuf bnd, cand, vflag, rflag, info, chg, dirty, dlist, dcount, ctl, touched, useen, filt;
     DevBuf q[2][NBIN], hrec[2], hpart, hrng;
     // grouped heavy rows of job slots (allocated on request)
     int32_t grouped = 0;
@@ -155,9 +155,14 @@ struct bp_instance {
     // partials; allocated on first use) and sort buffers
     DevBuf sc_chunks, sc_rows, sc_first, sc_work, sc_tmp, sc_keys;
     int64_t sc_nchunks = 0, sc_nlong = 0;
-    // bound-propagation rounding work buffers
+    // bound-propagation rounding work buffers (rd_start: the box the
+    // rounding started from, the repair's original box)
     DevBuf rd_order, rd_order2, rd_flags, rd_small, rd_S, rd_keys, rd_val, rd_keep, rd_mpos;
-    DevBuf rd_mbox, rd_vk, rd_vl, rd_vu, rd_chg, rd_cpos, rd_bcnt;
+    DevBuf rd_mbox, rd_vk, rd_vl, rd_vu, rd_chg, rd_cpos, rd_bcnt, rd_start;
+    // repair work buffers: row activities, candidates of a row, control
+    // record, fixed flags, the box propagated from the original bounds
+    DevBuf rp_sums, rp_cand, rp_ctl, rp_fixed, rp_pl, rp_pu;
+    int64_t max_row_len = 0;
     // stats
     bp_stats stats;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
@@ -181,6 +186,9 @@ extern "C" void bp_options_default(bp_options *o) {
     o->rounds_per_launch = 16;
     o->probe_slots = 512;
     o->heavy_chunk = 1024;
+    o->repair_calls = 0;
+    o->repair_attempts = 8;
+    o->repair_shifts = 64;
 }
 
 extern "C" const char *bp_last_error(void) { return g_err.c_str(); }
@@ -442,6 +450,9 @@ extern "C" int bp_load(const bp_sparse *csr, const bp_sparse *csc, const double 
     if (o.rounds_per_launch <= 0) o.rounds_per_launch = 16;
     if (o.probe_slots <= 0) o.probe_slots = 512;
     if (o.heavy_chunk <= 0) o.heavy_chunk = 1024;
+    if (o.repair_calls < 0) o.repair_calls = 0;
+    if (o.repair_attempts <= 0) o.repair_attempts = 8;
+    if (o.repair_shifts <= 0) o.repair_shifts = 64;
     o.heavy_chunk = (o.heavy_chunk + WG - 1) / WG * WG;
     // CSR validation
     if (csr->ptr[0] != 0 || csr->ptr[m] != nnz) return fail(BP_EINVAL, "CSR ptr must run from 0 to nnz");
@@ -501,7 +512,10 @@ extern "C" int bp_load(const bp_sparse *csr, const bp_sparse *csc, const double 
     h->heavy_chunk = o.heavy_chunk;
     memset(&h->stats, 0, sizeof(h->stats));
     h->row_len.resize(m);
-    for (int64_t k = 0; k < m; ++k) h->row_len[k] = (int32_t)(csr->ptr[k + 1] - csr->ptr[k]);
+    for (int64_t k = 0; k < m; ++k) {
+        h->row_len[k] = (int32_t)(csr->ptr[k + 1] - csr->ptr[k]);
+        h->max_row_len = std::max<int64_t>(h->max_row_len, h->row_len[k]);
+    }
     std::vector<double> side(2 * m);
     for (int64_t k = 0; k < m; ++k) {
         side[2 * k] = row_lo[k] == 0.0 ? 0.0 : row_lo[k];
@@ -605,6 +619,8 @@ static int engine_alloc(std::unique_ptr<Engine> &eng, const Shape &sh, int32_t s
     if (count) {
         if ((rc = E->touched.alloc((size_t)S * nw_var * 4, B))) return rc;
         HIPTRY(hipMemsetAsync(E->touched.p, 0, E->touched.bytes, st));
+        if ((rc = E->useen.alloc((size_t)nw_row * 4, B))) return rc;
+        HIPTRY(hipMemsetAsync(E->useen.p, 0, E->useen.bytes, st));
     }
     if (dirty) {
         if ((rc = E->filt.alloc((size_t)S * FILT_WORDS * 4, B))) return rc;
@@ -693,6 +709,7 @@ static Params engine_params(const Engine &E, const bp_options &opt, int32_t heav
     P.chg_stride = (int64_t)E.cap_slots * P.sn;
     P.ctl = E.ctl.as<Ctl>();
     P.touched = (opt.flags & BP_FLAG_COUNT_VARS) ? E.touched.as<uint32_t>() : nullptr;
+    P.useen = (opt.flags & BP_FLAG_COUNT_VARS) ? E.useen.as<uint32_t>() : nullptr;
     P.overlay = 0;  // jobs read bounds as an overlay on the base
     P.filt = E.filt.as<uint32_t>();
     P.dirty = E.dirty.as<uint32_t>();
@@ -801,6 +818,8 @@ static int run_rounds(bp_instance *h, const Params &P, const JobIO *io, int64_t 
     h->stats.apply_entries += (int64_t)hc.stat_apply_entries;
     h->stats.apply_colent += (int64_t)hc.stat_apply_colent;
     h->stats.apply_corr += (int64_t)hc.stat_apply_corr;
+    h->stats.rows_union += (int64_t)hc.stat_urows;
+    h->stats.nnz_union += (int64_t)hc.stat_unnz;
     return 0;
 }
 
@@ -978,6 +997,17 @@ static int propagate_slots(bp_instance *h, int32_t Bv, double *lb, double *ub,
             P.hcrec[0] = E1.hcrec[0].as<int4>();
             P.hcrec[1] = E1.hcrec[1].as<int4>();
             P.inc_max = (uint32_t)std::max<int64_t>(64, (int64_t)h->n * Bv / BP_INC_DIV);
+            // Limb bound: a build adds at most L pieces below 2^32 to a limb
+            // of a row of L nonzeros, and a round at most 2L more (each of its
+            // variables' old term out, new term in, once per side); after k
+            // rounds |limb| < L 2^32 (1 + 2k), below 2^62 while 1 + 2k <
+            // 2^30 / L.  Rebuilding at least that often keeps carry_round's
+            // precondition whatever max_rounds is.
+            {
+                const int64_t L = std::max<int64_t>(h->max_row_len, 1);
+                const int64_t k = ((int64_t(1) << 30) / L - 1) / 2;
+                P.inc_period = (uint32_t)std::max<int64_t>(1, std::min<int64_t>(k, 1 << 30));
+            }
             HIPTRY(hipMemsetAsync(E1.hacc.p, 0, nh * 2 * HL * 8, st));
             HIPTRY(hipMemsetAsync(E1.hinf.p, 0, nh * 8, st));
             HIPTRY(hipMemsetAsync(E1.hwid.p, 0, nh * 8, st));
@@ -1395,6 +1425,8 @@ extern "C" int bp_probe(bp_instance *h, const int32_t *vars, int32_t k, bp_probe
 
 #include "bp_scores.h"
 #include "bp_scores_run.h"
+#include "bp_repair.h"
+#include "bp_repair_run.h"
 #include "bp_round.h"
 #include "bp_round_run.h"
 #include "bp_server.h"

@@ -120,6 +120,9 @@ struct Ctl {
     // incremental heavy-row activities (see Params::inc)
     uint32_t hbuild[2];              // the round of this parity rebuilds them from the bounds
     uint32_t hcand[2];               // heavy chunk tasks that need candidates (heads decided)
+    // distinct rows per round over all slots, and their nonzeros (byte
+    // accounting of batches: a row read for several vectors counts once)
+    unsigned long long stat_urows, stat_unnz;
 };
 
 // The leading fields of Ctl for the round in progress (its parity's queue
@@ -188,6 +191,8 @@ struct Params {
     Ctl *ctl;
     uint32_t *touched;           // [nslots][snw] bound records read this round
                                  // (only when counting them)
+    uint32_t *useen;             // [srw] rows read this round by any slot (only
+                                 // when counting; one instance)
     // jobs: bounds are an overlay on the instance's base; a slot's own
     // record of var i is valid only where its dirty bit is set
     int32_t overlay;
@@ -239,6 +244,8 @@ struct Params {
     double2 *hact;               // [slot][nheavy] the round's rounded (min, max) finite parts
     int4 *hcrec[2];              // chunk tasks of heavy rows whose head found candidates needed
     uint32_t inc_max;            // changed entries from which the next round rebuilds
+    uint32_t inc_period;         // a rebuild at least every inc_period rounds, so that no
+                                 // carry-save limb can reach 2^62 (see propagate_slots)
 };
 
 // Exact activities of a heavy row at the base bounds: each finite part as a
@@ -463,6 +470,18 @@ __device__ __forceinline__ bool scatter(const Params &P, int s, int i, double cl
     return any;
 }
 
+// Distinct rows read in this round over all slots (accounting mode only):
+// the matrix term of a batch counts a row once per round.
+__device__ __forceinline__ void count_row(const Params &P, int k, int64_t len) {
+    if (!P.useen) return;
+    uint32_t bit = 1u << (k & 31);
+    uint32_t old = atomicOr(&P.useen[k >> 5], bit);
+    if ((old & bit) == 0) {
+        atomicAdd(&P.ctl->stat_urows, 1ull);
+        atomicAdd(&P.ctl->stat_unnz, (unsigned long long)len);
+    }
+}
+
 // Distinct bound records read in this round (accounting mode only).
 __device__ __forceinline__ void count_read(const Params &P, int s, int i) {
     if (!P.touched) return;
@@ -656,6 +675,7 @@ __device__ void light_rows(const Params &P, const uint64_t *q, uint32_t count, u
             sc_nnz += (unsigned long long)(p1 - p0);
         }
     }
+    if (live && gl == 0) count_row(P, k, p1 - p0);
     if (!live) p1 = p0;
     const BView bnd = bview(P, s, I.base);
     Acc mn, mx;
@@ -816,6 +836,7 @@ __device__ void block_row(const Params &P, const uint64_t *q, uint32_t t, WgScra
             sc_nnz += (unsigned long long)(p1 - p0);
         }
     }
+    if (threadIdx.x == 0) count_row(P, k, p1 - p0);
     const BView bnd = bview(P, s, I.base);
     Acc mn, mx;
     acc_zero(mn);
@@ -887,6 +908,7 @@ __device__ void heavy_chunk_activity(const Params &P, int par, uint32_t u, WgScr
     const int64_t r0 = I.row_ptr[k], r1 = I.row_ptr[k + 1];
     int64_t p0 = r0 + (int64_t)c * P.heavy_chunk;
     int64_t p1 = min(r1, p0 + (int64_t)P.heavy_chunk);
+    if (c == 0 && threadIdx.x == 0 && !scan) count_row(P, k, r1 - r0);
     const BView bnd = bview(P, s, I.base);
     Acc mn, mx;
     acc_zero(mn);
@@ -1172,6 +1194,7 @@ __device__ void gh_chunk_corrections(const Params &P, int par, uint32_t t) {
     if (lane == 0) P.ghlive[t] = word;
     const DInst &I = P.I;
     const int64_t r0 = I.row_ptr[k], r1 = I.row_ptr[k + 1];
+    if (c == 0 && lane == 0 && word) count_row(P, k, r1 - r0);
     const int64_t p0 = r0 + (int64_t)c * P.heavy_chunk, p1 = min(r1, p0 + (int64_t)P.heavy_chunk);
     const double2 *own = P.bnd + (size_t)s * P.sn;
     const uint64_t *dm = P.dmaskg + (size_t)g * P.sn;
@@ -1654,6 +1677,8 @@ __global__ void __launch_bounds__(WG) k_end(Params P) {
         size_t words = (size_t)P.nslots * P.snw;
         for (size_t w = threadIdx.x; w < words; w += WG) P.touched[w] = 0u;
     }
+    if (P.useen)
+        for (size_t w = threadIdx.x; w < (size_t)P.srw; w += WG) P.useen[w] = 0u;
     // the next round rebuilds the heavy-row accumulators: start from zero
     if (P.inc && (par ? c_hb0 : c_hb1)) {
         const size_t nh = (size_t)P.inc_slots * P.nheavy;
@@ -1712,7 +1737,8 @@ __global__ void __launch_bounds__(WG) k_apply(Params P) {
     const bool scan_next = P.scan_ok && total >= P.scan_min;
     // many changes: the next round rebuilds the heavy-row accumulators
     // rather than taking that many corrections
-    const bool rebuild_next = P.inc && (scan_next || total >= P.inc_max);
+    const bool periodic = P.inc_period != 0u && (c_round + 1u) % P.inc_period == 0u;
+    const bool rebuild_next = P.inc && (scan_next || total >= P.inc_max || periodic);
     if (scan_now) {
         const size_t g = (size_t)blockIdx.x * WG + threadIdx.x, G = (size_t)gridDim.x * WG;
         for (size_t w = g; w < (size_t)P.snw; w += G) P.cbits[(size_t)par * P.snw + w] = 0u;

@@ -22,6 +22,15 @@
 // wave.  Arithmetic, the order-free integer atomics, the certified sums
 // and the exact fallback are those of the slot engine: a vector's result
 // is the same whichever engine runs it.
+//
+// Overlay mode (the instance has a base box, as the bulk-rounding
+// candidates do: each is the base with a few fixings): a vector's record of
+// variable i is its own record only where dmask[g][i] has its lane set (it
+// differs from the base), else the base's record.  A (row, group) task then
+// reads per nonzero an 8-byte mask word and the 16-byte base record, both
+// shared by the whole group (and the base by every group), and own records
+// only for the lanes that differ: instead of 1 KB per nonzero and group,
+// the records the vectors actually changed.
 #pragma once
 
 namespace bp {
@@ -52,6 +61,8 @@ struct LvParams {
     int32_t B, V, NG;
     int32_t m, n;
     double2 *bnd;        // [n][V]
+    const double2 *base; // [n] base records (overlay mode), else null
+    uint64_t *dmask;     // [NG][n] lanes whose own record is valid (overlay mode)
     longlong2 *cand;     // [n][V] (lower key, upper key)
     uint64_t *vmask;     // [NG][n] vectors with a candidate for the variable
     uint64_t *rmask[2];  // [NG][m] vectors that have the row queued
@@ -92,6 +103,16 @@ __device__ __forceinline__ double rl_f64(double x, int t) {
     return __longlong_as_double(((long long)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
+// The record of variable i for the lane's vector v (group g): its own, or
+// in overlay mode the base's where its lane is not marked.  The mask word
+// and the base record are the same for the whole wave.
+__device__ __forceinline__ double2 lv_rec(const LvParams &P, int g, int i, int v) {
+    if (!P.base) return P.bnd[(size_t)i * P.V + v];
+    const uint64_t dm = P.dmask[(size_t)g * P.n + i];
+    const double2 b0 = P.base[i];
+    return ((dm >> (v & 63)) & 1ull) ? P.bnd[(size_t)i * P.V + v] : b0;
+}
+
 // Wave-local buffer of appends to one list: lane j holds the j-th pending
 // entry; 64 entries (or the end of the wave's work) cost one atomic.
 struct WaveBuf {
@@ -119,13 +140,15 @@ __device__ __forceinline__ void wbuf_push(WaveBuf &w, int32_t x, uint32_t *count
 // The arrays come by value (not the parameter block by reference, which
 // would make every lane copy it to scratch memory on entry).
 __device__ __noinline__ double lv_exact_side(const double *val, const int32_t *col,
-                                             const double2 *bnd, int64_t V, int v, int64_t p0,
+                                             const double2 *bnd, const double2 *base,
+                                             const uint64_t *dm, int64_t V, int v, int64_t p0,
                                              int64_t p1, bool maxside) {
     SuperAcc S;
     sa_zero(S);
     for (int64_t p = p0; p < p1; ++p) {
         double a = val[p];
-        double2 b = bnd[(size_t)col[p] * V + v];
+        const int i = col[p];
+        double2 b = (base && !((dm[i] >> (v & 63)) & 1ull)) ? base[i] : bnd[(size_t)i * V + v];
         double bb = (a > 0.0) != maxside ? b.x : b.y;
         if (!isinf(bb)) sa_add(S, a * bb);
     }
@@ -167,6 +190,38 @@ __device__ __forceinline__ void lv_count_flush(const LvParams &P, const LvCount 
     if (K.vars) atomicAdd(&P.ctl->stat_vars, K.vars);
 }
 
+// Bound records of the nonzeros t0 .. t0 + LV_UNROLL - 1 of a block (column
+// of nonzero t in lane t of cj) for the lane's vector when `need`, issued
+// together: in overlay mode the mask words and base records first (the
+// same for the whole wave), then the own records of the marked lanes.
+__device__ __forceinline__ void lv_load(const LvParams &P, int g, int v, bool need, int cj, int t0,
+                                        int len, double2 (&b)[LV_UNROLL]) {
+    if (!P.base) {
+#pragma unroll
+        for (int u = 0; u < LV_UNROLL; ++u) {
+            b[u] = make_double2(0.0, 0.0);
+            if (t0 + u < len && need) b[u] = P.bnd[(size_t)rl_i32(cj, t0 + u) * P.V + v];
+        }
+        return;
+    }
+    uint64_t dm[LV_UNROLL];
+    const uint64_t *dg = P.dmask + (size_t)g * P.n;
+#pragma unroll
+    for (int u = 0; u < LV_UNROLL; ++u) {
+        dm[u] = 0ull;
+        b[u] = make_double2(0.0, 0.0);
+        if (t0 + u < len) {
+            const int i = rl_i32(cj, t0 + u);
+            dm[u] = dg[i];
+            b[u] = P.base[i];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < LV_UNROLL; ++u)
+        if (t0 + u < len && need && ((dm[u] >> (v & 63)) & 1ull))
+            b[u] = P.bnd[(size_t)rl_i32(cj, t0 + u) * P.V + v];
+}
+
 // Activity over nonzeros [q0, q1) of a row (at most 64 per block), for the
 // lanes in `live`.  Columns and coefficients are loaded once per block,
 // one per lane, and broadcast; bound records are loaded LV_UNROLL at a time.
@@ -183,11 +238,7 @@ __device__ __forceinline__ void lv_accumulate(const LvParams &P, int g, int v, b
         }
         for (int t0 = 0; t0 < len; t0 += LV_UNROLL) {
             double2 b[LV_UNROLL];
-#pragma unroll
-            for (int u = 0; u < LV_UNROLL; ++u) {
-                b[u] = make_double2(0.0, 0.0);
-                if (t0 + u < len && live) b[u] = P.bnd[(size_t)rl_i32(cj, t0 + u) * P.V + v];
-            }
+            lv_load(P, g, v, live, cj, t0, len, b);
 #pragma unroll
             for (int u = 0; u < LV_UNROLL; ++u) {
                 if (t0 + u < len) {
@@ -218,11 +269,7 @@ __device__ __forceinline__ void lv_candidates(const LvParams &P, int g, int v, b
         }
         for (int t0 = 0; t0 < len; t0 += LV_UNROLL) {
             double2 b[LV_UNROLL];
-#pragma unroll
-            for (int u = 0; u < LV_UNROLL; ++u) {
-                b[u] = make_double2(0.0, 0.0);
-                if (t0 + u < len && want) b[u] = P.bnd[(size_t)rl_i32(cj, t0 + u) * P.V + v];
-            }
+            lv_load(P, g, v, want, cj, t0, len, b);
 #pragma unroll
             for (int u = 0; u < LV_UNROLL; ++u) {
                 if (t0 + u < len) {
@@ -266,8 +313,9 @@ __device__ __forceinline__ void lv_finish_act(const LvParams &P, int v, bool liv
     R.maxfin = 0.0;
     bool ok_min = live && !P.force_exact && acc_certify(mn, R.minfin);
     bool ok_max = live && !P.force_exact && acc_certify(mx, R.maxfin);
-    if (live && !ok_min) R.minfin = lv_exact_side(P.I.val, P.I.col, P.bnd, P.V, v, p0, p1, false);
-    if (live && !ok_max) R.maxfin = lv_exact_side(P.I.val, P.I.col, P.bnd, P.V, v, p0, p1, true);
+    const uint64_t *dm = P.base ? P.dmask + (size_t)(v >> 6) * P.n : nullptr;
+    if (live && !ok_min) R.minfin = lv_exact_side(P.I.val, P.I.col, P.bnd, P.base, dm, P.V, v, p0, p1, false);
+    if (live && !ok_max) R.maxfin = lv_exact_side(P.I.val, P.I.col, P.bnd, P.base, dm, P.V, v, p0, p1, true);
 }
 
 // One short row for the 64 vectors of group g: activity, row test and
@@ -460,7 +508,7 @@ __global__ void __launch_bounds__(WG) k_lv_apply(LvParams P, int seed) {
             }
             if (mine && active) {
                 double2 *bp = &P.bnd[(size_t)i * P.V + v];
-                const double2 b = *bp;
+                const double2 b = lv_rec(P, g, i, v);
                 const bool is_int = P.I.vtype[i] != 0;
                 const double L = dunkey(kl), U = dunkey(ku);
                 double nl = b.x, nu = b.y;
@@ -481,6 +529,9 @@ __global__ void __launch_bounds__(WG) k_lv_apply(LvParams P, int seed) {
         const uint64_t gm = __ballot(go);
         written += __popcll(gm);
         if (gm == 0) continue;
+        // overlay mode: the written records are the lanes' own from now on
+        // (one wave handles a (variable, group) pair in a round)
+        if (P.base && !seed && lane == 0) P.dmask[(size_t)g * P.n + i] |= gm;
         const int64_t c0 = P.I.col_ptr[i], c1 = P.I.col_ptr[i + 1];
         for (int64_t j0 = c0; j0 < c1; j0 += 64) {
             const int64_t j = j0 + lane;
@@ -591,10 +642,13 @@ __global__ void __launch_bounds__(WG) k_lv_end(LvParams P) {
 // ---------------------------------------------------------------------------
 
 // Bounds in: [B][n] row-major vectors to the [n][V] layout through a
-// 64 x 64 LDS tile; crossed and NaN boxes per vector.
+// 64 x 64 LDS tile; crossed and NaN boxes per vector.  With a base
+// (overlay mode) only records that differ from it are stored, and the
+// lanes that hold one are marked in dmask.
 __global__ void __launch_bounds__(WG) k_lv_pack(const double *lb, const double *ub, double2 *bnd,
                                                 int32_t n, int32_t B, int32_t V, const uint8_t *vtype,
-                                                double feastol, int32_t *box) {
+                                                double feastol, int32_t *box, const double2 *base,
+                                                uint64_t *dmask) {
     __shared__ double2 tile[64][65];
     const int64_t tiles_i = (n + 63) / 64;
     const int ngv = V / 64;
@@ -617,16 +671,30 @@ __global__ void __launch_bounds__(WG) k_lv_pack(const double *lb, const double *
         __syncthreads();
         for (int c = threadIdx.x >> 6; c < 64; c += WG / 64) {
             const int64_t i = i0 + c;
-            if (i < n) bnd[(size_t)i * V + v0 + __lane_id()] = tile[__lane_id()][c];
+            if (i >= n) continue;  // wave-uniform
+            const double2 t = tile[__lane_id()][c];
+            if (!base) {
+                bnd[(size_t)i * V + v0 + __lane_id()] = t;
+                continue;
+            }
+            const double2 b0 = base[i];
+            const bool d = v0 + __lane_id() < B && (t.x != b0.x || t.y != b0.y);
+            if (d) bnd[(size_t)i * V + v0 + __lane_id()] = t;
+            const uint64_t m = __ballot(d);
+            if (__lane_id() == 0) dmask[(size_t)(v0 >> 6) * n + i] = m;
         }
         __syncthreads();
     }
 }
 
-// Bounds out: [n][V] back to [B][n].
+// Bounds out: [n][V] back to [B][n].  In overlay mode only the records the
+// vectors hold of their own are written (the others equal the base, and
+// so the input, which the arrays still hold).
 __global__ void __launch_bounds__(WG) k_lv_unpack(const double2 *bnd, double *lb, double *ub,
-                                                  int32_t n, int32_t B, int32_t V, const uint8_t *wmask) {
+                                                  int32_t n, int32_t B, int32_t V, const uint8_t *wmask,
+                                                  const uint64_t *dmask) {
     __shared__ double2 tile[64][65];
+    __shared__ uint64_t dms[64];
     const int64_t tiles_i = (n + 63) / 64;
     const int ngv = V / 64;
     for (int64_t t = blockIdx.x; t < tiles_i * ngv; t += gridDim.x) {
@@ -636,13 +704,16 @@ __global__ void __launch_bounds__(WG) k_lv_unpack(const double2 *bnd, double *lb
         if (__ballot(wmask[v0 + __lane_id()] != 0) == 0) continue;
         for (int c = threadIdx.x >> 6; c < 64; c += WG / 64) {
             const int64_t i = i0 + c;
-            tile[__lane_id()][c] = i < n ? bnd[(size_t)i * V + v0 + __lane_id()] : make_double2(0.0, 0.0);
+            const uint64_t dm = (dmask && i < n) ? dmask[(size_t)(v0 >> 6) * n + i] : ~0ull;
+            const bool own = (dm >> __lane_id()) & 1ull;
+            tile[__lane_id()][c] = (i < n && own) ? bnd[(size_t)i * V + v0 + __lane_id()] : make_double2(0.0, 0.0);
+            if (__lane_id() == 0) dms[c] = dm;
         }
         __syncthreads();
         for (int r = threadIdx.x >> 6; r < 64; r += WG / 64) {
             const int v = v0 + r;
             const int64_t i = i0 + __lane_id();
-            if (v < B && i < n && wmask[v]) {
+            if (v < B && i < n && wmask[v] && ((dms[__lane_id()] >> r) & 1ull)) {
                 const double2 b = tile[r][__lane_id()];
                 lb[(size_t)v * n + i] = b.x;
                 ub[(size_t)v * n + i] = b.y;
@@ -880,8 +951,8 @@ struct LvEngine {
     int32_t Vcap = 0;
     int64_t lcap = 0, nshort = 0, nlong = 0;
     bool have_touched = false;
-    DevBuf bnd, cand, vmask, rmask[2], qs[2], ql[2], lpart, lrng, lmask, chg, touched, rtouch, vec, vbad, ctl,
-        box, wmask;
+    DevBuf bnd, cand, vmask, dmask, rmask[2], qs[2], ql[2], lpart, lrng, lmask, chg, touched, rtouch, vec, vbad,
+        ctl, box, wmask;
     DevBuf short_rows, long_chunks;  // cold-start tasks of the instance
     hipGraphExec_t graph = nullptr;
     int graph_rounds = 0;

@@ -52,6 +52,7 @@ static int lv_ensure(bp_instance *h, int32_t V, bool count, hipStream_t st) {
         if ((rc = L.bnd.alloc((size_t)n * V * 16, B))) return rc;
         if ((rc = L.cand.alloc((size_t)n * V * 16, B))) return rc;
         if ((rc = L.vmask.alloc((size_t)NG * n * 8, B))) return rc;
+        if ((rc = L.dmask.alloc((size_t)NG * n * 8, B))) return rc;
         for (int p = 0; p < 2; ++p) {
             if ((rc = L.rmask[p].alloc((size_t)NG * m * 8, B))) return rc;
             if ((rc = L.qs[p].alloc((size_t)NG * m * 4, B))) return rc;
@@ -86,7 +87,7 @@ static int lv_ensure(bp_instance *h, int32_t V, bool count, hipStream_t st) {
     return 0;
 }
 
-static LvParams lv_params(const bp_instance *h, int32_t Bp, int32_t V, bool count) {
+static LvParams lv_params(const bp_instance *h, int32_t Bp, int32_t V, bool count, bool overlay) {
     LvEngine &L = *h->lv;
     LvParams P;
     memset(&P, 0, sizeof(P));
@@ -103,6 +104,8 @@ static LvParams lv_params(const bp_instance *h, int32_t Bp, int32_t V, bool coun
     P.m = h->m;
     P.n = h->n;
     P.bnd = L.bnd.as<double2>();
+    P.base = overlay ? h->base.as<double2>() : nullptr;
+    P.dmask = L.dmask.as<uint64_t>();
     P.cand = L.cand.as<longlong2>();
     P.vmask = L.vmask.as<uint64_t>();
     for (int p = 0; p < 2; ++p) {
@@ -220,7 +223,10 @@ static int lv_piece(bp_instance *h, int32_t Bp, double *lb, double *ub, const in
     const bool count = (h->opt.flags & BP_FLAG_COUNT_VARS) != 0;
     if (int rc = lv_ensure(h, V, count, st)) return rc;
     LvEngine &L = *h->lv;
-    const LvParams P = lv_params(h, Bp, V, count);
+    // Overlay mode when the instance has a base box (bulk-rounding
+    // candidates are the base with a few fixings); results are identical.
+    const bool overlay = h->have_base && !(h->opt.flags & BP_FLAG_LV_DENSE);
+    const LvParams P = lv_params(h, Bp, V, count, overlay);
     const int64_t n = h->n;
     const int NG = P.NG;
     // bounds in, box check
@@ -236,7 +242,7 @@ static int lv_piece(bp_instance *h, int32_t Bp, double *lb, double *ub, const in
         const int64_t tiles = (n + 63) / 64 * NG;
         k_lv_pack<<<(int)std::min<int64_t>(tiles, 8192), WG, 0, st>>>(lb, ub, P.bnd, (int32_t)n, Bp, V,
                                                                      h->vtype.as<uint8_t>(), h->opt.feastol,
-                                                                     L.box.as<int32_t>());
+                                                                     L.box.as<int32_t>(), P.base, P.dmask);
     }
     HIPTRY(hipGetLastError());
     std::vector<int32_t> box(2 * (size_t)V);
@@ -295,7 +301,8 @@ static int lv_piece(bp_instance *h, int32_t Bp, double *lb, double *ub, const in
         HIPTRY(hipMemcpyAsync(L.wmask.p, wm.data(), V, hipMemcpyHostToDevice, st));
         const int64_t tiles = (n + 63) / 64 * NG;
         k_lv_unpack<<<(int)std::min<int64_t>(tiles, 8192), WG, 0, st>>>(P.bnd, lb, ub, (int32_t)n, Bp, V,
-                                                                       L.wmask.as<uint8_t>());
+                                                                       L.wmask.as<uint8_t>(),
+                                                                       P.base ? P.dmask : nullptr);
         HIPTRY(hipGetLastError());
         HIPTRY(hipStreamSynchronize(st));
     }

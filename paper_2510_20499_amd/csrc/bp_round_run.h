@@ -73,6 +73,7 @@ static int round_impl(bp_instance *h, double *lb, double *ub, const double *x, c
     if ((rc = h->rd_vu.grow((size_t)2 * n * 8, h->bytes))) return rc;
     if ((rc = h->rd_chg.grow((size_t)3 * n * 4, h->bytes))) return rc;
     if ((rc = h->rd_cpos.grow((size_t)n * 4, h->bytes))) return rc;
+    if (h->opt.repair_calls > 0 && (rc = h->rd_start.grow((size_t)2 * n * 8, h->bytes))) return rc;
     int32_t *order = h->rd_order.as<int32_t>(), *order2 = h->rd_order2.as<int32_t>();
     uint8_t *flags = h->rd_flags.as<uint8_t>();
     int64_t *tot = h->rd_small.as<int64_t>();               // [0..1] counts
@@ -106,6 +107,13 @@ static int round_impl(bp_instance *h, double *lb, double *ub, const double *x, c
             return fail(BP_EINVAL, "bp_round: incomplete cache");
         if (entries > 0)
             if ((rc = check_ids(h, cache->var, entries, st))) return rc;
+    }
+    // the box the rounding starts from: the repair's original box
+    double *start_l = h->opt.repair_calls > 0 ? h->rd_start.as<double>() : nullptr;
+    double *start_u = start_l ? start_l + n : nullptr;
+    if (start_l) {
+        HIPTRY(hipMemcpyAsync(start_l, lb, (size_t)n * 8, hipMemcpyDeviceToDevice, st));
+        HIPTRY(hipMemcpyAsync(start_u, ub, (size_t)n * 8, hipMemcpyDeviceToDevice, st));
     }
     RdCache C;
     C.k = k;
@@ -219,6 +227,20 @@ static int round_impl(bp_instance *h, double *lb, double *ub, const double *x, c
             }
         }
         HIPTRY(hipGetLastError());
+        // Algorithm 1: on a marked path every step ends with a repair until
+        // one succeeds or the allowed repairs are spent
+        if (infeasible && res->repairs < h->opt.repair_calls) {
+            bp_repair_result rr;
+            if ((rc = rp_run(h, lb, ub, start_l, start_u, h->opt.repair_shifts, h->opt.repair_attempts,
+                             &rr, st)) < 0)
+                return rc;
+            res->repairs += 1;
+            res->nnz_propagated += rr.nnz_propagated;
+            if (rr.status == BP_OK) {
+                res->repaired += 1;
+                infeasible = false;
+            }
+        }
     }
     res->status = infeasible ? BP_INFEASIBLE : BP_OK;
     // integer variables fixed at the end

@@ -43,6 +43,13 @@ __device__ __forceinline__ double2 sc_slacks(double2 sd, double minfin, double m
     return make_double2(sh, sl);
 }
 
+// Exact activities of a row (the repair procedure needs them whole, not
+// only as slacks): finite parts and infinite-term counts.
+struct RowSums {
+    double minfin, maxfin;
+    int32_t nmin, nmax;
+};
+
 __device__ __forceinline__ BView sc_view(const double2 *bnd) {
     BView v;
     v.own = bnd;
@@ -58,7 +65,7 @@ __device__ __forceinline__ BView sc_view(const double2 *bnd) {
 // per lane); the row's slacks are stored.  Reached by whole waves.
 template <int G>
 __device__ void sc_light_unit(const DInst &I, const double2 *bnd, const int32_t *rows,
-                              int64_t count, int64_t unit, double2 *slk) {
+                              int64_t count, int64_t unit, double2 *slk, RowSums *full) {
     const int lane = __lane_id();
     const int gl = lane & (G - 1);
     const int64_t per_wave = 64 / G;
@@ -93,6 +100,7 @@ __device__ void sc_light_unit(const DInst &I, const double2 *bnd, const int32_t 
         if (!okmin) vmin = exact_side(I, view, p0, p1, false);
         if (!okmax) vmax = exact_side(I, view, p0, p1, true);
         slk[k] = sc_slacks(I.side[k], vmin, vmax, mn.ninf, mx.ninf);
+        if (full) full[k] = RowSums{canon0(vmin), canon0(vmax), mn.ninf, mx.ninf};
     }
 }
 
@@ -130,7 +138,7 @@ struct ScRowsWork {
 };
 
 __global__ void __launch_bounds__(WG) k_sc_rows(DInst I, const double2 *bnd, ScRowsWork R,
-                                                Acc *part, double2 *slk) {
+                                                Acc *part, double2 *slk, RowSums *full) {
     __shared__ WgScratch W;
     const int64_t total = R.start[NLIGHT + 1];
     for (int64_t u = blockIdx.x; u < total; u += gridDim.x) {
@@ -143,13 +151,13 @@ __global__ void __launch_bounds__(WG) k_sc_rows(DInst I, const double2 *bnd, ScR
         const int b = NLIGHT - 1 - j;
         const int64_t lu = u - R.start[1 + j];
         switch (b) {
-            case 0: sc_light_unit<1>(I, bnd, R.rows[0], R.count[0], lu, slk); break;
-            case 1: sc_light_unit<2>(I, bnd, R.rows[1], R.count[1], lu, slk); break;
-            case 2: sc_light_unit<4>(I, bnd, R.rows[2], R.count[2], lu, slk); break;
-            case 3: sc_light_unit<8>(I, bnd, R.rows[3], R.count[3], lu, slk); break;
-            case 4: sc_light_unit<16>(I, bnd, R.rows[4], R.count[4], lu, slk); break;
-            case 5: sc_light_unit<32>(I, bnd, R.rows[5], R.count[5], lu, slk); break;
-            default: sc_light_unit<64>(I, bnd, R.rows[b], R.count[b], lu, slk); break;
+            case 0: sc_light_unit<1>(I, bnd, R.rows[0], R.count[0], lu, slk, full); break;
+            case 1: sc_light_unit<2>(I, bnd, R.rows[1], R.count[1], lu, slk, full); break;
+            case 2: sc_light_unit<4>(I, bnd, R.rows[2], R.count[2], lu, slk, full); break;
+            case 3: sc_light_unit<8>(I, bnd, R.rows[3], R.count[3], lu, slk, full); break;
+            case 4: sc_light_unit<16>(I, bnd, R.rows[4], R.count[4], lu, slk, full); break;
+            case 5: sc_light_unit<32>(I, bnd, R.rows[5], R.count[5], lu, slk, full); break;
+            default: sc_light_unit<64>(I, bnd, R.rows[b], R.count[b], lu, slk, full); break;
         }
     }
 }
@@ -158,7 +166,7 @@ __global__ void __launch_bounds__(WG) k_sc_rows(DInst I, const double2 *bnd, ScR
 // takes chunks l, l + 64, ...), certified, else the exact accumulator.
 __global__ void __launch_bounds__(WG) k_sc_combine(DInst I, const double2 *bnd, const int32_t *rows,
                                                    const int64_t *first, int64_t nrows,
-                                                   const Acc *part, double2 *slk) {
+                                                   const Acc *part, double2 *slk, RowSums *full) {
     const int lane = __lane_id();
     const int64_t nwaves = (int64_t)gridDim.x * (WG / 64);
     const BView view = sc_view(bnd);
@@ -183,6 +191,7 @@ __global__ void __launch_bounds__(WG) k_sc_combine(DInst I, const double2 *bnd, 
             if (!okmin) vmin = exact_side(I, view, p0, p1, false);
             if (!okmax) vmax = exact_side(I, view, p0, p1, true);
             slk[k] = sc_slacks(I.side[k], vmin, vmax, A.ninf, B.ninf);
+            if (full) full[k] = RowSums{canon0(vmin), canon0(vmax), A.ninf, B.ninf};
         }
     }
 }

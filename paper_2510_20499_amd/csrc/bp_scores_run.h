@@ -76,11 +76,14 @@ static int sc_tables(bp_instance *h, const std::vector<int32_t> &cold, hipStream
     return 0;
 }
 
+// The exact activity of every row at the packed bounds W.bnd: the slacks
+// into W.act and, when full is not null, the whole activities into full.
+static int sc_rows_run(bp_instance *h, const ScWork &W, RowSums *full, hipStream_t st);
+
 // Bounds in (NaN rejected), then the exact activity of every row, into W.
 static int sc_rows_pass(bp_instance *h, const double *lb, const double *ub, const ScWork &W,
                         hipStream_t st) {
     const int64_t n = h->n;
-    const DInst I = dinst_of(h);
     if (n > 0) {
         k_pack<<<grid_for(n), 256, 0, st>>>(lb, ub, W.bnd, n, 1);
         k_fill_i32<<<1, 64, 0, st>>>(W.flag, 0, 1);
@@ -91,6 +94,11 @@ static int sc_rows_pass(bp_instance *h, const double *lb, const double *ub, cons
         HIPTRY(hipStreamSynchronize(st));
         if (bad) return fail(BP_EINVAL, "NaN bound");
     }
+    return sc_rows_run(h, W, nullptr, st);
+}
+
+static int sc_rows_run(bp_instance *h, const ScWork &W, RowSums *full, hipStream_t st) {
+    const DInst I = dinst_of(h);
     const int32_t *cold = h->cold_rows.as<int32_t>();
     ScRowsWork R;
     R.chunks = h->sc_chunks.as<int4>();
@@ -106,11 +114,12 @@ static int sc_rows_pass(bp_instance *h, const double *lb, const double *ub, cons
     }
     const int64_t units = R.start[NLIGHT + 1];
     if (units > 0)
-        k_sc_rows<<<(int)std::min<int64_t>(units, 8192), WG, 0, st>>>(I, W.bnd, R, W.part, W.act);
+        k_sc_rows<<<(int)std::min<int64_t>(units, 8192), WG, 0, st>>>(I, W.bnd, R, W.part, W.act,
+                                                                      full);
     if (h->sc_nlong > 0)
         k_sc_combine<<<(int)std::min<int64_t>((h->sc_nlong + 3) / 4, 4096), WG, 0, st>>>(
             I, W.bnd, h->sc_rows.as<int32_t>(), h->sc_first.as<int64_t>(), h->sc_nlong, W.part,
-            W.act);
+            W.act, full);
     HIPTRY(hipGetLastError());
     return 0;
 }

@@ -205,6 +205,7 @@ extern "C" int bp_server_create(bp_instance *const *instances, int32_t count, co
     Params P = engine_params(*sv->eng, sv->opt, sv->heavy_chunk, sv->slots);
     P.I = tab[0];
     P.multi = 1;
+    P.useen = nullptr;  // row ids repeat across instances
     P.insts = sv->dinst.as<DInst>();
     P.overlay = 1;
     sv->P = P;
