@@ -67,6 +67,50 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+METRIC = "propagated nnz/s (batched vs plain) + HBM GB/s; p50/p99 probe latency"
+
+# Oracle threads of the all-cores CPU baselines: the host's cores, at most
+# the 16 a one-GPU share of the machine holds.
+CPU_POOL_MAX = 16
+
+
+def inst_sha256(inst):
+    """sha256 of an instance's arrays (row pointers, columns, coefficients,
+    sides, types, bounds), as generated: what the record was measured on."""
+    import hashlib
+    import numpy as np
+    h = hashlib.sha256()
+    for k in ("row_ptr", "col", "val", "lo", "hi", "vtype", "lb", "ub"):
+        h.update(np.ascontiguousarray(inst[k]).tobytes())
+    return h.hexdigest()
+
+
+def cpu_info():
+    """Host CPU model and logical core count (recorded with every CPU leg)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "model": model}
+
+
+def oracle_pool(fn, items):
+    """Run fn over items on a pool of threads, each calling the unchanged
+    single-threaded oracle (its C calls release the interpreter lock).
+    Returns (results, wall seconds, threads)."""
+    from concurrent.futures import ThreadPoolExecutor
+    threads = max(1, min(CPU_POOL_MAX, os.cpu_count() or 1, len(items)))
+    t = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        out = list(ex.map(fn, items))
+    return out, time.perf_counter() - t, threads
+
+
 def fresh(*ts):
     """Clones of device tensors (a call's in/out bounds)."""
     return tuple(t.clone() for t in ts)
@@ -142,7 +186,7 @@ def main():
     ap.add_argument("--only-serving", action="store_true")
     ap.add_argument("--serve-instances", type=int, default=64)
     ap.add_argument("--serve-mmax", type=float, default=1e6)
-    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-rounds", type=int, default=4,
                     help="rounds per server step between admissions")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
@@ -162,6 +206,15 @@ def main():
                     help="run only the double-probing measurement (for profilers)")
     ap.add_argument("--probe-cpu", type=int, default=16,
                     help="binaries the oracle probes for a CPU probing rate (0: skip)")
+    ap.add_argument("--skip-tiny", action="store_true",
+                    help="skip the Tiny workload (propagation and double probing of 150 binaries)")
+    ap.add_argument("--bulk-light", type=float, default=0.002,
+                    help="fraction of the unfixed integers each vector of the multi-round bulk leg "
+                         "fixes (0: skip that leg)")
+    ap.add_argument("--bulk-fp-rounds", type=int, default=5000,
+                    help="round limit of the fixed-point root of the multi-round bulk leg")
+    ap.add_argument("--bulk-cpu", type=int, default=8,
+                    help="bulk vectors the oracle propagates one thread for the CPU baseline (0: skip)")
     ap.add_argument("--skip-round", action="store_true",
                     help="skip the bound-propagation rounding measurement")
     ap.add_argument("--only-round", action="store_true")
@@ -245,7 +298,7 @@ def main():
         if other["avg_launch_us"] > roofline["avg_launch_us"]:
             roofline, other = other, roofline
 
-    cpu = None
+    cpu = cpu_all = None
     if not args.no_cpu_baseline:
         import oracle
         reps_cpu = 0
@@ -260,15 +313,23 @@ def main():
         assert ro["nnz_propagated"] == r["nnz_propagated"] and ro["rounds"] == r["rounds"]
         cpu = {"value": nnz_cpu / t_cpu, "unit": "nnz/s", "cores": 1, "kind": "oracle",
                "sample": "%d cold propagation(s) of the full single-instance workload, "
-                         "worklist mode, one thread" % reps_cpu}
+                         "worklist mode, one thread" % reps_cpu, "host": cpu_info()}
+        outs, wall, thr = oracle_pool(lambda _: oracle.propagate(inst)[0]["nnz_propagated"],
+                                      list(range(min(CPU_POOL_MAX, os.cpu_count() or 1))))
+        cpu_all = {"value": sum(outs) / wall, "unit": "nnz/s", "cores": thr, "kind": "oracle",
+                   "sample": "%d independent cold propagations of the full single-instance "
+                             "workload, one per thread, unchanged single-threaded oracle" % len(outs),
+                   "host": cpu_info()}
+        log("cpu: one thread %.3g nnz/s, %d threads %.3g nnz/s" % (cpu["value"], thr, cpu_all["value"]))
 
+    tiny = None if args.skip_tiny else bench_tiny(args, bp, gen, torch, np)
     rounding = None if args.skip_round else bench_round(args, bp, gen, torch, np, inst=inst, I=I)
     probe = None if args.skip_probe else bench_probe(args, bp, gen, torch, np)
     bulk = None if args.skip_bulk else bench_bulk(args, bp, gen, torch, np)
     serving = None if args.skip_serving else bench_serving(args, bp, gen, torch, np)
 
     out = {
-        "metric": "propagated nnz/s (plain cold propagation, single instance)",
+        "metric": METRIC,
         "value": value,
         "unit": "nnz/s",
         "n_gpus": 1,
@@ -282,18 +343,87 @@ def main():
         "data": "synthetic (seeded generator standing in for MIPLIB2017)",
         "config": {"workload": "single-instance plain propagation: m=%d, n=%d, nnz=%d, cold start "
                                "to fixed point with changed-row worklist" % (m, n, nnz),
-                   "m": m, "n": n, "nnz": nnz, "seed": args.seed,
+                   "m": m, "n": n, "nnz": nnz, "seed": args.seed, "sha256": inst_sha256(inst),
                    "rounds": r["rounds"], "nnz_propagated_per_step": r["nnz_propagated"],
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "roofline_other": other,
         "cpu_baseline": cpu,
+        "cpu_baseline_all_cores": cpu_all,
+        "batched_vs_plain": {
+            "probe": None if probe is None else {
+                k: probe[k] for k in ("batched_nnz_per_s", "plain_nnz_per_s", "batched_probes_per_s",
+                                      "plain_probes_per_s", "batched_over_plain")},
+            "bulk": None if bulk is None else {
+                k: bulk[k] for k in ("batched_nnz_per_s", "plain_nnz_per_s", "batched_vectors_per_s",
+                                     "plain_vectors_per_s", "batched_over_plain")},
+            "serving": None if serving is None else {
+                k: serving[k] for k in ("saturated_requests_per_s", "throughput_over_fifo")},
+        },
+        "tiny": tiny,
         "rounding": rounding,
         "probe_batched": probe,
         "bulk_batched": bulk,
         "serving": serving,
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_tiny(args, bp, gen, torch, np):
+    """The Tiny workload (m=200, n=300: 150 binaries, 100 integers in
+    [0, 10], 50 continuous; 4-6 nonzeros per row, integer coefficients),
+    seeds 0-9: a cold propagation to the fixed point, then double probing of
+    all 150 binaries around it, with the instance resident.  Latency-bound:
+    reported as time per instance and rounds, beside the oracle doing the
+    same on one thread."""
+    dev = torch.device("cuda:0")
+    seeds = list(range(10))
+    gpu_ms, rounds, nnz, probes = [], [], 0, 0
+    insts = [gen.make("tiny", s) for s in seeds]
+    for inst in insts:
+        I = bp.Instance(inst)
+        lb0 = torch.tensor(inst["lb"], dtype=torch.float64, device=dev)
+        ub0 = torch.tensor(inst["ub"], dtype=torch.float64, device=dev)
+        binv = np.nonzero((inst["vtype"] == 1) & (inst["lb"] == 0) & (inst["ub"] == 1))[0].astype(np.int32)
+        bins = torch.tensor(binv, dtype=torch.int32, device=dev)
+
+        def call():
+            lb, ub = fresh(lb0, ub0)
+            r = I.propagate(lb, ub)
+            G = I.probe(bins)
+            torch.cuda.synchronize()
+            return r, G
+
+        call()  # warm
+        t = time.perf_counter()
+        reps = 20
+        for _ in range(reps):
+            r, G = call()
+        gpu_ms.append((time.perf_counter() - t) / reps * 1e3)
+        rounds.append(r["rounds"])
+        nnz += r["nnz_propagated"] + int(G["nnz"].sum().item())
+        probes += 2 * binv.size
+        del I
+    res = {"workload": "tiny: m=200, n=300 (150 binaries), seeds 0-9; cold propagation to the "
+                       "fixed point, then double probing of all 150 binaries",
+           "ms_per_instance_median": float(np.median(gpu_ms)),
+           "ms_per_instance": [round(x, 4) for x in gpu_ms],
+           "rounds": rounds, "probes_per_instance": probes // len(seeds),
+           "nnz_per_s": nnz / (sum(gpu_ms) * 1e-3)}
+    if not args.no_cpu_baseline:
+        import oracle
+        t = time.perf_counter()
+        for inst in insts:
+            ro, lo, uo = oracle.propagate(inst)
+            binv = np.nonzero((inst["vtype"] == 1) & (inst["lb"] == 0) & (inst["ub"] == 1))[0]
+            oracle.probe(inst, lo, uo, binv.astype(np.int32))
+        tc = (time.perf_counter() - t) / len(insts)
+        res["cpu_baseline"] = {"value": tc * 1e3, "unit": "ms per instance", "cores": 1,
+                               "kind": "oracle", "sample": "the same ten instances, one thread",
+                               "host": cpu_info()}
+    log("tiny: %.3f ms per instance (median), oracle %s ms"
+        % (res["ms_per_instance_median"], res.get("cpu_baseline", {}).get("value")))
+    return res
 
 
 def _round_inputs(inst, lb, ub, seed, np):
@@ -423,6 +553,7 @@ def bench_probe(args, bp, gen, torch, np):
     res = {
         "workload": "double probing: m=%d, n=%d, nnz=%d; %d binaries x {0,1} = %d bound vectors"
                     % (inst["m"], inst["n"], int(inst["row_ptr"][-1]), k, 2 * k),
+        "sha256": inst_sha256(inst),
         "batched_probes_per_s": 2 * k / tb,
         "batched_nnz_per_s": nnz_b / tb,
         "batched_ms": tb * 1e3,
@@ -435,6 +566,10 @@ def bench_probe(args, bp, gen, torch, np):
         "implied_entries": int(G["off"][-1].item()),
         "infeasible_probes": int((G["status"] == bp.BP_INFEASIBLE).sum().item()),
     }
+    res["roofline"] = probe_roofline(bp, inst, lb, ub, vars_d, cap, tb, torch)
+    log("probe: batched %.2f ms, k_rows %.1f GB/s (%.4f of peak), call %.1f GB/s"
+        % (tb * 1e3, res["roofline"]["achieved"], res["roofline"]["frac"],
+           res["roofline"]["call_alg_GBps"]))
     res["scores"] = bench_scores(args, bp, inst, I, lb, ub, torch, np)
     if args.probe_cpu:
         import oracle
@@ -446,8 +581,60 @@ def bench_probe(args, bp, gen, torch, np):
         res["cpu_baseline"] = {"value": 2 * kc / tc, "unit": "probes/s", "cores": 1,
                                "kind": "oracle", "nnz_per_s": float(O["nnz"].sum()) / tc,
                                "sample": "%d binaries x {0,1} of the same sample, around the "
-                                         "oracle's own root fixed point, one thread" % kc}
+                                         "oracle's own root fixed point, one thread" % kc,
+                               "host": cpu_info()}
+        per = args.probe_cpu
+        chunks = [vs[kc + j * per: kc + (j + 1) * per] for j in range(min(CPU_POOL_MAX, os.cpu_count() or 1))]
+        chunks = [c for c in chunks if c.size]
+        outs, wall, thr = oracle_pool(lambda c: float(oracle.probe(inst, olb, oub, c)["nnz"].sum()), chunks)
+        nb = sum(c.size for c in chunks)
+        res["cpu_baseline_all_cores"] = {
+            "value": 2 * nb / wall, "unit": "probes/s", "cores": thr, "kind": "oracle",
+            "nnz_per_s": sum(outs) / wall,
+            "sample": "%d further binaries x {0,1} of the same sample, %d per thread, unchanged "
+                      "single-threaded oracle" % (nb, per), "host": cpu_info()}
     return res
+
+
+def probe_roofline(bp, inst, lb, ub, vars_d, cap, t_call, torch):
+    """Roofline of the activity kernel k_rows in the batched double probing.
+    Bytes (the algorithmic count for a batch): the matrix term once per row
+    and round over the union of the slots' worklists -- 12 B per nonzero and
+    24 B per row -- plus, per vector, 16 B per distinct bound record read;
+    counted by an instrumented run of the same call (the base of the
+    instrumented instance is the same root), divided by its launches.  Time:
+    HIP events around every k_rows launch (rounds driven from the host),
+    average over the launches of one call.  Also the whole call's
+    algorithmic bytes (bound records written too) over its measured time."""
+    def run(flags):
+        J = bp.Instance(inst, bp.default_options(flags=flags))
+        l2, u2 = fresh(lb, ub)
+        J.propagate(l2, u2, torch.zeros(0, dtype=torch.int32, device=lb.device))
+        J.kernel_stats(reset=True)
+        J.probe(vars_d, cap=cap)
+        torch.cuda.synchronize()
+        st = J.kernel_stats(reset=True)
+        del J
+        return st
+
+    cs = run(bp.FLAG_COUNT_VARS)
+    run(bp.FLAG_TIME_KERNELS)  # warm
+    ts = run(bp.FLAG_TIME_KERNELS)
+    launches = max(ts["launches"], 1)
+    rows_bytes = 12 * cs["nnz_union"] + 24 * cs["rows_union"] + 16 * cs["vars_read"]
+    per_launch = rows_bytes / launches
+    avg_ms = ts["ms"] / launches
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    call_bytes = rows_bytes + 16 * cs["vars_written"]
+    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 5), "traffic": None, "kernel": "k_rows",
+            "avg_launch_us": round(avg_ms * 1e3, 3), "launches_per_call": ts["launches"],
+            "alg_bytes_per_launch": int(per_launch),
+            "union_rows": cs["rows_union"], "union_nnz": cs["nnz_union"],
+            "task_rows": cs["rows"], "task_nnz": cs["nnz"], "vars_read": cs["vars_read"],
+            "call_alg_bytes": int(call_bytes), "call_alg_GBps": round(call_bytes / t_call / 1e9, 2),
+            "call_frac": round(call_bytes / t_call / 1e9 / HBM_PEAK_GBPS, 5),
+            "k_rows_share_of_call": round(ts["ms"] * 1e-3 / t_call, 3)}
 
 
 def bench_scores(args, bp, inst, I, lb, ub, torch, np):
@@ -528,6 +715,10 @@ def bench_bulk(args, bp, gen, torch, np):
     rl, ru = fresh(lb0, ub0)
     root = I.propagate(rl, ru)
     assert root["status"] in (bp.BP_OK, bp.BP_ROUND_LIMIT), root
+    # the root becomes the instance's base (a warm start with an empty change
+    # list): the batched calls then read each candidate as an overlay on it
+    empty = torch.zeros(0, dtype=torch.int32, device=dev)
+    assert I.propagate(*fresh(rl, ru), empty)["rounds"] == 0
     # cold root propagation at this size (plain path)
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -604,8 +795,60 @@ def bench_bulk(args, bp, gen, torch, np):
             nnz_p += r1[0]["nnz_propagated"]
             assert r1[0] == res[v], (v, r1[0], res[v])
     log("bulk: plain %.2f ms per vector" % (tp / kp * 1e3))
-    roof = kernel_roofline(bp, inst, batch_call, reps=2, kernel="k_lv_rows", **opt_kw)
+    def with_base(J):
+        # the base is set once per instance, before the counted or timed
+        # calls (its warm start runs no round of the lane kernels)
+        if not getattr(J, "bench_base_set", False):
+            J.propagate(*fresh(rl, ru), empty)
+            J.kernel_stats(reset=True)
+            J.bench_base_set = True
+        return batch_call(J)
+
+    roof = kernel_roofline(bp, inst, with_base, reps=2, kernel="k_lv_rows", **opt_kw)
+    cpu = cpu_all = None
+    if args.bulk_cpu and not args.no_cpu_baseline:
+        # The oracle's own root of this size takes minutes, so the CPU legs
+        # start from its first three rounds (a valid box of the same
+        # workload); the vectors fix 5% of its unfixed integers as above.
+        import oracle
+        oo = oracle.Options()
+        oo.max_rounds = 3
+        t = time.perf_counter()
+        _, olb, oub = oracle.propagate(inst, opts=oo)
+        t_root3 = time.perf_counter() - t
+        olists = gen.bulk_fix_lists(inst, olb, oub, B, frac=0.05, seed=args.seed)
+
+        def one(v):
+            p, val = olists[v]
+            l2, u2 = olb.copy(), oub.copy()
+            l2[p] = val
+            u2[p] = val
+            return oracle.propagate(inst, l2, u2, changed=p)[0]["nnz_propagated"]
+
+        kc = min(args.bulk_cpu, B)
+        t = time.perf_counter()
+        nn = sum(one(v) for v in range(kc))
+        tc = time.perf_counter() - t
+        cpu = {"value": kc / tc, "unit": "vectors/s", "cores": 1, "kind": "oracle",
+               "nnz_per_s": nn / tc,
+               "extrapolated_ms_per_%d_vectors" % B: tc / kc * B * 1e3,
+               "sample": "%d of the %d vectors (fixing 5%% each), from the oracle's first three "
+                         "root rounds (%.1f s, not included), one thread; a call of %d vectors "
+                         "extrapolated" % (kc, B, t_root3, B), "host": cpu_info()}
+        items = list(range(kc, min(B, kc + 2 * min(CPU_POOL_MAX, os.cpu_count() or 1))))
+        outs, wall, thr = oracle_pool(one, items)
+        cpu_all = {"value": len(items) / wall, "unit": "vectors/s", "cores": thr, "kind": "oracle",
+                   "nnz_per_s": sum(outs) / wall,
+                   "sample": "%d further vectors, two per thread, unchanged single-threaded oracle"
+                             % len(items), "host": cpu_info()}
+        log("bulk: oracle %.2f vectors/s one thread, %.2f on %d threads" % (cpu["value"], cpu_all["value"], thr))
+    light = None
+    if args.bulk_light > 0:
+        del LB, UB
+        light = bench_bulk_light(args, bp, gen, torch, np, inst, lb0, ub0, opt_kw, B)
     return {
+        "sha256": inst_sha256(inst),
+        "multi_round_leg": light,
         "workload": "bulk rounding: m=%d, n=%d, nnz=%d; %d vectors per call, each fixing %d "
                     "integer variables (5%%) and propagating"
                     % (inst["m"], inst["n"], int(inst["row_ptr"][-1]), B, int(ptr[1])),
@@ -620,7 +863,81 @@ def bench_bulk(args, bp, gen, torch, np):
                       "nnz_per_s": r["nnz_propagated"] / t_cold},
         "load_s": t_load, "schedule": opt_kw, "tune_trials": tune["trials"],
         "roofline": roof,
+        "cpu_baseline": cpu,
+        "cpu_baseline_all_cores": cpu_all,
     }
+
+
+def bench_bulk_light(args, bp, gen, torch, np, inst, lb0, ub0, opt_kw, B):
+    """Multi-round bulk leg: the root propagated to its fixed point (the bulk
+    workload's cold root needs 1223 rounds; the round limit here is
+    --bulk-fp-rounds), which becomes the instance's base; then B vectors,
+    each fixing a seeded --bulk-light fraction of its unfixed integer
+    variables to rint(U[lb, ub]), so that most stay feasible and propagate
+    for several rounds."""
+    dev = lb0.device
+    o = dict(opt_kw, max_rounds=args.bulk_fp_rounds)
+    I = bp.Instance(inst, bp.default_options(**o))
+    fl, fu = fresh(lb0, ub0)
+    t = time.perf_counter()
+    fp = I.propagate(fl, fu)
+    torch.cuda.synchronize()
+    t_fp = time.perf_counter() - t
+    assert fp["status"] == bp.BP_OK, fp
+    lists = gen.bulk_fix_lists(inst, fl.cpu().numpy(), fu.cpu().numpy(), B, frac=args.bulk_light,
+                               seed=args.seed + 1)
+    ptr = np.zeros(B + 1, np.int64)
+    ptr[1:] = np.cumsum([p.size for p, _ in lists])
+    idx = torch.tensor(np.concatenate([p for p, _ in lists]), dtype=torch.int32, device=dev)
+    vals = torch.tensor(np.concatenate([v for _, v in lists]), dtype=torch.float64, device=dev)
+    vec = torch.repeat_interleave(torch.arange(B, device=dev), torch.tensor(np.diff(ptr), device=dev))
+    flat = vec * inst["n"] + idx.long()
+    ptr_d = torch.tensor(ptr, dtype=torch.int64, device=dev)
+    LB = torch.empty(B, inst["n"], dtype=torch.float64, device=dev)
+    UB = torch.empty_like(LB)
+    empty = torch.zeros(0, dtype=torch.int32, device=dev)
+
+    def call(J):
+        if not getattr(J, "bench_base_set", False):
+            J.propagate(*fresh(fl, fu), empty)
+            J.kernel_stats(reset=True)
+            J.bench_base_set = True
+        LB.copy_(fl.expand(B, -1))
+        UB.copy_(fu.expand(B, -1))
+        LB.view(-1)[flat] = vals
+        UB.view(-1)[flat] = vals
+        return J.propagate_batch(LB, UB, ptr_d, idx)
+
+    res = call(I)  # warm
+    torch.cuda.synchronize()
+    tb = 0.0
+    reps = 3
+    for _ in range(reps):
+        LB.copy_(fl.expand(B, -1))
+        UB.copy_(fu.expand(B, -1))
+        LB.view(-1)[flat] = vals
+        UB.view(-1)[flat] = vals
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = I.propagate_batch(LB, UB, ptr_d, idx)
+        torch.cuda.synchronize()
+        tb += time.perf_counter() - t
+    tb /= reps
+    nnz_b = sum(x["nnz_propagated"] for x in res)
+    status = np.array([x["status"] for x in res])
+    rounds = np.array([x["rounds"] for x in res])
+    log("bulk light: %.1f ms per call, rounds mean %.2f, %d infeasible"
+        % (tb * 1e3, rounds.mean(), int((status == bp.BP_INFEASIBLE).sum())))
+    roof = kernel_roofline(bp, inst, call, reps=2, kernel="k_lv_rows", **o)
+    del LB, UB
+    return {"workload": "bulk rounding from the fixed-point root (%d rounds): %d vectors per call, "
+                        "each fixing %d integer variables (%.1f%%) and propagating"
+                        % (fp["rounds"], B, int(ptr[1]), 100 * args.bulk_light),
+            "root_fixed_point": {"rounds": fp["rounds"], "ms": t_fp * 1e3},
+            "batched_ms": tb * 1e3, "batched_nnz_per_s": nnz_b / tb, "batched_vectors_per_s": B / tb,
+            "infeasible": int((status == bp.BP_INFEASIBLE).sum()),
+            "rounds_mean": float(rounds.mean()), "rounds_max": int(rounds.max()),
+            "nnz_per_vector_mean": nnz_b / B, "roofline": roof}
 
 
 def bench_serving(args, bp, gen, torch, np):
@@ -632,7 +949,7 @@ def bench_serving(args, bp, gen, torch, np):
     Poisson arrivals at 0.5 C and 0.9 C report p50/p99 latency.  Baseline:
     the same requests served one at a time in arrival order (FIFO) with
     bp_propagate / bp_probe, its latency derived from measured service times
-    and the same arrival times."""
+    and the same arrival trace as the server's run at that load."""
     import math
     dev = torch.device("cuda:0")
     t_gen = time.perf_counter()
@@ -728,13 +1045,17 @@ def bench_serving(args, bp, gen, torch, np):
     out = {"workload": "%d instances, m log-uniform [1e3, %g], %d nnz resident; %d requests "
                        "(50%% propagate fixing 1%% of binaries, 50%% probe k~exp U[0, ln 512])"
                        % (len(insts), args.serve_mmax, nnz_total, len(reqs)),
+           "sha256_of_instance_digests": __import__("hashlib").sha256(
+               "".join(inst_sha256(x) for x in insts).encode()).hexdigest(),
            "slots": info["slots"], "bytes_per_slot": info["bytes_per_slot"],
            "generate_s": t_gen, "saturated_requests_per_s": C,
            "saturated_p50_ms": float(np.percentile(lat_sat, 50)) / 1e3,
            "saturated_p99_ms": float(np.percentile(lat_sat, 99)) / 1e3}
+    # one Poisson arrival trace per load, served both by the server and by
+    # the FIFO baseline below
+    traces = {frac: np.cumsum(rng.exponential(1.0 / (frac * C), size=len(reqs))) for frac in (0.5, 0.9)}
     for frac in (0.5, 0.9):
-        gaps = rng.exponential(1.0 / (frac * C), size=len(reqs))
-        arrivals = np.cumsum(gaps)
+        arrivals = traces[frac]
         el, lat = run_trace(arrivals)
         log("serving: load %g done in %.1f s" % (frac, el))
         out["load_%g" % frac] = {"offered_per_s": frac * C, "served_per_s": len(reqs) / el,
@@ -788,8 +1109,7 @@ def bench_serving(args, bp, gen, torch, np):
         torch.cuda.synchronize()
     base = {"saturated_requests_per_s": len(reqs) / svc.sum()}
     for frac in (0.5, 0.9):
-        rng2 = np.random.default_rng(args.seed + int(frac * 100))
-        arrivals = np.cumsum(rng2.exponential(1.0 / (frac * C), size=len(reqs)))
+        arrivals = traces[frac]
         finish = np.zeros(len(reqs))
         tcur = 0.0
         for j in range(len(reqs)):
