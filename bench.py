@@ -686,10 +686,12 @@ def bench_scores(args, bp, inst, I, lb, ub, torch, np):
 def bench_bulk(args, bp, gen, torch, np):
     """Bulk-rounding fix-and-propagate on the bulk workload (m=2M, n=3M,
     50% binary, 30% integer in [0,1000], ~20M nnz): B bound vectors per
-    call, each the root fixed point with a seeded 5% of the unfixed integer
-    variables fixed to rint(U[lb, ub]), propagated from their changed lists
-    with bp_propagate_batch.  The schedule comes from the autotuner.  Plain:
-    the same vectors one per call."""
+    call, each the root with a seeded 5% of the unfixed integer variables
+    fixed to rint(U[lb, ub]), propagated from their changed lists with
+    bp_propagate_batch.  The schedule comes from the autotuners: the
+    slot-engine knobs from a cold propagation (bp_autotune), the lane
+    engine's workgroups per round kernel and rounds per graph from this
+    batch (bp_autotune_batch).  Plain: the same vectors one per call."""
     dev = torch.device("cuda:0")
     B = args.bulk_vectors
     t = time.perf_counter()
@@ -750,6 +752,13 @@ def bench_bulk(args, bp, gen, torch, np):
         return J.propagate_batch(LB, UB, ptr_d, idx)
 
     log("bulk: %d vectors of %d fixings ready" % (B, int(ptr[1])))
+    if not args.profile_bulk:
+        # the lane engine's schedule, timed on this batch itself
+        restore()
+        tb_tune = I.autotune_batch(LB, UB, ptr_d, idx)
+        opt_kw.update(lv_grid=tb_tune["lv_grid"], rounds_per_launch=tb_tune["rounds_per_launch"])
+        tune["trials"] += tb_tune["trials"]
+        log("bulk: lane schedule %s" % tb_tune)
     res = batch_call(I)  # warm
     torch.cuda.synchronize()
     if args.profile_bulk:
@@ -873,8 +882,9 @@ def bench_bulk_light(args, bp, gen, torch, np, inst, lb0, ub0, opt_kw, B):
     workload's cold root needs 1223 rounds; the round limit here is
     --bulk-fp-rounds), which becomes the instance's base; then B vectors,
     each fixing a seeded --bulk-light fraction of its unfixed integer
-    variables to rint(U[lb, ub]), so that most stay feasible and propagate
-    for several rounds."""
+    variables to the planted point's values (random values in the bounds
+    make every vector infeasible in its first round), so that the vectors
+    stay feasible and propagate for several rounds."""
     dev = lb0.device
     o = dict(opt_kw, max_rounds=args.bulk_fp_rounds)
     I = bp.Instance(inst, bp.default_options(**o))
@@ -885,7 +895,7 @@ def bench_bulk_light(args, bp, gen, torch, np, inst, lb0, ub0, opt_kw, B):
     t_fp = time.perf_counter() - t
     assert fp["status"] == bp.BP_OK, fp
     lists = gen.bulk_fix_lists(inst, fl.cpu().numpy(), fu.cpu().numpy(), B, frac=args.bulk_light,
-                               seed=args.seed + 1)
+                               seed=args.seed + 1, point=inst["xstar"])
     ptr = np.zeros(B + 1, np.int64)
     ptr[1:] = np.cumsum([p.size for p, _ in lists])
     idx = torch.tensor(np.concatenate([p for p, _ in lists]), dtype=torch.int32, device=dev)
@@ -931,7 +941,8 @@ def bench_bulk_light(args, bp, gen, torch, np, inst, lb0, ub0, opt_kw, B):
     roof = kernel_roofline(bp, inst, call, reps=2, kernel="k_lv_rows", **o)
     del LB, UB
     return {"workload": "bulk rounding from the fixed-point root (%d rounds): %d vectors per call, "
-                        "each fixing %d integer variables (%.1f%%) and propagating"
+                        "each fixing %d integer variables (%.1f%%) to the planted point's values "
+                        "and propagating"
                         % (fp["rounds"], B, int(ptr[1]), 100 * args.bulk_light),
             "root_fixed_point": {"rounds": fp["rounds"], "ms": t_fp * 1e3},
             "batched_ms": tb * 1e3, "batched_nnz_per_s": nnz_b / tb, "batched_vectors_per_s": B / tb,

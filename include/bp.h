@@ -120,6 +120,9 @@ typedef struct {
                                 marked path; default 0 (no repair) */
     int32_t repair_attempts; /* bp_round: attempts per repair; default 8 (0: default) */
     int32_t repair_shifts;   /* bp_round: shifts per attempt; default 64 (0: default) */
+    int32_t lv_grid;         /* bp_propagate_batch, one vector per lane: workgroups
+                                per round kernel over all vector groups; default
+                                2048 (0: default) */
 } bp_options;
 
 typedef struct {
@@ -425,6 +428,8 @@ typedef struct {
     double ms;                 /* time of the chosen schedule on the workload */
     int32_t trials;            /* schedules timed (0: taken from the cache) */
     int32_t from_cache;
+    int32_t lv_grid;           /* bp_autotune_batch: lane-engine workgroups per round
+                                  kernel (0: not tuned) */
 } bp_tuning;
 
 /* Autotuner: time candidate schedules (heavy-row threshold and chunk size,
@@ -438,6 +443,21 @@ typedef struct {
  * left at the cold propagation's result. */
 int bp_autotune(bp_instance *h, const double *lb, const double *ub, const int32_t *vars,
                 int32_t k, const char *cache_path, bp_tuning *out, void *stream);
+
+/* Autotuner of batched propagation: time bp_propagate_batch of the caller's
+ * own batch (B vectors DEVICE lb/ub [B*n] with changed_ptr/changed_idx as
+ * bp_propagate_batch takes them; left unchanged: each trial starts from a
+ * copy) over the schedules of the engine that runs it -- for 16 or more
+ * vectors the lane engine's workgroups per round kernel (lv_grid) and the
+ * rounds per captured graph -- and keep the fastest in the instance's
+ * options.  Every schedule gives the same results (checked per vector on
+ * every trial).  With cache_path != NULL the choice is read from / appended
+ * to that text file, keyed by the device architecture, the instance
+ * signature and the batch size.  Returns BP_OK, or an error of the batch
+ * call. */
+int bp_autotune_batch(bp_instance *h, int32_t B, const double *lb, const double *ub,
+                      const int64_t *changed_ptr, const int32_t *changed_idx, const char *cache_path,
+                      bp_tuning *out, void *stream);
 
 /* Copy the base bounds into DEVICE lb/ub [n].  BP_ESTATE without a base. */
 int bp_get_base(bp_instance *h, double *lb, double *ub, void *stream);

@@ -26,7 +26,8 @@ EXPORTS = ["bp_options_default", "bp_load", "bp_propagate", "bp_propagate_batch"
            "bp_get_base", "bp_kernel_stats", "bp_device_bytes", "bp_free", "bp_last_error",
            "bp_server_create", "bp_server_submit", "bp_server_run", "bp_server_poll",
            "bp_server_results", "bp_server_info", "bp_server_destroy", "bp_autotune",
-           "bp_scores", "bp_probe_order", "bp_round", "bp_scores_noalloc", "bp_repair"]
+           "bp_scores", "bp_probe_order", "bp_round", "bp_scores_noalloc", "bp_repair",
+           "bp_autotune_batch"]
 REQ_PROBE, REQ_PROPAGATE = 0, 1
 
 
@@ -41,7 +42,7 @@ class Options(C.Structure):
                 ("heavy_threshold", C.c_int32), ("rounds_per_launch", C.c_int32),
                 ("probe_slots", C.c_int32), ("heavy_chunk", C.c_int32),
                 ("repair_calls", C.c_int32), ("repair_attempts", C.c_int32),
-                ("repair_shifts", C.c_int32)]
+                ("repair_shifts", C.c_int32), ("lv_grid", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -84,7 +85,8 @@ class Completion(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("heavy_threshold", C.c_int32), ("heavy_chunk", C.c_int32),
                 ("rounds_per_launch", C.c_int32), ("probe_slots", C.c_int32),
-                ("ms", C.c_double), ("trials", C.c_int32), ("from_cache", C.c_int32)]
+                ("ms", C.c_double), ("trials", C.c_int32), ("from_cache", C.c_int32),
+                ("lv_grid", C.c_int32)]
 
 
 class ScoresOut(C.Structure):
@@ -180,6 +182,9 @@ def load_library(path: str = LIB_PATH):
     lib.bp_autotune.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                 C.c_char_p, C.POINTER(Tuning), C.c_void_p]
     lib.bp_autotune.restype = C.c_int
+    lib.bp_autotune_batch.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_void_p, C.c_char_p, C.POINTER(Tuning), C.c_void_p]
+    lib.bp_autotune_batch.restype = C.c_int
     lib.bp_server_destroy.argtypes = [C.c_void_p]
     lib.bp_server_destroy.restype = None
     return lib
@@ -418,6 +423,20 @@ class Instance:
         return dict(heavy_threshold=t.heavy_threshold, heavy_chunk=t.heavy_chunk,
                     rounds_per_launch=t.rounds_per_launch, probe_slots=t.probe_slots,
                     ms=t.ms, trials=t.trials, from_cache=bool(t.from_cache))
+
+    def autotune_batch(self, lb: torch.Tensor, ub: torch.Tensor, changed_ptr: torch.Tensor = None,
+                       changed_idx: torch.Tensor = None, cache_path: str = None, stream=None) -> dict:
+        """bp_autotune_batch on the batch (lb, ub [B, n]; left unchanged) with
+        its changed lists; the chosen schedule stays in the instance."""
+        assert lb.dim() == 2 and lb.shape == ub.shape and lb.shape[1] == self.n
+        t = Tuning()
+        _check(_LIB.bp_autotune_batch(self._h, lb.shape[0], _dptr(lb), _dptr(ub),
+                                      _dptr(changed_ptr) if changed_ptr is not None else None,
+                                      _dptr(changed_idx) if changed_idx is not None else None,
+                                      cache_path.encode() if cache_path else None, C.byref(t),
+                                      _stream_ptr(stream)))
+        return dict(lv_grid=t.lv_grid, rounds_per_launch=t.rounds_per_launch, ms=t.ms,
+                    trials=t.trials, from_cache=bool(t.from_cache))
 
     def base(self, stream=None):
         lb = torch.empty(self.n, dtype=torch.float64, device="cuda")

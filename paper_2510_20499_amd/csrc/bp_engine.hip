@@ -189,6 +189,7 @@ extern "C" void bp_options_default(bp_options *o) {
     o->repair_calls = 0;
     o->repair_attempts = 8;
     o->repair_shifts = 64;
+    o->lv_grid = 0;
 }
 
 extern "C" const char *bp_last_error(void) { return g_err.c_str(); }
@@ -453,6 +454,7 @@ extern "C" int bp_load(const bp_sparse *csr, const bp_sparse *csc, const double 
     if (o.repair_calls < 0) o.repair_calls = 0;
     if (o.repair_attempts <= 0) o.repair_attempts = 8;
     if (o.repair_shifts <= 0) o.repair_shifts = 64;
+    if (o.lv_grid < 0) o.lv_grid = 0;
     o.heavy_chunk = (o.heavy_chunk + WG - 1) / WG * WG;
     // CSR validation
     if (csr->ptr[0] != 0 || csr->ptr[m] != nnz) return fail(BP_EINVAL, "CSR ptr must run from 0 to nnz");

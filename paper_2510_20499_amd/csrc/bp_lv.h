@@ -35,10 +35,19 @@
 
 namespace bp {
 
-constexpr int LV_SHORT = 64;          // rows up to this length: one task
-constexpr int LV_CHUNK = 512;         // nonzeros per chunk of longer rows
-constexpr int LV_MAX_GROUPS = 128;    // batches of up to 8192 vectors
-constexpr int LV_UNROLL = 8;          // bound loads issued together
+#ifndef BP_LV_CHUNK
+#define BP_LV_CHUNK 512
+#endif
+#ifndef BP_LV_UNROLL
+#define BP_LV_UNROLL 8
+#endif
+#ifndef BP_LV_WAVES
+#define BP_LV_WAVES 4  // waves per SIMD the row kernel's register budget targets
+#endif
+constexpr int LV_SHORT = 64;             // rows up to this length: one task
+constexpr int LV_CHUNK = BP_LV_CHUNK;    // nonzeros per chunk of longer rows
+constexpr int LV_MAX_GROUPS = 128;       // batches of up to 8192 vectors
+constexpr int LV_UNROLL = BP_LV_UNROLL;  // bound loads issued together
 
 struct LvVec {
     int32_t state, status, rounds;
@@ -377,7 +386,7 @@ __device__ void lv_chunk_activity(const LvParams &P, int par, int g, int v, bool
 }
 
 // Row kernel: chunk partials of long rows, then short rows.  Grid (x, NG).
-__global__ void __launch_bounds__(WG) k_lv_rows(LvParams P) {
+__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(BP_LV_WAVES))) k_lv_rows(LvParams P) {
     LvCtl *C = P.ctl;
     if (C->done) return;
     const int par = C->round & 1;

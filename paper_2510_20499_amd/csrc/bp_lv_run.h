@@ -2,7 +2,10 @@
 // of bp_engine.hip's translation unit; see bp_lv.h for the kernels).
 #pragma once
 
-static const int LV_GRID_ROWS = 2048;   // workgroups per round kernel, over all groups
+#ifndef BP_LV_GRID
+#define BP_LV_GRID 2048
+#endif
+static const int LV_GRID_ROWS = BP_LV_GRID;  // workgroups per round kernel, over all groups
 static const int LV_MIN_BATCH = 16;     // smaller batches run on the slot engine
 
 // Cold-start task tables of the instance: short rows, and (row, chunk) of
@@ -126,8 +129,12 @@ static LvParams lv_params(const bp_instance *h, int32_t Bp, int32_t V, bool coun
     return P;
 }
 
+// Workgroups of a lane round kernel over all groups: the instance's
+// lv_grid option (the autotuner's choice), else LV_GRID_ROWS.
+static int lv_grid(const bp_instance *h) { return h->opt.lv_grid > 0 ? h->opt.lv_grid : LV_GRID_ROWS; }
+
 static void lv_launch_round(bp_instance *h, const LvParams &P, hipStream_t st, bool timed) {
-    const int gx = std::max(1, LV_GRID_ROWS / P.NG);
+    const int gx = std::max(1, lv_grid(h) / P.NG);
     const dim3 grid(gx, P.NG);
     if (timed) hipExtLaunchKernelGGL(k_lv_rows, grid, dim3(WG), 0, st, h->ev0, h->ev1, 0, P);
     else k_lv_rows<<<grid, WG, 0, st>>>(P);
@@ -257,7 +264,7 @@ static int lv_piece(bp_instance *h, int32_t Bp, double *lb, double *ub, const in
     memset(&c, 0, sizeof(c));
     HIPTRY(hipMemcpyAsync(P.ctl, &c, sizeof(LvCtl), hipMemcpyHostToDevice, st));
     k_lv_reset<<<grid_for(V), 256, 0, st>>>(P, L.box.as<int32_t>());
-    const int gx = std::max(1, LV_GRID_ROWS / NG);
+    const int gx = std::max(1, lv_grid(h) / NG);
     if (cold) {
         if (h->m > 0)
             k_lv_seed_cold<<<dim3(std::max(1, gx / 4), NG), 256, 0, st>>>(

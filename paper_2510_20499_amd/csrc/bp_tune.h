@@ -221,3 +221,136 @@ extern "C" int bp_autotune(bp_instance *h, const double *lb, const double *ub, c
     *out = best;
     return BP_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Batched propagation: the lane engine's workgroups per round kernel and the
+// rounds per graph, timed on the caller's batch (best of two calls each).
+// ---------------------------------------------------------------------------
+static bool tune_lookup_batch(const char *path, const std::string &key, bp_tuning *t) {
+    if (!path) return false;
+    std::ifstream f(path);
+    if (!f) return false;
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        std::istringstream is(line);
+        std::string k;
+        bp_tuning x;
+        memset(&x, 0, sizeof(x));
+        if (!(is >> k >> x.lv_grid >> x.rounds_per_launch >> x.ms)) continue;
+        if (k == key && x.lv_grid >= 64 && x.rounds_per_launch >= 1) {
+            *t = x;
+            found = true;
+        }
+    }
+    return found;
+}
+
+extern "C" int bp_autotune_batch(bp_instance *h, int32_t B, const double *lb, const double *ub,
+                                 const int64_t *changed_ptr, const int32_t *changed_idx,
+                                 const char *cache_path, bp_tuning *out, void *stream) {
+    g_err.clear();
+    if (!h || !out || B <= 0 || (h->n > 0 && (!lb || !ub)))
+        return fail(BP_EINVAL, "bp_autotune_batch: bad argument");
+    hipStream_t st = as_stream(stream);
+    std::ostringstream ks;
+    ks << "batch/" << tune_key(h) << "/B" << B << (changed_ptr ? "/warm" : "/cold");
+    const std::string key = ks.str();
+    bp_tuning best;
+    memset(&best, 0, sizeof(best));
+    best.heavy_threshold = h->opt.heavy_threshold;
+    best.heavy_chunk = h->opt.heavy_chunk;
+    best.probe_slots = h->opt.probe_slots;
+    if (tune_lookup_batch(cache_path, key, &best)) {
+        h->opt.lv_grid = best.lv_grid;
+        h->opt.rounds_per_launch = best.rounds_per_launch;
+        best.heavy_threshold = h->opt.heavy_threshold;
+        best.heavy_chunk = h->opt.heavy_chunk;
+        best.probe_slots = h->opt.probe_slots;
+        best.trials = 0;
+        best.from_cache = 1;
+        *out = best;
+        return BP_OK;
+    }
+    const size_t N = (size_t)B * (size_t)std::max<int32_t>(h->n, 1);
+    DevBuf wl, wu;
+    int64_t dummy = 0;
+    if (int rc = wl.alloc(N * 8, dummy)) return rc;
+    if (int rc = wu.alloc(N * 8, dummy)) return rc;
+    std::vector<bp_result> ref((size_t)B), res((size_t)B);
+    bool have_ref = false;
+    int trials = 0;
+    auto time_batch = [&](double &ms) -> int {
+        ms = 1e300;
+        for (int rep = 0; rep < 2; ++rep) {
+            if (h->n) {
+                HIPTRY(hipMemcpyAsync(wl.p, lb, N * 8, hipMemcpyDeviceToDevice, st));
+                HIPTRY(hipMemcpyAsync(wu.p, ub, N * 8, hipMemcpyDeviceToDevice, st));
+            }
+            HIPTRY(hipStreamSynchronize(st));
+            auto t0 = std::chrono::steady_clock::now();
+            int rc = bp_propagate_batch(h, B, wl.as<double>(), wu.as<double>(), changed_ptr, changed_idx,
+                                        res.data(), st);
+            auto t1 = std::chrono::steady_clock::now();
+            if (rc < 0) return rc;
+            ms = std::min(ms, std::chrono::duration<double, std::milli>(t1 - t0).count());
+            if (!have_ref) {
+                ref = res;
+                have_ref = true;
+            } else {
+                for (int32_t j = 0; j < B; ++j)
+                    if (res[j].status != ref[j].status || res[j].rounds != ref[j].rounds ||
+                        res[j].nnz_propagated != ref[j].nnz_propagated)
+                        return fail(BP_EDEVICE, "autotuner: a schedule changed a batch result");
+            }
+        }
+        ++trials;
+        return 0;
+    };
+    const int32_t grids[] = {1024, 2048, 4096, 8192};
+    const int32_t rounds[] = {8, 16, 32};
+    best.ms = 1e300;
+    const int32_t saved_grid = h->opt.lv_grid, saved_rounds = h->opt.rounds_per_launch;
+    int rc = 0;
+    for (int32_t g : grids) {
+        h->opt.lv_grid = g;
+        h->opt.rounds_per_launch = 16;
+        double ms;
+        if ((rc = time_batch(ms))) break;
+        if (ms < best.ms) {
+            best.ms = ms;
+            best.lv_grid = g;
+            best.rounds_per_launch = 16;
+        }
+    }
+    for (int32_t r : rounds) {
+        if (rc) break;
+        h->opt.lv_grid = best.lv_grid;
+        h->opt.rounds_per_launch = r;
+        double ms;
+        if ((rc = time_batch(ms))) break;
+        if (ms < best.ms) {
+            best.ms = ms;
+            best.rounds_per_launch = r;
+        }
+    }
+    if (rc) {
+        h->opt.lv_grid = saved_grid;
+        h->opt.rounds_per_launch = saved_rounds;
+        return rc;
+    }
+    h->opt.lv_grid = best.lv_grid;
+    h->opt.rounds_per_launch = best.rounds_per_launch;
+    best.trials = trials;
+    best.from_cache = 0;
+    if (cache_path) {
+        FILE *f = fopen(cache_path, "a");
+        if (f) {
+            fprintf(f, "%s %d %d %.6f\n", key.c_str(), best.lv_grid, best.rounds_per_launch, best.ms);
+            fclose(f);
+        }
+    }
+    *out = best;
+    return BP_OK;
+}
+

@@ -407,10 +407,12 @@ def pick_probe_vars(inst, lb, ub, k: int, seed: int = 0):
     return np.sort(rng.choice(cand, size=k, replace=False)).astype(np.int32)
 
 
-def bulk_fix_lists(inst, lb, ub, count: int, frac: float = 0.05, seed: int = 0):
+def bulk_fix_lists(inst, lb, ub, count: int, frac: float = 0.05, seed: int = 0, point=None):
     """Bulk-rounding candidates as fixing lists: for each of ``count``
     vectors, a seeded ``frac`` of the unfixed integer variables (sorted) and
-    their values rint(U[lb, ub]).  Returns a list of (vars int32, values)."""
+    their values rint(U[lb, ub]), or, with ``point``, the point's values
+    rounded and clipped into [lb, ub] (the planted point gives candidates
+    that stay feasible).  Returns a list of (vars int32, values)."""
     rng = _stream(seed + 104729)[0]
     ints = np.nonzero(inst["vtype"] == 1)[0]
     ints = ints[np.isfinite(lb[ints]) & np.isfinite(ub[ints]) & (lb[ints] < ub[ints])]
@@ -418,7 +420,10 @@ def bulk_fix_lists(inst, lb, ub, count: int, frac: float = 0.05, seed: int = 0):
     out = []
     for _ in range(count):
         pick = np.sort(rng.choice(ints, size=k, replace=False))
-        val = np.rint(rng.uniform(lb[pick], ub[pick]))
+        if point is None:
+            val = np.rint(rng.uniform(lb[pick], ub[pick]))
+        else:
+            val = np.clip(np.rint(point[pick]), lb[pick], ub[pick])
         out.append((pick.astype(np.int32), val))
     return out
 

@@ -67,3 +67,53 @@ def test_autotune_and_cache():
         assert t3["from_cache"]
         for k in ("heavy_threshold", "heavy_chunk", "rounds_per_launch", "probe_slots"):
             assert t3[k] == t[k]
+
+
+@pytest.mark.parametrize("grid", [256, 1024, 8192])
+def test_lane_grids_give_identical_results(grid):
+    """The lane engine's workgroups per round kernel change nothing."""
+    inst = gen.make("single", 4, scale=0.02)
+    _, lb, ub = oracle.propagate(inst)
+    LB, UB, changed = gen.bulk_fix_vectors(inst, lb, ub, count=40, frac=0.004, seed=8)
+    ptr = np.zeros(41, np.int64)
+    ptr[1:] = np.cumsum([c.size for c in changed])
+    idx = np.concatenate(changed).astype(np.int32)
+    out = []
+    for g in (0, grid):
+        I = bp().Instance(inst, bp().default_options(lv_grid=g))
+        tl, tu = dev(LB, torch.float64), dev(UB, torch.float64)
+        res = I.propagate_batch(tl, tu, dev(ptr, torch.int64), dev(idx, torch.int32))
+        torch.cuda.synchronize()
+        out.append((res, tl.cpu().numpy(), tu.cpu().numpy()))
+    assert out[0][0] == out[1][0]
+    assert np.array_equal(out[0][1], out[1][1]) and np.array_equal(out[0][2], out[1][2])
+
+
+def test_autotune_batch_and_cache():
+    """bp_autotune_batch times the batch itself, leaves the inputs alone,
+    keeps a lane schedule that gives the oracle's results, and its cache
+    round-trips."""
+    inst = gen.make("single", 9, scale=0.02)
+    _, lb, ub = oracle.propagate(inst)
+    LB, UB, changed = gen.bulk_fix_vectors(inst, lb, ub, count=48, frac=0.003, seed=4)
+    ptr = np.zeros(49, np.int64)
+    ptr[1:] = np.cumsum([c.size for c in changed])
+    idx = np.concatenate(changed).astype(np.int32)
+    tl, tu = dev(LB, torch.float64), dev(UB, torch.float64)
+    pd, idd = dev(ptr, torch.int64), dev(idx, torch.int32)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tune.txt")
+        I = bp().Instance(inst)
+        t = I.autotune_batch(tl, tu, pd, idd, cache_path=path)
+        assert t["trials"] >= 6 and not t["from_cache"] and t["lv_grid"] in (1024, 2048, 4096, 8192)
+        assert np.array_equal(tl.cpu().numpy(), LB) and np.array_equal(tu.cpu().numpy(), UB)
+        res = I.propagate_batch(tl, tu, pd, idd)
+        torch.cuda.synchronize()
+        GL, GU = tl.cpu().numpy(), tu.cpu().numpy()
+        for v in range(48):
+            ro, lo, uo = oracle.propagate(inst, LB[v], UB[v], changed=changed[v])
+            assert_same(inst, res[v], GL[v], GU[v], ro, lo, uo, "tuned batch v%d" % v)
+        I2 = bp().Instance(inst)
+        t2 = I2.autotune_batch(dev(LB, torch.float64), dev(UB, torch.float64), pd, idd, cache_path=path)
+        assert t2["from_cache"] and t2["trials"] == 0
+        assert (t2["lv_grid"], t2["rounds_per_launch"]) == (t["lv_grid"], t["rounds_per_launch"])
