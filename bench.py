@@ -76,13 +76,10 @@ CPU_POOL_MAX = 16
 
 def inst_sha256(inst):
     """sha256 of an instance's arrays (row pointers, columns, coefficients,
-    sides, types, bounds), as generated: what the record was measured on."""
-    import hashlib
-    import numpy as np
-    h = hashlib.sha256()
-    for k in ("row_ptr", "col", "val", "lo", "hi", "vtype", "lb", "ub"):
-        h.update(np.ascontiguousarray(inst[k]).tobytes())
-    return h.hexdigest()
+    sides, types, bounds), as generated: what the record was measured on
+    (the digest the instance files' manifests carry)."""
+    from paper_2510_20499_amd import gen
+    return gen.digest(inst)
 
 
 def cpu_info():

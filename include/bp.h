@@ -69,6 +69,7 @@ extern "C" {
 #define BP_EDEVICE (-3)    /* a HIP call failed */
 #define BP_ECAPACITY (-4)  /* an output buffer is too small (see bp_probe_out) */
 #define BP_ESTATE (-5)     /* bp_probe before a feasible base exists */
+#define BP_ECANCELED (-6)  /* bp_server_results of a request that was cancelled */
 
 /* Flags (bp_options.flags). */
 #define BP_FLAG_FORCE_EXACT 1u  /* compute every activity on the exact slow path
@@ -503,10 +504,12 @@ typedef struct {
     int64_t id;            /* as returned by bp_server_submit */
     int32_t instance, kind;
     int32_t jobs;          /* 1 (propagate) or 2*count (probe) */
-    int32_t reserved;
+    int32_t flags;         /* BP_COMPLETION_CANCELLED or 0 */
     double submit_us;      /* host clock, microseconds since bp_server_create */
     double done_us;        /* when the server observed the last job finish */
 } bp_completion;
+
+#define BP_COMPLETION_CANCELLED 1  /* taken out of the queue before it ran */
 
 /* Create a server over `count` loaded instances, each with a base (a
  * feasible bp_propagate was run on it; BP_ESTATE otherwise).  The slot pool
@@ -531,6 +534,19 @@ int bp_server_submit(bp_server *sv, const bp_request *req, int64_t *id);
  * requests submitted and not yet finished. */
 int bp_server_run(bp_server *sv, int32_t rounds, int32_t *busy);
 
+/* Cancel a request that still waits in the host queue: requests submitted
+ * while the device job list is full, or not yet moved to the device by a
+ * bp_server_run.  It finishes at once: bp_server_poll reports it with
+ * flags = BP_COMPLETION_CANCELLED, and bp_server_results returns
+ * BP_ECANCELED.  BP_ESTATE if its jobs are already on the device or it has
+ * finished (those run to the end); BP_EINVAL for an unknown id. */
+int bp_server_cancel(bp_server *sv, int64_t id);
+
+/* Queue timeout: cancel, as bp_server_cancel does, every request that has
+ * waited in the host queue for more than max_wait_us microseconds since its
+ * bp_server_submit.  *n (if not NULL) receives the number cancelled. */
+int bp_server_expire(bp_server *sv, double max_wait_us, int32_t *n);
+
 /* Finished requests since the last poll, in completion order (at most max;
  * *n receives the number written). */
 int bp_server_poll(bp_server *sv, bp_completion *out, int32_t max, int32_t *n);
@@ -551,6 +567,18 @@ void bp_server_destroy(bp_server *sv);
 
 /* Thread-local description of the last error ("" if none). */
 const char *bp_last_error(void);
+
+/* Failure injection, for tests of the error paths: from this call on, the
+ * k-th device allocation the library makes (in any entry point, on any
+ * thread) fails with BP_ENOMEM as if the device were out of memory, and the
+ * injection then disarms itself; k = 0 disarms it.  A call that fails this
+ * way returns BP_ENOMEM and leaks nothing: an instance or server under
+ * construction is destroyed, and an existing instance may lose its work
+ * buffers, which its next call allocates again.  Outputs are untouched as
+ * for any error, except that bp_round, whose repairs allocate their buffers
+ * on first use, may leave lb/ub at a later step's box.  BP_EINVAL for
+ * k < 0. */
+int bp_debug_fail_alloc(int64_t k);
 
 #ifdef __cplusplus
 }

@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbp.so")
 
 BP_OK, BP_INFEASIBLE, BP_ROUND_LIMIT = 0, 1, 2
-BP_EINVAL, BP_ENOMEM, BP_EDEVICE, BP_ECAPACITY, BP_ESTATE = -1, -2, -3, -4, -5
+BP_EINVAL, BP_ENOMEM, BP_EDEVICE, BP_ECAPACITY, BP_ESTATE, BP_ECANCELED = -1, -2, -3, -4, -5, -6
+COMPLETION_CANCELLED = 1
 FLAG_FORCE_EXACT, FLAG_TIME_KERNELS, FLAG_HOST_ROUNDS, FLAG_COUNT_VARS, FLAG_BATCH_SLOTS = 1, 2, 4, 8, 16
 FLAG_FULL_ROWS = 32
 FLAG_LV_DENSE = 64
@@ -27,7 +28,7 @@ EXPORTS = ["bp_options_default", "bp_load", "bp_propagate", "bp_propagate_batch"
            "bp_server_create", "bp_server_submit", "bp_server_run", "bp_server_poll",
            "bp_server_results", "bp_server_info", "bp_server_destroy", "bp_autotune",
            "bp_scores", "bp_probe_order", "bp_round", "bp_scores_noalloc", "bp_repair",
-           "bp_autotune_batch"]
+           "bp_autotune_batch", "bp_debug_fail_alloc", "bp_server_cancel", "bp_server_expire"]
 REQ_PROBE, REQ_PROPAGATE = 0, 1
 
 
@@ -78,7 +79,7 @@ class Request(C.Structure):
 
 class Completion(C.Structure):
     _fields_ = [("id", C.c_int64), ("instance", C.c_int32), ("kind", C.c_int32),
-                ("jobs", C.c_int32), ("reserved", C.c_int32), ("submit_us", C.c_double),
+                ("jobs", C.c_int32), ("flags", C.c_int32), ("submit_us", C.c_double),
                 ("done_us", C.c_double)]
 
 
@@ -187,6 +188,12 @@ def load_library(path: str = LIB_PATH):
     lib.bp_autotune_batch.restype = C.c_int
     lib.bp_server_destroy.argtypes = [C.c_void_p]
     lib.bp_server_destroy.restype = None
+    lib.bp_server_cancel.argtypes = [C.c_void_p, C.c_int64]
+    lib.bp_server_cancel.restype = C.c_int
+    lib.bp_server_expire.argtypes = [C.c_void_p, C.c_double, C.POINTER(C.c_int32)]
+    lib.bp_server_expire.restype = C.c_int
+    lib.bp_debug_fail_alloc.argtypes = [C.c_int64]
+    lib.bp_debug_fail_alloc.restype = C.c_int
     return lib
 
 
@@ -195,6 +202,12 @@ _LIB = load_library()
 
 def lib():
     return _LIB
+
+
+def debug_fail_alloc(k: int):
+    """bp_debug_fail_alloc: make the k-th device allocation from now on fail
+    with BP_ENOMEM (k = 0 disarms)."""
+    _check(_LIB.bp_debug_fail_alloc(int(k)))
 
 
 def _check(rc):
@@ -507,7 +520,21 @@ class Server:
         n = C.c_int32()
         _check(_LIB.bp_server_poll(self._h, buf, max_items, C.byref(n)))
         return [dict(id=buf[i].id, instance=buf[i].instance, kind=buf[i].kind, jobs=buf[i].jobs,
+                     cancelled=bool(buf[i].flags & COMPLETION_CANCELLED),
                      submit_us=buf[i].submit_us, done_us=buf[i].done_us) for i in range(n.value)]
+
+    def cancel(self, rid: int):
+        """bp_server_cancel: take a request that still waits in the host
+        queue out of it (BPError with BP_ESTATE once its jobs are on the
+        device)."""
+        _check(_LIB.bp_server_cancel(self._h, rid))
+
+    def expire(self, max_wait_us: float) -> int:
+        """bp_server_expire: cancel the host-queued requests that waited
+        longer than max_wait_us; returns how many."""
+        n = C.c_int32()
+        _check(_LIB.bp_server_expire(self._h, float(max_wait_us), C.byref(n)))
+        return n.value
 
     def results(self, rid: int, jobs: int) -> dict:
         req = C.c_int64()
@@ -534,3 +561,59 @@ class Server:
             tot = int(off[-1])
             return dict(status=st, rounds=rd, nnz=nz, n_infeasible_rows=nb, infeasible_row=br,
                         infeasible_var=bv, off=off, var=var[:tot], lb=lb[:tot], ub=ub[:tot])
+
+
+# ---------------------------------------------------------------------------
+# Probing cache files (bp_probe output kept for later rounding calls)
+# ---------------------------------------------------------------------------
+CACHE_KEYS = ("vars", "status", "rounds", "nnz", "off", "var", "lb", "ub")
+
+
+def _cache_sha256(arrays: dict) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for k in CACHE_KEYS:
+        a = np.ascontiguousarray(arrays[k])
+        h.update(k.encode())
+        h.update(str(a.dtype).encode())
+        h.update(a.tobytes())
+    return h.hexdigest()
+
+
+def save_probe_cache(path: str, vars_: torch.Tensor, probe_out: dict, instance_sha256: str = None) -> str:
+    """Write a probing cache (the probed variables and Instance.probe's
+    output) to ``path`` (.npz) with a manifest ``path + '.sha256.json'``
+    holding the content digest and, if given, the digest of the instance it
+    was computed on.  Returns the content digest."""
+    import json
+    arrays = {"vars": vars_.detach().cpu().numpy()}
+    for k in CACHE_KEYS[1:]:
+        arrays[k] = probe_out[k].detach().cpu().numpy()
+    with open(path, "wb") as fh:
+        np.savez(fh, **arrays)
+    digest = _cache_sha256(arrays)
+    with open(path + ".sha256.json", "w") as fh:
+        json.dump({"sha256": digest, "instance_sha256": instance_sha256,
+                   "probes": int(arrays["vars"].size)}, fh, indent=1, sort_keys=True)
+    return digest
+
+
+def load_probe_cache(path: str, device="cuda", instance_sha256: str = None) -> dict:
+    """Read a cache written by save_probe_cache into device tensors (the dict
+    Instance.round takes as ``cache``).  ValueError if the content does not
+    match its manifest, or the manifest names another instance than
+    ``instance_sha256``."""
+    import json
+    with np.load(path, allow_pickle=False) as z:
+        arrays = {k: z[k] for k in CACHE_KEYS}
+    with open(path + ".sha256.json") as fh:
+        man = json.load(fh)
+    if _cache_sha256(arrays) != man["sha256"]:
+        raise ValueError("probing cache %s does not match its manifest" % path)
+    if instance_sha256 is not None and man.get("instance_sha256") != instance_sha256:
+        raise ValueError("probing cache %s was computed on another instance" % path)
+    k = int(arrays["vars"].size)
+    off = arrays["off"]
+    if off.size != 2 * k + 1 or arrays["status"].size != 2 * k or int(off[-1]) != arrays["var"].size:
+        raise ValueError("probing cache %s has inconsistent sizes" % path)
+    return {key: torch.from_numpy(a).to(device) for key, a in arrays.items()}

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -17,10 +18,24 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/bp.h"
 #include "bp_kernels.h"
 
 using namespace bp;
+
+// ------------------------------------------------------------------------
+// Tracing: one roctx range per compute entry point call, named after it
+// (rocprofv3 --marker-trace shows them around the call's kernels).
+// ------------------------------------------------------------------------
+struct RoctxRange {
+    explicit RoctxRange(const char *name) { roctxRangePushA(name); }
+    ~RoctxRange() { roctxRangePop(); }
+    RoctxRange(const RoctxRange &) = delete;
+    RoctxRange &operator=(const RoctxRange &) = delete;
+};
+#define BP_RANGE(name) RoctxRange bp_range_(name)
 
 // ------------------------------------------------------------------------
 // Errors
@@ -43,6 +58,17 @@ static int fail(int code, const std::string &msg) {
 // ------------------------------------------------------------------------
 // Device buffers
 // ------------------------------------------------------------------------
+// Failure injection (bp_debug_fail_alloc): the number of device
+// allocations still to succeed before one fails; 0 when disarmed.
+static std::atomic<int64_t> g_fail_alloc{0};
+
+static bool alloc_injected_failure() {
+    int64_t k = g_fail_alloc.load();
+    while (k > 0)
+        if (g_fail_alloc.compare_exchange_weak(k, k - 1)) return k == 1;
+    return false;
+}
+
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
@@ -57,6 +83,9 @@ struct DevBuf {
         p = nullptr;
         bytes = 0;
         if (n == 0) n = 16;
+        if (alloc_injected_failure())
+            return fail(BP_ENOMEM, "injected failure of device allocation (" + std::to_string(n) +
+                                       " bytes; bp_debug_fail_alloc)");
         hipError_t e = hipMalloc(&p, n);
         if (e != hipSuccess) {
             p = nullptr;
@@ -69,7 +98,7 @@ struct DevBuf {
     }
     // Keeps the allocation when it is already large enough.
     int grow(size_t n, int64_t &total) {
-        if (p && bytes >= std::max<size_t>(n, 16)) return 0;
+        if (p && bytes >= n) return 0;
         return alloc(n, total);
     }
     template <class T>
@@ -163,6 +192,9 @@ struct bp_instance {
     // record, fixed flags, the box propagated from the original bounds
     DevBuf rp_sums, rp_cand, rp_ctl, rp_fixed, rp_pl, rp_pu;
     int64_t max_row_len = 0;
+    // false while the row tables are being (re)built, and after a failed
+    // rebuild: the instance then takes no further calls
+    bool tables_ok = false;
     // stats
     bp_stats stats;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
@@ -193,6 +225,12 @@ extern "C" void bp_options_default(bp_options *o) {
 }
 
 extern "C" const char *bp_last_error(void) { return g_err.c_str(); }
+
+extern "C" int bp_debug_fail_alloc(int64_t k) {
+    if (k < 0) return fail(BP_EINVAL, "bp_debug_fail_alloc: negative count");
+    g_fail_alloc.store(k);
+    return BP_OK;
+}
 
 // ------------------------------------------------------------------------
 // Small kernels: packing, checks, seeding
@@ -386,6 +424,7 @@ static int sc_tables(bp_instance *h, const std::vector<int32_t> &cold, hipStream
 // schedule.
 static int bin_rows(bp_instance *h, hipStream_t st) {
     const int64_t m = h->m;
+    h->tables_ok = false;
     h->gh_version = -1;  // the heavy rows change with the threshold
     for (int b = 0; b < NBIN; ++b) h->bin_count[b] = 0;
     std::vector<uint8_t> rbin(m);
@@ -427,12 +466,26 @@ static int bin_rows(bp_instance *h, hipStream_t st) {
                               hipMemcpyHostToDevice, st));
     if ((rc = sc_tables(h, cold, st))) return rc;
     HIPTRY(hipStreamSynchronize(st));
+    h->tables_ok = true;
     return 0;
 }
+
+// Entry points on an instance whose row tables were lost (an allocation
+// failed while the autotuner re-binned its rows) fail with BP_ESTATE.  A
+// null instance is left to the entry point's own argument check.
+static int tables_check(const bp_instance *h) {
+    if (!h || h->tables_ok) return 0;
+    return fail(BP_ESTATE, "the instance's row tables were lost in a failed allocation; load it again");
+}
+#define BP_TABLES_CHECK(h)                       \
+    do {                                         \
+        if (int rc_ = tables_check(h)) return rc_; \
+    } while (0)
 
 extern "C" int bp_load(const bp_sparse *csr, const bp_sparse *csc, const double *row_lo,
                        const double *row_hi, const uint8_t *vartype, const bp_options *opt,
                        void *stream, bp_instance **out) {
+    BP_RANGE("bp_load");
     g_err.clear();
     if (!csr || !row_lo || !row_hi || !vartype || !out)
         return fail(BP_EINVAL, "bp_load: null argument");
@@ -1079,6 +1132,8 @@ static int propagate_slots(bp_instance *h, int32_t Bv, double *lb, double *ub,
 
 extern "C" int bp_propagate(bp_instance *h, double *lb, double *ub, const int32_t *changed,
                             int64_t n_changed, bp_result *res, void *stream) {
+    BP_RANGE("bp_propagate");
+    BP_TABLES_CHECK(h);
     g_err.clear();
     if (!h || !res || (h->n > 0 && (!lb || !ub))) return fail(BP_EINVAL, "bp_propagate: null argument");
     hipStream_t st = as_stream(stream);
@@ -1110,6 +1165,8 @@ extern "C" int bp_propagate(bp_instance *h, double *lb, double *ub, const int32_
 extern "C" int bp_propagate_batch(bp_instance *h, int32_t B, double *lb, double *ub,
                                   const int64_t *changed_ptr, const int32_t *changed_idx,
                                   bp_result *res, void *stream) {
+    BP_RANGE("bp_propagate_batch");
+    BP_TABLES_CHECK(h);
     g_err.clear();
     if (!h || !res || B < 0 || (B > 0 && h->n > 0 && (!lb || !ub)))
         return fail(BP_EINVAL, "bp_propagate_batch: bad argument");
@@ -1305,6 +1362,8 @@ static int ensure_buf(DevBuf &b, size_t bytes) {
 
 extern "C" int bp_probe(bp_instance *h, const int32_t *vars, int32_t k, bp_probe_out *out,
                         void *stream) {
+    BP_RANGE("bp_probe");
+    BP_TABLES_CHECK(h);
     g_err.clear();
     if (!h || !out || k < 0 || (k > 0 && !vars)) return fail(BP_EINVAL, "bp_probe: bad argument");
     if (!out->off || out->cap < 0 || (k > 0 && (!out->status || !out->rounds || !out->nnz)))

@@ -1448,9 +1448,13 @@ __device__ __forceinline__ void count_pending(const Params &P, bool first, int s
 // Append the (slot, row) tasks of the lanes with first == true to their bin
 // queues of parity par: one ballot per bin, then one atomic per non-empty
 // bin issued by lanes 0..BIN_HEAVY-1 in parallel; heavy rows become chunk
-// records.  Reached by every lane of the wave.
+// records.  With heads_only (incremental heavy rows, next round without an
+// accumulator rebuild) a heavy row queues only its chunk 0: that round
+// tests the row from its accumulators in the head task, and the head lists
+// the row's chunks as candidate tasks itself when it needs them.  Reached
+// by every lane of the wave.
 __device__ __forceinline__ void append_rows(const Params &P, int par, bool first, int s, int k,
-                                            int bin, int64_t len) {
+                                            int bin, int64_t len, bool heads_only = false) {
     if (!__any(first)) return;
     const int lane = __lane_id();
     if (first && bin == BIN_HEAVY) {
@@ -1467,8 +1471,9 @@ __device__ __forceinline__ void append_rows(const Params &P, int par, bool first
                 for (int c = 0; c < nch; ++c) P.ghrec[par][cb + c] = make_int4(g, k, c, nch);
             }
         } else {
-            uint32_t cb = atomicAdd(&P.ctl->hchunks[par], (uint32_t)nch);
-            for (int c = 0; c < nch; ++c) P.hrec[par][cb + c] = make_int4(s, k, c, nch);
+            const int nrec = heads_only ? 1 : nch;
+            uint32_t cb = atomicAdd(&P.ctl->hchunks[par], (uint32_t)nrec);
+            for (int c = 0; c < nrec; ++c) P.hrec[par][cb + c] = make_int4(s, k, c, nch);
         }
     }
     const bool lt = first && bin != BIN_HEAVY;
@@ -1569,7 +1574,7 @@ __device__ void enqueue_columns(const Params &P, int par, bool want, int s, long
             tot_nnz += x;
             tot_rows += (uint32_t)__popcll(__ballot(first));
         }
-        append_rows(P, par, first, os, k, bin, rlen);
+        append_rows(P, par, first, os, k, bin, rlen, correct);
     }
     if (rows_out) *rows_out = tot_rows;
     if (nnz_out) *nnz_out = tot_nnz;

@@ -39,8 +39,13 @@ static int lv_tables(bp_instance *h, LvEngine &L, hipStream_t st) {
 // (-inf, +inf) and every mask with zero once; each call leaves them so.
 static int lv_ensure(bp_instance *h, int32_t V, bool count, hipStream_t st) {
     if (!h->lv) {
-        h->lv.reset(new LvEngine());
-        if (int rc = lv_tables(h, *h->lv, st)) return rc;
+        // the engine is kept only once its tables exist
+        std::unique_ptr<LvEngine> E(new LvEngine());
+        if (int rc = lv_tables(h, *E, st)) {
+            h->bytes -= (int64_t)(E->short_rows.bytes + E->long_chunks.bytes);
+            return rc;
+        }
+        h->lv = std::move(E);
     }
     LvEngine &L = *h->lv;
     const int64_t n = std::max<int32_t>(h->n, 1), m = std::max<int32_t>(h->m, 1);
@@ -52,6 +57,10 @@ static int lv_ensure(bp_instance *h, int32_t V, bool count, hipStream_t st) {
             L.graph = nullptr;
         }
         const int64_t NG = V / 64;
+        // Until every buffer below exists no call may use the old ones (a
+        // failed allocation has already freed its buffer).
+        L.Vcap = 0;
+        L.have_touched = false;
         if ((rc = L.bnd.alloc((size_t)n * V * 16, B))) return rc;
         if ((rc = L.cand.alloc((size_t)n * V * 16, B))) return rc;
         if ((rc = L.vmask.alloc((size_t)NG * n * 8, B))) return rc;

@@ -128,6 +128,8 @@ static int rp_check(bp_instance *h, const double *lb, const double *ub, const do
 extern "C" int bp_repair(bp_instance *h, double *lb, double *ub, const double *lb0, const double *ub0,
                          int32_t max_shifts, int32_t max_attempts, bp_repair_result *res,
                          void *stream) {
+    BP_RANGE("bp_repair");
+    BP_TABLES_CHECK(h);
     g_err.clear();
     if (!h || !res || (h->n > 0 && (!lb || !ub || !lb0 || !ub0)))
         return fail(BP_EINVAL, "bp_repair: null argument");

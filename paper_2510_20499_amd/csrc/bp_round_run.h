@@ -37,6 +37,8 @@ static int round_impl(bp_instance *h, double *lb, double *ub, const double *x, c
 
 extern "C" int bp_round(bp_instance *h, double *lb, double *ub, const double *x, const double *draws,
                         const bp_cache *cache, bp_round_result *res, void *stream) {
+    BP_RANGE("bp_round");
+    BP_TABLES_CHECK(h);
     g_err.clear();
     if (!h || !res || (h->n > 0 && (!lb || !ub || !x || !draws)))
         return fail(BP_EINVAL, "bp_round: null argument");

@@ -154,6 +154,8 @@ static int sc_scores(bp_instance *h, const double *lb, const double *ub, bp_scor
 
 extern "C" int bp_scores(bp_instance *h, const double *lb, const double *ub, bp_scores_out *out,
                          void *stream) {
+    BP_RANGE("bp_scores");
+    BP_TABLES_CHECK(h);
     if (!h || !out) return fail(BP_EINVAL, "null argument");
     if (h->n > 0 && (!lb || !ub)) return fail(BP_EINVAL, "null bounds");
     hipStream_t st = as_stream(stream);
@@ -196,6 +198,7 @@ static int scratch_ptr(void **out) {
 extern "C" int bp_scores_noalloc(bp_instance *h, const double *lb, const double *ub,
                                  bp_scores_out *out, void *stream) {
     if (!h || !out) return fail(BP_EINVAL, "null argument");
+    BP_TABLES_CHECK(h);
     if (h->n > 0 && (!lb || !ub)) return fail(BP_EINVAL, "null bounds");
     const size_t need = sc_work_size(h).total();
     if (need > (size_t)BP_SCORES_NOALLOC_MAX_BYTES)
@@ -210,6 +213,8 @@ extern "C" int bp_scores_noalloc(bp_instance *h, const double *lb, const double 
 
 extern "C" int bp_probe_order(bp_instance *h, const double *lb, const double *ub,
                               const int32_t *vars, int32_t k, int32_t *order, void *stream) {
+    BP_RANGE("bp_probe_order");
+    BP_TABLES_CHECK(h);
     if (!h || k < 0) return fail(BP_EINVAL, "bad argument");
     if (k > 0 && (!vars || !order)) return fail(BP_EINVAL, "null argument");
     if (h->n > 0 && (!lb || !ub)) return fail(BP_EINVAL, "null bounds");

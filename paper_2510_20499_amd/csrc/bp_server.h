@@ -55,7 +55,7 @@ struct ServerReq {
     std::vector<int32_t> vars;
     std::vector<double> lb, ub;
     int32_t remaining = 0;
-    bool on_device = false, done = false;
+    bool on_device = false, done = false, cancelled = false;
     double submit_us = 0, done_us = 0;
     std::vector<JobOut> out;              // per job
     std::vector<std::vector<int32_t>> lvar; // per job implied lists
@@ -114,12 +114,14 @@ static int64_t slot_bytes(const Shape &sh) {
 
 extern "C" int bp_server_create(bp_instance *const *instances, int32_t count, const bp_options *opt,
                                 int64_t budget_bytes, void *stream, bp_server **out) {
+    BP_RANGE("bp_server_create");
     g_err.clear();
     if (!instances || count <= 0 || !out || budget_bytes <= 0)
         return fail(BP_EINVAL, "bp_server_create: bad argument");
     *out = nullptr;
     std::unique_ptr<bp_server> sv(new bp_server());
     sv->st = as_stream(stream);
+    if (!opt && !instances[0]) return fail(BP_EINVAL, "bp_server_create: null instance");
     sv->opt = opt ? *opt : instances[0]->opt;
     if (int rc = validate_options(sv->opt)) return rc;
     if (sv->opt.rounds_per_launch <= 0) sv->opt.rounds_per_launch = 16;
@@ -127,6 +129,7 @@ extern "C" int bp_server_create(bp_instance *const *instances, int32_t count, co
     for (int32_t t = 0; t < count; ++t) {
         bp_instance *h = instances[t];
         if (!h) return fail(BP_EINVAL, "bp_server_create: null instance");
+        BP_TABLES_CHECK(h);
         if (!h->have_base) return fail(BP_ESTATE, "instance " + std::to_string(t) + " has no base");
         if (t == 0) sv->heavy_chunk = h->heavy_chunk;
         else if (h->heavy_chunk != sv->heavy_chunk)
@@ -431,6 +434,7 @@ static int server_collect(bp_server *sv) {
 }
 
 extern "C" int bp_server_run(bp_server *sv, int32_t rounds, int32_t *busy) {
+    BP_RANGE("bp_server_run");
     g_err.clear();
     if (!sv || rounds < 0) return fail(BP_EINVAL, "bp_server_run: bad argument");
     hipStream_t st = sv->st;
@@ -468,6 +472,51 @@ extern "C" int bp_server_run(bp_server *sv, int32_t rounds, int32_t *busy) {
     return BP_OK;
 }
 
+// Take a request that still waits in the host queue out of it; it
+// finishes at once as cancelled.
+static void server_cancel_pending(bp_server *sv, std::deque<int64_t>::iterator at, double t) {
+    ServerReq &R = sv->reqs[*at];
+    R.cancelled = true;
+    R.done = true;
+    R.done_us = t;
+    sv->completed.push_back(R.id);
+    sv->unfinished -= 1;
+    sv->pending.erase(at);
+}
+
+extern "C" int bp_server_cancel(bp_server *sv, int64_t id) {
+    g_err.clear();
+    if (!sv) return fail(BP_EINVAL, "bp_server_cancel: null server");
+    auto it = sv->reqs.find(id);
+    if (it == sv->reqs.end()) return fail(BP_EINVAL, "unknown request id");
+    const ServerReq &R = it->second;
+    if (R.done || R.on_device)
+        return fail(BP_ESTATE, R.done ? "request has finished" : "request's jobs are on the device");
+    auto at = std::find(sv->pending.begin(), sv->pending.end(), id);
+    if (at == sv->pending.end()) return fail(BP_ESTATE, "request is not queued");
+    server_cancel_pending(sv, at, sv->now_us());
+    return BP_OK;
+}
+
+extern "C" int bp_server_expire(bp_server *sv, double max_wait_us, int32_t *n) {
+    g_err.clear();
+    if (!sv || !(max_wait_us >= 0.0)) return fail(BP_EINVAL, "bp_server_expire: bad argument");
+    const double t = sv->now_us();
+    int32_t k = 0;
+    for (auto at = sv->pending.begin(); at != sv->pending.end();) {
+        if (t - sv->reqs[*at].submit_us > max_wait_us) {
+            const auto pos = at - sv->pending.begin();
+            server_cancel_pending(sv, at, t);
+            at = sv->pending.begin() + pos;
+            ++k;
+        } else {
+            ++at;
+        }
+    }
+    if (n) *n = k;
+    return BP_OK;
+}
+
 extern "C" int bp_server_poll(bp_server *sv, bp_completion *out, int32_t max, int32_t *n) {
     if (!sv || !n || max < 0 || (max > 0 && !out)) return fail(BP_EINVAL, "bp_server_poll: bad argument");
     int32_t k = 0;
@@ -478,7 +527,7 @@ extern "C" int bp_server_poll(bp_server *sv, bp_completion *out, int32_t max, in
         c.instance = R.inst;
         c.kind = R.kind;
         c.jobs = R.njobs;
-        c.reserved = 0;
+        c.flags = R.cancelled ? BP_COMPLETION_CANCELLED : 0;
         c.submit_us = R.submit_us;
         c.done_us = R.done_us;
         sv->completed.pop_front();
@@ -496,6 +545,7 @@ extern "C" int bp_server_results(bp_server *sv, int64_t id, int8_t *status, int3
     auto it = sv->reqs.find(id);
     if (it == sv->reqs.end()) return fail(BP_EINVAL, "unknown request id");
     const ServerReq &R = it->second;
+    if (R.cancelled) return fail(BP_ECANCELED, "request was cancelled before it ran");
     if (!R.done) return fail(BP_ESTATE, "request has not finished");
     int64_t tot = 0;
     for (int32_t j = 0; j < R.njobs; ++j) tot += (int64_t)R.lvar[j].size();

@@ -85,6 +85,8 @@ static int tune_apply(bp_instance *h, const bp_tuning &t, hipStream_t st) {
 
 extern "C" int bp_autotune(bp_instance *h, const double *lb, const double *ub, const int32_t *vars,
                            int32_t k, const char *cache_path, bp_tuning *out, void *stream) {
+    BP_RANGE("bp_autotune");
+    BP_TABLES_CHECK(h);
     g_err.clear();
     if (!h || !out || (h->n > 0 && (!lb || !ub)) || k < 0 || (k > 0 && !vars))
         return fail(BP_EINVAL, "bp_autotune: bad argument");
@@ -249,6 +251,8 @@ static bool tune_lookup_batch(const char *path, const std::string &key, bp_tunin
 extern "C" int bp_autotune_batch(bp_instance *h, int32_t B, const double *lb, const double *ub,
                                  const int64_t *changed_ptr, const int32_t *changed_idx,
                                  const char *cache_path, bp_tuning *out, void *stream) {
+    BP_RANGE("bp_autotune_batch");
+    BP_TABLES_CHECK(h);
     g_err.clear();
     if (!h || !out || B <= 0 || (h->n > 0 && (!lb || !ub)))
         return fail(BP_EINVAL, "bp_autotune_batch: bad argument");

@@ -440,3 +440,66 @@ def bulk_fix_vectors(inst, lb, ub, count: int, frac: float = 0.05, seed: int = 0
         UB[v, pick] = val
         changed.append(pick)
     return LB, UB, changed
+
+
+# ---------------------------------------------------------------------------
+# Instance files: an .npz of the arrays plus a sha256 manifest beside it.
+# ---------------------------------------------------------------------------
+ARRAYS = ("row_ptr", "col", "val", "lo", "hi", "vtype", "lb", "ub")
+
+
+def digest(inst) -> str:
+    """sha256 over the instance's arrays (row pointers, columns,
+    coefficients, sides, types, bounds) in that order, as their bytes."""
+    import hashlib
+    h = hashlib.sha256()
+    for k in ARRAYS:
+        h.update(np.ascontiguousarray(inst[k]).tobytes())
+    return h.hexdigest()
+
+
+def _manifest(inst) -> dict:
+    import hashlib
+    return {"m": int(inst["m"]), "n": int(inst["n"]), "sha256": digest(inst),
+            "arrays": {k: {"dtype": str(np.asarray(inst[k]).dtype),
+                           "shape": list(np.asarray(inst[k]).shape),
+                           "sha256": hashlib.sha256(np.ascontiguousarray(inst[k]).tobytes()).hexdigest()}
+                       for k in ARRAYS}}
+
+
+def save(inst, path: str) -> str:
+    """Write the instance to ``path`` (.npz, uncompressed) and its manifest
+    to ``path + '.sha256.json'``; returns the instance digest."""
+    import json
+    arrays = {k: np.ascontiguousarray(inst[k]) for k in ARRAYS}
+    if "xstar" in inst:
+        arrays["xstar"] = np.ascontiguousarray(inst["xstar"])
+    with open(path, "wb") as fh:
+        np.savez(fh, m=np.int64(inst["m"]), n=np.int64(inst["n"]), **arrays)
+    man = _manifest(inst)
+    with open(path + ".sha256.json", "w") as fh:
+        json.dump(man, fh, indent=1, sort_keys=True)
+    return man["sha256"]
+
+
+def load(path: str, verify: bool = True) -> dict:
+    """Read an instance written by ``save``; with ``verify`` every array is
+    checked against the manifest (ValueError on a mismatch or a missing
+    manifest)."""
+    import json
+    with np.load(path, allow_pickle=False) as z:
+        inst = {k: z[k] for k in z.files}
+    inst["m"] = int(inst["m"])
+    inst["n"] = int(inst["n"])
+    if verify:
+        try:
+            with open(path + ".sha256.json") as fh:
+                want = json.load(fh)
+        except FileNotFoundError:
+            raise ValueError("no manifest beside %s" % path)
+        got = _manifest(inst)
+        if got != want:
+            bad = [k for k in ARRAYS if got["arrays"][k] != want["arrays"].get(k)]
+            raise ValueError("instance %s does not match its manifest (%s)"
+                             % (path, ", ".join(bad) or "sizes"))
+    return inst

@@ -46,3 +46,14 @@ def test_host_side_errors_without_gpu():
 def test_binding_exports_match_header():
     from paper_2510_20499_amd import bp
     assert sorted(bp.EXPORTS) == declared_functions()
+
+
+def test_failure_hook_and_server_queue_calls_check_arguments_without_gpu():
+    from paper_2510_20499_amd import bp
+    lib = bp.lib()
+    assert lib.bp_debug_fail_alloc(-1) == bp.BP_EINVAL
+    assert lib.bp_debug_fail_alloc(0) == bp.BP_OK
+    assert lib.bp_server_cancel(None, 1) == bp.BP_EINVAL
+    n = C.c_int32(7)
+    assert lib.bp_server_expire(None, 1.0, C.byref(n)) == bp.BP_EINVAL
+    assert n.value == 7  # untouched on error
