@@ -29,36 +29,49 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E datasheet peak
 
 
-# HBM traffic of k_rows on the single-instance workload, from rocprofv3
-# --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of `bench.py --profile-steps 5`
-# (averages over its 400 launches), scaled by what the same counters read
-# for a 1 GiB device copy (FETCH_SIZE x2.0, WRITE_SIZE x1.0).  The figure
-# belongs to the kernel sources it was measured on: when any of them
+# HBM traffic per launch of the kernels the roofline records cover, from
+# rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs (one counter per run;
+# the commands are in profiles/), averaged over the named launches and scaled
+# by what the same counters read for a 1 GiB device copy (FETCH_SIZE x2.0,
+# WRITE_SIZE x1.0).  The figures belong to the library sources they were
+# measured on (SOURCES_SHA256, see sources_sha256()): when any source
 # differs, the bench line reports null.
-K_ROWS_TRAFFIC = {
-    "fetch_kib": 1869.6, "write_kib": 191.7, "fetch_scale": 2.0, "write_scale": 1.0,
-    "sources": {
-        "paper_2510_20499_amd/csrc/bp_kernels.h": "9d05fedec86ef73f51f4a8e444b698433815339ce87a4e83f89a95a1faa6500a",
-        "paper_2510_20499_amd/csrc/bp_carry.h": "b1eff190d608e908e8c3f26c2e243dacd0c147e4c4fcbfc82bb1cfff34e98925",
-        "paper_2510_20499_amd/csrc/bp_sum.h": "833f834eb740e1aaeae0a7fe22dd2566f3b231f64aa197bf2945502c9275c3e9",
-        "paper_2510_20499_amd/csrc/bp_engine.hip": "f744540542cfb47807e7c385ad294e73e1741b1b1f5b0b702681e1e88c38c025",
-        "paper_2510_20499_amd/build.py": "59ebd25b1830763aa61f6bec85069db133f4df462c1f98ccd7131cf909bc6407",
-    },
+SOURCES_SHA256 = "3b5104936884fceda3168f517e81046edfe1f898edb5660d990d3bbd458c05b1"
+TRAFFIC = {
+    # single-instance workload, `bench.py --profile-steps 5`: 5 cold calls of
+    # 79 working launches each (KiB per working launch)
+    "plain k_rows": {"fetch_kib": 1861.96, "write_kib": 194.16, "fetch_scale": 2.0, "write_scale": 1.0},
+    "plain k_apply": {"fetch_kib": 403.89, "write_kib": 177.45, "fetch_scale": 2.0, "write_scale": 1.0},
+    # probe workload, `bench.py --only-probe --profile-probe 3`: 4 batched
+    # calls of 8192 probes, 32 launches each
+    "probe k_rows": {"fetch_kib": 864302.5, "write_kib": 66892.4, "fetch_scale": 2.0, "write_scale": 1.0},
+    # bulk workload, `bench.py --only-bulk --profile-bulk 2 --bulk-schedule
+    # 4096,16`: 3 calls of 256 vectors, one working launch each
+    "bulk k_lv_rows": {"fetch_kib": 21012876.8, "write_kib": 675080.1, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 
-# The bound-update kernel k_apply in the same counter runs.
-K_APPLY_TRAFFIC = dict(K_ROWS_TRAFFIC, fetch_kib=397.4, write_kib=188.4)
-
-
-def measured_traffic(t=K_ROWS_TRAFFIC):
-    """HBM bytes per launch of the kernel a record covers, or None when the
-    sources changed since the counters were taken."""
+def sources_sha256():
+    """sha256 over the library's kernel sources and build script, in name
+    order: what the traffic records were measured on."""
+    import glob
     import hashlib
-    for rel, digest in t["sources"].items():
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            if hashlib.sha256(fh.read()).hexdigest() != digest:
-                return None
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2510_20499_amd", "csrc", "*")))
+    files.append(os.path.join(ROOT, "paper_2510_20499_amd", "build.py"))
+    for f in files:
+        h.update(os.path.relpath(f, ROOT).encode())
+        with open(f, "rb") as fh:
+            h.update(hashlib.sha256(fh.read()).digest())
+    return h.hexdigest()
+
+
+def measured_traffic(key):
+    """HBM bytes per launch for TRAFFIC[key], or None when there is no
+    record or the sources changed since the counters were taken."""
+    t = TRAFFIC.get(key)
+    if t is None or SOURCES_SHA256 is None or sources_sha256() != SOURCES_SHA256:
+        return None
     return int((t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024)
 
 
@@ -196,6 +209,10 @@ def main():
     ap.add_argument("--bulk-steps", type=int, default=3)
     ap.add_argument("--bulk-plain", type=int, default=16,
                     help="vectors propagated one call at a time for the plain baseline")
+    ap.add_argument("--profile-probe", type=int, default=0,
+                    help="only the probe leg's root and this many batched calls (counter runs)")
+    ap.add_argument("--bulk-schedule", default="",
+                    help="lv_grid,rounds_per_launch for --profile-bulk (the tuned schedule)")
     ap.add_argument("--profile-bulk", type=int, default=0,
                     help="run only this many batched bulk calls (no tuning, no baselines; "
                          "for profilers) and exit")
@@ -287,10 +304,10 @@ def main():
     value = total_nnz / dt
 
     roofline = kernel_roofline(bp, inst, lambda J: J.propagate(*fresh(lb0, ub0)))
-    roofline["traffic"] = measured_traffic()
+    roofline["traffic"] = measured_traffic("plain k_rows")
     other = roofline.pop("apply", None)
     if other is not None:
-        other["traffic"] = measured_traffic(K_APPLY_TRAFFIC)
+        other["traffic"] = measured_traffic("plain k_apply")
         # the roofline is the kernel with the larger share of a call
         if other["avg_launch_us"] > roofline["avg_launch_us"]:
             roofline, other = other, roofline
@@ -528,6 +545,12 @@ def bench_probe(args, bp, gen, torch, np):
     G = I.probe(vars_d)  # warm (sizes the output buffers)
     cap = int(G["off"][-1].item()) + 16
     torch.cuda.synchronize()
+    if args.profile_probe:
+        # counter runs: only batched calls after the root
+        for _ in range(args.profile_probe):
+            G = I.probe(vars_d, cap=cap)
+        torch.cuda.synchronize()
+        return {"profile_probe": args.profile_probe, "nnz_per_call": int(G["nnz"].sum().item())}
     reps = 3
     t0 = time.perf_counter()
     for _ in range(reps):
@@ -564,6 +587,7 @@ def bench_probe(args, bp, gen, torch, np):
         "infeasible_probes": int((G["status"] == bp.BP_INFEASIBLE).sum().item()),
     }
     res["roofline"] = probe_roofline(bp, inst, lb, ub, vars_d, cap, tb, torch)
+    res["roofline"]["traffic"] = measured_traffic("probe k_rows")
     log("probe: batched %.2f ms, k_rows %.1f GB/s (%.4f of peak), call %.1f GB/s"
         % (tb * 1e3, res["roofline"]["achieved"], res["roofline"]["frac"],
            res["roofline"]["call_alg_GBps"]))
@@ -701,8 +725,14 @@ def bench_bulk(args, bp, gen, torch, np):
     lb0 = torch.tensor(inst["lb"], dtype=torch.float64, device=dev)
     ub0 = torch.tensor(inst["ub"], dtype=torch.float64, device=dev)
     if args.profile_bulk:
+        # counter runs: the schedule the bench line's tuner chose, given
         tune = dict(trials=0)
         opt_kw = {}
+        if args.bulk_schedule:
+            g, r = (int(x) for x in args.bulk_schedule.split(","))
+            opt_kw = dict(lv_grid=g, rounds_per_launch=r)
+            I.close()
+            I = bp.Instance(inst, bp.default_options(**opt_kw))
     else:
         tune = I.autotune(lb0, ub0)
         opt_kw = dict(heavy_threshold=tune["heavy_threshold"], heavy_chunk=tune["heavy_chunk"],
@@ -811,6 +841,7 @@ def bench_bulk(args, bp, gen, torch, np):
         return batch_call(J)
 
     roof = kernel_roofline(bp, inst, with_base, reps=2, kernel="k_lv_rows", **opt_kw)
+    roof["traffic"] = measured_traffic("bulk k_lv_rows")
     cpu = cpu_all = None
     if args.bulk_cpu and not args.no_cpu_baseline:
         # The oracle's own root of this size takes minutes, so the CPU legs

@@ -1338,8 +1338,8 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(BP_ROWS
         qc[b] = scan ? (uint32_t)(P.allstart[b + 1] - P.allstart[b]) : H.qcount[b];
     const uint32_t C_ghchunks = scan ? 0u : H.ghchunks;
     // Heavy chunks: partial states of the queued chunks, or, with
-    // incremental accumulators, every chunk in a rebuild round and none
-    // otherwise.
+    // incremental accumulators, every chunk in a rebuild round and the
+    // queued row heads (one record per row) otherwise.
     const uint32_t C_hchunks = P.inc ? (H.hbuild ? (uint32_t)P.allhchunks * (uint32_t)P.inc_slots : H.hchunks)
                                      : (scan ? (uint32_t)P.allhchunks : H.hchunks);
     unsigned long long sc_rows = 0, sc_nnz = 0;

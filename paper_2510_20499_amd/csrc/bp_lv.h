@@ -738,6 +738,86 @@ __global__ void k_lv_fill_cand(longlong2 *c, size_t N) {
         c[j] = make_longlong2(dkey(-INF), dkey(INF));
 }
 
+// 64 x 64 bit matrix held one row per lane (bit c of lane r's word is
+// element (r, c)) transposed across the wave: lane c ends with column c.
+// Stage j exchanges bit j of the row index with bit j of the column index
+// (the off-diagonal j x j blocks of every 2j x 2j block swap); the six
+// exchanges commute and together transpose.
+__device__ __forceinline__ uint64_t wave_bit_transpose(uint64_t x) {
+    const uint64_t M[6] = {0xAAAAAAAAAAAAAAAAull, 0xCCCCCCCCCCCCCCCCull, 0xF0F0F0F0F0F0F0F0ull,
+                           0xFF00FF00FF00FF00ull, 0xFFFF0000FFFF0000ull, 0xFFFFFFFF00000000ull};
+    const int lane = __lane_id();
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        const int j = 1 << s;
+        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, j, 64);
+        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), j, 64);
+        const uint64_t y = ((uint64_t)hi << 32) | lo;
+        x = (lane & j) ? ((x & M[s]) | ((y & M[s]) >> j)) : ((x & ~M[s]) | ((y & ~M[s]) << j));
+    }
+    return x;
+}
+
+// Bounds in, overlay mode: the same records, flags and mask words as
+// k_lv_pack with a base, read without a transpose through LDS.  Tile: 64
+// variables x one group; each wave takes 16 vectors, one coalesced load of
+// lb and of ub per vector, compares with the base and ballots; the 64
+// ballots (bit c: variable i0 + c) are transposed into one mask word per
+// variable.  Only differing records are written.
+__global__ void __launch_bounds__(WG) k_lv_pack_overlay(const double *lb, const double *ub, double2 *bnd,
+                                                        int32_t n, int32_t B, int32_t V,
+                                                        const uint8_t *vtype, double feastol, int32_t *box,
+                                                        const double2 *base, uint64_t *dmask) {
+    __shared__ uint64_t words[64];
+    const int lane = __lane_id(), wave = threadIdx.x >> 6;
+    const int64_t tiles_i = (n + 63) / 64;
+    const int ngv = V / 64;
+    for (int64_t t = blockIdx.x; t < tiles_i * ngv; t += gridDim.x) {
+        const int64_t i0 = (t / ngv) * 64;
+        const int v0 = (int)(t % ngv) * 64;
+        const int64_t i = i0 + lane;
+        const bool iin = i < n;
+        double2 b0 = make_double2(0.0, 0.0);
+        double slack = 0.0;
+        if (iin) {
+            b0 = base[i];
+            slack = vtype[i] ? 0.0 : feastol;
+        }
+        // the wave's 16 vectors: every load issued before any use
+        double l[16], u[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int v = v0 + wave * 16 + q;
+            l[q] = 0.0;
+            u[q] = 0.0;
+            if (v < B && iin) {
+                l[q] = lb[(size_t)v * n + i];
+                u[q] = ub[(size_t)v * n + i];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int r = wave * 16 + q, v = v0 + r;
+            bool d = false;
+            if (v < B && iin) {
+                const double lq = canon0(l[q]), uq = canon0(u[q]);
+                if (isnan(lq) || isnan(uq)) atomicOr(&box[2 * v + 1], 1);
+                if (lq > uq + slack) atomicMin(&box[2 * v], (int32_t)i);
+                d = lq != b0.x || uq != b0.y;
+                if (d) bnd[(size_t)i * V + v] = make_double2(lq, uq);
+            }
+            const uint64_t m = __ballot(d);
+            if (lane == 0) words[r] = m;
+        }
+        __syncthreads();
+        if (wave == 0) {
+            const uint64_t col = wave_bit_transpose(words[lane]);
+            if (iin) dmask[(size_t)(v0 >> 6) * n + i] = col;
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void k_lv_fill_u64(uint64_t *p, size_t N) {
     for (size_t j = blockIdx.x * (size_t)blockDim.x + threadIdx.x; j < N; j += (size_t)gridDim.x * blockDim.x)
         p[j] = 0ull;
@@ -787,8 +867,10 @@ __global__ void k_lv_seed_cold(LvParams P, const int32_t *short_rows, int64_t ns
 // Warm start: the listed variables of every vector (entries of
 // changed_idx, vector v owning [ptr[v], ptr[v+1])) are marked in vmask and
 // listed once per group; k_lv_apply with seed = 1 then queues their rows.
+// lists = 0: only the (group, variable) masks are set (the rows are then
+// queued by k_lv_seed_rows, and the masks cleared whole afterwards).
 __global__ void k_lv_seed_vars(LvParams P, const int32_t *vars, const int64_t *ptr, int64_t e0,
-                               int64_t total) {
+                               int64_t total, int lists) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += stride) {
         const int64_t e = e0 + base + threadIdx.x;  // entry of vars; ptr is absolute
@@ -806,10 +888,12 @@ __global__ void k_lv_seed_vars(LvParams P, const int32_t *vars, const int64_t *p
             i = vars[e];
             if (P.vec[v].state == SLOT_ACTIVE) {
                 const uint64_t bit = 1ull << (v & 63);
-                const uint64_t old = atomicOr((unsigned long long *)&P.vmask[(size_t)(v >> 6) * P.n + i], bit);
-                first = old == 0;
+                unsigned long long *w = (unsigned long long *)&P.vmask[(size_t)(v >> 6) * P.n + i];
+                if (lists) first = atomicOr(w, bit) == 0;
+                else atomicOr(w, bit);
             }
         }
+        if (!lists) continue;  // uniform
         // one atomic per wave when the wave's new entries share a group
         const int g = v >> 6;
         const uint64_t fm = __ballot(first);
@@ -876,14 +960,6 @@ __global__ void __launch_bounds__(WG) k_lv_seed_rows(LvParams P) {
         atomicAdd(&P.vec[v].pending_rows, my_rows);
         atomicAdd(&P.vec[v].pending_nnz, my_nnz);
     }
-}
-
-// After row seeding: clear the variable masks that k_lv_seed_vars set.
-__global__ void k_lv_seed_clear(LvParams P) {
-    const int g = blockIdx.y;
-    const uint32_t cnt = P.ctl->nchg[g];
-    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += gridDim.x * blockDim.x)
-        P.vmask[(size_t)g * P.n + P.chg[(size_t)g * P.n + e]] = 0ull;
 }
 
 // After seeding: first-round counters of every vector.

@@ -256,9 +256,14 @@ static int lv_piece(bp_instance *h, int32_t Bp, double *lb, double *ub, const in
     }
     if (n > 0) {
         const int64_t tiles = (n + 63) / 64 * NG;
-        k_lv_pack<<<(int)std::min<int64_t>(tiles, 8192), WG, 0, st>>>(lb, ub, P.bnd, (int32_t)n, Bp, V,
-                                                                     h->vtype.as<uint8_t>(), h->opt.feastol,
-                                                                     L.box.as<int32_t>(), P.base, P.dmask);
+        if (P.base)
+            k_lv_pack_overlay<<<(int)std::min<int64_t>(tiles, 16384), WG, 0, st>>>(
+                lb, ub, P.bnd, (int32_t)n, Bp, V, h->vtype.as<uint8_t>(), h->opt.feastol, L.box.as<int32_t>(),
+                P.base, P.dmask);
+        else
+            k_lv_pack<<<(int)std::min<int64_t>(tiles, 8192), WG, 0, st>>>(lb, ub, P.bnd, (int32_t)n, Bp, V,
+                                                                         h->vtype.as<uint8_t>(), h->opt.feastol,
+                                                                         L.box.as<int32_t>(), P.base, P.dmask);
     }
     HIPTRY(hipGetLastError());
     std::vector<int32_t> box(2 * (size_t)V);
@@ -279,17 +284,19 @@ static int lv_piece(bp_instance *h, int32_t Bp, double *lb, double *ub, const in
             k_lv_seed_cold<<<dim3(std::max(1, gx / 4), NG), 256, 0, st>>>(
                 P, L.short_rows.as<int32_t>(), L.nshort, L.long_chunks.as<int2>(), L.nlong);
     } else if (ecount > 0) {
-        k_lv_seed_vars<<<grid_for(ecount), 256, 0, st>>>(P, idx, ptr_dev, e0, ecount);
         // Queue the rows of the listed variables: by columns (one atomic per
         // column entry and group) for short lists, by rows (a read of the
         // matrix per group, no atomics) when the columns would cover a good
-        // part of it.
+        // part of it.  The row path needs only the (group, variable) masks,
+        // which it then clears whole.
         const double col_cost = 4.0 * (double)std::min<int64_t>(ecount, (int64_t)n * NG) *
                                 ((double)h->nnz / (double)std::max<int64_t>(n, 1));
         const double row_cost = (double)NG * ((double)h->nnz + (double)h->m);
-        if (col_cost > row_cost) {
+        const bool by_rows = col_cost > row_cost;
+        k_lv_seed_vars<<<grid_for(ecount), 256, 0, st>>>(P, idx, ptr_dev, e0, ecount, by_rows ? 0 : 1);
+        if (by_rows) {
             k_lv_seed_rows<<<dim3(gx, NG), WG, 0, st>>>(P);
-            k_lv_seed_clear<<<dim3(std::max(1, gx / 4), NG), 256, 0, st>>>(P);
+            k_lv_fill_u64<<<4096, 256, 0, st>>>(P.vmask, (size_t)NG * n);
         } else {
             k_lv_apply<<<dim3(gx, NG), WG, 0, st>>>(P, 1);
         }
