@@ -231,6 +231,20 @@ __device__ __forceinline__ void lv_load(const LvParams &P, int g, int v, bool ne
             b[u] = P.bnd[(size_t)rl_i32(cj, t0 + u) * P.V + v];
 }
 
+// The two sides' terms of one nonzero, as add_terms computes them but
+// without branches: an infinite bound is counted and adds +0.0, which
+// leaves the state's exact value and error bound as they were (at most
+// the sign of a zero sum changes, and results store zeros as +0.0).
+__device__ __forceinline__ void lv_add_terms(Acc &mn, Acc &mx, double a, double lb, double ub) {
+    const bool pos = a > 0.0;
+    const double bmin = pos ? lb : ub, bmax = pos ? ub : lb;
+    const bool imin = isinf(bmin), imax = isinf(bmax);
+    mn.ninf += imin ? 1 : 0;
+    mx.ninf += imax ? 1 : 0;
+    acc_add(mn, imin ? 0.0 : a * bmin);
+    acc_add(mx, imax ? 0.0 : a * bmax);
+}
+
 // Activity over nonzeros [q0, q1) of a row (at most 64 per block), for the
 // lanes in `live`.  Columns and coefficients are loaded once per block,
 // one per lane, and broadcast; bound records are loaded LV_UNROLL at a time.
@@ -251,11 +265,11 @@ __device__ __forceinline__ void lv_accumulate(const LvParams &P, int g, int v, b
 #pragma unroll
             for (int u = 0; u < LV_UNROLL; ++u) {
                 if (t0 + u < len) {
+                    // every lane accumulates, without branches; the states
+                    // of lanes that are not live are never read
                     double a = rl_f64(aj, t0 + u);
-                    if (live) {
-                        add_terms(mn, mx, a, b[u].x, b[u].y);
-                        wmax = fmax(wmax, nz_width(a, b[u].x, b[u].y));
-                    }
+                    lv_add_terms(mn, mx, a, b[u].x, b[u].y);
+                    wmax = fmax(wmax, nz_width(a, b[u].x, b[u].y));
                     lv_count_read(P, g, rl_i32(cj, t0 + u), livemask, K);
                 }
             }
