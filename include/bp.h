@@ -520,9 +520,22 @@ typedef struct {
  * budget bounds the slot pool, not each request's own footprint.  The
  * request queue and the result staging (about 1.2 GB: 2^21 jobs, 2^24
  * fixings, 2^25 staged implications) are allocated beside the budget.  The
- * instances must outlive the server. */
+ * instances must outlive the server, or their eviction (bp_server_evict). */
 int bp_server_create(bp_instance *const *instances, int32_t count, const bp_options *opt,
                      int64_t budget_bytes, void *stream, bp_server **out);
+
+/* Serve one more loaded instance (with a base; BP_ESTATE otherwise) under
+ * the next free index (*index; an evicted instance's index is reused).
+ * BP_ECAPACITY if the instance does not fit the slots sized at creation
+ * (more variables, rows, row-bin tasks or heavy chunks than the largest
+ * instance then) or the table of 4096 instances is full; BP_EINVAL for a
+ * different heavy chunk size or an instance already served. */
+int bp_server_add_instance(bp_server *sv, bp_instance *instance, int32_t *index);
+
+/* Stop serving instance `index`: later requests for it get BP_EINVAL, and
+ * its owner may free it.  BP_ESTATE while it has requests that are neither
+ * finished nor cancelled; BP_EINVAL for an index not served. */
+int bp_server_evict(bp_server *sv, int32_t index);
 
 /* Queue a request (arrays are copied).  BP_EINVAL for a bad instance index,
  * kind, variable, a repeated variable, or a probe variable that is not a

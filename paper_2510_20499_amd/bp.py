@@ -28,7 +28,8 @@ EXPORTS = ["bp_options_default", "bp_load", "bp_propagate", "bp_propagate_batch"
            "bp_server_create", "bp_server_submit", "bp_server_run", "bp_server_poll",
            "bp_server_results", "bp_server_info", "bp_server_destroy", "bp_autotune",
            "bp_scores", "bp_probe_order", "bp_round", "bp_scores_noalloc", "bp_repair",
-           "bp_autotune_batch", "bp_debug_fail_alloc", "bp_server_cancel", "bp_server_expire"]
+           "bp_autotune_batch", "bp_debug_fail_alloc", "bp_server_cancel", "bp_server_expire",
+           "bp_server_add_instance", "bp_server_evict"]
 REQ_PROBE, REQ_PROPAGATE = 0, 1
 
 
@@ -192,6 +193,10 @@ def load_library(path: str = LIB_PATH):
     lib.bp_server_cancel.restype = C.c_int
     lib.bp_server_expire.argtypes = [C.c_void_p, C.c_double, C.POINTER(C.c_int32)]
     lib.bp_server_expire.restype = C.c_int
+    lib.bp_server_add_instance.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]
+    lib.bp_server_add_instance.restype = C.c_int
+    lib.bp_server_evict.argtypes = [C.c_void_p, C.c_int32]
+    lib.bp_server_evict.restype = C.c_int
     lib.bp_debug_fail_alloc.argtypes = [C.c_int64]
     lib.bp_debug_fail_alloc.restype = C.c_int
     return lib
@@ -522,6 +527,22 @@ class Server:
         return [dict(id=buf[i].id, instance=buf[i].instance, kind=buf[i].kind, jobs=buf[i].jobs,
                      cancelled=bool(buf[i].flags & COMPLETION_CANCELLED),
                      submit_us=buf[i].submit_us, done_us=buf[i].done_us) for i in range(n.value)]
+
+    def add_instance(self, instance) -> int:
+        """bp_server_add_instance: serve one more loaded Instance; returns
+        its index."""
+        t = C.c_int32()
+        _check(_LIB.bp_server_add_instance(self._h, instance._h, C.byref(t)))
+        while len(self._insts) <= t.value:
+            self._insts.append(None)
+        self._insts[t.value] = instance
+        return t.value
+
+    def evict(self, index: int):
+        """bp_server_evict: stop serving instance `index` (BP_ESTATE while it
+        has unfinished requests)."""
+        _check(_LIB.bp_server_evict(self._h, index))
+        self._insts[index] = None
 
     def cancel(self, rid: int):
         """bp_server_cancel: take a request that still waits in the host

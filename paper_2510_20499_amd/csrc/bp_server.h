@@ -63,7 +63,10 @@ struct ServerReq {
 };
 
 struct bp_server {
-    std::vector<bp_instance *> insts;
+    std::vector<bp_instance *> insts;  // nullptr: evicted
+    std::vector<int64_t> inst_open;    // unfinished requests per instance
+    Shape shape;                       // the slot shape every instance must fit
+    int64_t cap_insts = 0;             // entries of the device instance table
     bp_options opt;
     int32_t heavy_chunk = 1024;
     hipStream_t st = nullptr;
@@ -99,6 +102,11 @@ struct bp_server {
         return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
     }
 };
+
+// Entries of a server's device instance table (instances added after
+// creation take free entries; the table never moves, so captured graphs
+// keep reading it).
+constexpr int64_t SERVER_MAX_INSTANCES = 4096;
 
 // Device bytes one slot of shape `sh` needs (the engine's per-slot arrays).
 static int64_t slot_bytes(const Shape &sh) {
@@ -142,6 +150,8 @@ extern "C" int bp_server_create(bp_instance *const *instances, int32_t count, co
         sh.heavy_rows = std::max(sh.heavy_rows, s1.heavy_rows);
         sv->insts.push_back(h);
     }
+    sv->inst_open.assign(sv->insts.size(), 0);
+    sv->shape = sh;
     sv->bytes_per_slot = slot_bytes(sh);
     int64_t fit = budget_bytes / sv->bytes_per_slot;
     sv->slots = (int32_t)std::min<int64_t>(fit, std::max(1, sv->opt.probe_slots));
@@ -163,7 +173,8 @@ extern "C" int bp_server_create(bp_instance *const *instances, int32_t count, co
         sv->base.push_back(std::move(bs));
     }
     int64_t dummy = 0;
-    if (int rc = sv->dinst.alloc(tab.size() * sizeof(DInst), dummy)) return rc;
+    sv->cap_insts = std::max<int64_t>((int64_t)tab.size(), SERVER_MAX_INSTANCES);
+    if (int rc = sv->dinst.alloc((size_t)sv->cap_insts * sizeof(DInst), dummy)) return rc;
     HIPTRY(hipMemcpyAsync(sv->dinst.p, tab.data(), tab.size() * sizeof(DInst), hipMemcpyHostToDevice, st));
     // job storage
     sv->cap_jobs = 1 << 21;
@@ -235,6 +246,71 @@ extern "C" int bp_server_info(const bp_server *sv, int32_t *slots, int64_t *byte
     return BP_OK;
 }
 
+extern "C" int bp_server_add_instance(bp_server *sv, bp_instance *h, int32_t *index) {
+    BP_RANGE("bp_server_add_instance");
+    g_err.clear();
+    if (!sv || !h || !index) return fail(BP_EINVAL, "bp_server_add_instance: null argument");
+    BP_TABLES_CHECK(h);
+    if (!h->have_base) return fail(BP_ESTATE, "instance has no base");
+    if (h->heavy_chunk != sv->heavy_chunk) return fail(BP_EINVAL, "instances must share the heavy chunk size");
+    for (bp_instance *o : sv->insts)
+        if (o == h) return fail(BP_EINVAL, "instance already served");
+    if (!sv->shape.covers(shape_of(h)))
+        return fail(BP_ECAPACITY, "instance larger than the server's slots");
+    int32_t t = 0;
+    while (t < (int32_t)sv->insts.size() && sv->insts[t]) ++t;
+    if (t >= sv->cap_insts) return fail(BP_ECAPACITY, "instance table full");
+    hipStream_t st = sv->st;
+    std::vector<uint8_t> vt(h->n);
+    std::vector<double2> bs(h->n);
+    if (h->n) {
+        HIPTRY(hipMemcpyAsync(vt.data(), h->vtype.p, h->n, hipMemcpyDeviceToHost, st));
+        HIPTRY(hipMemcpyAsync(bs.data(), h->base.p, (size_t)h->n * 16, hipMemcpyDeviceToHost, st));
+    }
+    const DInst d = dinst_of(h);
+    HIPTRY(hipMemcpyAsync(sv->dinst.as<DInst>() + t, &d, sizeof(DInst), hipMemcpyHostToDevice, st));
+    HIPTRY(hipStreamSynchronize(st));
+    if (t == (int32_t)sv->insts.size()) {
+        sv->insts.push_back(h);
+        sv->inst_open.push_back(0);
+        sv->vtype.push_back(std::move(vt));
+        sv->base.push_back(std::move(bs));
+    } else {
+        sv->insts[t] = h;
+        sv->inst_open[t] = 0;
+        sv->vtype[t] = std::move(vt);
+        sv->base[t] = std::move(bs);
+    }
+    *index = t;
+    return BP_OK;
+}
+
+extern "C" int bp_server_evict(bp_server *sv, int32_t index) {
+    g_err.clear();
+    if (!sv || index < 0 || index >= (int32_t)sv->insts.size() || !sv->insts[index])
+        return fail(BP_EINVAL, "bp_server_evict: no such instance");
+    if (sv->inst_open[index] > 0)
+        return fail(BP_ESTATE, "instance " + std::to_string(index) + " has unfinished requests");
+    sv->insts[index] = nullptr;
+    // The launch parameters name one instance as the default descriptor;
+    // point them at a served one (the graph is captured again) so nothing
+    // refers to an instance its owner may now free.
+    for (bp_instance *o : sv->insts) {
+        if (!o) continue;
+        sv->P.I = dinst_of(o);
+        if (sv->graph) {
+            (void)hipGraphExecDestroy(sv->graph);
+            sv->graph = nullptr;
+        }
+        break;
+    }
+    sv->vtype[index].clear();
+    sv->vtype[index].shrink_to_fit();
+    sv->base[index].clear();
+    sv->base[index].shrink_to_fit();
+    return BP_OK;
+}
+
 extern "C" int bp_server_submit(bp_server *sv, const bp_request *req, int64_t *id) {
     g_err.clear();
     if (!sv || !req || !id) return fail(BP_EINVAL, "bp_server_submit: null argument");
@@ -245,6 +321,7 @@ extern "C" int bp_server_submit(bp_server *sv, const bp_request *req, int64_t *i
     if (req->kind == BP_REQ_PROPAGATE && req->count > 0 && (!req->lb || !req->ub))
         return fail(BP_EINVAL, "propagate request without bounds");
     const bp_instance *h = sv->insts[req->instance];
+    if (!h) return fail(BP_EINVAL, "instance " + std::to_string(req->instance) + " was evicted");
     const int64_t njobs = req->kind == BP_REQ_PROBE ? 2 * (int64_t)req->count : 1;
     if (njobs > sv->cap_jobs || (req->kind == BP_REQ_PROPAGATE && req->count > sv->cap_fix))
         return fail(BP_EINVAL, "request larger than the server's job storage");
@@ -292,6 +369,7 @@ extern "C" int bp_server_submit(bp_server *sv, const bp_request *req, int64_t *i
         return BP_OK;
     }
     sv->pending.push_back(R.id);
+    sv->inst_open[R.inst] += 1;
     sv->reqs.emplace(R.id, std::move(R));
     sv->unfinished += 1;
     return BP_OK;
@@ -427,6 +505,7 @@ static int server_collect(bp_server *sv) {
             R.done_us = t;
             sv->completed.push_back(R.id);
             sv->unfinished -= 1;
+            sv->inst_open[R.inst] -= 1;
         }
     }
     sv->ring_seen = r1;
@@ -481,6 +560,7 @@ static void server_cancel_pending(bp_server *sv, std::deque<int64_t>::iterator a
     R.done_us = t;
     sv->completed.push_back(R.id);
     sv->unfinished -= 1;
+    sv->inst_open[R.inst] -= 1;
     sv->pending.erase(at);
 }
 

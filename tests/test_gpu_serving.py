@@ -221,3 +221,66 @@ def test_serving_integer_probes():
     for j, req in enumerate(reqs):
         t = req[0]
         _same(mix[j], _oracle_result(insts[t], bases[t], req), insts[t], "intprobe%d" % j)
+
+
+def _drain(S):
+    guard = 0
+    while S.run(8):
+        guard += 1
+        assert guard < 10000
+    return {c["id"]: c for c in S.poll(100000)}
+
+
+def _check_requests(S, done, ids, reqs, insts, bases, what):
+    for rid, q in zip(ids, reqs):
+        t = q[0]
+        got = S.results(rid, done[rid]["jobs"])
+        _same(got, _oracle_result(insts[t], bases[t], q), insts[t], "%s %d" % (what, rid),
+              evidence=q[1] == bp().REQ_PROPAGATE)
+
+
+def test_serving_add_and_evict_instances():
+    insts, loaded, bases = _instances()
+    # the slots are sized by the instances given at creation; every row
+    # bin of tiny_inf fits them
+    S = bp().Server([loaded[4], loaded[0], loaded[2]], 1 << 28)
+    order = [4, 0, 2]  # server index -> _instances() index
+    reqs = [q for q in _requests(insts, bases, 40, seed=21) if q[0] in order][:12]
+    local = [(order.index(q[0]),) + q[1:] for q in reqs]
+    ids = [S.submit(*q) for q in local]
+    busy = {order.index(q[0]) for q in reqs}
+    for t in busy:  # instances with queued requests stay
+        with pytest.raises(bp().BPError) as e:
+            S.evict(t)
+        assert e.value.code == bp().BP_ESTATE
+    done = _drain(S)
+    _check_requests(S, done, ids, reqs, insts, bases, "before eviction")
+    S.evict(1)
+    S.evict(2)
+    vs = np.array([0], np.int32)
+    with pytest.raises(bp().BPError) as e:
+        S.submit(1, bp().REQ_PROBE, vs)
+    assert e.value.code == bp().BP_EINVAL
+    with pytest.raises(bp().BPError) as e:
+        S.evict(1)
+    assert e.value.code == bp().BP_EINVAL
+    # freed indices are taken in order
+    assert S.add_instance(loaded[1]) == 1
+    assert S.add_instance(loaded[2]) == 2
+    order = [4, 1, 2]
+    with pytest.raises(bp().BPError) as e:
+        S.add_instance(loaded[1])
+    assert e.value.code == bp().BP_EINVAL
+    reqs = [q for q in _requests(insts, bases, 60, seed=22) if q[0] in order][:18]
+    local = [(order.index(q[0]),) + q[1:] for q in reqs]
+    ids = [S.submit(*q) for q in local]
+    done = _drain(S)
+    _check_requests(S, done, ids, reqs, insts, bases, "after adding")
+    # an instance larger than the slots is refused
+    big = gen.make("single", 6, scale=0.2)
+    B = bp().Instance(big, bp().default_options(heavy_threshold=2048))
+    r, lb, ub = gpu_propagate(B, big)
+    assert r["status"] == bp().BP_OK
+    with pytest.raises(bp().BPError) as e:
+        S.add_instance(B)
+    assert e.value.code == bp().BP_ECAPACITY
