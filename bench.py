@@ -232,6 +232,7 @@ def main():
     ap.add_argument("--skip-round", action="store_true",
                     help="skip the bound-propagation rounding measurement")
     ap.add_argument("--only-round", action="store_true")
+    ap.add_argument("--only-tiny", action="store_true")
     ap.add_argument("--round-reps", type=int, default=2)
     ap.add_argument("--round-cpu-scale", type=float, default=0.2,
                     help="scale of the single-instance workload the oracle rounds for the "
@@ -249,6 +250,9 @@ def main():
 
     if args.only_probe:
         print(json.dumps({"probe_batched": bench_probe(args, bp, gen, torch, np)}), flush=True)
+        return
+    if args.only_tiny:
+        print(json.dumps({"tiny": bench_tiny(args, bp, gen, torch, np)}), flush=True)
         return
     if args.only_round:
         print(json.dumps({"rounding": bench_round(args, bp, gen, torch, np)}), flush=True)

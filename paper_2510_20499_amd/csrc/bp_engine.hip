@@ -137,14 +137,24 @@ struct Engine {
     // grouped heavy rows of job slots (allocated on request)
     int32_t grouped = 0;
     DevBuf ghmask[2], ghrec[2], ghpart, ghlive, dmaskg;
-    // captured graph of `graph_rounds` rounds for this engine's Params
-    hipGraphExec_t graph = nullptr;
-    int graph_rounds = 0;
-    Params graph_params;
-    JobIO graph_io;
-    bool graph_jobs = false;
+    // Captured graphs of K rounds, keyed by their kernel arguments (held by
+    // value): calls that alternate between argument sets (a propagation
+    // and a probe on one instance) each keep theirs; the least recently
+    // used is replaced.
+    struct GraphEntry {
+        hipGraphExec_t exec = nullptr;
+        int rounds = 0;
+        bool jobs = false;
+        Params P;
+        JobIO io;
+        uint64_t used = 0;
+    };
+    static constexpr int GRAPHS = 4;
+    GraphEntry graphs[GRAPHS];
+    uint64_t graph_clock = 0;
     ~Engine() {
-        if (graph) (void)hipGraphExecDestroy(graph);
+        for (GraphEntry &g : graphs)
+            if (g.exec) (void)hipGraphExecDestroy(g.exec);
     }
 };
 
@@ -833,10 +843,18 @@ static int run_rounds(bp_instance *h, const Params &P, const JobIO *io, int64_t 
                 h->stats.apply_ms += ms;
             }
         } else {
-            if (!E.graph || E.graph_rounds != K) {
-                if (E.graph) {
-                    (void)hipGraphExecDestroy(E.graph);
-                    E.graph = nullptr;
+            Engine::GraphEntry *G = nullptr;
+            for (Engine::GraphEntry &g : E.graphs)
+                if (g.exec && g.rounds == K && g.jobs == (io != nullptr) &&
+                    memcmp(&g.P, &P, sizeof(Params)) == 0 && (!io || memcmp(&g.io, io, sizeof(JobIO)) == 0))
+                    G = &g;
+            if (!G) {
+                G = &E.graphs[0];
+                for (Engine::GraphEntry &g : E.graphs)
+                    if (!g.exec || g.used < G->used) G = &g;
+                if (G->exec) {
+                    (void)hipGraphExecDestroy(G->exec);
+                    G->exec = nullptr;
                 }
                 hipStream_t cs;
                 HIPTRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -850,13 +868,18 @@ static int run_rounds(bp_instance *h, const Params &P, const JobIO *io, int64_t 
                 }
                 hipGraph_t g;
                 HIPTRY(hipStreamEndCapture(cs, &g));
-                hipError_t e = hipGraphInstantiate(&E.graph, g, nullptr, nullptr, 0);
+                hipError_t e = hipGraphInstantiate(&G->exec, g, nullptr, nullptr, 0);
                 (void)hipGraphDestroy(g);
                 (void)hipStreamDestroy(cs);
+                if (e != hipSuccess) G->exec = nullptr;
                 HIPTRY(e);
-                E.graph_rounds = K;
+                G->rounds = K;
+                G->jobs = io != nullptr;
+                G->P = P;
+                if (io) G->io = *io;
             }
-            HIPTRY(hipGraphLaunch(E.graph, st));
+            G->used = ++E.graph_clock;
+            HIPTRY(hipGraphLaunch(G->exec, st));
             launched += K;
         }
         HIPTRY(hipMemcpyAsync(&hc, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
@@ -878,20 +901,6 @@ static int run_rounds(bp_instance *h, const Params &P, const JobIO *io, int64_t 
     return 0;
 }
 
-// Graphs hold their kernel arguments by value: rebuild when they change.
-static void invalidate_graph(bp_instance *h, const Params &P, const JobIO *io) {
-    Engine &E = *h->eng;
-    bool same = E.graph && memcmp(&E.graph_params, &P, sizeof(Params)) == 0 &&
-                E.graph_jobs == (io != nullptr) &&
-                (!io || memcmp(&E.graph_io, io, sizeof(JobIO)) == 0);
-    if (E.graph && !same) {
-        (void)hipGraphExecDestroy(E.graph);
-        E.graph = nullptr;
-    }
-    E.graph_params = P;
-    E.graph_jobs = io != nullptr;
-    if (io) E.graph_io = *io;
-}
 
 // Reset the slots [0, ns) to `state`.
 __global__ void k_reset_slots(SlotInfo *info, int32_t ns, int32_t job0, int32_t state) {
@@ -1072,7 +1081,6 @@ static int propagate_slots(bp_instance *h, int32_t Bv, double *lb, double *ub,
                                                              h->cold_hbase_d.as<int32_t>(), nheavy, h->heavy_chunk,
                                                              E1.allhrec.as<int4>());
     }
-    invalidate_graph(h, P, nullptr);
     Engine &E = *h->eng;
     // Bounds in, box check.
     if (n > 0) k_pack<<<grid_for(n * Bv), 256, 0, st>>>(lb, ub, E.bnd.as<double2>(), n, Bv);
@@ -1453,7 +1461,6 @@ extern "C" int bp_probe(bp_instance *h, const int32_t *vars, int32_t k, bp_probe
         P.ghlive = E.ghlive.as<uint64_t>();
         P.dmaskg = E.dmaskg.as<uint64_t>();
     }
-    invalidate_graph(h, P, &IO);
     Ctl c;
     memset(&c, 0, sizeof(c));
     c.max_rounds = (uint32_t)h->opt.max_rounds;
