@@ -970,6 +970,27 @@ def bench_bulk_light(args, bp, gen, torch, np, inst, lb0, ub0, opt_kw, B):
     rounds = np.array([x["rounds"] for x in res])
     log("bulk light: %.1f ms per call, rounds mean %.2f, %d infeasible"
         % (tb * 1e3, rounds.mean(), int((status == bp.BP_INFEASIBLE).sum())))
+    # plain: the first vectors one per call (bp_propagate warm starts from
+    # the same base, with their fixings as the changed list)
+    kp = min(args.bulk_plain, B)
+    I.propagate(*fresh(fl, fu), empty)
+    torch.cuda.synchronize()
+    tp, nnz_p = 0.0, 0
+    for v in range(kp):
+        p, val = lists[v]
+        l1, u1 = fresh(fl, fu)
+        pd = torch.tensor(p, dtype=torch.int32, device=dev)
+        vd = torch.tensor(val, dtype=torch.float64, device=dev)
+        l1[pd.long()] = vd
+        u1[pd.long()] = vd
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r1 = I.propagate(l1, u1, pd)
+        torch.cuda.synchronize()
+        tp += time.perf_counter() - t
+        nnz_p += r1["nnz_propagated"]
+        assert r1 == res[v], (v, r1, res[v])
+    log("bulk light: plain %.2f ms per vector" % (tp / max(kp, 1) * 1e3))
     roof = kernel_roofline(bp, inst, call, reps=2, kernel="k_lv_rows", **o)
     del LB, UB
     return {"workload": "bulk rounding from the fixed-point root (%d rounds): %d vectors per call, "
@@ -978,6 +999,10 @@ def bench_bulk_light(args, bp, gen, torch, np, inst, lb0, ub0, opt_kw, B):
                         % (fp["rounds"], B, int(ptr[1]), 100 * args.bulk_light),
             "root_fixed_point": {"rounds": fp["rounds"], "ms": t_fp * 1e3},
             "batched_ms": tb * 1e3, "batched_nnz_per_s": nnz_b / tb, "batched_vectors_per_s": B / tb,
+            "plain_vectors_per_s": kp / tp if kp else None,
+            "plain_nnz_per_s": nnz_p / tp if kp else None,
+            "batched_over_plain": (B / tb) / (kp / tp) if kp else None,
+            "plain_sample": "the first %d vectors, one bp_propagate per vector" % kp,
             "infeasible": int((status == bp.BP_INFEASIBLE).sum()),
             "rounds_mean": float(rounds.mean()), "rounds_max": int(rounds.max()),
             "nnz_per_vector_mean": nnz_b / B, "roofline": roof}

@@ -45,6 +45,12 @@ namespace bp {
 #define BP_LV_WAVES 4  // waves per SIMD the row kernel's register budget targets
 #endif
 constexpr int LV_SHORT = 64;             // rows up to this length: one task
+// Chunks queued for at most this many vectors of a group split their
+// nonzeros over the wave, one vector at a time (lv_chunk_few).
+#ifndef BP_LV_FEW
+#define BP_LV_FEW 16
+#endif
+constexpr int LV_FEW = BP_LV_FEW;
 constexpr int LV_CHUNK = BP_LV_CHUNK;    // nonzeros per chunk of longer rows
 constexpr int LV_MAX_GROUPS = 128;       // batches of up to 8192 vectors
 constexpr int LV_UNROLL = BP_LV_UNROLL;  // bound loads issued together
@@ -377,6 +383,58 @@ __device__ void lv_short_row(const LvParams &P, int par, int g, int v, bool acti
     lv_candidates(P, g, v, want, R, p0, p1, wb);
 }
 
+// Chunk activity when the row is queued for few vectors of the group: the
+// wave splits the chunk's nonzeros instead of the vectors, one live vector
+// at a time, and the lanes' states are merged across the wave.  The sums
+// are correctly rounded exact sums, so the certified values are those of
+// the one-lane-per-vector loop; lane l ends with the state of vector l (a
+// zero state when l is not live).  Distinct records read are counted once
+// per nonzero for the whole live mask, as that loop counts them.
+__device__ void lv_chunk_few(const LvParams &P, int g, uint64_t livemask, int64_t q0, int64_t q1, Acc &own_mn,
+                             Acc &own_mx, double &own_w, LvCount &K) {
+    const int lane = __lane_id();
+    acc_zero(own_mn);
+    acc_zero(own_mx);
+    own_w = 0.0;
+    const uint64_t *dg = P.dmask + (size_t)g * P.n;
+    unsigned long long reads = 0;
+    bool first = true;
+    for (uint64_t rest = livemask; rest; rest &= rest - 1, first = false) {
+        const int vl = __ffsll((long long)rest) - 1;  // uniform
+        const size_t v = (size_t)g * 64 + vl;
+        Acc mn, mx;
+        acc_zero(mn);
+        acc_zero(mx);
+        double w = 0.0;
+        for (int64_t p = q0 + lane; p < q1; p += 64) {
+            const int i = P.I.col[p];
+            const double a = P.I.val[p];
+            double2 b;
+            if (P.base) b = ((dg[i] >> vl) & 1ull) ? P.bnd[(size_t)i * P.V + v] : P.base[i];
+            else b = P.bnd[(size_t)i * P.V + v];
+            lv_add_terms(mn, mx, a, b.x, b.y);
+            w = fmax(w, nz_width(a, b.x, b.y));
+            if (first && P.count_vars) {
+                const uint64_t old = atomicOr((unsigned long long *)&P.touched[(size_t)g * P.n + i], livemask);
+                reads += (unsigned long long)__popcll(livemask & ~old);
+            }
+        }
+        acc_group_reduce<64>(mn);
+        acc_group_reduce<64>(mx);
+        w = group_max<64>(w);
+        if (lane == vl) {
+            own_mn = mn;
+            own_mx = mx;
+            own_w = w;
+        }
+    }
+    if (P.count_vars) {
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) reads += __shfl_xor(reads, o, 64);
+        if (lane == 0) K.vars += reads;
+    }
+}
+
 // Chunk c of a long row: per-lane partial states.
 __device__ void lv_chunk_activity(const LvParams &P, int par, int g, int v, bool active, uint32_t u,
                                   LvCount &K) {
@@ -389,10 +447,14 @@ __device__ void lv_chunk_activity(const LvParams &P, int par, int g, int v, bool
     if (__lane_id() == 0) P.lmask[(size_t)g * P.lcap + u] = livemask;
     if (c == 0) lv_count_row(P, k, r1 - r0, K);
     Acc mn, mx;
-    acc_zero(mn);
-    acc_zero(mx);
     double wmax = 0.0;
-    lv_accumulate(P, g, v, live, livemask, q0, q1, mn, mx, wmax, K);
+    if (__popcll(livemask) <= LV_FEW) {
+        lv_chunk_few(P, g, livemask, q0, q1, mn, mx, wmax, K);
+    } else {
+        acc_zero(mn);
+        acc_zero(mx);
+        lv_accumulate(P, g, v, live, livemask, q0, q1, mn, mx, wmax, K);
+    }
     const size_t base = ((size_t)g * P.lcap + u) * 128;
     P.lpart[base + __lane_id()] = mn;
     P.lpart[base + 64 + __lane_id()] = mx;
