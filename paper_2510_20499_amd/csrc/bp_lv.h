@@ -35,8 +35,12 @@
 
 namespace bp {
 
+// Nonzeros per chunk of a long row: every chunk task merges the partial
+// states of all chunks of its row, so shorter chunks trade that merge
+// (quadratic in the chunk count) against parallelism.  1024 was the
+// fastest of 256-4096 on the bulk workload (both legs).
 #ifndef BP_LV_CHUNK
-#define BP_LV_CHUNK 512
+#define BP_LV_CHUNK 1024
 #endif
 #ifndef BP_LV_UNROLL
 #define BP_LV_UNROLL 8
@@ -333,6 +337,62 @@ __device__ __forceinline__ void lv_candidates(const LvParams &P, int g, int v, b
     }
 }
 
+// Candidates of nonzeros [q0, q1) for few vectors (the lanes in wantmask):
+// one vector at a time, the wave spread over the nonzeros.  The same keys,
+// masks and changed-list entries as lv_candidates: a variable enters the
+// group's list once, from the first vector whose bit it gets.
+__device__ void lv_candidates_few(const LvParams &P, int g, uint64_t wantmask, const RowAct &R, int64_t q0,
+                                  int64_t q1) {
+    const int lane = __lane_id();
+    const uint64_t *dg = P.dmask + (size_t)g * P.n;
+    for (uint64_t rest = wantmask; rest; rest &= rest - 1) {
+        const int vl = __ffsll((long long)rest) - 1;  // uniform
+        const size_t v = (size_t)g * 64 + vl;
+        RowAct Rv;
+        Rv.lo = __shfl(R.lo, vl, 64);
+        Rv.hi = __shfl(R.hi, vl, 64);
+        Rv.minfin = __shfl(R.minfin, vl, 64);
+        Rv.maxfin = __shfl(R.maxfin, vl, 64);
+        Rv.rng = __shfl(R.rng, vl, 64);
+        Rv.nmin = __shfl(R.nmin, vl, 64);
+        Rv.nmax = __shfl(R.nmax, vl, 64);
+        for (int64_t b0 = q0; b0 < q1; b0 += 64) {
+            const int64_t p = b0 + lane;
+            bool push = false;
+            int i = 0;
+            if (p < q1) {
+                i = P.I.col[p];
+                const double a = P.I.val[p];
+                double2 b;
+                if (P.base) b = ((dg[i] >> vl) & 1ull) ? P.bnd[(size_t)i * P.V + v] : P.base[i];
+                else b = P.bnd[(size_t)i * P.V + v];
+                const bool is_int = P.I.vtype[i] != 0;
+                double cl, cu;
+                nz_candidates(Rv, a, b.x, b.y, is_int, P.inttol, cl, cu);
+                longlong2 *cp = &P.cand[(size_t)i * P.V + v];
+                bool pass = false;
+                if (take_lower(is_int, cl, b.x, P.tau)) {
+                    atomicMax(&cp->x, dkey(canon0(cl)));
+                    pass = true;
+                }
+                if (take_upper(is_int, cu, b.y, P.tau)) {
+                    atomicMin(&cp->y, dkey(canon0(cu)));
+                    pass = true;
+                }
+                if (pass)
+                    push = atomicOr((unsigned long long *)&P.vmask[(size_t)g * P.n + i], 1ull << vl) == 0ull;
+            }
+            const uint64_t pm = __ballot(push);
+            if (pm) {
+                uint32_t at = 0;
+                if (lane == 0) at = atomicAdd(&P.ctl->nchg[g], (uint32_t)__popcll(pm));
+                at = __shfl(at, 0, 64);
+                if (push) P.chg[(size_t)g * P.n + at + lane_rank(pm)] = i;
+            }
+        }
+    }
+}
+
 // Certified activities of the lane's vector, with the exact fallback.
 __device__ __forceinline__ void lv_finish_act(const LvParams &P, int v, bool live, Acc &mn, Acc &mx,
                                               int64_t p0, int64_t p1, RowAct &R) {
@@ -522,12 +582,41 @@ __global__ void __launch_bounds__(WG) k_lv_heavy(LvParams P) {
         acc_zero(A);
         acc_zero(Bm);
         double wmax = 0.0;
-        for (int j = 0; j < nch; ++j) {
-            const size_t base = ((size_t)g * P.lcap + u0 + j) * 128;
-            Acc a = P.lpart[base + __lane_id()], b = P.lpart[base + 64 + __lane_id()];
-            acc_merge(A, a.s, a.c, a.e, a.ninf);
-            acc_merge(Bm, b.s, b.c, b.e, b.ninf);
-            wmax = fmax(wmax, P.lrng[((size_t)g * P.lcap + u0 + j) * 64 + __lane_id()]);
+        const uint64_t lm = __ballot(live);
+        if (__popcll(lm) <= LV_FEW) {
+            // few live vectors: one at a time, the lanes over the row's
+            // chunks, then a merge across the wave (exact sums: the
+            // certified values do not depend on the merge order)
+            for (uint64_t rest = lm; rest; rest &= rest - 1) {
+                const int vl = __ffsll((long long)rest) - 1;  // uniform
+                Acc a1, b1;
+                acc_zero(a1);
+                acc_zero(b1);
+                double w1 = 0.0;
+                for (int j = __lane_id(); j < nch; j += 64) {
+                    const size_t base = ((size_t)g * P.lcap + u0 + j) * 128;
+                    const Acc a = P.lpart[base + vl], b = P.lpart[base + 64 + vl];
+                    acc_merge(a1, a.s, a.c, a.e, a.ninf);
+                    acc_merge(b1, b.s, b.c, b.e, b.ninf);
+                    w1 = fmax(w1, P.lrng[((size_t)g * P.lcap + u0 + j) * 64 + vl]);
+                }
+                acc_group_reduce<64>(a1);
+                acc_group_reduce<64>(b1);
+                w1 = group_max<64>(w1);
+                if (__lane_id() == vl) {
+                    A = a1;
+                    Bm = b1;
+                    wmax = w1;
+                }
+            }
+        } else {
+            for (int j = 0; j < nch; ++j) {
+                const size_t base = ((size_t)g * P.lcap + u0 + j) * 128;
+                Acc a = P.lpart[base + __lane_id()], b = P.lpart[base + 64 + __lane_id()];
+                acc_merge(A, a.s, a.c, a.e, a.ninf);
+                acc_merge(Bm, b.s, b.c, b.e, b.ninf);
+                wmax = fmax(wmax, P.lrng[((size_t)g * P.lcap + u0 + j) * 64 + __lane_id()]);
+            }
         }
         RowAct R;
         lv_finish_act(P, v, live, A, Bm, r0, r1, R);
@@ -546,7 +635,12 @@ __global__ void __launch_bounds__(WG) k_lv_heavy(LvParams P) {
         }
         const bool want = live && !bad && !kb && !flagged && !row_quiet(R);
         const int64_t q0 = r0 + (int64_t)c * LV_CHUNK, q1 = min(r1, q0 + (int64_t)LV_CHUNK);
-        lv_candidates(P, g, v, want, R, q0, q1, wb);
+        const uint64_t wantmask = __ballot(want);
+        if (__popcll(wantmask) <= LV_FEW) {
+            if (wantmask) lv_candidates_few(P, g, wantmask, R, q0, q1);
+        } else {
+            lv_candidates(P, g, v, want, R, q0, q1, wb);
+        }
     }
     wbuf_flush(wb, &C->nchg[g], P.chg + (size_t)g * P.n);
     if (bad_cnt) {
