@@ -396,7 +396,7 @@ def bench_tiny(args, bp, gen, torch, np):
     same on one thread."""
     dev = torch.device("cuda:0")
     seeds = list(range(10))
-    gpu_ms, rounds, nnz, probes = [], [], 0, 0
+    gpu_ms, rounds, nnz, probes, tuned = [], [], 0, 0, []
     insts = [gen.make("tiny", s) for s in seeds]
     for inst in insts:
         I = bp.Instance(inst)
@@ -404,6 +404,10 @@ def bench_tiny(args, bp, gen, torch, np):
         ub0 = torch.tensor(inst["ub"], dtype=torch.float64, device=dev)
         binv = np.nonzero((inst["vtype"] == 1) & (inst["lb"] == 0) & (inst["ub"] == 1))[0].astype(np.int32)
         bins = torch.tensor(binv, dtype=torch.int32, device=dev)
+        # the schedule (rounds per graph, probe slots) tuned on this
+        # instance's own propagation and probe, before timing
+        t = I.autotune(*fresh(lb0, ub0), bins)
+        tuned.append({k: t[k] for k in ("rounds_per_launch", "probe_slots")})
 
         def call():
             lb, ub = fresh(lb0, ub0)
@@ -426,7 +430,7 @@ def bench_tiny(args, bp, gen, torch, np):
                        "fixed point, then double probing of all 150 binaries",
            "ms_per_instance_median": float(np.median(gpu_ms)),
            "ms_per_instance": [round(x, 4) for x in gpu_ms],
-           "rounds": rounds, "probes_per_instance": probes // len(seeds),
+           "rounds": rounds, "probes_per_instance": probes // len(seeds), "schedules": tuned,
            "nnz_per_s": nnz / (sum(gpu_ms) * 1e-3)}
     if not args.no_cpu_baseline:
         import oracle
