@@ -50,9 +50,11 @@ namespace bp {
 #endif
 constexpr int LV_SHORT = 64;             // rows up to this length: one task
 // Chunks queued for at most this many vectors of a group split their
-// nonzeros over the wave, one vector at a time (lv_chunk_few).
+// nonzeros over the wave, one vector at a time (lv_chunk_few; also the
+// merge and candidates of k_lv_heavy).  1, 2, 4, 8, 16, 32 and 48 were
+// timed on the multi-round bulk workload: 4 was the fastest.
 #ifndef BP_LV_FEW
-#define BP_LV_FEW 16
+#define BP_LV_FEW 4
 #endif
 constexpr int LV_FEW = BP_LV_FEW;
 constexpr int LV_CHUNK = BP_LV_CHUNK;    // nonzeros per chunk of longer rows
