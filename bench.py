@@ -36,18 +36,18 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E datasheet peak
 # WRITE_SIZE x1.0).  The figures belong to the library sources they were
 # measured on (SOURCES_SHA256, see sources_sha256()): when any source
 # differs, the bench line reports null.
-SOURCES_SHA256 = "60fb6055b33a1af04b233b0544b6e85a453573d83abb18a6ee4472bfe5e0da66"
+SOURCES_SHA256 = "406d978d78158aa5db5706e5f0b224891c819aca6449bb47bccf8681beaceaa4"
 TRAFFIC = {
     # single-instance workload, `bench.py --profile-steps 5`: 5 cold calls of
     # 79 working launches each (KiB per working launch)
-    "plain k_rows": {"fetch_kib": 1865.38, "write_kib": 194.15, "fetch_scale": 2.0, "write_scale": 1.0},
-    "plain k_apply": {"fetch_kib": 398.66, "write_kib": 177.38, "fetch_scale": 2.0, "write_scale": 1.0},
+    "plain k_rows": {"fetch_kib": 1869.88, "write_kib": 194.14, "fetch_scale": 2.0, "write_scale": 1.0},
+    "plain k_apply": {"fetch_kib": 403.00, "write_kib": 179.28, "fetch_scale": 2.0, "write_scale": 1.0},
     # probe workload, `bench.py --only-probe --profile-probe 3`: 4 batched
     # calls of 8192 probes, 32 launches each
-    "probe k_rows": {"fetch_kib": 867684.5, "write_kib": 66982.7, "fetch_scale": 2.0, "write_scale": 1.0},
+    "probe k_rows": {"fetch_kib": 865559.37, "write_kib": 66774.49, "fetch_scale": 2.0, "write_scale": 1.0},
     # bulk workload, `bench.py --only-bulk --profile-bulk 2 --bulk-schedule
     # 4096,16`: 3 calls of 256 vectors, one working launch each
-    "bulk k_lv_rows": {"fetch_kib": 21043928.6, "write_kib": 682912.6, "fetch_scale": 2.0, "write_scale": 1.0},
+    "bulk k_lv_rows": {"fetch_kib": 21052563.90, "write_kib": 463350.90, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 
