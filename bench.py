@@ -629,7 +629,9 @@ def probe_roofline(bp, inst, lb, ub, vars_d, cap, t_call, torch):
     """Roofline of the activity kernel k_rows in the batched double probing.
     Bytes (the algorithmic count for a batch): the matrix term once per row
     and round over the union of the slots' worklists -- 12 B per nonzero and
-    24 B per row -- plus, per vector, 16 B per distinct bound record read;
+    24 B per row -- plus, per vector, 16 B per distinct bound record read
+    and 1088 B of accumulator limbs per heavy row tested from them (a heavy
+    row's nonzeros count in the union only when its candidates are read);
     counted by an instrumented run of the same call (the base of the
     instrumented instance is the same root), divided by its launches.  Time:
     HIP events around every k_rows launch (rounds driven from the host),
@@ -650,7 +652,8 @@ def probe_roofline(bp, inst, lb, ub, vars_d, cap, t_call, torch):
     run(bp.FLAG_TIME_KERNELS)  # warm
     ts = run(bp.FLAG_TIME_KERNELS)
     launches = max(ts["launches"], 1)
-    rows_bytes = 12 * cs["nnz_union"] + 24 * cs["rows_union"] + 16 * cs["vars_read"]
+    rows_bytes = (12 * cs["nnz_union"] + 24 * cs["rows_union"] + 16 * cs["vars_read"]
+                  + 1088 * cs["rows_kept"])
     per_launch = rows_bytes / launches
     avg_ms = ts["ms"] / launches
     achieved = per_launch / (avg_ms * 1e-3) / 1e9
@@ -661,6 +664,7 @@ def probe_roofline(bp, inst, lb, ub, vars_d, cap, t_call, torch):
             "alg_bytes_per_launch": int(per_launch),
             "union_rows": cs["rows_union"], "union_nnz": cs["nnz_union"],
             "task_rows": cs["rows"], "task_nnz": cs["nnz"], "vars_read": cs["vars_read"],
+            "heavy_rows_kept": cs["rows_kept"],
             "call_alg_bytes": int(call_bytes), "call_alg_GBps": round(call_bytes / t_call / 1e9, 2),
             "call_frac": round(call_bytes / t_call / 1e9 / HBM_PEAK_GBPS, 5),
             "k_rows_share_of_call": round(ts["ms"] * 1e-3 / t_call, 3)}

@@ -127,16 +127,14 @@ struct Engine {
     int32_t cap_slots = 0;
     int32_t track_dirty = 0;
     int32_t nstripe = 1;  // changed-list stripes (NSTRIPE for one slot)
-    // scan rounds and incremental heavy rows of one plain vector (engines
-    // of one slot)
+    // scan rounds (engines of one slot) and incremental heavy rows (the
+    // first inc_cap slots: INC_SLOTS, or every slot of a probe engine)
     DevBuf cbits, hhit, allhrec, hacc, hinf, hwid, hact, hcrec[2];
+    int32_t inc_cap = 0;
     Shape shape;
     int64_t bytes = 0;
     DevBuf bnd, cand, vflag, rflag, info, chg, dirty, dlist, dcount, ctl, touched, useen, filt;
     DevBuf q[2][NBIN], hrec[2], hpart, hrng;
-    // grouped heavy rows of job slots (allocated on request)
-    int32_t grouped = 0;
-    DevBuf ghmask[2], ghrec[2], ghpart, ghlive, dmaskg;
     // Captured graphs of K rounds, keyed by their kernel arguments (held by
     // value): calls that alternate between argument sets (a propagation
     // and a probe on one instance) each keep theirs; the least recently
@@ -177,9 +175,10 @@ struct bp_instance {
     DevBuf st_status, st_rounds, st_nnz, st_jobs;  // per-job results and descriptors
     int64_t st_cap = 0;
     DevBuf box_d, ptr_d, idflag_d;  // per-call box check, changed offsets, id check
-    // base expansions of the heavy rows (grouped heavy rows of probe slots)
-    DevBuf ghidx_d, ghbase_d;
-    int64_t gh_version = -1;  // base_version they were computed for
+    // the heavy rows at the base bounds (incremental heavy rows of probe
+    // slots): limbs [H][2][HL], infinite counts [H][2], widths [H]
+    DevBuf hb_limb, hb_inf, hb_wid;
+    int64_t hb_version = -1;  // base_version they were computed for
     // row bins (host)
     int64_t bin_count[NBIN] = {0};
     int64_t bin_start[NBIN + 1] = {0};
@@ -435,7 +434,7 @@ static int sc_tables(bp_instance *h, const std::vector<int32_t> &cold, hipStream
 static int bin_rows(bp_instance *h, hipStream_t st) {
     const int64_t m = h->m;
     h->tables_ok = false;
-    h->gh_version = -1;  // the heavy rows change with the threshold
+    h->hb_version = -1;  // the heavy rows change with the threshold
     for (int b = 0; b < NBIN; ++b) h->bin_count[b] = 0;
     std::vector<uint8_t> rbin(m);
     for (int64_t k = 0; k < m; ++k) {
@@ -636,11 +635,12 @@ static Shape shape_of(const bp_instance *h) {
 
 // (Re)allocate `E` for `slots` bound vectors of shape `sh`; dirty: with the
 // overlay bookkeeping of jobs; count: with the distinct-record bitmap;
-// grouped: with the grouped heavy-row tasks of job slots.
+// inc_all: incremental heavy-row accumulators for every slot (probe slots),
+// not only the first INC_SLOTS.
 static int engine_alloc(std::unique_ptr<Engine> &eng, const Shape &sh, int32_t slots, bool dirty,
-                        bool count, hipStream_t st, bool grouped = false) {
+                        bool count, hipStream_t st, bool inc_all = false) {
     if (eng && eng->cap_slots >= slots && eng->shape.covers(sh) && (!dirty || eng->track_dirty) &&
-        (!count || eng->touched.p) && (!grouped || eng->grouped))
+        (!count || eng->touched.p) && (!inc_all || eng->inc_cap >= slots))
         return 0;
     eng.reset();
     std::unique_ptr<Engine> E(new Engine());
@@ -664,9 +664,11 @@ static int engine_alloc(std::unique_ptr<Engine> &eng, const Shape &sh, int32_t s
     }
     if ((rc = E->allhrec.alloc((size_t)std::max<int64_t>(sh.heavy_chunks, 1) * sizeof(int4), B))) return rc;
     if (sh.heavy_rows > 0) {
-        // incremental heavy rows of the first INC_SLOTS slots
-        const int64_t H = sh.heavy_rows * std::min<int64_t>(S, INC_SLOTS);
-        const int64_t HC = std::max<int64_t>(sh.heavy_chunks, 1) * std::min<int64_t>(S, INC_SLOTS);
+        // incremental heavy rows of the first INC_SLOTS slots, or of all
+        const int64_t IS = inc_all ? S : std::min<int64_t>(S, INC_SLOTS);
+        const int64_t H = sh.heavy_rows * IS;
+        const int64_t HC = std::max<int64_t>(sh.heavy_chunks, 1) * IS;
+        E->inc_cap = (int32_t)IS;
         if ((rc = E->hacc.alloc((size_t)H * 2 * HL * 8, B)) || (rc = E->hinf.alloc((size_t)H * 8, B)) ||
             (rc = E->hwid.alloc((size_t)H * 8, B)) || (rc = E->hact.alloc((size_t)H * 16, B)) ||
             (rc = E->hcrec[0].alloc((size_t)HC * sizeof(int4), B)) ||
@@ -696,23 +698,6 @@ static int engine_alloc(std::unique_ptr<Engine> &eng, const Shape &sh, int32_t s
         HIPTRY(hipMemsetAsync(E->dirty.p, 0, E->dirty.bytes, st));
         HIPTRY(hipMemsetAsync(E->dcount.p, 0, E->dcount.bytes, st));
     }
-    if (grouped) {
-        // groups of 64 slots; per parity every chunk of every heavy row of
-        // every group may be queued
-        const int64_t NG = (S + 63) / 64;
-        const int64_t H = std::max<int64_t>(sh.heavy_rows, 1);
-        const int64_t cap = std::max<int64_t>(NG * sh.heavy_chunks, 1);
-        for (int par = 0; par < 2; ++par) {
-            if ((rc = E->ghmask[par].alloc((size_t)NG * H * 8, B))) return rc;
-            if ((rc = E->ghrec[par].alloc((size_t)cap * sizeof(int4), B))) return rc;
-            HIPTRY(hipMemsetAsync(E->ghmask[par].p, 0, E->ghmask[par].bytes, st));
-        }
-        if ((rc = E->ghpart.alloc((size_t)cap * 128 * sizeof(Acc), B))) return rc;
-        if ((rc = E->ghlive.alloc((size_t)cap * 8, B))) return rc;
-        if ((rc = E->dmaskg.alloc((size_t)NG * n * 8, B))) return rc;
-        HIPTRY(hipMemsetAsync(E->dmaskg.p, 0, E->dmaskg.bytes, st));
-        E->grouped = 1;
-    }
     HIPTRY(hipMemsetAsync(E->vflag.p, 0, E->vflag.bytes, st));
     HIPTRY(hipMemsetAsync(E->rflag.p, 0, E->rflag.bytes, st));
     HIPTRY(hipMemsetAsync(E->info.p, 0, E->info.bytes, st));
@@ -723,9 +708,9 @@ static int engine_alloc(std::unique_ptr<Engine> &eng, const Shape &sh, int32_t s
 }
 
 static int engine_ensure(bp_instance *h, int32_t slots, bool dirty, hipStream_t st,
-                         bool grouped = false) {
+                         bool inc_all = false) {
     return engine_alloc(h->eng, shape_of(h), slots, dirty, (h->opt.flags & BP_FLAG_COUNT_VARS) != 0,
-                        st, grouped);
+                        st, inc_all);
 }
 
 static DInst dinst_of(const bp_instance *h) {
@@ -780,7 +765,6 @@ static Params engine_params(const Engine &E, const bp_options &opt, int32_t heav
     P.dirty = E.dirty.as<uint32_t>();
     P.dlist = E.dlist.as<int32_t>();
     P.dcount = E.dcount.as<int32_t>();
-    P.gh = 0;  // enabled by bp_probe
     return P;
 }
 
@@ -1220,117 +1204,56 @@ extern "C" int bp_kernel_stats(bp_instance *h, bp_stats *out, int reset) {
     return BP_OK;
 }
 
-// One thread's share of the exact sum of one side of row [p0, p1) at the
-// base bounds: the nonzeros p0 + t, p0 + t + WG, ...
-__device__ __noinline__ void exact_share(const DInst &I, int64_t p0, int64_t p1, bool maxside,
-                                         SuperAcc &S) {
-    sa_zero(S);
-    for (int64_t p = p0 + threadIdx.x; p < p1; p += WG) {
-        const double a = I.val[p];
-        const double2 b = I.base[I.col[p]];
-        const double bb = (a > 0.0) != maxside ? b.x : b.y;
-        if (!isinf(bb)) sa_add(S, a * bb);
-    }
-}
-
-// The accumulator's value as a non-overlapping expansion of up to GH_COMPS
-// doubles (largest first); false if it needs more.
-__device__ __noinline__ bool sa_expansion(SuperAcc &S, double *out) {
-    for (int q = 0; q < GH_COMPS; ++q) out[q] = 0.0;
-    for (int q = 0; q < GH_COMPS; ++q) {
-        SuperAcc T = S;  // sa_round works in place (it negates a negative state)
-        const double x = sa_round(T);
-        if (x == 0.0) return true;
-        out[q] = x;
-        sa_add(S, -x);  // exact: the remainder stays on the fixed-point grid
-    }
-    return sa_is_zero(S);
-}
-
-// Base expansions, infinite counts and widths of the heavy rows (one
-// workgroup per row); ghidx[k] = the row's index, or -1 if its expansion
-// does not fit (the row then stays on per-slot chunks).  Each thread sums
-// its share of the row exactly; the shares are added word by word in 32-bit
-// halves (the sum of the two's-complement words modulo 2^2176 is the
-// two's-complement sum) and one carry pass gives the row's accumulator.
-__global__ void __launch_bounds__(WG) k_gh_base(DInst I, const int32_t *hrows, int32_t H, GhBase *out,
-                                                int32_t *ghidx) {
-    __shared__ uint64_t words[SA_WORDS][WG];
-    __shared__ uint64_t lo_sum[SA_WORDS], hi_sum[SA_WORDS];
-    __shared__ double sw[WG / 64];
-    __shared__ int snmin[WG / 64], snmax[WG / 64];
-    __shared__ SuperAcc tot;
-    __shared__ int ok_s;
-    for (int hi = blockIdx.x; hi < H; hi += gridDim.x) {
-        const int k = hrows[hi];
-        const int64_t p0 = I.row_ptr[k], p1 = I.row_ptr[k + 1];
-        double w = 0.0;
-        int nmin = 0, nmax = 0;
-        for (int64_t p = p0 + threadIdx.x; p < p1; p += WG) {
-            const double a = I.val[p];
-            const double2 b = I.base[I.col[p]];
-            w = fmax(w, nz_width(a, b.x, b.y));
-            nmin += isinf(a > 0.0 ? b.x : b.y) ? 1 : 0;
-            nmax += isinf(a > 0.0 ? b.y : b.x) ? 1 : 0;
-        }
-        w = group_max<64>(w);
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            nmin += __shfl_xor(nmin, o, 64);
-            nmax += __shfl_xor(nmax, o, 64);
-        }
-        if (__lane_id() == 0) {
-            sw[threadIdx.x >> 6] = w;
-            snmin[threadIdx.x >> 6] = nmin;
-            snmax[threadIdx.x >> 6] = nmax;
-        }
-        if (threadIdx.x == 0) ok_s = 1;
-        __syncthreads();
-        GhBase &G = out[hi];
+// The heavy rows at the base bounds (one workgroup per row): each side's
+// exact finite sum as carry-save limbs (every term's pieces added in LDS,
+// the order-independent integer form of the incremental heavy rows), the
+// counts of infinite contributions and the largest nonzero width.
+__global__ void __launch_bounds__(WG) k_base_limbs(DInst I, const int32_t *hrows, int32_t H,
+                                                   long long *limbs, int32_t *ninf_out, double *wid_out) {
+    __shared__ long long L[2 * HL];
+    __shared__ int32_t ninf[2];
+    __shared__ unsigned long long wbits;
+    for (int h = blockIdx.x; h < H; h += gridDim.x) {
+        for (int j = threadIdx.x; j < 2 * HL; j += WG) L[j] = 0;
         if (threadIdx.x == 0) {
-            double ww = sw[0];
-            int a0 = snmin[0], a1 = snmax[0];
-            for (int q = 1; q < WG / 64; ++q) {
-                ww = fmax(ww, sw[q]);
-                a0 += snmin[q];
-                a1 += snmax[q];
-            }
-            G.rng = ww;
-            G.nmin = a0;
-            G.nmax = a1;
+            ninf[0] = 0;
+            ninf[1] = 0;
+            wbits = 0ull;
         }
-        for (int side = 0; side < 2; ++side) {
-            SuperAcc S;
-            exact_share(I, p0, p1, side == 1, S);
-            for (int q = 0; q < SA_WORDS; ++q) words[q][threadIdx.x] = S.w[q];
-            __syncthreads();
-            if (threadIdx.x < SA_WORDS) {
-                uint64_t l = 0, h = 0;  // at most 256 * 2^32 each: no overflow
-                for (int t = 0; t < WG; ++t) {
-                    const uint64_t x = words[threadIdx.x][t];
-                    l += x & 0xffffffffull;
-                    h += x >> 32;
-                }
-                lo_sum[threadIdx.x] = l;
-                hi_sum[threadIdx.x] = h;
+        __syncthreads();
+        const int k = hrows[h];
+        const int64_t p0 = I.row_ptr[k], p1 = I.row_ptr[k + 1];
+        int nmin = 0, nmax = 0;
+        double wmax = 0.0;
+        const int iters = (int)((p1 - p0 + WG - 1) / WG);  // uniform: whole waves add together
+        for (int it = 0; it < iters; ++it) {
+            const int64_t p = p0 + threadIdx.x + (int64_t)it * WG;
+            const bool in = p < p1;
+            double tmin = 0.0, tmax = 0.0;
+            if (in) {
+                const double a = I.val[p];
+                const double2 b = I.base[I.col[p]];
+                const double bmin = a > 0.0 ? b.x : b.y;
+                const double bmax = a > 0.0 ? b.y : b.x;
+                if (isinf(bmin)) nmin += 1;
+                else tmin = a * bmin;
+                if (isinf(bmax)) nmax += 1;
+                else tmax = a * bmax;
+                wmax = fmax(wmax, nz_width(a, b.x, b.y));
             }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                // word q of the total = lo + (hi << 32) + carry, modulo 2^64
-                unsigned __int128 carry = 0;
-                for (int q = 0; q < SA_WORDS; ++q) {
-                    const unsigned __int128 v =
-                        (unsigned __int128)lo_sum[q] + ((unsigned __int128)hi_sum[q] << 32) + carry;
-                    tot.w[q] = (uint64_t)v;
-                    carry = v >> 64;
-                }
-                SuperAcc T = tot;
-                const bool ok = sa_expansion(T, side == 0 ? G.emin : G.emax);
-                if (!ok) ok_s = 0;
-            }
-            __syncthreads();
+            inc_add_wave(L, tmin, in);
+            inc_add_wave(L + HL, tmax, in);
         }
-        if (threadIdx.x == 0) ghidx[k] = ok_s ? hi : -1;
+        if (nmin) atomicAdd(&ninf[0], nmin);
+        if (nmax) atomicAdd(&ninf[1], nmax);
+        if (wmax > 0.0) atomicMax(&wbits, (unsigned long long)__double_as_longlong(wmax));
+        __syncthreads();
+        for (int j = threadIdx.x; j < 2 * HL; j += WG) limbs[(size_t)h * 2 * HL + j] = L[j];
+        if (threadIdx.x == 0) {
+            ninf_out[2 * h] = ninf[0];
+            ninf_out[2 * h + 1] = ninf[1];
+            wid_out[h] = __longlong_as_double((long long)wbits);
+        }
         __syncthreads();
     }
 }
@@ -1406,18 +1329,28 @@ extern "C" int bp_probe(bp_instance *h, const int32_t *vars, int32_t k, bp_probe
     }
     const int32_t S = (int32_t)std::min<int64_t>(std::max(1, h->opt.probe_slots), jobs);
     const int64_t H = h->bin_count[BIN_HEAVY];
-    if (int rc = engine_ensure(h, S, true, st, H > 0)) return rc;
+    // Incremental heavy rows over the base.  Limb bound: the base limbs
+    // hold at most L pieces below 2^32 (a row of L nonzeros), admission and
+    // each round of a job at most 2L more (old term out, new term in, once
+    // per variable and side), so after a job's r <= max_rounds rounds
+    // |limb| < L 2^32 (3 + 2r), below carry_round's 2^62 while
+    // L (3 + 2 max_rounds) < 2^30.  Otherwise, or with FULL_ROWS, each
+    // slot's heavy rows are summed chunk by chunk.
+    const int64_t Lmax = std::max<int64_t>(h->max_row_len, 1);
+    const bool inc = H > 0 && !(h->opt.flags & BP_FLAG_FULL_ROWS) &&
+                     Lmax * (3 + 2 * (int64_t)h->opt.max_rounds) < (int64_t(1) << 30);
+    if (int rc = engine_ensure(h, S, true, st, inc)) return rc;
     Engine &E = *h->eng;
-    // Base expansions of the heavy rows, once per base.
-    if (H > 0 && h->gh_version != h->base_version) {
-        if (int rc = h->ghidx_d.grow((size_t)std::max<int64_t>(h->m, 1) * 4, h->bytes)) return rc;
-        if (int rc = h->ghbase_d.grow((size_t)H * sizeof(GhBase), h->bytes)) return rc;
-        k_fill_i32<<<grid_for(h->m), 256, 0, st>>>(h->ghidx_d.as<int32_t>(), -1, h->m);
-        k_gh_base<<<(int)std::min<int64_t>(H, 4096), WG, 0, st>>>(
+    // The heavy rows at the base bounds, once per base.
+    if (inc && h->hb_version != h->base_version) {
+        if (int rc = h->hb_limb.grow((size_t)H * 2 * HL * 8, h->bytes)) return rc;
+        if (int rc = h->hb_inf.grow((size_t)H * 8, h->bytes)) return rc;
+        if (int rc = h->hb_wid.grow((size_t)H * 8, h->bytes)) return rc;
+        k_base_limbs<<<(int)std::min<int64_t>(H, 4096), WG, 0, st>>>(
             dinst_of(h), h->cold_rows.as<int32_t>() + h->bin_start[BIN_HEAVY], (int32_t)H,
-            h->ghbase_d.as<GhBase>(), h->ghidx_d.as<int32_t>());
+            h->hb_limb.as<long long>(), h->hb_inf.as<int32_t>(), h->hb_wid.as<double>());
         HIPTRY(hipGetLastError());
-        h->gh_version = h->base_version;
+        h->hb_version = h->base_version;
     }
     // Probe slots read the base except where their dirty bits are set; a
     // retired probe clears its bits, so no slot needs initialising.
@@ -1448,18 +1381,27 @@ extern "C" int bp_probe(bp_instance *h, const int32_t *vars, int32_t k, bp_probe
     IO.stage_cap = cap;
     Params P = make_params(h, S);
     P.overlay = 1;
-    if (H > 0) {
-        P.gh = 1;
-        P.gH = (int32_t)H;
-        P.ghidx = h->ghidx_d.as<int32_t>();
-        P.ghbase = h->ghbase_d.as<GhBase>();
-        for (int par = 0; par < 2; ++par) {
-            P.ghmask[par] = E.ghmask[par].as<uint64_t>();
-            P.ghrec[par] = E.ghrec[par].as<int4>();
-        }
-        P.ghpart = E.ghpart.as<Acc>();
-        P.ghlive = E.ghlive.as<uint64_t>();
-        P.dmaskg = E.dmaskg.as<uint64_t>();
+    if (inc) {
+        // every slot's corrections start at zero (a retired job clears its
+        // own; this also drops what an interrupted call left)
+        P.inc = 1;
+        P.nheavy = (int32_t)H;
+        P.inc_slots = S;
+        P.hacc = E.hacc.as<long long>();
+        P.hinf = E.hinf.as<int32_t>();
+        P.hwid = E.hwid.as<unsigned long long>();
+        P.hidx = h->hidx_d.as<int32_t>();
+        P.cval = h->col_val.as<double>();
+        P.hact = E.hact.as<double2>();
+        P.hcrec[0] = E.hcrec[0].as<int4>();
+        P.hcrec[1] = E.hcrec[1].as<int4>();
+        P.inc_max = 0xffffffffu;  // never rebuilt
+        P.inc_period = 0;
+        P.hblimb = h->hb_limb.as<long long>();
+        P.hbinf = h->hb_inf.as<int32_t>();
+        P.hbwid = h->hb_wid.as<double>();
+        HIPTRY(hipMemsetAsync(E.hacc.p, 0, (size_t)S * H * 2 * HL * 8, st));
+        HIPTRY(hipMemsetAsync(E.hinf.p, 0, (size_t)S * H * 8, st));
     }
     Ctl c;
     memset(&c, 0, sizeof(c));

@@ -90,7 +90,6 @@ struct Ctl {
     uint32_t done;
     uint32_t qcount[2][NBIN];   // queue lengths per parity
     uint32_t hchunks[2];        // heavy chunks per parity
-    uint32_t ghchunks[2];       // grouped heavy chunk tasks per parity
     uint32_t nchanged[NSTRIPE]; // (slot, var) entries of the current round, per stripe
     uint32_t active;            // slots active or draining after the last round end
     uint32_t finished;          // slots finished at the last round end
@@ -131,7 +130,7 @@ struct Ctl {
 struct CtlHead {
     uint32_t round, done;
     uint32_t qcount[NBIN];
-    uint32_t hchunks, ghchunks;
+    uint32_t hchunks;
     uint32_t scan;
     uint32_t hbuild;
     uint32_t hcand;
@@ -154,9 +153,7 @@ __device__ __forceinline__ CtlHead ctl_head(const Ctl *C) {
         H.qcount[b] = odd ? q1 : q0;
     }
     const uint32_t h0 = C->hchunks[0], h1 = C->hchunks[1];
-    const uint32_t g0 = C->ghchunks[0], g1 = C->ghchunks[1];
     H.hchunks = odd ? h1 : h0;
-    H.ghchunks = odd ? g1 : g0;
     const uint32_t sc0 = C->scan[0], sc1 = C->scan[1];
     H.scan = odd ? sc1 : sc0;
     const uint32_t hb0 = C->hbuild[0], hb1 = C->hbuild[1];
@@ -200,19 +197,6 @@ struct Params {
     uint32_t *dirty;             // [nslots][snw]
     int32_t *dlist;              // [nslots][sn]
     int32_t *dcount;             // [nslots]
-    // grouped heavy rows (jobs of one instance): a heavy row queued by any
-    // slot of a group of 64 is one task per chunk for the whole group; a
-    // slot's activity is the base row's exact sum plus the corrections of
-    // its dirty variables
-    int32_t gh;                  // enabled
-    int32_t gH;                  // heavy rows with a base expansion
-    const int32_t *ghidx;        // [m] index of the row's base expansion, -1 if none
-    const struct GhBase *ghbase; // [gH]
-    uint64_t *ghmask[2];         // [groups][gH] slots that queued the row
-    int4 *ghrec[2];              // (group, row, chunk, chunks of the row)
-    Acc *ghpart;                 // [task][2][64] per-slot corrections of a chunk
-    uint64_t *ghlive;            // [task] the row's slot mask, as read by the chunk
-    uint64_t *dmaskg;            // [groups][sn] slots of the group with var i dirty
     // Scan rounds (one plain vector): when a bound update changes many
     // variables, the next round does not queue rows through the columns;
     // instead the row kernel walks every row and processes those holding a
@@ -246,16 +230,17 @@ struct Params {
     uint32_t inc_max;            // changed entries from which the next round rebuilds
     uint32_t inc_period;         // a rebuild at least every inc_period rounds, so that no
                                  // carry-save limb can reach 2^62 (see propagate_slots)
-};
-
-// Exact activities of a heavy row at the base bounds: each finite part as a
-// non-overlapping expansion (sum of the components = the exact sum), the
-// counts of infinite contributions, and the row's slack-filter width.
-constexpr int GH_COMPS = 8;
-struct GhBase {
-    double emin[GH_COMPS], emax[GH_COMPS];
-    int32_t nmin, nmax;
-    double rng;
+    // Incremental heavy rows of job slots (one instance, overlays on the
+    // base): a slot's limbs and infinite counts hold only the corrections of
+    // its own bound changes, so a heavy row's activity is the base row's
+    // exact sum plus them.  Admission corrects for the job's first bounds,
+    // the update kernel for every later change, and a retired slot clears
+    // the rows of its changed variables.  Never rebuilt.
+    const long long *hblimb;     // [nheavy][2][HL] limbs of the base rows (null: limbs hold
+                                 // whole sums)
+    const int32_t *hbinf;        // [nheavy][2] infinite contributions at the base bounds
+    const double *hbwid;         // [nheavy] slack-filter widths at the base bounds (a job's
+                                 // bounds lie inside the base, so these bound its widths)
 };
 
 // Instance of slot s (MULTI: slots mix instances; otherwise the kernel
@@ -1002,16 +987,18 @@ __device__ void inc_build_chunk(const Params &P, int par, uint32_t u, bool scan)
     }
 }
 
-// The rounded finite parts of heavy row h from its accumulators, by the
-// whole workgroup: limbs staged in LDS, one lane per side rounds them.
-__device__ double2 inc_row_activity(const Params &P, size_t hs) {
+// The rounded finite parts of heavy row h (accumulators hs) by the whole
+// workgroup: limbs staged in LDS (the base row's limbs added for job slots),
+// one lane per side rounds them.
+__device__ double2 inc_row_activity(const Params &P, size_t hs, int h) {
     __shared__ long long L[2 * HL];
     __shared__ double act[2];
     __shared__ int range[4];  // lowest and highest nonzero limb of each side
     if (threadIdx.x < 4) range[threadIdx.x] = (threadIdx.x & 1) ? -1 : HL;
     __syncthreads();
     for (int j = threadIdx.x; j < 2 * HL; j += WG) {
-        const long long v = P.hacc[hs * 2 * HL + j];
+        long long v = P.hacc[hs * 2 * HL + j];
+        if (P.hblimb) v += P.hblimb[(size_t)h * 2 * HL + j];
         L[j] = v;
         if (v) {
             const int side = j >= HL ? 2 : 0, d = j >= HL ? j - HL : j;
@@ -1028,6 +1015,21 @@ __device__ double2 inc_row_activity(const Params &P, size_t hs) {
     return r;
 }
 
+// Infinite counts and slack-filter width of heavy row h (accumulators hs):
+// for job slots the base row's counts plus the slot's corrections, and the
+// base width.
+__device__ __forceinline__ void inc_counts(const Params &P, size_t hs, int h, RowAct &R) {
+    R.nmin = P.hinf[2 * hs];
+    R.nmax = P.hinf[2 * hs + 1];
+    if (P.hblimb) {
+        R.nmin += P.hbinf[2 * h];
+        R.nmax += P.hbinf[2 * h + 1];
+        R.rng = P.hbwid[h];
+    } else {
+        R.rng = __longlong_as_double((long long)P.hwid[hs]);
+    }
+}
+
 // Heavy row head (round without a rebuild): chunk 0 of each queued heavy
 // row rounds the row's accumulators once for all its chunks.
 // It also tests the row: an infeasible row is reported, a quiet one ends
@@ -1039,17 +1041,16 @@ __device__ void inc_head(const Params &P, int par, uint32_t u) {
     if (c != 0) return;  // workgroup-uniform
     if (threadIdx.x == 0) clear_rflag(P, s, k);
     if (P.info[s].state != SLOT_ACTIVE) return;  // workgroup-uniform
-    const size_t hs = (size_t)s * P.nheavy + P.hidx[k];
-    const double2 a = inc_row_activity(P, hs);
+    const int h = P.hidx[k];
+    const size_t hs = (size_t)s * P.nheavy + h;
+    const double2 a = inc_row_activity(P, hs, h);
     if (threadIdx.x == 0) {
         P.hact[hs] = a;
         const double2 sd = P.I.side[k];
         RowAct R;
         R.minfin = a.x;
         R.maxfin = a.y;
-        R.nmin = P.hinf[2 * hs];
-        R.nmax = P.hinf[2 * hs + 1];
-        R.rng = __longlong_as_double((long long)P.hwid[hs]);
+        inc_counts(P, hs, h, R);
         R.lo = sd.x;
         R.hi = sd.y;
         const bool bad = row_bad(R, P.feastol), quiet = !bad && row_quiet(R);
@@ -1105,11 +1106,10 @@ __device__ void heavy_chunk_candidates(const Params &P, int par, uint32_t u, boo
         // head in the row kernel, or here in a rebuild round (the row
         // kernel built them); the stored width bounds the current one
         // (bounds only shrink)
-        const size_t hs = (size_t)s * P.nheavy + P.hidx[k];
-        R.nmin = P.hinf[2 * hs];
-        R.nmax = P.hinf[2 * hs + 1];
-        R.rng = __longlong_as_double((long long)P.hwid[hs]);
-        const double2 a = rebuild ? inc_row_activity(P, hs) : P.hact[hs];
+        const int h = P.hidx[k];
+        const size_t hs = (size_t)s * P.nheavy + h;
+        inc_counts(P, hs, h, R);
+        const double2 a = rebuild ? inc_row_activity(P, hs, h) : P.hact[hs];
         R.minfin = a.x;
         R.maxfin = a.y;
     } else {
@@ -1153,6 +1153,7 @@ __device__ void heavy_chunk_candidates(const Params &P, int par, uint32_t u, boo
         return;
     }
     if (quiet) return;
+    if (decided && c == 0 && threadIdx.x == 0) count_row(P, k, r1 - r0);  // read for its candidates
     const int iters = (int)((p1 - p0 + WG - 1) / WG);
     for (int it = 0; it < iters; ++it) {
         int64_t p = p0 + threadIdx.x + (int64_t)it * WG;
@@ -1163,149 +1164,6 @@ __device__ void heavy_chunk_candidates(const Params &P, int par, uint32_t u, boo
             double a = I.val[p];
             double2 b = bnd[i];
             bool is_int = I.vtype[i] != 0;
-            double cl, cu;
-            nz_candidates(R, a, b.x, b.y, is_int, P.inttol, cl, cu);
-            need = scatter(P, s, i, cl, cu, b.x, b.y, is_int);
-        }
-        mark_var(P, need, s, i);
-    }
-}
-
-// ------------------------------------------------------------------------
-// Grouped heavy rows (jobs of one instance): one wave per chunk task, lane
-// l standing for slot 64*g + l.
-// ------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t rl_u64(uint64_t x, int t) {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, t);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), t);
-    return ((uint64_t)hi << 32) | lo;
-}
-
-// Activity pass of a chunk: for every slot of the group with the row
-// queued, the exact corrections (its term minus the base term, and the
-// change of the infinite count) of the chunk's variables it has dirty.
-__device__ void gh_chunk_corrections(const Params &P, int par, uint32_t t) {
-    const int4 rec = P.ghrec[par][t];
-    const int g = rec.x, k = rec.y, c = rec.z;
-    const int lane = __lane_id();
-    const int s = g * 64 + lane;
-    const uint64_t word = P.ghmask[par][(size_t)g * P.gH + P.ghidx[k]];
-    const bool live = ((word >> lane) & 1ull) && s < P.nslots && P.info[s].state == SLOT_ACTIVE;
-    if (lane == 0) P.ghlive[t] = word;
-    const DInst &I = P.I;
-    const int64_t r0 = I.row_ptr[k], r1 = I.row_ptr[k + 1];
-    if (c == 0 && lane == 0 && word) count_row(P, k, r1 - r0);
-    const int64_t p0 = r0 + (int64_t)c * P.heavy_chunk, p1 = min(r1, p0 + (int64_t)P.heavy_chunk);
-    const double2 *own = P.bnd + (size_t)s * P.sn;
-    const uint64_t *dm = P.dmaskg + (size_t)g * P.sn;
-    Acc mn, mx;
-    acc_zero(mn);
-    acc_zero(mx);
-    for (int64_t b0 = p0; b0 < p1; b0 += 64) {
-        const int64_t j = b0 + lane;
-        int i = 0;
-        double a = 0.0;
-        uint64_t w = 0;
-        if (j < p1) {
-            i = I.col[j];
-            a = I.val[j];
-            w = dm[i];
-        }
-        uint64_t any = __ballot(w != 0);
-        while (any) {
-            const int q = __ffsll((long long)any) - 1;
-            any &= any - 1;
-            const uint64_t wq = rl_u64(w, q);
-            if (live && ((wq >> lane) & 1ull)) {
-                const int iq = __builtin_amdgcn_readlane(i, q);
-                const long long ab = __double_as_longlong(a);
-                const double aq = __longlong_as_double(
-                    ((long long)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(ab >> 32), q) << 32) |
-                    (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)ab, q));
-                const double2 bo = own[iq], bb = I.base[iq];
-                // min side: lb for a > 0, ub for a < 0; max side the other
-                const double on = aq > 0.0 ? bo.x : bo.y, bn = aq > 0.0 ? bb.x : bb.y;
-                const double ox = aq > 0.0 ? bo.y : bo.x, bx = aq > 0.0 ? bb.y : bb.x;
-                if (isinf(on)) mn.ninf += 1; else acc_add(mn, aq * on);
-                if (isinf(bn)) mn.ninf -= 1; else acc_add(mn, -(aq * bn));
-                if (isinf(ox)) mx.ninf += 1; else acc_add(mx, aq * ox);
-                if (isinf(bx)) mx.ninf -= 1; else acc_add(mx, -(aq * bx));
-            }
-        }
-    }
-    P.ghpart[(size_t)t * 128 + lane] = mn;
-    P.ghpart[(size_t)t * 128 + 64 + lane] = mx;
-}
-
-// Candidate pass of a chunk: each slot's row activity (base expansion plus
-// the corrections of every chunk, certified, exact fallback), row test,
-// slack filter, then the chunk's candidates for the slots that need them.
-template <bool MULTI>
-__device__ void gh_chunk_candidates(const Params &P, int par, uint32_t t) {
-    const int4 rec = P.ghrec[par][t];
-    const int g = rec.x, k = rec.y, c = rec.z, nch = rec.w;
-    const int lane = __lane_id();
-    const int s = g * 64 + lane;
-    const uint64_t word = P.ghlive[t];
-    const bool live = ((word >> lane) & 1ull) && s < P.nslots && P.info[s].state == SLOT_ACTIVE;
-    const DInst &I = P.I;
-    const int hi = P.ghidx[k];
-    if (c == 0 && lane == 0) P.ghmask[par][(size_t)g * P.gH + hi] = 0ull;
-    // every slot that queued the row (draining ones included) may queue it
-    // again from the next round on
-    if (c == 0 && ((word >> lane) & 1ull) && s < P.nslots) clear_rflag(P, s, k);
-    const GhBase &GB = P.ghbase[hi];
-    Acc A, B;
-    acc_zero(A);
-    acc_zero(B);
-#pragma unroll 1
-    for (int q = 0; q < GH_COMPS; ++q) {
-        if (GB.emin[q] != 0.0) acc_add(A, GB.emin[q]);
-        if (GB.emax[q] != 0.0) acc_add(B, GB.emax[q]);
-    }
-    A.ninf = GB.nmin;
-    B.ninf = GB.nmax;
-    const uint32_t u0 = t - (uint32_t)c;
-    for (int j = 0; j < nch; ++j) {
-        const Acc a = P.ghpart[(size_t)(u0 + j) * 128 + lane];
-        const Acc b = P.ghpart[(size_t)(u0 + j) * 128 + 64 + lane];
-        acc_merge(A, a.s, a.c, a.e, a.ninf);
-        acc_merge(B, b.s, b.c, b.e, b.ninf);
-    }
-    const int64_t r0 = I.row_ptr[k], r1 = I.row_ptr[k + 1];
-    const BView bnd = bview(P, s, I.base);
-    RowAct R;
-    R.nmin = A.ninf;
-    R.nmax = B.ninf;
-    R.minfin = 0.0;
-    R.maxfin = 0.0;
-    R.rng = GB.rng;  // the base width bounds every slot's (job bounds only shrink)
-    const double2 sd = I.side[k];
-    R.lo = sd.x;
-    R.hi = sd.y;
-    bool ok_min = live && !P.force_exact && acc_certify(A, R.minfin);
-    bool ok_max = live && !P.force_exact && acc_certify(B, R.maxfin);
-    if (live && !ok_min) R.minfin = exact_side(I, bnd, r0, r1, false);
-    if (live && !ok_max) R.maxfin = exact_side(I, bnd, r0, r1, true);
-    bool bad = false;
-    if (live) {
-        bad = row_bad(R, P.feastol);
-        if (bad && c == 0) report_bad_row(P, s, k);
-    }
-    const bool want = live && !bad && !row_quiet(R);
-    if (__ballot(want) == 0) return;
-    const int64_t p0 = r0 + (int64_t)c * P.heavy_chunk, p1 = min(r1, p0 + (int64_t)P.heavy_chunk);
-    const uint64_t *dm = P.dmaskg + (size_t)g * P.sn;
-    const double2 *own = P.bnd + (size_t)s * P.sn;
-    for (int64_t p = p0; p < p1; ++p) {
-        const int i = I.col[p];
-        const double a = I.val[p];
-        const uint64_t w = dm[i];
-        double2 b = I.base[i];
-        if ((w >> lane) & 1ull) b = own[i];
-        bool need = false;
-        if (want) {
-            const bool is_int = I.vtype[i] != 0;
             double cl, cu;
             nz_candidates(R, a, b.x, b.y, is_int, P.inttol, cl, cu);
             need = scatter(P, s, i, cl, cu, b.x, b.y, is_int);
@@ -1336,20 +1194,16 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(BP_ROWS
 #pragma unroll
     for (int b = 0; b < NBIN; ++b)
         qc[b] = scan ? (uint32_t)(P.allstart[b + 1] - P.allstart[b]) : H.qcount[b];
-    const uint32_t C_ghchunks = scan ? 0u : H.ghchunks;
     // Heavy chunks: partial states of the queued chunks, or, with
     // incremental accumulators, every chunk in a rebuild round and the
     // queued row heads (one record per row) otherwise.
     const uint32_t C_hchunks = P.inc ? (H.hbuild ? (uint32_t)P.allhchunks * (uint32_t)P.inc_slots : H.hchunks)
                                      : (scan ? (uint32_t)P.allhchunks : H.hchunks);
     unsigned long long sc_rows = 0, sc_nnz = 0;
-    // Work units: grouped heavy chunk tasks (four per unit, one per wave),
-    // heavy chunks, block rows, then light bins 10..0.
-    const uint32_t ngh = C_ghchunks;
-    const uint32_t gh_units = (ngh + (WG / 64) - 1) / (WG / 64);
-    uint32_t start[NBIN + 2];
-    start[0] = gh_units;
-    start[1] = start[0] + C_hchunks;
+    // Work units: heavy chunks, block rows, then light bins 10..0.
+    uint32_t start[NBIN + 1];
+    start[0] = 0;
+    start[1] = C_hchunks;
     start[2] = start[1] + qc[BIN_BLOCK];
     for (int j = 0; j < NLIGHT; ++j) {
         int b = NLIGHT - 1 - j;
@@ -1357,13 +1211,10 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(BP_ROWS
     }
     const uint32_t total = H.done ? 0u : start[2 + NLIGHT];
     for (uint32_t u = blockIdx.x; u < total; u += gridDim.x) {
-        if (u < start[0]) {
-            const uint32_t t = u * (WG / 64) + (threadIdx.x >> 6);
-            if (t < ngh) gh_chunk_corrections(P, par, t);
-        } else if (u < start[1]) {
-            if (P.inc && H.hbuild) inc_build_chunk(P, par, u - start[0], scan);
-            else if (P.inc) inc_head(P, par, u - start[0]);
-            else heavy_chunk_activity<MULTI>(P, par, u - start[0], W, scan);
+        if (u < start[1]) {
+            if (P.inc && H.hbuild) inc_build_chunk(P, par, u, scan);
+            else if (P.inc) inc_head(P, par, u);
+            else heavy_chunk_activity<MULTI>(P, par, u, W, scan);
         } else if (u < start[2]) {
             block_row<MULTI>(P, P.q[par][BIN_BLOCK], u - start[1], W,
                              scan ? P.allrows + P.allstart[BIN_BLOCK] : nullptr, par, sc_rows, sc_nnz);
@@ -1403,21 +1254,13 @@ __global__ void __launch_bounds__(WG) k_heavy(Params P) {
     const CtlHead H = ctl_head(P.ctl);
     const int par = H.round & 1;
     const bool scan = P.scan_ok && H.scan;
-    const uint32_t ngh = scan ? 0u : H.ghchunks;
-    const uint32_t gh_units = (ngh + (WG / 64) - 1) / (WG / 64);
     // with incremental heavy rows, a round without a rebuild takes only the
     // chunks whose row head asked for candidates
     const bool decided = P.inc && !H.hbuild;
     const uint32_t nh = decided ? H.hcand : (scan ? (uint32_t)P.allhchunks : H.hchunks);
-    const uint32_t total = H.done ? 0u : gh_units + nh;
-    for (uint32_t u = blockIdx.x; u < total; u += gridDim.x) {
-        if (u < gh_units) {
-            const uint32_t t = u * (WG / 64) + (threadIdx.x >> 6);
-            if (t < ngh) gh_chunk_candidates<MULTI>(P, par, t);
-        } else {
-            heavy_chunk_candidates<MULTI>(P, par, u - gh_units, scan, P.inc && H.hbuild, decided);
-        }
-    }
+    const uint32_t total = H.done ? 0u : nh;
+    for (uint32_t u = blockIdx.x; u < total; u += gridDim.x)
+        heavy_chunk_candidates<MULTI>(P, par, u, scan, P.inc && H.hbuild, decided);
 }
 
 // ------------------------------------------------------------------------
@@ -1459,22 +1302,9 @@ __device__ __forceinline__ void append_rows(const Params &P, int par, bool first
     const int lane = __lane_id();
     if (first && bin == BIN_HEAVY) {
         const int nch = (int)((len + P.heavy_chunk - 1) / P.heavy_chunk);
-        const int hi = P.gh ? P.ghidx[k] : -1;
-        if (hi >= 0) {
-            // grouped: the first slot of the group to queue the row adds
-            // the group's chunk tasks
-            const int g = s >> 6;
-            const uint64_t old = atomicOr((unsigned long long *)&P.ghmask[par][(size_t)g * P.gH + hi],
-                                          1ull << (s & 63));
-            if (old == 0) {
-                uint32_t cb = atomicAdd(&P.ctl->ghchunks[par], (uint32_t)nch);
-                for (int c = 0; c < nch; ++c) P.ghrec[par][cb + c] = make_int4(g, k, c, nch);
-            }
-        } else {
-            const int nrec = heads_only ? 1 : nch;
-            uint32_t cb = atomicAdd(&P.ctl->hchunks[par], (uint32_t)nrec);
-            for (int c = 0; c < nrec; ++c) P.hrec[par][cb + c] = make_int4(s, k, c, nch);
-        }
+        const int nrec = heads_only ? 1 : nch;
+        uint32_t cb = atomicAdd(&P.ctl->hchunks[par], (uint32_t)nrec);
+        for (int c = 0; c < nrec; ++c) P.hrec[par][cb + c] = make_int4(s, k, c, nch);
     }
     const bool lt = first && bin != BIN_HEAVY;
     uint32_t cnt = 0;
@@ -1589,8 +1419,6 @@ __device__ void enqueue_columns(const Params &P, int par, bool want, int s, long
 __device__ __forceinline__ void mark_dirty(const Params &P, int s, int i) {
     uint32_t bit = 1u << (i & 31);
     uint32_t old = atomicOr(&P.dirty[(size_t)s * P.snw + (i >> 5)], bit);
-    if (P.gh && (old & bit) == 0)
-        atomicOr((unsigned long long *)&P.dmaskg[(size_t)(s >> 6) * P.sn + i], 1ull << (s & 63));
     uint32_t h = fhash(i);
     atomicOr(&P.filt[(size_t)s * FILT_WORDS + (h >> 5)], 1u << (h & 31));
     if ((old & bit) == 0) {
@@ -1695,7 +1523,6 @@ __global__ void __launch_bounds__(WG) k_end(Params P) {
     if (threadIdx.x == 0) {
         for (int b = 0; b < NBIN; ++b) C->qcount[par][b] = 0;
         C->hchunks[par] = 0;
-        C->ghchunks[par] = 0;
         C->hcand[par] = 0;
         for (int st = 0; st < NSTRIPE; ++st) C->nchanged[st] = 0;
         if (P.scan_ok) {
@@ -2036,7 +1863,10 @@ __device__ void stage_sorted(const Params &P, const JobIO &IO, int s, const DIns
     }
 }
 
-// Forget the dirty variables of slot s: it reads the base again.
+// Forget the dirty variables of slot s: it reads the base again.  With
+// incremental heavy rows over the base, the corrections of every heavy row
+// holding one of them are cleared as well: a row's corrections come only
+// from bound changes of its own variables, all of which are dirty.
 __device__ void restore_slot(const Params &P, int s, int cnt) {
     uint32_t *dw = P.dirty + (size_t)s * P.snw;
     uint32_t *fw = P.filt + (size_t)s * FILT_WORDS;
@@ -2045,8 +1875,30 @@ __device__ void restore_slot(const Params &P, int s, int cnt) {
         // every set bit of these words belongs to this list
         dw[i >> 5] = 0u;
         fw[fhash(i) >> 5] = 0u;
-        if (P.gh)
-            atomicAnd((unsigned long long *)&P.dmaskg[(size_t)(s >> 6) * P.sn + i], ~(1ull << (s & 63)));
+    }
+    if (P.inc && P.hblimb) {
+        // one wave per variable, its column 64 entries at a time; the wave
+        // clears the accumulators of each heavy row among them
+        const int lane = __lane_id();
+        const DInst &I = P.I;
+        for (int t = threadIdx.x >> 6; t < cnt; t += WG / 64) {
+            const int i = P.dlist[(size_t)s * P.sn + t];
+            const int64_t c0 = I.col_ptr[i], c1 = I.col_ptr[i + 1];
+            for (int64_t e0 = c0; e0 < c1; e0 += 64) {
+                const int64_t e = e0 + lane;
+                const int h = e < c1 ? P.hidx[I.col_row[e]] : -1;
+                uint64_t hm = __ballot(h >= 0);
+                while (hm) {
+                    const int q = __ffsll((long long)hm) - 1;
+                    hm &= hm - 1;
+                    const size_t hs = (size_t)s * P.nheavy + __shfl(h, q, 64);
+                    long long *L = P.hacc + hs * 2 * HL;
+                    for (int j = lane; j < 2 * HL; j += 64) L[j] = 0;
+                    if (lane < 2) P.hinf[2 * hs + lane] = 0;
+                }
+            }
+        }
+        __threadfence();  // cleared before the next job's corrections (atomics)
     }
     __syncthreads();
     if (threadIdx.x == 0) P.dcount[s] = 0;
@@ -2127,21 +1979,29 @@ __device__ bool admit_job(const Params &P, const JobIO &IO, int s, int p, int pa
         restore_slot(P, s, nd);
         return false;
     }
-    // The first round holds the rows of the changed variables.
+    // The first round holds the rows of the changed variables; with
+    // incremental heavy rows their changes from the base bounds are the
+    // slot's first corrections.
     const int wave = threadIdx.x >> 6;
     for (int d0 = wave * 64; d0 < nd; d0 += WG) {
         int d = d0 + __lane_id();
         bool want = d < nd;
         long long c0 = 0;
         uint32_t len = 0;
+        double2 ob = make_double2(0.0, 0.0), nb = make_double2(0.0, 0.0);
         if (want) {
             int i = P.dlist[(size_t)s * P.sn + d];
             c0 = I.col_ptr[i];
             len = (uint32_t)(I.col_ptr[i + 1] - c0);
+            if (P.inc) {
+                ob = I.base[i];
+                nb = P.bnd[(size_t)s * P.sn + i];
+            }
         }
         uint32_t rows = 0;
         unsigned long long nnz = 0;
-        enqueue_columns<MULTI>(P, par, want, s, c0, len, false, &rows, &nnz);
+        enqueue_columns<MULTI>(P, par, want, s, c0, len, false, &rows, &nnz, P.inc != 0, ob.x, ob.y,
+                               nb.x, nb.y);
         if (__lane_id() == 0) {
             atomicAdd(&R.rows, rows);
             atomicAdd(&R.nnz, nnz);

@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_util import bp, dev, gpu_base, gpu_propagate
+from gpu_util import assert_same, bp, dev, gpu_base, gpu_propagate
 from helpers import load_golden, rel_close
 from paper_2510_20499_amd import gen
 
@@ -28,7 +28,9 @@ def _probe_both(inst, vars_, slots=None, cap=None, opts_kw=None):
     vs = np.asarray(vars_, np.int32)
     G = I.probe(dev(vs, torch.int32), cap=cap)
     torch.cuda.synchronize()
-    O = oracle.probe(inst, lb, ub, vs)
+    oo = oracle.Options()
+    oo.max_rounds = int(kw.get("max_rounds", oo.max_rounds))
+    O = oracle.probe(inst, lb, ub, vs, opts=oo)
     integ = inst["vtype"] == 1
     st = G["status"].cpu().numpy()
     rd = G["rounds"].cpu().numpy()
@@ -95,19 +97,57 @@ def test_single_scaled_with_heavy_rows():
     _probe_both(inst, vs, slots=32, opts_kw=dict(heavy_threshold=1024))
 
 
-@pytest.mark.parametrize("slots,chunk", [(200, 256), (64, 1024)])
-def test_grouped_heavy_rows(slots, chunk):
-    """Heavy rows of probe slots are processed per group of 64 slots from
-    the base row's exact expansion plus each slot's dirty corrections:
-    several groups (the last one partial), several chunks per row."""
+@pytest.mark.parametrize("slots,chunk,mode", [(200, 256, "inc"), (64, 1024, "inc"), (200, 256, "full_rows"),
+                                             (96, 512, "long_rounds"), (64, 512, "round_limit")])
+def test_heavy_rows_of_probe_slots(slots, chunk, mode):
+    """Heavy rows of probe slots keep exact incremental activities over the
+    base row's limbs: corrected at admission and by every bound change,
+    cleared when a slot retires, over several generations of jobs per slot.
+    With FULL_ROWS, or a round limit too long for the limb bound, each
+    slot's heavy rows are summed chunk by chunk instead; a round limit of
+    two ends jobs at the limit, draining their queued heads."""
     inst = gen.make("probe", 2, scale=0.05)
     assert (np.diff(inst["row_ptr"]) > 1024).sum() > 20
     _, lb, ub = oracle.propagate(inst)
     vs = gen.pick_probe_vars(inst, lb, ub, 300, seed=2)
-    _probe_both(inst, vs, slots=slots, opts_kw=dict(heavy_threshold=1024, heavy_chunk=chunk))
+    kw = dict(heavy_threshold=1024, heavy_chunk=chunk)
+    if mode == "full_rows":
+        kw["flags"] = bp().FLAG_FULL_ROWS
+    elif mode == "long_rounds":
+        kw["max_rounds"] = 1 << 20
+    elif mode == "round_limit":
+        kw["max_rounds"] = 2
+    G, O = _probe_both(inst, vs, slots=slots, opts_kw=kw)
+    if mode == "round_limit":
+        assert (O["status"] == 2).any()
 
 
-def test_grouped_heavy_rows_exact_path():
+def test_heavy_rows_of_probe_slots_repeated_calls():
+    """The same instance probed three times with different binaries: every
+    call starts from cleared corrections, and a plain propagation between
+    two calls keeps its own accumulators."""
+    inst = gen.make("probe", 3, scale=0.05)
+    ro, lb, ub = oracle.propagate(inst)
+    I = bp().Instance(inst, bp().default_options(heavy_threshold=1024, heavy_chunk=512, probe_slots=100))
+    gpu_base(I, lb, ub)
+    for seed in range(3):
+        vs = gen.pick_probe_vars(inst, lb, ub, 150, seed=10 + seed).astype(np.int32)
+        G = I.probe(dev(vs, torch.int32))
+        torch.cuda.synchronize()
+        O = oracle.probe(inst, lb, ub, vs)
+        assert np.array_equal(G["status"].cpu().numpy(), O["status"])
+        assert np.array_equal(G["rounds"].cpu().numpy(), O["rounds"])
+        assert np.array_equal(G["nnz"].cpu().numpy(), O["nnz"])
+        assert np.array_equal(G["off"].cpu().numpy(), O["off"])
+        assert np.array_equal(G["var"].cpu().numpy(), O["var"])
+        # a cold propagation from the root on the same engine (it also sets
+        # the base again: the next call recomputes the base rows)
+        r, l2, u2 = gpu_propagate(I, inst, lb, ub)
+        r2, lo2, uo2 = oracle.propagate(inst, lb, ub)
+        assert_same(inst, r, l2, u2, r2, lo2, uo2, "cold propagation after probe call %d" % seed)
+
+
+def test_heavy_rows_of_probe_slots_exact_path():
     inst = gen.make("single", 4, scale=0.1)
     _, lb, ub = oracle.propagate(inst)
     vs = gen.pick_probe_vars(inst, lb, ub, 100, seed=4)
