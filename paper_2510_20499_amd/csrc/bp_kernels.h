@@ -82,7 +82,14 @@ struct SlotInfo {
     unsigned long long pending_nnz;
     int32_t retire;     // finished at the last round end, results not yet written
     int32_t inst;       // instance of the slot
+    // Assigned by the round end of a job engine (valid while Ctl::claims is
+    // set): the next job of a slot that is free (CLAIM_NONE: none left), and
+    // the staging offset and completion-ring position of a finished job.
+    int32_t claim;
+    uint32_t ring_pos;
+    unsigned long long stage_off;
 };
+constexpr int32_t CLAIM_NONE = -1;
 
 // Round control block (one per engine).
 struct Ctl {
@@ -99,7 +106,7 @@ struct Ctl {
     uint32_t next_job;
     uint32_t total_jobs;
     uint32_t done_jobs;              // entries of the completion ring
-    uint32_t pad_;
+    uint32_t claims;                 // the slots' claim / staging fields are assigned
     unsigned long long stage_count;  // implied entries staged so far
     // cumulative counters (byte accounting)
     unsigned long long stat_rows;    // row tasks at round starts
@@ -1428,6 +1435,89 @@ __device__ __forceinline__ void mark_dirty(const Params &P, int s, int i) {
 }
 
 // Round end for every slot: outcome, counters, next round (one workgroup).
+// Job engines, at the round end (the one workgroup of k_end, after its slot
+// pass; each thread reads back the slots it wrote): the slots that are free
+// now get the next jobs in slot order, and the finished ones their staging
+// offsets and completion-ring positions, by workgroup prefix sums.  The
+// retire kernel then needs no atomics on these shared counters, which every
+// one of its workgroups would otherwise hit at once.
+__device__ __forceinline__ uint32_t lane_prefix(uint64_t mask) {
+    return (uint32_t)__popcll(mask & ((1ull << __lane_id()) - 1ull));
+}
+
+__device__ void assign_claims(const Params &P, uint32_t next0, uint32_t total) {
+    Ctl *C = P.ctl;
+    __shared__ uint32_t w_free[WG / 64], w_fin[WG / 64];
+    __shared__ unsigned long long w_cnt[WG / 64];
+    __shared__ unsigned long long b_stage;
+    __shared__ uint32_t b_free, b_fin, b_ring;
+    const int lane = __lane_id(), wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) {
+        b_free = 0;
+        b_fin = 0;
+        b_stage = C->stage_count;
+        b_ring = C->done_jobs;
+    }
+    __syncthreads();
+    const uint32_t avail = next0 < total ? total - next0 : 0u;
+    for (int c0 = 0; c0 < P.nslots; c0 += WG) {
+        const int s = c0 + threadIdx.x;
+        bool fr = false, fn = false;
+        unsigned long long cnt = 0;
+        if (s < P.nslots) {
+            const SlotInfo &S = P.info[s];
+            fr = S.state == SLOT_FREE;
+            fn = S.retire != 0;
+            if (fn && S.status != 1)
+                cnt = (unsigned long long)__hip_atomic_load(&P.dcount[s], __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const uint64_t mf = __ballot(fr), mn = __ballot(fn);
+        unsigned long long inc = cnt;  // inclusive prefix of the staged counts in the wave
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const unsigned long long y = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += y;
+        }
+        if (lane == 63) {
+            w_free[wave] = (uint32_t)__popcll(mf);
+            w_fin[wave] = (uint32_t)__popcll(mn);
+            w_cnt[wave] = inc;
+        }
+        __syncthreads();
+        uint32_t rf = b_free + lane_prefix(mf), rn = b_fin + lane_prefix(mn);
+        unsigned long long off = b_stage + inc - cnt;
+        for (int w = 0; w < wave; ++w) {
+            rf += w_free[w];
+            rn += w_fin[w];
+            off += w_cnt[w];
+        }
+        if (s < P.nslots) {
+            SlotInfo &S = P.info[s];
+            if (fr) S.claim = rf < avail ? (int32_t)(next0 + rf) : CLAIM_NONE;
+            if (fn) {
+                S.stage_off = off;
+                S.ring_pos = b_ring + rn;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 0; w < WG / 64; ++w) {
+                b_free += w_free[w];
+                b_fin += w_fin[w];
+                b_stage += w_cnt[w];
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        C->next_job = next0 + min(b_free, avail);
+        C->stage_count = b_stage;
+        C->done_jobs = b_ring + b_fin;
+        C->claims = 1u;
+    }
+}
+
 __global__ void __launch_bounds__(WG) k_end(Params P) {
     Ctl *C = P.ctl;
     // Control fields and this thread's first slot record read together,
@@ -1506,6 +1596,7 @@ __global__ void __launch_bounds__(WG) k_end(Params P) {
             if (drain) atomicAdd(&s_active, 1u);  // still has queued tasks
         }
     }
+    if (c_total_jobs > 0) assign_claims(P, c_next_job, c_total_jobs);
     if (P.touched) {
         size_t words = (size_t)P.nslots * P.snw;
         for (size_t w = threadIdx.x; w < words; w += WG) P.touched[w] = 0u;
@@ -1762,12 +1853,18 @@ struct RetireScratch {
     int32_t job, flag, badv;
     uint32_t rows;
     unsigned long long nnz;
+    // the claimed job: its descriptor and, for a probe, the variable's base
+    // bounds and column range
+    Job jd;
+    double2 pb;
+    long long pc0, pc1;
 };
 
-// Write a job's outcome and reserve its staged list.
+// Write a job's outcome and reserve its staged list: at the offset and
+// ring position the round end assigned (pre), or by atomics.
 __device__ void write_job(const Params &P, const JobIO &IO, int p, int status, int rounds,
                           unsigned long long nnz, int nbad, int badrow, int badvar, int cnt,
-                          RetireScratch &R) {
+                          RetireScratch &R, const SlotInfo *pre = nullptr) {
     if (threadIdx.x == 0) {
         IO.status[p] = (int8_t)status;
         IO.rounds[p] = rounds;
@@ -1777,12 +1874,13 @@ __device__ void write_job(const Params &P, const JobIO &IO, int p, int status, i
             IO.bad_row[p] = badrow;
             IO.bad_var[p] = badvar;
         }
-        unsigned long long off = atomicAdd(&P.ctl->stage_count, (unsigned long long)cnt);
+        const unsigned long long off =
+            pre ? pre->stage_off : atomicAdd(&P.ctl->stage_count, (unsigned long long)cnt);
         IO.stage_off[p] = (int64_t)off;
         IO.stage_cnt[p] = cnt;
         R.off = (long long)off;
         if (IO.done_ring) {
-            uint32_t d = atomicAdd(&P.ctl->done_jobs, 1u);
+            const uint32_t d = pre ? pre->ring_pos : atomicAdd(&P.ctl->done_jobs, 1u);
             IO.done_ring[d] = (uint32_t)p;
         }
     }
@@ -1881,6 +1979,7 @@ __device__ void restore_slot(const Params &P, int s, int cnt) {
         // clears the accumulators of each heavy row among them
         const int lane = __lane_id();
         const DInst &I = P.I;
+        unsigned long long junk = 0;
         for (int t = threadIdx.x >> 6; t < cnt; t += WG / 64) {
             const int i = P.dlist[(size_t)s * P.sn + t];
             const int64_t c0 = I.col_ptr[i], c1 = I.col_ptr[i + 1];
@@ -1892,13 +1991,15 @@ __device__ void restore_slot(const Params &P, int s, int cnt) {
                     const int q = __ffsll((long long)hm) - 1;
                     hm &= hm - 1;
                     const size_t hs = (size_t)s * P.nheavy + __shfl(h, q, 64);
-                    long long *L = P.hacc + hs * 2 * HL;
-                    for (int j = lane; j < 2 * HL; j += 64) L[j] = 0;
-                    if (lane < 2) P.hinf[2 * hs + lane] = 0;
+                    unsigned long long *L = (unsigned long long *)(P.hacc + hs * 2 * HL);
+                    for (int j = lane; j < 2 * HL; j += 64) junk |= atomicExch(&L[j], 0ull);
+                    if (lane < 2) junk |= (unsigned long long)(uint32_t)atomicExch(&P.hinf[2 * hs + lane], 0);
                 }
             }
         }
-        __threadfence();  // cleared before the next job's corrections (atomics)
+        // The clears are atomics like the next job's corrections, and their
+        // results are waited for here: they are done before the barrier.
+        asm volatile("" ::"v"(junk));
     }
     __syncthreads();
     if (threadIdx.x == 0) P.dcount[s] = 0;
@@ -1909,20 +2010,56 @@ __device__ __forceinline__ int dcount_now(const Params &P, int s) {
     return (int)__hip_atomic_load(&P.dcount[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Set up job p in the free slot s.  Returns true if the slot now runs it;
-// false if the job finished at admission (its results are written).
+// Claim the next job (by thread 64, the second wave, so that the round
+// trips overlap the first wave's work) and read what its admission needs
+// first: the descriptor and, for a probe, the variable's base bounds and
+// column range.  Visible to the workgroup after its next barrier.
+template <bool MULTI>
+__device__ __forceinline__ void claim_job(const Params &P, const JobIO &IO, RetireScratch &R,
+                                          const SlotInfo *pre = nullptr) {
+    if (threadIdx.x != 64) return;
+    uint32_t p;
+    if (pre) p = pre->claim == CLAIM_NONE ? 0xffffffffu : (uint32_t)pre->claim;  // assigned at the round end
+    else p = atomicAdd(&P.ctl->next_job, 1u);
+    R.job = (int)p;
+    if (p >= P.ctl->total_jobs) return;
+    const Job J = IO.jobs[p];
+    R.jd = J;
+    if (J.kind == JOB_PROBE) {
+        DInst I;
+        if constexpr (MULTI) I = P.insts[J.inst];
+        else I = P.I;
+        R.pb = I.base[J.a];
+        R.pc0 = I.col_ptr[J.a];
+        R.pc1 = I.col_ptr[J.a + 1];
+    }
+}
+
+// The first dirty variable of a clean slot (every free slot is clean): no
+// returning atomics are needed to find out that it is new.
+__device__ __forceinline__ void mark_dirty_first(const Params &P, int s, int i) {
+    atomicOr(&P.dirty[(size_t)s * P.snw + (i >> 5)], 1u << (i & 31));
+    const uint32_t h = fhash(i);
+    atomicOr(&P.filt[(size_t)s * FILT_WORDS + (h >> 5)], 1u << (h & 31));
+    P.dlist[(size_t)s * P.sn] = i;
+    P.dcount[s] = 1;
+}
+
+// Set up the claimed job p (its descriptor and first reads in R) in the
+// free slot s.  Returns true if the slot now runs it; false if the job
+// finished at admission (its results are written).
 template <bool MULTI>
 __device__ bool admit_job(const Params &P, const JobIO &IO, int s, int p, int par,
                           RetireScratch &R) {
     SlotInfo &S = P.info[s];
-    const Job J = IO.jobs[p];
+    const Job J = R.jd;
     DInst I;
     if constexpr (MULTI) I = P.insts[J.inst];
     else I = P.I;
     double2 pbox = make_double2(0.0, 0.0);  // a probe's box, within the base
     if (J.kind == JOB_PROBE) {
         const int j = J.a;
-        const double2 b = I.base[j];
+        const double2 b = R.pb;
         double lo = 0.0, hi = 0.0;
         probe_restriction(b.x, b.y, J.b, lo, hi);
         pbox = make_double2(canon0(fmax(lo, b.x)), canon0(fmin(hi, b.y)));
@@ -1956,7 +2093,7 @@ __device__ bool admit_job(const Params &P, const JobIO &IO, int s, int p, int pa
     if (J.kind == JOB_PROBE) {
         if (threadIdx.x == 0) {
             P.bnd[(size_t)s * P.sn + J.a] = pbox;
-            mark_dirty(P, s, J.a);
+            mark_dirty_first(P, s, J.a);
         }
     } else {
         for (int f = J.a + threadIdx.x; f < J.a + J.b; f += WG) {
@@ -1973,7 +2110,8 @@ __device__ bool admit_job(const Params &P, const JobIO &IO, int s, int p, int pa
         }
     }
     __syncthreads();
-    const int nd = dcount_now(P, s);
+    const bool probe = J.kind == JOB_PROBE;
+    const int nd = probe ? 1 : dcount_now(P, s);
     if (R.badv != NONE) {  // a crossed box before the first round
         write_job(P, IO, p, 1, 0, 0ull, 0, -1, R.badv, 0, R);
         restore_slot(P, s, nd);
@@ -1989,7 +2127,12 @@ __device__ bool admit_job(const Params &P, const JobIO &IO, int s, int p, int pa
         long long c0 = 0;
         uint32_t len = 0;
         double2 ob = make_double2(0.0, 0.0), nb = make_double2(0.0, 0.0);
-        if (want) {
+        if (want && probe) {  // the probed variable, read at the claim
+            c0 = R.pc0;
+            len = (uint32_t)(R.pc1 - R.pc0);
+            ob = R.pb;
+            nb = pbox;
+        } else if (want) {
             int i = P.dlist[(size_t)s * P.sn + d];
             c0 = I.col_ptr[i];
             len = (uint32_t)(I.col_ptr[i + 1] - c0);
@@ -2036,6 +2179,11 @@ __global__ void __launch_bounds__(WG) k_retire(Params P, JobIO IO) {
     const int par = C->round & 1;
     for (int s = blockIdx.x; s < P.nslots; s += gridDim.x) {
         SlotInfo &S = P.info[s];
+        // A slot that is free after this step (retired without draining, or
+        // idle) claims its next job before retiring the last one.
+        const bool admits = S.state == SLOT_FREE;
+        const SlotInfo *pre = C->claims ? &S : nullptr;
+        if (admits) claim_job<MULTI>(P, IO, R, pre);
         if (S.retire) {
             const int p = S.job;
             const int status = S.status;
@@ -2053,24 +2201,25 @@ __global__ void __launch_bounds__(WG) k_retire(Params P, JobIO IO) {
                     bvar = S.var_bad_min;
                 }
             }
-            write_job(P, IO, p, status, S.rounds, S.nnz, nbad, brow, bvar, cnt, R);
+            write_job(P, IO, p, status, S.rounds, S.nnz, nbad, brow, bvar, cnt, R, pre);
             if (cnt > 0) stage_sorted(P, IO, s, I, cnt, R);
             restore_slot(P, s, dcnt);
             if (threadIdx.x == 0) S.retire = 0;
             __syncthreads();
         }
-        if (S.state != SLOT_FREE) continue;
+        if (!admits) continue;
         // Admit jobs until one needs rounds or none is left.  A claim past
         // the end of the list takes no job; the counter may then exceed the
         // list length, and a host that appends jobs first lowers it back to
         // the old length (no kernel runs meanwhile).
+        __syncthreads();
         for (;;) {
-            if (threadIdx.x == 0) R.job = (int)atomicAdd(&C->next_job, 1u);
-            __syncthreads();
             const uint32_t p = (uint32_t)R.job;
             __syncthreads();
             if (p >= C->total_jobs) break;
             if (admit_job<MULTI>(P, IO, s, (int)p, par, R)) break;
+            claim_job<MULTI>(P, IO, R);
+            __syncthreads();
         }
         __syncthreads();
     }

@@ -446,6 +446,9 @@ static int server_append(bp_server *sv) {
     sv->nfix_dev += (int64_t)fv.size();
     uint32_t tot = (uint32_t)sv->njobs_dev;
     HIPTRY(hipMemcpyAsync(&sv->P.ctl->total_jobs, &tot, 4, hipMemcpyHostToDevice, st));
+    // the claims the last round end assigned predate these jobs
+    const uint32_t no_claims = 0;
+    HIPTRY(hipMemcpyAsync(&sv->P.ctl->claims, &no_claims, 4, hipMemcpyHostToDevice, st));
     // Admit right away, then recompute the done flag.
     k_retire<true><<<std::min(sv->slots, 4096), WG, 0, st>>>(sv->P, sv->IO);
     k_jobs_done_check<<<1, 256, 0, st>>>(sv->P);
