@@ -189,6 +189,9 @@ def main():
     ap.add_argument("--skip-probe", action="store_true",
                     help="skip the batched double-probing measurement")
     ap.add_argument("--probe-vars", type=int, default=4096)
+    ap.add_argument("--probe-schedule", default="",
+                    help="heavy_threshold,heavy_chunk,rounds_per_launch,probe_slots for the probe leg "
+                         "instead of tuning it (counter runs)")
     ap.add_argument("--probe-plain", type=int, default=256,
                     help="binaries probed one call at a time for the plain baseline")
     ap.add_argument("--skip-serving", action="store_true",
@@ -541,14 +544,26 @@ def bench_probe(args, bp, gen, torch, np):
     refilled at round boundaries."""
     dev = torch.device("cuda:0")
     inst = gen.make("probe", args.seed)
-    I = bp.Instance(inst)
-    lb = torch.tensor(inst["lb"], dtype=torch.float64, device=dev)
-    ub = torch.tensor(inst["ub"], dtype=torch.float64, device=dev)
+    sched = None
+    if args.probe_schedule:  # given (counter runs take the bench line's schedule)
+        ht, hc, rk, ps = (int(x) for x in args.probe_schedule.split(","))
+        sched = dict(heavy_threshold=ht, heavy_chunk=hc, rounds_per_launch=rk, probe_slots=ps)
+    I = bp.Instance(inst, bp.default_options(**(sched or {})))
+    lb0 = torch.tensor(inst["lb"], dtype=torch.float64, device=dev)
+    ub0 = torch.tensor(inst["ub"], dtype=torch.float64, device=dev)
+    lb, ub = fresh(lb0, ub0)
     root = I.propagate(lb, ub)
     assert root["status"] == bp.BP_OK
     vs = gen.pick_probe_vars(inst, lb.cpu().numpy(), ub.cpu().numpy(), args.probe_vars, seed=args.seed)
     k = int(vs.size)
     vars_d = torch.tensor(vs, dtype=torch.int32, device=dev)
+    if sched is None and not args.profile_probe:
+        # the schedule (row split, rounds per graph, probe slots) tuned on
+        # this instance's cold propagation and on these probes, before
+        # timing; the tuner leaves the base at the root fixed point
+        t = I.autotune(*fresh(lb0, ub0), vars_d)
+        sched = {key: t[key] for key in ("heavy_threshold", "heavy_chunk", "rounds_per_launch", "probe_slots")}
+        log("probe: tuned schedule %s (%d trials)" % (sched, t["trials"]))
     # batched
     G = I.probe(vars_d)  # warm (sizes the output buffers)
     cap = int(G["off"][-1].item()) + 16
@@ -567,17 +582,23 @@ def bench_probe(args, bp, gen, torch, np):
     tb = (time.perf_counter() - t0) / reps
     nnz_b = int(G["nnz"].sum().item())
     rounds = G["rounds"].cpu().numpy()
-    # plain: one binary per call
+    # plain: one binary per call, on an instance with the default schedule
+    # (the batch's tuned graphs of many rounds would only slow calls of a
+    # round or two)
     kp = min(args.probe_plain, k)
-    I.probe(vars_d[:1], cap=cap)
+    Ip = bp.Instance(inst)
+    lp, up = fresh(lb0, ub0)
+    assert Ip.propagate(lp, up)["status"] == bp.BP_OK
+    Ip.probe(vars_d[:1], cap=cap)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     nnz_p = 0
     for t in range(kp):
-        Gp = I.probe(vars_d[t:t + 1], cap=cap)
+        Gp = Ip.probe(vars_d[t:t + 1], cap=cap)
         nnz_p += int(Gp["nnz"].sum().item())
     torch.cuda.synchronize()
     tp = time.perf_counter() - t0
+    del Ip
     res = {
         "workload": "double probing: m=%d, n=%d, nnz=%d; %d binaries x {0,1} = %d bound vectors"
                     % (inst["m"], inst["n"], int(inst["row_ptr"][-1]), k, 2 * k),
@@ -588,13 +609,14 @@ def bench_probe(args, bp, gen, torch, np):
         "plain_probes_per_s": 2 * kp / tp,
         "plain_nnz_per_s": nnz_p / tp,
         "batched_over_plain": (2 * k / tb) / (2 * kp / tp),
-        "probe_slots": int(I.options.probe_slots),
+        "probe_slots": int(sched["probe_slots"] if sched else I.options.probe_slots),
+        "schedule": sched,
         "rounds_mean": float(rounds.mean()), "rounds_max": int(rounds.max()),
         "nnz_per_probe_mean": nnz_b / (2 * k),
         "implied_entries": int(G["off"][-1].item()),
         "infeasible_probes": int((G["status"] == bp.BP_INFEASIBLE).sum().item()),
     }
-    res["roofline"] = probe_roofline(bp, inst, lb, ub, vars_d, cap, tb, torch)
+    res["roofline"] = probe_roofline(bp, inst, lb, ub, vars_d, cap, tb, torch, sched)
     res["roofline"]["traffic"] = measured_traffic("probe k_rows")
     log("probe: batched %.2f ms, k_rows %.1f GB/s (%.4f of peak), call %.1f GB/s"
         % (tb * 1e3, res["roofline"]["achieved"], res["roofline"]["frac"],
@@ -625,7 +647,7 @@ def bench_probe(args, bp, gen, torch, np):
     return res
 
 
-def probe_roofline(bp, inst, lb, ub, vars_d, cap, t_call, torch):
+def probe_roofline(bp, inst, lb, ub, vars_d, cap, t_call, torch, sched=None):
     """Roofline of the activity kernel k_rows in the batched double probing.
     Bytes (the algorithmic count for a batch): the matrix term once per row
     and round over the union of the slots' worklists -- 12 B per nonzero and
@@ -638,7 +660,7 @@ def probe_roofline(bp, inst, lb, ub, vars_d, cap, t_call, torch):
     average over the launches of one call.  Also the whole call's
     algorithmic bytes (bound records written too) over its measured time."""
     def run(flags):
-        J = bp.Instance(inst, bp.default_options(flags=flags))
+        J = bp.Instance(inst, bp.default_options(flags=flags, **(sched or {})))
         l2, u2 = fresh(lb, ub)
         J.propagate(l2, u2, torch.zeros(0, dtype=torch.int32, device=lb.device))
         J.kernel_stats(reset=True)

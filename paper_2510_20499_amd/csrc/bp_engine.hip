@@ -131,6 +131,9 @@ struct Engine {
     // first inc_cap slots: INC_SLOTS, or every slot of a probe engine)
     DevBuf cbits, hhit, allhrec, hacc, hinf, hwid, hact, hcrec[2];
     int32_t inc_cap = 0;
+    // every slot's heavy-row corrections are zero (a probe call ran to the
+    // end: each retired job cleared its own)
+    bool inc_clear = false;
     Shape shape;
     int64_t bytes = 0;
     DevBuf bnd, cand, vflag, rflag, info, chg, dirty, dlist, dcount, ctl, touched, useen, filt;
@@ -1059,6 +1062,7 @@ static int propagate_slots(bp_instance *h, int32_t Bv, double *lb, double *ub,
             HIPTRY(hipMemsetAsync(E1.hacc.p, 0, nh * 2 * HL * 8, st));
             HIPTRY(hipMemsetAsync(E1.hinf.p, 0, nh * 8, st));
             HIPTRY(hipMemsetAsync(E1.hwid.p, 0, nh * 8, st));
+            E1.inc_clear = false;  // this call's accumulators are not cleared at its end
         }
         if (nheavy > 0 && (P.scan_ok || P.inc))
             k_fill_allhrec<<<grid_for(nheavy), 256, 0, st>>>(dinst_of(h), h->cold_rows.as<int32_t>() + h->bin_start[BIN_HEAVY],
@@ -1400,8 +1404,11 @@ extern "C" int bp_probe(bp_instance *h, const int32_t *vars, int32_t k, bp_probe
         P.hblimb = h->hb_limb.as<long long>();
         P.hbinf = h->hb_inf.as<int32_t>();
         P.hbwid = h->hb_wid.as<double>();
-        HIPTRY(hipMemsetAsync(E.hacc.p, 0, (size_t)S * H * 2 * HL * 8, st));
-        HIPTRY(hipMemsetAsync(E.hinf.p, 0, (size_t)S * H * 8, st));
+        if (!E.inc_clear) {
+            HIPTRY(hipMemsetAsync(E.hacc.p, 0, (size_t)E.inc_cap * H * 2 * HL * 8, st));
+            HIPTRY(hipMemsetAsync(E.hinf.p, 0, (size_t)E.inc_cap * H * 8, st));
+        }
+        E.inc_clear = false;  // until this call ends normally
     }
     Ctl c;
     memset(&c, 0, sizeof(c));
@@ -1415,6 +1422,7 @@ extern "C" int bp_probe(bp_instance *h, const int32_t *vars, int32_t k, bp_probe
     HIPTRY(hipGetLastError());
     const int64_t limit = ((int64_t)h->opt.max_rounds + 2) * (jobs + 1);
     if (int rc = run_rounds(h, P, &IO, limit, st)) return rc;
+    if (inc) E.inc_clear = true;  // every job retired
     Ctl hc;
     HIPTRY(hipMemcpyAsync(&hc, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     HIPTRY(hipStreamSynchronize(st));
