@@ -800,7 +800,8 @@ static int launch_round(bp_instance *h, const Params &P, const JobIO *io, hipStr
     k_heavy<false><<<GRID_HEAVY, WG, 0, st>>>(P);
     if (timed) hipExtLaunchKernelGGL(k_apply<false>, dim3(GRID_APPLY), dim3(WG), 0, st, h->ev2, h->ev3, 0, P);
     else k_apply<false><<<GRID_APPLY, WG, 0, st>>>(P);
-    k_end<<<1, WG, 0, st>>>(P);
+    if (io) k_end<END_WG><<<1, END_WG, 0, st>>>(P);
+    else k_end<WG><<<1, WG, 0, st>>>(P);
     if (io) k_retire<false><<<std::min(P.nslots, 4096), WG, 0, st>>>(P, *io);
     HIPTRY(hipGetLastError());
     return 0;
@@ -850,7 +851,8 @@ static int run_rounds(bp_instance *h, const Params &P, const JobIO *io, int64_t 
                     k_rows<false><<<GRID_ROWS, WG, 0, cs>>>(P);
                     k_heavy<false><<<GRID_HEAVY, WG, 0, cs>>>(P);
                     k_apply<false><<<GRID_APPLY, WG, 0, cs>>>(P);
-                    k_end<<<1, WG, 0, cs>>>(P);
+                    if (io) k_end<END_WG><<<1, END_WG, 0, cs>>>(P);
+                    else k_end<WG><<<1, WG, 0, cs>>>(P);
                     if (io) k_retire<false><<<std::min(P.nslots, 4096), WG, 0, cs>>>(P, *io);
                 }
                 hipGraph_t g;

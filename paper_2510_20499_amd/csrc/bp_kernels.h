@@ -1445,10 +1445,11 @@ __device__ __forceinline__ uint32_t lane_prefix(uint64_t mask) {
     return (uint32_t)__popcll(mask & ((1ull << __lane_id()) - 1ull));
 }
 
+template <int NT>
 __device__ void assign_claims(const Params &P, uint32_t next0, uint32_t total) {
     Ctl *C = P.ctl;
-    __shared__ uint32_t w_free[WG / 64], w_fin[WG / 64];
-    __shared__ unsigned long long w_cnt[WG / 64];
+    __shared__ uint32_t w_free[NT / 64], w_fin[NT / 64];
+    __shared__ unsigned long long w_cnt[NT / 64];
     __shared__ unsigned long long b_stage;
     __shared__ uint32_t b_free, b_fin, b_ring;
     const int lane = __lane_id(), wave = threadIdx.x >> 6;
@@ -1460,7 +1461,7 @@ __device__ void assign_claims(const Params &P, uint32_t next0, uint32_t total) {
     }
     __syncthreads();
     const uint32_t avail = next0 < total ? total - next0 : 0u;
-    for (int c0 = 0; c0 < P.nslots; c0 += WG) {
+    for (int c0 = 0; c0 < P.nslots; c0 += NT) {
         const int s = c0 + threadIdx.x;
         bool fr = false, fn = false;
         unsigned long long cnt = 0;
@@ -1502,7 +1503,7 @@ __device__ void assign_claims(const Params &P, uint32_t next0, uint32_t total) {
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            for (int w = 0; w < WG / 64; ++w) {
+            for (int w = 0; w < NT / 64; ++w) {
                 b_free += w_free[w];
                 b_fin += w_fin[w];
                 b_stage += w_cnt[w];
@@ -1518,7 +1519,11 @@ __device__ void assign_claims(const Params &P, uint32_t next0, uint32_t total) {
     }
 }
 
-__global__ void __launch_bounds__(WG) k_end(Params P) {
+// NT threads: END_WG for job engines, whose many slots the one workgroup
+// walks every round; WG otherwise.
+constexpr int END_WG = 1024;
+template <int NT>
+__global__ void __launch_bounds__(NT) k_end(Params P) {
     Ctl *C = P.ctl;
     // Control fields and this thread's first slot record read together,
     // before the early exit.
@@ -1551,7 +1556,7 @@ __global__ void __launch_bounds__(WG) k_end(Params P) {
         s_finished = 0;
     }
     __syncthreads();
-    for (int s = threadIdx.x; s < P.nslots; s += WG) {
+    for (int s = threadIdx.x; s < P.nslots; s += NT) {
         SlotInfo &S = P.info[s];
         const SlotInfo V = s == s_first ? first : S;  // values at the round end
         if (V.state == SLOT_DRAINING) {
@@ -1596,19 +1601,19 @@ __global__ void __launch_bounds__(WG) k_end(Params P) {
             if (drain) atomicAdd(&s_active, 1u);  // still has queued tasks
         }
     }
-    if (c_total_jobs > 0) assign_claims(P, c_next_job, c_total_jobs);
+    if (c_total_jobs > 0) assign_claims<NT>(P, c_next_job, c_total_jobs);
     if (P.touched) {
         size_t words = (size_t)P.nslots * P.snw;
-        for (size_t w = threadIdx.x; w < words; w += WG) P.touched[w] = 0u;
+        for (size_t w = threadIdx.x; w < words; w += NT) P.touched[w] = 0u;
     }
     if (P.useen)
-        for (size_t w = threadIdx.x; w < (size_t)P.srw; w += WG) P.useen[w] = 0u;
+        for (size_t w = threadIdx.x; w < (size_t)P.srw; w += NT) P.useen[w] = 0u;
     // the next round rebuilds the heavy-row accumulators: start from zero
     if (P.inc && (par ? c_hb0 : c_hb1)) {
         const size_t nh = (size_t)P.inc_slots * P.nheavy;
-        for (size_t w = threadIdx.x; w < nh * 2 * HL; w += WG) P.hacc[w] = 0;
-        for (size_t w = threadIdx.x; w < 2 * nh; w += WG) P.hinf[w] = 0;
-        for (size_t w = threadIdx.x; w < nh; w += WG) P.hwid[w] = 0ull;
+        for (size_t w = threadIdx.x; w < nh * 2 * HL; w += NT) P.hacc[w] = 0;
+        for (size_t w = threadIdx.x; w < 2 * nh; w += NT) P.hinf[w] = 0;
+        for (size_t w = threadIdx.x; w < nh; w += NT) P.hwid[w] = 0ull;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1961,10 +1966,41 @@ __device__ void stage_sorted(const Params &P, const JobIO &IO, int s, const DIns
     }
 }
 
-// Forget the dirty variables of slot s: it reads the base again.  With
-// incremental heavy rows over the base, the corrections of every heavy row
-// holding one of them are cleared as well: a row's corrections come only
-// from bound changes of its own variables, all of which are dirty.
+// With incremental heavy rows over the base: clear the corrections of
+// every heavy row holding one of slot s's cnt dirty variables (a row's
+// corrections come only from bound changes of its own variables, all of
+// which are dirty).  Waves w0, w0 + nw, ... each take a variable and walk
+// its column 64 entries at a time.  The clears are atomics like the next
+// job's corrections, and their results are waited for: they are done when
+// the caller's next barrier is.
+__device__ void clear_heavy(const Params &P, int s, int cnt, int w0, int nw) {
+    if (!(P.inc && P.hblimb)) return;
+    const int lane = __lane_id();
+    const DInst &I = P.I;
+    unsigned long long junk = 0;
+    for (int t = w0; t < cnt; t += nw) {
+        const int i = P.dlist[(size_t)s * P.sn + t];
+        const int64_t c0 = I.col_ptr[i], c1 = I.col_ptr[i + 1];
+        for (int64_t e0 = c0; e0 < c1; e0 += 64) {
+            const int64_t e = e0 + lane;
+            const int h = e < c1 ? P.hidx[I.col_row[e]] : -1;
+            uint64_t hm = __ballot(h >= 0);
+            while (hm) {
+                const int q = __ffsll((long long)hm) - 1;
+                hm &= hm - 1;
+                const size_t hs = (size_t)s * P.nheavy + __shfl(h, q, 64);
+                unsigned long long *L = (unsigned long long *)(P.hacc + hs * 2 * HL);
+                for (int j = lane; j < 2 * HL; j += 64) junk |= atomicExch(&L[j], 0ull);
+                if (lane < 2) junk |= (unsigned long long)(uint32_t)atomicExch(&P.hinf[2 * hs + lane], 0);
+            }
+        }
+    }
+    asm volatile("" ::"v"(junk));
+}
+
+// Forget the dirty variables of slot s: it reads the base again, and its
+// heavy-row corrections are cleared.  (Clearing them in two waves while the
+// others write the job's results was timed slower.)
 __device__ void restore_slot(const Params &P, int s, int cnt) {
     uint32_t *dw = P.dirty + (size_t)s * P.snw;
     uint32_t *fw = P.filt + (size_t)s * FILT_WORDS;
@@ -1974,33 +2010,7 @@ __device__ void restore_slot(const Params &P, int s, int cnt) {
         dw[i >> 5] = 0u;
         fw[fhash(i) >> 5] = 0u;
     }
-    if (P.inc && P.hblimb) {
-        // one wave per variable, its column 64 entries at a time; the wave
-        // clears the accumulators of each heavy row among them
-        const int lane = __lane_id();
-        const DInst &I = P.I;
-        unsigned long long junk = 0;
-        for (int t = threadIdx.x >> 6; t < cnt; t += WG / 64) {
-            const int i = P.dlist[(size_t)s * P.sn + t];
-            const int64_t c0 = I.col_ptr[i], c1 = I.col_ptr[i + 1];
-            for (int64_t e0 = c0; e0 < c1; e0 += 64) {
-                const int64_t e = e0 + lane;
-                const int h = e < c1 ? P.hidx[I.col_row[e]] : -1;
-                uint64_t hm = __ballot(h >= 0);
-                while (hm) {
-                    const int q = __ffsll((long long)hm) - 1;
-                    hm &= hm - 1;
-                    const size_t hs = (size_t)s * P.nheavy + __shfl(h, q, 64);
-                    unsigned long long *L = (unsigned long long *)(P.hacc + hs * 2 * HL);
-                    for (int j = lane; j < 2 * HL; j += 64) junk |= atomicExch(&L[j], 0ull);
-                    if (lane < 2) junk |= (unsigned long long)(uint32_t)atomicExch(&P.hinf[2 * hs + lane], 0);
-                }
-            }
-        }
-        // The clears are atomics like the next job's corrections, and their
-        // results are waited for here: they are done before the barrier.
-        asm volatile("" ::"v"(junk));
-    }
+    clear_heavy(P, s, cnt, threadIdx.x >> 6, WG / 64);
     __syncthreads();
     if (threadIdx.x == 0) P.dcount[s] = 0;
     __syncthreads();

@@ -532,7 +532,7 @@ extern "C" int bp_server_run(bp_server *sv, int32_t rounds, int32_t *busy) {
             k_rows<true><<<GRID_ROWS, WG, 0, cs>>>(sv->P);
             k_heavy<true><<<GRID_HEAVY, WG, 0, cs>>>(sv->P);
             k_apply<true><<<GRID_APPLY, WG, 0, cs>>>(sv->P);
-            k_end<<<1, WG, 0, cs>>>(sv->P);
+            k_end<END_WG><<<1, END_WG, 0, cs>>>(sv->P);
             k_retire<true><<<std::min(sv->slots, 4096), WG, 0, cs>>>(sv->P, sv->IO);
         }
         hipGraph_t g;
