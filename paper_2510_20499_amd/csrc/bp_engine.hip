@@ -729,6 +729,12 @@ static DInst dinst_of(const bp_instance *h) {
     I.vtype = h->vtype.as<uint8_t>();
     I.rbin = h->rbin.as<uint8_t>();
     I.base = h->base.as<double2>();
+    I.hidx = h->hidx_d.as<int32_t>();
+    I.cval = h->col_val.as<double>();
+    const bool hb = h->hb_version == h->base_version && h->hb_limb.p;
+    I.hblimb = hb ? h->hb_limb.as<long long>() : nullptr;
+    I.hbinf = hb ? h->hb_inf.as<int32_t>() : nullptr;
+    I.hbwid = hb ? h->hb_wid.as<double>() : nullptr;
     return I;
 }
 
@@ -1044,8 +1050,6 @@ static int propagate_slots(bp_instance *h, int32_t Bv, double *lb, double *ub,
             P.hacc = E1.hacc.as<long long>();
             P.hinf = E1.hinf.as<int32_t>();
             P.hwid = E1.hwid.as<unsigned long long>();
-            P.hidx = h->hidx_d.as<int32_t>();
-            P.cval = h->col_val.as<double>();
             P.hact = E1.hact.as<double2>();
             P.hcrec[0] = E1.hcrec[0].as<int4>();
             P.hcrec[1] = E1.hcrec[1].as<int4>();
@@ -1264,6 +1268,36 @@ __global__ void __launch_bounds__(WG) k_base_limbs(DInst I, const int32_t *hrows
     }
 }
 
+// The heavy rows of h at its base bounds (k_base_limbs), once per base.
+static int base_limbs(bp_instance *h, hipStream_t st) {
+    const int64_t H = h->bin_count[BIN_HEAVY];
+    if (h->hb_version == h->base_version) return 0;
+    if (H == 0) {
+        h->hb_version = h->base_version;  // nothing to sum
+        return 0;
+    }
+    if (int rc = h->hb_limb.grow((size_t)H * 2 * HL * 8, h->bytes)) return rc;
+    if (int rc = h->hb_inf.grow((size_t)H * 8, h->bytes)) return rc;
+    if (int rc = h->hb_wid.grow((size_t)H * 8, h->bytes)) return rc;
+    k_base_limbs<<<(int)std::min<int64_t>(H, 4096), WG, 0, st>>>(
+        dinst_of(h), h->cold_rows.as<int32_t>() + h->bin_start[BIN_HEAVY], (int32_t)H,
+        h->hb_limb.as<long long>(), h->hb_inf.as<int32_t>(), h->hb_wid.as<double>());
+    HIPTRY(hipGetLastError());
+    h->hb_version = h->base_version;
+    return 0;
+}
+
+// Incremental heavy rows over the base keep their limbs below carry_round's
+// 2^62: the base limbs hold at most L pieces below 2^32 per limb (a row of L
+// nonzeros), admission and each round of a job at most 2L more (old term
+// out, new term in, once per variable and side), so after a job's
+// r <= max_rounds rounds |limb| < L 2^32 (3 + 2r), in range while
+// L (3 + 2 max_rounds) < 2^30.
+static bool base_inc_ok(const bp_instance *h, int32_t max_rounds) {
+    const int64_t L = std::max<int64_t>(h->max_row_len, 1);
+    return L * (3 + 2 * (int64_t)max_rounds) < (int64_t(1) << 30);
+}
+
 // Probe variables must be integers with at least one finite base bound.
 __global__ void k_check_probe_vars(const int32_t *vars, int32_t k, int32_t n, const uint8_t *vtype,
                                    const double2 *base, int32_t *bad) {
@@ -1335,29 +1369,14 @@ extern "C" int bp_probe(bp_instance *h, const int32_t *vars, int32_t k, bp_probe
     }
     const int32_t S = (int32_t)std::min<int64_t>(std::max(1, h->opt.probe_slots), jobs);
     const int64_t H = h->bin_count[BIN_HEAVY];
-    // Incremental heavy rows over the base.  Limb bound: the base limbs
-    // hold at most L pieces below 2^32 (a row of L nonzeros), admission and
-    // each round of a job at most 2L more (old term out, new term in, once
-    // per variable and side), so after a job's r <= max_rounds rounds
-    // |limb| < L 2^32 (3 + 2r), below carry_round's 2^62 while
-    // L (3 + 2 max_rounds) < 2^30.  Otherwise, or with FULL_ROWS, each
-    // slot's heavy rows are summed chunk by chunk.
-    const int64_t Lmax = std::max<int64_t>(h->max_row_len, 1);
-    const bool inc = H > 0 && !(h->opt.flags & BP_FLAG_FULL_ROWS) &&
-                     Lmax * (3 + 2 * (int64_t)h->opt.max_rounds) < (int64_t(1) << 30);
+    // Incremental heavy rows over the base while their limbs stay in range;
+    // otherwise, or with FULL_ROWS, each slot's heavy rows are summed chunk
+    // by chunk.
+    const bool inc = H > 0 && !(h->opt.flags & BP_FLAG_FULL_ROWS) && base_inc_ok(h, h->opt.max_rounds);
     if (int rc = engine_ensure(h, S, true, st, inc)) return rc;
     Engine &E = *h->eng;
-    // The heavy rows at the base bounds, once per base.
-    if (inc && h->hb_version != h->base_version) {
-        if (int rc = h->hb_limb.grow((size_t)H * 2 * HL * 8, h->bytes)) return rc;
-        if (int rc = h->hb_inf.grow((size_t)H * 8, h->bytes)) return rc;
-        if (int rc = h->hb_wid.grow((size_t)H * 8, h->bytes)) return rc;
-        k_base_limbs<<<(int)std::min<int64_t>(H, 4096), WG, 0, st>>>(
-            dinst_of(h), h->cold_rows.as<int32_t>() + h->bin_start[BIN_HEAVY], (int32_t)H,
-            h->hb_limb.as<long long>(), h->hb_inf.as<int32_t>(), h->hb_wid.as<double>());
-        HIPTRY(hipGetLastError());
-        h->hb_version = h->base_version;
-    }
+    if (inc)
+        if (int rc = base_limbs(h, st)) return rc;
     // Probe slots read the base except where their dirty bits are set; a
     // retired probe clears its bits, so no slot needs initialising.
     // Staging for the implied lists.
@@ -1396,16 +1415,12 @@ extern "C" int bp_probe(bp_instance *h, const int32_t *vars, int32_t k, bp_probe
         P.hacc = E.hacc.as<long long>();
         P.hinf = E.hinf.as<int32_t>();
         P.hwid = E.hwid.as<unsigned long long>();
-        P.hidx = h->hidx_d.as<int32_t>();
-        P.cval = h->col_val.as<double>();
         P.hact = E.hact.as<double2>();
         P.hcrec[0] = E.hcrec[0].as<int4>();
         P.hcrec[1] = E.hcrec[1].as<int4>();
         P.inc_max = 0xffffffffu;  // never rebuilt
         P.inc_period = 0;
-        P.hblimb = h->hb_limb.as<long long>();
-        P.hbinf = h->hb_inf.as<int32_t>();
-        P.hbwid = h->hb_wid.as<double>();
+        P.inc_base = 1;
         if (!E.inc_clear) {
             HIPTRY(hipMemsetAsync(E.hacc.p, 0, (size_t)E.inc_cap * H * 2 * HL * 8, st));
             HIPTRY(hipMemsetAsync(E.hinf.p, 0, (size_t)E.inc_cap * H * 8, st));

@@ -66,6 +66,14 @@ struct DInst {
     const uint8_t *vtype;
     const uint8_t *rbin;
     const double2 *base;    // base bounds (jobs read them as an overlay)
+    // heavy rows (incremental activities)
+    const int32_t *hidx;    // [m] heavy index of a row, -1 for the others
+    const double *cval;     // [nnz] coefficients in column order
+    // the heavy rows at the base bounds (null until computed for the
+    // current base): limbs [H][2][HL], infinite counts [H][2], widths [H]
+    const long long *hblimb;
+    const int32_t *hbinf;
+    const double *hbwid;
 };
 
 // Per-slot bookkeeping.
@@ -230,24 +238,20 @@ struct Params {
     long long *hacc;             // [slot][nheavy][2][HL] limbs (min side, max side)
     int32_t *hinf;               // [slot][nheavy][2] infinite contributions
     unsigned long long *hwid;    // [slot][nheavy] slack-filter width bound (bits of a double >= 0)
-    const int32_t *hidx;         // [m] heavy index of a row, -1 for the others
-    const double *cval;          // [nnz] coefficients in column order
     double2 *hact;               // [slot][nheavy] the round's rounded (min, max) finite parts
     int4 *hcrec[2];              // chunk tasks of heavy rows whose head found candidates needed
     uint32_t inc_max;            // changed entries from which the next round rebuilds
     uint32_t inc_period;         // a rebuild at least every inc_period rounds, so that no
                                  // carry-save limb can reach 2^62 (see propagate_slots)
-    // Incremental heavy rows of job slots (one instance, overlays on the
+    // Incremental heavy rows of job slots (overlays on their instance's
     // base): a slot's limbs and infinite counts hold only the corrections of
     // its own bound changes, so a heavy row's activity is the base row's
-    // exact sum plus them.  Admission corrects for the job's first bounds,
-    // the update kernel for every later change, and a retired slot clears
-    // the rows of its changed variables.  Never rebuilt.
-    const long long *hblimb;     // [nheavy][2][HL] limbs of the base rows (null: limbs hold
-                                 // whole sums)
-    const int32_t *hbinf;        // [nheavy][2] infinite contributions at the base bounds
-    const double *hbwid;         // [nheavy] slack-filter widths at the base bounds (a job's
-                                 // bounds lie inside the base, so these bound its widths)
+    // exact sum (the instance's hblimb, hbinf) plus them, and the base width
+    // bounds its width (a job's bounds lie inside the base).  Admission
+    // corrects for the job's first bounds, the update kernel for every later
+    // change, and a retired slot clears the rows of its changed variables.
+    // Never rebuilt.
+    int32_t inc_base;
 };
 
 // Instance of slot s (MULTI: slots mix instances; otherwise the kernel
@@ -983,7 +987,7 @@ __device__ void inc_build_chunk(const Params &P, int par, uint32_t u, bool scan)
     if (wmax > 0.0) atomicMax(&wbits, (unsigned long long)__double_as_longlong(wmax));
     if (scan && __syncthreads_or(mine) && threadIdx.x == 0) atomicOr(&P.hhit[k], 1u);
     __syncthreads();
-    const size_t hs = (size_t)s * P.nheavy + P.hidx[k];
+    const size_t hs = (size_t)s * P.nheavy + P.I.hidx[k];
     long long *G = P.hacc + hs * 2 * HL;
     for (int j = threadIdx.x; j < 2 * HL; j += WG)
         if (L[j]) atomicAdd((unsigned long long *)&G[j], (unsigned long long)L[j]);
@@ -995,9 +999,9 @@ __device__ void inc_build_chunk(const Params &P, int par, uint32_t u, bool scan)
 }
 
 // The rounded finite parts of heavy row h (accumulators hs) by the whole
-// workgroup: limbs staged in LDS (the base row's limbs added for job slots),
-// one lane per side rounds them.
-__device__ double2 inc_row_activity(const Params &P, size_t hs, int h) {
+// workgroup: limbs staged in LDS (plus the base row's limbs blimb for job
+// slots), one lane per side rounds them.
+__device__ double2 inc_row_activity(const Params &P, size_t hs, const long long *blimb) {
     __shared__ long long L[2 * HL];
     __shared__ double act[2];
     __shared__ int range[4];  // lowest and highest nonzero limb of each side
@@ -1005,7 +1009,7 @@ __device__ double2 inc_row_activity(const Params &P, size_t hs, int h) {
     __syncthreads();
     for (int j = threadIdx.x; j < 2 * HL; j += WG) {
         long long v = P.hacc[hs * 2 * HL + j];
-        if (P.hblimb) v += P.hblimb[(size_t)h * 2 * HL + j];
+        if (blimb) v += blimb[j];
         L[j] = v;
         if (v) {
             const int side = j >= HL ? 2 : 0, d = j >= HL ? j - HL : j;
@@ -1025,13 +1029,13 @@ __device__ double2 inc_row_activity(const Params &P, size_t hs, int h) {
 // Infinite counts and slack-filter width of heavy row h (accumulators hs):
 // for job slots the base row's counts plus the slot's corrections, and the
 // base width.
-__device__ __forceinline__ void inc_counts(const Params &P, size_t hs, int h, RowAct &R) {
+__device__ __forceinline__ void inc_counts(const Params &P, const DInst &I, size_t hs, int h, RowAct &R) {
     R.nmin = P.hinf[2 * hs];
     R.nmax = P.hinf[2 * hs + 1];
-    if (P.hblimb) {
-        R.nmin += P.hbinf[2 * h];
-        R.nmax += P.hbinf[2 * h + 1];
-        R.rng = P.hbwid[h];
+    if (P.inc_base) {
+        R.nmin += I.hbinf[2 * h];
+        R.nmax += I.hbinf[2 * h + 1];
+        R.rng = I.hbwid[h];
     } else {
         R.rng = __longlong_as_double((long long)P.hwid[hs]);
     }
@@ -1042,22 +1046,24 @@ __device__ __forceinline__ void inc_counts(const Params &P, size_t hs, int h, Ro
 // It also tests the row: an infeasible row is reported, a quiet one ends
 // here, and only the chunks of the others become candidate tasks for the
 // heavy kernel, so a round whose heavy rows are all quiet leaves it idle.
+template <bool MULTI>
 __device__ void inc_head(const Params &P, int par, uint32_t u) {
     const int4 rec = P.hrec[par][u];
     const int s = rec.x, k = rec.y, c = rec.z, nch = rec.w;
     if (c != 0) return;  // workgroup-uniform
     if (threadIdx.x == 0) clear_rflag(P, s, k);
     if (P.info[s].state != SLOT_ACTIVE) return;  // workgroup-uniform
-    const int h = P.hidx[k];
+    const DInst I = inst_of<MULTI>(P, s);
+    const int h = I.hidx[k];
     const size_t hs = (size_t)s * P.nheavy + h;
-    const double2 a = inc_row_activity(P, hs, h);
+    const double2 a = inc_row_activity(P, hs, P.inc_base ? I.hblimb + (size_t)h * 2 * HL : nullptr);
     if (threadIdx.x == 0) {
         P.hact[hs] = a;
-        const double2 sd = P.I.side[k];
+        const double2 sd = I.side[k];
         RowAct R;
         R.minfin = a.x;
         R.maxfin = a.y;
-        inc_counts(P, hs, h, R);
+        inc_counts(P, I, hs, h, R);
         R.lo = sd.x;
         R.hi = sd.y;
         const bool bad = row_bad(R, P.feastol), quiet = !bad && row_quiet(R);
@@ -1065,7 +1071,7 @@ __device__ void inc_head(const Params &P, int par, uint32_t u) {
         if (P.touched) {  // byte accounting: tested from the accumulators
             atomicAdd(&P.ctl->stat_kept_rows, 1ull);
             if (bad || quiet)
-                atomicAdd(&P.ctl->stat_kept_nnz, (unsigned long long)(P.I.row_ptr[k + 1] - P.I.row_ptr[k]));
+                atomicAdd(&P.ctl->stat_kept_nnz, (unsigned long long)(I.row_ptr[k + 1] - I.row_ptr[k]));
         }
         if (!bad && !quiet) {
             const uint32_t at = atomicAdd(&P.ctl->hcand[par], (uint32_t)nch);
@@ -1113,10 +1119,10 @@ __device__ void heavy_chunk_candidates(const Params &P, int par, uint32_t u, boo
         // head in the row kernel, or here in a rebuild round (the row
         // kernel built them); the stored width bounds the current one
         // (bounds only shrink)
-        const int h = P.hidx[k];
+        const int h = I.hidx[k];
         const size_t hs = (size_t)s * P.nheavy + h;
-        inc_counts(P, hs, h, R);
-        const double2 a = rebuild ? inc_row_activity(P, hs, h) : P.hact[hs];
+        inc_counts(P, I, hs, h, R);
+        const double2 a = rebuild ? inc_row_activity(P, hs, nullptr) : P.hact[hs];
         R.minfin = a.x;
         R.maxfin = a.y;
     } else {
@@ -1220,7 +1226,7 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(BP_ROWS
     for (uint32_t u = blockIdx.x; u < total; u += gridDim.x) {
         if (u < start[1]) {
             if (P.inc && H.hbuild) inc_build_chunk(P, par, u, scan);
-            else if (P.inc) inc_head(P, par, u);
+            else if (P.inc) inc_head<MULTI>(P, par, u);
             else heavy_chunk_activity<MULTI>(P, par, u, W, scan);
         } else if (u < start[2]) {
             block_row<MULTI>(P, P.q[par][BIN_BLOCK], u - start[1], W,
@@ -1395,8 +1401,8 @@ __device__ void enqueue_columns(const Params &P, int par, bool want, int s, long
             rlen = rp1 - rp0;
             if (correct && bin == BIN_HEAVY) {
                 tot_corr += 1;
-                const double a = P.cval[e];
-                const size_t hs = (size_t)os * P.nheavy + P.hidx[k];
+                const double a = I.cval[e];
+                const size_t hs = (size_t)os * P.nheavy + I.hidx[k];
                 long long *Lh = P.hacc + hs * 2 * HL;
                 inc_move(Lh, &P.hinf[2 * hs], a, a > 0.0 ? obl : obu, a > 0.0 ? onl : onu);
                 inc_move(Lh + HL, &P.hinf[2 * hs + 1], a, a > 0.0 ? obu : obl, a > 0.0 ? onu : onl);
@@ -1973,17 +1979,25 @@ __device__ void stage_sorted(const Params &P, const JobIO &IO, int s, const DIns
 // its column 64 entries at a time.  The clears are atomics like the next
 // job's corrections, and their results are waited for: they are done when
 // the caller's next barrier is.
-__device__ void clear_heavy(const Params &P, int s, int cnt, int w0, int nw) {
-    if (!(P.inc && P.hblimb)) return;
+__device__ void clear_heavy(const Params &P, const DInst &I, int s, int cnt, int w0, int nw) {
+    if (!(P.inc && P.inc_base)) return;
     const int lane = __lane_id();
-    const DInst &I = P.I;
     unsigned long long junk = 0;
+    if (cnt >= P.nheavy) {
+        // a long list (a fixing job): every heavy row of the slot instead
+        const size_t n = (size_t)P.nheavy * 2 * HL, t0 = (size_t)w0 * 64 + lane, step = (size_t)nw * 64;
+        unsigned long long *L = (unsigned long long *)(P.hacc + (size_t)s * n);
+        for (size_t j = t0; j < n; j += step) junk |= atomicExch(&L[j], 0ull);
+        for (size_t j = t0; j < 2 * (size_t)P.nheavy; j += step)
+            junk |= (unsigned long long)(uint32_t)atomicExch(&P.hinf[(size_t)s * 2 * P.nheavy + j], 0);
+        cnt = 0;
+    }
     for (int t = w0; t < cnt; t += nw) {
         const int i = P.dlist[(size_t)s * P.sn + t];
         const int64_t c0 = I.col_ptr[i], c1 = I.col_ptr[i + 1];
         for (int64_t e0 = c0; e0 < c1; e0 += 64) {
             const int64_t e = e0 + lane;
-            const int h = e < c1 ? P.hidx[I.col_row[e]] : -1;
+            const int h = e < c1 ? I.hidx[I.col_row[e]] : -1;
             uint64_t hm = __ballot(h >= 0);
             while (hm) {
                 const int q = __ffsll((long long)hm) - 1;
@@ -1998,10 +2012,10 @@ __device__ void clear_heavy(const Params &P, int s, int cnt, int w0, int nw) {
     asm volatile("" ::"v"(junk));
 }
 
-// Forget the dirty variables of slot s: it reads the base again, and its
-// heavy-row corrections are cleared.  (Clearing them in two waves while the
-// others write the job's results was timed slower.)
-__device__ void restore_slot(const Params &P, int s, int cnt) {
+// Forget the dirty variables of slot s (instance I): it reads the base
+// again, and its heavy-row corrections are cleared.  (Clearing them in two
+// waves while the others write the job's results was timed slower.)
+__device__ void restore_slot(const Params &P, const DInst &I, int s, int cnt) {
     uint32_t *dw = P.dirty + (size_t)s * P.snw;
     uint32_t *fw = P.filt + (size_t)s * FILT_WORDS;
     for (int t = threadIdx.x; t < cnt; t += WG) {
@@ -2010,7 +2024,7 @@ __device__ void restore_slot(const Params &P, int s, int cnt) {
         dw[i >> 5] = 0u;
         fw[fhash(i) >> 5] = 0u;
     }
-    clear_heavy(P, s, cnt, threadIdx.x >> 6, WG / 64);
+    clear_heavy(P, I, s, cnt, threadIdx.x >> 6, WG / 64);
     __syncthreads();
     if (threadIdx.x == 0) P.dcount[s] = 0;
     __syncthreads();
@@ -2124,7 +2138,7 @@ __device__ bool admit_job(const Params &P, const JobIO &IO, int s, int p, int pa
     const int nd = probe ? 1 : dcount_now(P, s);
     if (R.badv != NONE) {  // a crossed box before the first round
         write_job(P, IO, p, 1, 0, 0ull, 0, -1, R.badv, 0, R);
-        restore_slot(P, s, nd);
+        restore_slot(P, I, s, nd);
         return false;
     }
     // The first round holds the rows of the changed variables; with
@@ -2176,7 +2190,7 @@ __device__ bool admit_job(const Params &P, const JobIO &IO, int s, int p, int pa
     // changed variables themselves.
     write_job(P, IO, p, 0, 0, 0ull, 0, -1, -1, nd, R);
     stage_sorted(P, IO, s, I, nd, R);
-    restore_slot(P, s, nd);
+    restore_slot(P, I, s, nd);
     return false;
 }
 
@@ -2213,7 +2227,7 @@ __global__ void __launch_bounds__(WG) k_retire(Params P, JobIO IO) {
             }
             write_job(P, IO, p, status, S.rounds, S.nnz, nbad, brow, bvar, cnt, R, pre);
             if (cnt > 0) stage_sorted(P, IO, s, I, cnt, R);
-            restore_slot(P, s, dcnt);
+            restore_slot(P, I, s, dcnt);
             if (threadIdx.x == 0) S.retire = 0;
             __syncthreads();
         }

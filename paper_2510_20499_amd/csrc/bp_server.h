@@ -74,6 +74,7 @@ struct bp_server {
     DevBuf dinst;
     int32_t slots = 0;
     int64_t bytes_per_slot = 0;
+    bool inc = false;  // incremental heavy rows over each instance's base
     // device job storage
     DevBuf jobs, fix_var, fix_box, r_status, r_rounds, r_nnz, r_nbad, r_brow, r_bvar, r_soff, r_scnt;
     DevBuf stage_var, stage_lb, stage_ub, ring, collect;
@@ -108,8 +109,9 @@ struct bp_server {
 // keep reading it).
 constexpr int64_t SERVER_MAX_INSTANCES = 4096;
 
-// Device bytes one slot of shape `sh` needs (the engine's per-slot arrays).
-static int64_t slot_bytes(const Shape &sh) {
+// Device bytes one slot of shape `sh` needs (the engine's per-slot arrays;
+// inc: with incremental heavy-row accumulators).
+static int64_t slot_bytes(const Shape &sh, bool inc) {
     int64_t n = std::max<int64_t>(sh.sn, 1), m = std::max<int64_t>(sh.sm, 1);
     int64_t nw = (n + 31) / 32, mw = (m + 31) / 32;
     int64_t b = 16 * n + 16 * n + 8 * n + 4 * n;   // bounds, candidates, changed list, dirty list
@@ -117,6 +119,7 @@ static int64_t slot_bytes(const Shape &sh) {
     b += 4 * FILT_WORDS + (int64_t)sizeof(SlotInfo) + 4;
     for (int q = 0; q < BIN_HEAVY; ++q) b += 2 * 8 * sh.bin_cap[q];
     b += 2 * 16 * sh.heavy_chunks + 64 * sh.heavy_chunks + 8 * sh.heavy_chunks;
+    if (inc) b += sh.heavy_rows * (2 * HL * 8 + 8 + 8 + 16) + 2 * 16 * sh.heavy_chunks;
     return b;
 }
 
@@ -152,16 +155,23 @@ extern "C" int bp_server_create(bp_instance *const *instances, int32_t count, co
     }
     sv->inst_open.assign(sv->insts.size(), 0);
     sv->shape = sh;
-    sv->bytes_per_slot = slot_bytes(sh);
+    // Heavy rows of the slots keep exact corrections over their instance's
+    // base row when every served instance keeps the limbs in range;
+    // otherwise (or with FULL_ROWS) they are summed chunk by chunk.
+    sv->inc = sh.heavy_rows > 0 && !(sv->opt.flags & BP_FLAG_FULL_ROWS);
+    for (bp_instance *h : sv->insts) sv->inc = sv->inc && base_inc_ok(h, sv->opt.max_rounds);
+    sv->bytes_per_slot = slot_bytes(sh, sv->inc);
     int64_t fit = budget_bytes / sv->bytes_per_slot;
     sv->slots = (int32_t)std::min<int64_t>(fit, std::max(1, sv->opt.probe_slots));
     if (sv->slots < 1) return fail(BP_ENOMEM, "budget smaller than one slot (" +
                                                   std::to_string(sv->bytes_per_slot) + " bytes)");
     hipStream_t st = sv->st;
-    if (int rc = engine_alloc(sv->eng, sh, sv->slots, true, false, st)) return rc;
+    if (int rc = engine_alloc(sv->eng, sh, sv->slots, true, false, st, sv->inc)) return rc;
     // instance table and host copies for request validation
     std::vector<DInst> tab;
     for (bp_instance *h : sv->insts) {
+        if (sv->inc)
+            if (int rc = base_limbs(h, st)) return rc;
         tab.push_back(dinst_of(h));
         std::vector<uint8_t> vt(h->n);
         std::vector<double2> bs(h->n);
@@ -222,6 +232,24 @@ extern "C" int bp_server_create(bp_instance *const *instances, int32_t count, co
     P.useen = nullptr;  // row ids repeat across instances
     P.insts = sv->dinst.as<DInst>();
     P.overlay = 1;
+    if (sv->inc) {
+        Engine &E = *sv->eng;
+        P.inc = 1;
+        P.nheavy = (int32_t)sh.heavy_rows;
+        P.inc_slots = sv->slots;
+        P.hacc = E.hacc.as<long long>();
+        P.hinf = E.hinf.as<int32_t>();
+        P.hwid = E.hwid.as<unsigned long long>();
+        P.hact = E.hact.as<double2>();
+        P.hcrec[0] = E.hcrec[0].as<int4>();
+        P.hcrec[1] = E.hcrec[1].as<int4>();
+        P.inc_max = 0xffffffffu;  // never rebuilt
+        P.inc_period = 0;
+        P.inc_base = 1;
+        // retired jobs clear their own corrections from here on
+        HIPTRY(hipMemsetAsync(E.hacc.p, 0, (size_t)sv->slots * sh.heavy_rows * 2 * HL * 8, st));
+        HIPTRY(hipMemsetAsync(E.hinf.p, 0, (size_t)sv->slots * sh.heavy_rows * 8, st));
+    }
     sv->P = P;
     Ctl c;
     memset(&c, 0, sizeof(c));
@@ -257,6 +285,8 @@ extern "C" int bp_server_add_instance(bp_server *sv, bp_instance *h, int32_t *in
         if (o == h) return fail(BP_EINVAL, "instance already served");
     if (!sv->shape.covers(shape_of(h)))
         return fail(BP_ECAPACITY, "instance larger than the server's slots");
+    if (sv->inc && !base_inc_ok(h, sv->opt.max_rounds))
+        return fail(BP_ECAPACITY, "instance rows too long for the server's heavy-row accumulators");
     int32_t t = 0;
     while (t < (int32_t)sv->insts.size() && sv->insts[t]) ++t;
     if (t >= sv->cap_insts) return fail(BP_ECAPACITY, "instance table full");
@@ -267,6 +297,8 @@ extern "C" int bp_server_add_instance(bp_server *sv, bp_instance *h, int32_t *in
         HIPTRY(hipMemcpyAsync(vt.data(), h->vtype.p, h->n, hipMemcpyDeviceToHost, st));
         HIPTRY(hipMemcpyAsync(bs.data(), h->base.p, (size_t)h->n * 16, hipMemcpyDeviceToHost, st));
     }
+    if (sv->inc)
+        if (int rc = base_limbs(h, st)) return rc;
     const DInst d = dinst_of(h);
     HIPTRY(hipMemcpyAsync(sv->dinst.as<DInst>() + t, &d, sizeof(DInst), hipMemcpyHostToDevice, st));
     HIPTRY(hipStreamSynchronize(st));
@@ -520,6 +552,17 @@ extern "C" int bp_server_run(bp_server *sv, int32_t rounds, int32_t *busy) {
     g_err.clear();
     if (!sv || rounds < 0) return fail(BP_EINVAL, "bp_server_run: bad argument");
     hipStream_t st = sv->st;
+    if (sv->inc) {
+        // an instance whose base moved since its base rows were summed gets
+        // them again (the stream is idle between graph launches)
+        for (size_t t = 0; t < sv->insts.size(); ++t) {
+            bp_instance *h = sv->insts[t];
+            if (!h || h->hb_version == h->base_version) continue;
+            if (int rc = base_limbs(h, st)) return rc;
+            const DInst d = dinst_of(h);
+            HIPTRY(hipMemcpyAsync(sv->dinst.as<DInst>() + t, &d, sizeof(DInst), hipMemcpyHostToDevice, st));
+        }
+    }
     if (int rc = server_append(sv)) return rc;
     const int K = std::max(1, (int)sv->opt.rounds_per_launch);
     if (!sv->graph || sv->graph_rounds != K) {

@@ -85,8 +85,8 @@ def _same(a, b, inst, what, evidence=False):
     assert rel_close(np.asarray(a["ub"])[~integ], np.asarray(b["ub"])[~integ]), what
 
 
-def _serve(loaded, reqs, budget, rounds_per_step=8, waves=1):
-    S = bp().Server(loaded, budget)
+def _serve(loaded, reqs, budget, rounds_per_step=8, waves=1, opts=None):
+    S = bp().Server(loaded, budget, opts)
     ids = []
     # submit in `waves` batches, running between them (requests arrive
     # while others are on the device)
@@ -126,6 +126,36 @@ def test_serving_mix_matches_oracle_and_alone():
         _, alone, _ = _serve(loaded, [reqs[j]], budget=64 << 20)
         _same(alone[0], mix[j], insts[reqs[j][0]], "alone%d" % j,
               evidence=reqs[j][1] == bp().REQ_PROPAGATE)
+
+
+@pytest.mark.parametrize("full_rows", [False, True])
+def test_serving_heavy_rows_incremental_and_full(full_rows):
+    """Heavy rows of serving slots keep exact corrections over their
+    instance's base rows (cleared per changed variable when a probe
+    retires, all at once after a long fixing list), or, with FULL_ROWS, are
+    summed chunk by chunk; both match the oracle on a pool of six slots
+    that every slot reuses for many jobs."""
+    insts, loaded, bases = _instances()
+    reqs = _requests(insts, bases, 40, seed=21)
+    t = 4  # the instance with heavy rows (5 rows over the threshold of 2048)
+    inst = insts[t]
+    lb, ub = bases[t]
+    assert (np.diff(inst["row_ptr"]) > 2048).sum() >= 5
+    ints = np.nonzero((inst["vtype"] == 1) & (lb < ub))[0]
+    rng = np.random.default_rng(5)
+    for _ in range(6):
+        vs = np.sort(rng.choice(ints, size=min(400, ints.size), replace=False)).astype(np.int32)
+        val = np.rint(rng.uniform(lb[vs], ub[vs]))
+        reqs.append((t, bp().REQ_PROPAGATE, vs, val, val))
+    opts = bp().default_options(heavy_threshold=2048)
+    if full_rows:
+        opts.flags |= bp().FLAG_FULL_ROWS
+    per_slot = bp().Server(loaded, 1 << 40, opts).info()["bytes_per_slot"]
+    S, out, done = _serve(loaded, reqs, budget=6 * per_slot, waves=3, opts=opts)
+    assert S.info()["slots"] == 6
+    for j, req in enumerate(reqs):
+        want = _oracle_result(insts[req[0]], bases[req[0]], req)
+        _same(out[j], want, insts[req[0]], "req%d" % j, evidence=req[1] == bp().REQ_PROPAGATE)
 
 
 def test_serving_small_pool_and_validation():
