@@ -1086,6 +1086,8 @@ def bench_serving(args, bp, gen, torch, np):
     S.close()
     log("serving: instances resident, %d requests, %d slots of %d bytes"
         % (len(reqs), info["slots"], info["bytes_per_slot"]))
+    for q, pl in enumerate(info["pools"]):
+        log("  pool %d: %d instances, %d slots of %d bytes" % (q, pl["instances"], pl["slots"], pl["bytes_per_slot"]))
 
     def run_trace(arrivals):
         """arrivals: seconds from start (None: all at once).  Returns
@@ -1145,7 +1147,7 @@ def bench_serving(args, bp, gen, torch, np):
                        % (len(insts), args.serve_mmax, nnz_total, len(reqs)),
            "sha256_of_instance_digests": __import__("hashlib").sha256(
                "".join(inst_sha256(x) for x in insts).encode()).hexdigest(),
-           "slots": info["slots"], "bytes_per_slot": info["bytes_per_slot"],
+           "slots": info["slots"], "bytes_per_slot": info["bytes_per_slot"], "pools": info["pools"],
            "generate_s": t_gen, "saturated_requests_per_s": C,
            "saturated_p50_ms": float(np.percentile(lat_sat, 50)) / 1e3,
            "saturated_p99_ms": float(np.percentile(lat_sat, 99)) / 1e3}

@@ -512,24 +512,31 @@ typedef struct {
 #define BP_COMPLETION_CANCELLED 1  /* taken out of the queue before it ran */
 
 /* Create a server over `count` loaded instances, each with a base (a
- * feasible bp_propagate was run on it; BP_ESTATE otherwise).  The slot pool
- * holds as many bound vectors as fit in `budget_bytes` of device memory,
- * at most opt->probe_slots (opt NULL: the first instance's options).  Every
- * slot is sized for the largest instance (its variables, rows, row bins and
- * heavy chunks), so a request holds one slot whatever its instance: the
- * budget bounds the slot pool, not each request's own footprint.  The
- * request queue and the result staging (about 1.2 GB: 2^21 jobs, 2^24
- * fixings, 2^25 staged implications) are allocated beside the budget.  The
- * instances must outlive the server, or their eviction (bp_server_evict). */
+ * feasible bp_propagate was run on it; BP_ESTATE otherwise).  Instances are
+ * grouped into at most four classes by their number of variables (a class
+ * spans a factor of r = max(8, (n_max / n_min)^(1/3.5)) from its smallest
+ * instance), and each class gets a pool of slots sized for its own largest
+ * instance (variables, rows, row bins and heavy chunks), so a request holds
+ * a slot of its class's footprint.  `budget_bytes` of device memory are
+ * shared out from the pool with the smallest slots up, each taking at most
+ * its fair share of what is left and at most opt->probe_slots slots (opt
+ * NULL: the first instance's options).  If that leaves a pool fewer than
+ * min(16, probe_slots) slots, all instances share one pool of slots sized
+ * for the largest.  Pools run side by side on streams of their own (the
+ * first on `stream`).  Each pool's request queue and result staging (about
+ * 1.2 GB: 2^21 jobs, 2^24 fixings, 2^25 staged implications) are allocated
+ * beside the budget.  The instances must outlive the server, or their
+ * eviction (bp_server_evict). */
 int bp_server_create(bp_instance *const *instances, int32_t count, const bp_options *opt,
                      int64_t budget_bytes, void *stream, bp_server **out);
 
 /* Serve one more loaded instance (with a base; BP_ESTATE otherwise) under
- * the next free index (*index; an evicted instance's index is reused).
- * BP_ECAPACITY if the instance does not fit the slots sized at creation
- * (more variables, rows, row-bin tasks or heavy chunks than the largest
- * instance then) or the table of 4096 instances is full; BP_EINVAL for a
- * different heavy chunk size or an instance already served. */
+ * the next free index (*index; an evicted instance's index is reused), in
+ * the pool with the smallest slots that hold it.  BP_ECAPACITY if no pool's
+ * slots, sized at creation, hold it (more variables, rows, row-bin tasks or
+ * heavy chunks than a pool's largest instance then) or the table of 4096
+ * instances is full; BP_EINVAL for a different heavy chunk size or an
+ * instance already served. */
 int bp_server_add_instance(bp_server *sv, bp_instance *instance, int32_t *index);
 
 /* Stop serving instance `index`: later requests for it get BP_EINVAL, and
@@ -573,8 +580,17 @@ int bp_server_results(bp_server *sv, int64_t id, int8_t *status, int32_t *rounds
                       int32_t *n_bad_rows, int32_t *bad_row, int32_t *bad_var, int64_t *off,
                       int32_t *var, double *lb, double *ub, int64_t cap, int64_t *required);
 
-/* Slots in the pool and device bytes per slot. */
+/* Slots over all pools, and the device bytes of a slot sized for every
+ * served instance (the slot of a one-pool server: a budget of k times it
+ * gives such a server k slots). */
 int bp_server_info(const bp_server *sv, int32_t *slots, int64_t *bytes_per_slot);
+
+/* The server's pools: *npools receives their number (if not NULL); for
+ * 0 <= pool < npools, its slots, device bytes per slot and the number of
+ * instances it serves (outputs may be NULL).  BP_EINVAL for another pool
+ * index when an output other than npools is asked for. */
+int bp_server_pool_info(const bp_server *sv, int32_t pool, int32_t *npools, int32_t *slots,
+                        int64_t *bytes_per_slot, int32_t *instances);
 
 void bp_server_destroy(bp_server *sv);
 

@@ -26,7 +26,7 @@ FLAG_LV_DENSE = 64
 EXPORTS = ["bp_options_default", "bp_load", "bp_propagate", "bp_propagate_batch", "bp_probe",
            "bp_get_base", "bp_kernel_stats", "bp_device_bytes", "bp_free", "bp_last_error",
            "bp_server_create", "bp_server_submit", "bp_server_run", "bp_server_poll",
-           "bp_server_results", "bp_server_info", "bp_server_destroy", "bp_autotune",
+           "bp_server_results", "bp_server_info", "bp_server_pool_info", "bp_server_destroy", "bp_autotune",
            "bp_scores", "bp_probe_order", "bp_round", "bp_scores_noalloc", "bp_repair",
            "bp_autotune_batch", "bp_debug_fail_alloc", "bp_server_cancel", "bp_server_expire",
            "bp_server_add_instance", "bp_server_evict"]
@@ -181,6 +181,9 @@ def load_library(path: str = LIB_PATH):
     lib.bp_server_results.restype = C.c_int
     lib.bp_server_info.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
     lib.bp_server_info.restype = C.c_int
+    lib.bp_server_pool_info.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                        C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
+    lib.bp_server_pool_info.restype = C.c_int
     lib.bp_autotune.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                 C.c_char_p, C.POINTER(Tuning), C.c_void_p]
     lib.bp_autotune.restype = C.c_int
@@ -496,9 +499,18 @@ class Server:
             pass
 
     def info(self):
+        """Slots over all pools, bytes of a slot sized for every instance,
+        and per pool its slots, bytes per slot and instances."""
         s, b = C.c_int32(), C.c_int64()
         _check(_LIB.bp_server_info(self._h, C.byref(s), C.byref(b)))
-        return dict(slots=s.value, bytes_per_slot=b.value)
+        npools = C.c_int32()
+        _check(_LIB.bp_server_pool_info(self._h, -1, C.byref(npools), None, None, None))
+        pools = []
+        for q in range(npools.value):
+            ps, pb, pi = C.c_int32(), C.c_int64(), C.c_int32()
+            _check(_LIB.bp_server_pool_info(self._h, q, None, C.byref(ps), C.byref(pb), C.byref(pi)))
+            pools.append(dict(slots=ps.value, bytes_per_slot=pb.value, instances=pi.value))
+        return dict(slots=s.value, bytes_per_slot=b.value, pools=pools)
 
     def submit(self, instance: int, kind: int, vars_, lb=None, ub=None) -> int:
         v = np.ascontiguousarray(vars_, dtype=np.int32)

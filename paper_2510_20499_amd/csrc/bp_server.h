@@ -1,16 +1,20 @@
 // bp_server.h -- continuous-batching server (part of bp_engine.hip's
 // translation unit; see include/bp.h for the C ABI).
 //
-// All requests become jobs in one device job list: a probe request of k
-// binaries is 2k probe jobs, a propagate request is one fixing job.  One
-// engine whose slots may hold any of the server's instances runs them: each
-// round's kernels process the tasks of every busy slot, and k_retire
-// writes finished jobs' results, restores their slots and admits the next
-// jobs.  The host appends newly submitted requests between graph launches
-// and collects finished jobs from a completion ring.
+// Requests become jobs: a probe request of k binaries is 2k probe jobs, a
+// propagate request is one fixing job.  The served instances are grouped
+// into classes by size, and each class has its own pool: an engine whose
+// slots are sized for the class's largest instance, a device job list, a
+// completion ring and a stream.  Each round's kernels of a pool process the
+// tasks of its busy slots, and k_retire writes finished jobs' results,
+// restores their slots and admits the next jobs.  The host appends newly
+// submitted requests to their pool's list between graph launches, runs the
+// pools' graphs side by side on their streams, and collects finished jobs
+// from the rings.
 #pragma once
 #include <chrono>
 #include <deque>
+#include <numeric>
 #include <unordered_map>
 
 struct JobOut {
@@ -62,19 +66,17 @@ struct ServerReq {
     std::vector<std::vector<double>> llb, lub;
 };
 
-struct bp_server {
-    std::vector<bp_instance *> insts;  // nullptr: evicted
-    std::vector<int64_t> inst_open;    // unfinished requests per instance
-    Shape shape;                       // the slot shape every instance must fit
-    int64_t cap_insts = 0;             // entries of the device instance table
-    bp_options opt;
-    int32_t heavy_chunk = 1024;
-    hipStream_t st = nullptr;
-    std::unique_ptr<Engine> eng;
-    DevBuf dinst;
+// One slot pool: an engine whose slots hold any instance of its class, its
+// job storage, launch parameters, captured rounds and stream.
+struct ServerPool {
+    Shape shape;                 // the slot shape (its class's largest instance)
     int32_t slots = 0;
     int64_t bytes_per_slot = 0;
-    bool inc = false;  // incremental heavy rows over each instance's base
+    bool inc = false;            // incremental heavy rows over each instance's base
+    int32_t members = 0;         // instances served by this pool
+    hipStream_t st = nullptr;
+    bool own_stream = false;
+    std::unique_ptr<Engine> eng;
     // device job storage
     DevBuf jobs, fix_var, fix_box, r_status, r_rounds, r_nnz, r_nbad, r_brow, r_bvar, r_soff, r_scnt;
     DevBuf stage_var, stage_lb, stage_ub, ring, collect;
@@ -83,8 +85,29 @@ struct bp_server {
     uint32_t ring_seen = 0;
     std::vector<int64_t> job_req;   // device job -> request id
     std::vector<int32_t> job_local; // device job -> index within its request
+    std::deque<int64_t> pending;    // requests waiting for room in the job list
+    Params P;
+    JobIO IO;
+    hipGraphExec_t graph = nullptr;
+    int graph_rounds = 0;
+    ~ServerPool() {
+        if (graph) (void)hipGraphExecDestroy(graph);
+        if (own_stream && st) (void)hipStreamDestroy(st);
+    }
+};
+
+struct bp_server {
+    std::vector<bp_instance *> insts;  // nullptr: evicted
+    std::vector<int64_t> inst_open;    // unfinished requests per instance
+    std::vector<int32_t> inst_pool;    // pool of each instance
+    int64_t cap_insts = 0;             // entries of the device instance table
+    bp_options opt;
+    int32_t heavy_chunk = 1024;
+    hipStream_t st = nullptr;          // the caller's stream (the first pool's)
+    DevBuf dinst;
+    std::vector<std::unique_ptr<ServerPool>> pools;
+    int64_t one_pool_bytes = 0;        // bytes of a slot sized for every instance
     // host side
-    std::deque<int64_t> pending;
     std::unordered_map<int64_t, ServerReq> reqs;
     std::deque<int64_t> completed;
     int64_t next_id = 1;
@@ -92,13 +115,6 @@ struct bp_server {
     std::vector<std::vector<uint8_t>> vtype;   // host copies for validation
     std::vector<std::vector<double2>> base;
     std::chrono::steady_clock::time_point t0;
-    Params P;
-    JobIO IO;
-    hipGraphExec_t graph = nullptr;
-    int graph_rounds = 0;
-    ~bp_server() {
-        if (graph) (void)hipGraphExecDestroy(graph);
-    }
     double now_us() const {
         return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
     }
@@ -108,6 +124,9 @@ struct bp_server {
 // creation take free entries; the table never moves, so captured graphs
 // keep reading it).
 constexpr int64_t SERVER_MAX_INSTANCES = 4096;
+// Classes of instances, at most one stream each (the device's hardware
+// queues run them side by side).
+constexpr int SERVER_MAX_POOLS = 4;
 
 // Device bytes one slot of shape `sh` needs (the engine's per-slot arrays;
 // inc: with incremental heavy-row accumulators).
@@ -123,6 +142,163 @@ static int64_t slot_bytes(const Shape &sh, bool inc) {
     return b;
 }
 
+static Shape shape_union(const Shape &a, const Shape &b) {
+    Shape s;
+    s.sn = std::max(a.sn, b.sn);
+    s.sm = std::max(a.sm, b.sm);
+    for (int q = 0; q < NBIN; ++q) s.bin_cap[q] = std::max(a.bin_cap[q], b.bin_cap[q]);
+    s.heavy_chunks = std::max(a.heavy_chunks, b.heavy_chunks);
+    s.heavy_rows = std::max(a.heavy_rows, b.heavy_rows);
+    return s;
+}
+
+struct PoolPlan {
+    std::vector<int32_t> members;
+    Shape shape;
+    bool inc = false;
+    int64_t bytes = 0;
+    int32_t slots = 0;
+};
+
+// Heavy rows of a pool keep exact corrections over their instance's base
+// rows when every member keeps the limbs in range; otherwise (or with
+// FULL_ROWS) they are summed chunk by chunk.
+static void plan_finish(PoolPlan &p, const std::vector<bp_instance *> &insts, const bp_options &opt) {
+    Shape sh;
+    for (int32_t t : p.members) sh = shape_union(sh, shape_of(insts[t]));
+    p.shape = sh;
+    p.inc = sh.heavy_rows > 0 && !(opt.flags & BP_FLAG_FULL_ROWS);
+    for (int32_t t : p.members) p.inc = p.inc && base_inc_ok(insts[t], opt.max_rounds);
+    p.bytes = slot_bytes(sh, p.inc);
+}
+
+// The pools of a server.  Split: instances sorted by variables form classes
+// of up to r times the class's smallest, r = max(8, (n_max / n_min)^(1/3.5)),
+// so at most four.  The budget is shared out from the smallest slots up:
+// each pool takes at most its fair share of what is left, and at most
+// opt.probe_slots slots.
+static std::vector<PoolPlan> plan_pools(const std::vector<bp_instance *> &insts, const bp_options &opt,
+                                        int64_t budget, bool split) {
+    std::vector<int32_t> order(insts.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return insts[a]->n < insts[b]->n; });
+    std::vector<PoolPlan> plans;
+    if (split) {
+        const double nmin = std::max(1, insts[order.front()]->n), nmax = std::max(1, insts[order.back()]->n);
+        const double r = std::max(8.0, std::pow(nmax / nmin, 1.0 / 3.5));
+        for (int32_t t : order) {
+            if (plans.empty() || (double)insts[t]->n > r * std::max(1, insts[plans.back().members[0]]->n))
+                plans.emplace_back();
+            plans.back().members.push_back(t);
+        }
+    } else {
+        plans.emplace_back();
+        plans.back().members = order;
+    }
+    for (PoolPlan &p : plans) plan_finish(p, insts, opt);
+    std::stable_sort(plans.begin(), plans.end(), [](const PoolPlan &a, const PoolPlan &b) { return a.bytes < b.bytes; });
+    const int64_t cap = std::max(1, opt.probe_slots);
+    int64_t left = budget;
+    for (size_t i = 0; i < plans.size(); ++i) {
+        const int64_t share = left / (int64_t)(plans.size() - i);
+        plans[i].slots = (int32_t)std::min<int64_t>(cap, share / plans[i].bytes);
+        left -= (int64_t)plans[i].slots * plans[i].bytes;
+    }
+    return plans;
+}
+
+// Allocate a pool's engine and job storage and set its launch parameters.
+static int pool_create(bp_server *sv, ServerPool &pl, const PoolPlan &plan, bool first) {
+    pl.shape = plan.shape;
+    pl.slots = plan.slots;
+    pl.bytes_per_slot = plan.bytes;
+    pl.inc = plan.inc;
+    pl.members = (int32_t)plan.members.size();
+    if (first) {
+        pl.st = sv->st;
+    } else {
+        HIPTRY(hipStreamCreateWithFlags(&pl.st, hipStreamNonBlocking));
+        pl.own_stream = true;
+    }
+    hipStream_t st = pl.st;
+    if (int rc = engine_alloc(pl.eng, pl.shape, pl.slots, true, false, st, pl.inc)) return rc;
+    int64_t dummy = 0;
+    pl.cap_jobs = 1 << 21;
+    pl.cap_fix = 1 << 24;
+    pl.cap_stage = 1 << 25;
+    const int64_t J = pl.cap_jobs;
+    int rc;
+    if ((rc = pl.jobs.alloc(J * sizeof(Job), dummy))) return rc;
+    if ((rc = pl.fix_var.alloc(pl.cap_fix * 4, dummy))) return rc;
+    if ((rc = pl.fix_box.alloc(pl.cap_fix * 16, dummy))) return rc;
+    if ((rc = pl.r_status.alloc(J, dummy))) return rc;
+    if ((rc = pl.r_rounds.alloc(J * 4, dummy))) return rc;
+    if ((rc = pl.r_nnz.alloc(J * 8, dummy))) return rc;
+    if ((rc = pl.r_nbad.alloc(J * 4, dummy))) return rc;
+    if ((rc = pl.r_brow.alloc(J * 4, dummy))) return rc;
+    if ((rc = pl.r_bvar.alloc(J * 4, dummy))) return rc;
+    if ((rc = pl.r_soff.alloc(J * 8, dummy))) return rc;
+    if ((rc = pl.r_scnt.alloc(J * 8, dummy))) return rc;
+    if ((rc = pl.stage_var.alloc(pl.cap_stage * 4, dummy))) return rc;
+    if ((rc = pl.stage_lb.alloc(pl.cap_stage * 8, dummy))) return rc;
+    if ((rc = pl.stage_ub.alloc(pl.cap_stage * 8, dummy))) return rc;
+    if ((rc = pl.ring.alloc(J * 4, dummy))) return rc;
+    if ((rc = pl.collect.alloc(J * sizeof(JobOut), dummy))) return rc;
+    JobIO &IO = pl.IO;
+    memset(&IO, 0, sizeof(IO));
+    IO.jobs = pl.jobs.as<Job>();
+    IO.fix_var = pl.fix_var.as<int32_t>();
+    IO.fix_box = pl.fix_box.as<double2>();
+    IO.status = pl.r_status.as<int8_t>();
+    IO.rounds = pl.r_rounds.as<int32_t>();
+    IO.nnz = pl.r_nnz.as<int64_t>();
+    IO.n_bad_rows = pl.r_nbad.as<int32_t>();
+    IO.bad_row = pl.r_brow.as<int32_t>();
+    IO.bad_var = pl.r_bvar.as<int32_t>();
+    IO.stage_off = pl.r_soff.as<int64_t>();
+    IO.stage_cnt = pl.r_scnt.as<int64_t>();
+    IO.stage_var = pl.stage_var.as<int32_t>();
+    IO.stage_lb = pl.stage_lb.as<double>();
+    IO.stage_ub = pl.stage_ub.as<double>();
+    IO.stage_cap = pl.cap_stage;
+    IO.done_ring = pl.ring.as<uint32_t>();
+    Params P = engine_params(*pl.eng, sv->opt, sv->heavy_chunk, pl.slots);
+    P.I = dinst_of(sv->insts[plan.members[0]]);
+    P.multi = 1;
+    P.useen = nullptr;  // row ids repeat across instances
+    P.insts = sv->dinst.as<DInst>();
+    P.overlay = 1;
+    if (pl.inc) {
+        Engine &E = *pl.eng;
+        P.inc = 1;
+        P.nheavy = (int32_t)pl.shape.heavy_rows;
+        P.inc_slots = pl.slots;
+        P.hacc = E.hacc.as<long long>();
+        P.hinf = E.hinf.as<int32_t>();
+        P.hwid = E.hwid.as<unsigned long long>();
+        P.hact = E.hact.as<double2>();
+        P.hcrec[0] = E.hcrec[0].as<int4>();
+        P.hcrec[1] = E.hcrec[1].as<int4>();
+        P.inc_max = 0xffffffffu;  // never rebuilt
+        P.inc_period = 0;
+        P.inc_base = 1;
+        // retired jobs clear their own corrections from here on
+        HIPTRY(hipMemsetAsync(E.hacc.p, 0, (size_t)pl.slots * pl.shape.heavy_rows * 2 * HL * 8, st));
+        HIPTRY(hipMemsetAsync(E.hinf.p, 0, (size_t)pl.slots * pl.shape.heavy_rows * 8, st));
+    }
+    pl.P = P;
+    Ctl c;
+    memset(&c, 0, sizeof(c));
+    c.max_rounds = (uint32_t)sv->opt.max_rounds;
+    c.nslots = (uint32_t)pl.slots;
+    c.done = 1;
+    HIPTRY(hipMemcpyAsync(P.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, st));
+    k_reset_slots<<<grid_for(pl.slots), 256, 0, st>>>(P.info, pl.slots, 0, SLOT_FREE);
+    HIPTRY(hipGetLastError());
+    return 0;
+}
+
 extern "C" int bp_server_create(bp_instance *const *instances, int32_t count, const bp_options *opt,
                                 int64_t budget_bytes, void *stream, bp_server **out) {
     BP_RANGE("bp_server_create");
@@ -136,7 +312,6 @@ extern "C" int bp_server_create(bp_instance *const *instances, int32_t count, co
     sv->opt = opt ? *opt : instances[0]->opt;
     if (int rc = validate_options(sv->opt)) return rc;
     if (sv->opt.rounds_per_launch <= 0) sv->opt.rounds_per_launch = 16;
-    Shape sh;
     for (int32_t t = 0; t < count; ++t) {
         bp_instance *h = instances[t];
         if (!h) return fail(BP_EINVAL, "bp_server_create: null instance");
@@ -145,33 +320,39 @@ extern "C" int bp_server_create(bp_instance *const *instances, int32_t count, co
         if (t == 0) sv->heavy_chunk = h->heavy_chunk;
         else if (h->heavy_chunk != sv->heavy_chunk)
             return fail(BP_EINVAL, "instances must share the heavy chunk size");
-        Shape s1 = shape_of(h);
-        sh.sn = std::max(sh.sn, s1.sn);
-        sh.sm = std::max(sh.sm, s1.sm);
-        for (int b = 0; b < NBIN; ++b) sh.bin_cap[b] = std::max(sh.bin_cap[b], s1.bin_cap[b]);
-        sh.heavy_chunks = std::max(sh.heavy_chunks, s1.heavy_chunks);
-        sh.heavy_rows = std::max(sh.heavy_rows, s1.heavy_rows);
         sv->insts.push_back(h);
     }
     sv->inst_open.assign(sv->insts.size(), 0);
-    sv->shape = sh;
-    // Heavy rows of the slots keep exact corrections over their instance's
-    // base row when every served instance keeps the limbs in range;
-    // otherwise (or with FULL_ROWS) they are summed chunk by chunk.
-    sv->inc = sh.heavy_rows > 0 && !(sv->opt.flags & BP_FLAG_FULL_ROWS);
-    for (bp_instance *h : sv->insts) sv->inc = sv->inc && base_inc_ok(h, sv->opt.max_rounds);
-    sv->bytes_per_slot = slot_bytes(sh, sv->inc);
-    int64_t fit = budget_bytes / sv->bytes_per_slot;
-    sv->slots = (int32_t)std::min<int64_t>(fit, std::max(1, sv->opt.probe_slots));
-    if (sv->slots < 1) return fail(BP_ENOMEM, "budget smaller than one slot (" +
-                                                  std::to_string(sv->bytes_per_slot) + " bytes)");
+    // Pools by class; when the budget leaves a class fewer than
+    // min(16, probe_slots) slots, every instance shares one pool.
+    std::vector<PoolPlan> plans = plan_pools(sv->insts, sv->opt, budget_bytes, true);
+    const int32_t least = std::min(16, std::max(1, sv->opt.probe_slots));
+    for (const PoolPlan &p : plans)
+        if (plans.size() > 1 && p.slots < least) {
+            plans = plan_pools(sv->insts, sv->opt, budget_bytes, false);
+            break;
+        }
+    {
+        PoolPlan all;
+        all.members.resize(sv->insts.size());
+        std::iota(all.members.begin(), all.members.end(), 0);
+        plan_finish(all, sv->insts, sv->opt);
+        sv->one_pool_bytes = all.bytes;
+    }
+    if (plans[0].slots < 1 || plans.back().slots < 1)
+        return fail(BP_ENOMEM, "budget smaller than one slot (" + std::to_string(plans.back().bytes) + " bytes)");
     hipStream_t st = sv->st;
-    if (int rc = engine_alloc(sv->eng, sh, sv->slots, true, false, st, sv->inc)) return rc;
+    // the heavy rows of the pools that keep them incrementally, then the
     // instance table and host copies for request validation
+    sv->inst_pool.assign(sv->insts.size(), 0);
+    for (size_t q = 0; q < plans.size(); ++q)
+        for (int32_t t : plans[q].members) {
+            sv->inst_pool[t] = (int32_t)q;
+            if (plans[q].inc)
+                if (int rc = base_limbs(sv->insts[t], st)) return rc;
+        }
     std::vector<DInst> tab;
     for (bp_instance *h : sv->insts) {
-        if (sv->inc)
-            if (int rc = base_limbs(h, st)) return rc;
         tab.push_back(dinst_of(h));
         std::vector<uint8_t> vt(h->n);
         std::vector<double2> bs(h->n);
@@ -186,80 +367,12 @@ extern "C" int bp_server_create(bp_instance *const *instances, int32_t count, co
     sv->cap_insts = std::max<int64_t>((int64_t)tab.size(), SERVER_MAX_INSTANCES);
     if (int rc = sv->dinst.alloc((size_t)sv->cap_insts * sizeof(DInst), dummy)) return rc;
     HIPTRY(hipMemcpyAsync(sv->dinst.p, tab.data(), tab.size() * sizeof(DInst), hipMemcpyHostToDevice, st));
-    // job storage
-    sv->cap_jobs = 1 << 21;
-    sv->cap_fix = 1 << 24;
-    sv->cap_stage = 1 << 25;
-    const int64_t J = sv->cap_jobs;
-    int rc;
-    if ((rc = sv->jobs.alloc(J * sizeof(Job), dummy))) return rc;
-    if ((rc = sv->fix_var.alloc(sv->cap_fix * 4, dummy))) return rc;
-    if ((rc = sv->fix_box.alloc(sv->cap_fix * 16, dummy))) return rc;
-    if ((rc = sv->r_status.alloc(J, dummy))) return rc;
-    if ((rc = sv->r_rounds.alloc(J * 4, dummy))) return rc;
-    if ((rc = sv->r_nnz.alloc(J * 8, dummy))) return rc;
-    if ((rc = sv->r_nbad.alloc(J * 4, dummy))) return rc;
-    if ((rc = sv->r_brow.alloc(J * 4, dummy))) return rc;
-    if ((rc = sv->r_bvar.alloc(J * 4, dummy))) return rc;
-    if ((rc = sv->r_soff.alloc(J * 8, dummy))) return rc;
-    if ((rc = sv->r_scnt.alloc(J * 8, dummy))) return rc;
-    if ((rc = sv->stage_var.alloc(sv->cap_stage * 4, dummy))) return rc;
-    if ((rc = sv->stage_lb.alloc(sv->cap_stage * 8, dummy))) return rc;
-    if ((rc = sv->stage_ub.alloc(sv->cap_stage * 8, dummy))) return rc;
-    if ((rc = sv->ring.alloc(J * 4, dummy))) return rc;
-    if ((rc = sv->collect.alloc(J * sizeof(JobOut), dummy))) return rc;
-    JobIO &IO = sv->IO;
-    memset(&IO, 0, sizeof(IO));
-    IO.jobs = sv->jobs.as<Job>();
-    IO.fix_var = sv->fix_var.as<int32_t>();
-    IO.fix_box = sv->fix_box.as<double2>();
-    IO.status = sv->r_status.as<int8_t>();
-    IO.rounds = sv->r_rounds.as<int32_t>();
-    IO.nnz = sv->r_nnz.as<int64_t>();
-    IO.n_bad_rows = sv->r_nbad.as<int32_t>();
-    IO.bad_row = sv->r_brow.as<int32_t>();
-    IO.bad_var = sv->r_bvar.as<int32_t>();
-    IO.stage_off = sv->r_soff.as<int64_t>();
-    IO.stage_cnt = sv->r_scnt.as<int64_t>();
-    IO.stage_var = sv->stage_var.as<int32_t>();
-    IO.stage_lb = sv->stage_lb.as<double>();
-    IO.stage_ub = sv->stage_ub.as<double>();
-    IO.stage_cap = sv->cap_stage;
-    IO.done_ring = sv->ring.as<uint32_t>();
-    Params P = engine_params(*sv->eng, sv->opt, sv->heavy_chunk, sv->slots);
-    P.I = tab[0];
-    P.multi = 1;
-    P.useen = nullptr;  // row ids repeat across instances
-    P.insts = sv->dinst.as<DInst>();
-    P.overlay = 1;
-    if (sv->inc) {
-        Engine &E = *sv->eng;
-        P.inc = 1;
-        P.nheavy = (int32_t)sh.heavy_rows;
-        P.inc_slots = sv->slots;
-        P.hacc = E.hacc.as<long long>();
-        P.hinf = E.hinf.as<int32_t>();
-        P.hwid = E.hwid.as<unsigned long long>();
-        P.hact = E.hact.as<double2>();
-        P.hcrec[0] = E.hcrec[0].as<int4>();
-        P.hcrec[1] = E.hcrec[1].as<int4>();
-        P.inc_max = 0xffffffffu;  // never rebuilt
-        P.inc_period = 0;
-        P.inc_base = 1;
-        // retired jobs clear their own corrections from here on
-        HIPTRY(hipMemsetAsync(E.hacc.p, 0, (size_t)sv->slots * sh.heavy_rows * 2 * HL * 8, st));
-        HIPTRY(hipMemsetAsync(E.hinf.p, 0, (size_t)sv->slots * sh.heavy_rows * 8, st));
-    }
-    sv->P = P;
-    Ctl c;
-    memset(&c, 0, sizeof(c));
-    c.max_rounds = (uint32_t)sv->opt.max_rounds;
-    c.nslots = (uint32_t)sv->slots;
-    c.done = 1;
-    HIPTRY(hipMemcpyAsync(P.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, st));
-    k_reset_slots<<<grid_for(sv->slots), 256, 0, st>>>(P.info, sv->slots, 0, SLOT_FREE);
-    HIPTRY(hipGetLastError());
     HIPTRY(hipStreamSynchronize(st));
+    for (size_t q = 0; q < plans.size(); ++q) {
+        sv->pools.emplace_back(new ServerPool());
+        if (int rc = pool_create(sv.get(), *sv->pools.back(), plans[q], q == 0)) return rc;
+    }
+    for (auto &pl : sv->pools) HIPTRY(hipStreamSynchronize(pl->st));
     sv->t0 = std::chrono::steady_clock::now();
     *out = sv.release();
     return BP_OK;
@@ -269,8 +382,25 @@ extern "C" void bp_server_destroy(bp_server *sv) { delete sv; }
 
 extern "C" int bp_server_info(const bp_server *sv, int32_t *slots, int64_t *bytes_per_slot) {
     if (!sv) return fail(BP_EINVAL, "bp_server_info: null server");
-    if (slots) *slots = sv->slots;
-    if (bytes_per_slot) *bytes_per_slot = sv->bytes_per_slot;
+    int32_t tot = 0;
+    for (const auto &pl : sv->pools) tot += pl->slots;
+    if (slots) *slots = tot;
+    if (bytes_per_slot) *bytes_per_slot = sv->one_pool_bytes;
+    return BP_OK;
+}
+
+extern "C" int bp_server_pool_info(const bp_server *sv, int32_t pool, int32_t *npools, int32_t *slots,
+                                   int64_t *bytes_per_slot, int32_t *instances) {
+    if (!sv) return fail(BP_EINVAL, "bp_server_pool_info: null server");
+    if (npools) *npools = (int32_t)sv->pools.size();
+    if (pool < 0 || pool >= (int32_t)sv->pools.size()) {
+        if (slots || bytes_per_slot || instances) return fail(BP_EINVAL, "bp_server_pool_info: no such pool");
+        return BP_OK;
+    }
+    const ServerPool &pl = *sv->pools[pool];
+    if (slots) *slots = pl.slots;
+    if (bytes_per_slot) *bytes_per_slot = pl.bytes_per_slot;
+    if (instances) *instances = pl.members;
     return BP_OK;
 }
 
@@ -283,10 +413,15 @@ extern "C" int bp_server_add_instance(bp_server *sv, bp_instance *h, int32_t *in
     if (h->heavy_chunk != sv->heavy_chunk) return fail(BP_EINVAL, "instances must share the heavy chunk size");
     for (bp_instance *o : sv->insts)
         if (o == h) return fail(BP_EINVAL, "instance already served");
-    if (!sv->shape.covers(shape_of(h)))
-        return fail(BP_ECAPACITY, "instance larger than the server's slots");
-    if (sv->inc && !base_inc_ok(h, sv->opt.max_rounds))
-        return fail(BP_ECAPACITY, "instance rows too long for the server's heavy-row accumulators");
+    // the pool with the smallest slots that hold it
+    int32_t q = -1;
+    for (size_t c = 0; c < sv->pools.size(); ++c) {
+        const ServerPool &pl = *sv->pools[c];
+        if (!pl.shape.covers(shape_of(h))) continue;
+        if (pl.inc && !base_inc_ok(h, sv->opt.max_rounds)) continue;
+        if (q < 0 || pl.bytes_per_slot < sv->pools[q]->bytes_per_slot) q = (int32_t)c;
+    }
+    if (q < 0) return fail(BP_ECAPACITY, "instance larger than the server's slots");
     int32_t t = 0;
     while (t < (int32_t)sv->insts.size() && sv->insts[t]) ++t;
     if (t >= sv->cap_insts) return fail(BP_ECAPACITY, "instance table full");
@@ -297,7 +432,7 @@ extern "C" int bp_server_add_instance(bp_server *sv, bp_instance *h, int32_t *in
         HIPTRY(hipMemcpyAsync(vt.data(), h->vtype.p, h->n, hipMemcpyDeviceToHost, st));
         HIPTRY(hipMemcpyAsync(bs.data(), h->base.p, (size_t)h->n * 16, hipMemcpyDeviceToHost, st));
     }
-    if (sv->inc)
+    if (sv->pools[q]->inc)
         if (int rc = base_limbs(h, st)) return rc;
     const DInst d = dinst_of(h);
     HIPTRY(hipMemcpyAsync(sv->dinst.as<DInst>() + t, &d, sizeof(DInst), hipMemcpyHostToDevice, st));
@@ -305,14 +440,17 @@ extern "C" int bp_server_add_instance(bp_server *sv, bp_instance *h, int32_t *in
     if (t == (int32_t)sv->insts.size()) {
         sv->insts.push_back(h);
         sv->inst_open.push_back(0);
+        sv->inst_pool.push_back(q);
         sv->vtype.push_back(std::move(vt));
         sv->base.push_back(std::move(bs));
     } else {
         sv->insts[t] = h;
         sv->inst_open[t] = 0;
+        sv->inst_pool[t] = q;
         sv->vtype[t] = std::move(vt);
         sv->base[t] = std::move(bs);
     }
+    sv->pools[q]->members += 1;
     *index = t;
     return BP_OK;
 }
@@ -324,15 +462,18 @@ extern "C" int bp_server_evict(bp_server *sv, int32_t index) {
     if (sv->inst_open[index] > 0)
         return fail(BP_ESTATE, "instance " + std::to_string(index) + " has unfinished requests");
     sv->insts[index] = nullptr;
+    sv->pools[sv->inst_pool[index]]->members -= 1;
     // The launch parameters name one instance as the default descriptor;
-    // point them at a served one (the graph is captured again) so nothing
+    // point them at a served one (the graphs are captured again) so nothing
     // refers to an instance its owner may now free.
     for (bp_instance *o : sv->insts) {
         if (!o) continue;
-        sv->P.I = dinst_of(o);
-        if (sv->graph) {
-            (void)hipGraphExecDestroy(sv->graph);
-            sv->graph = nullptr;
+        for (auto &pl : sv->pools) {
+            pl->P.I = dinst_of(o);
+            if (pl->graph) {
+                (void)hipGraphExecDestroy(pl->graph);
+                pl->graph = nullptr;
+            }
         }
         break;
     }
@@ -354,8 +495,9 @@ extern "C" int bp_server_submit(bp_server *sv, const bp_request *req, int64_t *i
         return fail(BP_EINVAL, "propagate request without bounds");
     const bp_instance *h = sv->insts[req->instance];
     if (!h) return fail(BP_EINVAL, "instance " + std::to_string(req->instance) + " was evicted");
+    ServerPool &pl = *sv->pools[sv->inst_pool[req->instance]];
     const int64_t njobs = req->kind == BP_REQ_PROBE ? 2 * (int64_t)req->count : 1;
-    if (njobs > sv->cap_jobs || (req->kind == BP_REQ_PROPAGATE && req->count > sv->cap_fix))
+    if (njobs > pl.cap_jobs || (req->kind == BP_REQ_PROPAGATE && req->count > pl.cap_fix))
         return fail(BP_EINVAL, "request larger than the server's job storage");
     std::vector<int32_t> seen;
     seen.assign(req->vars, req->vars + req->count);
@@ -400,25 +542,25 @@ extern "C" int bp_server_submit(bp_server *sv, const bp_request *req, int64_t *i
         sv->reqs.emplace(R.id, std::move(R));
         return BP_OK;
     }
-    sv->pending.push_back(R.id);
+    pl.pending.push_back(R.id);
     sv->inst_open[R.inst] += 1;
     sv->reqs.emplace(R.id, std::move(R));
     sv->unfinished += 1;
     return BP_OK;
 }
 
-// Copy queued requests into the device job list while it has room.
-static int server_append(bp_server *sv) {
-    hipStream_t st = sv->st;
+// Copy a pool's queued requests into its device job list while it has room.
+static int server_append(bp_server *sv, ServerPool &pl) {
+    hipStream_t st = pl.st;
     // The job list is rewound whenever every job on it has finished.
-    if (sv->njobs_dev > 0 && sv->ring_seen == (uint32_t)sv->njobs_dev && !sv->pending.empty()) {
-        sv->njobs_dev = 0;
-        sv->nfix_dev = 0;
-        sv->ring_seen = 0;
-        sv->job_req.clear();
-        sv->job_local.clear();
+    if (pl.njobs_dev > 0 && pl.ring_seen == (uint32_t)pl.njobs_dev && !pl.pending.empty()) {
+        pl.njobs_dev = 0;
+        pl.nfix_dev = 0;
+        pl.ring_seen = 0;
+        pl.job_req.clear();
+        pl.job_local.clear();
         uint32_t zeros[4] = {0, 0, 0, 0};
-        Ctl *C = sv->P.ctl;
+        Ctl *C = pl.P.ctl;
         HIPTRY(hipMemcpyAsync(&C->next_job, zeros, 12, hipMemcpyHostToDevice, st));  // next, total, done_jobs
         unsigned long long z = 0;
         HIPTRY(hipMemcpyAsync(&C->stage_count, &z, 8, hipMemcpyHostToDevice, st));
@@ -426,11 +568,11 @@ static int server_append(bp_server *sv) {
     std::vector<Job> nj;
     std::vector<int32_t> fv;
     std::vector<double2> fb;
-    while (!sv->pending.empty()) {
-        ServerReq &R = sv->reqs[sv->pending.front()];
+    while (!pl.pending.empty()) {
+        ServerReq &R = sv->reqs[pl.pending.front()];
         int64_t nfix = R.kind == BP_REQ_PROPAGATE ? R.count : 0;
-        if (sv->njobs_dev + (int64_t)nj.size() + R.njobs > sv->cap_jobs) break;
-        if (sv->nfix_dev + (int64_t)fv.size() + nfix > sv->cap_fix) break;
+        if (pl.njobs_dev + (int64_t)nj.size() + R.njobs > pl.cap_jobs) break;
+        if (pl.nfix_dev + (int64_t)fv.size() + nfix > pl.cap_fix) break;
         for (int32_t j = 0; j < R.njobs; ++j) {
             Job J;
             J.inst = R.inst;
@@ -440,7 +582,7 @@ static int server_append(bp_server *sv) {
                 J.b = j & 1;
             } else {
                 J.kind = JOB_FIX;
-                J.a = (int32_t)(sv->nfix_dev + (int64_t)fv.size());
+                J.a = (int32_t)(pl.nfix_dev + (int64_t)fv.size());
                 J.b = R.count;
                 for (int32_t t = 0; t < R.count; ++t) {
                     fv.push_back(R.vars[t]);
@@ -448,61 +590,61 @@ static int server_append(bp_server *sv) {
                 }
             }
             nj.push_back(J);
-            sv->job_req.push_back(R.id);
-            sv->job_local.push_back(j);
+            pl.job_req.push_back(R.id);
+            pl.job_local.push_back(j);
         }
         R.on_device = true;
-        sv->pending.pop_front();
+        pl.pending.pop_front();
     }
     if (nj.empty()) return 0;
     // Claims past the end of the list took no job; lower the counter to the
     // old end so the appended jobs are claimed (the stream is idle here).
     {
         uint32_t next = 0;
-        HIPTRY(hipMemcpyAsync(&next, &sv->P.ctl->next_job, 4, hipMemcpyDeviceToHost, st));
+        HIPTRY(hipMemcpyAsync(&next, &pl.P.ctl->next_job, 4, hipMemcpyDeviceToHost, st));
         HIPTRY(hipStreamSynchronize(st));
-        if (next > (uint32_t)sv->njobs_dev) {
-            uint32_t old_end = (uint32_t)sv->njobs_dev;
-            HIPTRY(hipMemcpyAsync(&sv->P.ctl->next_job, &old_end, 4, hipMemcpyHostToDevice, st));
+        if (next > (uint32_t)pl.njobs_dev) {
+            uint32_t old_end = (uint32_t)pl.njobs_dev;
+            HIPTRY(hipMemcpyAsync(&pl.P.ctl->next_job, &old_end, 4, hipMemcpyHostToDevice, st));
         }
     }
-    HIPTRY(hipMemcpyAsync(sv->jobs.as<Job>() + sv->njobs_dev, nj.data(), nj.size() * sizeof(Job),
+    HIPTRY(hipMemcpyAsync(pl.jobs.as<Job>() + pl.njobs_dev, nj.data(), nj.size() * sizeof(Job),
                           hipMemcpyHostToDevice, st));
     if (!fv.empty()) {
-        HIPTRY(hipMemcpyAsync(sv->fix_var.as<int32_t>() + sv->nfix_dev, fv.data(), fv.size() * 4,
+        HIPTRY(hipMemcpyAsync(pl.fix_var.as<int32_t>() + pl.nfix_dev, fv.data(), fv.size() * 4,
                               hipMemcpyHostToDevice, st));
-        HIPTRY(hipMemcpyAsync(sv->fix_box.as<double2>() + sv->nfix_dev, fb.data(), fb.size() * 16,
+        HIPTRY(hipMemcpyAsync(pl.fix_box.as<double2>() + pl.nfix_dev, fb.data(), fb.size() * 16,
                               hipMemcpyHostToDevice, st));
     }
-    sv->njobs_dev += (int64_t)nj.size();
-    sv->nfix_dev += (int64_t)fv.size();
-    uint32_t tot = (uint32_t)sv->njobs_dev;
-    HIPTRY(hipMemcpyAsync(&sv->P.ctl->total_jobs, &tot, 4, hipMemcpyHostToDevice, st));
+    pl.njobs_dev += (int64_t)nj.size();
+    pl.nfix_dev += (int64_t)fv.size();
+    uint32_t tot = (uint32_t)pl.njobs_dev;
+    HIPTRY(hipMemcpyAsync(&pl.P.ctl->total_jobs, &tot, 4, hipMemcpyHostToDevice, st));
     // the claims the last round end assigned predate these jobs
     const uint32_t no_claims = 0;
-    HIPTRY(hipMemcpyAsync(&sv->P.ctl->claims, &no_claims, 4, hipMemcpyHostToDevice, st));
+    HIPTRY(hipMemcpyAsync(&pl.P.ctl->claims, &no_claims, 4, hipMemcpyHostToDevice, st));
     // Admit right away, then recompute the done flag.
-    k_retire<true><<<std::min(sv->slots, 4096), WG, 0, st>>>(sv->P, sv->IO);
-    k_jobs_done_check<<<1, 256, 0, st>>>(sv->P);
+    k_retire<true><<<std::min(pl.slots, 4096), WG, 0, st>>>(pl.P, pl.IO);
+    k_jobs_done_check<<<1, 256, 0, st>>>(pl.P);
     HIPTRY(hipGetLastError());
     return 0;
 }
 
-// Gather finished jobs from the completion ring and finish requests.
-static int server_collect(bp_server *sv) {
-    hipStream_t st = sv->st;
+// Gather a pool's finished jobs from its completion ring and finish requests.
+static int server_collect(bp_server *sv, ServerPool &pl) {
+    hipStream_t st = pl.st;
     Ctl hc;
-    HIPTRY(hipMemcpyAsync(&hc, sv->P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    HIPTRY(hipMemcpyAsync(&hc, pl.P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     HIPTRY(hipStreamSynchronize(st));
-    const uint32_t r0 = sv->ring_seen, r1 = hc.done_jobs;
+    const uint32_t r0 = pl.ring_seen, r1 = hc.done_jobs;
     if (r1 == r0) return 0;
-    if (hc.stage_count > (unsigned long long)sv->cap_stage)
+    if (hc.stage_count > (unsigned long long)pl.cap_stage)
         return fail(BP_ECAPACITY, "server implication storage exceeded");
     const int64_t nr = r1 - r0;
-    k_collect<<<grid_for(nr), 256, 0, st>>>(sv->IO, sv->ring.as<uint32_t>(), r0, r1, sv->collect.as<JobOut>());
+    k_collect<<<grid_for(nr), 256, 0, st>>>(pl.IO, pl.ring.as<uint32_t>(), r0, r1, pl.collect.as<JobOut>());
     HIPTRY(hipGetLastError());
     std::vector<JobOut> got(nr);
-    HIPTRY(hipMemcpyAsync(got.data(), sv->collect.p, nr * sizeof(JobOut), hipMemcpyDeviceToHost, st));
+    HIPTRY(hipMemcpyAsync(got.data(), pl.collect.p, nr * sizeof(JobOut), hipMemcpyDeviceToHost, st));
     // their lists form one contiguous range of the stage
     int64_t s0 = INT64_MAX, s1 = 0;
     HIPTRY(hipStreamSynchronize(st));
@@ -519,15 +661,15 @@ static int server_collect(bp_server *sv) {
         sv_var.resize(c);
         sv_lb.resize(c);
         sv_ub.resize(c);
-        HIPTRY(hipMemcpyAsync(sv_var.data(), sv->stage_var.as<int32_t>() + s0, c * 4, hipMemcpyDeviceToHost, st));
-        HIPTRY(hipMemcpyAsync(sv_lb.data(), sv->stage_lb.as<double>() + s0, c * 8, hipMemcpyDeviceToHost, st));
-        HIPTRY(hipMemcpyAsync(sv_ub.data(), sv->stage_ub.as<double>() + s0, c * 8, hipMemcpyDeviceToHost, st));
+        HIPTRY(hipMemcpyAsync(sv_var.data(), pl.stage_var.as<int32_t>() + s0, c * 4, hipMemcpyDeviceToHost, st));
+        HIPTRY(hipMemcpyAsync(sv_lb.data(), pl.stage_lb.as<double>() + s0, c * 8, hipMemcpyDeviceToHost, st));
+        HIPTRY(hipMemcpyAsync(sv_ub.data(), pl.stage_ub.as<double>() + s0, c * 8, hipMemcpyDeviceToHost, st));
         HIPTRY(hipStreamSynchronize(st));
     }
     const double t = sv->now_us();
     for (const JobOut &o : got) {
-        ServerReq &R = sv->reqs[sv->job_req[o.job]];
-        int32_t j = sv->job_local[o.job];
+        ServerReq &R = sv->reqs[pl.job_req[o.job]];
+        int32_t j = pl.job_local[o.job];
         R.out[j] = o;
         if (o.stage_cnt > 0) {
             int64_t a = o.stage_off - s0;
@@ -543,7 +685,32 @@ static int server_collect(bp_server *sv) {
             sv->inst_open[R.inst] -= 1;
         }
     }
-    sv->ring_seen = r1;
+    pl.ring_seen = r1;
+    return 0;
+}
+
+static int pool_graph(bp_server *sv, ServerPool &pl) {
+    const int K = std::max(1, (int)sv->opt.rounds_per_launch);
+    if (pl.graph && pl.graph_rounds == K) return 0;
+    if (pl.graph) (void)hipGraphExecDestroy(pl.graph);
+    pl.graph = nullptr;
+    hipStream_t cs;
+    HIPTRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    HIPTRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    for (int r = 0; r < K; ++r) {
+        k_rows<true><<<GRID_ROWS, WG, 0, cs>>>(pl.P);
+        k_heavy<true><<<GRID_HEAVY, WG, 0, cs>>>(pl.P);
+        k_apply<true><<<GRID_APPLY, WG, 0, cs>>>(pl.P);
+        k_end<END_WG><<<1, END_WG, 0, cs>>>(pl.P);
+        k_retire<true><<<std::min(pl.slots, 4096), WG, 0, cs>>>(pl.P, pl.IO);
+    }
+    hipGraph_t g;
+    HIPTRY(hipStreamEndCapture(cs, &g));
+    hipError_t e = hipGraphInstantiate(&pl.graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    HIPTRY(e);
+    pl.graph_rounds = K;
     return 0;
 }
 
@@ -552,54 +719,50 @@ extern "C" int bp_server_run(bp_server *sv, int32_t rounds, int32_t *busy) {
     g_err.clear();
     if (!sv || rounds < 0) return fail(BP_EINVAL, "bp_server_run: bad argument");
     hipStream_t st = sv->st;
-    if (sv->inc) {
+    {
         // an instance whose base moved since its base rows were summed gets
-        // them again (the stream is idle between graph launches)
+        // them again (every pool's stream is idle between runs)
+        bool moved = false;
         for (size_t t = 0; t < sv->insts.size(); ++t) {
             bp_instance *h = sv->insts[t];
-            if (!h || h->hb_version == h->base_version) continue;
+            if (!h || !sv->pools[sv->inst_pool[t]]->inc || h->hb_version == h->base_version) continue;
             if (int rc = base_limbs(h, st)) return rc;
             const DInst d = dinst_of(h);
             HIPTRY(hipMemcpyAsync(sv->dinst.as<DInst>() + t, &d, sizeof(DInst), hipMemcpyHostToDevice, st));
+            moved = true;
         }
+        if (moved) HIPTRY(hipStreamSynchronize(st));
     }
-    if (int rc = server_append(sv)) return rc;
+    for (auto &pl : sv->pools) {
+        if (int rc = server_append(sv, *pl)) return rc;
+        if (int rc = pool_graph(sv, *pl)) return rc;
+    }
     const int K = std::max(1, (int)sv->opt.rounds_per_launch);
-    if (!sv->graph || sv->graph_rounds != K) {
-        if (sv->graph) (void)hipGraphExecDestroy(sv->graph);
-        sv->graph = nullptr;
-        hipStream_t cs;
-        HIPTRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-        HIPTRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        for (int r = 0; r < K; ++r) {
-            k_rows<true><<<GRID_ROWS, WG, 0, cs>>>(sv->P);
-            k_heavy<true><<<GRID_HEAVY, WG, 0, cs>>>(sv->P);
-            k_apply<true><<<GRID_APPLY, WG, 0, cs>>>(sv->P);
-            k_end<END_WG><<<1, END_WG, 0, cs>>>(sv->P);
-            k_retire<true><<<std::min(sv->slots, 4096), WG, 0, cs>>>(sv->P, sv->IO);
-        }
-        hipGraph_t g;
-        HIPTRY(hipStreamEndCapture(cs, &g));
-        hipError_t e = hipGraphInstantiate(&sv->graph, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        (void)hipStreamDestroy(cs);
-        HIPTRY(e);
-        sv->graph_rounds = K;
-    }
+    std::vector<char> live(sv->pools.size());
     for (int32_t r = 0; r < rounds; r += K) {
-        HIPTRY(hipGraphLaunch(sv->graph, st));
-        if (int rc = server_collect(sv)) return rc;
-        if (int rc = server_append(sv)) return rc;
+        // the pools with jobs on the device run side by side
+        for (size_t q = 0; q < sv->pools.size(); ++q) {
+            ServerPool &pl = *sv->pools[q];
+            live[q] = pl.njobs_dev > (int64_t)pl.ring_seen;
+            if (live[q]) HIPTRY(hipGraphLaunch(pl.graph, pl.st));
+        }
+        for (size_t q = 0; q < sv->pools.size(); ++q) {
+            if (!live[q]) continue;
+            if (int rc = server_collect(sv, *sv->pools[q])) return rc;
+            if (int rc = server_append(sv, *sv->pools[q])) return rc;
+        }
     }
     if (rounds == 0)
-        if (int rc = server_collect(sv)) return rc;
+        for (auto &pl : sv->pools)
+            if (int rc = server_collect(sv, *pl)) return rc;
     if (busy) *busy = (int32_t)sv->unfinished;
     return BP_OK;
 }
 
-// Take a request that still waits in the host queue out of it; it
+// Take a request that still waits in its pool's host queue out of it; it
 // finishes at once as cancelled.
-static void server_cancel_pending(bp_server *sv, std::deque<int64_t>::iterator at, double t) {
+static void server_cancel_pending(bp_server *sv, std::deque<int64_t> &q, std::deque<int64_t>::iterator at,
+                                  double t) {
     ServerReq &R = sv->reqs[*at];
     R.cancelled = true;
     R.done = true;
@@ -607,7 +770,7 @@ static void server_cancel_pending(bp_server *sv, std::deque<int64_t>::iterator a
     sv->completed.push_back(R.id);
     sv->unfinished -= 1;
     sv->inst_open[R.inst] -= 1;
-    sv->pending.erase(at);
+    q.erase(at);
 }
 
 extern "C" int bp_server_cancel(bp_server *sv, int64_t id) {
@@ -618,9 +781,10 @@ extern "C" int bp_server_cancel(bp_server *sv, int64_t id) {
     const ServerReq &R = it->second;
     if (R.done || R.on_device)
         return fail(BP_ESTATE, R.done ? "request has finished" : "request's jobs are on the device");
-    auto at = std::find(sv->pending.begin(), sv->pending.end(), id);
-    if (at == sv->pending.end()) return fail(BP_ESTATE, "request is not queued");
-    server_cancel_pending(sv, at, sv->now_us());
+    std::deque<int64_t> &q = sv->pools[sv->inst_pool[R.inst]]->pending;
+    auto at = std::find(q.begin(), q.end(), id);
+    if (at == q.end()) return fail(BP_ESTATE, "request is not queued");
+    server_cancel_pending(sv, q, at, sv->now_us());
     return BP_OK;
 }
 
@@ -629,14 +793,17 @@ extern "C" int bp_server_expire(bp_server *sv, double max_wait_us, int32_t *n) {
     if (!sv || !(max_wait_us >= 0.0)) return fail(BP_EINVAL, "bp_server_expire: bad argument");
     const double t = sv->now_us();
     int32_t k = 0;
-    for (auto at = sv->pending.begin(); at != sv->pending.end();) {
-        if (t - sv->reqs[*at].submit_us > max_wait_us) {
-            const auto pos = at - sv->pending.begin();
-            server_cancel_pending(sv, at, t);
-            at = sv->pending.begin() + pos;
-            ++k;
-        } else {
-            ++at;
+    for (auto &pl : sv->pools) {
+        std::deque<int64_t> &q = pl->pending;
+        for (auto at = q.begin(); at != q.end();) {
+            if (t - sv->reqs[*at].submit_us > max_wait_us) {
+                const auto pos = at - q.begin();
+                server_cancel_pending(sv, q, at, t);
+                at = q.begin() + pos;
+                ++k;
+            } else {
+                ++at;
+            }
         }
     }
     if (n) *n = k;

@@ -141,7 +141,8 @@ def test_batch_and_probe_fail_cleanly_then_recover():
 
 def test_server_create_fails_cleanly():
     insts, loaded, bases = _instances()
-    for k in range(1, 100):
+    # every allocation of the server's pools (engine and job storage each)
+    for k in range(1, 400):
         bp().debug_fail_alloc(k)
         held = []
         if _enomem(lambda: held.append(bp().Server(loaded, 1 << 28))):

@@ -233,7 +233,12 @@ def test_serving_mix_full_size():
             vs = np.sort(rr.choice(bins, size=min(k, bins.size), replace=False)).astype(np.int32)
             reqs.append((t, bp().REQ_PROBE, vs, None))
     S = bp().Server(loaded, 64 << 30, bp().default_options(rounds_per_launch=4))
-    assert S.info()["slots"] == 512
+    pools = S.info()["pools"]
+    # classes by size, each with its own slot footprint, all at the slot cap
+    assert len(pools) >= 2 and sum(p["instances"] for p in pools) == len(insts)
+    assert all(p["slots"] == 512 for p in pools)
+    sizes = [p["bytes_per_slot"] for p in pools]
+    assert sizes == sorted(sizes) and sizes[-1] > 8 * sizes[0]
     ids = [S.submit(t, kind, vs, val, val) for t, kind, vs, val in reqs]
     guard = 0
     while S.run(4):

@@ -116,7 +116,10 @@ def test_serving_mix_matches_oracle_and_alone():
     insts, loaded, bases = _instances()
     reqs = _requests(insts, bases, 60, seed=3)
     S, mix, done = _serve(loaded, reqs, budget=256 << 20, waves=4)
-    assert S.info()["slots"] >= 4
+    # two classes (300 and 3000-7500 variables), each with its own slots
+    pools = S.info()["pools"]
+    assert len(pools) == 2 and [p["instances"] for p in pools] == [2, 3]
+    assert pools[0]["bytes_per_slot"] < pools[1]["bytes_per_slot"]
     for j, req in enumerate(reqs):
         t = req[0]
         want = _oracle_result(insts[t], bases[t], req)
