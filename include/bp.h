@@ -182,6 +182,9 @@ typedef struct {
                                bp_propagate, bp_propagate_batch on the slot
                                engine and bp_probe; scan rounds not counted) */
     int64_t nnz_union;      /* nonzeros of those rows */
+    int64_t lv_corr_chunks; /* long-row chunk tasks of the one-vector-per-lane
+                               batch engine summed as the chunk's sums at the
+                               base bounds plus each vector's corrections */
 } bp_stats;
 
 /* Fill *opt with the defaults. */

@@ -69,7 +69,7 @@ class Stats(C.Structure):
                 ("nnz", C.c_int64), ("vars_read", C.c_int64), ("vars_written", C.c_int64),
                 ("rows_kept", C.c_int64), ("nnz_kept", C.c_int64), ("apply_ms", C.c_double),
                 ("apply_entries", C.c_int64), ("apply_colent", C.c_int64), ("apply_corr", C.c_int64),
-                ("rows_union", C.c_int64), ("nnz_union", C.c_int64)]
+                ("rows_union", C.c_int64), ("nnz_union", C.c_int64), ("lv_corr_chunks", C.c_int64)]
 
 
 class Request(C.Structure):
@@ -472,7 +472,8 @@ class Instance:
                     vars_read=s.vars_read, vars_written=s.vars_written,
                     rows_kept=s.rows_kept, nnz_kept=s.nnz_kept, apply_ms=s.apply_ms,
                     apply_entries=s.apply_entries, apply_colent=s.apply_colent,
-                    apply_corr=s.apply_corr, rows_union=s.rows_union, nnz_union=s.nnz_union)
+                    apply_corr=s.apply_corr, rows_union=s.rows_union, nnz_union=s.nnz_union,
+                    lv_corr_chunks=s.lv_corr_chunks)
 
 
 class Server:

@@ -73,6 +73,7 @@ struct LvCtl {
     uint32_t nlong[2][LV_MAX_GROUPS];   // chunk tasks per parity and group
     uint32_t nchg[LV_MAX_GROUPS];       // variables with candidates this round
     unsigned long long stat_rows, stat_nnz, stat_vars, stat_written;
+    unsigned long long stat_corr;  // chunk tasks summed as base plus corrections
 };
 
 struct LvParams {
@@ -99,6 +100,12 @@ struct LvParams {
     LvVec *vec;          // [V]
     uint32_t *vbad;      // [V] vector has an infeasible row this round (set early, read relaxed)
     LvCtl *ctl;
+    // overlay mode: each long-row chunk's sums at the base bounds, so that a
+    // chunk whose nonzeros are mostly unchanged in every lane is summed as
+    // the base plus each lane's corrections (null: always summed whole)
+    const int32_t *lchunk0;  // [m] chunk id of chunk 0 of a long row
+    const Acc *lbase;        // [chunks][2] (min, max) states at the base bounds
+    const double *lbw;       // [chunks] largest nonzero width at the base bounds
 };
 
 // A vector with an infeasible row in the current round finishes at its end
@@ -117,6 +124,11 @@ __device__ __forceinline__ void lv_mark_bad(const LvParams &P, int v, bool bad, 
 }
 
 __device__ __forceinline__ int rl_i32(int x, int t) { return __builtin_amdgcn_readlane(x, t); }
+__device__ __forceinline__ uint64_t rl_u64(uint64_t x, int t) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, t);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), t);
+    return ((uint64_t)hi << 32) | lo;
+}
 __device__ __forceinline__ double rl_f64(double x, int t) {
     long long b = __double_as_longlong(x);
     int lo = __builtin_amdgcn_readlane((int)(uint32_t)b, t);
@@ -255,6 +267,19 @@ __device__ __forceinline__ void lv_add_terms(Acc &mn, Acc &mx, double a, double 
     mx.ninf += imax ? 1 : 0;
     acc_add(mn, imin ? 0.0 : a * bmin);
     acc_add(mx, imax ? 0.0 : a * bmax);
+}
+
+// The two sides' terms of one nonzero at the given bounds taken out again
+// (the exact negations of what lv_add_terms adds; an infinite bound is
+// uncounted).
+__device__ __forceinline__ void lv_sub_terms(Acc &mn, Acc &mx, double a, double lb, double ub) {
+    const bool pos = a > 0.0;
+    const double bmin = pos ? lb : ub, bmax = pos ? ub : lb;
+    const bool imin = isinf(bmin), imax = isinf(bmax);
+    mn.ninf -= imin ? 1 : 0;
+    mx.ninf -= imax ? 1 : 0;
+    acc_add(mn, imin ? 0.0 : -(a * bmin));
+    acc_add(mx, imax ? 0.0 : -(a * bmax));
 }
 
 // Activity over nonzeros [q0, q1) of a row (at most 64 per block), for the
@@ -497,6 +522,52 @@ __device__ void lv_chunk_few(const LvParams &P, int g, uint64_t livemask, int64_
     }
 }
 
+// Chunk partial states as the chunk's sums at the base bounds (chunk id
+// `id`) plus each lane's corrections: for every nonzero whose variable some
+// live lane has changed (its mask bit set; the word is the same for the
+// whole wave, so unchanged nonzeros cost no arithmetic), those lanes add
+// their own terms and take out the base terms.  The exact sums are those of
+// the lane's own records over the chunk.  The width is the base's, or a
+// changed nonzero's own when larger: a bound on the lane's widths.
+__device__ void lv_chunk_corr(const LvParams &P, int g, int v, uint64_t livemask, int64_t q0, int64_t q1,
+                              int64_t id, Acc &mn, Acc &mx, double &wmax) {
+    const int lane = __lane_id();
+    const uint64_t *dg = P.dmask + (size_t)g * P.n;
+    acc_zero(mn);
+    acc_zero(mx);
+    double w = 0.0;
+    for (int64_t b0 = q0; b0 < q1; b0 += 64) {
+        const int64_t p = b0 + lane;
+        int i = 0;
+        double a = 0.0;
+        uint64_t dm = 0;
+        if (p < q1) {
+            i = P.I.col[p];
+            a = P.I.val[p];
+            dm = dg[i] & livemask;
+        }
+        uint64_t any = __ballot(dm != 0);
+        while (any) {
+            const int q = __ffsll((long long)any) - 1;  // uniform
+            any &= any - 1;
+            const uint64_t wq = rl_u64(dm, q);
+            const int iq = rl_i32(i, q);
+            const double aq = rl_f64(a, q);
+            const double2 bb = P.base[iq];
+            if ((wq >> lane) & 1ull) {
+                const double2 bo = P.bnd[(size_t)iq * P.V + v];
+                lv_add_terms(mn, mx, aq, bo.x, bo.y);
+                lv_sub_terms(mn, mx, aq, bb.x, bb.y);
+                w = fmax(w, nz_width(aq, bo.x, bo.y));
+            }
+        }
+    }
+    const Acc bmn = P.lbase[2 * id], bmx = P.lbase[2 * id + 1];
+    acc_merge(mn, bmn.s, bmn.c, bmn.e, bmn.ninf);
+    acc_merge(mx, bmx.s, bmx.c, bmx.e, bmx.ninf);
+    wmax = fmax(w, P.lbw[id]);
+}
+
 // Chunk c of a long row: per-lane partial states.
 __device__ void lv_chunk_activity(const LvParams &P, int par, int g, int v, bool active, uint32_t u,
                                   LvCount &K) {
@@ -510,8 +581,25 @@ __device__ void lv_chunk_activity(const LvParams &P, int par, int g, int v, bool
     if (c == 0) lv_count_row(P, k, r1 - r0, K);
     Acc mn, mx;
     double wmax = 0.0;
+    bool corr = false;
+    if (__popcll(livemask) > LV_FEW && P.lbase && !P.count_vars) {
+        // base plus corrections when fewer than half of the chunk's
+        // nonzeros are changed in some live lane (each costs four terms
+        // there, two in the whole sum); counting runs sum whole
+        const uint64_t *dg = P.dmask + (size_t)g * P.n;
+        int64_t dirty = 0;
+        for (int64_t b0 = q0; b0 < q1; b0 += 64) {
+            const int64_t p = b0 + __lane_id();
+            const bool d = p < q1 && (dg[P.I.col[p]] & livemask) != 0;
+            dirty += __popcll(__ballot(d));
+        }
+        corr = 2 * dirty < q1 - q0;
+    }
     if (__popcll(livemask) <= LV_FEW) {
         lv_chunk_few(P, g, livemask, q0, q1, mn, mx, wmax, K);
+    } else if (corr) {
+        lv_chunk_corr(P, g, v, livemask, q0, q1, (int64_t)P.lchunk0[k] + c, mn, mx, wmax);
+        if (__lane_id() == 0) atomicAdd(&P.ctl->stat_corr, 1ull);
     } else {
         acc_zero(mn);
         acc_zero(mx);
@@ -990,6 +1078,36 @@ __global__ void __launch_bounds__(WG) k_lv_pack_overlay(const double *lb, const 
     }
 }
 
+// Every long-row chunk's (min, max) states and largest nonzero width at the
+// base bounds (one wave per chunk; chunk id = index in the chunk table).
+__global__ void __launch_bounds__(WG) k_lv_base_chunks(DInst I, const int2 *chunks, int64_t nchunks,
+                                                       Acc *lbase, double *lbw) {
+    const int64_t nw = (int64_t)gridDim.x * (WG / 64);
+    for (int64_t id = (int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6); id < nchunks; id += nw) {
+        const int2 ck = chunks[id];
+        const int64_t r0 = I.row_ptr[ck.x], r1 = I.row_ptr[ck.x + 1];
+        const int64_t q0 = r0 + (int64_t)ck.y * LV_CHUNK, q1 = min(r1, q0 + (int64_t)LV_CHUNK);
+        Acc mn, mx;
+        acc_zero(mn);
+        acc_zero(mx);
+        double w = 0.0;
+        for (int64_t p = q0 + __lane_id(); p < q1; p += 64) {
+            const double a = I.val[p];
+            const double2 b = I.base[I.col[p]];
+            lv_add_terms(mn, mx, a, b.x, b.y);
+            w = fmax(w, nz_width(a, b.x, b.y));
+        }
+        acc_group_reduce<64>(mn);
+        acc_group_reduce<64>(mx);
+        w = group_max<64>(w);
+        if (__lane_id() == 0) {
+            lbase[2 * id] = mn;
+            lbase[2 * id + 1] = mx;
+            lbw[id] = w;
+        }
+    }
+}
+
 __global__ void k_lv_fill_u64(uint64_t *p, size_t N) {
     for (size_t j = blockIdx.x * (size_t)blockDim.x + threadIdx.x; j < N; j += (size_t)gridDim.x * blockDim.x)
         p[j] = 0ull;
@@ -1208,6 +1326,11 @@ struct LvEngine {
     int32_t Vcap = 0;
     int64_t lcap = 0, nshort = 0, nlong = 0;
     bool have_touched = false;
+    // long-row chunks at the base bounds (overlay mode): chunk id of each
+    // long row's chunk 0, the chunks' states and widths, and the base
+    // version they were summed for
+    DevBuf lchunk0, lbase, lbw;
+    int64_t lb_version = -1;
     DevBuf bnd, cand, vmask, dmask, rmask[2], qs[2], ql[2], lpart, lrng, lmask, chg, touched, rtouch, vec, vbad,
         ctl, box, wmask;
     DevBuf short_rows, long_chunks;  // cold-start tasks of the instance

@@ -13,12 +13,14 @@ static const int LV_MIN_BATCH = 16;     // smaller batches run on the slot engin
 static int lv_tables(bp_instance *h, LvEngine &L, hipStream_t st) {
     std::vector<int32_t> sr;
     std::vector<int2> lc;
+    std::vector<int32_t> c0((size_t)std::max<int64_t>(h->m, 1), -1);  // chunk id of a long row's chunk 0
     for (int64_t k = 0; k < h->m; ++k) {
         const int64_t len = h->row_len[k];
         if (len <= LV_SHORT) {
             sr.push_back((int32_t)k);
         } else {
             const int64_t nch = (len + LV_CHUNK - 1) / LV_CHUNK;
+            c0[k] = (int32_t)lc.size();
             for (int64_t c = 0; c < nch; ++c) lc.push_back(make_int2((int)k, (int)c));
         }
     }
@@ -28,6 +30,8 @@ static int lv_tables(bp_instance *h, LvEngine &L, hipStream_t st) {
     int rc;
     if ((rc = L.short_rows.alloc(sr.size() * 4, h->bytes))) return rc;
     if ((rc = L.long_chunks.alloc(lc.size() * sizeof(int2), h->bytes))) return rc;
+    if ((rc = L.lchunk0.alloc(c0.size() * 4, h->bytes))) return rc;
+    HIPTRY(hipMemcpyAsync(L.lchunk0.p, c0.data(), c0.size() * 4, hipMemcpyHostToDevice, st));
     if (!sr.empty()) HIPTRY(hipMemcpyAsync(L.short_rows.p, sr.data(), sr.size() * 4, hipMemcpyHostToDevice, st));
     if (!lc.empty())
         HIPTRY(hipMemcpyAsync(L.long_chunks.p, lc.data(), lc.size() * sizeof(int2), hipMemcpyHostToDevice, st));
@@ -42,7 +46,7 @@ static int lv_ensure(bp_instance *h, int32_t V, bool count, hipStream_t st) {
         // the engine is kept only once its tables exist
         std::unique_ptr<LvEngine> E(new LvEngine());
         if (int rc = lv_tables(h, *E, st)) {
-            h->bytes -= (int64_t)(E->short_rows.bytes + E->long_chunks.bytes);
+            h->bytes -= (int64_t)(E->short_rows.bytes + E->long_chunks.bytes + E->lchunk0.bytes);
             return rc;
         }
         h->lv = std::move(E);
@@ -99,6 +103,20 @@ static int lv_ensure(bp_instance *h, int32_t V, bool count, hipStream_t st) {
     return 0;
 }
 
+// The long-row chunks at the base bounds (overlay mode), once per base.
+static int lv_base_chunks(bp_instance *h, hipStream_t st) {
+    LvEngine &L = *h->lv;
+    if (L.nlong == 0 || L.lb_version == h->base_version) return 0;
+    L.lb_version = -1;
+    if (int rc = L.lbase.grow((size_t)L.nlong * 2 * sizeof(Acc), h->bytes)) return rc;
+    if (int rc = L.lbw.grow((size_t)L.nlong * 8, h->bytes)) return rc;
+    k_lv_base_chunks<<<(int)std::min<int64_t>((L.nlong + 3) / 4, 8192), WG, 0, st>>>(
+        dinst_of(h), L.long_chunks.as<int2>(), L.nlong, L.lbase.as<Acc>(), L.lbw.as<double>());
+    HIPTRY(hipGetLastError());
+    L.lb_version = h->base_version;
+    return 0;
+}
+
 static LvParams lv_params(const bp_instance *h, int32_t Bp, int32_t V, bool count, bool overlay) {
     LvEngine &L = *h->lv;
     LvParams P;
@@ -135,6 +153,11 @@ static LvParams lv_params(const bp_instance *h, int32_t Bp, int32_t V, bool coun
     P.vec = L.vec.as<LvVec>();
     P.vbad = L.vbad.as<uint32_t>();
     P.ctl = L.ctl.as<LvCtl>();
+    if (overlay && L.nlong > 0 && L.lb_version == h->base_version) {
+        P.lchunk0 = L.lchunk0.as<int32_t>();
+        P.lbase = L.lbase.as<Acc>();
+        P.lbw = L.lbw.as<double>();
+    }
     return P;
 }
 
@@ -205,6 +228,7 @@ static int lv_run_rounds(bp_instance *h, const LvParams &P, hipStream_t st) {
     h->stats.nnz += (int64_t)hc.stat_nnz;
     h->stats.vars_read += (int64_t)hc.stat_vars;
     h->stats.vars_written += (int64_t)hc.stat_written;
+    h->stats.lv_corr_chunks += (int64_t)hc.stat_corr;
     return 0;
 }
 
@@ -242,6 +266,8 @@ static int lv_piece(bp_instance *h, int32_t Bp, double *lb, double *ub, const in
     // Overlay mode when the instance has a base box (bulk-rounding
     // candidates are the base with a few fixings); results are identical.
     const bool overlay = h->have_base && !(h->opt.flags & BP_FLAG_LV_DENSE);
+    if (overlay)
+        if (int rc = lv_base_chunks(h, st)) return rc;
     const LvParams P = lv_params(h, Bp, V, count, overlay);
     const int64_t n = h->n;
     const int NG = P.NG;

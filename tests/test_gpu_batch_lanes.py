@@ -171,3 +171,26 @@ def test_overlay_and_dense_agree_bit_for_bit():
         res, GL, GU = _batch(I, LB, UB, changed)
         assert res == ref, flags
         assert np.array_equal(GL, RL) and np.array_equal(GU, RU), flags
+
+
+def test_long_rows_as_base_plus_corrections():
+    """Dense rows queued by most vectors of each group, every vector fixing
+    a few variables of the base: their chunks are summed as the chunk's sums
+    at the base bounds plus each vector's corrections (counted), and every
+    result matches the oracle.  When the base moves, the chunk sums are
+    taken again, and the results match on the new base too."""
+    inst = gen.make("single", 7, scale=0.06)
+    assert np.diff(inst["row_ptr"]).max() > 1024
+    lb, ub = _root(inst)
+    I = _instance(inst, True, lb, ub)
+    for step in range(2):
+        LB, UB, changed = gen.bulk_fix_vectors(inst, lb, ub, count=128, frac=0.002, seed=40 + step)
+        I.kernel_stats(reset=True)
+        res, GL, GU = _batch(I, LB, UB, changed)
+        assert I.kernel_stats(reset=True)["lv_corr_chunks"] > 0
+        _check(inst, res, GL, GU, LB, UB, changed, "corr%d" % step)
+        # a new base: the fixed point of one feasible vector
+        v = next(j for j, r in enumerate(res) if r["status"] == oracle.BP_OK)
+        ro, lb, ub = oracle.propagate(inst, LB[v], UB[v], changed=changed[v])
+        assert ro["status"] == oracle.BP_OK
+        gpu_base(I, lb, ub)
