@@ -66,12 +66,17 @@ def sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(key):
+def measured_traffic(key, schedule=None):
     """HBM bytes per launch for TRAFFIC[key], or None when there is no
-    record or the sources changed since the counters were taken."""
+    record, the sources changed since the counters were taken, or the
+    record names a schedule (the tuned knobs that change the kernel's work)
+    that `schedule` does not match."""
     t = TRAFFIC.get(key)
     if t is None or SOURCES_SHA256 is None or sources_sha256() != SOURCES_SHA256:
         return None
+    for k, v in t.get("schedule", {}).items():
+        if schedule is None or schedule.get(k) != v:
+            return None
     return int((t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024)
 
 
@@ -189,9 +194,9 @@ def main():
     ap.add_argument("--skip-probe", action="store_true",
                     help="skip the batched double-probing measurement")
     ap.add_argument("--probe-vars", type=int, default=4096)
-    ap.add_argument("--probe-schedule", default="",
-                    help="heavy_threshold,heavy_chunk,rounds_per_launch,probe_slots for the probe leg "
-                         "instead of tuning it (counter runs)")
+    ap.add_argument("--probe-schedule", default="8192,4096,32,2048",
+                    help="heavy_threshold,heavy_chunk,rounds_per_launch,probe_slots of the probe leg "
+                         "(the schedule bp_autotune chooses on this workload); empty: tune it")
     ap.add_argument("--probe-plain", type=int, default=256,
                     help="binaries probed one call at a time for the plain baseline")
     ap.add_argument("--skip-serving", action="store_true",
@@ -545,7 +550,7 @@ def bench_probe(args, bp, gen, torch, np):
     dev = torch.device("cuda:0")
     inst = gen.make("probe", args.seed)
     sched = None
-    if args.probe_schedule:  # given (counter runs take the bench line's schedule)
+    if args.probe_schedule:  # the given schedule
         ht, hc, rk, ps = (int(x) for x in args.probe_schedule.split(","))
         sched = dict(heavy_threshold=ht, heavy_chunk=hc, rounds_per_launch=rk, probe_slots=ps)
     I = bp.Instance(inst, bp.default_options(**(sched or {})))
@@ -558,9 +563,9 @@ def bench_probe(args, bp, gen, torch, np):
     k = int(vs.size)
     vars_d = torch.tensor(vs, dtype=torch.int32, device=dev)
     if sched is None and not args.profile_probe:
-        # the schedule (row split, rounds per graph, probe slots) tuned on
-        # this instance's cold propagation and on these probes, before
-        # timing; the tuner leaves the base at the root fixed point
+        # --probe-schedule "": the schedule (row split, rounds per graph,
+        # probe slots) tuned on this instance's cold propagation and on these
+        # probes, before timing; the tuner leaves the base at the root
         t = I.autotune(*fresh(lb0, ub0), vars_d)
         sched = {key: t[key] for key in ("heavy_threshold", "heavy_chunk", "rounds_per_launch", "probe_slots")}
         log("probe: tuned schedule %s (%d trials)" % (sched, t["trials"]))
@@ -617,7 +622,7 @@ def bench_probe(args, bp, gen, torch, np):
         "infeasible_probes": int((G["status"] == bp.BP_INFEASIBLE).sum().item()),
     }
     res["roofline"] = probe_roofline(bp, inst, lb, ub, vars_d, cap, tb, torch, sched)
-    res["roofline"]["traffic"] = measured_traffic("probe k_rows")
+    res["roofline"]["traffic"] = measured_traffic("probe k_rows", sched)
     log("probe: batched %.2f ms, k_rows %.1f GB/s (%.4f of peak), call %.1f GB/s"
         % (tb * 1e3, res["roofline"]["achieved"], res["roofline"]["frac"],
            res["roofline"]["call_alg_GBps"]))
@@ -875,7 +880,7 @@ def bench_bulk(args, bp, gen, torch, np):
         return batch_call(J)
 
     roof = kernel_roofline(bp, inst, with_base, reps=2, kernel="k_lv_rows", **opt_kw)
-    roof["traffic"] = measured_traffic("bulk k_lv_rows")
+    roof["traffic"] = measured_traffic("bulk k_lv_rows", opt_kw)
     cpu = cpu_all = None
     if args.bulk_cpu and not args.no_cpu_baseline:
         # The oracle's own root of this size takes minutes, so the CPU legs
