@@ -803,7 +803,7 @@ static int launch_round(bp_instance *h, const Params &P, const JobIO *io, hipStr
     } else {
         k_rows<false><<<GRID_ROWS, WG, 0, st>>>(P);
     }
-    k_heavy<false><<<GRID_HEAVY, WG, 0, st>>>(P);
+    if (!P.inc_base) k_heavy<false><<<GRID_HEAVY, WG, 0, st>>>(P);  // job slots: decided by the heads
     if (timed) hipExtLaunchKernelGGL(k_apply<false>, dim3(GRID_APPLY), dim3(WG), 0, st, h->ev2, h->ev3, 0, P);
     else k_apply<false><<<GRID_APPLY, WG, 0, st>>>(P);
     if (io) k_end<END_WG><<<1, END_WG, 0, st>>>(P);
@@ -855,7 +855,8 @@ static int run_rounds(bp_instance *h, const Params &P, const JobIO *io, int64_t 
                 HIPTRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
                 for (int r = 0; r < K; ++r) {
                     k_rows<false><<<GRID_ROWS, WG, 0, cs>>>(P);
-                    k_heavy<false><<<GRID_HEAVY, WG, 0, cs>>>(P);
+                    // job slots' heavy rows are decided by their heads
+                    if (!P.inc_base) k_heavy<false><<<GRID_HEAVY, WG, 0, cs>>>(P);
                     k_apply<false><<<GRID_APPLY, WG, 0, cs>>>(P);
                     if (io) k_end<END_WG><<<1, END_WG, 0, cs>>>(P);
                     else k_end<WG><<<1, WG, 0, cs>>>(P);

@@ -1057,6 +1057,8 @@ __device__ void inc_head(const Params &P, int par, uint32_t u) {
     const int h = I.hidx[k];
     const size_t hs = (size_t)s * P.nheavy + h;
     const double2 a = inc_row_activity(P, hs, P.inc_base ? I.hblimb + (size_t)h * 2 * HL : nullptr);
+    __shared__ RowAct RS;
+    __shared__ int todo;
     if (threadIdx.x == 0) {
         P.hact[hs] = a;
         const double2 sd = I.side[k];
@@ -1073,11 +1075,46 @@ __device__ void inc_head(const Params &P, int par, uint32_t u) {
             if (bad || quiet)
                 atomicAdd(&P.ctl->stat_kept_nnz, (unsigned long long)(I.row_ptr[k + 1] - I.row_ptr[k]));
         }
+        todo = 0;
         if (!bad && !quiet) {
-            const uint32_t at = atomicAdd(&P.ctl->hcand[par], (uint32_t)nch);
-            for (int j = 0; j < nch; ++j) P.hcrec[par][at + j] = make_int4(s, k, j, nch);
+            if (P.inc_base) {
+                // job slots: the head computes the candidates itself
+                RS = R;
+                todo = 1;
+            } else {
+                const uint32_t at = atomicAdd(&P.ctl->hcand[par], (uint32_t)nch);
+                for (int j = 0; j < nch; ++j) P.hcrec[par][at + j] = make_int4(s, k, j, nch);
+            }
         }
     }
+    if (!P.inc_base) return;  // uniform
+    __syncthreads();
+    if (todo) {
+        // Job slots never rebuild their accumulators, so a round's heavy
+        // rows are decided here and the heavy kernel is not launched: the
+        // workgroup walks the whole row for the slot's candidates.
+        const RowAct R = RS;
+        const int64_t r0 = I.row_ptr[k], r1 = I.row_ptr[k + 1];
+        if (threadIdx.x == 0) count_row(P, k, r1 - r0);
+        const BView bnd = bview(P, s, I.base);
+        const int iters = (int)((r1 - r0 + WG - 1) / WG);
+        for (int it = 0; it < iters; ++it) {
+            const int64_t p = r0 + threadIdx.x + (int64_t)it * WG;
+            bool need = false;
+            int i = 0;
+            if (p < r1) {
+                i = I.col[p];
+                const double av = I.val[p];
+                const double2 b = bnd[i];
+                const bool is_int = I.vtype[i] != 0;
+                double cl, cu;
+                nz_candidates(R, av, b.x, b.y, is_int, P.inttol, cl, cu);
+                need = scatter(P, s, i, cl, cu, b.x, b.y, is_int);
+            }
+            mark_var(P, need, s, i);
+        }
+    }
+    __syncthreads();  // RS and todo are reused by the next task
 }
 
 // Heavy chunk, candidate part.  Every wave combines the row's partials

@@ -117,7 +117,10 @@ static int lv_base_chunks(bp_instance *h, hipStream_t st) {
     return 0;
 }
 
-static LvParams lv_params(const bp_instance *h, int32_t Bp, int32_t V, bool count, bool overlay) {
+// corr: long-row chunks may be summed as base plus corrections (each chunk
+// task still decides from its own changed nonzeros).
+static LvParams lv_params(const bp_instance *h, int32_t Bp, int32_t V, bool count, bool overlay,
+                          bool corr = true) {
     LvEngine &L = *h->lv;
     LvParams P;
     memset(&P, 0, sizeof(P));
@@ -153,7 +156,7 @@ static LvParams lv_params(const bp_instance *h, int32_t Bp, int32_t V, bool coun
     P.vec = L.vec.as<LvVec>();
     P.vbad = L.vbad.as<uint32_t>();
     P.ctl = L.ctl.as<LvCtl>();
-    if (overlay && L.nlong > 0 && L.lb_version == h->base_version) {
+    if (overlay && corr && L.nlong > 0 && L.lb_version == h->base_version) {
         P.lchunk0 = L.lchunk0.as<int32_t>();
         P.lbase = L.lbase.as<Acc>();
         P.lbw = L.lbw.as<double>();
@@ -268,7 +271,12 @@ static int lv_piece(bp_instance *h, int32_t Bp, double *lb, double *ub, const in
     const bool overlay = h->have_base && !(h->opt.flags & BP_FLAG_LV_DENSE);
     if (overlay)
         if (int rc = lv_base_chunks(h, st)) return rc;
-    const LvParams P = lv_params(h, Bp, V, count, overlay);
+    // A batch whose vectors change more than n/96 variables each on average
+    // leaves most of a 64-vector group's nonzeros changed in some lane
+    // (1 - (1 - 1/96)^64 > 1/2): its chunks are summed whole without the
+    // per-chunk test.
+    const bool corr = cold || ecount * 96 <= (int64_t)Bp * h->n;
+    const LvParams P = lv_params(h, Bp, V, count, overlay, corr);
     const int64_t n = h->n;
     const int NG = P.NG;
     // bounds in, box check

@@ -699,7 +699,7 @@ static int pool_graph(bp_server *sv, ServerPool &pl) {
     HIPTRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     for (int r = 0; r < K; ++r) {
         k_rows<true><<<GRID_ROWS, WG, 0, cs>>>(pl.P);
-        k_heavy<true><<<GRID_HEAVY, WG, 0, cs>>>(pl.P);
+        if (!pl.P.inc_base) k_heavy<true><<<GRID_HEAVY, WG, 0, cs>>>(pl.P);  // heavy rows decided by the heads
         k_apply<true><<<GRID_APPLY, WG, 0, cs>>>(pl.P);
         k_end<END_WG><<<1, END_WG, 0, cs>>>(pl.P);
         k_retire<true><<<std::min(pl.slots, 4096), WG, 0, cs>>>(pl.P, pl.IO);
