@@ -36,19 +36,19 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E datasheet peak
 # WRITE_SIZE x1.0).  The figures belong to the library sources they were
 # measured on (SOURCES_SHA256, see sources_sha256()): when any source
 # differs, the bench line reports null.
-SOURCES_SHA256 = "37dd41f97ae85c06ca2bf9979e01ec4a5eb2fa45a66f6cc1d58e2d0184a2003e"
+SOURCES_SHA256 = "3c0ebfed23f988653817986080095881d6eae3f61b7a0dbe49a932fd079045c1"
 TRAFFIC = {
     # single-instance workload, `bench.py --profile-steps 5`: 5 cold calls of
     # 79 working launches each (KiB per working launch)
-    "plain k_rows": {"fetch_kib": 1851.24, "write_kib": 194.18, "fetch_scale": 2.0, "write_scale": 1.0},
-    "plain k_apply": {"fetch_kib": 403.03, "write_kib": 179.04, "fetch_scale": 2.0, "write_scale": 1.0},
+    "plain k_rows": {"fetch_kib": 1851.30, "write_kib": 194.17, "fetch_scale": 2.0, "write_scale": 1.0},
+    "plain k_apply": {"fetch_kib": 404.34, "write_kib": 179.45, "fetch_scale": 2.0, "write_scale": 1.0},
     # probe workload, `bench.py --only-probe --profile-probe 3`: 4 batched
     # calls of 8192 probes on 2048 slots, 15 working launches each
-    "probe k_rows": {"fetch_kib": 15527.86, "write_kib": 343.54, "fetch_scale": 2.0, "write_scale": 1.0,
+    "probe k_rows": {"fetch_kib": 15528.86, "write_kib": 343.49, "fetch_scale": 2.0, "write_scale": 1.0,
                      "schedule": {"heavy_threshold": 8192, "heavy_chunk": 4096, "probe_slots": 2048}},
     # bulk workload, `bench.py --only-bulk --profile-bulk 2 --bulk-schedule
     # 4096,16`: 3 calls of 256 vectors, one working launch each
-    "bulk k_lv_rows": {"fetch_kib": 23756011.03, "write_kib": 463511.60, "fetch_scale": 2.0, "write_scale": 1.0},
+    "bulk k_lv_rows": {"fetch_kib": 21056886.40, "write_kib": 463723.83, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 
