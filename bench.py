@@ -36,19 +36,25 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E datasheet peak
 # WRITE_SIZE x1.0).  The figures belong to the library sources they were
 # measured on (SOURCES_SHA256, see sources_sha256()): when any source
 # differs, the bench line reports null.
-SOURCES_SHA256 = "3c0ebfed23f988653817986080095881d6eae3f61b7a0dbe49a932fd079045c1"
+SOURCES_SHA256 = "344ed4762f7db8e1e19c87b0c8ff40839cf71e305638a6ca5d0da17eacb54b75"
 TRAFFIC = {
     # single-instance workload, `bench.py --profile-steps 5`: 5 cold calls of
     # 79 working launches each (KiB per working launch)
-    "plain k_rows": {"fetch_kib": 1851.30, "write_kib": 194.17, "fetch_scale": 2.0, "write_scale": 1.0},
-    "plain k_apply": {"fetch_kib": 404.34, "write_kib": 179.45, "fetch_scale": 2.0, "write_scale": 1.0},
+    "plain k_rows": {"fetch_kib": 1851.31, "write_kib": 194.17, "fetch_scale": 2.0, "write_scale": 1.0},
+    "plain k_apply": {"fetch_kib": 404.36, "write_kib": 179.30, "fetch_scale": 2.0, "write_scale": 1.0},
     # probe workload, `bench.py --only-probe --profile-probe 3`: 4 batched
     # calls of 8192 probes on 2048 slots, 15 working launches each
-    "probe k_rows": {"fetch_kib": 15528.86, "write_kib": 343.49, "fetch_scale": 2.0, "write_scale": 1.0,
+    "probe k_rows": {"fetch_kib": 15515.24, "write_kib": 343.53, "fetch_scale": 2.0, "write_scale": 1.0,
                      "schedule": {"heavy_threshold": 8192, "heavy_chunk": 4096, "probe_slots": 2048}},
     # bulk workload, `bench.py --only-bulk --profile-bulk 2 --bulk-schedule
-    # 4096,16`: 3 calls of 256 vectors, one working launch each
-    "bulk k_lv_rows": {"fetch_kib": 21056886.40, "write_kib": 463723.83, "fetch_scale": 2.0, "write_scale": 1.0},
+    # G,16`: 3 calls of 256 vectors, one working launch each; one record per
+    # lane-engine grid G the tuner chooses between
+    "bulk k_lv_rows": [
+        {"fetch_kib": 21055542.90, "write_kib": 463667.37, "fetch_scale": 2.0, "write_scale": 1.0,
+         "schedule": {"lv_grid": 4096}},
+        {"fetch_kib": 21032531.31, "write_kib": 470869.04, "fetch_scale": 2.0, "write_scale": 1.0,
+         "schedule": {"lv_grid": 8192}},
+    ],
 }
 
 
@@ -71,14 +77,15 @@ def measured_traffic(key, schedule=None):
     """HBM bytes per launch for TRAFFIC[key], or None when there is no
     record, the sources changed since the counters were taken, or the
     record names a schedule (the tuned knobs that change the kernel's work)
-    that `schedule` does not match."""
-    t = TRAFFIC.get(key)
-    if t is None or SOURCES_SHA256 is None or sources_sha256() != SOURCES_SHA256:
+    that `schedule` does not match.  A key may hold one record per
+    schedule."""
+    recs = TRAFFIC.get(key)
+    if recs is None or SOURCES_SHA256 is None or sources_sha256() != SOURCES_SHA256:
         return None
-    for k, v in t.get("schedule", {}).items():
-        if schedule is None or schedule.get(k) != v:
-            return None
-    return int((t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024)
+    for t in recs if isinstance(recs, list) else [recs]:
+        if all(schedule is not None and schedule.get(k) == v for k, v in t.get("schedule", {}).items()):
+            return int((t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024)
+    return None
 
 
 def log(msg):

@@ -113,7 +113,11 @@ typedef struct {
     uint32_t flags;      /* BP_FLAG_* */
     int32_t heavy_threshold; /* rows longer than this are split across
                                 workgroups; default 8192 (0: default) */
-    int32_t rounds_per_launch; /* rounds per captured graph; default 16 */
+    int32_t rounds_per_launch; /* rounds per captured graph; default 16.  A
+                                  bp_probe call after the instance's first
+                                  uses the smallest power of two from 8 up
+                                  that covered the last call's rounds, when
+                                  that is fewer */
     int32_t probe_slots; /* bound vectors in flight during bp_probe; default 512 */
     int32_t heavy_chunk; /* nonzeros per workgroup of a heavy row; default 1024,
                             rounded up to a multiple of 256 */

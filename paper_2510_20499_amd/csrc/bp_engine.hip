@@ -134,6 +134,8 @@ struct Engine {
     // every slot's heavy-row corrections are zero (a probe call ran to the
     // end: each retired job cleared its own)
     bool inc_clear = false;
+    // rounds the last probe call ran (0: none yet)
+    int32_t job_rounds = 0;
     Shape shape;
     int64_t bytes = 0;
     DevBuf bnd, cand, vflag, rflag, info, chg, dirty, dlist, dcount, ctl, touched, useen, filt;
@@ -820,7 +822,15 @@ static int run_rounds(bp_instance *h, const Params &P, const JobIO *io, int64_t 
     Ctl hc;
     const bool timed = (h->opt.flags & BP_FLAG_TIME_KERNELS) != 0;
     const bool host_rounds = timed || (h->opt.flags & BP_FLAG_HOST_ROUNDS) != 0;
-    const int K = std::max(1, (int)h->opt.rounds_per_launch);
+    // Rounds per graph: rounds_per_launch, or for probe calls the smallest
+    // power of two from 8 up that covered the last call's rounds, if less
+    // (rounds after the last one still cost their launches).
+    int K = std::max(1, (int)h->opt.rounds_per_launch);
+    if (io && E.job_rounds > 0) {
+        int k = 8;
+        while (k < E.job_rounds && k < K) k *= 2;
+        K = std::min(K, k);
+    }
     int64_t launched = 0;
     for (;;) {
         if (host_rounds) {
@@ -883,6 +893,7 @@ static int run_rounds(bp_instance *h, const Params &P, const JobIO *io, int64_t 
         if (hc.done) break;
         if (launched > limit) return fail(BP_EDEVICE, "round loop did not terminate");
     }
+    if (io) E.job_rounds = (int32_t)std::min<uint32_t>(hc.round, 1u << 30);
     h->stats.rows += (int64_t)hc.stat_rows;
     h->stats.nnz += (int64_t)hc.stat_nnz;
     h->stats.vars_read += (int64_t)hc.stat_vars;
