@@ -36,23 +36,23 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E datasheet peak
 # WRITE_SIZE x1.0).  The figures belong to the library sources they were
 # measured on (SOURCES_SHA256, see sources_sha256()): when any source
 # differs, the bench line reports null.
-SOURCES_SHA256 = "344ed4762f7db8e1e19c87b0c8ff40839cf71e305638a6ca5d0da17eacb54b75"
+SOURCES_SHA256 = "985df3f92fc5e8fe51e0824fd58dda8f099c01bfcdb958d13e696e7a43788c40"
 TRAFFIC = {
     # single-instance workload, `bench.py --profile-steps 5`: 5 cold calls of
     # 79 working launches each (KiB per working launch)
-    "plain k_rows": {"fetch_kib": 1851.31, "write_kib": 194.17, "fetch_scale": 2.0, "write_scale": 1.0},
-    "plain k_apply": {"fetch_kib": 404.36, "write_kib": 179.30, "fetch_scale": 2.0, "write_scale": 1.0},
+    "plain k_rows": {"fetch_kib": 1851.30, "write_kib": 194.19, "fetch_scale": 2.0, "write_scale": 1.0},
+    "plain k_apply": {"fetch_kib": 403.82, "write_kib": 179.62, "fetch_scale": 2.0, "write_scale": 1.0},
     # probe workload, `bench.py --only-probe --profile-probe 3`: 4 batched
     # calls of 8192 probes on 2048 slots, 15 working launches each
-    "probe k_rows": {"fetch_kib": 15515.24, "write_kib": 343.53, "fetch_scale": 2.0, "write_scale": 1.0,
+    "probe k_rows": {"fetch_kib": 15505.34, "write_kib": 343.61, "fetch_scale": 2.0, "write_scale": 1.0,
                      "schedule": {"heavy_threshold": 8192, "heavy_chunk": 4096, "probe_slots": 2048}},
     # bulk workload, `bench.py --only-bulk --profile-bulk 2 --bulk-schedule
     # G,16`: 3 calls of 256 vectors, one working launch each; one record per
     # lane-engine grid G the tuner chooses between
     "bulk k_lv_rows": [
-        {"fetch_kib": 21055542.90, "write_kib": 463667.37, "fetch_scale": 2.0, "write_scale": 1.0,
+        {"fetch_kib": 21053940.33, "write_kib": 463640.53, "fetch_scale": 2.0, "write_scale": 1.0,
          "schedule": {"lv_grid": 4096}},
-        {"fetch_kib": 21032531.31, "write_kib": 470869.04, "fetch_scale": 2.0, "write_scale": 1.0,
+        {"fetch_kib": 21028913.88, "write_kib": 470956.22, "fetch_scale": 2.0, "write_scale": 1.0,
          "schedule": {"lv_grid": 8192}},
     ],
 }

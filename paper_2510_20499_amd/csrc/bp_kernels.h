@@ -2012,14 +2012,58 @@ __device__ void stage_sorted(const Params &P, const JobIO &IO, int s, const DIns
 // With incremental heavy rows over the base: clear the corrections of
 // every heavy row holding one of slot s's cnt dirty variables (a row's
 // corrections come only from bound changes of its own variables, all of
-// which are dirty).  Waves w0, w0 + nw, ... each take a variable and walk
-// its column 64 entries at a time.  The clears are atomics like the next
-// job's corrections, and their results are waited for: they are done when
-// the caller's next barrier is.
-__device__ void clear_heavy(const Params &P, const DInst &I, int s, int cnt, int w0, int nw) {
-    if (!(P.inc && P.inc_base)) return;
-    const int lane = __lane_id();
+// which are dirty).  Each wave takes a variable and walks its column 64
+// entries at a time, marking the column's heavy rows in an LDS bitmap;
+// the workgroup then clears the marked rows together, so that the clears
+// of a slot's rows are in flight at once.  (Instances of more heavy rows
+// than the bitmap holds clear each row as its column walk finds it.)  The
+// clears are atomics like the next job's corrections, and their results
+// are waited for: they are done when the caller's next barrier is.
+constexpr int CLEAR_MAP = 64;  // bitmap words (one per lane of a wave)
+static_assert(CLEAR_MAP == 64 && SORT_MAX >= CLEAR_MAP * 33, "clear bitmap and row list fit the sort keys");
+__device__ void clear_heavy(const Params &P, const DInst &I, int s, int cnt, RetireScratch &R) {
+    if (!(P.inc && P.inc_base)) return;  // uniform
+    const int lane = __lane_id(), wave = threadIdx.x >> 6;
+    const int w0 = wave, nw = WG / 64;
     unsigned long long junk = 0;
+    if (cnt < P.nheavy && P.nheavy <= CLEAR_MAP * 32) {  // uniform
+        uint32_t *map = (uint32_t *)R.key;
+        int32_t *list = R.key + CLEAR_MAP;
+        if (threadIdx.x < CLEAR_MAP) map[threadIdx.x] = 0u;
+        __syncthreads();
+        for (int t = wave; t < cnt; t += nw) {
+            const int i = P.dlist[(size_t)s * P.sn + t];
+            const int64_t c0 = I.col_ptr[i], c1 = I.col_ptr[i + 1];
+            for (int64_t e = c0 + lane; e < c1; e += 64) {
+                const int h = I.hidx[I.col_row[e]];
+                if (h >= 0) atomicOr(&map[h >> 5], 1u << (h & 31));
+            }
+        }
+        __syncthreads();
+        if (wave == 0) {  // the marked rows, in order, by a prefix of the words' popcounts
+            const uint32_t w = map[lane];
+            const int c = __popc(w);
+            int x = c;
+            for (int d = 1; d < 64; d <<= 1) {
+                const int y = __shfl_up(x, d, 64);
+                if (lane >= d) x += y;
+            }
+            int pos = x - c;
+            for (uint32_t b = w; b; b &= b - 1) list[pos++] = lane * 32 + __ffs(b) - 1;
+            if (lane == 63) R.total = (uint32_t)x;
+        }
+        __syncthreads();
+        const int per = 2 * HL + 2;  // limbs of both sides, then the two infinite counts
+        const int items = (int)R.total * per;
+        for (int u = threadIdx.x; u < items; u += WG) {
+            const int q = u / per, j = u - q * per;
+            const size_t hs = (size_t)s * P.nheavy + list[q];
+            if (j < 2 * HL) junk |= atomicExch((unsigned long long *)(P.hacc + hs * 2 * HL) + j, 0ull);
+            else junk |= (unsigned long long)(uint32_t)atomicExch(&P.hinf[2 * hs + (j - 2 * HL)], 0);
+        }
+        asm volatile("" ::"v"(junk));
+        return;
+    }
     if (cnt >= P.nheavy) {
         // a long list (a fixing job): every heavy row of the slot instead
         const size_t n = (size_t)P.nheavy * 2 * HL, t0 = (size_t)w0 * 64 + lane, step = (size_t)nw * 64;
@@ -2051,8 +2095,9 @@ __device__ void clear_heavy(const Params &P, const DInst &I, int s, int cnt, int
 
 // Forget the dirty variables of slot s (instance I): it reads the base
 // again, and its heavy-row corrections are cleared.  (Clearing them in two
-// waves while the others write the job's results was timed slower.)
-__device__ void restore_slot(const Params &P, const DInst &I, int s, int cnt) {
+// waves while the others write the job's results was timed slower.)  R's
+// sort keys are free here and serve the clear.
+__device__ void restore_slot(const Params &P, const DInst &I, int s, int cnt, RetireScratch &R) {
     uint32_t *dw = P.dirty + (size_t)s * P.snw;
     uint32_t *fw = P.filt + (size_t)s * FILT_WORDS;
     for (int t = threadIdx.x; t < cnt; t += WG) {
@@ -2061,7 +2106,7 @@ __device__ void restore_slot(const Params &P, const DInst &I, int s, int cnt) {
         dw[i >> 5] = 0u;
         fw[fhash(i) >> 5] = 0u;
     }
-    clear_heavy(P, I, s, cnt, threadIdx.x >> 6, WG / 64);
+    clear_heavy(P, I, s, cnt, R);
     __syncthreads();
     if (threadIdx.x == 0) P.dcount[s] = 0;
     __syncthreads();
@@ -2175,7 +2220,7 @@ __device__ bool admit_job(const Params &P, const JobIO &IO, int s, int p, int pa
     const int nd = probe ? 1 : dcount_now(P, s);
     if (R.badv != NONE) {  // a crossed box before the first round
         write_job(P, IO, p, 1, 0, 0ull, 0, -1, R.badv, 0, R);
-        restore_slot(P, I, s, nd);
+        restore_slot(P, I, s, nd, R);
         return false;
     }
     // The first round holds the rows of the changed variables; with
@@ -2227,7 +2272,7 @@ __device__ bool admit_job(const Params &P, const JobIO &IO, int s, int p, int pa
     // changed variables themselves.
     write_job(P, IO, p, 0, 0, 0ull, 0, -1, -1, nd, R);
     stage_sorted(P, IO, s, I, nd, R);
-    restore_slot(P, I, s, nd);
+    restore_slot(P, I, s, nd, R);
     return false;
 }
 
@@ -2264,7 +2309,7 @@ __global__ void __launch_bounds__(WG) k_retire(Params P, JobIO IO) {
             }
             write_job(P, IO, p, status, S.rounds, S.nnz, nbad, brow, bvar, cnt, R, pre);
             if (cnt > 0) stage_sorted(P, IO, s, I, cnt, R);
-            restore_slot(P, I, s, dcnt);
+            restore_slot(P, I, s, dcnt, R);
             if (threadIdx.x == 0) S.retire = 0;
             __syncthreads();
         }
