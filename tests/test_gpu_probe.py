@@ -122,6 +122,28 @@ def test_heavy_rows_of_probe_slots(slots, chunk, mode):
         assert (O["status"] == 2).any()
 
 
+def test_heavy_rows_of_probe_slots_past_the_clear_bitmap():
+    """More heavy rows (2050) than a retiring slot's LDS bitmap covers
+    (2048): the slot clears each heavy row of its dirty variables' columns
+    as its walk finds it.  Rows of 1025 binaries of which at most one may
+    be 1, consecutive rows sharing 25 variables: fixing a binary to 1 fixes
+    the other 1024 or 2024 variables of its rows to 0, fewer dirty variables
+    than heavy rows, and 16 slots each run many jobs."""
+    m, L, step = 2050, 1025, 1000
+    n = (m - 1) * step + L
+    inst = dict(m=m, n=n, row_ptr=np.arange(m + 1, dtype=np.int64) * L,
+                col=(np.arange(m)[:, None] * step + np.arange(L)[None, :]).reshape(-1).astype(np.int32),
+                val=np.ones(m * L), lo=np.full(m, -INF), hi=np.ones(m), vtype=np.ones(n, np.uint8),
+                lb=np.zeros(n), ub=np.ones(n))
+    assert (np.diff(inst["row_ptr"]) > 1024).sum() == m
+    shared = np.array([(k + 1) * step + o for k in range(0, m - 1, 97) for o in (0, 24)])
+    rng = np.random.default_rng(5)
+    vs = np.unique(np.concatenate([shared, rng.choice(n, 24, replace=False)])).astype(np.int32)
+    G, O = _probe_both(inst, vs, slots=16, opts_kw=dict(heavy_threshold=1024, heavy_chunk=512))
+    cnt = np.diff(O["off"])
+    assert set(cnt[0::2]) == {1} and {1025, 2025} <= set(cnt[1::2])  # lists hold the probed variable
+
+
 def test_heavy_rows_of_probe_slots_repeated_calls():
     """The same instance probed three times with different binaries: every
     call starts from cleared corrections, and a plain propagation between
